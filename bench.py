@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Benchmark of PERCH successor evaluation (arXiv:1510.05613) on one MI355X.
+
+Workload (default): the 640x480 plain configuration -- 3 objects from a seeded
+library of 6 convex meshes (2k-5k triangles), observed depth = ground-truth render
++ N(0, 2 mm) noise quantised to 1 mm, pose grid 50 x 50 x 16 = 40,000 poses per
+object, delta = 5 mm.  One step walks the ground-truth path of the Monotone Scene
+Generation Tree: at every level it materialises the parent state and evaluates
+all of its successors (every remaining object at every pose) -- 120,000 + 80,000
++ 40,000 = 240,000 successor evaluations (render + validity + edge cost).
+
+Prints one JSON line.  ``value`` is successor evaluations per second over the
+timed steps (inputs resident in HBM).  ``roofline`` compares the evaluation
+kernel's algorithmic bytes per second (mesh, parent depth and observed depth
+under each successor's silhouette, outputs) with the HBM peak; ``cpu_baseline``
+times the CPU oracle on a bounded seeded sample of the same successors.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "successor evals/s @640x480 (render+cost); time-to-best-scene learned vs plain"
+
+
+def parse_args(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--scene", type=int, default=0)
+    ap.add_argument("--threads", type=int, default=0, help="threads per successor (0 = default)")
+    ap.add_argument("--tile", type=int, default=0, help="z-tile pixels (0 = default)")
+    ap.add_argument("--cell", type=float, default=0.0, help="voxel cell / delta (0 = default)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="also run a plain device copy of this size (counter calibration)")
+    return ap.parse_args(argv)
+
+
+def level_work(scene):
+    """(parent, mesh ids, pose ids) of every level along the ground-truth order."""
+    out = []
+    order = scene.gt_order
+    P = scene.grid.P
+    for level in range(scene.K):
+        parent = [(int(scene.obj_mesh[k]), int(scene.gt_pose[k])) for k in order[:level]]
+        rest = sorted({int(scene.obj_mesh[k]) for k in order[level:]})
+        ms = np.repeat(np.array(rest, np.int32), P)
+        ps = np.tile(np.arange(P, dtype=np.int32), len(rest))
+        out.append((parent, ms, ps))
+    return out
+
+
+def algorithmic_bytes(scene, level, ms, S):
+    """Compulsory bytes of evaluating each successor in isolation: candidate mesh
+    (12 B per vertex, 12 B per triangle), parent depth under the silhouette (below
+    the root), observed depth under the silhouette (4 B per pixel; the dilated
+    footprint is larger, so this is a lower bound), the goal-level U bits, and the
+    two int32 outputs."""
+    V = np.array([len(m.verts) for m in scene.library.meshes], np.int64)[ms]
+    T = np.array([len(m.tris) for m in scene.library.meshes], np.int64)[ms]
+    S = S.astype(np.int64)
+    b = 12 * V + 12 * T + 4 * S + 8
+    if level > 0:
+        b += 4 * S
+    if level + 1 == scene.K:
+        b += (S + 7) // 8
+    return int(b.sum())
+
+
+def cpu_baseline(args, work_gpu):
+    """The oracle, as it stands, on a seeded sample of this step's successors."""
+    import oracle
+    from paper_1510_05613_amd import scenes
+
+    lib = scenes.make_library(scenes.CONFIGS[args.config]["lib"])
+    sc = scenes.make_scene(args.config, args.scene, oracle.render_fn, lib)
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(16, cores))
+    o = oracle.Oracle.from_scene(sc, nthreads=cores)
+    work = level_work(sc)
+    sizes = np.array([len(w[1]) for w in work], np.float64)
+    rng = np.random.default_rng(12345)
+    n_done, t_used, chunk = 0, 0.0, 4 * cores
+    while t_used < args.cpu_seconds:
+        lv = int(rng.choice(len(work), p=sizes / sizes.sum()))
+        parent, ms, ps = work[lv]
+        idx = rng.integers(len(ms), size=chunk)
+        t0 = time.perf_counter()
+        o.eval([p[0] for p in parent], [p[1] for p in parent], ms[idx], ps[idx])
+        t_used += time.perf_counter() - t0
+        n_done += chunk
+        chunk = min(4096, chunk * 2)
+    return {"value": round(n_done / t_used, 1), "unit": "evals/s", "cores": cores,
+            "kind": "oracle",
+            "sample": (f"{n_done} successors drawn uniformly (level-weighted) from the step's "
+                       f"{int(sizes.sum())}, scene regenerated with the oracle renderer, "
+                       f"{t_used:.1f} s on {cores} threads")}
+
+
+def main(argv=None):
+    args = parse_args(argv)
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the successor "
+              "batch of one GPU is the unit measured here.", file=sys.stderr)
+        return 2
+    import torch
+
+    from paper_1510_05613_amd import perch, scenes
+
+    perch.load()  # no library, no benchmark
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        return 3
+    cfg = scenes.CONFIGS[args.config]
+    lib = scenes.make_library(cfg["lib"])
+    sc = scenes.make_scene(args.config, args.scene, perch.GpuRenderer(), lib)
+    ctx = perch.context_from_scene(sc)
+    if args.threads or args.tile or args.cell:
+        ctx.set_tuning(args.threads, args.tile, args.cell)
+    work = level_work(sc)
+    dev = []
+    for parent, ms, ps in work:
+        cands = torch.as_tensor(np.ascontiguousarray(np.stack([ms, ps], 1))).cuda()
+        n = len(ms)
+        dev.append(dict(parent=parent, cands=cands,
+                        cost=torch.empty(n, dtype=torch.int32, device="cuda"),
+                        status=torch.empty(n, dtype=torch.int32, device="cuda"),
+                        comps=torch.empty((n, 5), dtype=torch.int32, device="cuda")))
+    n_step = sum(len(w[1]) for w in work)
+
+    # silhouettes for the algorithmic byte count (one untimed pass with components)
+    for d in dev:
+        ctx.set_parent(d["parent"])
+        ctx.eval_children(d["cands"], d["cost"], d["status"], d["comps"])
+    torch.cuda.synchronize()
+    bytes_per_step = 0
+    valid = 0
+    for lv, (d, (parent, ms, ps)) in enumerate(zip(dev, work)):
+        S = d["comps"][:, 0].cpu().numpy()
+        st = d["status"].cpu().numpy()
+        if np.any(st < 0):
+            raise RuntimeError(f"error status {np.unique(st)} at level {lv + 1}")
+        valid += int((st == 1).sum())
+        bytes_per_step += algorithmic_bytes(sc, lv, ms, S)
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in dev]
+    kernel_ms = 0.0
+
+    def step(timed):
+        nonlocal kernel_ms
+        for d, (e0, e1) in zip(dev, ev):
+            ctx.set_parent(d["parent"])
+            if timed:
+                e0.record()
+            ctx.eval_children(d["cands"], d["cost"], d["status"])
+            if timed:
+                e1.record()
+        if timed:
+            torch.cuda.synchronize()
+            kernel_ms += sum(e0.elapsed_time(e1) for e0, e1 in ev)
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    if args.copy_probe_mb:
+        a = torch.empty(args.copy_probe_mb << 20, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+
+    evals = n_step * args.steps
+    kernel_s = kernel_ms / 1e3
+    achieved = bytes_per_step * args.steps / kernel_s / 1e9
+    out = {
+        "metric": METRIC, "value": round(evals / wall, 1), "unit": "evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": (f"config {args.config} ({cfg['name']}), scene {args.scene}: "
+                                f"K={sc.K}, {sc.grid.P} poses/object, delta={cfg['delta']} m; "
+                                f"one step = every successor of every level on the "
+                                f"ground-truth path ({n_step})"),
+                   "successors_per_step": n_step, "valid_per_step": valid,
+                   "threads_per_successor": args.threads or 256},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_eval", "kernel_ms_per_step": round(kernel_ms / args.steps, 3),
+                     "algorithmic_bytes_per_step": bytes_per_step},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args, work)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,190 @@
+/*
+ * perch.h -- C ABI of libperch.so: PERCH successor evaluation on AMD MI355X (gfx950).
+ *
+ * PERCH (Narayanan & Likhachev, arXiv:1510.05613) localises K known objects on a
+ * table by searching the Monotone Scene Generation Tree (MSGT).  A tree state is a
+ * set of placed objects O = (ID, x, y, theta) (Sec. III-A); a successor adds one
+ * more object that must not occlude the scene rendered so far (Eq. 3); the edge
+ * cost is the per-object explanation cost dJ_r + dJ_o (+ residual at the last
+ * level) of Eq. (2)/(4), built on the point indicator of Eq. (1): a point is
+ * unexplained by a cloud C iff its distance to every point of C exceeds delta.
+ *
+ * Conventions
+ *   - Units: metres, radians.  World frame: table top is z = 0, z up.
+ *   - Camera frame: x right, y down, z forward.  cam_from_world = [R | t] row-major
+ *     3x4 float32, p_cam = R p_world + t (the known sensor pose, Sec. III).
+ *   - Pixel (u, v) = (column, row); pixel centres at integer coordinates;
+ *     u = fx X / Z + cx, v = fy Y / Z + cy.  Depth = camera Z.
+ *   - Pose table row (x, y, cos theta, sin theta): model point m goes to
+ *     (cos m_x - sin m_y + x, sin m_x + cos m_y + y, m_z).
+ *   - Meshes are closed and convex, triangles counter-clockwise seen from outside,
+ *     model frame resting on z = 0.  Their solid V(O) (Sec. III-A) is given as
+ *     planes (n, d): inside iff n.p <= d for every plane.
+ *   - A rendered cloud holds one point per covered pixel centre (front-facing
+ *     triangles, vertices snapped to 1/256 px, top-left fill rule).
+ *
+ * Memory and streams
+ *   - "host" pointers are read before the call returns; "device" pointers are
+ *     borrowed, must live on the context's device, and are used in stream order
+ *     on the context's HIP stream (asynchronously unless stated otherwise).
+ *   - The library owns every buffer it allocates (observation, hash, meshes,
+ *     pose table, parent buffers) and frees them in perch_destroy.
+ *
+ * Errors
+ *   - Every call returns perch_status (0 = OK, < 0 = error); perch_last_error()
+ *     gives a thread-local message.  No C++ exception crosses the ABI.  HIP
+ *     failures map to PERCH_E_HIP with the HIP error string.
+ *   - One thread may use a context at a time.
+ */
+#ifndef PERCH_H
+#define PERCH_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PERCH_OK = 0,
+  PERCH_E_ARG = -1,         /* bad argument (null, out of range, wrong size)        */
+  PERCH_E_OOM = -2,         /* device allocation failed                              */
+  PERCH_E_HIP = -3,         /* a HIP runtime call failed                             */
+  PERCH_E_STATE = -4,       /* call order violated (e.g. eval before observation)    */
+  PERCH_E_UNSUPPORTED = -5, /* input outside what the kernels handle                 */
+  PERCH_E_BUDGET = -6       /* search budget exhausted; the incumbent is returned    */
+} perch_status;
+
+typedef struct perch_ctx perch_ctx;
+
+/* An object state O = (ID, x, y, theta) of Sec. III-A, with (x, y, theta) given as
+ * an index into the context's pose table. */
+typedef struct {
+  int32_t mesh_id;
+  int32_t pose_idx;
+} perch_object;
+
+/* The sensor of the problem statement (Sec. III): intrinsics, 6-DoF pose and the
+ * noise threshold delta of Eq. (1). */
+typedef struct {
+  int32_t width, height;    /* pixels                                               */
+  float fx, fy, cx, cy;     /* pinhole intrinsics                                   */
+  float cam_from_world[12]; /* row-major [R | t]                                    */
+  float delta;              /* metres: explained iff distance <= delta              */
+} perch_sensor;
+
+/* Per-successor status values written by perch_eval_successors. */
+#define PERCH_SUCC_VALID 1          /* R_j subset of R_{j+1} holds (Eq. 3)            */
+#define PERCH_SUCC_INVALID 0        /* the new object occludes the parent scene        */
+#define PERCH_SUCC_NEAR_PLANE -2    /* a vertex lies within 1 cm of the camera plane   */
+#define PERCH_SUCC_TOO_WIDE -3      /* footprint wider than the configured z-tile      */
+#define PERCH_SUCC_BAD_INPUT -4     /* mesh_id or pose_idx out of range                */
+
+/* Creates a context on the current HIP device.  hip_stream: the hipStream_t all
+ * work is ordered on (NULL = the null stream).  Synchronous. */
+perch_status perch_create(const perch_sensor* sensor, void* hip_stream, perch_ctx** out);
+
+/* Destroys the context and frees its device memory.  Synchronises its stream. */
+void perch_destroy(perch_ctx* ctx);
+
+/* Sets the observed depth image I of Sec. III (device, H*W float32 metres, 0 = no
+ * return; the table and background already removed, as Sec. III assumes).  The
+ * image is copied; the library back-projects it and builds the uniform voxel hash
+ * used for the radius tests of Eq. (1).  Synchronous. */
+perch_status perch_set_observation(perch_ctx* ctx, const float* depth_dev);
+
+/* Adds (or replaces) mesh mesh_id of the model library (the 3D models of Sec. III).
+ * All arrays are host memory: verts n_verts x 3, tris n_tris x 3 (0-based, local),
+ * planes n_planes x 4.  Uploaded before the next evaluation.  mesh ids are dense
+ * from 0. */
+perch_status perch_add_mesh(perch_ctx* ctx, int32_t mesh_id, const float* verts,
+                            int32_t n_verts, const int32_t* tris, int32_t n_tris,
+                            const float* planes, int32_t n_planes);
+
+/* Sets the discretised pose set (Sec. IV-E, the x/y/yaw grid): host, P x 4 rows
+ * (x, y, cos theta, sin theta). */
+perch_status perch_set_poses(perch_ctx* ctx, const float* poses, int32_t P);
+
+/* Sets the known multiset of K <= 8 mesh ids in the scene (Sec. III assumptions);
+ * the goal level of the tree is K. */
+perch_status perch_set_objects(perch_ctx* ctx, const int32_t* mesh_ids, int32_t K);
+
+/* The hot path: evaluates n successors s' = s + cands[i] of the parent state
+ * s = parent[0..j) (host array, j < K), i.e. Succ(s) membership (Eq. 3) and the
+ * edge cost c(s, s') (Eq. 4).  cands_dev: device, n perch_object.  Outputs
+ * (device, n int32 each): cost_dev (-1 unless valid), status_dev (PERCH_SUCC_*),
+ * comps_dev (nullable, n x 5: silhouette pixels S, |dR|, dJ_r, dJ_o, residual;
+ * all -1 unless the successor is valid).
+ * The parent composite R_j (and, at the goal level, the set U of observed points
+ * outside every parent volume and unexplained by R_j) is materialised first, on
+ * the same stream.  Asynchronous. */
+perch_status perch_eval_successors(perch_ctx* ctx, const perch_object* parent, int32_t j,
+                                   const perch_object* cands_dev, int32_t n,
+                                   int32_t* cost_dev, int32_t* status_dev,
+                                   int32_t* comps_dev);
+
+/* The same evaluation in two steps, for callers that evaluate the children of one
+ * parent in several batches: perch_set_parent materialises R_j of parent[0..j)
+ * (and U at the goal level); perch_eval_children evaluates successors of the
+ * parent last set, with the outputs of perch_eval_successors.  Asynchronous. */
+perch_status perch_set_parent(perch_ctx* ctx, const perch_object* parent, int32_t j);
+perch_status perch_eval_children(perch_ctx* ctx, const perch_object* cands_dev, int32_t n,
+                                 int32_t* cost_dev, int32_t* status_dev, int32_t* comps_dev);
+
+/* Renders objects (host array objs[0..n)) to depth images (device output, float32,
+ * +inf where uncovered): composite != 0 writes one H*W image holding the minimum
+ * over the objects (the rendered scene R_n); composite == 0 writes n stand-alone
+ * images.  Asynchronous. */
+perch_status perch_render(perch_ctx* ctx, const perch_object* objs, int32_t n,
+                          int32_t composite, float* depth_dev);
+
+/* Tuning knobs of the successor kernel: threads per successor (64, 128 or 256),
+ * z-tile capacity in pixels (LDS), and voxel cell size in units of delta
+ * (>= 1).  Pass 0 to keep a value.  Results do not depend on them. */
+perch_status perch_set_tuning(perch_ctx* ctx, int32_t threads, int32_t tile_px,
+                              float cell_over_delta);
+
+/* Observed point count |I| and the pixel window halo (host outputs). */
+perch_status perch_get_info(perch_ctx* ctx, int32_t* n_points, int32_t* halo);
+
+/* ---- tree search (Alg. 1: ComputePath over the implicit MSGT) ---- */
+
+#define PERCH_SEARCH_EXHAUSTIVE 0 /* enumerate the whole tree, argmin (cost, key)        */
+#define PERCH_SEARCH_UCS 1        /* best-first on g with duplicate detection (w = 1)    */
+#define PERCH_SEARCH_FOCAL 2      /* anchor g-queue + depth-first inadmissible queue,    */
+                                  /* goal accepted when g <= w * min g (Theorem 2)       */
+
+typedef struct {
+  int32_t mode;                /* PERCH_SEARCH_*                                        */
+  float w;                     /* suboptimality bound for FOCAL (>= 1)                  */
+  int32_t anytime;             /* FOCAL: keep searching until the incumbent is optimal  */
+  double budget_s;             /* wall-clock budget in seconds, 0 = none                */
+  int64_t budget_expansions;   /* 0 = none                                              */
+  const int32_t* pose_subset;  /* host; NULL = every pose of the table                  */
+  int32_t n_pose_subset;
+} perch_search_opts;
+
+typedef struct {
+  perch_object objs[8];        /* the goal, in insertion order (a valid order)           */
+  int32_t K;
+  int32_t found;               /* 1 if a goal was reached                               */
+  int64_t cost;                /* sum of edge costs (Eq. 2)                             */
+  int32_t edge_cost[8];        /* c(s_i, s_{i+1}) along the path                        */
+  int64_t n_expanded, n_evaluated, n_invalid;
+  double t_total_s;            /* wall time of the call                                 */
+  double t_best_s;             /* wall time until the returned cost was first reached   */
+  int64_t lower_bound;         /* min g over the open list at exit (UCS/FOCAL)          */
+} perch_result;
+
+/* Runs the tree search of Alg. 1 on the context's scene: root = empty state, goal =
+ * all K objects placed, successors and edge costs from perch_set_parent /
+ * perch_eval_children on the GPU (one launch per expansion).  Synchronous.
+ * Returns PERCH_E_BUDGET (with the incumbent in *out) when a budget runs out. */
+perch_status perch_search(perch_ctx* ctx, const perch_search_opts* opts, perch_result* out);
+
+/* Thread-local message of the last failing call on this thread ("" if none). */
+const char* perch_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

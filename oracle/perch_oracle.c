@@ -509,31 +509,43 @@ static int eval_one(const orc_scene* sc, const parent_t* par, int mesh, int pose
       if (m2 > sc->delta2) ++dJr;
       if (near_delta(sc, m2)) ++nfd;
     }
-  /* dJ_o: observed points inside V(O_{j+1}) unexplained by dR */
-  int32_t dJo = 0;
-  for (int k = 0; k < sc->nI; ++k) {
-    double vm = vol_margin(sc, mesh, pose, sc->I_w + 3 * (size_t)k);
-    if (fabs(vm) <= FLAG_EPS) ++nfv;
-    if (vm > 0) continue;
-    int pix = sc->I_pix[k];
-    double m2 = min_d2_to_depth(sc, sc->I_cam + 3 * (size_t)k, pix % W, pix / W, w->DR);
-    if (m2 > sc->delta2) ++dJo;
-    if (near_delta(sc, m2)) ++nfd;
-  }
-  /* residual (goal level only): observed points outside every volume that are
-   * unexplained by the full render R_K = R_j with dR added */
-  int32_t res = 0;
-  if (par->goal) {
+  /* dJ_o: observed points inside V(O_{j+1}) unexplained by dR; and at the goal
+   * level the residual: observed points outside every volume that are unexplained
+   * by the full render R_K = R_j with dR added.
+   * Volume flags count only points whose membership flip would change this edge's
+   * cost: near the candidate's boundary, "inside" contributes [unexplained by dR]
+   * and "outside" contributes [outside the parent volumes and unexplained by R_K]
+   * (0 below the goal level); near a parent's boundary (goal level, outside the
+   * candidate) the flip toggles [unexplained by R_K]. */
+  int32_t dJo = 0, res = 0;
+  if (par->goal)
     for (size_t i = 0; i < npx; ++i) w->RK[i] = Dp[i] < INFINITY ? Dp[i] : w->DR[i];
-    for (int k = 0; k < sc->nI; ++k) {
-      if (par->nearVpar[k]) ++nfv;
-      if (par->inVpar[k]) continue;
-      if (vol_margin(sc, mesh, pose, sc->I_w + 3 * (size_t)k) <= 0) continue;
-      int pix = sc->I_pix[k];
-      double m2 = min_d2_to_depth(sc, sc->I_cam + 3 * (size_t)k, pix % W, pix / W, w->RK);
-      if (m2 > sc->delta2) ++res;
+  for (int k = 0; k < sc->nI; ++k) {
+    const double* pc = sc->I_cam + 3 * (size_t)k;
+    const int pix = sc->I_pix[k];
+    const int up = pix % W, vp = pix / W;
+    double vm = vol_margin(sc, mesh, pose, sc->I_w + 3 * (size_t)k);
+    int inV = vm <= 0, nearV = fabs(vm) <= FLAG_EPS;
+    int unexp_dr = 0, unexp_rk = 0;
+    if (inV || nearV) {
+      double m2 = min_d2_to_depth(sc, pc, up, vp, w->DR);
+      unexp_dr = m2 > sc->delta2;
       if (near_delta(sc, m2)) ++nfd;
     }
+    if (inV) dJo += unexp_dr;
+    if (!par->goal) {
+      if (nearV && unexp_dr) ++nfv;
+      continue;
+    }
+    int inVp = par->inVpar[k], nearVp = par->nearVpar[k];
+    if ((!inV && !inVp) || (nearV && !inVp) || (nearVp && !inV)) {
+      double m2 = min_d2_to_depth(sc, pc, up, vp, w->RK);
+      unexp_rk = m2 > sc->delta2;
+      if (near_delta(sc, m2)) ++nfd;
+    }
+    if (!inV && !inVp) res += unexp_rk;
+    if (nearV && unexp_dr != (inVp ? 0 : unexp_rk)) ++nfv;
+    if (nearVp && !inV && unexp_rk) ++nfv;
   }
   comps[2] = dJr;
   comps[3] = dJo;

@@ -1,0 +1,420 @@
+// perch_api.cpp -- the C ABI of libperch.so (declared in include/perch.h).
+//
+// Host side of PERCH successor evaluation (arXiv:1510.05613): owns the scene's
+// device buffers (observed depth, voxel hash of I, mesh library, pose table,
+// parent buffers), materialises a parent state R_j before its successors are
+// evaluated (Sec. IV-A), and launches the gfx950 kernels on the context's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "perch_ctx.h"
+
+using namespace perch;
+
+namespace perch {
+
+namespace {
+thread_local std::string g_err;
+}
+
+perch_status fail(perch_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+}  // namespace perch
+
+static perch_status upload_meshes(perch_ctx* c) {
+  if (!c->meshes_dirty) return PERCH_OK;
+  const int nm = (int)c->meshes.size();
+  if (nm == 0) return fail(PERCH_E_STATE, "no meshes added");
+  std::vector<float4> v;
+  std::vector<int4> t, rg;
+  std::vector<float4> pl, bb;
+  std::vector<int2> fr;
+  int max_nv = 0;
+  for (int m = 0; m < nm; ++m) {
+    const HostMesh& h = c->meshes[m];
+    if (!h.set) return fail(PERCH_E_STATE, "mesh id %d was never added (ids must be dense)", m);
+    const int nv = (int)h.verts.size() / 3, nt = (int)h.tris.size() / 3,
+              nf = (int)h.planes.size() / 4;
+    rg.push_back(make_int4((int)v.size(), nv, (int)t.size(), nt));
+    fr.push_back(make_int2((int)pl.size(), nf));
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int k = 0; k < nv; ++k) {
+      float x = h.verts[3 * k], y = h.verts[3 * k + 1], z = h.verts[3 * k + 2];
+      v.push_back(make_float4(x, y, z, 0.0f));
+      lo[0] = std::min(lo[0], x); lo[1] = std::min(lo[1], y); lo[2] = std::min(lo[2], z);
+      hi[0] = std::max(hi[0], x); hi[1] = std::max(hi[1], y); hi[2] = std::max(hi[2], z);
+    }
+    for (int k = 0; k < nt; ++k)
+      t.push_back(make_int4(h.tris[3 * k], h.tris[3 * k + 1], h.tris[3 * k + 2], 0));
+    for (int k = 0; k < nf; ++k)
+      pl.push_back(make_float4(h.planes[4 * k], h.planes[4 * k + 1], h.planes[4 * k + 2],
+                               h.planes[4 * k + 3]));
+    bb.push_back(make_float4(lo[0], lo[1], lo[2], 0.0f));
+    bb.push_back(make_float4(hi[0], hi[1], hi[2], 0.0f));
+    max_nv = std::max(max_nv, nv);
+  }
+  HIP_TRY(c->verts.ensure(v.size() * sizeof(float4)));
+  HIP_TRY(c->tris.ensure(std::max<size_t>(1, t.size()) * sizeof(int4)));
+  HIP_TRY(c->planes.ensure(std::max<size_t>(1, pl.size()) * sizeof(float4)));
+  HIP_TRY(c->range.ensure(rg.size() * sizeof(int4)));
+  HIP_TRY(c->frange.ensure(fr.size() * sizeof(int2)));
+  HIP_TRY(c->aabb.ensure(bb.size() * sizeof(float4)));
+  HIP_TRY(hipMemcpy(c->verts.p, v.data(), v.size() * sizeof(float4), hipMemcpyHostToDevice));
+  if (!t.empty())
+    HIP_TRY(hipMemcpy(c->tris.p, t.data(), t.size() * sizeof(int4), hipMemcpyHostToDevice));
+  if (!pl.empty())
+    HIP_TRY(hipMemcpy(c->planes.p, pl.data(), pl.size() * sizeof(float4), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(c->range.p, rg.data(), rg.size() * sizeof(int4), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(c->frange.p, fr.data(), fr.size() * sizeof(int2), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(c->aabb.p, bb.data(), bb.size() * sizeof(float4), hipMemcpyHostToDevice));
+  c->max_nv = max_nv;
+  c->meshes_dirty = false;
+  return PERCH_OK;
+}
+
+static size_t eval_lds_bytes(const perch_ctx* c) {
+  return (size_t)c->max_nv * sizeof(int2) + (size_t)c->tile_px * sizeof(unsigned);
+}
+
+static bool objects_ok(const perch_ctx* c, const perch_object* o, int n) {
+  for (int k = 0; k < n; ++k)
+    if (o[k].mesh_id < 0 || o[k].mesh_id >= (int)c->meshes.size() || o[k].pose_idx < 0 ||
+        o[k].pose_idx >= c->P)
+      return false;
+  return true;
+}
+
+// Composite R_j of the parent objects into par_depth; at the goal level also the
+// set U (bitmap + count) of observed points outside every parent volume and
+// unexplained by R_j.
+static perch_status materialise_parent(perch_ctx* c, const perch_object* parent, int j,
+                                       bool goal) {
+  const size_t npx = (size_t)c->cam.W * c->cam.H;
+  HIP_TRY(c->par_depth.ensure(npx * sizeof(unsigned)));
+  HIP_TRY(c->par_ubits.ensure(((npx + 31) / 32) * sizeof(unsigned)));
+  HIP_TRY(c->par_ucount.ensure(sizeof(int)));
+  const Meshes M = c->dev_meshes();
+  const float4* poses = c->poses.as<float4>();
+  launch_fill_u32(c->par_depth.as<unsigned>(), kInfBits, npx, c->stream);
+  for (int k = 0; k < j; ++k)
+    launch_render_object(c->cam, M, poses, parent[k].mesh_id, parent[k].pose_idx,
+                         (int)c->meshes[parent[k].mesh_id].tris.size() / 3,
+                         c->par_depth.as<unsigned>(), c->stream);
+  if (goal) {
+    launch_fill_u32(c->par_ubits.as<unsigned>(), 0u, (npx + 31) / 32, c->stream);
+    launch_fill_i32(c->par_ucount.as<int>(), 0, 1, c->stream);
+    int mp[16];
+    for (int k = 0; k < j; ++k) {
+      mp[2 * k] = parent[k].mesh_id;
+      mp[2 * k + 1] = parent[k].pose_idx;
+    }
+    launch_parent_u(c->cam, M, poses, c->obs.as<float>(), mp, j, c->par_depth.as<unsigned>(),
+                    c->par_ubits.as<unsigned>(), c->par_ucount.as<int>(), c->ep, c->stream);
+  }
+  HIP_TRY(hipGetLastError());
+  return PERCH_OK;
+}
+
+extern "C" {
+
+const char* perch_last_error(void) { return perch::g_err.c_str(); }
+
+perch_status perch_create(const perch_sensor* s, void* hip_stream, perch_ctx** out) {
+  if (!s || !out) return fail(PERCH_E_ARG, "null argument");
+  *out = nullptr;
+  if (s->width <= 0 || s->height <= 0 || s->width > 16384 || s->height > 16384)
+    return fail(PERCH_E_ARG, "bad image size %dx%d", s->width, s->height);
+  if (!(s->fx > 0) || !(s->fy > 0) || !(s->delta >= 0))
+    return fail(PERCH_E_ARG, "bad intrinsics or delta");
+  double R[9], t[3];
+  for (int r = 0; r < 3; ++r) {
+    for (int k = 0; k < 3; ++k) R[3 * r + k] = s->cam_from_world[4 * r + k];
+    t[r] = s->cam_from_world[4 * r + 3];
+  }
+  const double A = R[4] * R[8] - R[5] * R[7], B = -(R[3] * R[8] - R[5] * R[6]),
+               C = R[3] * R[7] - R[4] * R[6];
+  const double det = R[0] * A + R[1] * B + R[2] * C;
+  if (!(std::fabs(det) > 1e-12)) return fail(PERCH_E_ARG, "singular camera rotation");
+  double Ri[9] = {A / det,
+                  -(R[1] * R[8] - R[2] * R[7]) / det,
+                  (R[1] * R[5] - R[2] * R[4]) / det,
+                  B / det,
+                  (R[0] * R[8] - R[2] * R[6]) / det,
+                  -(R[0] * R[5] - R[2] * R[3]) / det,
+                  C / det,
+                  -(R[0] * R[7] - R[1] * R[6]) / det,
+                  (R[0] * R[4] - R[1] * R[3]) / det};
+  perch_ctx* c = new perch_ctx();
+  Cam& cam = c->cam;
+  cam.W = s->width;
+  cam.H = s->height;
+  cam.fx = s->fx;
+  cam.fy = s->fy;
+  cam.cx = s->cx;
+  cam.cy = s->cy;
+  for (int k = 0; k < 12; ++k) cam.M[k] = s->cam_from_world[k];
+  for (int r = 0; r < 3; ++r) {
+    for (int k = 0; k < 3; ++k) cam.Winv[4 * r + k] = (float)Ri[3 * r + k];
+    cam.Winv[4 * r + 3] = (float)(-(Ri[3 * r] * t[0] + Ri[3 * r + 1] * t[1] + Ri[3 * r + 2] * t[2]));
+  }
+  cam.delta = s->delta;
+  cam.delta2 = s->delta * s->delta;
+  cam.inv_fx = 1.0f / s->fx;
+  cam.inv_fy = 1.0f / s->fy;
+  cam.dfx = s->fx;
+  cam.dfy = s->fy;
+  cam.dcx = s->cx;
+  cam.dcy = s->cy;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return fail(PERCH_E_HIP, "hipGetDevice failed");
+  }
+  *out = c;
+  return PERCH_OK;
+}
+
+void perch_destroy(perch_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (DevBuf* b : {&c->verts, &c->tris, &c->planes, &c->range, &c->frange, &c->aabb, &c->poses,
+                    &c->obs, &c->h_keys, &c->h_cells, &c->h_pts, &c->h_counts, &c->par_depth,
+                    &c->par_ubits, &c->par_ucount, &c->s_cands, &c->s_out})
+    b->release();
+  c->s_hcands.release();
+  c->s_hout.release();
+  delete c;
+}
+
+// Back-projects the observation, derives the pixel-window halo and builds the
+// voxel hash of I from c->obs (synchronous).
+static perch_status build_observation(perch_ctx* c) {
+  const Cam& cam = c->cam;
+  const size_t npx = (size_t)cam.W * cam.H;
+  std::vector<float> host(npx);
+  HIP_TRY(hipMemcpyAsync(host.data(), c->obs.p, npx * sizeof(float), hipMemcpyDeviceToHost,
+                         c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  int n = 0;
+  float zmin = INFINITY;
+  for (size_t k = 0; k < npx; ++k)
+    if (host[k] > 0.0f) {
+      ++n;
+      zmin = std::min(zmin, host[k]);
+    }
+  // Pixel halo: the largest window radius fx dwin sqrt(1 + a^2) / (Z - dwin) + 1
+  // over the observed points (a = |u - cx| / fx at the image border, Z >= zmin).
+  const double dwin = (double)cam.delta * 1.001 + 1e-6;
+  int halo = 1;
+  if (n > 0) {
+    if (!(zmin > dwin)) return fail(PERCH_E_UNSUPPORTED, "observed depth within delta of camera");
+    const double amax = std::max(std::fabs(0.0 - cam.cx), std::fabs(cam.W - 1.0 - cam.cx)) / cam.fx;
+    const double bmax = std::max(std::fabs(0.0 - cam.cy), std::fabs(cam.H - 1.0 - cam.cy)) / cam.fy;
+    const double ru = cam.fx * dwin * std::sqrt(1 + amax * amax) / (zmin - dwin);
+    const double rv = cam.fy * dwin * std::sqrt(1 + bmax * bmax) / (zmin - dwin);
+    halo = (int)std::floor(std::max(ru, rv)) + 2;
+  }
+  c->ep.halo = halo;
+  c->ep.dwin = (float)dwin;
+  c->n_points = n;
+  // voxel hash of I
+  const int slots = next_pow2(std::max(64, 2 * n));
+  c->h_mask = slots - 1;
+  HIP_TRY(c->h_keys.ensure((size_t)slots * sizeof(unsigned long long)));
+  HIP_TRY(c->h_cells.ensure((size_t)slots * sizeof(int2)));
+  HIP_TRY(c->h_counts.ensure((size_t)(2 * slots + 1) * sizeof(int)));
+  HIP_TRY(c->h_pts.ensure((size_t)std::max(1, n) * sizeof(float4)));
+  int* counts = c->h_counts.as<int>();
+  int* fill = counts + slots;
+  int* npts = counts + 2 * slots;
+  launch_fill_u32(reinterpret_cast<unsigned*>(c->h_keys.p), 0xffffffffu, 2 * (size_t)slots,
+                  c->stream);
+  launch_fill_i32(counts, 0, 2 * (size_t)slots + 1, c->stream);
+  const Hash h = c->dev_hash();
+  launch_hash_insert(cam, c->obs.as<float>(), c->h_keys.as<unsigned long long>(), counts, c->h_mask,
+                     h.inv_cell, npts, c->stream);
+  launch_scan_cells(counts, c->h_cells.as<int2>(), slots, c->stream);
+  launch_hash_scatter(cam, c->obs.as<float>(), c->h_keys.as<unsigned long long>(),
+                      c->h_cells.as<int2>(), fill, c->h_pts.as<float4>(), c->h_mask, h.inv_cell,
+                      c->stream);
+  HIP_TRY(hipGetLastError());
+  int dev_n = 0;
+  HIP_TRY(hipMemcpyAsync(&dev_n, npts, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (dev_n != n) return fail(PERCH_E_HIP, "hash build counted %d points, expected %d", dev_n, n);
+  c->has_obs = true;
+  return PERCH_OK;
+}
+
+perch_status perch_set_observation(perch_ctx* c, const float* depth_dev) {
+  if (!c || !depth_dev) return fail(PERCH_E_ARG, "null argument");
+  const size_t npx = (size_t)c->cam.W * c->cam.H;
+  c->has_obs = false;
+  c->parent_j = -1;
+  HIP_TRY(c->obs.ensure(npx * sizeof(float)));
+  HIP_TRY(hipMemcpyAsync(c->obs.p, depth_dev, npx * sizeof(float), hipMemcpyDeviceToDevice,
+                         c->stream));
+  return build_observation(c);
+}
+
+perch_status perch_add_mesh(perch_ctx* c, int32_t mesh_id, const float* verts, int32_t nv,
+                            const int32_t* tris, int32_t nt, const float* planes, int32_t nf) {
+  if (!c || !verts || !tris || (!planes && nf > 0)) return fail(PERCH_E_ARG, "null argument");
+  if (mesh_id < 0 || mesh_id > 4096 || nv < 3 || nt < 1 || nf < 0)
+    return fail(PERCH_E_ARG, "bad mesh sizes");
+  for (int k = 0; k < 3 * nt; ++k)
+    if (tris[k] < 0 || tris[k] >= nv) return fail(PERCH_E_ARG, "triangle index out of range");
+  if ((int)c->meshes.size() <= mesh_id) c->meshes.resize(mesh_id + 1);
+  HostMesh& h = c->meshes[mesh_id];
+  h.verts.assign(verts, verts + 3 * (size_t)nv);
+  h.tris.assign(tris, tris + 3 * (size_t)nt);
+  h.planes.assign(planes, planes + 4 * (size_t)nf);
+  h.set = true;
+  c->meshes_dirty = true;
+  return PERCH_OK;
+}
+
+perch_status perch_set_poses(perch_ctx* c, const float* poses, int32_t P) {
+  if (!c || !poses || P <= 0) return fail(PERCH_E_ARG, "bad pose table");
+  HIP_TRY(c->poses.ensure((size_t)P * sizeof(float4)));
+  HIP_TRY(hipMemcpy(c->poses.p, poses, (size_t)P * sizeof(float4), hipMemcpyHostToDevice));
+  c->P = P;
+  c->parent_j = -1;
+  return PERCH_OK;
+}
+
+perch_status perch_set_objects(perch_ctx* c, const int32_t* mesh_ids, int32_t K) {
+  if (!c || (!mesh_ids && K > 0) || K < 1 || K > 8) return fail(PERCH_E_ARG, "bad object list");
+  c->objects.assign(mesh_ids, mesh_ids + K);
+  c->parent_j = -1;
+  return PERCH_OK;
+}
+
+perch_status perch_set_tuning(perch_ctx* c, int32_t threads, int32_t tile_px,
+                              float cell_over_delta) {
+  if (!c) return fail(PERCH_E_ARG, "null context");
+  if (threads && threads != 64 && threads != 128 && threads != 256)
+    return fail(PERCH_E_ARG, "threads must be 64, 128 or 256");
+  if (tile_px && (tile_px < 256 || tile_px > 36864)) return fail(PERCH_E_ARG, "bad tile_px");
+  if (cell_over_delta != 0.0f && !(cell_over_delta >= 1.0f && cell_over_delta <= 8.0f))
+    return fail(PERCH_E_ARG, "cell_over_delta must be in [1, 8]");
+  if (threads) c->threads = threads;
+  if (tile_px) c->tile_px = tile_px;
+  if (cell_over_delta != 0.0f && cell_over_delta != c->cell_over_delta) {
+    c->cell_over_delta = cell_over_delta;
+    if (c->has_obs) {
+      perch_status st = build_observation(c);  // rebuild the hash with the new cell size
+      if (st) return st;
+    }
+  }
+  return PERCH_OK;
+}
+
+perch_status perch_get_info(perch_ctx* c, int32_t* n_points, int32_t* halo) {
+  if (!c) return fail(PERCH_E_ARG, "null context");
+  if (n_points) *n_points = c->n_points;
+  if (halo) *halo = c->ep.halo;
+  return PERCH_OK;
+}
+
+perch_status perch_set_parent(perch_ctx* c, const perch_object* parent, int32_t j) {
+  if (!c) return fail(PERCH_E_ARG, "null context");
+  c->parent_j = -1;
+  if (!c->has_obs) return fail(PERCH_E_STATE, "perch_set_observation not called");
+  if (c->P <= 0) return fail(PERCH_E_STATE, "perch_set_poses not called");
+  const int K = (int)c->objects.size();
+  if (K < 1) return fail(PERCH_E_STATE, "perch_set_objects not called");
+  if (j < 0 || j >= K || (j > 0 && !parent)) return fail(PERCH_E_ARG, "bad parent (j=%d, K=%d)", j, K);
+  perch_status st = upload_meshes(c);
+  if (st) return st;
+  if (!objects_ok(c, parent, j)) return fail(PERCH_E_ARG, "parent object out of range");
+  st = materialise_parent(c, parent, j, j + 1 == K);
+  if (st) return st;
+  c->parent_j = j;
+  return PERCH_OK;
+}
+
+perch_status perch_eval_children(perch_ctx* c, const perch_object* cands_dev, int32_t n,
+                                 int32_t* cost_dev, int32_t* status_dev, int32_t* comps_dev) {
+  if (!c) return fail(PERCH_E_ARG, "null context");
+  if (n < 0 || (n > 0 && (!cands_dev || !cost_dev || !status_dev)))
+    return fail(PERCH_E_ARG, "bad successor arrays");
+  if (c->parent_j < 0) return fail(PERCH_E_STATE, "perch_set_parent not called");
+  if (c->meshes_dirty) return fail(PERCH_E_STATE, "meshes changed since perch_set_parent");
+  const size_t lds = eval_lds_bytes(c);
+  if (lds > 160 * 1024 - 256)
+    return fail(PERCH_E_UNSUPPORTED, "LDS need %zu B exceeds the CU (max_nv=%d, tile=%d)", lds,
+                c->max_nv, c->tile_px);
+  if (n == 0) return PERCH_OK;
+  const int K = (int)c->objects.size();
+  Parent par;
+  par.depth = c->par_depth.as<unsigned>();
+  par.ubits = c->par_ubits.as<unsigned>();
+  par.ucount = c->par_ucount.as<int>();
+  par.has_parent = c->parent_j > 0;
+  par.goal = (c->parent_j + 1 == K);
+  EvalParams ep = c->ep;
+  ep.tile_px = c->tile_px;
+  ep.max_nv = c->max_nv;
+  ep.n_mesh = (int)c->meshes.size();
+  ep.n_poses = c->P;
+  HIP_TRY(launch_eval(c->threads, c->cam, c->dev_meshes(), c->poses.as<float4>(),
+                      c->obs.as<float>(), c->dev_hash(), par,
+                      reinterpret_cast<const int2*>(cands_dev), n, cost_dev, status_dev, comps_dev,
+                      ep, lds, c->stream));
+  return PERCH_OK;
+}
+
+perch_status perch_eval_successors(perch_ctx* c, const perch_object* parent, int32_t j,
+                                   const perch_object* cands_dev, int32_t n, int32_t* cost_dev,
+                                   int32_t* status_dev, int32_t* comps_dev) {
+  if (!c) return fail(PERCH_E_ARG, "null context");
+  if (n < 0 || (n > 0 && (!cands_dev || !cost_dev || !status_dev)))
+    return fail(PERCH_E_ARG, "bad successor arrays");
+  perch_status st = perch_set_parent(c, parent, j);
+  if (st) return st;
+  return perch_eval_children(c, cands_dev, n, cost_dev, status_dev, comps_dev);
+}
+
+perch_status perch_render(perch_ctx* c, const perch_object* objs, int32_t n, int32_t composite,
+                          float* depth_dev) {
+  if (!c || (n > 0 && (!objs || !depth_dev)) || n < 0) return fail(PERCH_E_ARG, "bad arguments");
+  if (c->P <= 0) return fail(PERCH_E_STATE, "perch_set_poses not called");
+  perch_status st = upload_meshes(c);
+  if (st) return st;
+  if (!objects_ok(c, objs, n)) return fail(PERCH_E_ARG, "object out of range");
+  const size_t npx = (size_t)c->cam.W * c->cam.H;
+  unsigned* out = reinterpret_cast<unsigned*>(depth_dev);
+  const Meshes M = c->dev_meshes();
+  if (composite) {
+    launch_fill_u32(out, kInfBits, npx, c->stream);
+    for (int k = 0; k < n; ++k)
+      launch_render_object(c->cam, M, c->poses.as<float4>(), objs[k].mesh_id, objs[k].pose_idx,
+                           (int)c->meshes[objs[k].mesh_id].tris.size() / 3, out, c->stream);
+  } else {
+    launch_fill_u32(out, kInfBits, npx * (size_t)n, c->stream);
+    for (int k = 0; k < n; ++k)
+      launch_render_object(c->cam, M, c->poses.as<float4>(), objs[k].mesh_id, objs[k].pose_idx,
+                           (int)c->meshes[objs[k].mesh_id].tris.size() / 3, out + npx * k,
+                           c->stream);
+  }
+  HIP_TRY(hipGetLastError());
+  return PERCH_OK;
+}
+
+}  // extern "C"

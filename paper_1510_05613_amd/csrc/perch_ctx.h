@@ -1,0 +1,149 @@
+// perch_ctx.h -- the context object behind the C ABI (internal to libperch.so).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/perch.h"
+#include "perch_internal.h"
+
+namespace perch {
+
+// A device allocation owned by the context.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipError_t ensure(size_t n) {
+    if (n <= bytes && p) return hipSuccess;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+    hipError_t e = hipMalloc(&p, n ? n : 16);
+    if (e == hipSuccess) bytes = n;
+    return e;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+struct HostMesh {
+  std::vector<float> verts;
+  std::vector<int32_t> tris;
+  std::vector<float> planes;
+  bool set = false;
+};
+
+// Page-locked host memory owned by the context (fast, truly asynchronous copies).
+struct PinnedBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipError_t ensure(size_t n) {
+    if (n <= bytes && p) return hipSuccess;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+    hipError_t e = hipHostMalloc(&p, n ? n : 16, hipHostMallocDefault);
+    if (e == hipSuccess) bytes = n;
+    return e;
+  }
+  void release() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+inline int next_pow2(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+// Records a message for perch_last_error() and returns st.
+perch_status fail(perch_status st, const char* fmt, ...);
+
+}  // namespace perch
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return perch::fail(e_ == hipErrorOutOfMemory ? PERCH_E_OOM : PERCH_E_HIP, "%s: %s", \
+                         #expr, hipGetErrorString(e_));                                 \
+  } while (0)
+
+
+struct perch_ctx {
+  using DevBuf = perch::DevBuf;
+  using HostMesh = perch::HostMesh;
+  using PinnedBuf = perch::PinnedBuf;
+  using Cam = perch::Cam;
+  using Meshes = perch::Meshes;
+  using Hash = perch::Hash;
+  using EvalParams = perch::EvalParams;
+  Cam cam;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  // model library
+  std::vector<HostMesh> meshes;
+  bool meshes_dirty = true;
+  int max_nv = 0;
+  DevBuf verts, tris, planes, range, frange, aabb;
+  // pose table
+  DevBuf poses;
+  int P = 0;
+  // known objects
+  std::vector<int32_t> objects;
+  // observation and hash
+  DevBuf obs;
+  bool has_obs = false;
+  int n_points = 0;
+  DevBuf h_keys, h_cells, h_pts, h_counts;
+  int h_mask = 0;
+  float cell_over_delta = 2.0f;
+  // parent buffers (parent_j = level of the materialised parent, -1 = none)
+  DevBuf par_depth, par_ubits, par_ucount;
+  int parent_j = -1;
+  // search scratch: candidate list and outputs of one expansion
+  DevBuf s_cands, s_out;
+  PinnedBuf s_hcands, s_hout;
+  // tuning
+  int threads = 256;
+  int tile_px = 12288;
+  EvalParams ep{};
+
+  Meshes dev_meshes() const {
+    Meshes M;
+    M.verts = verts.as<float4>();
+    M.tris = tris.as<int4>();
+    M.planes = planes.as<float4>();
+    M.range = range.as<int4>();
+    M.frange = frange.as<int2>();
+    M.aabb = aabb.as<float4>();
+    return M;
+  }
+  Hash dev_hash() const {
+    Hash h;
+    h.keys = h_keys.as<unsigned long long>();
+    h.cells = h_cells.as<int2>();
+    h.pts = h_pts.as<float4>();
+    h.mask = h_mask;
+    const float delta = cam.delta;
+    h.qpad = delta * 1.001f + 1e-6f;
+    h.inv_cell = 1.0f / (cell_over_delta * h.qpad);
+    return h;
+  }
+};
+

@@ -1,0 +1,86 @@
+// perch_internal.h -- device-side data layout shared by the kernels and the host
+// code of libperch.so (not part of the public ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace perch {
+
+// Sensor in float32 (the vertex stage works in float32; see vstage()).
+struct Cam {
+  int W, H;
+  float fx, fy, cx, cy;
+  float M[12];     // cam_from_world, row-major [R | t]
+  float Winv[12];  // world_from_cam (rounded from the FP64 inverse of M)
+  float delta, delta2;
+  float inv_fx, inv_fy;
+  double dfx, dfy, dcx, dcy;  // the same intrinsics widened to FP64 (depth planes)
+};
+
+// Uniform voxel hash of the observed cloud I (camera frame).  Cell (i, j, k) holds
+// the points p with floor(p * inv_cell) == (i, j, k); the open-addressing table
+// maps a packed cell key to its (start, count) run in pts.
+struct Hash {
+  const unsigned long long* keys;  // table keys, kEmptyKey when free
+  const int2* cells;               // (start, count) per table slot
+  const float4* pts;               // camera-frame points grouped by cell
+  int mask;                        // table size - 1 (power of two)
+  float inv_cell;
+  float qpad;  // query half-width: delta with a rounding margin
+};
+
+constexpr unsigned long long kEmptyKey = ~0ull;
+constexpr unsigned kInfBits = 0x7f800000u;  // +inf as float bits (empty z-buffer)
+
+// Mesh library, flattened.  range[m] = (v_off, nv, t_off, nt); frange[m] = (f_off, nf).
+struct Meshes {
+  const float4* verts;
+  const int4* tris;
+  const float4* planes;
+  const int4* range;
+  const int2* frange;
+  const float4* aabb;  // 2 per mesh: min and max corner of the vertices (model frame)
+};
+
+// Materialised parent state R_j (Sec. III-A): composite depth as float bits
+// (+inf = empty), and at the goal level the bitmap U of observed pixels outside
+// every parent volume and unexplained by R_j, with |U|.
+struct Parent {
+  const unsigned* depth;
+  const unsigned* ubits;
+  const int* ucount;
+  int has_parent;
+  int goal;
+};
+
+struct EvalParams {
+  int tile_px;  // z-tile capacity (pixels) in LDS
+  int halo;     // largest pixel-window radius over the observed cloud
+  int max_nv;   // largest vertex count in the library
+  float dwin;   // window radius in metres (delta with a rounding margin)
+  int n_mesh;   // candidates with mesh_id outside [0, n_mesh) or pose_idx outside
+  int n_poses;  // [0, n_poses) are rejected with status -4
+};
+
+// ---- launchers (perch_kernels.hip) ----
+void launch_fill_u32(unsigned* p, unsigned v, size_t n, hipStream_t s);
+void launch_fill_i32(int* p, int v, size_t n, hipStream_t s);
+// hash build: counts, table insert, scan, scatter
+void launch_hash_insert(const Cam& cam, const float* depth, unsigned long long* keys,
+                        int* counts, int mask, float inv_cell, int* n_points, hipStream_t s);
+void launch_scan_cells(const int* counts, int2* cells, int n_slots, hipStream_t s);
+void launch_hash_scatter(const Cam& cam, const float* depth, const unsigned long long* keys,
+                         const int2* cells, int* fill, float4* pts, int mask, float inv_cell,
+                         hipStream_t s);
+void launch_render_object(const Cam& cam, const Meshes& M, const float4* poses, int mesh,
+                          int pose, int n_tris, unsigned* depth_bits, hipStream_t s);
+void launch_parent_u(const Cam& cam, const Meshes& M, const float4* poses, const float* obs,
+                     const int* par_mesh_pose, int j, const unsigned* depth_bits,
+                     unsigned* ubits, int* ucount, const EvalParams& ep, hipStream_t s);
+void launch_bits_to_float(const unsigned* bits, float* out, size_t n, hipStream_t s);
+hipError_t launch_eval(int threads, const Cam& cam, const Meshes& M, const float4* poses,
+                 const float* obs, const Hash& hs, const Parent& par, const int2* cands,
+                 int n, int* cost, int* status, int* comps, const EvalParams& ep,
+                 size_t lds_bytes, hipStream_t s);
+
+}  // namespace perch

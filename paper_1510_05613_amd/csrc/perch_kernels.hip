@@ -1,0 +1,753 @@
+// perch_kernels.hip -- gfx950 kernels of PERCH successor evaluation
+// (Narayanan & Likhachev, arXiv:1510.05613).
+//
+// One workgroup evaluates one successor s' = s + (mesh, pose) of a materialised
+// parent s (Sec. IV-A): it transforms the candidate's vertices into LDS, rasterises
+// its front faces into an LDS z-tile over the footprint, composites against the
+// parent depth (the non-occlusion test of Eq. 3 and the new points dR), counts
+// dR points unexplained by the observed cloud through a uniform voxel hash
+// (dJ_r), counts observed points inside the candidate's volume unexplained by dR
+// through an exact pixel window over the LDS tile (dJ_o), and at the goal level
+// updates the parent's residual set U (Eq. 2, residual(K)).  Counts are wave
+// ballot/popcount reductions.
+//
+// Built with -ffp-contract=off: the float32 vertex stage is part of the
+// rasterisation rule and must not have products fused into adds.
+#include <climits>
+
+#include "perch_internal.h"
+
+namespace perch {
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int floor256(int x) { return x >> 8; }
+__device__ __forceinline__ int ceil256(int x) { return -((-x) >> 8); }
+
+__device__ __forceinline__ int wave_sum(int v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ int wave_min(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ int ballot_count(bool p) { return __popcll(__ballot(p)); }
+
+// ---------------------------------------------------------------------------
+// vertex stage (float32, fixed operation order)
+// ---------------------------------------------------------------------------
+
+// Places model point m by pose (x, y, cos, sin) and maps it to the camera frame:
+// w = (c m_x - s m_y + x, s m_x + c m_y + y, m_z); cam_k = ((M_k0 w_x + M_k1 w_y)
+// + M_k2 w_z) + M_k3.
+__device__ __forceinline__ void vcam(const Cam& c, const float4 pz, const float4 m, float& X,
+                                     float& Y, float& Z) {
+  const float wx = (pz.z * m.x - pz.w * m.y) + pz.x;
+  const float wy = (pz.w * m.x + pz.z * m.y) + pz.y;
+  const float wz = m.z;
+  X = ((c.M[0] * wx + c.M[1] * wy) + c.M[2] * wz) + c.M[3];
+  Y = ((c.M[4] * wx + c.M[5] * wy) + c.M[6] * wz) + c.M[7];
+  Z = ((c.M[8] * wx + c.M[9] * wy) + c.M[10] * wz) + c.M[11];
+}
+
+// Projection and snap to 1/256 pixel: inv = 1/Z (IEEE division), u = fx (X inv) + cx,
+// U = rint(256 u) (ties to even).  False when the vertex is within 1 cm of the
+// camera plane or the snapped value leaves +-2^24.
+__device__ __forceinline__ bool vsnap(const Cam& c, float X, float Y, float Z, int& U, int& V) {
+  const float inv = 1.0f / Z;
+  const float u = c.fx * (X * inv) + c.cx;
+  const float v = c.fy * (Y * inv) + c.cy;
+  const float su = rintf(256.0f * u), sv = rintf(256.0f * v);
+  const bool ok = (Z > 0.01f) && (fabsf(su) <= 16777216.0f) && (fabsf(sv) <= 16777216.0f);
+  U = ok ? (int)su : 0;
+  V = ok ? (int)sv : 0;
+  return ok;
+}
+
+// ---------------------------------------------------------------------------
+// depth: FP64 plane of the triangle's float32 camera-space vertices
+// ---------------------------------------------------------------------------
+
+// Camera Z where the ray through pixel centre (i, j) meets the triangle's plane:
+// with n = (b - a) x (c - a), z = (n.a) / (n.r), r = ((i - cx)/fx, (j - cy)/fy, 1),
+// written as z = N / (A i + B j + C).
+struct Plane64 {
+  double A, B, C, N;
+};
+
+__device__ __forceinline__ Plane64 make_plane(const Cam& c, float ax, float ay, float az,
+                                              float bx, float by, float bz, float cx_,
+                                              float cy_, float cz) {
+  const double e1x = (double)bx - ax, e1y = (double)by - ay, e1z = (double)bz - az;
+  const double e2x = (double)cx_ - ax, e2y = (double)cy_ - ay, e2z = (double)cz - az;
+  const double nx = e1y * e2z - e1z * e2y;
+  const double ny = e1z * e2x - e1x * e2z;
+  const double nz = e1x * e2y - e1y * e2x;
+  Plane64 p;
+  p.N = nx * ax + ny * ay + nz * az;
+  p.A = nx / c.dfx;
+  p.B = ny / c.dfy;
+  p.C = nz - p.A * c.dcx - p.B * c.dcy;
+  return p;
+}
+
+__device__ __forceinline__ float plane_depth(const Plane64& p, int i, int j) {
+  const double den = p.A * (double)i + p.B * (double)j + p.C;
+  return (float)(p.N / den);
+}
+
+// ---------------------------------------------------------------------------
+// triangle coverage: integer edge functions, top-left rule, front faces only
+// ---------------------------------------------------------------------------
+
+// Calls emit(i, j) for every pixel centre (256 i, 256 j) covered by the triangle
+// with snapped vertices (x_k, y_k), restricted to columns [c0, c1] and rows
+// [r0, r1].  Outward-CCW faces seen from the front have negative signed area in
+// these y-down coordinates; others (back faces, zero area) are skipped.  A centre
+// on an edge is covered iff the edge is a top edge (horizontal, interior below) or
+// a left edge (interior to its right) of the positively oriented triangle.
+template <class Emit>
+__device__ __forceinline__ void raster_tri(int x0, int y0, int x1, int y1, int x2, int y2,
+                                           int c0, int c1, int r0, int r1, Emit&& emit) {
+  const int xmin = min(x0, min(x1, x2)), xmax = max(x0, max(x1, x2));
+  const int ymin = min(y0, min(y1, y2)), ymax = max(y0, max(y1, y2));
+  const int ia = max(c0, ceil256(xmin)), ib = min(c1, floor256(xmax));
+  const int ja = max(r0, ceil256(ymin)), jb = min(r1, floor256(ymax));
+  if (ia > ib || ja > jb) return;
+  if (xmax - xmin < 16384 && ymax - ymin < 16384) {
+    // all products below 2^28: int32 is exact
+    int bx = x1 - x0, by = y1 - y0, cx = x2 - x0, cy = y2 - y0;
+    const int area = bx * cy - by * cx;
+    if (area >= 0) return;
+    int t = bx; bx = cx; cx = t;
+    t = by; by = cy; cy = t;
+    // edges a->b, b->c, c->a (a at the origin)
+    const int d0x = bx, d0y = by, d1x = cx - bx, d1y = cy - by, d2x = -cx, d2y = -cy;
+    const int b0 = (d0y < 0 || (d0y == 0 && d0x > 0)) ? 0 : -1;
+    const int b1 = (d1y < 0 || (d1y == 0 && d1x > 0)) ? 0 : -1;
+    const int b2 = (d2y < 0 || (d2y == 0 && d2x > 0)) ? 0 : -1;
+    for (int j = ja; j <= jb; ++j) {
+      const int py = 256 * j - y0;
+      const int px0 = 256 * ia - x0;
+      int e0 = d0x * py - d0y * px0 + b0;
+      int e1 = d1x * (py - by) - d1y * (px0 - bx) + b1;
+      int e2 = d2x * (py - cy) - d2y * (px0 - cx) + b2;
+      for (int i = ia; i <= ib; ++i) {
+        if ((e0 | e1 | e2) >= 0) emit(i, j);
+        e0 -= 256 * d0y;
+        e1 -= 256 * d1y;
+        e2 -= 256 * d2y;
+      }
+    }
+  } else {
+    long long bx = (long long)x1 - x0, by = (long long)y1 - y0;
+    long long cx = (long long)x2 - x0, cy = (long long)y2 - y0;
+    const long long area = bx * cy - by * cx;
+    if (area >= 0) return;
+    long long t = bx; bx = cx; cx = t;
+    t = by; by = cy; cy = t;
+    const long long d0x = bx, d0y = by, d1x = cx - bx, d1y = cy - by, d2x = -cx, d2y = -cy;
+    const long long b0 = (d0y < 0 || (d0y == 0 && d0x > 0)) ? 0 : -1;
+    const long long b1 = (d1y < 0 || (d1y == 0 && d1x > 0)) ? 0 : -1;
+    const long long b2 = (d2y < 0 || (d2y == 0 && d2x > 0)) ? 0 : -1;
+    for (int j = ja; j <= jb; ++j) {
+      const long long py = 256LL * j - y0;
+      const long long px0 = 256LL * ia - x0;
+      long long e0 = d0x * py - d0y * px0 + b0;
+      long long e1 = d1x * (py - by) - d1y * (px0 - bx) + b1;
+      long long e2 = d2x * (py - cy) - d2y * (px0 - cx) + b2;
+      for (int i = ia; i <= ib; ++i) {
+        if ((e0 | e1 | e2) >= 0) emit(i, j);
+        e0 -= 256 * d0y;
+        e1 -= 256 * d1y;
+        e2 -= 256 * d2y;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// observed cloud helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ float3 backproject(const Cam& c, int i, int j, float z) {
+  return make_float3(((float)i - c.cx) * z * c.inv_fx, ((float)j - c.cy) * z * c.inv_fy, z);
+}
+
+__device__ __forceinline__ unsigned long long cell_key(int x, int y, int z) {
+  return (unsigned long long)((unsigned)(x + (1 << 20)) & 0x1FFFFFu) |
+         ((unsigned long long)((unsigned)(y + (1 << 20)) & 0x1FFFFFu) << 21) |
+         ((unsigned long long)((unsigned)(z + (1 << 20)) & 0x1FFFFFu) << 42);
+}
+
+__device__ __forceinline__ unsigned hash_key(unsigned long long k) {
+  k ^= k >> 31;
+  k *= 0x7fb5d329728ea185ull;
+  k ^= k >> 27;
+  k *= 0x81dadef4bc2dd44dull;
+  k ^= k >> 33;
+  return (unsigned)k;
+}
+
+// Eq. (1) against the whole observed cloud: true iff some observed point lies
+// within delta of q (camera frame).  Scans every voxel cell overlapping the cube
+// q +- qpad (qpad slightly above delta, so float rounding of the cell index cannot
+// drop a neighbour) and stops at the first hit.
+__device__ __forceinline__ bool explained_by_cloud(const Hash& hs, float qx, float qy, float qz,
+                                                   float d2max) {
+  const int x0 = (int)floorf((qx - hs.qpad) * hs.inv_cell);
+  const int x1 = (int)floorf((qx + hs.qpad) * hs.inv_cell);
+  const int y0 = (int)floorf((qy - hs.qpad) * hs.inv_cell);
+  const int y1 = (int)floorf((qy + hs.qpad) * hs.inv_cell);
+  const int z0 = (int)floorf((qz - hs.qpad) * hs.inv_cell);
+  const int z1 = (int)floorf((qz + hs.qpad) * hs.inv_cell);
+  for (int cz = z0; cz <= z1; ++cz)
+    for (int cy = y0; cy <= y1; ++cy)
+      for (int cx = x0; cx <= x1; ++cx) {
+        const unsigned long long key = cell_key(cx, cy, cz);
+        unsigned slot = hash_key(key) & (unsigned)hs.mask;
+        for (;;) {
+          const unsigned long long k = hs.keys[slot];
+          if (k == key) {
+            const int2 se = hs.cells[slot];
+            for (int t = se.x; t < se.x + se.y; ++t) {
+              const float4 p = hs.pts[t];
+              const float dx = p.x - qx, dy = p.y - qy, dz = p.z - qz;
+              if (dx * dx + dy * dy + dz * dz <= d2max) return true;
+            }
+            break;
+          }
+          if (k == kEmptyKey) break;
+          slot = (slot + 1) & (unsigned)hs.mask;
+        }
+      }
+  return false;
+}
+
+// Object-frame coordinates of camera-frame point p for pose (x, y, c, s):
+// world w = Winv p, then the exact inverse of the pose placement.
+__device__ __forceinline__ float3 cam_to_object(const Cam& c, const float4 pz, float3 p) {
+  const float wx = c.Winv[0] * p.x + c.Winv[1] * p.y + c.Winv[2] * p.z + c.Winv[3];
+  const float wy = c.Winv[4] * p.x + c.Winv[5] * p.y + c.Winv[6] * p.z + c.Winv[7];
+  const float wz = c.Winv[8] * p.x + c.Winv[9] * p.y + c.Winv[10] * p.z + c.Winv[11];
+  const float dx = wx - pz.x, dy = wy - pz.y;
+  const float inv_n2 = 1.0f / (pz.z * pz.z + pz.w * pz.w);
+  return make_float3((pz.z * dx + pz.w * dy) * inv_n2, (pz.z * dy - pz.w * dx) * inv_n2, wz);
+}
+
+// p in V(O): inside the mesh's box of vertices (with a 1e-5 m margin) and on the
+// inner side of every plane.
+__device__ __forceinline__ bool in_volume(const Meshes& M, int mesh, float3 o) {
+  const float4 lo = M.aabb[2 * mesh], hi = M.aabb[2 * mesh + 1];
+  if (o.x < lo.x - 1e-5f || o.y < lo.y - 1e-5f || o.z < lo.z - 1e-5f || o.x > hi.x + 1e-5f ||
+      o.y > hi.y + 1e-5f || o.z > hi.z + 1e-5f)
+    return false;
+  const int2 fr = M.frange[mesh];
+  for (int f = 0; f < fr.y; ++f) {
+    const float4 pl = M.planes[fr.x + f];
+    if (pl.x * o.x + pl.y * o.y + pl.z * o.z - pl.w > 0.0f) return false;
+  }
+  return true;
+}
+
+// Pixel window radii (columns, rows) that hold every point within dwin of the
+// point p seen at depth p.z: |du| <= fx dwin sqrt(1 + (X/Z)^2) / (Z - dwin), +1 for
+// rounding, capped by the scene-wide halo.
+__device__ __forceinline__ void window_radius(const Cam& c, const EvalParams& ep, float3 p,
+                                              int& ru, int& rv) {
+  const float den = p.z - ep.dwin;
+  if (!(den > 0.0f)) {
+    ru = rv = ep.halo;
+    return;
+  }
+  const float a = p.x / p.z, b = p.y / p.z;
+  ru = min(ep.halo, (int)(c.fx * ep.dwin * sqrtf(1.0f + a * a) / den) + 1);
+  rv = min(ep.halo, (int)(c.fy * ep.dwin * sqrtf(1.0f + b * b) / den) + 1);
+}
+
+// ---------------------------------------------------------------------------
+// fills
+// ---------------------------------------------------------------------------
+
+__global__ void k_fill_u32(unsigned* p, unsigned v, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_fill_i32(int* p, int v, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// voxel hash of the observed cloud
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ unsigned long long point_cell(float3 p, float inv_cell) {
+  return cell_key((int)floorf(p.x * inv_cell), (int)floorf(p.y * inv_cell),
+                  (int)floorf(p.z * inv_cell));
+}
+
+__device__ __forceinline__ unsigned find_slot(const unsigned long long* keys, int mask,
+                                              unsigned long long key) {
+  unsigned slot = hash_key(key) & (unsigned)mask;
+  while (keys[slot] != key) slot = (slot + 1) & (unsigned)mask;
+  return slot;
+}
+
+__global__ void k_hash_insert(Cam cam, const float* depth, unsigned long long* keys, int* counts,
+                              int mask, float inv_cell, int* n_points) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= cam.W * cam.H) return;
+  const float z = depth[k];
+  if (!(z > 0.0f)) return;
+  const float3 p = backproject(cam, k % cam.W, k / cam.W, z);
+  const unsigned long long key = point_cell(p, inv_cell);
+  unsigned slot = hash_key(key) & (unsigned)mask;
+  for (;;) {
+    const unsigned long long prev = atomicCAS(&keys[slot], kEmptyKey, key);
+    if (prev == kEmptyKey || prev == key) break;
+    slot = (slot + 1) & (unsigned)mask;
+  }
+  atomicAdd(&counts[slot], 1);
+  atomicAdd(n_points, 1);
+}
+
+// exclusive scan of the per-slot counts (one workgroup of 1024 threads)
+__global__ void __launch_bounds__(1024) k_scan_cells(const int* counts, int2* cells, int n) {
+  __shared__ int part[1024];
+  const int t = threadIdx.x;
+  const int chunk = (n + 1023) / 1024;
+  const int a = min(n, t * chunk), b = min(n, a + chunk);
+  int s = 0;
+  for (int i = a; i < b; ++i) s += counts[i];
+  part[t] = s;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int v = t >= o ? part[t - o] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int run = part[t] - s;
+  for (int i = a; i < b; ++i) {
+    cells[i] = make_int2(run, counts[i]);
+    run += counts[i];
+  }
+}
+
+__global__ void k_hash_scatter(Cam cam, const float* depth, const unsigned long long* keys,
+                               const int2* cells, int* fill, float4* pts, int mask,
+                               float inv_cell) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= cam.W * cam.H) return;
+  const float z = depth[k];
+  if (!(z > 0.0f)) return;
+  const float3 p = backproject(cam, k % cam.W, k / cam.W, z);
+  const unsigned slot = find_slot(keys, mask, point_cell(p, inv_cell));
+  const int pos = cells[slot].x + atomicAdd(&fill[slot], 1);
+  pts[pos] = make_float4(p.x, p.y, p.z, 0.0f);
+}
+
+// ---------------------------------------------------------------------------
+// full-frame render of one object (parent composites, perch_render)
+// ---------------------------------------------------------------------------
+
+__global__ void k_render_object(Cam cam, Meshes M, const float4* poses, int mesh, int pose,
+                                unsigned* depth) {
+  const int4 rg = M.range[mesh];
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= rg.w) return;
+  const float4 pz = poses[pose];
+  const int4 tr = M.tris[rg.z + t];
+  float X[3], Y[3], Z[3];
+  int U[3], V[3];
+  const int idx[3] = {tr.x, tr.y, tr.z};
+  bool ok = true;
+  for (int k = 0; k < 3; ++k) {
+    vcam(cam, pz, M.verts[rg.x + idx[k]], X[k], Y[k], Z[k]);
+    ok &= vsnap(cam, X[k], Y[k], Z[k], U[k], V[k]);
+  }
+  if (!ok) return;
+  const Plane64 pl = make_plane(cam, X[0], Y[0], Z[0], X[1], Y[1], Z[1], X[2], Y[2], Z[2]);
+  const int W = cam.W;
+  raster_tri(U[0], V[0], U[1], V[1], U[2], V[2], 0, cam.W - 1, 0, cam.H - 1,
+             [&](int i, int j) {
+               const float z = plane_depth(pl, i, j);
+               atomicMin(&depth[j * W + i], __float_as_uint(z));
+             });
+}
+
+// ---------------------------------------------------------------------------
+// goal-level parent set U: observed points outside every parent volume and
+// unexplained by the parent composite R_{K-1}
+// ---------------------------------------------------------------------------
+
+struct ParentObjs {
+  int2 o[8];
+};
+
+__global__ void k_parent_u(Cam cam, Meshes M, const float4* poses, const float* obs,
+                           ParentObjs po, int j, const unsigned* pdepth, unsigned* ubits,
+                           int* ucount, EvalParams ep) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int W = cam.W, H = cam.H;
+  bool inU = false;
+  if (k < W * H) {
+    const float z = obs[k];
+    if (z > 0.0f) {
+      const int i = k % W, jj = k / W;
+      const float3 p = backproject(cam, i, jj, z);
+      bool inV = false;
+      for (int a = 0; a < j && !inV; ++a)
+        inV = in_volume(M, po.o[a].x, cam_to_object(cam, poses[po.o[a].y], p));
+      if (!inV) {
+        int ru, rv;
+        window_radius(cam, ep, p, ru, rv);
+        bool expl = false;
+        for (int jq = max(0, jj - rv); jq <= min(H - 1, jj + rv) && !expl; ++jq)
+          for (int iq = max(0, i - ru); iq <= min(W - 1, i + ru); ++iq) {
+            const unsigned kq = pdepth[jq * W + iq];
+            if (kq == kInfBits) continue;
+            const float3 q = backproject(cam, iq, jq, __uint_as_float(kq));
+            const float dx = q.x - p.x, dy = q.y - p.y, dz = q.z - p.z;
+            if (dx * dx + dy * dy + dz * dz <= cam.delta2) {
+              expl = true;
+              break;
+            }
+          }
+        inU = !expl;
+      }
+    }
+  }
+  const unsigned long long b = __ballot(inU);
+  if (inU) atomicOr(&ubits[k >> 5], 1u << (k & 31));
+  if ((threadIdx.x & 63) == 0 && b) atomicAdd(ucount, __popcll(b));
+}
+
+// ---------------------------------------------------------------------------
+// successor evaluation: one workgroup per successor
+// ---------------------------------------------------------------------------
+
+template <int NT>
+__global__ void __launch_bounds__(NT)
+    k_eval(Cam cam, Meshes M, const float4* __restrict__ poses, const float* __restrict__ obs,
+           Hash hs, Parent par, const int2* __restrict__ cands, int n, int* __restrict__ out_cost,
+           int* __restrict__ out_status, int* __restrict__ out_comps, EvalParams ep) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int s_bb[4];
+  __shared__ int s_acc[8];  // S, |dR|, dJ_r, dJ_o, removed-from-U, invalid, near-plane
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int s = blockIdx.x;
+  if (s >= n) return;
+  const int W = cam.W, H = cam.H;
+  const int2 cd = cands[s];
+  if (cd.x < 0 || cd.x >= ep.n_mesh || cd.y < 0 || cd.y >= ep.n_poses) {
+    if (tid == 0) {
+      out_status[s] = -4;
+      out_cost[s] = -1;
+      if (out_comps)
+        for (int c = 0; c < 5; ++c) out_comps[5 * s + c] = -1;
+    }
+    return;
+  }
+  const int mesh = cd.x;
+  const float4 pz = poses[cd.y];
+  const int4 rg = M.range[mesh];
+  int2* suv = reinterpret_cast<int2*>(smem);
+  unsigned* tile = reinterpret_cast<unsigned*>(smem + (size_t)ep.max_nv * sizeof(int2));
+  if (tid < 4) s_bb[tid] = tid < 2 ? INT_MAX : INT_MIN;
+  if (tid < 8) s_acc[tid] = 0;
+  __syncthreads();
+
+  // ---- vertex stage into LDS, footprint bounding box ----
+  {
+    int xmn = INT_MAX, ymn = INT_MAX, xmx = INT_MIN, ymx = INT_MIN;
+    bool bad = false;
+    for (int v = tid; v < rg.y; v += NT) {
+      float X, Y, Z;
+      vcam(cam, pz, M.verts[rg.x + v], X, Y, Z);
+      int U, V;
+      bad |= !vsnap(cam, X, Y, Z, U, V);
+      suv[v] = make_int2(U, V);
+      xmn = min(xmn, U);
+      ymn = min(ymn, V);
+      xmx = max(xmx, U);
+      ymx = max(ymx, V);
+    }
+    xmn = wave_min(xmn);
+    ymn = wave_min(ymn);
+    xmx = wave_max(xmx);
+    ymx = wave_max(ymx);
+    const bool any_bad = __ballot(bad) != 0;
+    if (lane == 0) {
+      atomicMin(&s_bb[0], xmn);
+      atomicMin(&s_bb[1], ymn);
+      atomicMax(&s_bb[2], xmx);
+      atomicMax(&s_bb[3], ymx);
+      if (any_bad) s_acc[6] = 1;
+    }
+  }
+  __syncthreads();
+  if (s_acc[6]) {
+    if (tid == 0) {
+      out_status[s] = -2;
+      out_cost[s] = -1;
+      if (out_comps)
+        for (int c = 0; c < 5; ++c) out_comps[5 * s + c] = -1;
+    }
+    return;
+  }
+
+  // observed region: the vertex box (+1 px: every point of V(O) projects inside it),
+  // grown by the window halo at the goal level (points of U explained by dR)
+  const int ext = par.goal ? max(1, ep.halo) : 1;
+  const int ca = max(0, floor256(s_bb[0]) - ext), cb = min(W - 1, ceil256(s_bb[2]) + ext);
+  const int ra = max(0, floor256(s_bb[1]) - ext), rb = min(H - 1, ceil256(s_bb[3]) + ext);
+  const int tw = cb - ca + 1;
+  const int nrows = rb - ra + 1;
+  int core = nrows;
+  if (tw > 0 && nrows > 0 && tw * nrows > ep.tile_px) core = ep.tile_px / tw - 2 * ep.halo;
+  if (tw > 0 && nrows > 0 && core < 1) {
+    if (tid == 0) {
+      out_status[s] = -3;
+      out_cost[s] = -1;
+      if (out_comps)
+        for (int c = 0; c < 5; ++c) out_comps[5 * s + c] = -1;
+    }
+    return;
+  }
+  const float delta2 = cam.delta2;
+  int n_dJr = 0, n_dJo = 0, n_rem = 0;  // wave-uniform ballot counts
+
+  for (int b0 = ra; b0 <= rb && tw > 0; b0 += core) {
+    const int b1 = min(rb, b0 + core - 1);
+    const int t0 = max(ra, b0 - ep.halo), t1 = min(rb, b1 + ep.halo);
+    const int tn = (t1 - t0 + 1) * tw;
+    for (int k = tid; k < tn; k += NT) tile[k] = kInfBits;
+    __syncthreads();
+
+    // ---- rasterise the candidate into the z-tile (rows t0..t1) ----
+    for (int t = tid; t < rg.w; t += NT) {
+      const int4 tr = M.tris[rg.z + t];
+      const int2 a = suv[tr.x], b = suv[tr.y], c = suv[tr.z];
+      bool have = false;
+      Plane64 pl;
+      raster_tri(a.x, a.y, b.x, b.y, c.x, c.y, ca, cb, t0, t1, [&](int i, int j) {
+        if (!have) {
+          float X0, Y0, Z0, X1, Y1, Z1, X2, Y2, Z2;
+          vcam(cam, pz, M.verts[rg.x + tr.x], X0, Y0, Z0);
+          vcam(cam, pz, M.verts[rg.x + tr.y], X1, Y1, Z1);
+          vcam(cam, pz, M.verts[rg.x + tr.z], X2, Y2, Z2);
+          pl = make_plane(cam, X0, Y0, Z0, X1, Y1, Z1, X2, Y2, Z2);
+          have = true;
+        }
+        const float z = plane_depth(pl, i, j);
+        atomicMin(&tile[(j - t0) * tw + (i - ca)], __float_as_uint(z));
+      });
+    }
+    __syncthreads();
+
+    // ---- composite against the parent: validity (Eq. 3) and dR ----
+    {
+      int sl = 0, dr = 0;
+      bool occ = false;
+      for (int k = tid; k < tn; k += NT) {
+        const int jj = t0 + k / tw, ii = ca + k % tw;
+        const unsigned key = tile[k];
+        const bool cov = key != kInfBits;
+        const unsigned pk = par.has_parent ? par.depth[jj * W + ii] : kInfBits;
+        const bool pfin = pk != kInfBits;
+        occ |= cov && pfin && key < pk;  // positive floats order like their bits
+        const bool core_row = jj >= b0 && jj <= b1;
+        sl += (cov && core_row);
+        dr += (cov && !pfin && core_row);
+        tile[k] = (cov && !pfin) ? key : kInfBits;
+      }
+      sl = wave_sum(sl);
+      dr = wave_sum(dr);
+      const bool any_occ = __ballot(occ) != 0;
+      if (lane == 0) {
+        atomicAdd(&s_acc[0], sl);
+        atomicAdd(&s_acc[1], dr);
+        if (any_occ) atomicOr(&s_acc[5], 1);
+      }
+    }
+    __syncthreads();
+    if (s_acc[5]) break;
+
+    // ---- dJ_r: new points unexplained by the observed cloud (voxel hash) ----
+    {
+      const int k0 = (b0 - t0) * tw, k1 = (b1 - t0 + 1) * tw;
+      for (int base = k0; base < k1; base += NT) {
+        const int k = base + tid;
+        bool unexp = false;
+        if (k < k1) {
+          const unsigned key = tile[k];
+          if (key != kInfBits) {
+            const float3 q = backproject(cam, ca + k % tw, t0 + k / tw, __uint_as_float(key));
+            unexp = !explained_by_cloud(hs, q.x, q.y, q.z, delta2);
+          }
+        }
+        n_dJr += ballot_count(unexp);
+      }
+    }
+
+    // ---- dJ_o and U: observed points of the core rows ----
+    {
+      const int nk = (b1 - b0 + 1) * tw;
+      for (int base = 0; base < nk; base += NT) {
+        const int k = base + tid;
+        bool cnt_o = false, cnt_rem = false;
+        if (k < nk) {
+          const int jj = b0 + k / tw, ii = ca + k % tw;
+          const float z = obs[jj * W + ii];
+          if (z > 0.0f) {
+            const float3 p = backproject(cam, ii, jj, z);
+            const bool inV = in_volume(M, mesh, cam_to_object(cam, pz, p));
+            const int pix = jj * W + ii;
+            const bool inU = par.goal && ((par.ubits[pix >> 5] >> (pix & 31)) & 1u);
+            bool expl = false;
+            if (inV || inU) {
+              int ru, rv;
+              window_radius(cam, ep, p, ru, rv);
+              const int ja = max(t0, jj - rv), jb = min(t1, jj + rv);
+              const int ia = max(ca, ii - ru), ib = min(cb, ii + ru);
+              for (int jq = ja; jq <= jb && !expl; ++jq)
+                for (int iq = ia; iq <= ib; ++iq) {
+                  const unsigned kq = tile[(jq - t0) * tw + (iq - ca)];
+                  if (kq == kInfBits) continue;
+                  const float3 q = backproject(cam, iq, jq, __uint_as_float(kq));
+                  const float dx = q.x - p.x, dy = q.y - p.y, dz = q.z - p.z;
+                  if (dx * dx + dy * dy + dz * dz <= delta2) {
+                    expl = true;
+                    break;
+                  }
+                }
+            }
+            cnt_o = inV && !expl;
+            cnt_rem = inU && (inV || expl);
+          }
+        }
+        n_dJo += ballot_count(cnt_o);
+        n_rem += ballot_count(cnt_rem);
+      }
+    }
+    __syncthreads();  // the next band overwrites the tile
+  }
+
+  if (lane == 0) {
+    atomicAdd(&s_acc[2], n_dJr);
+    atomicAdd(&s_acc[3], n_dJo);
+    atomicAdd(&s_acc[4], n_rem);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const bool valid = s_acc[5] == 0;
+    const int res = par.goal ? (*par.ucount - s_acc[4]) : 0;
+    out_status[s] = valid ? 1 : 0;
+    out_cost[s] = valid ? s_acc[2] + s_acc[3] + res : -1;
+    if (out_comps) {  // an invalid successor stops at its first occluding band
+      out_comps[5 * s + 0] = valid ? s_acc[0] : -1;
+      out_comps[5 * s + 1] = valid ? s_acc[1] : -1;
+      out_comps[5 * s + 2] = valid ? s_acc[2] : -1;
+      out_comps[5 * s + 3] = valid ? s_acc[3] : -1;
+      out_comps[5 * s + 4] = valid ? res : -1;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+static int blocks_for(size_t n, int t) { return (int)std::min<size_t>((n + t - 1) / t, 65535); }
+
+void launch_fill_u32(unsigned* p, unsigned v, size_t n, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, v, n);
+}
+void launch_fill_i32(int* p, int v, size_t n, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, v, n);
+}
+
+void launch_hash_insert(const Cam& cam, const float* depth, unsigned long long* keys, int* counts,
+                        int mask, float inv_cell, int* n_points, hipStream_t s) {
+  const int n = cam.W * cam.H;
+  hipLaunchKernelGGL(k_hash_insert, dim3((n + 255) / 256), dim3(256), 0, s, cam, depth, keys,
+                     counts, mask, inv_cell, n_points);
+}
+void launch_scan_cells(const int* counts, int2* cells, int n_slots, hipStream_t s) {
+  hipLaunchKernelGGL(k_scan_cells, dim3(1), dim3(1024), 0, s, counts, cells, n_slots);
+}
+void launch_hash_scatter(const Cam& cam, const float* depth, const unsigned long long* keys,
+                         const int2* cells, int* fill, float4* pts, int mask, float inv_cell,
+                         hipStream_t s) {
+  const int n = cam.W * cam.H;
+  hipLaunchKernelGGL(k_hash_scatter, dim3((n + 255) / 256), dim3(256), 0, s, cam, depth, keys,
+                     cells, fill, pts, mask, inv_cell);
+}
+
+void launch_render_object(const Cam& cam, const Meshes& M, const float4* poses, int mesh,
+                          int pose, int n_tris, unsigned* depth_bits, hipStream_t s) {
+  if (n_tris <= 0) return;
+  hipLaunchKernelGGL(k_render_object, dim3((n_tris + 127) / 128), dim3(128), 0, s, cam, M,
+                     poses, mesh, pose, depth_bits);
+}
+
+void launch_parent_u(const Cam& cam, const Meshes& M, const float4* poses, const float* obs,
+                     const int* par_mesh_pose, int j, const unsigned* depth_bits, unsigned* ubits,
+                     int* ucount, const EvalParams& ep, hipStream_t s) {
+  ParentObjs po;
+  for (int a = 0; a < 8; ++a)
+    po.o[a] = a < j ? make_int2(par_mesh_pose[2 * a], par_mesh_pose[2 * a + 1]) : make_int2(0, 0);
+  const int n = cam.W * cam.H;
+  hipLaunchKernelGGL(k_parent_u, dim3((n + 255) / 256), dim3(256), 0, s, cam, M, poses, obs, po,
+                     j, depth_bits, ubits, ucount, ep);
+}
+
+template <int NT>
+static hipError_t launch_eval_t(const Cam& cam, const Meshes& M, const float4* poses,
+                                const float* obs, const Hash& hs, const Parent& par,
+                                const int2* cands, int n, int* cost, int* status, int* comps,
+                                const EvalParams& ep, size_t lds, hipStream_t s) {
+  static size_t configured = 0;
+  if (lds > 65536 && lds > configured) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eval<NT>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    configured = lds;
+  }
+  hipLaunchKernelGGL(k_eval<NT>, dim3(n), dim3(NT), lds, s, cam, M, poses, obs, hs, par, cands,
+                     n, cost, status, comps, ep);
+  return hipGetLastError();
+}
+
+hipError_t launch_eval(int threads, const Cam& cam, const Meshes& M, const float4* poses,
+                       const float* obs, const Hash& hs, const Parent& par, const int2* cands,
+                       int n, int* cost, int* status, int* comps, const EvalParams& ep,
+                       size_t lds_bytes, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  switch (threads) {
+    case 64:
+      return launch_eval_t<64>(cam, M, poses, obs, hs, par, cands, n, cost, status, comps, ep,
+                               lds_bytes, s);
+    case 128:
+      return launch_eval_t<128>(cam, M, poses, obs, hs, par, cands, n, cost, status, comps, ep,
+                                lds_bytes, s);
+    default:
+      return launch_eval_t<256>(cam, M, poses, obs, hs, par, cands, n, cost, status, comps, ep,
+                                lds_bytes, s);
+  }
+}
+
+}  // namespace perch

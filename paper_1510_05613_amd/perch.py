@@ -1,0 +1,283 @@
+"""Python binding of libperch.so (the C ABI in include/perch.h).
+
+Argument marshalling only: every step of PERCH's successor evaluation runs in the
+HIP kernels of libperch.so.  torch supplies device memory (tensors on the GPU) and
+the HIP stream.  There is no CPU path: if the library is missing, or no GPU is
+present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libperch.so")
+
+PERCH_SUCC_VALID = 1
+PERCH_SUCC_INVALID = 0
+PERCH_SUCC_NEAR_PLANE = -2
+PERCH_SUCC_TOO_WIDE = -3
+PERCH_SUCC_BAD_INPUT = -4
+
+# the public symbols declared in include/perch.h
+EXPORTS = ("perch_create", "perch_destroy", "perch_set_observation", "perch_add_mesh",
+           "perch_set_poses", "perch_set_objects", "perch_eval_successors", "perch_set_parent",
+           "perch_eval_children", "perch_render", "perch_set_tuning", "perch_get_info",
+           "perch_search", "perch_last_error")
+
+SEARCH_EXHAUSTIVE, SEARCH_UCS, SEARCH_FOCAL = 0, 1, 2
+
+
+class PerchError(RuntimeError):
+    pass
+
+
+class _Sensor(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("fx", C.c_float),
+                ("fy", C.c_float), ("cx", C.c_float), ("cy", C.c_float),
+                ("cam_from_world", C.c_float * 12), ("delta", C.c_float)]
+
+
+class PerchObject(C.Structure):
+    _fields_ = [("mesh_id", C.c_int32), ("pose_idx", C.c_int32)]
+
+
+class _SearchOpts(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("w", C.c_float), ("anytime", C.c_int32),
+                ("budget_s", C.c_double), ("budget_expansions", C.c_int64),
+                ("pose_subset", C.c_void_p), ("n_pose_subset", C.c_int32)]
+
+
+class _Result(C.Structure):
+    _fields_ = [("objs", PerchObject * 8), ("K", C.c_int32), ("found", C.c_int32),
+                ("cost", C.c_int64), ("edge_cost", C.c_int32 * 8), ("n_expanded", C.c_int64),
+                ("n_evaluated", C.c_int64), ("n_invalid", C.c_int64), ("t_total_s", C.c_double),
+                ("t_best_s", C.c_double), ("lower_bound", C.c_int64)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Loads libperch.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise PerchError(f"{path} is missing: build it with paper_1510_05613_amd.build.build()")
+    L = C.CDLL(path)
+    P, I32 = C.c_void_p, C.c_int32
+    L.perch_create.argtypes = [C.POINTER(_Sensor), P, C.POINTER(P)]
+    L.perch_destroy.argtypes = [P]
+    L.perch_destroy.restype = None
+    L.perch_set_observation.argtypes = [P, P]
+    L.perch_add_mesh.argtypes = [P, I32, P, I32, P, I32, P, I32]
+    L.perch_set_poses.argtypes = [P, P, I32]
+    L.perch_set_objects.argtypes = [P, P, I32]
+    L.perch_eval_successors.argtypes = [P, P, I32, P, I32, P, P, P]
+    L.perch_set_parent.argtypes = [P, P, I32]
+    L.perch_eval_children.argtypes = [P, P, I32, P, P, P]
+    L.perch_render.argtypes = [P, P, I32, I32, P]
+    L.perch_set_tuning.argtypes = [P, I32, I32, C.c_float]
+    L.perch_get_info.argtypes = [P, C.POINTER(I32), C.POINTER(I32)]
+    L.perch_search.argtypes = [P, C.POINTER(_SearchOpts), C.POINTER(_Result)]
+    L.perch_last_error.restype = C.c_char_p
+    for name in EXPORTS:
+        if name not in ("perch_destroy", "perch_last_error"):
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != 0:
+        msg = load().perch_last_error().decode(errors="replace")
+        raise PerchError(f"perch error {rc}: {msg}")
+
+
+def _objects(objs) -> C.Array:
+    arr = (PerchObject * max(1, len(objs)))()
+    for k, (m, p) in enumerate(objs):
+        arr[k].mesh_id = int(m)
+        arr[k].pose_idx = int(p)
+    return arr
+
+
+def _dev_ptr(t, dtype_name: str, numel: Optional[int] = None) -> int:
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise PerchError("expected a GPU tensor")
+    if str(t.dtype) != f"torch.{dtype_name}" or not t.is_contiguous():
+        raise PerchError(f"expected a contiguous {dtype_name} tensor, got {t.dtype}")
+    if numel is not None and t.numel() < numel:
+        raise PerchError(f"tensor has {t.numel()} elements, need {numel}")
+    return t.data_ptr()
+
+
+class Context:
+    """One scene on one GPU: sensor, observation, mesh library, pose table, objects."""
+
+    def __init__(self, sensor, stream=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise PerchError("no GPU: libperch.so has no CPU path")
+        L = load()
+        s = _Sensor()
+        s.width, s.height = int(sensor.W), int(sensor.H)
+        s.fx, s.fy, s.cx, s.cy = sensor.fx, sensor.fy, sensor.cx, sensor.cy
+        M = np.asarray(sensor.cam_from_world, np.float32).reshape(-1)
+        for i in range(12):
+            s.cam_from_world[i] = float(M[i])
+        s.delta = float(sensor.delta)
+        self.sensor = sensor
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        _check(L.perch_create(C.byref(s), C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+        self.H, self.W = int(sensor.H), int(sensor.W)
+        self.K = 0
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().perch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_observation(self, depth):
+        _check(load().perch_set_observation(self.h, _dev_ptr(depth, "float32", self.H * self.W)))
+
+    def add_mesh(self, mesh_id: int, verts, tris, planes):
+        v = np.ascontiguousarray(verts, np.float32)
+        t = np.ascontiguousarray(tris, np.int32)
+        p = np.ascontiguousarray(planes, np.float32)
+        _check(load().perch_add_mesh(self.h, mesh_id, v.ctypes.data, len(v), t.ctypes.data,
+                                     len(t), p.ctypes.data, len(p)))
+
+    def set_poses(self, poses):
+        p = np.ascontiguousarray(poses, np.float32)
+        _check(load().perch_set_poses(self.h, p.ctypes.data, len(p)))
+
+    def set_objects(self, mesh_ids: Sequence[int]):
+        m = np.ascontiguousarray(mesh_ids, np.int32)
+        _check(load().perch_set_objects(self.h, m.ctypes.data, len(m)))
+        self.K = len(m)
+
+    def set_tuning(self, threads: int = 0, tile_px: int = 0, cell_over_delta: float = 0.0):
+        _check(load().perch_set_tuning(self.h, threads, tile_px, cell_over_delta))
+
+    def info(self):
+        n, h = C.c_int32(), C.c_int32()
+        _check(load().perch_get_info(self.h, C.byref(n), C.byref(h)))
+        return dict(n_points=n.value, halo=h.value)
+
+    def eval_successors(self, parent, cands, cost, status, comps=None):
+        """parent: sequence of (mesh, pose); cands: int32 GPU tensor (n, 2); outputs:
+        int32 GPU tensors (n,), (n,), and optionally (n, 5).  Asynchronous."""
+        n = cands.shape[0]
+        par = _objects(parent)
+        _check(load().perch_eval_successors(
+            self.h, C.cast(par, C.c_void_p), len(parent), _dev_ptr(cands, "int32", 2 * n), n,
+            _dev_ptr(cost, "int32", n), _dev_ptr(status, "int32", n),
+            None if comps is None else _dev_ptr(comps, "int32", 5 * n)))
+
+    def set_parent(self, parent):
+        """Materialises the parent state R_j (and U at the goal level)."""
+        _check(load().perch_set_parent(self.h, C.cast(_objects(parent), C.c_void_p),
+                                       len(parent)))
+
+    def eval_children(self, cands, cost, status, comps=None):
+        """Successors of the parent last set; same tensors as eval_successors."""
+        n = cands.shape[0]
+        _check(load().perch_eval_children(
+            self.h, _dev_ptr(cands, "int32", 2 * n), n, _dev_ptr(cost, "int32", n),
+            _dev_ptr(status, "int32", n),
+            None if comps is None else _dev_ptr(comps, "int32", 5 * n)))
+
+    def evaluate(self, parent, cands, with_comps: bool = True):
+        """Convenience: allocates outputs, evaluates and returns GPU tensors."""
+        import torch
+
+        n = cands.shape[0]
+        dev = cands.device
+        cost = torch.empty(n, dtype=torch.int32, device=dev)
+        status = torch.empty(n, dtype=torch.int32, device=dev)
+        comps = torch.empty((n, 5), dtype=torch.int32, device=dev) if with_comps else None
+        self.eval_successors(parent, cands, cost, status, comps)
+        return status, cost, comps
+
+    def search(self, mode: int = SEARCH_UCS, w: float = 1.0, anytime: bool = False,
+               budget_s: float = 0.0, budget_expansions: int = 0, pose_subset=None) -> dict:
+        """Tree search of Alg. 1 on this scene (synchronous).  Returns the goal in
+        insertion order plus its canonical (sorted) form, cost and statistics."""
+        o = _SearchOpts()
+        o.mode, o.w, o.anytime = int(mode), float(w), int(bool(anytime))
+        o.budget_s, o.budget_expansions = float(budget_s), int(budget_expansions)
+        sub = None
+        if pose_subset is not None:
+            sub = np.ascontiguousarray(pose_subset, np.int32)
+            o.pose_subset, o.n_pose_subset = sub.ctypes.data, len(sub)
+        r = _Result()
+        rc = load().perch_search(self.h, C.byref(o), C.byref(r))
+        if rc not in (0, -6):
+            _check(rc)
+        objs = [(r.objs[k].mesh_id, r.objs[k].pose_idx) for k in range(r.K)] if r.found else []
+        return dict(found=bool(r.found), budget_exhausted=(rc == -6), objs=objs,
+                    canonical=sorted(objs), cost=int(r.cost),
+                    edge_cost=[int(r.edge_cost[k]) for k in range(r.K)] if r.found else [],
+                    n_expanded=int(r.n_expanded), n_evaluated=int(r.n_evaluated),
+                    n_invalid=int(r.n_invalid), t_total_s=float(r.t_total_s),
+                    t_best_s=float(r.t_best_s), lower_bound=int(r.lower_bound))
+
+    def render(self, objs, composite: bool = True):
+        """Depth images (+inf = empty) of objects [(mesh, pose), ...]."""
+        import torch
+
+        n = len(objs)
+        shape = (self.H, self.W) if composite else (n, self.H, self.W)
+        out = torch.empty(shape, dtype=torch.float32, device="cuda")
+        _check(load().perch_render(self.h, C.cast(_objects(objs), C.c_void_p), n,
+                                   1 if composite else 0, out.data_ptr()))
+        return out
+
+
+def context_from_scene(scene, depth=None, stream=None) -> Context:
+    """Context loaded with a generated scene (observation on the GPU)."""
+    import torch
+
+    ctx = Context(scene.sensor, stream)
+    for m, mesh in enumerate(scene.library.meshes):
+        ctx.add_mesh(m, mesh.verts, mesh.tris, mesh.planes)
+    ctx.set_poses(scene.poses)
+    ctx.set_objects(scene.obj_mesh)
+    d = scene.depth_obs if depth is None else depth
+    ctx.set_observation(torch.as_tensor(np.ascontiguousarray(d, np.float32)).cuda())
+    return ctx
+
+
+class GpuRenderer:
+    """Renderer callback for the scene generator, backed by perch_render."""
+
+    def __init__(self):
+        self._cache = {}
+
+    def __call__(self, sensor, library, mesh_ids, pose_idx, poses):
+        key = (id(sensor), id(library), id(poses))
+        ctx = self._cache.get(key)
+        if ctx is None:
+            ctx = Context(sensor)
+            for m, mesh in enumerate(library.meshes):
+                ctx.add_mesh(m, mesh.verts, mesh.tris, mesh.planes)
+            ctx.set_poses(poses)
+            self._cache = {key: ctx}
+        D = ctx.render(list(zip(mesh_ids, pose_idx)), composite=False)
+        return D.double().cpu().numpy()

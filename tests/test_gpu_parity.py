@@ -1,0 +1,208 @@
+"""GPU parity: libperch.so (through the C ABI) against the CPU oracle on the same
+seeded scenes.  Rule (edge cost of Eq. (4), validity of Eq. (3)):
+  - status equal unless the oracle flags a parent/candidate depth tie within 1e-6 m;
+  - both valid: |cost_gpu - cost_oracle| <= n_flag_delta + n_flag_vol (points the
+    oracle finds within 1e-6 m of delta, or of a volume boundary), and equal when
+    both flag counts are 0; silhouette and |dR| counts are integer coverage and
+    must be equal;
+  - depth within 1e-4 m where both renderers cover a pixel, with identical coverage.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import Oracle  # noqa: E402
+from paper_1510_05613_amd import perch, scenes  # noqa: E402
+from tests import helpers as H  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    perch.load()
+
+
+def _cands(mesh, pose):
+    c = np.stack([np.asarray(mesh, np.int32), np.asarray(pose, np.int32)], 1)
+    return torch.as_tensor(np.ascontiguousarray(c)).cuda()
+
+
+def _gpu_eval(ctx, parent, mesh, pose):
+    st, cost, comps = ctx.evaluate(parent, _cands(mesh, pose))
+    torch.cuda.synchronize()
+    return st.cpu().numpy(), cost.cpu().numpy(), comps.cpu().numpy()
+
+
+def compare(g, o, label=""):
+    st_g, cost_g, comps_g = g
+    st_o, cost_o, comps_o, flags_o = o
+    tie = flags_o[:, 2] == 1
+    bad = (st_g != st_o) & ~tie
+    assert not bad.any(), f"{label}: status mismatch at {np.nonzero(bad)[0][:10]}"
+    both = (st_g == 1) & (st_o == 1)
+    tol = flags_o[:, 0] + flags_o[:, 1]
+    d = np.abs(cost_g.astype(np.int64) - cost_o)
+    over = both & (d > tol)
+    assert not over.any(), (f"{label}: cost mismatch at {np.nonzero(over)[0][:10]}: "
+                            f"gpu {cost_g[over][:5]} oracle {cost_o[over][:5]} tol {tol[over][:5]}")
+    cov = both & np.any(comps_g[:, :2] != comps_o[:, :2], axis=1)
+    assert not cov.any(), f"{label}: coverage counts differ at {np.nonzero(cov)[0][:10]}"
+    assert np.all(st_g >= 0), f"{label}: error status {np.unique(st_g)}"
+    return dict(n=len(st_g), valid=int(both.sum()), flagged=int((both & (tol > 0)).sum()),
+                flag_diff=int((both & (d > 0)).sum()))
+
+
+@pytest.fixture(scope="module")
+def c1():
+    out = []
+    for i in range(3):
+        sc = H.c1_scene(i)
+        out.append((sc, Oracle.from_scene(sc, nthreads=8), perch.context_from_scene(sc)))
+    return out
+
+
+def test_render_matches_oracle_coverage_and_depth(c1):
+    sc, o, ctx = c1[0]
+    rng = np.random.default_rng(0)
+    worst = 0.0
+    for _ in range(30):
+        m = int(rng.integers(len(sc.library.meshes)))
+        p = int(rng.integers(sc.grid.P))
+        Dg = ctx.render([(m, p)]).cpu().numpy().astype(np.float64)
+        Do = o.render_objects([m], [p])[0]
+        assert np.array_equal(np.isfinite(Dg), np.isfinite(Do))
+        f = np.isfinite(Do)
+        if f.any():
+            err = np.abs(Dg[f] - Do[f]).max()
+            worst = max(worst, err)
+            assert err <= 1e-4
+    assert worst < 1e-5
+
+
+def test_render_matches_oracle_640x480():
+    sc = H.c2_scene(0)
+    o = Oracle.from_scene(sc)
+    ctx = perch.context_from_scene(sc)
+    D = ctx.render(list(zip(sc.obj_mesh, sc.gt_pose)), composite=False).cpu().numpy()
+    Do = o.render_objects(sc.obj_mesh, sc.gt_pose)
+    assert np.array_equal(np.isfinite(D), np.isfinite(Do))
+    f = np.isfinite(Do)
+    assert np.abs(D[f] - Do[f]).max() < 1e-4
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_level1_all_successors_160x120(c1, k):
+    sc, o, ctx = c1[k]
+    ms = np.repeat(np.unique(sc.obj_mesh), sc.grid.P)
+    ps = np.tile(np.arange(sc.grid.P), len(np.unique(sc.obj_mesh)))
+    g = _gpu_eval(ctx, [], ms, ps)
+    r = o.eval([], [], ms, ps)
+    s = compare(g, r, f"c1[{k}] level 1")
+    assert s["valid"] == len(ms)  # nothing to occlude at the root
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_goal_level_successors_160x120(c1, k):
+    """Level 2 = goal level for K = 2: exercises the residual set U."""
+    sc, o, ctx = c1[k]
+    rng = np.random.default_rng(10 + k)
+    first = sc.gt_order[0]
+    parents = [(int(sc.obj_mesh[first]), int(sc.gt_pose[first]))]
+    for _ in range(3):
+        parents.append((int(sc.obj_mesh[first]), int(rng.integers(sc.grid.P))))
+    other = int(sc.obj_mesh[sc.gt_order[1]])
+    for par in parents:
+        ms = np.full(sc.grid.P, other)
+        ps = np.arange(sc.grid.P)
+        g = _gpu_eval(ctx, [par], ms, ps)
+        r = o.eval([par[0]], [par[1]], ms, ps)
+        s = compare(g, r, f"c1[{k}] goal under {par}")
+        assert s["valid"] > 0
+
+
+def test_empty_and_ragged_batches(c1):
+    sc, o, ctx = c1[0]
+    # n = 0 is a no-op
+    st, cost, comps = ctx.evaluate([], torch.zeros((0, 2), dtype=torch.int32, device="cuda"))
+    torch.cuda.synchronize()
+    assert st.numel() == 0
+    # ragged sizes and a single successor
+    for n in (1, 7, 65, 257):
+        ms = np.full(n, sc.obj_mesh[0])
+        ps = np.arange(n) % sc.grid.P
+        compare(_gpu_eval(ctx, [], ms, ps), o.eval([], [], ms, ps), f"n={n}")
+
+
+def test_out_of_range_candidates_are_rejected(c1):
+    sc, o, ctx = c1[0]
+    st, cost, comps = _gpu_eval(ctx, [], [0, 99, 0, -1], [0, 0, sc.grid.P, 5])
+    assert st.tolist() == [1, perch.PERCH_SUCC_BAD_INPUT, perch.PERCH_SUCC_BAD_INPUT,
+                           perch.PERCH_SUCC_BAD_INPUT]
+
+
+def test_results_independent_of_tuning(c1):
+    """Threads per successor, z-tile size (forcing several row bands) and voxel
+    cell size change nothing (the kernel's determinism / race check)."""
+    sc, o, ctx = c1[1]
+    first = sc.gt_order[0]
+    par = [(int(sc.obj_mesh[first]), int(sc.gt_pose[first]))]
+    other = int(sc.obj_mesh[sc.gt_order[1]])
+    ms = np.full(sc.grid.P, other)
+    ps = np.arange(sc.grid.P)
+    ref = _gpu_eval(ctx, par, ms, ps)
+    for threads, tile, cell in [(64, 0, 0), (128, 0, 1.0), (256, 300, 3.0), (64, 260, 2.0)]:
+        ctx.set_tuning(threads, tile, cell)
+        got = _gpu_eval(ctx, par, ms, ps)
+        for a, b in zip(ref, got):
+            assert np.array_equal(a, b), (threads, tile, cell)
+    ctx.set_tuning(256, 12288, 2.0)
+
+
+@pytest.fixture(scope="module")
+def c2():
+    sc = H.c2_scene(0)
+    return sc, Oracle.from_scene(sc, nthreads=8), perch.context_from_scene(sc)
+
+
+def test_640x480_levels_sampled(c2):
+    """Config-2 scene: every level, the launch evaluates the full successor set
+    (as the benchmark does) and a seeded sample is checked against the oracle."""
+    sc, o, ctx = c2
+    rng = np.random.default_rng(5)
+    order = sc.gt_order
+    for level in range(sc.K):
+        par = [(int(sc.obj_mesh[k]), int(sc.gt_pose[k])) for k in order[:level]]
+        rest = [int(sc.obj_mesh[k]) for k in order[level:]]
+        ms = np.repeat(rest, sc.grid.P)
+        ps = np.tile(np.arange(sc.grid.P), len(rest))
+        g = _gpu_eval(ctx, par, ms, ps)
+        assert np.all(g[0] >= 0)
+        # the ground-truth child and a random sample
+        gt_idx = [rest.index(int(sc.obj_mesh[order[level]])) * sc.grid.P +
+                  int(sc.gt_pose[order[level]])]
+        idx = np.unique(np.concatenate([gt_idx, rng.choice(len(ms), 150, replace=False)]))
+        r = o.eval([p[0] for p in par], [p[1] for p in par], ms[idx], ps[idx])
+        s = compare(tuple(a[idx] for a in g), r, f"c2 level {level + 1}")
+        assert s["valid"] > 0
+        assert g[0][gt_idx[0]] == 1
+
+
+def test_640x480_banded_tiles_match(c2):
+    """A small z-tile forces several row bands per successor: same results."""
+    sc, o, ctx = c2
+    order = sc.gt_order
+    par = [(int(sc.obj_mesh[order[0]]), int(sc.gt_pose[order[0]]))]
+    m = int(sc.obj_mesh[order[1]])
+    ps = np.arange(0, sc.grid.P, 97)
+    ms = np.full(len(ps), m)
+    ref = _gpu_eval(ctx, par, ms, ps)
+    ctx.set_tuning(0, 3000, 0)
+    got = _gpu_eval(ctx, par, ms, ps)
+    ctx.set_tuning(0, 12288, 0)
+    assert np.all(ref[0] >= 0) and np.all(got[0] >= 0)
+    for a, b in zip(ref, got):
+        assert np.array_equal(a, b)
