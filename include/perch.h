@@ -138,10 +138,12 @@ perch_status perch_render(perch_ctx* ctx, const perch_object* objs, int32_t n,
                           int32_t composite, float* depth_dev);
 
 /* Tuning knobs of the successor kernel: threads per successor (64, 128 or 256),
- * z-tile capacity in pixels (LDS), and voxel cell size in units of delta
- * (>= 1).  Pass 0 to keep a value.  Results do not depend on them. */
+ * z-tile capacity in pixels (LDS), voxel cell size in units of delta (>= 1), and
+ * the radius query behind dJ_r (0 = exact pixel window over the observed depth,
+ * 1 = uniform voxel hash of the observed cloud).  Pass 0 (radius_mode: -1) to keep
+ * a value.  Results do not depend on them. */
 perch_status perch_set_tuning(perch_ctx* ctx, int32_t threads, int32_t tile_px,
-                              float cell_over_delta);
+                              float cell_over_delta, int32_t radius_mode);
 
 /* Observed point count |I| and the pixel window halo (host outputs). */
 perch_status perch_get_info(perch_ctx* ctx, int32_t* n_points, int32_t* halo);

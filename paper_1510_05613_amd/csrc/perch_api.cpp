@@ -87,8 +87,10 @@ static perch_status upload_meshes(perch_ctx* c) {
   return PERCH_OK;
 }
 
+// vertex cache + z-tile + one 128-entry triangle ring per wave
 static size_t eval_lds_bytes(const perch_ctx* c) {
-  return (size_t)c->max_nv * sizeof(int2) + (size_t)c->tile_px * sizeof(unsigned);
+  return (size_t)c->max_nv * sizeof(int2) + (size_t)c->tile_px * sizeof(unsigned) +
+         (size_t)(c->threads / 64) * 128 * sizeof(unsigned);
 }
 
 static bool objects_ok(const perch_ctx* c, const perch_object* o, int n) {
@@ -193,7 +195,7 @@ void perch_destroy(perch_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
   for (DevBuf* b : {&c->verts, &c->tris, &c->planes, &c->range, &c->frange, &c->aabb, &c->poses,
-                    &c->obs, &c->h_keys, &c->h_cells, &c->h_pts, &c->h_counts, &c->par_depth,
+                    &c->obs, &c->obs_range, &c->h_keys, &c->h_cells, &c->h_pts, &c->h_counts, &c->par_depth,
                     &c->par_ubits, &c->par_ucount, &c->s_cands, &c->s_out})
     b->release();
   c->s_hcands.release();
@@ -232,6 +234,8 @@ static perch_status build_observation(perch_ctx* c) {
   c->ep.halo = halo;
   c->ep.dwin = (float)dwin;
   c->n_points = n;
+  HIP_TRY(c->obs_range.ensure(npx * sizeof(float2)));
+  launch_obs_range(cam, c->obs.as<float>(), c->obs_range.as<float2>(), halo, c->stream);
   // voxel hash of I
   const int slots = next_pow2(std::max(64, 2 * n));
   c->h_mask = slots - 1;
@@ -306,8 +310,10 @@ perch_status perch_set_objects(perch_ctx* c, const int32_t* mesh_ids, int32_t K)
 }
 
 perch_status perch_set_tuning(perch_ctx* c, int32_t threads, int32_t tile_px,
-                              float cell_over_delta) {
+                              float cell_over_delta, int32_t radius_mode) {
   if (!c) return fail(PERCH_E_ARG, "null context");
+  if (radius_mode < -1 || radius_mode > 1) return fail(PERCH_E_ARG, "radius_mode must be -1, 0 or 1");
+  if (radius_mode >= 0) c->radius_mode = radius_mode;
   if (threads && threads != 64 && threads != 128 && threads != 256)
     return fail(PERCH_E_ARG, "threads must be 64, 128 or 256");
   if (tile_px && (tile_px < 256 || tile_px > 36864)) return fail(PERCH_E_ARG, "bad tile_px");
@@ -373,8 +379,9 @@ perch_status perch_eval_children(perch_ctx* c, const perch_object* cands_dev, in
   ep.max_nv = c->max_nv;
   ep.n_mesh = (int)c->meshes.size();
   ep.n_poses = c->P;
+  ep.radius_mode = c->radius_mode;
   HIP_TRY(launch_eval(c->threads, c->cam, c->dev_meshes(), c->poses.as<float4>(),
-                      c->obs.as<float>(), c->dev_hash(), par,
+                      c->obs.as<float>(), c->obs_range.as<float2>(), c->dev_hash(), par,
                       reinterpret_cast<const int2*>(cands_dev), n, cost_dev, status_dev, comps_dev,
                       ep, lds, c->stream));
   return PERCH_OK;

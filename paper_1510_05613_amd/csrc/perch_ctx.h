@@ -107,7 +107,7 @@ struct perch_ctx {
   // known objects
   std::vector<int32_t> objects;
   // observation and hash
-  DevBuf obs;
+  DevBuf obs, obs_range;
   bool has_obs = false;
   int n_points = 0;
   DevBuf h_keys, h_cells, h_pts, h_counts;
@@ -121,7 +121,8 @@ struct perch_ctx {
   PinnedBuf s_hcands, s_hout;
   // tuning
   int threads = 256;
-  int tile_px = 12288;
+  int tile_px = 8192;
+  int radius_mode = 0;
   EvalParams ep{};
 
   Meshes dev_meshes() const {

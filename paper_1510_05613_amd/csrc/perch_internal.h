@@ -60,6 +60,7 @@ struct EvalParams {
   float dwin;   // window radius in metres (delta with a rounding margin)
   int n_mesh;   // candidates with mesh_id outside [0, n_mesh) or pose_idx outside
   int n_poses;  // [0, n_poses) are rejected with status -4
+  int radius_mode;  // dJ_r query: 0 exact pixel window, 1 voxel hash
 };
 
 // ---- launchers (perch_kernels.hip) ----
@@ -78,8 +79,10 @@ void launch_parent_u(const Cam& cam, const Meshes& M, const float4* poses, const
                      const int* par_mesh_pose, int j, const unsigned* depth_bits,
                      unsigned* ubits, int* ucount, const EvalParams& ep, hipStream_t s);
 void launch_bits_to_float(const unsigned* bits, float* out, size_t n, hipStream_t s);
+void launch_obs_range(const Cam& cam, const float* obs, float2* out, int R, hipStream_t s);
 hipError_t launch_eval(int threads, const Cam& cam, const Meshes& M, const float4* poses,
-                 const float* obs, const Hash& hs, const Parent& par, const int2* cands,
+                 const float* obs, const float2* obs_range, const Hash& hs, const Parent& par,
+                 const int2* cands,
                  int n, int* cost, int* status, int* comps, const EvalParams& ep,
                  size_t lds_bytes, hipStream_t s);
 

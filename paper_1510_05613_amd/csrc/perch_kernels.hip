@@ -40,6 +40,20 @@ __device__ __forceinline__ int wave_max(int v) {
 }
 __device__ __forceinline__ int ballot_count(bool p) { return __popcll(__ballot(p)); }
 
+// Number of set bits of m below this lane.
+__device__ __forceinline__ unsigned lanes_below(unsigned long long m) {
+  return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
+// Orders this wave's LDS accesses: writes before the call are visible to every lane
+// of the wave after it (a wave issues LDS operations in order; this stops the
+// compiler from moving them across).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ---------------------------------------------------------------------------
 // vertex stage (float32, fixed operation order)
 // ---------------------------------------------------------------------------
@@ -98,9 +112,39 @@ __device__ __forceinline__ Plane64 make_plane(const Cam& c, float ax, float ay, 
   return p;
 }
 
+// FP64 reciprocal estimate refined by two Newton steps (ample for the final
+// rounding to float32).
 __device__ __forceinline__ float plane_depth(const Plane64& p, int i, int j) {
-  const double den = p.A * (double)i + p.B * (double)j + p.C;
-  return (float)(p.N / den);
+  const double den = fma(p.A, (double)i, fma(p.B, (double)j, p.C));
+  double r = __builtin_amdgcn_rcp(den);
+  r = fma(r, fma(-den, r, 1.0), r);
+  r = fma(r, fma(-den, r, 1.0), r);
+  return (float)(p.N * r);
+}
+
+// Camera-space vertex for the depth plane only: the placement and camera
+// rotation folded into one 3x3 map plus offset (FMA).  Coverage never uses it;
+// it differs from the snapped vertex stage by float rounding only.
+struct PoseMap {
+  float a[9], b[3];
+};
+
+__device__ __forceinline__ PoseMap make_pose_map(const Cam& c, const float4 pz) {
+  PoseMap m;
+  for (int r = 0; r < 3; ++r) {
+    m.a[3 * r + 0] = fmaf(c.M[4 * r], pz.z, c.M[4 * r + 1] * pz.w);
+    m.a[3 * r + 1] = fmaf(c.M[4 * r + 1], pz.z, -(c.M[4 * r] * pz.w));
+    m.a[3 * r + 2] = c.M[4 * r + 2];
+    m.b[r] = fmaf(c.M[4 * r], pz.x, fmaf(c.M[4 * r + 1], pz.y, c.M[4 * r + 3]));
+  }
+  return m;
+}
+
+__device__ __forceinline__ void map_vertex(const PoseMap& m, const float4 v, float& X, float& Y,
+                                           float& Z) {
+  X = fmaf(m.a[0], v.x, fmaf(m.a[1], v.y, fmaf(m.a[2], v.z, m.b[0])));
+  Y = fmaf(m.a[3], v.x, fmaf(m.a[4], v.y, fmaf(m.a[5], v.z, m.b[1])));
+  Z = fmaf(m.a[6], v.x, fmaf(m.a[7], v.y, fmaf(m.a[8], v.z, m.b[2])));
 }
 
 // ---------------------------------------------------------------------------
@@ -171,6 +215,19 @@ __device__ __forceinline__ void raster_tri(int x0, int y0, int x1, int y1, int x
       }
     }
   }
+}
+
+// True when the triangle is front-facing (negative snapped area) and its box
+// holds at least one pixel centre inside columns [c0, c1] and rows [r0, r1]: the
+// triangles raster_tri can emit for.
+__device__ __forceinline__ bool tri_candidate(int x0, int y0, int x1, int y1, int x2, int y2,
+                                              int c0, int c1, int r0, int r1) {
+  const int xmin = min(x0, min(x1, x2)), xmax = max(x0, max(x1, x2));
+  const int ymin = min(y0, min(y1, y2)), ymax = max(y0, max(y1, y2));
+  if (max(c0, ceil256(xmin)) > min(c1, floor256(xmax))) return false;
+  if (max(r0, ceil256(ymin)) > min(r1, floor256(ymax))) return false;
+  const long long area = (long long)(x1 - x0) * (y2 - y0) - (long long)(y1 - y0) * (x2 - x0);
+  return area < 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -286,6 +343,27 @@ __global__ void k_fill_i32(int* p, int v, size_t n) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
        i += (size_t)gridDim.x * blockDim.x)
     p[i] = v;
+}
+
+// Per pixel: the least and greatest observed depth within the (2R+1)^2 window
+// around it ((+inf, -inf) when the window holds no return).  Every observed point
+// within delta of a point q seen at that pixel lies in its pixel window (radius
+// <= R), so |z_p - z_q| <= delta fails for all of them when z_q is outside
+// [min - delta, max + delta].
+__global__ void k_obs_range(Cam cam, const float* obs, float2* out, int R) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= cam.W * cam.H) return;
+  const int i = k % cam.W, j = k / cam.W;
+  float lo = INFINITY, hi = -INFINITY;
+  for (int jj = max(0, j - R); jj <= min(cam.H - 1, j + R); ++jj)
+    for (int ii = max(0, i - R); ii <= min(cam.W - 1, i + R); ++ii) {
+      const float z = obs[jj * cam.W + ii];
+      if (z > 0.0f) {
+        lo = fminf(lo, z);
+        hi = fmaxf(hi, z);
+      }
+    }
+  out[k] = make_float2(lo, hi);
 }
 
 // ---------------------------------------------------------------------------
@@ -441,7 +519,7 @@ __global__ void k_parent_u(Cam cam, Meshes M, const float4* poses, const float* 
 template <int NT>
 __global__ void __launch_bounds__(NT)
     k_eval(Cam cam, Meshes M, const float4* __restrict__ poses, const float* __restrict__ obs,
-           Hash hs, Parent par, const int2* __restrict__ cands, int n, int* __restrict__ out_cost,
+           const float2* __restrict__ obs_range, Hash hs, Parent par, const int2* __restrict__ cands, int n, int* __restrict__ out_cost,
            int* __restrict__ out_status, int* __restrict__ out_comps, EvalParams ep) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_bb[4];
@@ -466,6 +544,7 @@ __global__ void __launch_bounds__(NT)
   const int4 rg = M.range[mesh];
   int2* suv = reinterpret_cast<int2*>(smem);
   unsigned* tile = reinterpret_cast<unsigned*>(smem + (size_t)ep.max_nv * sizeof(int2));
+  unsigned* ring = tile + ep.tile_px + (tid >> 6) * 128;  // this wave's triangle queue
   if (tid < 4) s_bb[tid] = tid < 2 ? INT_MAX : INT_MIN;
   if (tid < 8) s_acc[tid] = 0;
   __syncthreads();
@@ -538,23 +617,49 @@ __global__ void __launch_bounds__(NT)
     __syncthreads();
 
     // ---- rasterise the candidate into the z-tile (rows t0..t1) ----
-    for (int t = tid; t < rg.w; t += NT) {
-      const int4 tr = M.tris[rg.z + t];
-      const int2 a = suv[tr.x], b = suv[tr.y], c = suv[tr.z];
-      bool have = false;
-      Plane64 pl;
-      raster_tri(a.x, a.y, b.x, b.y, c.x, c.y, ca, cb, t0, t1, [&](int i, int j) {
-        if (!have) {
-          float X0, Y0, Z0, X1, Y1, Z1, X2, Y2, Z2;
-          vcam(cam, pz, M.verts[rg.x + tr.x], X0, Y0, Z0);
-          vcam(cam, pz, M.verts[rg.x + tr.y], X1, Y1, Z1);
-          vcam(cam, pz, M.verts[rg.x + tr.z], X2, Y2, Z2);
-          pl = make_plane(cam, X0, Y0, Z0, X1, Y1, Z1, X2, Y2, Z2);
-          have = true;
+    // Each wave scans 64 triangles at a time, queues the front-facing ones whose
+    // box holds a pixel centre of the tile (ballot compaction into an LDS ring),
+    // and rasterises 64 queued triangles at once, so lanes stay busy although most
+    // triangles are back-facing or fall between pixel centres.
+    {
+      const PoseMap pm = make_pose_map(cam, pz);
+      auto raster_one = [&](unsigned t) {
+        const int4 tr = M.tris[rg.z + t];
+        const int2 a = suv[tr.x], b = suv[tr.y], c = suv[tr.z];
+        bool have = false;
+        Plane64 pl;
+        raster_tri(a.x, a.y, b.x, b.y, c.x, c.y, ca, cb, t0, t1, [&](int i, int j) {
+          if (!have) {
+            float X0, Y0, Z0, X1, Y1, Z1, X2, Y2, Z2;
+            map_vertex(pm, M.verts[rg.x + tr.x], X0, Y0, Z0);
+            map_vertex(pm, M.verts[rg.x + tr.y], X1, Y1, Z1);
+            map_vertex(pm, M.verts[rg.x + tr.z], X2, Y2, Z2);
+            pl = make_plane(cam, X0, Y0, Z0, X1, Y1, Z1, X2, Y2, Z2);
+            have = true;
+          }
+          atomicMin(&tile[(j - t0) * tw + (i - ca)], __float_as_uint(plane_depth(pl, i, j)));
+        });
+      };
+      unsigned head = 0, tail = 0;  // wave-uniform ring positions
+      for (int base = (tid >> 6) * 64; base < rg.w; base += NT) {
+        const int t = base + lane;
+        bool keep = false;
+        if (t < rg.w) {
+          const int4 tr = M.tris[rg.z + t];
+          const int2 a = suv[tr.x], b = suv[tr.y], c = suv[tr.z];
+          keep = tri_candidate(a.x, a.y, b.x, b.y, c.x, c.y, ca, cb, t0, t1);
         }
-        const float z = plane_depth(pl, i, j);
-        atomicMin(&tile[(j - t0) * tw + (i - ca)], __float_as_uint(z));
-      });
+        const unsigned long long m = __ballot(keep);
+        if (keep) ring[(tail + lanes_below(m)) & 127u] = (unsigned)t;
+        tail += (unsigned)__popcll(m);
+        wave_sync();
+        if (tail - head >= 64u) {
+          raster_one(ring[(head + lane) & 127u]);
+          head += 64u;
+          wave_sync();
+        }
+      }
+      if ((unsigned)lane < tail - head) raster_one(ring[(head + lane) & 127u]);
     }
     __syncthreads();
 
@@ -586,20 +691,74 @@ __global__ void __launch_bounds__(NT)
     __syncthreads();
     if (s_acc[5]) break;
 
-    // ---- dJ_r: new points unexplained by the observed cloud (voxel hash) ----
+    // ---- dJ_r: new points unexplained by the observed cloud ----
+    // Window mode: the observed point at the same pixel usually decides
+    // "explained"; the dilated depth range decides most "unexplained"; the rest
+    // are scanned over their exact pixel window by the whole wave at once.
+    // Hash mode: range query of the voxel hash.
     {
       const int k0 = (b0 - t0) * tw, k1 = (b1 - t0 + 1) * tw;
       for (int base = k0; base < k1; base += NT) {
         const int k = base + tid;
-        bool unexp = false;
+        int state = 0;  // 1 explained, 2 unexplained, 3 undecided
+        float3 q = make_float3(0.0f, 0.0f, 0.0f);
+        int qi = 0, qj = 0;
         if (k < k1) {
           const unsigned key = tile[k];
           if (key != kInfBits) {
-            const float3 q = backproject(cam, ca + k % tw, t0 + k / tw, __uint_as_float(key));
-            unexp = !explained_by_cloud(hs, q.x, q.y, q.z, delta2);
+            qi = ca + k % tw;
+            qj = t0 + k / tw;
+            q = backproject(cam, qi, qj, __uint_as_float(key));
+            if (ep.radius_mode == 1) {
+              state = explained_by_cloud(hs, q.x, q.y, q.z, delta2) ? 1 : 2;
+            } else {
+              const int pix = qj * W + qi;
+              const float zo = obs[pix];
+              bool expl = false;
+              if (zo > 0.0f) {
+                const float3 p = backproject(cam, qi, qj, zo);
+                const float dx = p.x - q.x, dy = p.y - q.y, dz = p.z - q.z;
+                expl = dx * dx + dy * dy + dz * dz <= delta2;
+              }
+              if (expl) {
+                state = 1;
+              } else {
+                const float2 zr = obs_range[pix];
+                state = (q.z + ep.dwin < zr.x || q.z - ep.dwin > zr.y) ? 2 : 3;
+              }
+            }
           }
         }
-        n_dJr += ballot_count(unexp);
+        n_dJr += ballot_count(state == 2);
+        unsigned long long und = __ballot(state == 3);
+        while (und) {  // wave-uniform: one undecided point at a time, 64 pixels per step
+          const int src = __ffsll((long long)und) - 1;
+          und &= und - 1;
+          const int si = __shfl(qi, src, 64), sj = __shfl(qj, src, 64);
+          const float3 sq = make_float3(__shfl(q.x, src, 64), __shfl(q.y, src, 64),
+                                        __shfl(q.z, src, 64));
+          int ru, rv;
+          window_radius(cam, ep, sq, ru, rv);
+          const int wu = 2 * ru + 1, nw = wu * (2 * rv + 1);
+          bool hit = false;
+          for (int w0 = 0; w0 < nw && !hit; w0 += 64) {
+            const int w = w0 + lane;
+            bool h = false;
+            if (w < nw) {
+              const int ii = si - ru + w % wu, jj = sj - rv + w / wu;
+              if (ii >= 0 && ii < W && jj >= 0 && jj < H) {
+                const float zo = obs[jj * W + ii];
+                if (zo > 0.0f) {
+                  const float3 p = backproject(cam, ii, jj, zo);
+                  const float dx = p.x - sq.x, dy = p.y - sq.y, dz = p.z - sq.z;
+                  h = dx * dx + dy * dy + dz * dz <= delta2;
+                }
+              }
+            }
+            hit = __ballot(h) != 0;
+          }
+          n_dJr += hit ? 0 : 1;
+        }
       }
     }
 
@@ -697,6 +856,11 @@ void launch_hash_scatter(const Cam& cam, const float* depth, const unsigned long
                      cells, fill, pts, mask, inv_cell);
 }
 
+void launch_obs_range(const Cam& cam, const float* obs, float2* out, int R, hipStream_t s) {
+  const int n = cam.W * cam.H;
+  hipLaunchKernelGGL(k_obs_range, dim3((n + 255) / 256), dim3(256), 0, s, cam, obs, out, R);
+}
+
 void launch_render_object(const Cam& cam, const Meshes& M, const float4* poses, int mesh,
                           int pose, int n_tris, unsigned* depth_bits, hipStream_t s) {
   if (n_tris <= 0) return;
@@ -717,7 +881,8 @@ void launch_parent_u(const Cam& cam, const Meshes& M, const float4* poses, const
 
 template <int NT>
 static hipError_t launch_eval_t(const Cam& cam, const Meshes& M, const float4* poses,
-                                const float* obs, const Hash& hs, const Parent& par,
+                                const float* obs, const float2* obs_range, const Hash& hs,
+                                const Parent& par,
                                 const int2* cands, int n, int* cost, int* status, int* comps,
                                 const EvalParams& ep, size_t lds, hipStream_t s) {
   static size_t configured = 0;
@@ -727,25 +892,29 @@ static hipError_t launch_eval_t(const Cam& cam, const Meshes& M, const float4* p
     if (e != hipSuccess) return e;
     configured = lds;
   }
-  hipLaunchKernelGGL(k_eval<NT>, dim3(n), dim3(NT), lds, s, cam, M, poses, obs, hs, par, cands,
-                     n, cost, status, comps, ep);
+  hipLaunchKernelGGL(k_eval<NT>, dim3(n), dim3(NT), lds, s, cam, M, poses, obs, obs_range, hs,
+                     par, cands, n, cost, status, comps, ep);
   return hipGetLastError();
 }
 
 hipError_t launch_eval(int threads, const Cam& cam, const Meshes& M, const float4* poses,
-                       const float* obs, const Hash& hs, const Parent& par, const int2* cands,
+                       const float* obs, const float2* obs_range, const Hash& hs,
+                       const Parent& par, const int2* cands,
                        int n, int* cost, int* status, int* comps, const EvalParams& ep,
                        size_t lds_bytes, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   switch (threads) {
     case 64:
-      return launch_eval_t<64>(cam, M, poses, obs, hs, par, cands, n, cost, status, comps, ep,
+      return launch_eval_t<64>(cam, M, poses, obs, obs_range, hs, par, cands, n, cost, status,
+                                comps, ep,
                                lds_bytes, s);
     case 128:
-      return launch_eval_t<128>(cam, M, poses, obs, hs, par, cands, n, cost, status, comps, ep,
+      return launch_eval_t<128>(cam, M, poses, obs, obs_range, hs, par, cands, n, cost, status,
+                                comps, ep,
                                 lds_bytes, s);
     default:
-      return launch_eval_t<256>(cam, M, poses, obs, hs, par, cands, n, cost, status, comps, ep,
+      return launch_eval_t<256>(cam, M, poses, obs, obs_range, hs, par, cands, n, cost, status,
+                                comps, ep,
                                 lds_bytes, s);
   }
 }

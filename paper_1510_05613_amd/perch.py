@@ -81,7 +81,7 @@ def load(path: str = LIB_PATH):
     L.perch_set_parent.argtypes = [P, P, I32]
     L.perch_eval_children.argtypes = [P, P, I32, P, P, P]
     L.perch_render.argtypes = [P, P, I32, I32, P]
-    L.perch_set_tuning.argtypes = [P, I32, I32, C.c_float]
+    L.perch_set_tuning.argtypes = [P, I32, I32, C.c_float, I32]
     L.perch_get_info.argtypes = [P, C.POINTER(I32), C.POINTER(I32)]
     L.perch_search.argtypes = [P, C.POINTER(_SearchOpts), C.POINTER(_Result)]
     L.perch_last_error.restype = C.c_char_p
@@ -172,8 +172,10 @@ class Context:
         _check(load().perch_set_objects(self.h, m.ctypes.data, len(m)))
         self.K = len(m)
 
-    def set_tuning(self, threads: int = 0, tile_px: int = 0, cell_over_delta: float = 0.0):
-        _check(load().perch_set_tuning(self.h, threads, tile_px, cell_over_delta))
+    def set_tuning(self, threads: int = 0, tile_px: int = 0, cell_over_delta: float = 0.0,
+                   radius_mode: int = -1):
+        """Kernel knobs (0 / -1 keep the current value); results do not depend on them."""
+        _check(load().perch_set_tuning(self.h, threads, tile_px, cell_over_delta, radius_mode))
 
     def info(self):
         n, h = C.c_int32(), C.c_int32()
