@@ -182,6 +182,8 @@ perch_status perch_create(const perch_sensor* s, void* hip_stream, perch_ctx** o
   cam.dfy = s->fy;
   cam.dcx = s->cx;
   cam.dcy = s->cy;
+  cam.dinv_fx = 1.0 / (double)s->fx;
+  cam.dinv_fy = 1.0 / (double)s->fy;
   c->stream = static_cast<hipStream_t>(hip_stream);
   if (hipGetDevice(&c->device) != hipSuccess) {
     delete c;

@@ -121,7 +121,7 @@ struct perch_ctx {
   PinnedBuf s_hcands, s_hout;
   // tuning
   int threads = 256;
-  int tile_px = 8192;
+  int tile_px = 4096;
   int radius_mode = 0;
   EvalParams ep{};
 

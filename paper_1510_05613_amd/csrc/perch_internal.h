@@ -15,6 +15,7 @@ struct Cam {
   float delta, delta2;
   float inv_fx, inv_fy;
   double dfx, dfy, dcx, dcy;  // the same intrinsics widened to FP64 (depth planes)
+  double dinv_fx, dinv_fy;
 };
 
 // Uniform voxel hash of the observed cloud I (camera frame).  Cell (i, j, k) holds

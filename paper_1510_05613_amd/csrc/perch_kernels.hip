@@ -106,8 +106,8 @@ __device__ __forceinline__ Plane64 make_plane(const Cam& c, float ax, float ay, 
   const double nz = e1x * e2y - e1y * e2x;
   Plane64 p;
   p.N = nx * ax + ny * ay + nz * az;
-  p.A = nx / c.dfx;
-  p.B = ny / c.dfy;
+  p.A = nx * c.dinv_fx;
+  p.B = ny * c.dinv_fy;
   p.C = nz - p.A * c.dcx - p.B * c.dcy;
   return p;
 }
@@ -226,6 +226,8 @@ __device__ __forceinline__ bool tri_candidate(int x0, int y0, int x1, int y1, in
   const int ymin = min(y0, min(y1, y2)), ymax = max(y0, max(y1, y2));
   if (max(c0, ceil256(xmin)) > min(c1, floor256(xmax))) return false;
   if (max(r0, ceil256(ymin)) > min(r1, floor256(ymax))) return false;
+  if (xmax - xmin < 16384 && ymax - ymin < 16384)  // products below 2^28: int32 is exact
+    return (x1 - x0) * (y2 - y0) - (y1 - y0) * (x2 - x0) < 0;
   const long long area = (long long)(x1 - x0) * (y2 - y0) - (long long)(y1 - y0) * (x2 - x0);
   return area < 0;
 }
@@ -288,15 +290,32 @@ __device__ __forceinline__ bool explained_by_cloud(const Hash& hs, float qx, flo
   return false;
 }
 
-// Object-frame coordinates of camera-frame point p for pose (x, y, c, s):
-// world w = Winv p, then the exact inverse of the pose placement.
-__device__ __forceinline__ float3 cam_to_object(const Cam& c, const float4 pz, float3 p) {
-  const float wx = c.Winv[0] * p.x + c.Winv[1] * p.y + c.Winv[2] * p.z + c.Winv[3];
-  const float wy = c.Winv[4] * p.x + c.Winv[5] * p.y + c.Winv[6] * p.z + c.Winv[7];
-  const float wz = c.Winv[8] * p.x + c.Winv[9] * p.y + c.Winv[10] * p.z + c.Winv[11];
-  const float dx = wx - pz.x, dy = wy - pz.y;
+// Camera frame -> object frame of one pose, folded into a 3x4 map:
+// o = Rz(theta)^-1 (Winv p - (x, y, 0)) with the exact inverse of the placement.
+struct ObjMap {
+  float a[9], b[3];
+};
+
+__device__ __forceinline__ ObjMap make_obj_map(const Cam& c, const float4 pz) {
   const float inv_n2 = 1.0f / (pz.z * pz.z + pz.w * pz.w);
-  return make_float3((pz.z * dx + pz.w * dy) * inv_n2, (pz.z * dy - pz.w * dx) * inv_n2, wz);
+  const float cs = pz.z * inv_n2, sn = pz.w * inv_n2;
+  ObjMap m;
+  for (int k = 0; k < 3; ++k) {
+    m.a[k] = fmaf(cs, c.Winv[k], sn * c.Winv[4 + k]);
+    m.a[3 + k] = fmaf(cs, c.Winv[4 + k], -(sn * c.Winv[k]));
+    m.a[6 + k] = c.Winv[8 + k];
+  }
+  const float tx = c.Winv[3] - pz.x, ty = c.Winv[7] - pz.y;
+  m.b[0] = fmaf(cs, tx, sn * ty);
+  m.b[1] = fmaf(cs, ty, -(sn * tx));
+  m.b[2] = c.Winv[11];
+  return m;
+}
+
+__device__ __forceinline__ float3 apply_obj_map(const ObjMap& m, float3 p) {
+  return make_float3(fmaf(m.a[0], p.x, fmaf(m.a[1], p.y, fmaf(m.a[2], p.z, m.b[0]))),
+                     fmaf(m.a[3], p.x, fmaf(m.a[4], p.y, fmaf(m.a[5], p.z, m.b[1]))),
+                     fmaf(m.a[6], p.x, fmaf(m.a[7], p.y, fmaf(m.a[8], p.z, m.b[2]))));
 }
 
 // p in V(O): inside the mesh's box of vertices (with a 1e-5 m margin) and on the
@@ -487,7 +506,7 @@ __global__ void k_parent_u(Cam cam, Meshes M, const float4* poses, const float* 
       const float3 p = backproject(cam, i, jj, z);
       bool inV = false;
       for (int a = 0; a < j && !inV; ++a)
-        inV = in_volume(M, po.o[a].x, cam_to_object(cam, poses[po.o[a].y], p));
+        inV = in_volume(M, po.o[a].x, apply_obj_map(make_obj_map(cam, poses[po.o[a].y]), p));
       if (!inV) {
         int ru, rv;
         window_radius(cam, ep, p, ru, rv);
@@ -541,6 +560,7 @@ __global__ void __launch_bounds__(NT)
   }
   const int mesh = cd.x;
   const float4 pz = poses[cd.y];
+  const ObjMap om = make_obj_map(cam, pz);
   const int4 rg = M.range[mesh];
   int2* suv = reinterpret_cast<int2*>(smem);
   unsigned* tile = reinterpret_cast<unsigned*>(smem + (size_t)ep.max_nv * sizeof(int2));
@@ -763,6 +783,9 @@ __global__ void __launch_bounds__(NT)
     }
 
     // ---- dJ_o and U: observed points of the core rows ----
+    // A point needs the dR window when it lies in V(O) (dJ_o) or in U (residual);
+    // the new point at its own pixel decides most of them, the rest scan their
+    // exact window with a depth pre-test.
     {
       const int nk = (b1 - b0 + 1) * tw;
       for (int base = 0; base < nk; base += NT) {
@@ -770,29 +793,38 @@ __global__ void __launch_bounds__(NT)
         bool cnt_o = false, cnt_rem = false;
         if (k < nk) {
           const int jj = b0 + k / tw, ii = ca + k % tw;
-          const float z = obs[jj * W + ii];
+          const int pix = jj * W + ii;
+          const float z = obs[pix];
           if (z > 0.0f) {
             const float3 p = backproject(cam, ii, jj, z);
-            const bool inV = in_volume(M, mesh, cam_to_object(cam, pz, p));
-            const int pix = jj * W + ii;
+            const bool inV = in_volume(M, mesh, apply_obj_map(om, p));
             const bool inU = par.goal && ((par.ubits[pix >> 5] >> (pix & 31)) & 1u);
             bool expl = false;
             if (inV || inU) {
-              int ru, rv;
-              window_radius(cam, ep, p, ru, rv);
-              const int ja = max(t0, jj - rv), jb = min(t1, jj + rv);
-              const int ia = max(ca, ii - ru), ib = min(cb, ii + ru);
-              for (int jq = ja; jq <= jb && !expl; ++jq)
-                for (int iq = ia; iq <= ib; ++iq) {
-                  const unsigned kq = tile[(jq - t0) * tw + (iq - ca)];
-                  if (kq == kInfBits) continue;
-                  const float3 q = backproject(cam, iq, jq, __uint_as_float(kq));
-                  const float dx = q.x - p.x, dy = q.y - p.y, dz = q.z - p.z;
-                  if (dx * dx + dy * dy + dz * dz <= delta2) {
-                    expl = true;
-                    break;
+              const unsigned k0 = tile[(jj - t0) * tw + (ii - ca)];
+              if (k0 != kInfBits) {
+                const float3 q = backproject(cam, ii, jj, __uint_as_float(k0));
+                const float dx = q.x - p.x, dy = q.y - p.y, dz = q.z - p.z;
+                expl = dx * dx + dy * dy + dz * dz <= delta2;
+              }
+              if (!expl) {
+                int ru, rv;
+                window_radius(cam, ep, p, ru, rv);
+                const int ja = max(t0, jj - rv), jb = min(t1, jj + rv);
+                const int ia = max(ca, ii - ru), ib = min(cb, ii + ru);
+                const float zlo = z - cam.delta, zhi = z + cam.delta;
+                for (int jq = ja; jq <= jb && !expl; ++jq)
+                  for (int iq = ia; iq <= ib; ++iq) {
+                    const float zq = __uint_as_float(tile[(jq - t0) * tw + (iq - ca)]);
+                    if (!(zq >= zlo && zq <= zhi)) continue;  // also skips +inf (no point)
+                    const float3 q = backproject(cam, iq, jq, zq);
+                    const float dx = q.x - p.x, dy = q.y - p.y, dz = q.z - p.z;
+                    if (dx * dx + dy * dy + dz * dz <= delta2) {
+                      expl = true;
+                      break;
+                    }
                   }
-                }
+              }
             }
             cnt_o = inV && !expl;
             cnt_rem = inU && (inV || expl);
