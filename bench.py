@@ -39,6 +39,8 @@ def parse_args(argv=None):
     ap.add_argument("--threads", type=int, default=0, help="threads per successor (0 = default)")
     ap.add_argument("--tile", type=int, default=0, help="z-tile pixels (0 = default)")
     ap.add_argument("--cell", type=float, default=0.0, help="voxel cell / delta (0 = default)")
+    ap.add_argument("--radius", type=int, default=-1,
+                    help="dJ_r query: 0 pixel window, 1 voxel hash (-1 = default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -75,6 +77,91 @@ def algorithmic_bytes(scene, level, ms, S):
     if level + 1 == scene.K:
         b += (S + 7) // 8
     return int(b.sum())
+
+
+def batched_levels(scs):
+    """Per level: the ground-truth prefix parent of every scene that has that level,
+    and the (parent slot, mesh, pose, 0) items of all its successors."""
+    out = []
+    for level in range(max(sc.K for sc in scs)):
+        parents, items = [], []
+        for ci, sc in enumerate(scs):
+            if level >= sc.K:
+                continue
+            order = sc.gt_order
+            objs = [(int(sc.obj_mesh[k]), int(sc.gt_pose[k])) for k in order[:level]]
+            rest = sorted({int(sc.obj_mesh[k]) for k in order[level:]})
+            slot = len(parents)
+            parents.append((ci, objs))
+            P = sc.grid.P
+            it = np.zeros((len(rest) * P, 4), np.int32)
+            it[:, 0] = slot
+            it[:, 1] = np.repeat(rest, P)
+            it[:, 2] = np.tile(np.arange(P), len(rest))
+            items.append(it)
+        out.append((parents, np.ascontiguousarray(np.concatenate(items))))
+    return out
+
+
+def run_batched(args):
+    """Config 3: 64 scenes; every level's successors of all scenes in one persistent,
+    graph-replayed launch."""
+    import torch
+
+    from paper_1510_05613_amd import perch, scenes
+
+    cfg = scenes.CONFIGS[args.config]
+    lib = scenes.make_library(cfg["lib"])
+    rend = perch.GpuRenderer()
+    scs = [scenes.make_scene(args.config, i, rend, lib) for i in range(cfg.get("n_scenes", 64))]
+    ctxs = [perch.context_from_scene(sc) for sc in scs]
+    batch = perch.Batch(ctxs)
+    if args.threads or args.tile:
+        batch.set_tuning(args.threads, args.tile)
+    levels = batched_levels(scs)
+    dev = []
+    for parents, items in levels:
+        n = len(items)
+        dev.append(dict(parents=parents, items=torch.as_tensor(items).cuda(),
+                        cost=torch.empty(n, dtype=torch.int32, device="cuda"),
+                        status=torch.empty(n, dtype=torch.int32, device="cuda")))
+    n_step = sum(len(it) for _, it in levels)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in dev]
+    kernel_ms = 0.0
+
+    def step(timed):
+        nonlocal kernel_ms
+        for d, (e0, e1) in zip(dev, ev):
+            batch.set_parents(d["parents"])
+            if timed:
+                e0.record()
+            batch.eval(d["items"], d["cost"], d["status"])
+            if timed:
+                e1.record()
+        torch.cuda.synchronize()
+        if timed:
+            kernel_ms += sum(e0.elapsed_time(e1) for e0, e1 in ev)
+
+    for _ in range(args.warmup):
+        step(False)
+    for d in dev:
+        st = d["status"].cpu().numpy()
+        if np.any(st < 0):
+            raise RuntimeError(f"error status {np.unique(st)}")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    wall = time.perf_counter() - t0
+    return {"metric": METRIC, "value": round(n_step * args.steps / wall, 1), "unit": "evals/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(wall / args.steps * 1e3, 3), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": (f"config {args.config} ({cfg['name']}): {len(scs)} scenes, "
+                                    f"K in {sorted({sc.K for sc in scs})}, 12-mesh library "
+                                    f"200-20k triangles; one step = every level's successors of "
+                                    f"all scenes, one launch per level ({n_step})"),
+                       "successors_per_step": n_step,
+                       "kernel_ms_per_step": round(kernel_ms / args.steps, 3)}}
 
 
 def cpu_baseline(args, work_gpu):
@@ -124,12 +211,15 @@ def main(argv=None):
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         return 3
+    if args.config == 3:
+        print(json.dumps(run_batched(args)), flush=True)
+        return 0
     cfg = scenes.CONFIGS[args.config]
     lib = scenes.make_library(cfg["lib"])
     sc = scenes.make_scene(args.config, args.scene, perch.GpuRenderer(), lib)
     ctx = perch.context_from_scene(sc)
-    if args.threads or args.tile or args.cell:
-        ctx.set_tuning(args.threads, args.tile, args.cell)
+    if args.threads or args.tile or args.cell or args.radius >= 0:
+        ctx.set_tuning(args.threads, args.tile, args.cell, args.radius)
     work = level_work(sc)
     dev = []
     for parent, ms, ps in work:

@@ -145,8 +145,65 @@ perch_status perch_render(perch_ctx* ctx, const perch_object* objs, int32_t n,
 perch_status perch_set_tuning(perch_ctx* ctx, int32_t threads, int32_t tile_px,
                               float cell_over_delta, int32_t radius_mode);
 
+typedef struct {
+  int32_t threads;        /* threads per successor                                   */
+  int32_t tile_px;        /* z-tile pixels                                           */
+  int32_t radius_mode;    /* 0 pixel window, 1 voxel hash                            */
+  float cell_over_delta;  /* voxel cell size / delta (radius_mode 1)                 */
+  float ms;               /* median time of the calibration batch                    */
+} perch_tuning;
+
+/* Autotuner: times every candidate setting of perch_set_tuning on the calibration
+ * batch cands_dev[0..n) (device) under parent[0..j) (host), reps timed runs each,
+ * checks that every setting reproduces the first one's outputs bit for bit, and
+ * applies the fastest.  cache_path (nullable): JSON-lines cache keyed by device and
+ * scene shape; a hit is applied without timing.  Synchronous. */
+perch_status perch_autotune(perch_ctx* ctx, const perch_object* parent, int32_t j,
+                            const perch_object* cands_dev, int32_t n, int32_t reps,
+                            const char* cache_path, perch_tuning* best);
+
 /* Observed point count |I| and the pixel window halo (host outputs). */
 perch_status perch_get_info(perch_ctx* ctx, int32_t* n_points, int32_t* halo);
+
+/* ---- batched evaluation across scenes and parents ---- */
+
+/* A batch evaluates successors of many parents, possibly of different scenes
+ * (contexts), in one persistent launch: workgroups pull (parent, mesh, pose) items
+ * from an atomic queue, so meshes of very different sizes balance across the GPU.
+ * The launch is captured once in a hipGraph and replayed while the work list and
+ * outputs keep their addresses and size.  The contexts must stay alive and
+ * unchanged while the batch uses them. */
+typedef struct perch_batch perch_batch;
+
+typedef struct {
+  int32_t ctx;            /* index into the batch's contexts                       */
+  int32_t j;              /* number of placed objects (j < K of that context)      */
+  perch_object objs[8];   /* the parent state s = objs[0..j)                       */
+} perch_parent;
+
+typedef struct {
+  int32_t parent;         /* parent slot (index into the last perch_batch_set_parents) */
+  int32_t mesh_id;
+  int32_t pose_idx;
+  int32_t reserved;
+} perch_work;
+
+/* hip_stream: the stream the batch orders its work on (NULL = null stream).
+ * Synchronous. */
+perch_status perch_batch_create(perch_ctx* const* ctxs, int32_t n_ctx, void* hip_stream,
+                                perch_batch** out);
+void perch_batch_destroy(perch_batch* b);
+/* Materialises each parent (R_j, and U at its goal level) into its own slot
+ * (host array).  Asynchronous. */
+perch_status perch_batch_set_parents(perch_batch* b, const perch_parent* parents, int32_t n);
+/* Evaluates n work items (device array) into cost/status/comps (device, as in
+ * perch_eval_successors, indexed like the items).  Asynchronous. */
+perch_status perch_batch_eval(perch_batch* b, const perch_work* items_dev, int32_t n,
+                              int32_t* cost_dev, int32_t* status_dev, int32_t* comps_dev);
+/* threads per workgroup (64/128/256), z-tile pixels, use_graph (0/1), persistent
+ * grid size (0 = one workgroup per resident slot); 0 / -1 keeps a value. */
+perch_status perch_batch_set_tuning(perch_batch* b, int32_t threads, int32_t tile_px,
+                                    int32_t use_graph, int32_t grid);
 
 /* ---- tree search (Alg. 1: ComputePath over the implicit MSGT) ---- */
 

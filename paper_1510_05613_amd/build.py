@@ -24,7 +24,8 @@ def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     objs = []
     for src, flags in (("perch_kernels.hip", DEVICE_FLAGS), ("perch_api.cpp", HOST_FLAGS),
-                       ("perch_search.cpp", HOST_FLAGS)):
+                       ("perch_search.cpp", HOST_FLAGS), ("perch_batch.cpp", HOST_FLAGS),
+                       ("perch_tune.cpp", HOST_FLAGS)):
         obj = os.path.join(BUILD, src.rsplit(".", 1)[0] + ".o")
         cmd = [HIPCC, *flags, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:

@@ -36,7 +36,7 @@ perch_status fail(perch_status st, const char* fmt, ...) {
 
 }  // namespace perch
 
-static perch_status upload_meshes(perch_ctx* c) {
+perch_status upload_meshes(perch_ctx* c) {
   if (!c->meshes_dirty) return PERCH_OK;
   const int nm = (int)c->meshes.size();
   if (nm == 0) return fail(PERCH_E_STATE, "no meshes added");
@@ -101,35 +101,41 @@ static bool objects_ok(const perch_ctx* c, const perch_object* o, int n) {
   return true;
 }
 
-// Composite R_j of the parent objects into par_depth; at the goal level also the
-// set U (bitmap + count) of observed points outside every parent volume and
-// unexplained by R_j.
+// Composite R_j of parent[0..j) into depth (float bits, +inf = empty); at the goal
+// level also the set U (bitmap + count) of observed points outside every parent
+// volume and unexplained by R_j.
+perch_status materialise_into(perch_ctx* c, const perch_object* parent, int j, bool goal,
+                              unsigned* depth, unsigned* ubits, int* ucount, hipStream_t st) {
+  const size_t npx = (size_t)c->cam.W * c->cam.H;
+  const Meshes M = c->dev_meshes();
+  const float4* poses = c->poses.as<float4>();
+  launch_fill_u32(depth, kInfBits, npx, st);
+  for (int k = 0; k < j; ++k)
+    launch_render_object(c->cam, M, poses, parent[k].mesh_id, parent[k].pose_idx,
+                         (int)c->meshes[parent[k].mesh_id].tris.size() / 3, depth, st);
+  if (goal) {
+    launch_fill_u32(ubits, 0u, (npx + 31) / 32, st);
+    launch_fill_i32(ucount, 0, 1, st);
+    int mp[16];
+    for (int k = 0; k < j; ++k) {
+      mp[2 * k] = parent[k].mesh_id;
+      mp[2 * k + 1] = parent[k].pose_idx;
+    }
+    launch_parent_u(c->cam, M, poses, c->obs.as<float>(), mp, j, depth, ubits, ucount, c->ep,
+                    st);
+  }
+  HIP_TRY(hipGetLastError());
+  return PERCH_OK;
+}
+
 static perch_status materialise_parent(perch_ctx* c, const perch_object* parent, int j,
                                        bool goal) {
   const size_t npx = (size_t)c->cam.W * c->cam.H;
   HIP_TRY(c->par_depth.ensure(npx * sizeof(unsigned)));
   HIP_TRY(c->par_ubits.ensure(((npx + 31) / 32) * sizeof(unsigned)));
   HIP_TRY(c->par_ucount.ensure(sizeof(int)));
-  const Meshes M = c->dev_meshes();
-  const float4* poses = c->poses.as<float4>();
-  launch_fill_u32(c->par_depth.as<unsigned>(), kInfBits, npx, c->stream);
-  for (int k = 0; k < j; ++k)
-    launch_render_object(c->cam, M, poses, parent[k].mesh_id, parent[k].pose_idx,
-                         (int)c->meshes[parent[k].mesh_id].tris.size() / 3,
-                         c->par_depth.as<unsigned>(), c->stream);
-  if (goal) {
-    launch_fill_u32(c->par_ubits.as<unsigned>(), 0u, (npx + 31) / 32, c->stream);
-    launch_fill_i32(c->par_ucount.as<int>(), 0, 1, c->stream);
-    int mp[16];
-    for (int k = 0; k < j; ++k) {
-      mp[2 * k] = parent[k].mesh_id;
-      mp[2 * k + 1] = parent[k].pose_idx;
-    }
-    launch_parent_u(c->cam, M, poses, c->obs.as<float>(), mp, j, c->par_depth.as<unsigned>(),
-                    c->par_ubits.as<unsigned>(), c->par_ucount.as<int>(), c->ep, c->stream);
-  }
-  HIP_TRY(hipGetLastError());
-  return PERCH_OK;
+  return materialise_into(c, parent, j, goal, c->par_depth.as<unsigned>(),
+                          c->par_ubits.as<unsigned>(), c->par_ucount.as<int>(), c->stream);
 }
 
 extern "C" {
@@ -376,16 +382,8 @@ perch_status perch_eval_children(perch_ctx* c, const perch_object* cands_dev, in
   par.ucount = c->par_ucount.as<int>();
   par.has_parent = c->parent_j > 0;
   par.goal = (c->parent_j + 1 == K);
-  EvalParams ep = c->ep;
-  ep.tile_px = c->tile_px;
-  ep.max_nv = c->max_nv;
-  ep.n_mesh = (int)c->meshes.size();
-  ep.n_poses = c->P;
-  ep.radius_mode = c->radius_mode;
-  HIP_TRY(launch_eval(c->threads, c->cam, c->dev_meshes(), c->poses.as<float4>(),
-                      c->obs.as<float>(), c->obs_range.as<float2>(), c->dev_hash(), par,
-                      reinterpret_cast<const int2*>(cands_dev), n, cost_dev, status_dev, comps_dev,
-                      ep, lds, c->stream));
+  HIP_TRY(launch_eval(c->threads, c->scene_dev(), par, reinterpret_cast<const int2*>(cands_dev),
+                      n, cost_dev, status_dev, comps_dev, lds, c->stream));
   return PERCH_OK;
 }
 

@@ -1,0 +1,228 @@
+// perch_batch.cpp -- batched successor evaluation across scenes and parents
+// (arXiv:1510.05613 Sec. IV-E: successor generation is embarrassingly parallel).
+//
+// The paper farms successors out to CPU processes; here every successor of every
+// parent of every scene in a batch goes into one persistent launch.  Parents are
+// materialised into slots of their own; the kernel reads a scene table and a
+// parent table from device memory and pulls (parent, mesh, pose) items from an
+// atomic counter.  The launch (counter reset + persistent kernel) is captured in
+// a hipGraph on a private stream and replayed on the caller's stream.
+#include <algorithm>
+#include <vector>
+
+#include "perch_ctx.h"
+
+using namespace perch;
+
+struct perch_batch {
+  std::vector<perch_ctx*> ctxs;
+  hipStream_t stream = nullptr;   // caller's stream
+  hipStream_t capture = nullptr;  // private stream used only to capture graphs
+  DevBuf scenes, parents, slot_depth, slot_ubits, slot_ucount, counter;
+  int n_parents = 0;
+  size_t npx_max = 0;
+  int threads = 256;
+  int tile_px = 4096;
+  int use_graph = 1;
+  int grid = 0;
+  // graph cache
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  const void* g_items = nullptr;
+  int g_n = -1;
+  const void *g_cost = nullptr, *g_status = nullptr, *g_comps = nullptr;
+  int g_threads = 0, g_tile = 0, g_grid = 0, g_parents = -1;
+  const void* g_ptab = nullptr;
+
+  int max_nv() const {
+    int m = 0;
+    for (perch_ctx* c : ctxs) m = std::max(m, c->max_nv);
+    return m;
+  }
+  size_t lds_bytes() const {
+    return (size_t)max_nv() * sizeof(int2) + (size_t)tile_px * sizeof(unsigned) +
+           (size_t)(threads / 64) * 128 * sizeof(unsigned);
+  }
+  void drop_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    g_items = nullptr;
+  }
+};
+
+extern "C" {
+
+perch_status perch_batch_create(perch_ctx* const* ctxs, int32_t n_ctx, void* hip_stream,
+                                perch_batch** out) {
+  if (!ctxs || !out || n_ctx < 1) return fail(PERCH_E_ARG, "bad context list");
+  *out = nullptr;
+  for (int k = 0; k < n_ctx; ++k) {
+    perch_ctx* c = ctxs[k];
+    if (!c) return fail(PERCH_E_ARG, "null context %d", k);
+    if (!c->has_obs || c->P <= 0 || c->objects.empty())
+      return fail(PERCH_E_STATE, "context %d lacks observation, poses or objects", k);
+    perch_status st = upload_meshes(c);
+    if (st) return st;
+  }
+  perch_batch* b = new perch_batch();
+  b->ctxs.assign(ctxs, ctxs + n_ctx);
+  b->stream = static_cast<hipStream_t>(hip_stream);
+  for (perch_ctx* c : b->ctxs) b->npx_max = std::max(b->npx_max, (size_t)c->cam.W * c->cam.H);
+  hipError_t e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
+  if (e == hipSuccess) e = b->counter.ensure(sizeof(int));
+  if (e == hipSuccess) e = b->scenes.ensure(sizeof(SceneDev) * n_ctx);
+  if (e != hipSuccess) {
+    if (b->capture) (void)hipStreamDestroy(b->capture);
+    b->counter.release();
+    b->scenes.release();
+    delete b;
+    return fail(e == hipErrorOutOfMemory ? PERCH_E_OOM : PERCH_E_HIP, "batch setup: %s",
+                hipGetErrorString(e));
+  }
+  *out = b;
+  return PERCH_OK;
+}
+
+void perch_batch_destroy(perch_batch* b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->stream);
+  b->drop_graph();
+  for (DevBuf* d : {&b->scenes, &b->parents, &b->slot_depth, &b->slot_ubits, &b->slot_ucount,
+                    &b->counter})
+    d->release();
+  if (b->capture) (void)hipStreamDestroy(b->capture);
+  delete b;
+}
+
+perch_status perch_batch_set_tuning(perch_batch* b, int32_t threads, int32_t tile_px,
+                                    int32_t use_graph, int32_t grid) {
+  if (!b) return fail(PERCH_E_ARG, "null batch");
+  if (threads && threads != 64 && threads != 128 && threads != 256)
+    return fail(PERCH_E_ARG, "threads must be 64, 128 or 256");
+  if (tile_px && (tile_px < 256 || tile_px > 36864)) return fail(PERCH_E_ARG, "bad tile_px");
+  if (threads) b->threads = threads;
+  if (tile_px) b->tile_px = tile_px;
+  if (use_graph >= 0) b->use_graph = use_graph ? 1 : 0;
+  if (grid >= 0) b->grid = grid;
+  return PERCH_OK;
+}
+
+perch_status perch_batch_set_parents(perch_batch* b, const perch_parent* parents, int32_t n) {
+  if (!b || n < 0 || (n > 0 && !parents)) return fail(PERCH_E_ARG, "bad parent list");
+  for (int k = 0; k < n; ++k) {
+    const perch_parent& p = parents[k];
+    if (p.ctx < 0 || p.ctx >= (int)b->ctxs.size()) return fail(PERCH_E_ARG, "parent %d: bad ctx", k);
+    perch_ctx* c = b->ctxs[p.ctx];
+    const int K = (int)c->objects.size();
+    if (p.j < 0 || p.j >= K) return fail(PERCH_E_ARG, "parent %d: j=%d with K=%d", k, p.j, K);
+    for (int o = 0; o < p.j; ++o)
+      if (p.objs[o].mesh_id < 0 || p.objs[o].mesh_id >= (int)c->meshes.size() ||
+          p.objs[o].pose_idx < 0 || p.objs[o].pose_idx >= c->P)
+        return fail(PERCH_E_ARG, "parent %d: object %d out of range", k, o);
+    if (c->meshes_dirty) return fail(PERCH_E_STATE, "context %d meshes changed", p.ctx);
+  }
+  // the previous evaluation may still read the slots
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  const size_t words = (b->npx_max + 31) / 32;
+  HIP_TRY(b->slot_depth.ensure(std::max<size_t>(1, n) * b->npx_max * sizeof(unsigned)));
+  HIP_TRY(b->slot_ubits.ensure(std::max<size_t>(1, n) * words * sizeof(unsigned)));
+  HIP_TRY(b->slot_ucount.ensure(std::max<size_t>(1, n) * sizeof(int)));
+  HIP_TRY(b->parents.ensure(std::max<size_t>(1, n) * sizeof(ParentDev)));
+  std::vector<ParentDev> pd(std::max(1, n));
+  for (int k = 0; k < n; ++k) {
+    const perch_parent& p = parents[k];
+    perch_ctx* c = b->ctxs[p.ctx];
+    unsigned* depth = b->slot_depth.as<unsigned>() + (size_t)k * b->npx_max;
+    unsigned* ubits = b->slot_ubits.as<unsigned>() + (size_t)k * words;
+    int* ucount = b->slot_ucount.as<int>() + k;
+    const bool goal = p.j + 1 == (int)c->objects.size();
+    perch_status st = materialise_into(c, p.objs, p.j, goal, depth, ubits, ucount, b->stream);
+    if (st) return st;
+    pd[k].depth = depth;
+    pd[k].ubits = ubits;
+    pd[k].ucount = ucount;
+    pd[k].has_parent = p.j > 0;
+    pd[k].goal = goal;
+    pd[k].scene = p.ctx;
+    pd[k].pad = 0;
+  }
+  std::vector<SceneDev> sd(b->ctxs.size());
+  const int max_nv = b->max_nv();
+  for (size_t k = 0; k < b->ctxs.size(); ++k) {
+    sd[k] = b->ctxs[k]->scene_dev();
+    sd[k].ep.tile_px = b->tile_px;
+    sd[k].ep.max_nv = max_nv;
+  }
+  HIP_TRY(hipMemcpyAsync(b->parents.p, pd.data(), sizeof(ParentDev) * pd.size(),
+                         hipMemcpyHostToDevice, b->stream));
+  HIP_TRY(hipMemcpyAsync(b->scenes.p, sd.data(), sizeof(SceneDev) * sd.size(),
+                         hipMemcpyHostToDevice, b->stream));
+  // the host vectors die here: the copies must complete first
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  b->n_parents = n;
+  return PERCH_OK;
+}
+
+perch_status perch_batch_eval(perch_batch* b, const perch_work* items_dev, int32_t n,
+                              int32_t* cost_dev, int32_t* status_dev, int32_t* comps_dev) {
+  if (!b) return fail(PERCH_E_ARG, "null batch");
+  if (n < 0 || (n > 0 && (!items_dev || !cost_dev || !status_dev)))
+    return fail(PERCH_E_ARG, "bad work arrays");
+  if (n == 0) return PERCH_OK;
+  const size_t lds = b->lds_bytes();
+  if (lds > 160 * 1024 - 256) return fail(PERCH_E_UNSUPPORTED, "LDS need %zu B too large", lds);
+  // resolve the persistent grid and the LDS limit outside any capture
+  int grid = b->grid;
+  {
+    int dev = 0, cus = 0, per_cu = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    HIP_TRY(prepare_eval_batch(b->threads, lds, &per_cu));
+    if (grid <= 0) grid = std::max(1, cus * std::max(1, per_cu));
+  }
+  const int4* items = reinterpret_cast<const int4*>(items_dev);
+  const SceneDev* scenes = b->scenes.as<SceneDev>();
+  const ParentDev* parents = b->parents.as<ParentDev>();
+  if (!b->use_graph) {
+    HIP_TRY(launch_eval_batch(b->threads, scenes, parents, b->n_parents, items, n,
+                              b->counter.as<int>(), cost_dev, status_dev, comps_dev, lds, grid,
+                              b->stream));
+    return PERCH_OK;
+  }
+  const bool same = b->exec && b->g_items == items_dev && b->g_n == n && b->g_cost == cost_dev &&
+                    b->g_status == status_dev && b->g_comps == comps_dev &&
+                    b->g_threads == b->threads && b->g_tile == b->tile_px && b->g_grid == grid &&
+                    b->g_parents == b->n_parents && b->g_ptab == b->parents.p;
+  if (!same) {
+    b->drop_graph();
+    HIP_TRY(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
+    hipError_t e = launch_eval_batch(b->threads, scenes, parents, b->n_parents, items, n,
+                                     b->counter.as<int>(), cost_dev, status_dev, comps_dev, lds,
+                                     grid, b->capture);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(b->capture, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(PERCH_E_HIP, "graph capture failed: %s",
+                  hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    b->graph = g;
+    HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    b->g_items = items_dev;
+    b->g_n = n;
+    b->g_cost = cost_dev;
+    b->g_status = status_dev;
+    b->g_comps = comps_dev;
+    b->g_threads = b->threads;
+    b->g_tile = b->tile_px;
+    b->g_grid = grid;
+    b->g_parents = b->n_parents;
+    b->g_ptab = b->parents.p;
+  }
+  HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+  return PERCH_OK;
+}
+
+}  // extern "C"

@@ -135,6 +135,23 @@ struct perch_ctx {
     M.aabb = aabb.as<float4>();
     return M;
   }
+  // Scene view for the kernels, with the context's tuning.
+  perch::SceneDev scene_dev() const {
+    perch::SceneDev S;
+    S.cam = cam;
+    S.M = dev_meshes();
+    S.poses = poses.as<float4>();
+    S.obs = obs.as<float>();
+    S.obs_range = obs_range.as<float2>();
+    S.hs = dev_hash();
+    S.ep = ep;
+    S.ep.tile_px = tile_px;
+    S.ep.max_nv = max_nv;
+    S.ep.n_mesh = (int)meshes.size();
+    S.ep.n_poses = P;
+    S.ep.radius_mode = radius_mode;
+    return S;
+  }
   Hash dev_hash() const {
     Hash h;
     h.keys = h_keys.as<unsigned long long>();
@@ -148,3 +165,7 @@ struct perch_ctx {
   }
 };
 
+// Shared with the batch and search code (perch_api.cpp).
+perch_status upload_meshes(perch_ctx* c);
+perch_status materialise_into(perch_ctx* c, const perch_object* parent, int j, bool goal,
+                              unsigned* depth, unsigned* ubits, int* ucount, hipStream_t st);

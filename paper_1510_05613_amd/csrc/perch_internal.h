@@ -64,6 +64,28 @@ struct EvalParams {
   int radius_mode;  // dJ_r query: 0 exact pixel window, 1 voxel hash
 };
 
+// Everything a successor evaluation reads about one scene.
+struct SceneDev {
+  Cam cam;
+  Meshes M;
+  const float4* poses;
+  const float* obs;         // observed depth (H*W)
+  const float2* obs_range;  // per pixel (min, max) observed depth over the window halo
+  Hash hs;
+  EvalParams ep;
+};
+
+// One materialised parent of a batch, in scene `scene` of the batch.
+struct ParentDev {
+  const unsigned* depth;
+  const unsigned* ubits;
+  const int* ucount;
+  int has_parent;
+  int goal;
+  int scene;
+  int pad;
+};
+
 // ---- launchers (perch_kernels.hip) ----
 void launch_fill_u32(unsigned* p, unsigned v, size_t n, hipStream_t s);
 void launch_fill_i32(int* p, int v, size_t n, hipStream_t s);
@@ -81,10 +103,15 @@ void launch_parent_u(const Cam& cam, const Meshes& M, const float4* poses, const
                      unsigned* ubits, int* ucount, const EvalParams& ep, hipStream_t s);
 void launch_bits_to_float(const unsigned* bits, float* out, size_t n, hipStream_t s);
 void launch_obs_range(const Cam& cam, const float* obs, float2* out, int R, hipStream_t s);
-hipError_t launch_eval(int threads, const Cam& cam, const Meshes& M, const float4* poses,
-                 const float* obs, const float2* obs_range, const Hash& hs, const Parent& par,
-                 const int2* cands,
-                 int n, int* cost, int* status, int* comps, const EvalParams& ep,
-                 size_t lds_bytes, hipStream_t s);
+hipError_t launch_eval(int threads, const SceneDev& S, const Parent& par, const int2* cands,
+                       int n, int* cost, int* status, int* comps, size_t lds_bytes,
+                       hipStream_t s);
+// Raises the kernel's LDS limit and reports resident workgroups per CU (call
+// before launch_eval_batch, outside any graph capture).
+hipError_t prepare_eval_batch(int threads, size_t lds_bytes, int* blocks_per_cu);
+// grid = number of persistent workgroups (clamped to n)
+hipError_t launch_eval_batch(int threads, const SceneDev* scenes, const ParentDev* parents,
+                             int n_parents, const int4* items, int n, int* counter, int* cost,
+                             int* status, int* comps, size_t lds_bytes, int grid, hipStream_t s);
 
 }  // namespace perch

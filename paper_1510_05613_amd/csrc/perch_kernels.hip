@@ -13,6 +13,7 @@
 //
 // Built with -ffp-contract=off: the float32 vertex stage is part of the
 // rasterisation rule and must not have products fused into adds.
+#include <algorithm>
 #include <climits>
 
 #include "perch_internal.h"
@@ -535,20 +536,25 @@ __global__ void k_parent_u(Cam cam, Meshes M, const float4* poses, const float* 
 // successor evaluation: one workgroup per successor
 // ---------------------------------------------------------------------------
 
+// Evaluates successor s' = parent + (cd.x = mesh, cd.y = pose) of scene S and
+// writes output slot s.  Every thread of the workgroup calls it with the same
+// arguments; it synchronises the workgroup internally.
 template <int NT>
-__global__ void __launch_bounds__(NT)
-    k_eval(Cam cam, Meshes M, const float4* __restrict__ poses, const float* __restrict__ obs,
-           const float2* __restrict__ obs_range, Hash hs, Parent par, const int2* __restrict__ cands, int n, int* __restrict__ out_cost,
-           int* __restrict__ out_status, int* __restrict__ out_comps, EvalParams ep) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ int s_bb[4];
-  __shared__ int s_acc[8];  // S, |dR|, dJ_r, dJ_o, removed-from-U, invalid, near-plane
+__device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& par, const int2 cd,
+                                               const int s, int* __restrict__ out_cost,
+                                               int* __restrict__ out_status,
+                                               int* __restrict__ out_comps, unsigned char* smem,
+                                               int* s_bb, int* s_acc) {
+  const Cam& cam = S.cam;
+  const Meshes& M = S.M;
+  const float4* __restrict__ poses = S.poses;
+  const float* __restrict__ obs = S.obs;
+  const float2* __restrict__ obs_range = S.obs_range;
+  const Hash& hs = S.hs;
+  const EvalParams& ep = S.ep;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int s = blockIdx.x;
-  if (s >= n) return;
   const int W = cam.W, H = cam.H;
-  const int2 cd = cands[s];
   if (cd.x < 0 || cd.x >= ep.n_mesh || cd.y < 0 || cd.y >= ep.n_poses) {
     if (tid == 0) {
       out_status[s] = -4;
@@ -858,6 +864,62 @@ __global__ void __launch_bounds__(NT)
   }
 }
 
+// One workgroup per successor of one parent.
+template <int NT>
+__global__ void __launch_bounds__(NT)
+    k_eval(SceneDev S, Parent par, const int2* __restrict__ cands, int n,
+           int* __restrict__ out_cost, int* __restrict__ out_status, int* __restrict__ out_comps) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int s_bb[4];
+  __shared__ int s_acc[8];  // S, |dR|, dJ_r, dJ_o, removed-from-U, invalid, near-plane
+  const int s = blockIdx.x;
+  if (s >= n) return;
+  eval_successor<NT>(S, par, cands[s], s, out_cost, out_status, out_comps, smem, s_bb, s_acc);
+}
+
+// Persistent workgroups over a work queue of (parent slot, mesh, pose) items that
+// may belong to different scenes: each workgroup takes the next item from an
+// atomic counter until the queue is empty, so uneven meshes balance across CUs.
+template <int NT>
+__global__ void __launch_bounds__(NT)
+    k_eval_batch(const SceneDev* __restrict__ scenes, const ParentDev* __restrict__ parents,
+                 int n_parents, const int4* __restrict__ items, int n, int* counter,
+                 int* __restrict__ out_cost, int* __restrict__ out_status,
+                 int* __restrict__ out_comps) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int s_bb[4];
+  __shared__ int s_acc[8];
+  __shared__ int s_item;
+  for (;;) {
+    __syncthreads();  // the previous item is done with LDS
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(s_item);
+    if (it >= n) break;
+    const int4 w = items[it];
+    const int pslot = __builtin_amdgcn_readfirstlane(w.x);
+    if (pslot < 0 || pslot >= n_parents) {
+      if (threadIdx.x == 0) {
+        out_status[it] = -4;
+        out_cost[it] = -1;
+        if (out_comps)
+          for (int c = 0; c < 5; ++c) out_comps[5 * it + c] = -1;
+      }
+      continue;
+    }
+    const ParentDev& pd = parents[pslot];
+    Parent par;
+    par.depth = pd.depth;
+    par.ubits = pd.ubits;
+    par.ucount = pd.ucount;
+    par.has_parent = pd.has_parent;
+    par.goal = pd.goal;
+    const int scene = __builtin_amdgcn_readfirstlane(pd.scene);
+    eval_successor<NT>(scenes[scene], par, make_int2(w.y, w.z), it, out_cost, out_status,
+                       out_comps, smem, s_bb, s_acc);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -911,43 +973,82 @@ void launch_parent_u(const Cam& cam, const Meshes& M, const float4* poses, const
                      j, depth_bits, ubits, ucount, ep);
 }
 
+template <class K>
+static hipError_t allow_lds(K kernel, size_t lds) {
+  if (lds <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
 template <int NT>
-static hipError_t launch_eval_t(const Cam& cam, const Meshes& M, const float4* poses,
-                                const float* obs, const float2* obs_range, const Hash& hs,
-                                const Parent& par,
-                                const int2* cands, int n, int* cost, int* status, int* comps,
-                                const EvalParams& ep, size_t lds, hipStream_t s) {
-  static size_t configured = 0;
-  if (lds > 65536 && lds > configured) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eval<NT>),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    configured = lds;
-  }
-  hipLaunchKernelGGL(k_eval<NT>, dim3(n), dim3(NT), lds, s, cam, M, poses, obs, obs_range, hs,
-                     par, cands, n, cost, status, comps, ep);
+static hipError_t launch_eval_t(const SceneDev& S, const Parent& par, const int2* cands, int n,
+                                int* cost, int* status, int* comps, size_t lds, hipStream_t s) {
+  hipError_t e = allow_lds(&k_eval<NT>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_eval<NT>, dim3(n), dim3(NT), lds, s, S, par, cands, n, cost, status,
+                     comps);
   return hipGetLastError();
 }
 
-hipError_t launch_eval(int threads, const Cam& cam, const Meshes& M, const float4* poses,
-                       const float* obs, const float2* obs_range, const Hash& hs,
-                       const Parent& par, const int2* cands,
-                       int n, int* cost, int* status, int* comps, const EvalParams& ep,
-                       size_t lds_bytes, hipStream_t s) {
+hipError_t launch_eval(int threads, const SceneDev& S, const Parent& par, const int2* cands,
+                       int n, int* cost, int* status, int* comps, size_t lds_bytes,
+                       hipStream_t s) {
   if (n <= 0) return hipSuccess;
   switch (threads) {
     case 64:
-      return launch_eval_t<64>(cam, M, poses, obs, obs_range, hs, par, cands, n, cost, status,
-                                comps, ep,
-                               lds_bytes, s);
+      return launch_eval_t<64>(S, par, cands, n, cost, status, comps, lds_bytes, s);
     case 128:
-      return launch_eval_t<128>(cam, M, poses, obs, obs_range, hs, par, cands, n, cost, status,
-                                comps, ep,
-                                lds_bytes, s);
+      return launch_eval_t<128>(S, par, cands, n, cost, status, comps, lds_bytes, s);
     default:
-      return launch_eval_t<256>(cam, M, poses, obs, obs_range, hs, par, cands, n, cost, status,
-                                comps, ep,
-                                lds_bytes, s);
+      return launch_eval_t<256>(S, par, cands, n, cost, status, comps, lds_bytes, s);
+  }
+}
+
+template <int NT>
+static hipError_t prepare_eval_batch_t(size_t lds, int* per_cu) {
+  hipError_t e = allow_lds(&k_eval_batch<NT>, lds);
+  if (e != hipSuccess) return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_eval_batch<NT>, NT, lds);
+}
+
+hipError_t prepare_eval_batch(int threads, size_t lds_bytes, int* blocks_per_cu) {
+  switch (threads) {
+    case 64:
+      return prepare_eval_batch_t<64>(lds_bytes, blocks_per_cu);
+    case 128:
+      return prepare_eval_batch_t<128>(lds_bytes, blocks_per_cu);
+    default:
+      return prepare_eval_batch_t<256>(lds_bytes, blocks_per_cu);
+  }
+}
+
+template <int NT>
+static hipError_t launch_eval_batch_t(const SceneDev* scenes, const ParentDev* parents,
+                                      int n_parents, const int4* items, int n, int* counter,
+                                      int* cost, int* status, int* comps, size_t lds, int grid,
+                                      hipStream_t s) {
+  grid = std::max(1, std::min(grid, n));
+  hipLaunchKernelGGL(k_eval_batch<NT>, dim3(grid), dim3(NT), lds, s, scenes, parents, n_parents,
+                     items, n, counter, cost, status, comps);
+  return hipGetLastError();
+}
+
+hipError_t launch_eval_batch(int threads, const SceneDev* scenes, const ParentDev* parents,
+                             int n_parents, const int4* items, int n, int* counter, int* cost,
+                             int* status, int* comps, size_t lds_bytes, int grid,
+                             hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  launch_fill_i32(counter, 0, 1, s);  // a fill kernel (not a memset): safe in captured graphs
+  switch (threads) {
+    case 64:
+      return launch_eval_batch_t<64>(scenes, parents, n_parents, items, n, counter, cost, status,
+                                     comps, lds_bytes, grid, s);
+    case 128:
+      return launch_eval_batch_t<128>(scenes, parents, n_parents, items, n, counter, cost,
+                                      status, comps, lds_bytes, grid, s);
+    default:
+      return launch_eval_batch_t<256>(scenes, parents, n_parents, items, n, counter, cost,
+                                      status, comps, lds_bytes, grid, s);
   }
 }
 

@@ -26,7 +26,9 @@ PERCH_SUCC_BAD_INPUT = -4
 EXPORTS = ("perch_create", "perch_destroy", "perch_set_observation", "perch_add_mesh",
            "perch_set_poses", "perch_set_objects", "perch_eval_successors", "perch_set_parent",
            "perch_eval_children", "perch_render", "perch_set_tuning", "perch_get_info",
-           "perch_search", "perch_last_error")
+           "perch_search", "perch_batch_create", "perch_batch_destroy",
+           "perch_batch_set_parents", "perch_batch_eval", "perch_batch_set_tuning",
+           "perch_autotune", "perch_last_error")
 
 SEARCH_EXHAUSTIVE, SEARCH_UCS, SEARCH_FOCAL = 0, 1, 2
 
@@ -43,6 +45,15 @@ class _Sensor(C.Structure):
 
 class PerchObject(C.Structure):
     _fields_ = [("mesh_id", C.c_int32), ("pose_idx", C.c_int32)]
+
+
+class PerchParent(C.Structure):
+    _fields_ = [("ctx", C.c_int32), ("j", C.c_int32), ("objs", PerchObject * 8)]
+
+
+class _Tuning(C.Structure):
+    _fields_ = [("threads", C.c_int32), ("tile_px", C.c_int32), ("radius_mode", C.c_int32),
+                ("cell_over_delta", C.c_float), ("ms", C.c_float)]
 
 
 class _SearchOpts(C.Structure):
@@ -84,9 +95,16 @@ def load(path: str = LIB_PATH):
     L.perch_set_tuning.argtypes = [P, I32, I32, C.c_float, I32]
     L.perch_get_info.argtypes = [P, C.POINTER(I32), C.POINTER(I32)]
     L.perch_search.argtypes = [P, C.POINTER(_SearchOpts), C.POINTER(_Result)]
+    L.perch_autotune.argtypes = [P, P, I32, P, I32, I32, C.c_char_p, C.POINTER(_Tuning)]
+    L.perch_batch_create.argtypes = [P, I32, P, C.POINTER(P)]
+    L.perch_batch_destroy.argtypes = [P]
+    L.perch_batch_destroy.restype = None
+    L.perch_batch_set_parents.argtypes = [P, P, I32]
+    L.perch_batch_eval.argtypes = [P, P, I32, P, P, P]
+    L.perch_batch_set_tuning.argtypes = [P, I32, I32, I32, I32]
     L.perch_last_error.restype = C.c_char_p
     for name in EXPORTS:
-        if name not in ("perch_destroy", "perch_last_error"):
+        if name not in ("perch_destroy", "perch_batch_destroy", "perch_last_error"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -177,6 +195,16 @@ class Context:
         """Kernel knobs (0 / -1 keep the current value); results do not depend on them."""
         _check(load().perch_set_tuning(self.h, threads, tile_px, cell_over_delta, radius_mode))
 
+    def autotune(self, parent, cands, reps: int = 3, cache_path: Optional[str] = None) -> dict:
+        """Times the kernel settings on a calibration batch and applies the fastest."""
+        t = _Tuning()
+        _check(load().perch_autotune(
+            self.h, C.cast(_objects(parent), C.c_void_p), len(parent),
+            _dev_ptr(cands, "int32", 2 * cands.shape[0]), cands.shape[0], reps,
+            None if cache_path is None else cache_path.encode(), C.byref(t)))
+        return dict(threads=t.threads, tile_px=t.tile_px, radius_mode=t.radius_mode,
+                    cell_over_delta=t.cell_over_delta, ms=t.ms)
+
     def info(self):
         n, h = C.c_int32(), C.c_int32()
         _check(load().perch_get_info(self.h, C.byref(n), C.byref(h)))
@@ -250,6 +278,54 @@ class Context:
         _check(load().perch_render(self.h, C.cast(_objects(objs), C.c_void_p), n,
                                    1 if composite else 0, out.data_ptr()))
         return out
+
+
+class Batch:
+    """Successors of many parents of many scenes in one persistent, graph-replayed
+    launch (work items (parent slot, mesh, pose, 0) as an int32 GPU tensor (n, 4))."""
+
+    def __init__(self, contexts, stream=None):
+        import torch
+
+        self.contexts = list(contexts)  # keeps them alive
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        arr = (C.c_void_p * len(self.contexts))(*[c.h.value for c in self.contexts])
+        h = C.c_void_p()
+        _check(load().perch_batch_create(C.cast(arr, C.c_void_p), len(self.contexts),
+                                         C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().perch_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_tuning(self, threads: int = 0, tile_px: int = 0, use_graph: int = -1, grid: int = -1):
+        _check(load().perch_batch_set_tuning(self.h, threads, tile_px, use_graph, grid))
+
+    def set_parents(self, parents):
+        """parents: list of (context index, [(mesh, pose), ...])."""
+        arr = (PerchParent * max(1, len(parents)))()
+        for k, (ci, objs) in enumerate(parents):
+            arr[k].ctx = int(ci)
+            arr[k].j = len(objs)
+            for o, (m, p) in enumerate(objs):
+                arr[k].objs[o].mesh_id = int(m)
+                arr[k].objs[o].pose_idx = int(p)
+        _check(load().perch_batch_set_parents(self.h, C.cast(arr, C.c_void_p), len(parents)))
+
+    def eval(self, items, cost, status, comps=None):
+        n = items.shape[0]
+        _check(load().perch_batch_eval(
+            self.h, _dev_ptr(items, "int32", 4 * n), n, _dev_ptr(cost, "int32", n),
+            _dev_ptr(status, "int32", n),
+            None if comps is None else _dev_ptr(comps, "int32", 5 * n)))
 
 
 def context_from_scene(scene, depth=None, stream=None) -> Context:

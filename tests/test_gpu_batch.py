@@ -1,0 +1,171 @@
+"""Batched evaluation (one persistent, graph-replayed launch over many parents of
+many scenes) against per-parent evaluation and against the oracle."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import Oracle, render_fn  # noqa: E402
+from paper_1510_05613_amd import perch, scenes  # noqa: E402
+from tests import helpers as H  # noqa: E402
+from tests.test_gpu_parity import compare  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    perch.load()
+
+
+def _gt_parents(sc, ci):
+    """root and every ground-truth prefix of scene sc (context index ci)"""
+    out = []
+    for level in range(sc.K):
+        objs = [(int(sc.obj_mesh[k]), int(sc.gt_pose[k])) for k in sc.gt_order[:level]]
+        out.append((ci, objs))
+    return out
+
+
+def _items_for(parents, scs, rng, per_parent):
+    items = []
+    for slot, (ci, objs) in enumerate(parents):
+        sc = scs[ci]
+        placed = [m for m, _ in objs]
+        rest = list(sc.obj_mesh)
+        for m in placed:
+            rest.remove(m)
+        for _ in range(per_parent):
+            items.append((slot, int(rng.choice(rest)), int(rng.integers(sc.grid.P)), 0))
+    return np.array(items, np.int32)
+
+
+@pytest.fixture(scope="module")
+def mixed():
+    scs = [H.c1_scene(0), H.c1_scene(1), H.c2_scene(0), H.c1_scene(2)]
+    ctxs = [perch.context_from_scene(sc) for sc in scs]
+    return scs, ctxs
+
+
+def _reference(ctxs, parents, items):
+    """per-parent evaluation through perch_eval_successors"""
+    n = len(items)
+    st = np.zeros(n, np.int32)
+    cost = np.zeros(n, np.int32)
+    comps = np.zeros((n, 5), np.int32)
+    for slot, (ci, objs) in enumerate(parents):
+        idx = np.nonzero(items[:, 0] == slot)[0]
+        if len(idx) == 0:
+            continue
+        cands = torch.as_tensor(np.ascontiguousarray(items[idx, 1:3])).cuda()
+        s, c, cp = ctxs[ci].evaluate(objs, cands)
+        torch.cuda.synchronize()
+        st[idx], cost[idx], comps[idx] = s.cpu().numpy(), c.cpu().numpy(), cp.cpu().numpy()
+    return st, cost, comps
+
+
+def test_batch_equals_per_parent_evaluation_and_replays(mixed):
+    scs, ctxs = mixed
+    rng = np.random.default_rng(0)
+    parents = []
+    for ci, sc in enumerate(scs):
+        parents += _gt_parents(sc, ci)
+    items = _items_for(parents, scs, rng, 300)
+    perm = rng.permutation(len(items))
+    items = np.ascontiguousarray(items[perm])
+    ref = _reference(ctxs, parents, items)
+    b = perch.Batch(ctxs)
+    b.set_parents(parents)
+    dev_items = torch.as_tensor(items).cuda()
+    n = len(items)
+    cost = torch.empty(n, dtype=torch.int32, device="cuda")
+    st = torch.empty(n, dtype=torch.int32, device="cuda")
+    comps = torch.empty((n, 5), dtype=torch.int32, device="cuda")
+    for replay in range(4):
+        cost.fill_(-7)
+        st.fill_(-7)
+        # eager work and a synchronisation between graph replays
+        junk = torch.randn(1 << 16, device="cuda").sum()
+        torch.cuda.synchronize()
+        b.eval(dev_items, cost, st, comps)
+        torch.cuda.synchronize()
+        got = (st.cpu().numpy(), cost.cpu().numpy(), comps.cpu().numpy())
+        for a, g in zip(ref, got):
+            assert np.array_equal(a, g), f"replay {replay}"
+        assert float(junk) == float(junk)
+    # without the graph, and with a small explicit grid (many items per workgroup)
+    for use_graph, grid in ((0, 0), (1, 7), (0, 1)):
+        b.set_tuning(0, 0, use_graph, grid)
+        b.eval(dev_items, cost, st, comps)
+        torch.cuda.synchronize()
+        for a, g in zip(ref, (st.cpu().numpy(), cost.cpu().numpy(), comps.cpu().numpy())):
+            assert np.array_equal(a, g), (use_graph, grid)
+    b.close()
+
+
+def test_batch_rejects_bad_parent_slots(mixed):
+    scs, ctxs = mixed
+    b = perch.Batch(ctxs[:1])
+    b.set_parents([(0, [])])
+    items = torch.as_tensor(np.array([[0, int(scs[0].obj_mesh[0]), 5, 0], [3, 0, 0, 0],
+                                      [-1, 0, 0, 0]], np.int32)).cuda()
+    cost = torch.empty(3, dtype=torch.int32, device="cuda")
+    st = torch.empty(3, dtype=torch.int32, device="cuda")
+    b.eval(items, cost, st)
+    torch.cuda.synchronize()
+    assert st.cpu().tolist() == [1, perch.PERCH_SUCC_BAD_INPUT, perch.PERCH_SUCC_BAD_INPUT]
+    with pytest.raises(perch.PerchError):
+        b.set_parents([(5, [])])
+
+
+def test_batched_scenes_with_uneven_meshes_match_oracle():
+    """Config-3 style: scenes of a 12-mesh library from 200 to 20,000 triangles,
+    every level's parent, sampled successors checked against the oracle."""
+    lib = scenes.make_library("c3")
+    scs = [scenes.make_scene(3, i, render_fn, lib) for i in range(4)]
+    ctxs = [perch.context_from_scene(sc) for sc in scs]
+    parents = []
+    for ci, sc in enumerate(scs):
+        parents += _gt_parents(sc, ci)
+    rng = np.random.default_rng(3)
+    items = _items_for(parents, scs, rng, 40)
+    b = perch.Batch(ctxs)
+    b.set_parents(parents)
+    n = len(items)
+    cost = torch.empty(n, dtype=torch.int32, device="cuda")
+    st = torch.empty(n, dtype=torch.int32, device="cuda")
+    comps = torch.empty((n, 5), dtype=torch.int32, device="cuda")
+    b.eval(torch.as_tensor(items).cuda(), cost, st, comps)
+    torch.cuda.synchronize()
+    st, cost, comps = st.cpu().numpy(), cost.cpu().numpy(), comps.cpu().numpy()
+    for slot, (ci, objs) in enumerate(parents):
+        idx = np.nonzero(items[:, 0] == slot)[0]
+        o = Oracle.from_scene(scs[ci], nthreads=8)
+        r = o.eval([m for m, _ in objs], [p for _, p in objs], items[idx, 1], items[idx, 2])
+        compare((st[idx], cost[idx], comps[idx]), r, f"scene {ci} parent {objs}")
+
+
+def test_autotuner_picks_a_setting_and_caches_it(tmp_path):
+    sc = H.c2_scene(0)
+    ctx = perch.context_from_scene(sc)
+    first = sc.gt_order[0]
+    parent = [(int(sc.obj_mesh[first]), int(sc.gt_pose[first]))]
+    m = int(sc.obj_mesh[sc.gt_order[1]])
+    ps = np.arange(0, sc.grid.P, 5, dtype=np.int32)
+    cands = torch.as_tensor(np.stack([np.full(len(ps), m, np.int32), ps], 1)).cuda()
+    before = ctx.evaluate(parent, cands)
+    torch.cuda.synchronize()
+    cache = str(tmp_path / "tune.jsonl")
+    t = ctx.autotune(parent, cands, reps=2, cache_path=cache)
+    assert t["threads"] in (128, 256) and t["radius_mode"] in (0, 1) and t["ms"] > 0
+    after = ctx.evaluate(parent, cands)
+    torch.cuda.synchronize()
+    for a, b in zip(before, after):
+        assert torch.equal(a, b)
+    again = ctx.autotune(parent, cands, reps=2, cache_path=cache)  # served from the cache
+    assert {k: again[k] for k in ("threads", "tile_px", "radius_mode", "cell_over_delta")} == \
+        {k: t[k] for k in ("threads", "tile_px", "radius_mode", "cell_over_delta")}
+    assert abs(again["ms"] - t["ms"]) <= 1e-3 * t["ms"]
+    assert open(cache).read().count("\n") == 1
