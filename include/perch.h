@@ -205,6 +205,55 @@ perch_status perch_batch_eval(perch_batch* b, const perch_work* items_dev, int32
 perch_status perch_batch_set_tuning(perch_batch* b, int32_t threads, int32_t tile_px,
                                     int32_t use_graph, int32_t grid);
 
+/* ---- learned successor-cost network (an inadmissible heuristic, Sec. IV-C) ---- */
+
+/* A small CNN predicting log(1 + c(s, s')) of a successor from a 64 x 64 x 2 depth
+ * crop (observed depth, parent composite) centred on the candidate's table point,
+ * the candidate's mesh and its yaw: 4 x (3x3 conv, 32 channels, ReLU; strides 1, 2,
+ * 2, 2), mean pooling of the 8 x 8 map and of its centre, a 16-d mesh embedding,
+ * and a 64-unit head.  Convolutions run on bfloat16 MFMA with FP32 accumulation;
+ * parameters are FP32 masters trained with Adam.  Parameters are one flat FP32
+ * array in the order cW0 cb0 cW1 cb1 cW2 cb2 cW3 cb3 emb hW1 hb1 hw2 hb2 (conv
+ * weights [32][(ky*3 + kx)*C_in + ci], C_in = 2 then 32; emb [n_mesh][16]; hW1
+ * [64][82] over [pooled 64, embedding 16, cos, sin]). */
+typedef struct perch_cnn perch_cnn;
+
+typedef struct {
+  int32_t crop;      /* crop index within the batch */
+  int32_t mesh_id;
+  float cos_yaw, sin_yaw;
+} perch_cnn_pair;
+
+/* max_crops / max_pairs: largest batch (device memory is sized for it).
+ * Parameters start at zero: set them before use.  Synchronous. */
+perch_status perch_cnn_create(int32_t n_mesh, int32_t max_crops, int32_t max_pairs,
+                              void* hip_stream, perch_cnn** out);
+void perch_cnn_destroy(perch_cnn* net);
+int64_t perch_cnn_param_count(const perch_cnn* net);
+/* host FP32 parameters in / out (set also resets the Adam state).  Synchronous. */
+perch_status perch_cnn_set_params(perch_cnn* net, const float* params, int64_t n);
+perch_status perch_cnn_get_params(perch_cnn* net, float* params, int64_t n);
+/* Crops of the context's current parent (perch_set_parent) for n table points
+ * xy (host, n x 2 metres): device output n x 64 x 64 x 2 bfloat16 (NHWC).
+ * Synchronous. */
+perch_status perch_cnn_crops(perch_ctx* ctx, const float* xy, int32_t n, uint16_t* crops_dev);
+/* Predictions (device, n_pairs floats) of log(1 + cost); a pair whose crop or
+ * mesh index is out of range gets NaN (and is ignored by training).
+ * Asynchronous on the network's stream. */
+perch_status perch_cnn_predict(perch_cnn* net, const uint16_t* crops_dev, int32_t n_crops,
+                               const perch_cnn_pair* pairs_dev, int32_t n_pairs, float* pred_dev);
+/* One Adam step on the mean squared error against target_dev (device, log(1 +
+ * cost)); loss_host (nullable) receives the batch loss before the step (then the
+ * call is synchronous). */
+perch_status perch_cnn_train_step(perch_cnn* net, const uint16_t* crops_dev, int32_t n_crops,
+                                  const perch_cnn_pair* pairs_dev, const float* target_dev,
+                                  int32_t n_pairs, float lr, float* loss_host);
+/* Loss and gradients (host, perch_cnn_param_count floats) without a step.
+ * Synchronous. */
+perch_status perch_cnn_gradients(perch_cnn* net, const uint16_t* crops_dev, int32_t n_crops,
+                                 const perch_cnn_pair* pairs_dev, const float* target_dev,
+                                 int32_t n_pairs, float* grads_host, float* loss_host);
+
 /* ---- tree search (Alg. 1: ComputePath over the implicit MSGT) ---- */
 
 #define PERCH_SEARCH_EXHAUSTIVE 0 /* enumerate the whole tree, argmin (cost, key)        */

@@ -23,7 +23,8 @@ HOST_FLAGS = ["--offload-arch=gfx950", "-O2", "-std=c++17", "-fPIC", "-Wall", "-
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     objs = []
-    for src, flags in (("perch_kernels.hip", DEVICE_FLAGS), ("perch_api.cpp", HOST_FLAGS),
+    for src, flags in (("perch_kernels.hip", DEVICE_FLAGS), ("perch_cnn.hip", DEVICE_FLAGS),
+                       ("perch_cnn_api.cpp", HOST_FLAGS), ("perch_api.cpp", HOST_FLAGS),
                        ("perch_search.cpp", HOST_FLAGS), ("perch_batch.cpp", HOST_FLAGS),
                        ("perch_tune.cpp", HOST_FLAGS)):
         obj = os.path.join(BUILD, src.rsplit(".", 1)[0] + ".o")

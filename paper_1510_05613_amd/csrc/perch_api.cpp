@@ -204,7 +204,7 @@ void perch_destroy(perch_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   for (DevBuf* b : {&c->verts, &c->tris, &c->planes, &c->range, &c->frange, &c->aabb, &c->poses,
                     &c->obs, &c->obs_range, &c->h_keys, &c->h_cells, &c->h_pts, &c->h_counts, &c->par_depth,
-                    &c->par_ubits, &c->par_ucount, &c->s_cands, &c->s_out})
+                    &c->par_ubits, &c->par_ucount, &c->s_cands, &c->s_out, &c->cnn_desc})
     b->release();
   c->s_hcands.release();
   c->s_hout.release();

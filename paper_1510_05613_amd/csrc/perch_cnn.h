@@ -1,0 +1,67 @@
+// perch_cnn.h -- layout of the learned successor-cost network (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace perch {
+namespace cnn {
+
+typedef unsigned short bf16_t;  // bfloat16 bits
+
+constexpr int kCrop = 64;                // crop side (pixels)
+constexpr int kC = 32;                   // channels of every conv layer
+constexpr int kEmb = 16;                 // mesh embedding
+constexpr int kFeat = 2 * kC;            // pooled features (whole map + centre)
+constexpr int kHid = 64;                 // head hidden units
+constexpr int kIn = kFeat + kEmb + 2;    // head input: features, embedding, cos, sin
+
+struct CropDesc {
+  int u0, v0;  // crop centre pixel
+  float zref;  // camera depth of the table point under the candidate
+  int pad;
+};
+
+struct Pair {
+  int crop;  // crop index within the batch
+  int mesh;
+  float cos_yaw, sin_yaw;
+};
+
+// Views of one flat FP32 parameter (or gradient) array, in the order
+// cW0 cb0 cW1 cb1 cW2 cb2 cW3 cb3 emb hW1 hb1 hw2 hb2, conv weights as
+// [co][(ky * 3 + kx) * C_in + ci].
+struct Params {
+  float* cW[4];
+  float* cb[4];
+  float* emb;
+  float* hW1;
+  float* hb1;
+  float* hw2;
+  float* hb2;
+};
+
+struct Net {
+  const bf16_t* crops;  // input of the current call, [n][64][64][2]
+  bf16_t* a[5];         // a[l] = output of conv l (l = 1..4), NHWC, 32 channels
+  bf16_t* d[5];         // d[l] = gradient at the pre-activation of conv l
+  bf16_t* Wb[4];        // bfloat16 conv weights [32][KP]
+  float* feat;          // [n][64]
+  float* dfeat;
+  float* loss;          // sum of squared errors
+  Params P, G;
+};
+
+void launch_crops(const float* obs, const unsigned* pdepth, int W, int H, const CropDesc* desc,
+                  int n, bf16_t* out, hipStream_t s);
+void launch_forward(const Net& net, int n_crops, hipStream_t s);
+// Pairs whose crop index is outside [0, n_crops) or mesh outside [0, n_mesh) are
+// ignored by the backward pass and predicted as NaN.
+void launch_predict(const Net& net, int n_crops, int n_mesh, const Pair* pairs, int n_pairs,
+                    float* pred, hipStream_t s);
+void launch_backward(const Net& net, int n_crops, int n_mesh, const Pair* pairs,
+                     const float* target, int n_pairs, hipStream_t s);
+void launch_adam(float* p, const float* g, float* m, float* v, int n, float lr, int step,
+                 hipStream_t s);
+void launch_pack(const Net& net, hipStream_t s);
+
+}  // namespace cnn
+}  // namespace perch

@@ -1,0 +1,505 @@
+// perch_cnn.hip -- learned successor-cost network: inference and training kernels
+// for gfx950 (bfloat16 MFMA, FP32 accumulation).
+//
+// The paper proposes learned, possibly inadmissible heuristics for its
+// multi-heuristic search (arXiv:1510.05613 Sec. IV-C and the conclusion).  This
+// network predicts log(1 + c(s, s')) of a successor from a 64 x 64 x 2 depth crop
+// (observed depth and the parent's composite, relative to the table point under
+// the candidate), the candidate's mesh and its yaw:
+//   4 x [3x3 conv, 32 channels, ReLU] (strides 1, 2, 2, 2) -> mean over the 8 x 8
+//   map and over its centre 2 x 2 -> [64 + 16-d mesh embedding + cos, sin yaw]
+//   -> 64 (ReLU) -> 1.
+// Convolutions are implicit GEMMs on v_mfma_f32_32x32x16_bf16: forward (pixels x
+// out-channels), input gradient (pixels x in-channels) and weight gradient
+// (out-channels x taps*in-channels, reduced over pixels).  Activations and the
+// gradients fed to the MFMAs are bfloat16; accumulation, pooling, the head, the
+// loss and Adam are FP32.  Tensors are NHWC.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "perch_cnn.h"
+
+namespace perch {
+namespace cnn {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// bfloat16 bits of f, rounded to nearest even (inputs are finite)
+__device__ __forceinline__ bf16_t f2bf(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (bf16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(bf16_t h) { return __uint_as_float(((unsigned)h) << 16); }
+
+__device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+// Row of the 32 x 32 MFMA result held in accumulator element e of lane l:
+// 8 (e / 4) + 4 (l / 32) + e % 4; its column is l % 32.
+__device__ __forceinline__ int acc_row(int e, int lane) {
+  return 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+}
+
+// ---------------------------------------------------------------------------
+// crops
+// ---------------------------------------------------------------------------
+
+// One crop per workgroup: 64 x 64 pixels centred on (u0, v0); channel 0 the
+// observed depth, channel 1 the parent composite, both as (z - zref) / 0.25 clipped
+// to [-1, 1], +1 where there is no return / no parent point or outside the image.
+__global__ void k_crops(const float* obs, const unsigned* pdepth, int W, int H,
+                        const CropDesc* desc, int n, bf16_t* out) {
+  const int c = blockIdx.x;
+  if (c >= n) return;
+  const CropDesc d = desc[c];
+  for (int t = threadIdx.x; t < kCrop * kCrop; t += blockDim.x) {
+    const int cy = t / kCrop, cx = t % kCrop;
+    const int u = d.u0 - kCrop / 2 + cx, v = d.v0 - kCrop / 2 + cy;
+    float a = 1.0f, b = 1.0f;
+    if (u >= 0 && u < W && v >= 0 && v < H) {
+      const float z = obs[v * W + u];
+      if (z > 0.0f) a = fminf(1.0f, fmaxf(-1.0f, (z - d.zref) * 4.0f));
+      if (pdepth) {
+        const unsigned k = pdepth[v * W + u];
+        if (k != 0x7f800000u) b = fminf(1.0f, fmaxf(-1.0f, (__uint_as_float(k) - d.zref) * 4.0f));
+      }
+    }
+    out[((size_t)c * kCrop * kCrop + t) * 2 + 0] = f2bf(a);
+    out[((size_t)c * kCrop * kCrop + t) * 2 + 1] = f2bf(b);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// convolution forward: out[m][co] = relu(b[co] + sum_k patch[m][k] W[co][k])
+// ---------------------------------------------------------------------------
+
+template <int CIN>
+struct KDim {
+  static constexpr int K = 9 * CIN;                  // taps x input channels
+  static constexpr int KP = (K + 15) / 16 * 16;      // padded to the MFMA depth
+  static constexpr int LDSROW = KP + 8;              // LDS row stride (bank spread)
+};
+
+// Eight consecutive k of the im2col patch of output pixel (n, oy, ox).
+template <int CIN, int S, int HIN>
+__device__ __forceinline__ uint4 patch8(const bf16_t* __restrict__ in, bool valid, int n, int oy,
+                                        int ox, int k0) {
+  uint4 r = make_uint4(0u, 0u, 0u, 0u);
+  if (!valid) return r;
+  if (CIN % 8 == 0) {
+    const int tap = k0 / CIN, ci0 = k0 % CIN;
+    const int iy = oy * S + tap / 3 - 1, ix = ox * S + tap % 3 - 1;
+    if (tap < 9 && iy >= 0 && iy < HIN && ix >= 0 && ix < HIN)
+      r = *reinterpret_cast<const uint4*>(in + (((size_t)n * HIN + iy) * HIN + ix) * CIN + ci0);
+  } else {
+    unsigned short v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int k = k0 + q;
+      v[q] = 0;
+      if (k < 9 * CIN) {
+        const int tap = k / CIN, ci = k % CIN;
+        const int iy = oy * S + tap / 3 - 1, ix = ox * S + tap % 3 - 1;
+        if (iy >= 0 && iy < HIN && ix >= 0 && ix < HIN)
+          v[q] = in[(((size_t)n * HIN + iy) * HIN + ix) * CIN + ci];
+      }
+    }
+    r.x = v[0] | ((unsigned)v[1] << 16);
+    r.y = v[2] | ((unsigned)v[3] << 16);
+    r.z = v[4] | ((unsigned)v[5] << 16);
+    r.w = v[6] | ((unsigned)v[7] << 16);
+  }
+  return r;
+}
+
+// 4 waves per workgroup, each a 32-pixel x 32-channel output tile.
+template <int CIN, int S, int HIN>
+__global__ void __launch_bounds__(256)
+    k_conv_fwd(const bf16_t* __restrict__ in, const bf16_t* __restrict__ Wb,
+               const float* __restrict__ bias, bf16_t* __restrict__ out, int n_img) {
+  using D = KDim<CIN>;
+  constexpr int HO = HIN / S, NPIX = HO * HO;
+  __shared__ __align__(16) bf16_t w[kC * D::LDSROW];
+  for (int i = threadIdx.x; i < kC * D::KP; i += blockDim.x)
+    w[(i / D::KP) * D::LDSROW + i % D::KP] = Wb[i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int total = n_img * NPIX;
+  const int m0 = (blockIdx.x * 4 + wave) * 32;
+  if (m0 >= total) return;
+  const int m = m0 + (lane & 31);
+  const bool mv = m < total;
+  const int n = m / NPIX, pix = m % NPIX, oy = pix / HO, ox = pix % HO;
+  const int kh = 8 * (lane >> 5);
+  f32x16 acc = {};
+  for (int kc = 0; kc < D::KP / 16; ++kc) {
+    const int k0 = kc * 16 + kh;
+    const uint4 a = patch8<CIN, S, HIN>(in, mv, n, oy, ox, k0);
+    const uint4 b = *reinterpret_cast<const uint4*>(w + (lane & 31) * D::LDSROW + k0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(a), as_bf16x8(b), acc, 0, 0, 0);
+  }
+  const int co = lane & 31;
+  const float bb = bias[co];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int mm = m0 + acc_row(e, lane);
+    if (mm < total) out[(size_t)mm * kC + co] = f2bf(fmaxf(acc[e] + bb, 0.0f));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// convolution input gradient: din[m][ci] = mask(m, ci) sum_{tap, co} dpre[o(m,tap)][co] W[co][tap][ci]
+// ---------------------------------------------------------------------------
+
+template <int S, int HIN>
+__global__ void __launch_bounds__(256)
+    k_conv_dgrad(const bf16_t* __restrict__ dpre, const bf16_t* __restrict__ Wb,
+                 const bf16_t* __restrict__ act_in, bf16_t* __restrict__ din, int n_img) {
+  constexpr int HO = HIN / S, NPIX = HIN * HIN, K = 9 * kC, ROW = K + 8;
+  __shared__ __align__(16) bf16_t wt[kC * ROW];  // wt[ci][tap * 32 + co]
+  for (int i = threadIdx.x; i < kC * K; i += blockDim.x) {
+    const int co = i / K, r = i % K, tap = r / kC, ci = r % kC;
+    wt[ci * ROW + tap * kC + co] = Wb[i];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int total = n_img * NPIX;
+  const int m0 = (blockIdx.x * 4 + wave) * 32;
+  if (m0 >= total) return;
+  const int m = m0 + (lane & 31);
+  const bool mv = m < total;
+  const int n = m / NPIX, pix = m % NPIX, iy = pix / HIN, ix = pix % HIN;
+  const int kh = 8 * (lane >> 5);
+  f32x16 acc = {};
+  for (int kc = 0; kc < K / 16; ++kc) {
+    const int k0 = kc * 16 + kh;
+    const int tap = k0 / kC, co0 = k0 % kC;
+    const int ny = iy + 1 - tap / 3, nx = ix + 1 - tap % 3;  // = o * S when o is a tap source
+    uint4 a = make_uint4(0u, 0u, 0u, 0u);
+    if (mv && ny >= 0 && nx >= 0 && ny % S == 0 && nx % S == 0 && ny / S < HO && nx / S < HO)
+      a = *reinterpret_cast<const uint4*>(dpre +
+                                          (((size_t)n * HO + ny / S) * HO + nx / S) * kC + co0);
+    const uint4 b = *reinterpret_cast<const uint4*>(wt + (lane & 31) * ROW + k0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(a), as_bf16x8(b), acc, 0, 0, 0);
+  }
+  const int ci = lane & 31;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int mm = m0 + acc_row(e, lane);
+    if (mm < total) {
+      const bool on = bf2f(act_in[(size_t)mm * kC + ci]) > 0.0f;  // ReLU of the previous layer
+      din[(size_t)mm * kC + ci] = f2bf(on ? acc[e] : 0.0f);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// convolution weight gradient: dW[co][k] += sum_m dpre[m][co] patch[m][k]
+// ---------------------------------------------------------------------------
+
+// Workgroup (kt, chunk): k columns [32 kt, 32 kt + 32), output pixels
+// [chunk * 64 * PW, ...); each wave reduces PW groups of 16 pixels with MFMAs and
+// adds its 32 x 32 partial to dW with atomics.
+template <int CIN, int S, int HIN, int PW>
+__global__ void __launch_bounds__(256)
+    k_conv_wgrad(const bf16_t* __restrict__ dpre, const bf16_t* __restrict__ in,
+                 float* __restrict__ dW, int n_img) {
+  constexpr int HO = HIN / S, NPIX = HO * HO, K = 9 * CIN;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int total = n_img * NPIX;
+  const int kt = blockIdx.x;
+  const int pbase = (blockIdx.y * 4 + wave) * 16 * PW;
+  if (pbase >= total) return;
+  const int co = lane & 31;
+  const int kk = kt * 32 + (lane & 31);
+  const int tap = kk / CIN, ci = kk % CIN;
+  const int ky = tap / 3, kx = tap % 3;
+  const int ph = 8 * (lane >> 5);
+  f32x16 acc = {};
+  for (int g = 0; g < PW; ++g) {
+    const int p0 = pbase + g * 16 + ph;
+    unsigned short av[8], bv[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int p = p0 + q;
+      av[q] = 0;
+      bv[q] = 0;
+      if (p < total) {
+        av[q] = dpre[(size_t)p * kC + co];
+        if (kk < K) {
+          const int n = p / NPIX, pix = p % NPIX, oy = pix / HO, ox = pix % HO;
+          const int iy = oy * S + ky - 1, ix = ox * S + kx - 1;
+          if (iy >= 0 && iy < HIN && ix >= 0 && ix < HIN)
+            bv[q] = in[(((size_t)n * HIN + iy) * HIN + ix) * CIN + ci];
+        }
+      }
+    }
+    uint4 a, b;
+    a.x = av[0] | ((unsigned)av[1] << 16); a.y = av[2] | ((unsigned)av[3] << 16);
+    a.z = av[4] | ((unsigned)av[5] << 16); a.w = av[6] | ((unsigned)av[7] << 16);
+    b.x = bv[0] | ((unsigned)bv[1] << 16); b.y = bv[2] | ((unsigned)bv[3] << 16);
+    b.z = bv[4] | ((unsigned)bv[5] << 16); b.w = bv[6] | ((unsigned)bv[7] << 16);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(a), as_bf16x8(b), acc, 0, 0, 0);
+  }
+  // D[row = co][col = k]
+  const int col = kt * 32 + (lane & 31);
+  if (col < K) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) atomicAdd(&dW[acc_row(e, lane) * K + col], acc[e]);
+  }
+}
+
+// db[co] += sum_m dpre[m][co]
+__global__ void k_bias_grad(const bf16_t* dpre, int total, float* db) {
+  __shared__ float part[256];
+  const int co = threadIdx.x & 31, grp = threadIdx.x >> 5;
+  float s = 0.0f;
+  for (int m = blockIdx.x * 8 + grp; m < total; m += gridDim.x * 8) s += bf2f(dpre[(size_t)m * kC + co]);
+  part[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x < 32) {
+    float t = 0.0f;
+    for (int g = 0; g < 8; ++g) t += part[g * 32 + threadIdx.x];
+    atomicAdd(&db[threadIdx.x], t);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// pooling and head
+// ---------------------------------------------------------------------------
+
+// feat[n] = [mean over 8 x 8 of a4[n], mean over the centre 2 x 2 of a4[n]]
+__global__ void k_pool_fwd(const bf16_t* a4, int n_img, float* feat) {
+  const int n = blockIdx.x, c = threadIdx.x;
+  if (n >= n_img || c >= kC) return;
+  float s = 0.0f, sc = 0.0f;
+  for (int p = 0; p < 64; ++p) {
+    const float v = bf2f(a4[((size_t)n * 64 + p) * kC + c]);
+    s += v;
+    const int y = p / 8, x = p % 8;
+    if (y >= 3 && y <= 4 && x >= 3 && x <= 4) sc += v;
+  }
+  feat[n * kFeat + c] = s / 64.0f;
+  feat[n * kFeat + kC + c] = sc / 4.0f;
+}
+
+__global__ void k_pool_bwd(const float* dfeat, const bf16_t* a4, int n_img, bf16_t* dpre4) {
+  const int n = blockIdx.x;
+  if (n >= n_img) return;
+  for (int t = threadIdx.x; t < 64 * kC; t += blockDim.x) {
+    const int p = t / kC, c = t % kC, y = p / 8, x = p % 8;
+    float g = dfeat[n * kFeat + c] / 64.0f;
+    if (y >= 3 && y <= 4 && x >= 3 && x <= 4) g += dfeat[n * kFeat + kC + c] / 4.0f;
+    const bool on = bf2f(a4[(size_t)n * 64 * kC + t]) > 0.0f;
+    dpre4[(size_t)n * 64 * kC + t] = f2bf(on ? g : 0.0f);
+  }
+}
+
+// head input of pair q: [feat (64), emb (16), cos, sin]
+__device__ __forceinline__ void head_input(const float* feat, const float* emb, const Pair& pr,
+                                           float* h) {
+  for (int i = 0; i < kFeat; ++i) h[i] = feat[pr.crop * kFeat + i];
+  for (int i = 0; i < kEmb; ++i) h[kFeat + i] = emb[pr.mesh * kEmb + i];
+  h[kFeat + kEmb] = pr.cos_yaw;
+  h[kFeat + kEmb + 1] = pr.sin_yaw;
+}
+
+// A pair is usable when its crop and mesh indices are in range.
+__device__ __forceinline__ bool pair_ok(const Pair& pr, int n_crops, int n_mesh) {
+  return pr.crop >= 0 && pr.crop < n_crops && pr.mesh >= 0 && pr.mesh < n_mesh;
+}
+
+// Prediction per pair (NaN for a pair with an out-of-range crop or mesh index).
+__global__ void k_head_fwd(const float* feat, const Params P, const Pair* pairs, int n_pairs,
+                           int n_crops, int n_mesh, float* pred) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n_pairs) return;
+  if (!pair_ok(pairs[q], n_crops, n_mesh)) {
+    pred[q] = __uint_as_float(0x7fc00000u);
+    return;
+  }
+  float h[kIn];
+  head_input(feat, P.emb, pairs[q], h);
+  float y = P.hb2[0];
+  for (int r = 0; r < kHid; ++r) {
+    float z = P.hb1[r];
+    for (int i = 0; i < kIn; ++i) z = fmaf(P.hW1[r * kIn + i], h[i], z);
+    y = fmaf(P.hw2[r], fmaxf(z, 0.0f), y);
+  }
+  pred[q] = y;
+}
+
+// Loss and head gradients for 64 pairs per workgroup: per-pair h and dz1 go to
+// LDS, the weight gradients are reduced over the workgroup's pairs and added once.
+__global__ void __launch_bounds__(64)
+    k_head_bwd(const float* feat, const Params P, const Pair* pairs, const float* target,
+               int n_pairs, int n_crops, int n_mesh, Params G, float* dfeat, float* loss_sum) {
+  __shared__ float sh[64][kIn];    // head input per pair
+  __shared__ float sdz[64][kHid];  // d loss / d z1 per pair
+  __shared__ float sr1[64][kHid];  // relu(z1) per pair
+  __shared__ float sdy[64];        // d loss / d y per pair
+  const int t = threadIdx.x;
+  const int q = blockIdx.x * 64 + t;
+  const Pair pr = q < n_pairs ? pairs[q] : Pair{0, 0, 0.0f, 0.0f};
+  const bool live = q < n_pairs && pair_ok(pr, n_crops, n_mesh);  // bad pairs contribute nothing
+  float dy = 0.0f;
+  if (live) {
+    head_input(feat, P.emb, pr, sh[t]);
+    float y = P.hb2[0];
+    for (int r = 0; r < kHid; ++r) {
+      float z = P.hb1[r];
+      for (int i = 0; i < kIn; ++i) z = fmaf(P.hW1[r * kIn + i], sh[t][i], z);
+      sr1[t][r] = fmaxf(z, 0.0f);
+      sdz[t][r] = z;  // pre-activation for now
+      y = fmaf(P.hw2[r], fmaxf(z, 0.0f), y);
+    }
+    const float diff = y - target[q];
+    atomicAdd(loss_sum, diff * diff);
+    dy = 2.0f * diff / (float)n_pairs;
+    for (int r = 0; r < kHid; ++r) sdz[t][r] = sdz[t][r] > 0.0f ? dy * P.hw2[r] : 0.0f;
+  } else {
+    for (int i = 0; i < kIn; ++i) sh[t][i] = 0.0f;
+    for (int r = 0; r < kHid; ++r) {
+      sr1[t][r] = 0.0f;
+      sdz[t][r] = 0.0f;
+    }
+  }
+  sdy[t] = dy;
+  __syncthreads();
+  // dh = W1^T dz1 -> dfeat (per crop) and the embedding gradient (per mesh)
+  if (live) {
+    for (int i = 0; i < kFeat + kEmb; ++i) {
+      float s = 0.0f;
+      for (int r = 0; r < kHid; ++r) s = fmaf(P.hW1[r * kIn + i], sdz[t][r], s);
+      if (i < kFeat)
+        atomicAdd(&dfeat[pr.crop * kFeat + i], s);
+      else
+        atomicAdd(&G.emb[pr.mesh * kEmb + (i - kFeat)], s);
+    }
+  }
+  // weight gradients reduced over the workgroup's pairs
+  for (int e = t; e < kHid * kIn; e += 64) {
+    const int r = e / kIn, i = e % kIn;
+    float s = 0.0f;
+    for (int u = 0; u < 64; ++u) s = fmaf(sdz[u][r], sh[u][i], s);
+    atomicAdd(&G.hW1[e], s);
+  }
+  {
+    const int r = t;  // kHid == blockDim.x
+    float sb = 0.0f, sw = 0.0f;
+    for (int u = 0; u < 64; ++u) {
+      sb += sdz[u][r];
+      sw = fmaf(sdy[u], sr1[u][r], sw);
+    }
+    atomicAdd(&G.hb1[r], sb);
+    atomicAdd(&G.hw2[r], sw);
+  }
+  if (t == 0) {
+    float s = 0.0f;
+    for (int u = 0; u < 64; ++u) s += sdy[u];
+    atomicAdd(&G.hb2[0], s);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// optimiser and weight packing
+// ---------------------------------------------------------------------------
+
+__global__ void k_adam(float* p, const float* g, float* m, float* v, int n, float lr, float b1,
+                       float b2, float eps, float c1, float c2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// bfloat16 MFMA copies of the conv weights: Wb[co][k] (k padded to KP with 0)
+__global__ void k_pack(const float* master, int K, int KP, bf16_t* Wb) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= kC * KP) return;
+  const int co = i / KP, k = i % KP;
+  Wb[i] = k < K ? f2bf(master[co * K + k]) : (bf16_t)0;
+}
+
+// ---------------------------------------------------------------------------
+// host-side launch helpers
+// ---------------------------------------------------------------------------
+
+void launch_crops(const float* obs, const unsigned* pdepth, int W, int H, const CropDesc* desc,
+                  int n, bf16_t* out, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_crops, dim3(n), dim3(256), 0, s, obs, pdepth, W, H, desc, n, out);
+}
+
+static int conv_blocks(int n_img, int npix) { return (n_img * npix + 127) / 128; }
+
+void launch_forward(const Net& net, int n_crops, hipStream_t s) {
+  hipLaunchKernelGGL((k_conv_fwd<2, 1, 64>), dim3(conv_blocks(n_crops, 64 * 64)), dim3(256), 0, s,
+                     net.crops, net.Wb[0], net.P.cb[0], net.a[1], n_crops);
+  hipLaunchKernelGGL((k_conv_fwd<32, 2, 64>), dim3(conv_blocks(n_crops, 32 * 32)), dim3(256), 0,
+                     s, net.a[1], net.Wb[1], net.P.cb[1], net.a[2], n_crops);
+  hipLaunchKernelGGL((k_conv_fwd<32, 2, 32>), dim3(conv_blocks(n_crops, 16 * 16)), dim3(256), 0,
+                     s, net.a[2], net.Wb[2], net.P.cb[2], net.a[3], n_crops);
+  hipLaunchKernelGGL((k_conv_fwd<32, 2, 16>), dim3(conv_blocks(n_crops, 8 * 8)), dim3(256), 0, s,
+                     net.a[3], net.Wb[3], net.P.cb[3], net.a[4], n_crops);
+  hipLaunchKernelGGL(k_pool_fwd, dim3(n_crops), dim3(kC), 0, s, net.a[4], n_crops, net.feat);
+}
+
+void launch_predict(const Net& net, int n_crops, int n_mesh, const Pair* pairs, int n_pairs,
+                    float* pred, hipStream_t s) {
+  if (n_pairs > 0)
+    hipLaunchKernelGGL(k_head_fwd, dim3((n_pairs + 127) / 128), dim3(128), 0, s, net.feat, net.P,
+                       pairs, n_pairs, n_crops, n_mesh, pred);
+}
+
+template <int CIN, int S, int HIN>
+static void wgrad(const bf16_t* dpre, const bf16_t* in, float* dW, float* db, int n_img,
+                  hipStream_t s) {
+  constexpr int HO = HIN / S, K = 9 * CIN, PW = 8;
+  const int total = n_img * HO * HO;
+  const dim3 grid((K + 31) / 32, (total + 64 * PW - 1) / (64 * PW));
+  hipLaunchKernelGGL((k_conv_wgrad<CIN, S, HIN, PW>), grid, dim3(256), 0, s, dpre, in, dW, n_img);
+  const int bb = std::min(1024, (total + 7) / 8);
+  hipLaunchKernelGGL(k_bias_grad, dim3(bb), dim3(256), 0, s, dpre, total, db);
+}
+
+void launch_backward(const Net& net, int n_crops, int n_mesh, const Pair* pairs,
+                     const float* target, int n_pairs, hipStream_t s) {
+  hipLaunchKernelGGL(k_head_bwd, dim3((n_pairs + 63) / 64), dim3(64), 0, s, net.feat, net.P,
+                     pairs, target, n_pairs, n_crops, n_mesh, net.G, net.dfeat, net.loss);
+  hipLaunchKernelGGL(k_pool_bwd, dim3(n_crops), dim3(256), 0, s, net.dfeat, net.a[4], n_crops,
+                     net.d[4]);
+  wgrad<32, 2, 16>(net.d[4], net.a[3], net.G.cW[3], net.G.cb[3], n_crops, s);
+  hipLaunchKernelGGL((k_conv_dgrad<2, 16>), dim3(conv_blocks(n_crops, 16 * 16)), dim3(256), 0, s,
+                     net.d[4], net.Wb[3], net.a[3], net.d[3], n_crops);
+  wgrad<32, 2, 32>(net.d[3], net.a[2], net.G.cW[2], net.G.cb[2], n_crops, s);
+  hipLaunchKernelGGL((k_conv_dgrad<2, 32>), dim3(conv_blocks(n_crops, 32 * 32)), dim3(256), 0, s,
+                     net.d[3], net.Wb[2], net.a[2], net.d[2], n_crops);
+  wgrad<32, 2, 64>(net.d[2], net.a[1], net.G.cW[1], net.G.cb[1], n_crops, s);
+  hipLaunchKernelGGL((k_conv_dgrad<2, 64>), dim3(conv_blocks(n_crops, 64 * 64)), dim3(256), 0, s,
+                     net.d[2], net.Wb[1], net.a[1], net.d[1], n_crops);
+  wgrad<2, 1, 64>(net.d[1], net.crops, net.G.cW[0], net.G.cb[0], n_crops, s);
+}
+
+void launch_adam(float* p, const float* g, float* m, float* v, int n, float lr, int step,
+                 hipStream_t s) {
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+  hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, s, p, g, m, v, n, lr, b1, b2,
+                     1e-8f, c1, c2);
+}
+
+void launch_pack(const Net& net, hipStream_t s) {
+  const int Ks[4] = {18, 288, 288, 288}, KPs[4] = {32, 288, 288, 288};
+  for (int l = 0; l < 4; ++l)
+    hipLaunchKernelGGL(k_pack, dim3((kC * KPs[l] + 255) / 256), dim3(256), 0, s, net.P.cW[l],
+                       Ks[l], KPs[l], net.Wb[l]);
+}
+
+}  // namespace cnn
+}  // namespace perch

@@ -1,0 +1,256 @@
+// perch_cnn_api.cpp -- C ABI of the learned successor-cost network (see
+// perch_cnn.hip for the kernels and include/perch.h for the contract).
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "perch_cnn.h"
+#include "perch_ctx.h"
+
+using namespace perch;
+using namespace perch::cnn;
+
+struct perch_cnn {
+  int n_mesh = 0, max_crops = 0, max_pairs = 0;
+  hipStream_t stream = nullptr;
+  int64_t n_params = 0;
+  int step = 0;
+  DevBuf params, grads, m, v;  // FP32, flat
+  DevBuf act, dact, wb, feat, dfeat, loss;
+  Net net{};
+  int64_t off[13];  // offsets of the 13 tensors in the flat arrays
+};
+
+namespace {
+
+void sizes(int n_mesh, int64_t* sz) {
+  int64_t k = 0;
+  const int cin[4] = {2, kC, kC, kC};
+  for (int l = 0; l < 4; ++l) {
+    sz[k++] = (int64_t)kC * 9 * cin[l];
+    sz[k++] = kC;
+  }
+  sz[k++] = (int64_t)n_mesh * kEmb;
+  sz[k++] = (int64_t)kHid * kIn;
+  sz[k++] = kHid;
+  sz[k++] = kHid;
+  sz[k++] = 1;
+}
+
+Params views(float* base, const int64_t* off) {
+  Params p;
+  for (int l = 0; l < 4; ++l) {
+    p.cW[l] = base + off[2 * l];
+    p.cb[l] = base + off[2 * l + 1];
+  }
+  p.emb = base + off[8];
+  p.hW1 = base + off[9];
+  p.hb1 = base + off[10];
+  p.hw2 = base + off[11];
+  p.hb2 = base + off[12];
+  return p;
+}
+
+}  // namespace
+
+extern "C" {
+
+perch_status perch_cnn_create(int32_t n_mesh, int32_t max_crops, int32_t max_pairs,
+                              void* hip_stream, perch_cnn** out) {
+  if (!out || n_mesh < 1 || max_crops < 1 || max_pairs < 1 || max_crops > 65536)
+    return fail(PERCH_E_ARG, "bad network sizes");
+  *out = nullptr;
+  perch_cnn* c = new perch_cnn();
+  c->n_mesh = n_mesh;
+  c->max_crops = max_crops;
+  c->max_pairs = max_pairs;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  int64_t sz[13];
+  sizes(n_mesh, sz);
+  int64_t o = 0;
+  for (int k = 0; k < 13; ++k) {
+    c->off[k] = o;
+    o += sz[k];
+  }
+  c->n_params = o;
+  const size_t pb = (size_t)o * sizeof(float);
+  const size_t per_crop = (size_t)kC * (64 * 64 + 32 * 32 + 16 * 16 + 8 * 8);  // a1..a4 elements
+  const size_t kp[4] = {32, 288, 288, 288};
+  hipError_t e = hipSuccess;
+  for (DevBuf* b : {&c->params, &c->grads, &c->m, &c->v})
+    if (e == hipSuccess) e = b->ensure(pb);
+  if (e == hipSuccess) e = c->act.ensure(per_crop * max_crops * sizeof(bf16_t));
+  if (e == hipSuccess) e = c->dact.ensure(per_crop * max_crops * sizeof(bf16_t));
+  if (e == hipSuccess) e = c->wb.ensure((kp[0] + 3 * kp[1]) * kC * sizeof(bf16_t));
+  if (e == hipSuccess) e = c->feat.ensure((size_t)max_crops * kFeat * sizeof(float));
+  if (e == hipSuccess) e = c->dfeat.ensure((size_t)max_crops * kFeat * sizeof(float));
+  if (e == hipSuccess) e = c->loss.ensure(sizeof(float));
+  if (e == hipSuccess) e = hipMemsetAsync(c->params.p, 0, pb, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->m.p, 0, pb, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->v.p, 0, pb, c->stream);
+  if (e != hipSuccess) {
+    for (DevBuf* b : {&c->params, &c->grads, &c->m, &c->v, &c->act, &c->dact, &c->wb, &c->feat,
+                      &c->dfeat, &c->loss})
+      b->release();
+    delete c;
+    return fail(e == hipErrorOutOfMemory ? PERCH_E_OOM : PERCH_E_HIP, "network setup: %s",
+                hipGetErrorString(e));
+  }
+  Net& n = c->net;
+  bf16_t* a = c->act.as<bf16_t>();
+  bf16_t* d = c->dact.as<bf16_t>();
+  const size_t sp[5] = {0, 64 * 64, 32 * 32, 16 * 16, 8 * 8};
+  n.a[0] = n.d[0] = nullptr;
+  for (int l = 1; l <= 4; ++l) {
+    n.a[l] = a;
+    n.d[l] = d;
+    a += sp[l] * kC * max_crops;
+    d += sp[l] * kC * max_crops;
+  }
+  bf16_t* w = c->wb.as<bf16_t>();
+  for (int l = 0; l < 4; ++l) {
+    n.Wb[l] = w;
+    w += kp[l] * kC;
+  }
+  n.feat = c->feat.as<float>();
+  n.dfeat = c->dfeat.as<float>();
+  n.loss = c->loss.as<float>();
+  n.P = views(c->params.as<float>(), c->off);
+  n.G = views(c->grads.as<float>(), c->off);
+  launch_pack(n, c->stream);
+  *out = c;
+  return PERCH_OK;
+}
+
+void perch_cnn_destroy(perch_cnn* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (DevBuf* b : {&c->params, &c->grads, &c->m, &c->v, &c->act, &c->dact, &c->wb, &c->feat,
+                    &c->dfeat, &c->loss})
+    b->release();
+  delete c;
+}
+
+int64_t perch_cnn_param_count(const perch_cnn* c) { return c ? c->n_params : -1; }
+
+perch_status perch_cnn_set_params(perch_cnn* c, const float* host, int64_t n) {
+  if (!c || !host || n != c->n_params) return fail(PERCH_E_ARG, "parameter count mismatch");
+  HIP_TRY(hipMemcpyAsync(c->params.p, host, n * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemsetAsync(c->m.p, 0, n * sizeof(float), c->stream));
+  HIP_TRY(hipMemsetAsync(c->v.p, 0, n * sizeof(float), c->stream));
+  launch_pack(c->net, c->stream);
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->step = 0;
+  return PERCH_OK;
+}
+
+perch_status perch_cnn_get_params(perch_cnn* c, float* host, int64_t n) {
+  if (!c || !host || n != c->n_params) return fail(PERCH_E_ARG, "parameter count mismatch");
+  HIP_TRY(hipMemcpyAsync(host, c->params.p, n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return PERCH_OK;
+}
+
+perch_status perch_cnn_crops(perch_ctx* ctx, const float* xy, int32_t n, uint16_t* crops_dev) {
+  if (!ctx || n < 0 || (n > 0 && (!xy || !crops_dev))) return fail(PERCH_E_ARG, "bad arguments");
+  if (!ctx->has_obs) return fail(PERCH_E_STATE, "perch_set_observation not called");
+  if (ctx->parent_j < 0) return fail(PERCH_E_STATE, "perch_set_parent not called");
+  if (n == 0) return PERCH_OK;
+  // crop centre: the table point (x, y, 0) projected to the nearest pixel
+  std::vector<CropDesc> d(n);
+  const Cam& cam = ctx->cam;
+  for (int k = 0; k < n; ++k) {
+    double p[3];
+    for (int r = 0; r < 3; ++r)
+      p[r] = (double)cam.M[4 * r] * xy[2 * k] + (double)cam.M[4 * r + 1] * xy[2 * k + 1] +
+             cam.M[4 * r + 3];
+    if (!(p[2] > 0.01)) return fail(PERCH_E_ARG, "crop centre %d behind the camera", k);
+    d[k].u0 = (int)std::lround(cam.fx * p[0] / p[2] + cam.cx);
+    d[k].v0 = (int)std::lround(cam.fy * p[1] / p[2] + cam.cy);
+    d[k].zref = (float)p[2];
+    d[k].pad = 0;
+  }
+  HIP_TRY(ctx->cnn_desc.ensure(sizeof(CropDesc) * n));
+  HIP_TRY(hipMemcpyAsync(ctx->cnn_desc.p, d.data(), sizeof(CropDesc) * n, hipMemcpyHostToDevice,
+                         ctx->stream));
+  launch_crops(ctx->obs.as<float>(), ctx->par_depth.as<unsigned>(), cam.W, cam.H,
+               ctx->cnn_desc.as<CropDesc>(), n, crops_dev, ctx->stream);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(ctx->stream));  // the host descriptors die here
+  return PERCH_OK;
+}
+
+static perch_status check_batch(perch_cnn* c, const uint16_t* crops, int32_t n_crops,
+                                const perch_cnn_pair* pairs, int32_t n_pairs) {
+  if (!c || !crops || !pairs || n_crops < 1 || n_pairs < 1)
+    return fail(PERCH_E_ARG, "empty or null batch");
+  if (n_crops > c->max_crops || n_pairs > c->max_pairs)
+    return fail(PERCH_E_ARG, "batch (%d crops, %d pairs) above the network's capacity (%d, %d)",
+                n_crops, n_pairs, c->max_crops, c->max_pairs);
+  return PERCH_OK;
+}
+
+perch_status perch_cnn_predict(perch_cnn* c, const uint16_t* crops_dev, int32_t n_crops,
+                               const perch_cnn_pair* pairs_dev, int32_t n_pairs, float* pred_dev) {
+  perch_status st = check_batch(c, crops_dev, n_crops, pairs_dev, n_pairs);
+  if (st) return st;
+  if (!pred_dev) return fail(PERCH_E_ARG, "null output");
+  c->net.crops = crops_dev;
+  launch_forward(c->net, n_crops, c->stream);
+  launch_predict(c->net, n_crops, c->n_mesh, reinterpret_cast<const Pair*>(pairs_dev), n_pairs,
+                 pred_dev, c->stream);
+  HIP_TRY(hipGetLastError());
+  return PERCH_OK;
+}
+
+static perch_status run_backward(perch_cnn* c, const uint16_t* crops, int32_t n_crops,
+                                 const perch_cnn_pair* pairs, const float* target, int32_t n_pairs,
+                                 float* loss_host) {
+  HIP_TRY(hipMemsetAsync(c->grads.p, 0, c->n_params * sizeof(float), c->stream));
+  HIP_TRY(hipMemsetAsync(c->dfeat.p, 0, (size_t)n_crops * kFeat * sizeof(float), c->stream));
+  HIP_TRY(hipMemsetAsync(c->loss.p, 0, sizeof(float), c->stream));
+  c->net.crops = crops;
+  launch_forward(c->net, n_crops, c->stream);
+  launch_backward(c->net, n_crops, c->n_mesh, reinterpret_cast<const Pair*>(pairs), target,
+                  n_pairs, c->stream);
+  HIP_TRY(hipGetLastError());
+  if (loss_host) {
+    float s = 0.0f;
+    HIP_TRY(hipMemcpyAsync(&s, c->loss.p, sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    *loss_host = s / (float)n_pairs;
+  }
+  return PERCH_OK;
+}
+
+perch_status perch_cnn_gradients(perch_cnn* c, const uint16_t* crops_dev, int32_t n_crops,
+                                 const perch_cnn_pair* pairs_dev, const float* target_dev,
+                                 int32_t n_pairs, float* grads_host, float* loss_host) {
+  perch_status st = check_batch(c, crops_dev, n_crops, pairs_dev, n_pairs);
+  if (st) return st;
+  if (!target_dev || !grads_host) return fail(PERCH_E_ARG, "null argument");
+  st = run_backward(c, crops_dev, n_crops, pairs_dev, target_dev, n_pairs, loss_host);
+  if (st) return st;
+  HIP_TRY(hipMemcpyAsync(grads_host, c->grads.p, c->n_params * sizeof(float),
+                         hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return PERCH_OK;
+}
+
+perch_status perch_cnn_train_step(perch_cnn* c, const uint16_t* crops_dev, int32_t n_crops,
+                                  const perch_cnn_pair* pairs_dev, const float* target_dev,
+                                  int32_t n_pairs, float lr, float* loss_host) {
+  perch_status st = check_batch(c, crops_dev, n_crops, pairs_dev, n_pairs);
+  if (st) return st;
+  if (!target_dev || !(lr > 0)) return fail(PERCH_E_ARG, "bad target or learning rate");
+  st = run_backward(c, crops_dev, n_crops, pairs_dev, target_dev, n_pairs, loss_host);
+  if (st) return st;
+  c->step += 1;
+  launch_adam(c->params.as<float>(), c->grads.as<float>(), c->m.as<float>(), c->v.as<float>(),
+              (int)c->n_params, lr, c->step, c->stream);
+  launch_pack(c->net, c->stream);
+  HIP_TRY(hipGetLastError());
+  return PERCH_OK;
+}
+
+}  // extern "C"

@@ -116,6 +116,8 @@ struct perch_ctx {
   // parent buffers (parent_j = level of the materialised parent, -1 = none)
   DevBuf par_depth, par_ubits, par_ucount;
   int parent_j = -1;
+  // crop descriptors of the learned heuristic
+  DevBuf cnn_desc;
   // search scratch: candidate list and outputs of one expansion
   DevBuf s_cands, s_out;
   PinnedBuf s_hcands, s_hout;

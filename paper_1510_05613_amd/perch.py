@@ -28,7 +28,9 @@ EXPORTS = ("perch_create", "perch_destroy", "perch_set_observation", "perch_add_
            "perch_eval_children", "perch_render", "perch_set_tuning", "perch_get_info",
            "perch_search", "perch_batch_create", "perch_batch_destroy",
            "perch_batch_set_parents", "perch_batch_eval", "perch_batch_set_tuning",
-           "perch_autotune", "perch_last_error")
+           "perch_autotune", "perch_cnn_create", "perch_cnn_destroy", "perch_cnn_param_count",
+           "perch_cnn_set_params", "perch_cnn_get_params", "perch_cnn_crops", "perch_cnn_predict",
+           "perch_cnn_train_step", "perch_cnn_gradients", "perch_last_error")
 
 SEARCH_EXHAUSTIVE, SEARCH_UCS, SEARCH_FOCAL = 0, 1, 2
 
@@ -96,15 +98,27 @@ def load(path: str = LIB_PATH):
     L.perch_get_info.argtypes = [P, C.POINTER(I32), C.POINTER(I32)]
     L.perch_search.argtypes = [P, C.POINTER(_SearchOpts), C.POINTER(_Result)]
     L.perch_autotune.argtypes = [P, P, I32, P, I32, I32, C.c_char_p, C.POINTER(_Tuning)]
+    L.perch_cnn_create.argtypes = [I32, I32, I32, P, C.POINTER(P)]
+    L.perch_cnn_destroy.argtypes = [P]
+    L.perch_cnn_destroy.restype = None
+    L.perch_cnn_param_count.argtypes = [P]
+    L.perch_cnn_set_params.argtypes = [P, P, C.c_int64]
+    L.perch_cnn_get_params.argtypes = [P, P, C.c_int64]
+    L.perch_cnn_crops.argtypes = [P, P, I32, P]
+    L.perch_cnn_predict.argtypes = [P, P, I32, P, I32, P]
+    L.perch_cnn_train_step.argtypes = [P, P, I32, P, P, I32, C.c_float, C.POINTER(C.c_float)]
+    L.perch_cnn_gradients.argtypes = [P, P, I32, P, P, I32, P, C.POINTER(C.c_float)]
     L.perch_batch_create.argtypes = [P, I32, P, C.POINTER(P)]
     L.perch_batch_destroy.argtypes = [P]
     L.perch_batch_destroy.restype = None
     L.perch_batch_set_parents.argtypes = [P, P, I32]
     L.perch_batch_eval.argtypes = [P, P, I32, P, P, P]
     L.perch_batch_set_tuning.argtypes = [P, I32, I32, I32, I32]
+    L.perch_cnn_param_count.restype = C.c_int64
     L.perch_last_error.restype = C.c_char_p
     for name in EXPORTS:
-        if name not in ("perch_destroy", "perch_batch_destroy", "perch_last_error"):
+        if name not in ("perch_destroy", "perch_batch_destroy", "perch_cnn_destroy",
+                        "perch_cnn_param_count", "perch_last_error"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -326,6 +340,117 @@ class Batch:
             self.h, _dev_ptr(items, "int32", 4 * n), n, _dev_ptr(cost, "int32", n),
             _dev_ptr(status, "int32", n),
             None if comps is None else _dev_ptr(comps, "int32", 5 * n)))
+
+
+# flat parameter order of the network (sizes depend on the number of meshes)
+CNN_TENSORS = ("cW0", "cb0", "cW1", "cb1", "cW2", "cb2", "cW3", "cb3", "emb", "hW1", "hb1",
+               "hw2", "hb2")
+
+
+def cnn_shapes(n_mesh: int):
+    shp = {}
+    cin = 2
+    for l in range(4):
+        shp[f"cW{l}"] = (32, 3, 3, cin)
+        shp[f"cb{l}"] = (32,)
+        cin = 32
+    shp.update(emb=(n_mesh, 16), hW1=(64, 82), hb1=(64,), hw2=(64,), hb2=(1,))
+    return shp
+
+
+class Cnn:
+    """The learned successor-cost network on the GPU (inference and training)."""
+
+    def __init__(self, n_mesh: int, max_crops: int = 256, max_pairs: int = 8192, stream=None):
+        import torch
+
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.n_mesh = n_mesh
+        h = C.c_void_p()
+        _check(load().perch_cnn_create(n_mesh, max_crops, max_pairs,
+                                       C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+        self.n_params = int(load().perch_cnn_param_count(self.h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().perch_cnn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def pack(self, params: dict) -> np.ndarray:
+        shp = cnn_shapes(self.n_mesh)
+        return np.concatenate([np.asarray(params[k], np.float32).reshape(-1) for k in CNN_TENSORS])
+
+    def unpack(self, flat: np.ndarray) -> dict:
+        out, o = {}, 0
+        for k in CNN_TENSORS:
+            s = cnn_shapes(self.n_mesh)[k]
+            n = int(np.prod(s))
+            out[k] = flat[o:o + n].reshape(s)
+            o += n
+        return out
+
+    def set_params(self, params):
+        flat = np.ascontiguousarray(self.pack(params) if isinstance(params, dict) else params,
+                                    np.float32)
+        _check(load().perch_cnn_set_params(self.h, flat.ctypes.data, self.n_params))
+
+    def get_params(self) -> dict:
+        flat = np.zeros(self.n_params, np.float32)
+        _check(load().perch_cnn_get_params(self.h, flat.ctypes.data, self.n_params))
+        return self.unpack(flat)
+
+    @staticmethod
+    def crops(ctx: "Context", xy):
+        """bfloat16 crops (as an int16 GPU tensor n x 64 x 64 x 2) of ctx's parent."""
+        import torch
+
+        xy = np.ascontiguousarray(xy, np.float32).reshape(-1, 2)
+        out = torch.empty((len(xy), 64, 64, 2), dtype=torch.int16, device="cuda")
+        _check(load().perch_cnn_crops(ctx.h, xy.ctypes.data, len(xy), out.data_ptr()))
+        return out
+
+    @staticmethod
+    def pairs(crop, mesh, cos_yaw, sin_yaw):
+        """int32 GPU tensor (n, 4) of (crop, mesh, cos bits, sin bits)."""
+        import torch
+
+        a = np.zeros((len(crop), 4), np.int32)
+        a[:, 0] = crop
+        a[:, 1] = mesh
+        a[:, 2] = np.asarray(cos_yaw, np.float32).view(np.int32)
+        a[:, 3] = np.asarray(sin_yaw, np.float32).view(np.int32)
+        return torch.as_tensor(a).cuda()
+
+    def predict(self, crops, pairs):
+        import torch
+
+        out = torch.empty(pairs.shape[0], dtype=torch.float32, device="cuda")
+        _check(load().perch_cnn_predict(self.h, crops.data_ptr(), crops.shape[0], pairs.data_ptr(),
+                                        pairs.shape[0], out.data_ptr()))
+        return out
+
+    def train_step(self, crops, pairs, target, lr: float, want_loss: bool = True):
+        loss = C.c_float(0.0)
+        _check(load().perch_cnn_train_step(self.h, crops.data_ptr(), crops.shape[0],
+                                           pairs.data_ptr(), _dev_ptr(target, "float32"),
+                                           pairs.shape[0], lr,
+                                           C.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def gradients(self, crops, pairs, target):
+        g = np.zeros(self.n_params, np.float32)
+        loss = C.c_float(0.0)
+        _check(load().perch_cnn_gradients(self.h, crops.data_ptr(), crops.shape[0],
+                                          pairs.data_ptr(), _dev_ptr(target, "float32"),
+                                          pairs.shape[0], g.ctypes.data, C.byref(loss)))
+        return loss.value, self.unpack(g)
 
 
 def context_from_scene(scene, depth=None, stream=None) -> Context:
