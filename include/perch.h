@@ -260,6 +260,9 @@ perch_status perch_cnn_gradients(perch_cnn* net, const uint16_t* crops_dev, int3
 #define PERCH_SEARCH_UCS 1        /* best-first on g with duplicate detection (w = 1)    */
 #define PERCH_SEARCH_FOCAL 2      /* anchor g-queue + depth-first inadmissible queue,    */
                                   /* goal accepted when g <= w * min g (Theorem 2)       */
+#define PERCH_SEARCH_LEARNED 3    /* FOCAL whose inadmissible queue only receives the    */
+                                  /* top-k children ranked by the learned network; the   */
+                                  /* rest wait, keyed at g(parent), in the anchor queue  */
 
 typedef struct {
   int32_t mode;                /* PERCH_SEARCH_*                                        */
@@ -269,6 +272,9 @@ typedef struct {
   int64_t budget_expansions;   /* 0 = none                                              */
   const int32_t* pose_subset;  /* host; NULL = every pose of the table                  */
   int32_t n_pose_subset;
+  perch_cnn* cnn;              /* LEARNED: the network (created with enough capacity   */
+                               /* for one crop per pose cell and one pair per child)   */
+  int32_t topk;                /* LEARNED: children evaluated exactly per expansion    */
 } perch_search_opts;
 
 typedef struct {
@@ -281,6 +287,8 @@ typedef struct {
   double t_total_s;            /* wall time of the call                                 */
   double t_best_s;             /* wall time until the returned cost was first reached   */
   int64_t lower_bound;         /* min g over the open list at exit (UCS/FOCAL)          */
+  int64_t n_evaluated_best;    /* successors evaluated when the returned cost was first */
+                               /* reached (a deterministic time-to-best-scene)          */
 } perch_result;
 
 /* Runs the tree search of Alg. 1 on the context's scene: root = empty state, goal =

@@ -306,6 +306,7 @@ perch_status perch_set_poses(perch_ctx* c, const float* poses, int32_t P) {
   HIP_TRY(c->poses.ensure((size_t)P * sizeof(float4)));
   HIP_TRY(hipMemcpy(c->poses.p, poses, (size_t)P * sizeof(float4), hipMemcpyHostToDevice));
   c->P = P;
+  c->h_poses.assign(poses, poses + 4 * (size_t)P);
   c->parent_j = -1;
   return PERCH_OK;
 }

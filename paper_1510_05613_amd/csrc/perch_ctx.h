@@ -101,8 +101,9 @@ struct perch_ctx {
   bool meshes_dirty = true;
   int max_nv = 0;
   DevBuf verts, tris, planes, range, frange, aabb;
-  // pose table
+  // pose table (device, and a host copy for the search driver)
   DevBuf poses;
+  std::vector<float> h_poses;
   int P = 0;
   // known objects
   std::vector<int32_t> objects;

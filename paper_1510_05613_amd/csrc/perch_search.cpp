@@ -14,10 +14,19 @@
 //     inadmissible queue preferring deeper states (h_depth = K - |s|, Sec. IV-C)
 //     restricted to FOCAL = {g <= w * min g}; a goal chosen from FOCAL costs at
 //     most w * OPT (Theorem 2).  With anytime = 1 the search continues, keeping the
-//     best goal, until the incumbent is no worse than the anchor's min g.
+//     best goal, until the incumbent is no worse than the anchor's min g;
+//   - learned: the focal scheme with a learned network ranking the children of an
+//     expanded state: only the top-k predicted children are evaluated exactly and
+//     enter the inadmissible queue; the remaining children wait as one lazy block
+//     keyed at g(parent) (a lower bound, edge costs being >= 0) in the anchor queue
+//     and are evaluated when the anchor reaches them, so completeness and the
+//     w-bound are those of the focal search.
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstring>
+#include <map>
+#include <numeric>
 #include <queue>
 #include <unordered_map>
 #include <vector>
@@ -37,6 +46,7 @@ struct Node {
   int32_t edge;    // cost of the edge from the parent
   perch_object objs[8];  // insertion order
   int64_t key[8];        // canonical: sorted (mesh << 32 | pose)
+  int32_t lazy;          // learned search: a block of unevaluated children of `parent`
 };
 
 int64_t pack(int32_t m, int32_t p) { return ((int64_t)m << 32) | (uint32_t)p; }
@@ -92,6 +102,7 @@ class Searcher {
     std::vector<int> seen;
     for (int m : c_->objects)
       if (std::find(seen.begin(), seen.end(), m) == seen.end()) seen.push_back(m), ++distinct;
+    distinct_ = distinct;
     const size_t cap = (size_t)distinct * poses_.size();
     HIP_TRY(c_->s_cands.ensure(cap * sizeof(int2)));
     HIP_TRY(c_->s_out.ensure(cap * 2 * sizeof(int32_t)));
@@ -169,6 +180,7 @@ class Searcher {
     m.objs[n.j].mesh_id = ch.mesh;
     m.objs[n.j].pose_idx = ch.pose;
     make_key(m);
+    m.lazy = 0;
     return m;
   }
 
@@ -177,7 +189,10 @@ class Searcher {
     const bool cost_improved = !have_ || g.g < best_.g;
     have_ = true;
     best_ = g;
-    if (cost_improved) t_best_ = elapsed();
+    if (cost_improved) {
+      t_best_ = elapsed();
+      n_eval_best_ = n_evaluated_;
+    }
     // edge costs along the path
     std::memset(best_edges_, 0, sizeof(best_edges_));
     if (store) {
@@ -293,8 +308,10 @@ class Searcher {
         const int id = (int)nodes.size() - 1;
         auto it = table.find(id);
         if (it != table.end()) {
-          const int old = it->second;
-          if (closed[old] || !(m.g < nodes[old].g)) {
+          // a cheaper path re-opens the state, also after its expansion: a state
+          // closed from FOCAL may carry a g above its optimum, and the anchor's
+          // min g stays a lower bound on the optimum only if it is re-opened
+          if (!(m.g < nodes[it->second].g)) {
             nodes.pop_back();
             closed.pop_back();
             continue;
@@ -306,6 +323,200 @@ class Searcher {
         if (focal) pending.push(id);
         if (m.j == K_ && focal && o_.anytime) offer_goal(m, &nodes);
       }
+    }
+    return PERCH_OK;
+  }
+
+  // ---- learned ----
+  perch_status learned() {
+    if (!o_.cnn) return fail(PERCH_E_ARG, "the learned search needs a network");
+    const int topk = o_.topk > 0 ? o_.topk : 64;
+    // pose cells: crops are taken once per distinct (x, y) of the pose set
+    std::vector<float> cells;
+    std::vector<int> cell_of(poses_.size());
+    {
+      std::map<std::pair<float, float>, int> idx;
+      for (size_t k = 0; k < poses_.size(); ++k) {
+        const float* pz = &c_->h_poses[4 * (size_t)poses_[k]];
+        auto it = idx.find({pz[0], pz[1]});
+        if (it == idx.end()) {
+          it = idx.emplace(std::make_pair(pz[0], pz[1]), (int)(cells.size() / 2)).first;
+          cells.push_back(pz[0]);
+          cells.push_back(pz[1]);
+        }
+        cell_of[k] = it->second;
+      }
+    }
+    const int n_cells = (int)(cells.size() / 2);
+    const size_t maxp = (size_t)distinct_ * poses_.size();
+    DevBuf crops, pairs, pred;
+    HIP_TRY(crops.ensure((size_t)n_cells * 64 * 64 * 2 * sizeof(uint16_t)));
+    HIP_TRY(pairs.ensure(maxp * sizeof(perch_cnn_pair)));
+    HIP_TRY(pred.ensure(maxp * sizeof(float)));
+    std::vector<perch_cnn_pair> hp(maxp);
+    std::vector<float> hpred(maxp);
+    std::vector<int> order(maxp);
+
+    // children of n: predict all, evaluate the top-k exactly (all = nothing left over)
+    auto learned_expand = [&](const Node& n, std::vector<Child>& out, bool& all) -> perch_status {
+      out.clear();
+      const std::vector<int> rest = remaining(n);
+      const int P = (int)poses_.size();
+      const int cnt = (int)rest.size() * P;
+      perch_status st = perch_set_parent(c_, n.objs, n.j);
+      if (st) return st;
+      st = perch_cnn_crops(c_, cells.data(), n_cells, crops.as<uint16_t>());
+      if (st) return st;
+      for (size_t a = 0; a < rest.size(); ++a)
+        for (int b = 0; b < P; ++b) {
+          const float* pz = &c_->h_poses[4 * (size_t)poses_[b]];
+          hp[a * P + b] = perch_cnn_pair{cell_of[b], rest[a], pz[2], pz[3]};
+        }
+      HIP_TRY(hipMemcpy(pairs.p, hp.data(), cnt * sizeof(perch_cnn_pair), hipMemcpyHostToDevice));
+      st = perch_cnn_predict(o_.cnn, crops.as<uint16_t>(), n_cells,
+                             pairs.as<perch_cnn_pair>(), cnt, pred.as<float>());
+      if (st) return st;
+      HIP_TRY(hipDeviceSynchronize());
+      HIP_TRY(hipMemcpy(hpred.data(), pred.p, cnt * sizeof(float), hipMemcpyDeviceToHost));
+      for (int i = 0; i < cnt; ++i)  // a NaN would break the ordering: rank it last
+        if (!(hpred[i] == hpred[i])) hpred[i] = INFINITY;
+      const int k = std::min(topk, cnt);
+      all = k == cnt;
+      std::iota(order.begin(), order.begin() + cnt, 0);
+      std::partial_sort(order.begin(), order.begin() + k, order.begin() + cnt,
+                        [&](int x, int y) { return hpred[x] < hpred[y] || (hpred[x] == hpred[y] && x < y); });
+      int2* hc = c_->s_hcands.as<int2>();
+      for (int i = 0; i < k; ++i) {
+        const int id = order[i];
+        hc[i] = make_int2(rest[id / P], poses_[id % P]);
+      }
+      HIP_TRY(hipMemcpyAsync(c_->s_cands.p, hc, k * sizeof(int2), hipMemcpyHostToDevice,
+                             c_->stream));
+      int32_t* dcost = c_->s_out.as<int32_t>();
+      int32_t* dstat = dcost + k;
+      st = perch_eval_children(c_, reinterpret_cast<const perch_object*>(c_->s_cands.p), k,
+                               dcost, dstat, nullptr);
+      if (st) return st;
+      int32_t* hout = c_->s_hout.as<int32_t>();
+      HIP_TRY(hipMemcpyAsync(hout, dcost, 2 * (size_t)k * sizeof(int32_t), hipMemcpyDeviceToHost,
+                             c_->stream));
+      HIP_TRY(hipStreamSynchronize(c_->stream));
+      ++n_expanded_;
+      n_evaluated_ += k;
+      for (int i = 0; i < k; ++i) {
+        const int s2 = hout[k + i];
+        if (s2 == 1)
+          out.push_back({hc[i].x, hc[i].y, hout[i]});
+        else if (s2 == 0)
+          ++n_invalid_;
+        else
+          return fail(PERCH_E_UNSUPPORTED, "successor (%d, %d) failed with status %d", hc[i].x,
+                      hc[i].y, s2);
+      }
+      return PERCH_OK;
+    };
+
+    std::vector<Node> nodes;
+    nodes.reserve(1 << 16);
+    Node root;
+    std::memset(&root, 0, sizeof(root));
+    root.parent = -1;
+    nodes.push_back(root);
+    std::unordered_map<int, int, KeyHash, KeyEq> table(1024, KeyHash{&nodes}, KeyEq{&nodes});
+    table.emplace(0, 0);
+    std::vector<char> closed(1, 0);
+    auto a_less = [&](int a, int b) {  // anchor: smaller key g, deeper, states before blocks
+      const Node &x = nodes[a], &y = nodes[b];
+      if (x.g != y.g) return x.g > y.g;
+      if (x.j != y.j) return x.j < y.j;
+      if (x.lazy != y.lazy) return x.lazy > y.lazy;
+      return cmp_key(x, y) > 0;
+    };
+    auto d_less = [&](int a, int b) {  // inadmissible: deeper first, then smaller g
+      const Node &x = nodes[a], &y = nodes[b];
+      if (x.j != y.j) return x.j < y.j;
+      if (x.g != y.g) return x.g > y.g;
+      return cmp_key(x, y) > 0;
+    };
+    std::priority_queue<int, std::vector<int>, decltype(a_less)> open(a_less), pending(a_less);
+    std::priority_queue<int, std::vector<int>, decltype(d_less)> focal_q(d_less);
+    auto live = [&](int id) {
+      if (closed[id]) return false;
+      if (nodes[id].lazy) return true;
+      auto it = table.find(id);
+      return it != table.end() && it->second == id;
+    };
+    auto push_child = [&](const Node& parent, int pid, const Child& ch) {
+      Node m = child_of(parent, pid, ch);
+      m.lazy = 0;
+      if (m.j == K_) offer_goal(m, &nodes);
+      if (have_ && m.g >= best_.g) return;  // cannot improve the incumbent
+      nodes.push_back(m);
+      closed.push_back(0);
+      const int id = (int)nodes.size() - 1;
+      auto it = table.find(id);
+      if (it != table.end()) {
+        if (!(m.g < nodes[it->second].g)) {  // re-open on a cheaper path, as above
+          nodes.pop_back();
+          closed.pop_back();
+          return;
+        }
+        table.erase(it);
+      }
+      table.emplace(id, id);
+      open.push(id);
+      pending.push(id);
+    };
+    open.push(0);
+    pending.push(0);
+    std::vector<Child> kids;
+    const double w = std::max(1.0f, o_.w);
+    for (;;) {
+      while (!open.empty() && !live(open.top())) open.pop();
+      if (open.empty()) {  // every state was expanded: the incumbent is optimal
+        if (have_) lower_bound_ = best_.g;
+        break;
+      }
+      const int64_t gmin = nodes[open.top()].g;
+      lower_bound_ = gmin;
+      if (have_ && best_.g <= gmin) break;  // incumbent proven optimal
+      if (have_ && !o_.anytime && (double)best_.g <= w * (double)gmin) break;  // w-bound met
+      if (over_budget()) return PERCH_E_BUDGET;
+      while (!pending.empty() && (double)nodes[pending.top()].g <= w * (double)gmin) {
+        if (live(pending.top())) focal_q.push(pending.top());
+        pending.pop();
+      }
+      while (!focal_q.empty() && !live(focal_q.top())) focal_q.pop();
+      int pick = -1;
+      if (!focal_q.empty() && (expansions_ % 2 == 0 || !o_.anytime)) {
+        pick = focal_q.top();
+        focal_q.pop();
+      } else {
+        pick = open.top();
+        open.pop();
+      }
+      ++expansions_;
+      closed[pick] = 1;
+      const Node cur = nodes[pick];
+      if (cur.lazy) {  // the rest of a parent's children: evaluate them all
+        const Node par = nodes[cur.parent];
+        perch_status st = expand(par, kids);
+        if (st) return st;
+        for (const Child& ch : kids) push_child(par, cur.parent, ch);
+        continue;
+      }
+      if (cur.j == K_) continue;  // goals were offered when generated
+      bool all = false;
+      perch_status st = learned_expand(cur, kids, all);
+      if (st) return st;
+      for (const Child& ch : kids) push_child(cur, pick, ch);
+      if (all) continue;
+      Node lz = cur;
+      lz.lazy = 1;
+      lz.parent = pick;
+      nodes.push_back(lz);
+      closed.push_back(0);
+      open.push((int)nodes.size() - 1);
     }
     return PERCH_OK;
   }
@@ -328,6 +539,7 @@ class Searcher {
     r->n_invalid = n_invalid_;
     r->t_total_s = elapsed();
     r->t_best_s = have_ ? t_best_ : -1.0;
+    r->n_evaluated_best = have_ ? n_eval_best_ : -1;
     r->lower_bound = lower_bound_;
   }
 
@@ -335,6 +547,7 @@ class Searcher {
   perch_ctx* c_;
   perch_search_opts o_;
   int K_ = 0;
+  int distinct_ = 0;
   std::vector<int> poses_;
   Clock::time_point t0_;
   int64_t n_expanded_ = 0, n_evaluated_ = 0, n_invalid_ = 0, expansions_ = 0;
@@ -344,6 +557,7 @@ class Searcher {
   int32_t best_edges_[8] = {0};
   std::vector<int32_t> path_edges_;
   double t_best_ = -1.0;
+  int64_t n_eval_best_ = -1;
 };
 
 }  // namespace
@@ -351,15 +565,17 @@ class Searcher {
 extern "C" perch_status perch_search(perch_ctx* c, const perch_search_opts* opts,
                                      perch_result* out) {
   if (!c || !opts || !out) return fail(PERCH_E_ARG, "null argument");
-  if (opts->mode < PERCH_SEARCH_EXHAUSTIVE || opts->mode > PERCH_SEARCH_FOCAL)
+  if (opts->mode < PERCH_SEARCH_EXHAUSTIVE || opts->mode > PERCH_SEARCH_LEARNED)
     return fail(PERCH_E_ARG, "unknown search mode %d", opts->mode);
-  if (opts->mode == PERCH_SEARCH_FOCAL && !(opts->w >= 1.0f))
-    return fail(PERCH_E_ARG, "focal search needs w >= 1");
+  if (opts->mode >= PERCH_SEARCH_FOCAL && !(opts->w >= 1.0f))
+    return fail(PERCH_E_ARG, "focal and learned searches need w >= 1");
   Searcher s(c, opts);
   perch_status st = s.init();
   if (st) return st;
   if (opts->mode == PERCH_SEARCH_EXHAUSTIVE)
     st = s.exhaustive();
+  else if (opts->mode == PERCH_SEARCH_LEARNED)
+    st = s.learned();
   else
     st = s.best_first(opts->mode == PERCH_SEARCH_FOCAL);
   s.fill(out);

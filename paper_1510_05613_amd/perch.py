@@ -32,7 +32,7 @@ EXPORTS = ("perch_create", "perch_destroy", "perch_set_observation", "perch_add_
            "perch_cnn_set_params", "perch_cnn_get_params", "perch_cnn_crops", "perch_cnn_predict",
            "perch_cnn_train_step", "perch_cnn_gradients", "perch_last_error")
 
-SEARCH_EXHAUSTIVE, SEARCH_UCS, SEARCH_FOCAL = 0, 1, 2
+SEARCH_EXHAUSTIVE, SEARCH_UCS, SEARCH_FOCAL, SEARCH_LEARNED = 0, 1, 2, 3
 
 
 class PerchError(RuntimeError):
@@ -61,14 +61,16 @@ class _Tuning(C.Structure):
 class _SearchOpts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("w", C.c_float), ("anytime", C.c_int32),
                 ("budget_s", C.c_double), ("budget_expansions", C.c_int64),
-                ("pose_subset", C.c_void_p), ("n_pose_subset", C.c_int32)]
+                ("pose_subset", C.c_void_p), ("n_pose_subset", C.c_int32),
+                ("cnn", C.c_void_p), ("topk", C.c_int32)]
 
 
 class _Result(C.Structure):
     _fields_ = [("objs", PerchObject * 8), ("K", C.c_int32), ("found", C.c_int32),
                 ("cost", C.c_int64), ("edge_cost", C.c_int32 * 8), ("n_expanded", C.c_int64),
                 ("n_evaluated", C.c_int64), ("n_invalid", C.c_int64), ("t_total_s", C.c_double),
-                ("t_best_s", C.c_double), ("lower_bound", C.c_int64)]
+                ("t_best_s", C.c_double), ("lower_bound", C.c_int64),
+                ("n_evaluated_best", C.c_int64)]
 
 
 _lib = None
@@ -260,12 +262,15 @@ class Context:
         return status, cost, comps
 
     def search(self, mode: int = SEARCH_UCS, w: float = 1.0, anytime: bool = False,
-               budget_s: float = 0.0, budget_expansions: int = 0, pose_subset=None) -> dict:
+               budget_s: float = 0.0, budget_expansions: int = 0, pose_subset=None,
+               cnn: "Optional[Cnn]" = None, topk: int = 64) -> dict:
         """Tree search of Alg. 1 on this scene (synchronous).  Returns the goal in
         insertion order plus its canonical (sorted) form, cost and statistics."""
         o = _SearchOpts()
         o.mode, o.w, o.anytime = int(mode), float(w), int(bool(anytime))
         o.budget_s, o.budget_expansions = float(budget_s), int(budget_expansions)
+        o.cnn = None if cnn is None else cnn.h.value
+        o.topk = int(topk)
         sub = None
         if pose_subset is not None:
             sub = np.ascontiguousarray(pose_subset, np.int32)
@@ -280,7 +285,8 @@ class Context:
                     edge_cost=[int(r.edge_cost[k]) for k in range(r.K)] if r.found else [],
                     n_expanded=int(r.n_expanded), n_evaluated=int(r.n_evaluated),
                     n_invalid=int(r.n_invalid), t_total_s=float(r.t_total_s),
-                    t_best_s=float(r.t_best_s), lower_bound=int(r.lower_bound))
+                    t_best_s=float(r.t_best_s), lower_bound=int(r.lower_bound),
+                    n_evaluated_best=int(r.n_evaluated_best))
 
     def render(self, objs, composite: bool = True):
         """Depth images (+inf = empty) of objects [(mesh, pose), ...]."""
