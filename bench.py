@@ -27,6 +27,35 @@ import numpy as np
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "successor evals/s @640x480 (render+cost); time-to-best-scene learned vs plain"
+ROOT = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SRC = os.path.join(ROOT, "paper_1510_05613_amd", "csrc", "perch_kernels.hip")
+COUNTERS = os.path.join(ROOT, "profiles", "k_eval_640x480_counters.md")
+CHECKPOINT = os.path.join(ROOT, "paper_1510_05613_amd", "weights", "c4_cnn.npz")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per k_eval launch from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE scaled by a plain copy's reading), or None when the summary is missing
+    or was taken on a different kernel source."""
+    try:
+        with open(COUNTERS) as f:
+            kv = dict(line.split(":", 1) for line in f if line.startswith(("source_sha256:",
+                                                                            "traffic_bytes_per_launch:")))
+    except OSError:
+        return None
+    if kv.get("source_sha256", "").strip() != kernel_source_hash():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def parse_args(argv=None):
@@ -43,6 +72,8 @@ def parse_args(argv=None):
                     help="dJ_r query: 0 pixel window, 1 voxel hash (-1 = default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--learned-scenes", type=int, default=20,
+                    help="held-out config-4 scenes for the learned-vs-plain search leg (0 = off)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     return ap.parse_args(argv)
@@ -197,6 +228,22 @@ def cpu_baseline(args, work_gpu):
                        f"{t_used:.1f} s on {cores} threads")}
 
 
+def learned_leg(n_scenes: int) -> dict:
+    """Time-to-best-scene of the learned search (committed checkpoint) against the
+    plain searches and a random-init control, on held-out 160x120 scenes (config 4)."""
+    from paper_1510_05613_amd import learn
+
+    if not os.path.exists(CHECKPOINT):
+        return {"skipped": "no trained checkpoint"}
+    net = learn.load(CHECKPOINT, max_crops=144, max_pairs=3 * 1152)
+    ctrl = learn.load(CHECKPOINT, max_crops=144, max_pairs=3 * 1152)
+    ctrl.set_params(learn.init_params(ctrl.n_mesh, 1))
+    g = learn.gain(net, ctrl, range(learn.HELD_OUT_FIRST, learn.HELD_OUT_FIRST + n_scenes))
+    g["workload"] = (f"config 4 (160x120, K=2, 1,152 poses/object), held-out scenes "
+                     f"{learn.HELD_OUT_FIRST}..{learn.HELD_OUT_FIRST + n_scenes - 1}; medians")
+    return g
+
+
 def main(argv=None):
     args = parse_args(argv)
     if args.gpus != 1:
@@ -278,8 +325,11 @@ def main(argv=None):
         torch.cuda.synchronize()
 
     evals = n_step * args.steps
-    kernel_s = kernel_ms / 1e3
-    achieved = bytes_per_step * args.steps / kernel_s / 1e9
+    launches = len(dev)
+    launch_s = kernel_ms / 1e3 / (args.steps * launches)  # mean k_eval launch duration
+    bytes_per_launch = bytes_per_step / launches           # mean algorithmic bytes per launch
+    achieved = bytes_per_launch / launch_s / 1e9
+    traffic = measured_traffic()
     out = {
         "metric": METRIC, "value": round(evals / wall, 1), "unit": "evals/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 3),
@@ -292,10 +342,14 @@ def main(argv=None):
                    "successors_per_step": n_step, "valid_per_step": valid,
                    "threads_per_successor": args.threads or 256},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_eval", "kernel_ms_per_step": round(kernel_ms / args.steps, 3),
-                     "algorithmic_bytes_per_step": bytes_per_step},
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None if traffic is None else round(traffic),
+                     "kernel": "k_eval", "launches_per_step": launches,
+                     "launch_ms": round(launch_s * 1e3, 4),
+                     "algorithmic_bytes_per_launch": round(bytes_per_launch)},
     }
+    if args.learned_scenes > 0 and args.config == 2:
+        out["learned"] = learned_leg(args.learned_scenes)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, work)
     print(json.dumps(out), flush=True)
