@@ -178,18 +178,26 @@ __device__ __forceinline__ void raster_tri(int x0, int y0, int x1, int y1, int x
     const int b0 = (d0y < 0 || (d0y == 0 && d0x > 0)) ? 0 : -1;
     const int b1 = (d1y < 0 || (d1y == 0 && d1x > 0)) ? 0 : -1;
     const int b2 = (d2y < 0 || (d2y == 0 && d2x > 0)) ? 0 : -1;
-    for (int j = ja; j <= jb; ++j) {
-      const int py = 256 * j - y0;
-      const int px0 = 256 * ia - x0;
-      int e0 = d0x * py - d0y * px0 + b0;
-      int e1 = d1x * (py - by) - d1y * (px0 - bx) + b1;
-      int e2 = d2x * (py - cy) - d2y * (px0 - cx) + b2;
-      for (int i = ia; i <= ib; ++i) {
-        if ((e0 | e1 | e2) >= 0) emit(i, j);
-        e0 -= 256 * d0y;
-        e1 -= 256 * d1y;
-        e2 -= 256 * d2y;
-      }
+    // one flat walk over the box, row by row: lanes of a wave rasterising boxes of
+    // different shapes then iterate max(w h) times, not max(h) max(w)
+    const int py = 256 * ja - y0, px0 = 256 * ia - x0;
+    int r0 = d0x * py - d0y * px0 + b0;
+    int r1 = d1x * (py - by) - d1y * (px0 - bx) + b1;
+    int r2 = d2x * (py - cy) - d2y * (px0 - cx) + b2;
+    int e0 = r0, e1 = r1, e2 = r2;
+    const int n = (ib - ia + 1) * (jb - ja + 1);
+    int i = ia, j = ja;
+    for (int k = 0; k < n; ++k) {
+      if ((e0 | e1 | e2) >= 0) emit(i, j);
+      const bool wrap = i == ib;
+      r0 += wrap ? 256 * d0x : 0;
+      r1 += wrap ? 256 * d1x : 0;
+      r2 += wrap ? 256 * d2x : 0;
+      e0 = wrap ? r0 : e0 - 256 * d0y;
+      e1 = wrap ? r1 : e1 - 256 * d1y;
+      e2 = wrap ? r2 : e2 - 256 * d2y;
+      j += wrap ? 1 : 0;
+      i = wrap ? ia : i + 1;
     }
   } else {
     long long bx = (long long)x1 - x0, by = (long long)y1 - y0;
@@ -650,19 +658,18 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
     {
       const PoseMap pm = make_pose_map(cam, pz);
       auto raster_one = [&](unsigned t) {
+        // queued triangles are front-facing with a pixel centre in their box, so
+        // the depth plane is set up for every lane at once, outside the pixel walk
         const int4 tr = M.tris[rg.z + t];
+        const float4 v0 = M.verts[rg.x + tr.x], v1 = M.verts[rg.x + tr.y];
+        const float4 v2 = M.verts[rg.x + tr.z];
         const int2 a = suv[tr.x], b = suv[tr.y], c = suv[tr.z];
-        bool have = false;
-        Plane64 pl;
+        float X0, Y0, Z0, X1, Y1, Z1, X2, Y2, Z2;
+        map_vertex(pm, v0, X0, Y0, Z0);
+        map_vertex(pm, v1, X1, Y1, Z1);
+        map_vertex(pm, v2, X2, Y2, Z2);
+        const Plane64 pl = make_plane(cam, X0, Y0, Z0, X1, Y1, Z1, X2, Y2, Z2);
         raster_tri(a.x, a.y, b.x, b.y, c.x, c.y, ca, cb, t0, t1, [&](int i, int j) {
-          if (!have) {
-            float X0, Y0, Z0, X1, Y1, Z1, X2, Y2, Z2;
-            map_vertex(pm, M.verts[rg.x + tr.x], X0, Y0, Z0);
-            map_vertex(pm, M.verts[rg.x + tr.y], X1, Y1, Z1);
-            map_vertex(pm, M.verts[rg.x + tr.z], X2, Y2, Z2);
-            pl = make_plane(cam, X0, Y0, Z0, X1, Y1, Z1, X2, Y2, Z2);
-            have = true;
-          }
           atomicMin(&tile[(j - t0) * tw + (i - ca)], __float_as_uint(plane_depth(pl, i, j)));
         });
       };

@@ -361,6 +361,44 @@ def footprint_radius(mesh: Mesh) -> float:
     return float(np.sqrt((mesh.verts[:, :2].astype(np.float64) ** 2).sum(1)).max())
 
 
+def footprint_polygon(mesh: Mesh) -> np.ndarray:
+    """Counter-clockwise convex hull of the mesh's vertices projected on the table
+    (Andrew's monotone chain)."""
+    pts = sorted(set(map(tuple, np.round(mesh.verts[:, :2].astype(np.float64), 9))))
+    if len(pts) < 3:
+        return np.array(pts)
+
+    def half(seq):
+        h = []
+        for q in seq:
+            while len(h) >= 2 and ((h[-1][0] - h[-2][0]) * (q[1] - h[-2][1]) -
+                                   (h[-1][1] - h[-2][1]) * (q[0] - h[-2][0])) <= 0:
+                h.pop()
+            h.append(q)
+        return h
+
+    lo, hi = half(pts), half(pts[::-1])
+    return np.array(lo[:-1] + hi[:-1])
+
+
+def _placed_polygon(poly: np.ndarray, pose: np.ndarray) -> np.ndarray:
+    c, s = float(pose[2]), float(pose[3])
+    R = np.array([[c, -s], [s, c]])
+    return poly @ R.T + np.asarray(pose[:2], np.float64)
+
+
+def _polygons_apart(a: np.ndarray, b: np.ndarray, gap: float) -> bool:
+    """Separating-axis test: some edge normal of a or b separates them by > gap."""
+    for P in (a, b):
+        e = np.roll(P, -1, axis=0) - P
+        n = np.stack([e[:, 1], -e[:, 0]], 1)
+        n /= np.linalg.norm(n, axis=1, keepdims=True)
+        pa, pb = a @ n.T, b @ n.T
+        if np.any(pa.min(0) - pb.max(0) > gap) or np.any(pb.min(0) - pa.max(0) > gap):
+            return True
+    return False
+
+
 # ----------------------------------------------------------------------------
 # scenes
 # ----------------------------------------------------------------------------
@@ -466,12 +504,53 @@ def make_scene(config: int, index: int, render: RenderFn, library: Optional[Libr
                     break
             if not ok:
                 continue
-        for k in range(len(ps), K):
-            for _t in range(1000):
-                p = random_pose()
-                if separated(ps, k, p):
+        if occl is not None and occl[0] == "heavy":
+            # one or two front objects, then each further object behind a placed one
+            # (larger y is farther from the camera) at a lateral offset, kept only
+            # when the part of it the placed objects hide is inside the range
+            n_front = int(rng.integers(1, 3))
+            polys = [footprint_polygon(lib.meshes[m]) for m in mesh_ids]
+
+            def apart(k, p):  # footprints (convex hulls) at least 1 mm apart
+                return all(_polygons_apart(_placed_polygon(polys[k], poses[p]),
+                                           _placed_polygon(polys[i], poses[q]), 1e-3)
+                           for i, q in enumerate(ps))
+
+            for k in range(K):
+                for _t in range(300):
+                    if k < n_front:
+                        p = random_pose()
+                    else:
+                        i = int(rng.integers(k))
+                        ia, ja, _ = grid.unindex(ps[i])
+                        reach = (radii[i] + radii[k]) / grid.step
+                        half = max(1, int(reach / 2))
+                        ib = ia + int(rng.integers(-half, half + 1))
+                        jb = ja + int(rng.integers(1, int(np.ceil(reach)) + 2))
+                        if not (0 <= ib < grid.nx and 0 <= jb < grid.ny):
+                            continue
+                        p = grid.index(ib, jb, int(rng.integers(grid.n_yaw)))
+                    if not apart(k, p):
+                        continue
+                    if k >= n_front:
+                        # the new object, and any earlier one it now hides, in range
+                        D = render(sensor, lib, mesh_ids[:k + 1], ps + [p], poses)
+                        fr = [_hidden_fraction(D, a) for a in range(k + 1)]
+                        if not (occl[1] <= fr[k] <= occl[2]):
+                            continue
+                        if any(0.0 < f < occl[1] or f > occl[2] for f in fr):
+                            continue
                     ps.append(p)
                     break
+                if len(ps) < k + 1:
+                    break
+        else:
+            for k in range(len(ps), K):
+                for _t in range(1000):
+                    p = random_pose()
+                    if separated(ps, k, p):
+                        ps.append(p)
+                        break
         if len(ps) < K:
             continue
         D = render(sensor, lib, mesh_ids, ps, poses)

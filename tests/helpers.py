@@ -76,6 +76,16 @@ def c2_scene(i):
     return scenes.make_scene(2, i, render_fn, c2_library())
 
 
+@functools.lru_cache(maxsize=None)
+def c3_library():
+    return scenes.make_library("c3")
+
+
+@functools.lru_cache(maxsize=None)
+def c5_scene(i):
+    return scenes.make_scene(5, i, render_fn, c3_library())
+
+
 # ----------------------------------------------------------------------------
 # independent evaluation of Eq.(1)-(4) on the oracle's depth images (KD-tree
 # nearest neighbours instead of pixel windows; numpy half-space tests)
