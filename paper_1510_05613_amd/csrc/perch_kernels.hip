@@ -152,6 +152,34 @@ __device__ __forceinline__ void map_vertex(const PoseMap& m, const float4 v, flo
 // triangle coverage: integer edge functions, top-left rule, front faces only
 // ---------------------------------------------------------------------------
 
+// Narrows the covered columns [lo, hi] of a row (offsets from the box start, box
+// width w) by one edge whose value at offset k is e - s k: for s > 0 the edge
+// holds for k <= floor(e / s), for s < 0 for k >= -floor(e / |s|), for s = 0
+// everywhere or nowhere.  floor(e / |s|) is estimated in float (|e| < 2^29,
+// 256 <= |s| < 2^22, so the estimate is off by at most one) and, when it lands
+// within the box, corrected with exact integer products; estimates beyond +-w
+// decide the same bound as the exact value.
+__device__ __forceinline__ void edge_bound(int e, int s, float rcp_abs_s, int w, int& lo,
+                                           int& hi) {
+  if (s == 0) {
+    if (e < 0) hi = -1;
+    return;
+  }
+  const int a = abs(s);
+  const float lim = (float)(w + 1);
+  int q = (int)fminf(fmaxf(floorf((float)e * rcp_abs_s), -lim), lim);
+  if (q >= -w && q <= w) {
+    if ((q + 1) * a <= e)
+      ++q;
+    else if (q * a > e)
+      --q;
+  }
+  if (s > 0)
+    hi = min(hi, q);
+  else
+    lo = max(lo, -q);
+}
+
 // Calls emit(i, j) for every pixel centre (256 i, 256 j) covered by the triangle
 // with snapped vertices (x_k, y_k), restricted to columns [c0, c1] and rows
 // [r0, r1].  Outward-CCW faces seen from the front have negative signed area in
@@ -178,26 +206,27 @@ __device__ __forceinline__ void raster_tri(int x0, int y0, int x1, int y1, int x
     const int b0 = (d0y < 0 || (d0y == 0 && d0x > 0)) ? 0 : -1;
     const int b1 = (d1y < 0 || (d1y == 0 && d1x > 0)) ? 0 : -1;
     const int b2 = (d2y < 0 || (d2y == 0 && d2x > 0)) ? 0 : -1;
-    // one flat walk over the box, row by row: lanes of a wave rasterising boxes of
-    // different shapes then iterate max(w h) times, not max(h) max(w)
+    // Per row the covered centres form one interval; each edge bounds it from one
+    // side (edge_bound), so only covered pixels are visited: thin triangles, whose
+    // boxes are mostly empty, cost one bound per row instead of a walk of the box.
     const int py = 256 * ja - y0, px0 = 256 * ia - x0;
-    int r0 = d0x * py - d0y * px0 + b0;
-    int r1 = d1x * (py - by) - d1y * (px0 - bx) + b1;
-    int r2 = d2x * (py - cy) - d2y * (px0 - cx) + b2;
-    int e0 = r0, e1 = r1, e2 = r2;
-    const int n = (ib - ia + 1) * (jb - ja + 1);
-    int i = ia, j = ja;
-    for (int k = 0; k < n; ++k) {
-      if ((e0 | e1 | e2) >= 0) emit(i, j);
-      const bool wrap = i == ib;
-      r0 += wrap ? 256 * d0x : 0;
-      r1 += wrap ? 256 * d1x : 0;
-      r2 += wrap ? 256 * d2x : 0;
-      e0 = wrap ? r0 : e0 - 256 * d0y;
-      e1 = wrap ? r1 : e1 - 256 * d1y;
-      e2 = wrap ? r2 : e2 - 256 * d2y;
-      j += wrap ? 1 : 0;
-      i = wrap ? ia : i + 1;
+    int e0 = d0x * py - d0y * px0 + b0;  // edge values at (ia, j)
+    int e1 = d1x * (py - by) - d1y * (px0 - bx) + b1;
+    int e2 = d2x * (py - cy) - d2y * (px0 - cx) + b2;
+    const int s0 = 256 * d0y, s1 = 256 * d1y, s2 = 256 * d2y;  // decrease per column
+    const float q0 = __builtin_amdgcn_rcpf((float)abs(s0));
+    const float q1 = __builtin_amdgcn_rcpf((float)abs(s1));
+    const float q2 = __builtin_amdgcn_rcpf((float)abs(s2));
+    const int w = ib - ia + 1;
+    for (int j = ja; j <= jb; ++j) {
+      int lo = 0, hi = w - 1;
+      edge_bound(e0, s0, q0, w, lo, hi);
+      edge_bound(e1, s1, q1, w, lo, hi);
+      edge_bound(e2, s2, q2, w, lo, hi);
+      for (int i = lo; i <= hi; ++i) emit(ia + i, j);
+      e0 += 256 * d0x;
+      e1 += 256 * d1x;
+      e2 += 256 * d2x;
     }
   } else {
     long long bx = (long long)x1 - x0, by = (long long)y1 - y0;
