@@ -24,6 +24,8 @@ namespace perch {
 // small helpers
 // ---------------------------------------------------------------------------
 
+constexpr int kLdsPlanes = 64;   // V(O) planes staged in LDS per successor (more: read from HBM)
+
 __device__ __forceinline__ int floor256(int x) { return x >> 8; }
 __device__ __forceinline__ int ceil256(int x) { return -((-x) >> 8); }
 
@@ -356,6 +358,20 @@ __device__ __forceinline__ float3 apply_obj_map(const ObjMap& m, float3 p) {
                      fmaf(m.a[6], p.x, fmaf(m.a[7], p.y, fmaf(m.a[8], p.z, m.b[2]))));
 }
 
+// p in V(O) as in_volume, with the box corners and the planes already at hand
+// (the planes staged in LDS by the successor kernel).
+__device__ __forceinline__ bool in_volume_at(const float4 lo, const float4 hi,
+                                             const float4* planes, int n_planes, float3 o) {
+  if (o.x < lo.x - 1e-5f || o.y < lo.y - 1e-5f || o.z < lo.z - 1e-5f || o.x > hi.x + 1e-5f ||
+      o.y > hi.y + 1e-5f || o.z > hi.z + 1e-5f)
+    return false;
+  for (int f = 0; f < n_planes; ++f) {
+    const float4 pl = planes[f];
+    if (pl.x * o.x + pl.y * o.y + pl.z * o.z - pl.w > 0.0f) return false;
+  }
+  return true;
+}
+
 // p in V(O): inside the mesh's box of vertices (with a 1e-5 m margin) and on the
 // inner side of every plane.
 __device__ __forceinline__ bool in_volume(const Meshes& M, int mesh, float3 o) {
@@ -381,9 +397,13 @@ __device__ __forceinline__ void window_radius(const Cam& c, const EvalParams& ep
     ru = rv = ep.halo;
     return;
   }
-  const float a = p.x / p.z, b = p.y / p.z;
-  ru = min(ep.halo, (int)(c.fx * ep.dwin * sqrtf(1.0f + a * a) / den) + 1);
-  rv = min(ep.halo, (int)(c.fy * ep.dwin * sqrtf(1.0f + b * b) / den) + 1);
+  // hardware reciprocal and square root: the largest integer offset needed is
+  // floor(x) for the exact bound x, and floor(x~) + 1 >= floor(x) whenever the
+  // estimate x~ > x - 1, which a relative error of a few ulps guarantees
+  const float iz = __builtin_amdgcn_rcpf(p.z), iden = __builtin_amdgcn_rcpf(den);
+  const float a = p.x * iz, b = p.y * iz;
+  ru = min(ep.halo, (int)(c.fx * ep.dwin * __builtin_amdgcn_sqrtf(1.0f + a * a) * iden) + 1);
+  rv = min(ep.halo, (int)(c.fy * ep.dwin * __builtin_amdgcn_sqrtf(1.0f + b * b) * iden) + 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -581,7 +601,7 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
                                                const int s, int* __restrict__ out_cost,
                                                int* __restrict__ out_status,
                                                int* __restrict__ out_comps, unsigned char* smem,
-                                               int* s_bb, int* s_acc) {
+                                               int* s_bb, int* s_acc, float4* s_pl) {
   const Cam& cam = S.cam;
   const Meshes& M = S.M;
   const float4* __restrict__ poses = S.poses;
@@ -610,6 +630,13 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
   unsigned* ring = tile + ep.tile_px + (tid >> 6) * 128;  // this wave's triangle queue
   if (tid < 4) s_bb[tid] = tid < 2 ? INT_MAX : INT_MIN;
   if (tid < 8) s_acc[tid] = 0;
+  // V(O): box corners in registers, planes in LDS when they fit
+  const int2 fr = M.frange[mesh];
+  const float4 vlo = M.aabb[2 * mesh], vhi = M.aabb[2 * mesh + 1];
+  const bool pl_lds = fr.y <= kLdsPlanes;
+  if (pl_lds)
+    for (int f = tid; f < fr.y; f += NT) s_pl[f] = M.planes[fr.x + f];
+  const float4* vplanes = pl_lds ? s_pl : M.planes + fr.x;
   __syncthreads();
 
   // ---- vertex stage into LDS, footprint bounding box ----
@@ -793,33 +820,60 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
         }
         n_dJr += ballot_count(state == 2);
         unsigned long long und = __ballot(state == 3);
-        while (und) {  // wave-uniform: one undecided point at a time, 64 pixels per step
-          const int src = __ffsll((long long)und) - 1;
+        // wave-uniform: two undecided points at a time, each lane testing one pixel
+        // of either window per step, so two observed-depth loads are in flight
+        while (und) {
+          const int sa = __ffsll((long long)und) - 1;
           und &= und - 1;
-          const int si = __shfl(qi, src, 64), sj = __shfl(qj, src, 64);
-          const float3 sq = make_float3(__shfl(q.x, src, 64), __shfl(q.y, src, 64),
-                                        __shfl(q.z, src, 64));
-          int ru, rv;
-          window_radius(cam, ep, sq, ru, rv);
-          const int wu = 2 * ru + 1, nw = wu * (2 * rv + 1);
-          bool hit = false;
-          for (int w0 = 0; w0 < nw && !hit; w0 += 64) {
+          const bool two = und != 0ull;
+          const int sb = two ? __ffsll((long long)und) - 1 : sa;
+          if (two) und &= und - 1;
+          const int ai = __shfl(qi, sa, 64), aj = __shfl(qj, sa, 64);
+          const int bi = __shfl(qi, sb, 64), bj = __shfl(qj, sb, 64);
+          const float3 aq = make_float3(__shfl(q.x, sa, 64), __shfl(q.y, sa, 64),
+                                        __shfl(q.z, sa, 64));
+          const float3 bq = make_float3(__shfl(q.x, sb, 64), __shfl(q.y, sb, 64),
+                                        __shfl(q.z, sb, 64));
+          int aru, arv, bru, brv;
+          window_radius(cam, ep, aq, aru, arv);
+          window_radius(cam, ep, bq, bru, brv);
+          const int awu = 2 * aru + 1, anw = awu * (2 * arv + 1);
+          const int bwu = 2 * bru + 1, bnw = two ? bwu * (2 * brv + 1) : 0;
+          // w / wu for w < 2^21: (w + 1/2) / wu is at least 1 / (2 wu) from an integer
+          const float ainv = __builtin_amdgcn_rcpf((float)awu);
+          const float binv = __builtin_amdgcn_rcpf((float)bwu);
+          bool ahit = false, bhit = !two;
+          for (int w0 = 0; w0 < max(anw, bnw) && !(ahit && bhit); w0 += 64) {
             const int w = w0 + lane;
-            bool h = false;
-            if (w < nw) {
-              const int ii = si - ru + w % wu, jj = sj - rv + w / wu;
-              if (ii >= 0 && ii < W && jj >= 0 && jj < H) {
-                const float zo = obs[jj * W + ii];
-                if (zo > 0.0f) {
-                  const float3 p = backproject(cam, ii, jj, zo);
-                  const float dx = p.x - sq.x, dy = p.y - sq.y, dz = p.z - sq.z;
-                  h = dx * dx + dy * dy + dz * dz <= delta2;
-                }
-              }
+            float za = 0.0f, zb = 0.0f;
+            int aii = 0, ajj = 0, bii = 0, bjj = 0;
+            if (!ahit && w < anw) {
+              const int r = (int)(((float)w + 0.5f) * ainv);
+              aii = ai - aru + (w - r * awu);
+              ajj = aj - arv + r;
+              if (aii >= 0 && aii < W && ajj >= 0 && ajj < H) za = obs[ajj * W + aii];
             }
-            hit = __ballot(h) != 0;
+            if (!bhit && w < bnw) {
+              const int r = (int)(((float)w + 0.5f) * binv);
+              bii = bi - bru + (w - r * bwu);
+              bjj = bj - brv + r;
+              if (bii >= 0 && bii < W && bjj >= 0 && bjj < H) zb = obs[bjj * W + bii];
+            }
+            bool ha = false, hb = false;
+            if (za > 0.0f) {
+              const float3 p = backproject(cam, aii, ajj, za);
+              const float dx = p.x - aq.x, dy = p.y - aq.y, dz = p.z - aq.z;
+              ha = dx * dx + dy * dy + dz * dz <= delta2;
+            }
+            if (zb > 0.0f) {
+              const float3 p = backproject(cam, bii, bjj, zb);
+              const float dx = p.x - bq.x, dy = p.y - bq.y, dz = p.z - bq.z;
+              hb = dx * dx + dy * dy + dz * dz <= delta2;
+            }
+            ahit = ahit || __ballot(ha) != 0ull;
+            bhit = bhit || __ballot(hb) != 0ull;
           }
-          n_dJr += hit ? 0 : 1;
+          n_dJr += (ahit ? 0 : 1) + (bhit ? 0 : 1);
         }
       }
     }
@@ -839,7 +893,7 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
           const float z = obs[pix];
           if (z > 0.0f) {
             const float3 p = backproject(cam, ii, jj, z);
-            const bool inV = in_volume(M, mesh, apply_obj_map(om, p));
+            const bool inV = in_volume_at(vlo, vhi, vplanes, fr.y, apply_obj_map(om, p));
             const bool inU = par.goal && ((par.ubits[pix >> 5] >> (pix & 31)) & 1u);
             bool expl = false;
             if (inV || inU) {
@@ -908,9 +962,11 @@ __global__ void __launch_bounds__(NT)
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_bb[4];
   __shared__ int s_acc[8];  // S, |dR|, dJ_r, dJ_o, removed-from-U, invalid, near-plane
+  __shared__ float4 s_pl[kLdsPlanes];
   const int s = blockIdx.x;
   if (s >= n) return;
-  eval_successor<NT>(S, par, cands[s], s, out_cost, out_status, out_comps, smem, s_bb, s_acc);
+  eval_successor<NT>(S, par, cands[s], s, out_cost, out_status, out_comps, smem, s_bb, s_acc,
+                     s_pl);
 }
 
 // Persistent workgroups over a work queue of (parent slot, mesh, pose) items that
@@ -925,6 +981,7 @@ __global__ void __launch_bounds__(NT)
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_bb[4];
   __shared__ int s_acc[8];
+  __shared__ float4 s_pl[kLdsPlanes];
   __shared__ int s_item;
   for (;;) {
     __syncthreads();  // the previous item is done with LDS
@@ -952,7 +1009,7 @@ __global__ void __launch_bounds__(NT)
     par.goal = pd.goal;
     const int scene = __builtin_amdgcn_readfirstlane(pd.scene);
     eval_successor<NT>(scenes[scene], par, make_int2(w.y, w.z), it, out_cost, out_status,
-                       out_comps, smem, s_bb, s_acc);
+                       out_comps, smem, s_bb, s_acc, s_pl);
   }
 }
 
