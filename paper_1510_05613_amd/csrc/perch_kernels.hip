@@ -909,17 +909,22 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
                 const int ja = max(t0, jj - rv), jb = min(t1, jj + rv);
                 const int ia = max(ca, ii - ru), ib = min(cb, ii + ru);
                 const float zlo = z - cam.delta, zhi = z + cam.delta;
-                for (int jq = ja; jq <= jb && !expl; ++jq)
-                  for (int iq = ia; iq <= ib; ++iq) {
-                    const float zq = __uint_as_float(tile[(jq - t0) * tw + (iq - ca)]);
-                    if (!(zq >= zlo && zq <= zhi)) continue;  // also skips +inf (no point)
+                // one flat walk over the clipped window, stopping at the first hit
+                const int n = (ib - ia + 1) * (jb - ja + 1);
+                int iq = ia, jq = ja;
+                int row = (ja - t0) * tw - ca;  // tile index of (0, jq)
+                for (int w = 0; w < n && !expl; ++w) {
+                  const float zq = __uint_as_float(tile[row + iq]);
+                  if (zq >= zlo && zq <= zhi) {  // also skips +inf (no point)
                     const float3 q = backproject(cam, iq, jq, zq);
                     const float dx = q.x - p.x, dy = q.y - p.y, dz = q.z - p.z;
-                    if (dx * dx + dy * dy + dz * dz <= delta2) {
-                      expl = true;
-                      break;
-                    }
+                    expl = dx * dx + dy * dy + dz * dz <= delta2;
                   }
+                  const bool wrap = iq == ib;
+                  row += wrap ? tw : 0;
+                  jq += wrap ? 1 : 0;
+                  iq = wrap ? ia : iq + 1;
+                }
               }
             }
             cnt_o = inV && !expl;
