@@ -155,31 +155,24 @@ __device__ __forceinline__ void map_vertex(const PoseMap& m, const float4 v, flo
 // ---------------------------------------------------------------------------
 
 // Narrows the covered columns [lo, hi] of a row (offsets from the box start, box
-// width w) by one edge whose value at offset k is e - s k: for s > 0 the edge
-// holds for k <= floor(e / s), for s < 0 for k >= -floor(e / |s|), for s = 0
+// width w <= 64) by one edge whose value at offset k is e - s k: for s > 0 the
+// edge holds for k <= floor(e / s), for s < 0 for k >= -floor(e / |s|), for s = 0
 // everywhere or nowhere.  floor(e / |s|) is estimated in float (|e| < 2^29,
-// 256 <= |s| < 2^22, so the estimate is off by at most one) and, when it lands
-// within the box, corrected with exact integer products; estimates beyond +-w
-// decide the same bound as the exact value.
+// 256 <= |s| < 2^22: the estimate is off by at most one), clamped to +-(w + 1)
+// (beyond the box every value decides the same) and corrected with exact 24-bit
+// products.  Branch-free: lanes of a wave take different cases.
 __device__ __forceinline__ void edge_bound(int e, int s, float rcp_abs_s, int w, int& lo,
                                            int& hi) {
-  if (s == 0) {
-    if (e < 0) hi = -1;
-    return;
-  }
   const int a = abs(s);
   const float lim = (float)(w + 1);
+  // for s = 0 the estimate is +-inf or NaN; fmaxf/fminf map it into range and the
+  // result is not used below
   int q = (int)fminf(fmaxf(floorf((float)e * rcp_abs_s), -lim), lim);
-  if (q >= -w && q <= w) {
-    if ((q + 1) * a <= e)
-      ++q;
-    else if (q * a > e)
-      --q;
-  }
-  if (s > 0)
-    hi = min(hi, q);
-  else
-    lo = max(lo, -q);
+  q += (__mul24(q + 1, a) <= e) ? 1 : 0;
+  q -= (__mul24(q, a) > e) ? 1 : 0;
+  hi = (s > 0) ? min(hi, q) : hi;
+  lo = (s < 0) ? max(lo, -q) : lo;
+  hi = (s == 0 && e < 0) ? -1 : hi;
 }
 
 // Calls emit(i, j) for every pixel centre (256 i, 256 j) covered by the triangle
