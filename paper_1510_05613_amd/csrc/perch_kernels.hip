@@ -154,25 +154,57 @@ __device__ __forceinline__ void map_vertex(const PoseMap& m, const float4 v, flo
 // triangle coverage: integer edge functions, top-left rule, front faces only
 // ---------------------------------------------------------------------------
 
-// Narrows the covered columns [lo, hi] of a row (offsets from the box start, box
-// width w <= 64) by one edge whose value at offset k is e - s k: for s > 0 the
-// edge holds for k <= floor(e / s), for s < 0 for k >= -floor(e / |s|), for s = 0
-// everywhere or nowhere.  floor(e / |s|) is estimated in float (|e| < 2^29,
-// 256 <= |s| < 2^22: the estimate is off by at most one), clamped to +-(w + 1)
-// (beyond the box every value decides the same) and corrected with exact 24-bit
-// products.  Branch-free: lanes of a wave take different cases.
-__device__ __forceinline__ void edge_bound(int e, int s, float rcp_abs_s, int w, int& lo,
-                                           int& hi) {
-  const int a = abs(s);
-  const float lim = (float)(w + 1);
-  // for s = 0 the estimate is +-inf or NaN; fmaxf/fminf map it into range and the
-  // result is not used below
-  int q = (int)fminf(fmaxf(floorf((float)e * rcp_abs_s), -lim), lim);
+// floor(e / a) for |e| < 2^29 and 1 <= a < 2^22: the float estimate is off by at
+// most one (|e| rounds by <= 16, the product by a few ulps of a quotient below
+// 2^21), and the exact 24-bit products fix it.
+__device__ __forceinline__ int floor_div(int e, int a) {
+  int q = (int)floorf((float)e * __builtin_amdgcn_rcpf((float)a));
   q += (__mul24(q + 1, a) <= e) ? 1 : 0;
   q -= (__mul24(q, a) > e) ? 1 : 0;
-  hi = (s > 0) ? min(hi, q) : hi;
-  lo = (s < 0) ? max(lo, -q) : lo;
-  hi = (s == 0 && e < 0) ? -1 : hi;
+  return q;
+}
+
+// One edge of raster_tri's int32 path, as a bound on a row's covered columns.
+// The edge value at column offset k of row j is e_j - s k with e_{j+1} = e_j + t
+// (s = 256 dy, t = 256 dx).  For s != 0 it holds for k <= q (s > 0) or k >= -q
+// (s < 0) with q = floor(e_j / |s|), kept with its remainder and stepped per row
+// by floor(t / |s|) and a carry.  For s = 0 it holds on whole rows: those are
+// clipped once (rows rlo..rhi) and the bound is neutral.
+struct EdgeDDA {
+  int q, rem, dq, dr, a;
+  bool pos;
+  __device__ __forceinline__ void bound(int& lo, int& hi) const {
+    hi = pos ? min(hi, q) : hi;
+    lo = pos ? lo : max(lo, -q);
+  }
+  __device__ __forceinline__ void step() {
+    rem += dr;
+    q += dq;
+    const bool c = rem >= a;
+    rem -= c ? a : 0;
+    q += c ? 1 : 0;
+  }
+};
+
+__device__ __forceinline__ void edge_dda(int e, int dy, int dx, int ja, int& rlo, int& rhi,
+                                         EdgeDDA& g) {
+  const int s = 256 * dy, t = 256 * dx;
+  const int a = abs(s);
+  const bool flat = a == 0;
+  const int aa = flat ? 1 : a;
+  const int q = floor_div(e, aa), dq = floor_div(t, aa);
+  g.q = flat ? (1 << 20) : q;
+  g.rem = flat ? 0 : e - q * aa;
+  g.dq = flat ? 0 : dq;
+  g.dr = flat ? 0 : t - dq * aa;
+  g.a = aa;
+  g.pos = flat || s > 0;
+  // horizontal edge: e + (j - ja) t >= 0 on rows j >= ja - floor(e / t) (t > 0) or
+  // j <= ja + floor(e / -t) (t < 0); t != 0 for an edge of non-zero length
+  // (for a sloped edge the quotient below is unused and may be garbage)
+  const int fr = floor_div(e, t != 0 ? abs(t) : 1);  // floor(e / |t|)
+  rlo = (flat && t > 0) ? max(rlo, ja - fr) : rlo;
+  rhi = (flat && t < 0) ? min(rhi, ja + fr) : rhi;
 }
 
 // Calls emit(i, j) for every pixel centre (256 i, 256 j) covered by the triangle
@@ -201,27 +233,27 @@ __device__ __forceinline__ void raster_tri(int x0, int y0, int x1, int y1, int x
     const int b0 = (d0y < 0 || (d0y == 0 && d0x > 0)) ? 0 : -1;
     const int b1 = (d1y < 0 || (d1y == 0 && d1x > 0)) ? 0 : -1;
     const int b2 = (d2y < 0 || (d2y == 0 && d2x > 0)) ? 0 : -1;
-    // Per row the covered centres form one interval; each edge bounds it from one
-    // side (edge_bound), so only covered pixels are visited: thin triangles, whose
-    // boxes are mostly empty, cost one bound per row instead of a walk of the box.
+    // Per row the covered centres form one interval; each sloped edge bounds it
+    // from one side at floor(e / |s|) pixels from the box start, a quotient that
+    // is stepped from row to row by exact integer DDA (quotient and remainder), so
+    // thin triangles, whose boxes are mostly empty, cost a few adds per row.  A
+    // horizontal edge (at most one) instead limits the rows.
     const int py = 256 * ja - y0, px0 = 256 * ia - x0;
-    int e0 = d0x * py - d0y * px0 + b0;  // edge values at (ia, j)
-    int e1 = d1x * (py - by) - d1y * (px0 - bx) + b1;
-    int e2 = d2x * (py - cy) - d2y * (px0 - cx) + b2;
-    const int s0 = 256 * d0y, s1 = 256 * d1y, s2 = 256 * d2y;  // decrease per column
-    const float q0 = __builtin_amdgcn_rcpf((float)abs(s0));
-    const float q1 = __builtin_amdgcn_rcpf((float)abs(s1));
-    const float q2 = __builtin_amdgcn_rcpf((float)abs(s2));
     const int w = ib - ia + 1;
+    int rlo = ja, rhi = jb;
+    EdgeDDA g0, g1, g2;
+    edge_dda(d0x * py - d0y * px0 + b0, d0y, d0x, ja, rlo, rhi, g0);
+    edge_dda(d1x * (py - by) - d1y * (px0 - bx) + b1, d1y, d1x, ja, rlo, rhi, g1);
+    edge_dda(d2x * (py - cy) - d2y * (px0 - cx) + b2, d2y, d2x, ja, rlo, rhi, g2);
     for (int j = ja; j <= jb; ++j) {
-      int lo = 0, hi = w - 1;
-      edge_bound(e0, s0, q0, w, lo, hi);
-      edge_bound(e1, s1, q1, w, lo, hi);
-      edge_bound(e2, s2, q2, w, lo, hi);
+      int lo = 0, hi = (j >= rlo && j <= rhi) ? w - 1 : -1;
+      g0.bound(lo, hi);
+      g1.bound(lo, hi);
+      g2.bound(lo, hi);
       for (int i = lo; i <= hi; ++i) emit(ia + i, j);
-      e0 += 256 * d0x;
-      e1 += 256 * d1x;
-      e2 += 256 * d2x;
+      g0.step();
+      g1.step();
+      g2.step();
     }
   } else {
     long long bx = (long long)x1 - x0, by = (long long)y1 - y0;
