@@ -66,7 +66,7 @@ def parse_args(argv=None):
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--scene", type=int, default=0)
     ap.add_argument("--threads", type=int, default=0, help="threads per successor (0 = default)")
-    ap.add_argument("--tile", type=int, default=0, help="z-tile pixels (0 = default)")
+    ap.add_argument("--tile", type=int, default=0, help="z-tile pixels (0 = sized automatically)")
     ap.add_argument("--cell", type=float, default=0.0, help="voxel cell / delta (0 = default)")
     ap.add_argument("--radius", type=int, default=-1,
                     help="dJ_r query: 0 pixel window, 1 voxel hash (-1 = default)")
@@ -343,7 +343,8 @@ def main(argv=None):
                                 f"one step = every successor of every level on the "
                                 f"ground-truth path ({n_step})"),
                    "successors_per_step": n_step, "valid_per_step": valid,
-                   "threads_per_successor": args.threads or 256},
+                   "threads_per_successor": args.threads or 512,
+                   "tile_px": args.tile or "auto"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic),

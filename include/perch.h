@@ -137,11 +137,12 @@ perch_status perch_eval_children(perch_ctx* ctx, const perch_object* cands_dev, 
 perch_status perch_render(perch_ctx* ctx, const perch_object* objs, int32_t n,
                           int32_t composite, float* depth_dev);
 
-/* Tuning knobs of the successor kernel: threads per successor (64, 128 or 256),
- * z-tile capacity in pixels (LDS), voxel cell size in units of delta (>= 1), and
- * the radius query behind dJ_r (0 = exact pixel window over the observed depth,
- * 1 = uniform voxel hash of the observed cloud).  Pass 0 (radius_mode: -1) to keep
- * a value.  Results do not depend on them. */
+/* Tuning knobs of the successor kernel: threads per successor (64, 128, 256, 512
+ * or 1024; default 512), z-tile capacity in pixels (LDS; -1 = sized automatically
+ * from the largest mesh so that two workgroups share a CU, the default), voxel cell
+ * size in units of delta (>= 1), and the radius query behind dJ_r (0 = exact pixel
+ * window over the observed depth, 1 = uniform voxel hash of the observed cloud).
+ * Pass 0 (radius_mode: -1) to keep a value.  Results do not depend on them. */
 perch_status perch_set_tuning(perch_ctx* ctx, int32_t threads, int32_t tile_px,
                               float cell_over_delta, int32_t radius_mode);
 
@@ -200,8 +201,9 @@ perch_status perch_batch_set_parents(perch_batch* b, const perch_parent* parents
  * perch_eval_successors, indexed like the items).  Asynchronous. */
 perch_status perch_batch_eval(perch_batch* b, const perch_work* items_dev, int32_t n,
                               int32_t* cost_dev, int32_t* status_dev, int32_t* comps_dev);
-/* threads per workgroup (64/128/256), z-tile pixels, use_graph (0/1), persistent
- * grid size (0 = one workgroup per resident slot); 0 / -1 keeps a value. */
+/* threads per workgroup (64/128/256/512, default 512), z-tile pixels (-1 = sized
+ * automatically, the default), use_graph (0/1), persistent grid size (0 = one
+ * workgroup per resident slot); 0 (use_graph, grid: -1) keeps a value. */
 perch_status perch_batch_set_tuning(perch_batch* b, int32_t threads, int32_t tile_px,
                                     int32_t use_graph, int32_t grid);
 

@@ -88,10 +88,6 @@ perch_status upload_meshes(perch_ctx* c) {
 }
 
 // vertex cache + z-tile + one 128-entry triangle ring per wave
-static size_t eval_lds_bytes(const perch_ctx* c) {
-  return (size_t)c->max_nv * sizeof(int2) + (size_t)c->tile_px * sizeof(unsigned) +
-         (size_t)(c->threads / 64) * 128 * sizeof(unsigned);
-}
 
 static bool objects_ok(const perch_ctx* c, const perch_object* o, int n) {
   for (int k = 0; k < n; ++k)
@@ -323,13 +319,15 @@ perch_status perch_set_tuning(perch_ctx* c, int32_t threads, int32_t tile_px,
   if (!c) return fail(PERCH_E_ARG, "null context");
   if (radius_mode < -1 || radius_mode > 1) return fail(PERCH_E_ARG, "radius_mode must be -1, 0 or 1");
   if (radius_mode >= 0) c->radius_mode = radius_mode;
-  if (threads && threads != 64 && threads != 128 && threads != 256)
-    return fail(PERCH_E_ARG, "threads must be 64, 128 or 256");
-  if (tile_px && (tile_px < 256 || tile_px > 36864)) return fail(PERCH_E_ARG, "bad tile_px");
+  if (threads && threads != 64 && threads != 128 && threads != 256 && threads != 512 &&
+      threads != 1024)
+    return fail(PERCH_E_ARG, "threads must be 64, 128, 256, 512 or 1024");
+  if (tile_px && tile_px != -1 && (tile_px < 256 || tile_px > 36864))
+    return fail(PERCH_E_ARG, "bad tile_px");
   if (cell_over_delta != 0.0f && !(cell_over_delta >= 1.0f && cell_over_delta <= 8.0f))
     return fail(PERCH_E_ARG, "cell_over_delta must be in [1, 8]");
   if (threads) c->threads = threads;
-  if (tile_px) c->tile_px = tile_px;
+  if (tile_px) c->tile_px = tile_px < 0 ? 0 : tile_px;
   if (cell_over_delta != 0.0f && cell_over_delta != c->cell_over_delta) {
     c->cell_over_delta = cell_over_delta;
     if (c->has_obs) {
@@ -371,10 +369,10 @@ perch_status perch_eval_children(perch_ctx* c, const perch_object* cands_dev, in
     return fail(PERCH_E_ARG, "bad successor arrays");
   if (c->parent_j < 0) return fail(PERCH_E_STATE, "perch_set_parent not called");
   if (c->meshes_dirty) return fail(PERCH_E_STATE, "meshes changed since perch_set_parent");
-  const size_t lds = eval_lds_bytes(c);
+  const size_t lds = c->eval_lds();
   if (lds > 160 * 1024 - 256)
     return fail(PERCH_E_UNSUPPORTED, "LDS need %zu B exceeds the CU (max_nv=%d, tile=%d)", lds,
-                c->max_nv, c->tile_px);
+                c->max_nv, c->tile());
   if (n == 0) return PERCH_OK;
   const int K = (int)c->objects.size();
   Parent par;

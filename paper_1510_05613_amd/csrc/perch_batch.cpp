@@ -21,8 +21,8 @@ struct perch_batch {
   DevBuf scenes, parents, slot_depth, slot_ubits, slot_ucount, counter;
   int n_parents = 0;
   size_t npx_max = 0;
-  int threads = 256;
-  int tile_px = 4096;
+  int threads = 512;
+  int tile_px = 0;  // 0 = sized automatically (auto_tile_px)
   int use_graph = 1;
   int grid = 0;
   // graph cache
@@ -39,10 +39,8 @@ struct perch_batch {
     for (perch_ctx* c : ctxs) m = std::max(m, c->max_nv);
     return m;
   }
-  size_t lds_bytes() const {
-    return (size_t)max_nv() * sizeof(int2) + (size_t)tile_px * sizeof(unsigned) +
-           (size_t)(threads / 64) * 128 * sizeof(unsigned);
-  }
+  int tile() const { return tile_px > 0 ? tile_px : auto_tile_px(max_nv(), threads); }
+  size_t lds_bytes() const { return eval_lds_bytes(max_nv(), tile(), threads); }
   void drop_graph() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -99,11 +97,12 @@ void perch_batch_destroy(perch_batch* b) {
 perch_status perch_batch_set_tuning(perch_batch* b, int32_t threads, int32_t tile_px,
                                     int32_t use_graph, int32_t grid) {
   if (!b) return fail(PERCH_E_ARG, "null batch");
-  if (threads && threads != 64 && threads != 128 && threads != 256)
-    return fail(PERCH_E_ARG, "threads must be 64, 128 or 256");
-  if (tile_px && (tile_px < 256 || tile_px > 36864)) return fail(PERCH_E_ARG, "bad tile_px");
+  if (threads && threads != 64 && threads != 128 && threads != 256 && threads != 512)
+    return fail(PERCH_E_ARG, "threads must be 64, 128, 256 or 512");
+  if (tile_px && tile_px != -1 && (tile_px < 256 || tile_px > 36864))
+    return fail(PERCH_E_ARG, "bad tile_px");
   if (threads) b->threads = threads;
-  if (tile_px) b->tile_px = tile_px;
+  if (tile_px) b->tile_px = tile_px < 0 ? 0 : tile_px;
   if (use_graph >= 0) b->use_graph = use_graph ? 1 : 0;
   if (grid >= 0) b->grid = grid;
   return PERCH_OK;
@@ -152,7 +151,7 @@ perch_status perch_batch_set_parents(perch_batch* b, const perch_parent* parents
   const int max_nv = b->max_nv();
   for (size_t k = 0; k < b->ctxs.size(); ++k) {
     sd[k] = b->ctxs[k]->scene_dev();
-    sd[k].ep.tile_px = b->tile_px;
+    sd[k].ep.tile_px = b->tile();
     sd[k].ep.max_nv = max_nv;
   }
   HIP_TRY(hipMemcpyAsync(b->parents.p, pd.data(), sizeof(ParentDev) * pd.size(),
@@ -193,7 +192,7 @@ perch_status perch_batch_eval(perch_batch* b, const perch_work* items_dev, int32
   }
   const bool same = b->exec && b->g_items == items_dev && b->g_n == n && b->g_cost == cost_dev &&
                     b->g_status == status_dev && b->g_comps == comps_dev &&
-                    b->g_threads == b->threads && b->g_tile == b->tile_px && b->g_grid == grid &&
+                    b->g_threads == b->threads && b->g_tile == b->tile() && b->g_grid == grid &&
                     b->g_parents == b->n_parents && b->g_ptab == b->parents.p;
   if (!same) {
     b->drop_graph();
@@ -216,7 +215,7 @@ perch_status perch_batch_eval(perch_batch* b, const perch_work* items_dev, int32
     b->g_status = status_dev;
     b->g_comps = comps_dev;
     b->g_threads = b->threads;
-    b->g_tile = b->tile_px;
+    b->g_tile = b->tile();
     b->g_grid = grid;
     b->g_parents = b->n_parents;
     b->g_ptab = b->parents.p;

@@ -2,6 +2,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <string>
 #include <vector>
 
@@ -85,6 +87,26 @@ perch_status fail(perch_status st, const char* fmt, ...);
   } while (0)
 
 
+// Dynamic LDS of the successor kernel: the snapped-vertex cache, the z-tile and
+// one 128-entry triangle queue per wave.
+inline size_t eval_lds_bytes(int max_nv, int tile_px, int threads) {
+  return (size_t)max_nv * sizeof(int2) + (size_t)tile_px * sizeof(unsigned) +
+         (size_t)(threads / 64) * 128 * sizeof(unsigned);
+}
+
+// Largest z-tile (a multiple of 256 pixels, at most 36,864) that lets two
+// workgroups share a CU's 160 KB of LDS (four for 256 threads or fewer), else one;
+// rows that do not fit are processed in bands.
+inline int auto_tile_px(int max_nv, int threads) {
+  const long fixed = (long)eval_lds_bytes(max_nv, 0, threads) + 2048;  // + static LDS
+  const int per_cu[3] = {threads <= 256 ? 4 : 2, 2, 1};
+  for (int k = 0; k < 3; ++k) {
+    const long budget = (160L * 1024) / per_cu[k] - 256 - fixed;
+    if (budget >= 4L * 4096) return (int)std::min(36864L, (budget / 4) & ~255L);
+  }
+  return 1024;
+}
+
 struct perch_ctx {
   using DevBuf = perch::DevBuf;
   using HostMesh = perch::HostMesh;
@@ -122,11 +144,14 @@ struct perch_ctx {
   // search scratch: candidate list and outputs of one expansion
   DevBuf s_cands, s_out;
   PinnedBuf s_hcands, s_hout;
-  // tuning
-  int threads = 256;
-  int tile_px = 4096;
+  // tuning (tile_px 0 = sized automatically, see auto_tile_px)
+  int threads = 512;
+  int tile_px = 0;
   int radius_mode = 0;
   EvalParams ep{};
+
+  int tile() const { return tile_px > 0 ? tile_px : auto_tile_px(max_nv, threads); }
+  size_t eval_lds() const { return eval_lds_bytes(max_nv, tile(), threads); }
 
   Meshes dev_meshes() const {
     Meshes M;
@@ -148,7 +173,7 @@ struct perch_ctx {
     S.obs_range = obs_range.as<float2>();
     S.hs = dev_hash();
     S.ep = ep;
-    S.ep.tile_px = tile_px;
+    S.ep.tile_px = tile();
     S.ep.max_nv = max_nv;
     S.ep.n_mesh = (int)meshes.size();
     S.ep.n_poses = P;

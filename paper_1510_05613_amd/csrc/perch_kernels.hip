@@ -1003,7 +1003,7 @@ __global__ void __launch_bounds__(NT)
 // may belong to different scenes: each workgroup takes the next item from an
 // atomic counter until the queue is empty, so uneven meshes balance across CUs.
 template <int NT>
-__global__ void __launch_bounds__(NT)
+__global__ void __launch_bounds__(NT, 4)  // at least 4 waves per SIMD: <= 128 VGPRs
     k_eval_batch(const SceneDev* __restrict__ scenes, const ParentDev* __restrict__ parents,
                  int n_parents, const int4* __restrict__ items, int n, int* counter,
                  int* __restrict__ out_cost, int* __restrict__ out_status,
@@ -1122,6 +1122,10 @@ hipError_t launch_eval(int threads, const SceneDev& S, const Parent& par, const 
       return launch_eval_t<64>(S, par, cands, n, cost, status, comps, lds_bytes, s);
     case 128:
       return launch_eval_t<128>(S, par, cands, n, cost, status, comps, lds_bytes, s);
+    case 512:
+      return launch_eval_t<512>(S, par, cands, n, cost, status, comps, lds_bytes, s);
+    case 1024:
+      return launch_eval_t<1024>(S, par, cands, n, cost, status, comps, lds_bytes, s);
     default:
       return launch_eval_t<256>(S, par, cands, n, cost, status, comps, lds_bytes, s);
   }
@@ -1140,6 +1144,8 @@ hipError_t prepare_eval_batch(int threads, size_t lds_bytes, int* blocks_per_cu)
       return prepare_eval_batch_t<64>(lds_bytes, blocks_per_cu);
     case 128:
       return prepare_eval_batch_t<128>(lds_bytes, blocks_per_cu);
+    case 512:
+      return prepare_eval_batch_t<512>(lds_bytes, blocks_per_cu);
     default:
       return prepare_eval_batch_t<256>(lds_bytes, blocks_per_cu);
   }
@@ -1168,6 +1174,9 @@ hipError_t launch_eval_batch(int threads, const SceneDev* scenes, const ParentDe
                                      comps, lds_bytes, grid, s);
     case 128:
       return launch_eval_batch_t<128>(scenes, parents, n_parents, items, n, counter, cost,
+                                      status, comps, lds_bytes, grid, s);
+    case 512:
+      return launch_eval_batch_t<512>(scenes, parents, n_parents, items, n, counter, cost,
                                       status, comps, lds_bytes, grid, s);
     default:
       return launch_eval_batch_t<256>(scenes, parents, n_parents, items, n, counter, cost,

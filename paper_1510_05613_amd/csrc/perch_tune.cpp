@@ -94,11 +94,13 @@ extern "C" perch_status perch_autotune(perch_ctx* c, const perch_object* parent,
     float cell;
   };
   std::vector<Cfg> cfgs;
-  for (int th : {256, 128})
-    for (int tile : {4096, 2048, 3072, 6144, 8192}) {
+  // tile -1: sized automatically for the thread count
+  for (int th : {512, 256})
+    for (int tile : {-1, 4096, 8192, 12288}) {
       cfgs.push_back({th, tile, 0, 2.0f});
-      for (float cell : {2.0f, 1.0f}) cfgs.push_back({th, tile, 1, cell});
+      cfgs.push_back({th, tile, 1, 2.0f});
     }
+  cfgs.push_back({512, -1, 1, 1.0f});
   const int keep_threads = c->threads, keep_tile = c->tile_px, keep_mode = c->radius_mode;
   const float keep_cell = c->cell_over_delta;
   perch_tuning bestt{};
@@ -110,9 +112,7 @@ extern "C" perch_status perch_autotune(perch_ctx* c, const perch_object* parent,
     // the cell change rebuilt the hash (and synchronised): materialise the parent again
     err = perch_set_parent(c, parent, j);
     if (err) break;
-    const size_t lds = (size_t)c->max_nv * sizeof(int2) + (size_t)g.tile * sizeof(unsigned) +
-                       (size_t)(g.threads / 64) * 128 * sizeof(unsigned);
-    if (lds > 160 * 1024 - 256) continue;
+    if (c->eval_lds() > 160 * 1024 - 2304) continue;  // with the static LDS
     err = perch_eval_children(c, cands_dev, n, cost, status, nullptr);  // warm-up
     if (err) break;
     std::vector<float> ms;
@@ -140,13 +140,13 @@ extern "C" perch_status perch_autotune(perch_ctx* c, const perch_object* parent,
     }
     std::sort(ms.begin(), ms.end());
     const float med = ms[ms.size() / 2];
-    if (med < bestt.ms) bestt = perch_tuning{g.threads, g.tile, g.mode, g.cell, med};
+    if (med < bestt.ms) bestt = perch_tuning{g.threads, c->tile(), g.mode, g.cell, med};
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   out.release();
   if (err || bestt.ms >= 1e30f) {
-    (void)perch_set_tuning(c, keep_threads, keep_tile, keep_cell, keep_mode);
+    (void)perch_set_tuning(c, keep_threads, keep_tile > 0 ? keep_tile : -1, keep_cell, keep_mode);
     return err ? err : fail(PERCH_E_UNSUPPORTED, "no tuning candidate fits the LDS");
   }
   st = perch_set_tuning(c, bestt.threads, bestt.tile_px, bestt.cell_over_delta, bestt.radius_mode);

@@ -208,7 +208,9 @@ class Context:
 
     def set_tuning(self, threads: int = 0, tile_px: int = 0, cell_over_delta: float = 0.0,
                    radius_mode: int = -1):
-        """Kernel knobs (0 / -1 keep the current value); results do not depend on them."""
+        """Kernel knobs: threads per successor, z-tile pixels (-1 = sized
+        automatically), voxel cell / delta, radius mode; 0 (radius_mode -1) keeps the
+        current value.  Results do not depend on them."""
         _check(load().perch_set_tuning(self.h, threads, tile_px, cell_over_delta, radius_mode))
 
     def autotune(self, parent, cands, reps: int = 3, cache_path: Optional[str] = None) -> dict:

@@ -159,7 +159,8 @@ def test_autotuner_picks_a_setting_and_caches_it(tmp_path):
     torch.cuda.synchronize()
     cache = str(tmp_path / "tune.jsonl")
     t = ctx.autotune(parent, cands, reps=2, cache_path=cache)
-    assert t["threads"] in (128, 256) and t["radius_mode"] in (0, 1) and t["ms"] > 0
+    assert t["threads"] in (256, 512) and t["radius_mode"] in (0, 1) and t["ms"] > 0
+    assert t["tile_px"] >= 256
     after = ctx.evaluate(parent, cands)
     torch.cuda.synchronize()
     for a, b in zip(before, after):

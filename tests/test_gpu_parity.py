@@ -155,12 +155,14 @@ def test_results_independent_of_tuning(c1):
     ps = np.arange(sc.grid.P)
     ref = _gpu_eval(ctx, par, ms, ps)
     for threads, tile, cell, mode in [(64, 0, 0, 1), (128, 0, 1.0, 1), (256, 300, 3.0, 0),
-                                      (64, 260, 2.0, 0), (128, 8192, 1.0, 1)]:
+                                      (64, 260, 2.0, 0), (128, 8192, 1.0, 1), (512, 300, 2.0, 0),
+                                      (1024, 20000, 2.0, 1), (1024, 700, 1.0, 0),
+                                      (512, -1, 2.0, 0)]:
         ctx.set_tuning(threads, tile, cell, mode)
         got = _gpu_eval(ctx, par, ms, ps)
         for a, b in zip(ref, got):
             assert np.array_equal(a, b), (threads, tile, cell, mode)
-    ctx.set_tuning(256, 8192, 2.0, 0)
+    ctx.set_tuning(512, -1, 2.0, 0)
 
 
 @pytest.fixture(scope="module")
@@ -206,7 +208,7 @@ def test_640x480_banded_tiles_match(c2):
     got = _gpu_eval(ctx, par, ms, ps)
     ctx.set_tuning(0, 8192, 0, 1)
     hashed = _gpu_eval(ctx, par, ms, ps)
-    ctx.set_tuning(0, 8192, 0, 0)
+    ctx.set_tuning(0, -1, 0, 0)
     for a, b in zip(ref, hashed):
         assert np.array_equal(a, b)
     assert np.all(ref[0] >= 0) and np.all(got[0] >= 0)
