@@ -24,6 +24,7 @@ def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     objs = []
     for src, flags in (("perch_kernels.hip", DEVICE_FLAGS), ("perch_cnn.hip", DEVICE_FLAGS),
+                       ("perch_select.hip", DEVICE_FLAGS),
                        ("perch_cnn_api.cpp", HOST_FLAGS), ("perch_api.cpp", HOST_FLAGS),
                        ("perch_search.cpp", HOST_FLAGS), ("perch_batch.cpp", HOST_FLAGS),
                        ("perch_tune.cpp", HOST_FLAGS)):

@@ -46,15 +46,23 @@ struct Net {
   bf16_t* Wb[4];        // bfloat16 conv weights [32][KP]
   float* feat;          // [n][64]
   float* dfeat;
+  float* hid;           // inference: [n_crops + n_mesh][64] partial first-layer sums
   float* loss;          // sum of squared errors
   Params P, G;
 };
 
 void launch_crops(const float* obs, const unsigned* pdepth, int W, int H, const CropDesc* desc,
                   int n, bf16_t* out, hipStream_t s);
+// Crop centres of table points (x, y): nearest pixel of the projection and the
+// camera depth of the point; false when a point lies behind the camera.
+bool crop_descriptors(const float M[12], float fx, float fy, float cx, float cy, const float* xy,
+                      int n, CropDesc* out);
 void launch_forward(const Net& net, int n_crops, hipStream_t s);
 // Pairs whose crop index is outside [0, n_crops) or mesh outside [0, n_mesh) are
 // ignored by the backward pass and predicted as NaN.
+// The first head layer splits into a per-crop part (features), a per-mesh part
+// (embedding and bias) and the yaw terms, so inference evaluates the two parts
+// once per crop and per mesh and only adds them per pair.
 void launch_predict(const Net& net, int n_crops, int n_mesh, const Pair* pairs, int n_pairs,
                     float* pred, hipStream_t s);
 void launch_backward(const Net& net, int n_crops, int n_mesh, const Pair* pairs,

@@ -82,36 +82,33 @@ struct KDim {
   static constexpr int LDSROW = KP + 8;              // LDS row stride (bank spread)
 };
 
-// Eight consecutive k of the im2col patch of output pixel (n, oy, ox).
+// Eight consecutive k of the im2col patch of output pixel (n, oy, ox); branch-free
+// (out-of-range reads are redirected to element 0 and zeroed).
 template <int CIN, int S, int HIN>
 __device__ __forceinline__ uint4 patch8(const bf16_t* __restrict__ in, bool valid, int n, int oy,
                                         int ox, int k0) {
-  uint4 r = make_uint4(0u, 0u, 0u, 0u);
-  if (!valid) return r;
   if (CIN % 8 == 0) {
     const int tap = k0 / CIN, ci0 = k0 % CIN;
     const int iy = oy * S + tap / 3 - 1, ix = ox * S + tap % 3 - 1;
-    if (tap < 9 && iy >= 0 && iy < HIN && ix >= 0 && ix < HIN)
-      r = *reinterpret_cast<const uint4*>(in + (((size_t)n * HIN + iy) * HIN + ix) * CIN + ci0);
+    const bool ok = valid && tap < 9 && iy >= 0 && iy < HIN && ix >= 0 && ix < HIN;
+    const size_t off = ok ? (((size_t)n * HIN + iy) * HIN + ix) * CIN + ci0 : 0;
+    const uint4 v = *reinterpret_cast<const uint4*>(in + off);
+    return ok ? v : make_uint4(0u, 0u, 0u, 0u);
   } else {
-    unsigned short v[8];
+    unsigned v[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int k = k0 + q;
-      v[q] = 0;
-      if (k < 9 * CIN) {
-        const int tap = k / CIN, ci = k % CIN;
-        const int iy = oy * S + tap / 3 - 1, ix = ox * S + tap % 3 - 1;
-        if (iy >= 0 && iy < HIN && ix >= 0 && ix < HIN)
-          v[q] = in[(((size_t)n * HIN + iy) * HIN + ix) * CIN + ci];
-      }
+      const int tap = k / CIN, ci = k % CIN;
+      const int iy = oy * S + tap / 3 - 1, ix = ox * S + tap % 3 - 1;
+      const bool ok = valid && k < 9 * CIN && iy >= 0 && iy < HIN && ix >= 0 && ix < HIN;
+      const size_t off = ok ? (((size_t)n * HIN + iy) * HIN + ix) * CIN + ci : 0;
+      const unsigned x = in[off];
+      v[q] = ok ? x : 0u;
     }
-    r.x = v[0] | ((unsigned)v[1] << 16);
-    r.y = v[2] | ((unsigned)v[3] << 16);
-    r.z = v[4] | ((unsigned)v[5] << 16);
-    r.w = v[6] | ((unsigned)v[7] << 16);
+    return make_uint4(v[0] | (v[1] << 16), v[2] | (v[3] << 16), v[4] | (v[5] << 16),
+                      v[6] | (v[7] << 16));
   }
-  return r;
 }
 
 // 4 waves per workgroup, each a 32-pixel x 32-channel output tile.
@@ -331,6 +328,48 @@ __global__ void k_head_fwd(const float* feat, const Params P, const Pair* pairs,
   pred[q] = y;
 }
 
+// Inference head, part 1: block b < n_crops holds crop b's feature term of every
+// hidden unit, A[b][r] = sum_i hW1[r][i] feat[b][i]; block n_crops + m holds mesh
+// m's term, B[m][r] = hb1[r] + sum_e hW1[r][64 + e] emb[m][e].
+__global__ void __launch_bounds__(kHid)
+    k_head_parts(const float* feat, const Params P, int n_crops, float* hid) {
+  __shared__ float x[kFeat];
+  const int b = blockIdx.x, r = threadIdx.x;
+  const bool crop = b < n_crops;
+  const int m = b - n_crops;
+  if (crop) x[r] = feat[b * kFeat + r];
+  else if (r < kEmb) x[r] = P.emb[m * kEmb + r];
+  __syncthreads();
+  const float* w = P.hW1 + r * kIn;
+  float z = crop ? 0.0f : P.hb1[r];
+  if (crop)
+    for (int i = 0; i < kFeat; ++i) z = fmaf(w[i], x[i], z);
+  else
+    for (int e = 0; e < kEmb; ++e) z = fmaf(w[kFeat + e], x[e], z);
+  hid[b * kHid + r] = z;
+}
+
+// Inference head, part 2: one pair per thread (NaN for an out-of-range pair).
+__global__ void k_head_pairs(const float* hid, const Params P, const Pair* pairs, int n_pairs,
+                             int n_crops, int n_mesh, float* pred) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n_pairs) return;
+  const Pair pr = pairs[q];
+  if (!pair_ok(pr, n_crops, n_mesh)) {
+    pred[q] = __uint_as_float(0x7fc00000u);
+    return;
+  }
+  const float* a = hid + pr.crop * kHid;
+  const float* bm = hid + (n_crops + pr.mesh) * kHid;
+  float y = P.hb2[0];
+  for (int r = 0; r < kHid; ++r) {
+    const float* w = P.hW1 + r * kIn + kFeat + kEmb;
+    const float z = fmaf(w[1], pr.sin_yaw, fmaf(w[0], pr.cos_yaw, a[r] + bm[r]));
+    y = fmaf(P.hw2[r], fmaxf(z, 0.0f), y);
+  }
+  pred[q] = y;
+}
+
 // Loss and head gradients for 64 pairs per workgroup: per-pair h and dz1 go to
 // LDS, the weight gradients are reduced over the workgroup's pairs and added once.
 __global__ void __launch_bounds__(64)
@@ -452,9 +491,11 @@ void launch_forward(const Net& net, int n_crops, hipStream_t s) {
 
 void launch_predict(const Net& net, int n_crops, int n_mesh, const Pair* pairs, int n_pairs,
                     float* pred, hipStream_t s) {
-  if (n_pairs > 0)
-    hipLaunchKernelGGL(k_head_fwd, dim3((n_pairs + 127) / 128), dim3(128), 0, s, net.feat, net.P,
-                       pairs, n_pairs, n_crops, n_mesh, pred);
+  if (n_pairs <= 0) return;
+  hipLaunchKernelGGL(k_head_parts, dim3(n_crops + n_mesh), dim3(kHid), 0, s, net.feat, net.P,
+                     n_crops, net.hid);
+  hipLaunchKernelGGL(k_head_pairs, dim3((n_pairs + 255) / 256), dim3(256), 0, s, net.hid, net.P,
+                     pairs, n_pairs, n_crops, n_mesh, pred);
 }
 
 template <int CIN, int S, int HIN>

@@ -16,7 +16,7 @@ struct perch_cnn {
   int64_t n_params = 0;
   int step = 0;
   DevBuf params, grads, m, v;  // FP32, flat
-  DevBuf act, dact, wb, feat, dfeat, loss;
+  DevBuf act, dact, wb, feat, dfeat, hid, loss;
   Net net{};
   int64_t off[13];  // offsets of the 13 tensors in the flat arrays
 };
@@ -53,6 +53,42 @@ Params views(float* base, const int64_t* off) {
 
 }  // namespace
 
+namespace perch {
+namespace cnn {
+
+bool crop_descriptors(const float M[12], float fx, float fy, float cx, float cy, const float* xy,
+                      int n, CropDesc* out) {
+  // crop centre: the table point (x, y, 0) projected to the nearest pixel
+  for (int k = 0; k < n; ++k) {
+    double p[3];
+    for (int r = 0; r < 3; ++r)
+      p[r] = (double)M[4 * r] * xy[2 * k] + (double)M[4 * r + 1] * xy[2 * k + 1] + M[4 * r + 3];
+    if (!(p[2] > 0.01)) return false;
+    out[k].u0 = (int)std::lround(fx * p[0] / p[2] + cx);
+    out[k].v0 = (int)std::lround(fy * p[1] / p[2] + cy);
+    out[k].zref = (float)p[2];
+    out[k].pad = 0;
+  }
+  return true;
+}
+
+}  // namespace cnn
+
+perch_status cnn_predict_on(perch_cnn* c, const uint16_t* crops, int n_crops, const void* pairs,
+                            int n_pairs, float* pred, hipStream_t s) {
+  if (!c || n_crops < 1 || n_pairs < 1 || n_crops > c->max_crops || n_pairs > c->max_pairs)
+    return fail(PERCH_E_ARG, "batch (%d crops, %d pairs) above the network's capacity (%d, %d)",
+                n_crops, n_pairs, c ? c->max_crops : 0, c ? c->max_pairs : 0);
+  c->net.crops = crops;
+  launch_forward(c->net, n_crops, s);
+  launch_predict(c->net, n_crops, c->n_mesh, reinterpret_cast<const Pair*>(pairs), n_pairs, pred,
+                 s);
+  HIP_TRY(hipGetLastError());
+  return PERCH_OK;
+}
+
+}  // namespace perch
+
 extern "C" {
 
 perch_status perch_cnn_create(int32_t n_mesh, int32_t max_crops, int32_t max_pairs,
@@ -84,6 +120,7 @@ perch_status perch_cnn_create(int32_t n_mesh, int32_t max_crops, int32_t max_pai
   if (e == hipSuccess) e = c->wb.ensure((kp[0] + 3 * kp[1]) * kC * sizeof(bf16_t));
   if (e == hipSuccess) e = c->feat.ensure((size_t)max_crops * kFeat * sizeof(float));
   if (e == hipSuccess) e = c->dfeat.ensure((size_t)max_crops * kFeat * sizeof(float));
+  if (e == hipSuccess) e = c->hid.ensure((size_t)(max_crops + n_mesh) * kHid * sizeof(float));
   if (e == hipSuccess) e = c->loss.ensure(sizeof(float));
   if (e == hipSuccess) e = hipMemsetAsync(c->params.p, 0, pb, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->m.p, 0, pb, c->stream);
@@ -114,6 +151,7 @@ perch_status perch_cnn_create(int32_t n_mesh, int32_t max_crops, int32_t max_pai
   }
   n.feat = c->feat.as<float>();
   n.dfeat = c->dfeat.as<float>();
+  n.hid = c->hid.as<float>();
   n.loss = c->loss.as<float>();
   n.P = views(c->params.as<float>(), c->off);
   n.G = views(c->grads.as<float>(), c->off);
@@ -126,7 +164,7 @@ void perch_cnn_destroy(perch_cnn* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
   for (DevBuf* b : {&c->params, &c->grads, &c->m, &c->v, &c->act, &c->dact, &c->wb, &c->feat,
-                    &c->dfeat, &c->loss})
+                    &c->dfeat, &c->hid, &c->loss})
     b->release();
   delete c;
 }
@@ -156,20 +194,10 @@ perch_status perch_cnn_crops(perch_ctx* ctx, const float* xy, int32_t n, uint16_
   if (!ctx->has_obs) return fail(PERCH_E_STATE, "perch_set_observation not called");
   if (ctx->parent_j < 0) return fail(PERCH_E_STATE, "perch_set_parent not called");
   if (n == 0) return PERCH_OK;
-  // crop centre: the table point (x, y, 0) projected to the nearest pixel
   std::vector<CropDesc> d(n);
   const Cam& cam = ctx->cam;
-  for (int k = 0; k < n; ++k) {
-    double p[3];
-    for (int r = 0; r < 3; ++r)
-      p[r] = (double)cam.M[4 * r] * xy[2 * k] + (double)cam.M[4 * r + 1] * xy[2 * k + 1] +
-             cam.M[4 * r + 3];
-    if (!(p[2] > 0.01)) return fail(PERCH_E_ARG, "crop centre %d behind the camera", k);
-    d[k].u0 = (int)std::lround(cam.fx * p[0] / p[2] + cam.cx);
-    d[k].v0 = (int)std::lround(cam.fy * p[1] / p[2] + cam.cy);
-    d[k].zref = (float)p[2];
-    d[k].pad = 0;
-  }
+  if (!crop_descriptors(cam.M, cam.fx, cam.fy, cam.cx, cam.cy, xy, n, d.data()))
+    return fail(PERCH_E_ARG, "a crop centre lies behind the camera");
   HIP_TRY(ctx->cnn_desc.ensure(sizeof(CropDesc) * n));
   HIP_TRY(hipMemcpyAsync(ctx->cnn_desc.p, d.data(), sizeof(CropDesc) * n, hipMemcpyHostToDevice,
                          ctx->stream));

@@ -76,6 +76,11 @@ inline int next_pow2(int v) {
 // Records a message for perch_last_error() and returns st.
 perch_status fail(perch_status st, const char* fmt, ...);
 
+// Runs the learned network (forward pass and head) on stream s, the context's
+// stream in the learned search (perch_cnn_api.cpp).
+perch_status cnn_predict_on(perch_cnn* c, const uint16_t* crops, int n_crops, const void* pairs,
+                            int n_pairs, float* pred, hipStream_t s);
+
 }  // namespace perch
 
 #define HIP_TRY(expr)                                                                   \

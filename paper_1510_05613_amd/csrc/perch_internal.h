@@ -114,4 +114,20 @@ hipError_t launch_eval_batch(int threads, const SceneDev* scenes, const ParentDe
                              int n_parents, const int4* items, int n, int* counter, int* cost,
                              int* status, int* comps, size_t lds_bytes, int grid, hipStream_t s);
 
+// ---- learned search: device-side ranking of children (perch_select.hip) ----
+constexpr int kMaxMeshes = 8;  // distinct meshes of one scene's object multiset
+struct MeshMask {
+  int allow[kMaxMeshes];  // 0: the mesh is placed already, its children rank last
+};
+// pred[u n_poses + b] = +inf for every mesh position u < n_meshes with allow[u] == 0
+void launch_mask_children(float* pred, int n_poses, int n_meshes, MeshMask mask, hipStream_t s);
+size_t select_temp_bytes(int n);
+// Stable sort of n predicted costs with their indices (ascending; NaN last).
+hipError_t sort_predictions(void* temp, size_t temp_bytes, const float* keys, float* keys_sorted,
+                            const int* idx, int* idx_sorted, int n, hipStream_t s);
+void launch_iota(int* idx, int n, hipStream_t s);
+// cands[i] = (rest[id / n_poses], pose_ids[id % n_poses]) for id = idx_sorted[i], i < k
+void launch_child_cands(const int* idx_sorted, int k, const int* rest, int n_poses,
+                        const int* pose_ids, int2* cands, hipStream_t s);
+
 }  // namespace perch

@@ -31,6 +31,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "perch_cnn.h"
 #include "perch_ctx.h"
 
 using namespace perch;
@@ -81,6 +82,21 @@ struct KeyEq {
 
 struct Child {
   int32_t mesh, pose, cost;
+};
+
+// Device buffers of one search call, released when it returns.
+struct Scratch {
+  std::vector<DevBuf*> bufs;
+  DevBuf& get() {
+    bufs.push_back(new DevBuf());
+    return *bufs.back();
+  }
+  ~Scratch() {
+    for (DevBuf* b : bufs) {
+      b->release();
+      delete b;
+    }
+  }
 };
 
 class Searcher {
@@ -331,7 +347,8 @@ class Searcher {
   perch_status learned() {
     if (!o_.cnn) return fail(PERCH_E_ARG, "the learned search needs a network");
     const int topk = o_.topk > 0 ? o_.topk : 64;
-    // pose cells: crops are taken once per distinct (x, y) of the pose set
+    const int P = (int)poses_.size();
+    // pose cells: one crop per distinct (x, y) of the pose set
     std::vector<float> cells;
     std::vector<int> cell_of(poses_.size());
     {
@@ -348,59 +365,83 @@ class Searcher {
       }
     }
     const int n_cells = (int)(cells.size() / 2);
-    const size_t maxp = (size_t)distinct_ * poses_.size();
-    DevBuf crops, pairs, pred;
-    HIP_TRY(crops.ensure((size_t)n_cells * 64 * 64 * 2 * sizeof(uint16_t)));
-    HIP_TRY(pairs.ensure(maxp * sizeof(perch_cnn_pair)));
-    HIP_TRY(pred.ensure(maxp * sizeof(float)));
+    // the distinct meshes of the multiset; child id = (position in this list) P + pose
+    std::vector<int> dist(c_->objects.begin(), c_->objects.end());
+    std::sort(dist.begin(), dist.end());
+    dist.erase(std::unique(dist.begin(), dist.end()), dist.end());
+    const int nd = (int)dist.size();
+    if (nd > kMaxMeshes) return fail(PERCH_E_UNSUPPORTED, "more than %d distinct meshes", kMaxMeshes);
+    const size_t maxp = (size_t)nd * P;
+    // everything a ranking needs stays on the device for the whole search
+    std::vector<cnn::CropDesc> hdesc(n_cells);
+    const Cam& cam = c_->cam;
+    if (!cnn::crop_descriptors(cam.M, cam.fx, cam.fy, cam.cx, cam.cy, cells.data(), n_cells,
+                               hdesc.data()))
+      return fail(PERCH_E_ARG, "a pose cell lies behind the camera");
     std::vector<perch_cnn_pair> hp(maxp);
-    std::vector<float> hpred(maxp);
-    std::vector<int> order(maxp);
+    for (int a = 0; a < nd; ++a)
+      for (int b = 0; b < P; ++b) {
+        const float* pz = &c_->h_poses[4 * (size_t)poses_[b]];
+        hp[(size_t)a * P + b] = perch_cnn_pair{cell_of[b], dist[a], pz[2], pz[3]};
+      }
+    Scratch sc;
+    DevBuf &d_desc = sc.get(), &d_pairs = sc.get(), &d_dist = sc.get(), &d_pose = sc.get();
+    DevBuf &d_crops = sc.get(), &d_pred = sc.get(), &d_keys = sc.get(), &d_idx = sc.get();
+    DevBuf &d_idx2 = sc.get(), &d_temp = sc.get();
+    const size_t temp_bytes = select_temp_bytes((int)maxp);
+    HIP_TRY(d_desc.ensure(sizeof(cnn::CropDesc) * n_cells));
+    HIP_TRY(d_pairs.ensure(sizeof(perch_cnn_pair) * maxp));
+    HIP_TRY(d_dist.ensure(sizeof(int) * nd));
+    HIP_TRY(d_pose.ensure(sizeof(int) * P));
+    HIP_TRY(d_crops.ensure((size_t)n_cells * 64 * 64 * 2 * sizeof(uint16_t)));
+    HIP_TRY(d_pred.ensure(sizeof(float) * maxp));
+    HIP_TRY(d_keys.ensure(sizeof(float) * maxp));
+    HIP_TRY(d_idx.ensure(sizeof(int) * maxp));
+    HIP_TRY(d_idx2.ensure(sizeof(int) * maxp));
+    HIP_TRY(d_temp.ensure(temp_bytes));
+    HIP_TRY(hipMemcpy(d_desc.p, hdesc.data(), sizeof(cnn::CropDesc) * n_cells,
+                      hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(d_pairs.p, hp.data(), sizeof(perch_cnn_pair) * maxp, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(d_dist.p, dist.data(), sizeof(int) * nd, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(d_pose.p, poses_.data(), sizeof(int) * P, hipMemcpyHostToDevice));
+    hipStream_t st0 = c_->stream;
+    launch_iota(d_idx.as<int>(), (int)maxp, st0);
 
-    // children of n: predict all, evaluate the top-k exactly (all = nothing left over)
+    // Children of n: materialise n, crop every cell, predict every (mesh, pose),
+    // rank on the device (children of meshes already placed rank last), evaluate
+    // the k best exactly; one synchronisation.  all = nothing is left over.
     auto learned_expand = [&](const Node& n, std::vector<Child>& out, bool& all) -> perch_status {
       out.clear();
       const std::vector<int> rest = remaining(n);
-      const int P = (int)poses_.size();
       const int cnt = (int)rest.size() * P;
+      MeshMask mask{};
+      for (int a = 0; a < nd; ++a)
+        mask.allow[a] = std::find(rest.begin(), rest.end(), dist[a]) != rest.end() ? 1 : 0;
       perch_status st = perch_set_parent(c_, n.objs, n.j);
       if (st) return st;
-      st = perch_cnn_crops(c_, cells.data(), n_cells, crops.as<uint16_t>());
+      cnn::launch_crops(c_->obs.as<float>(), c_->par_depth.as<unsigned>(), cam.W, cam.H,
+                        d_desc.as<cnn::CropDesc>(), n_cells, d_crops.as<uint16_t>(), st0);
+      st = cnn_predict_on(o_.cnn, d_crops.as<uint16_t>(), n_cells, d_pairs.p, (int)maxp,
+                          d_pred.as<float>(), st0);
       if (st) return st;
-      for (size_t a = 0; a < rest.size(); ++a)
-        for (int b = 0; b < P; ++b) {
-          const float* pz = &c_->h_poses[4 * (size_t)poses_[b]];
-          hp[a * P + b] = perch_cnn_pair{cell_of[b], rest[a], pz[2], pz[3]};
-        }
-      HIP_TRY(hipMemcpy(pairs.p, hp.data(), cnt * sizeof(perch_cnn_pair), hipMemcpyHostToDevice));
-      st = perch_cnn_predict(o_.cnn, crops.as<uint16_t>(), n_cells,
-                             pairs.as<perch_cnn_pair>(), cnt, pred.as<float>());
-      if (st) return st;
-      HIP_TRY(hipDeviceSynchronize());
-      HIP_TRY(hipMemcpy(hpred.data(), pred.p, cnt * sizeof(float), hipMemcpyDeviceToHost));
-      for (int i = 0; i < cnt; ++i)  // a NaN would break the ordering: rank it last
-        if (!(hpred[i] == hpred[i])) hpred[i] = INFINITY;
+      launch_mask_children(d_pred.as<float>(), P, nd, mask, st0);
+      HIP_TRY(sort_predictions(d_temp.p, temp_bytes, d_pred.as<float>(), d_keys.as<float>(),
+                               d_idx.as<int>(), d_idx2.as<int>(), (int)maxp, st0));
       const int k = std::min(topk, cnt);
       all = k == cnt;
-      std::iota(order.begin(), order.begin() + cnt, 0);
-      std::partial_sort(order.begin(), order.begin() + k, order.begin() + cnt,
-                        [&](int x, int y) { return hpred[x] < hpred[y] || (hpred[x] == hpred[y] && x < y); });
-      int2* hc = c_->s_hcands.as<int2>();
-      for (int i = 0; i < k; ++i) {
-        const int id = order[i];
-        hc[i] = make_int2(rest[id / P], poses_[id % P]);
-      }
-      HIP_TRY(hipMemcpyAsync(c_->s_cands.p, hc, k * sizeof(int2), hipMemcpyHostToDevice,
-                             c_->stream));
+      int2* dc = c_->s_cands.as<int2>();
+      launch_child_cands(d_idx2.as<int>(), k, d_dist.as<int>(), P, d_pose.as<int>(), dc, st0);
       int32_t* dcost = c_->s_out.as<int32_t>();
       int32_t* dstat = dcost + k;
-      st = perch_eval_children(c_, reinterpret_cast<const perch_object*>(c_->s_cands.p), k,
-                               dcost, dstat, nullptr);
+      st = perch_eval_children(c_, reinterpret_cast<const perch_object*>(dc), k, dcost, dstat,
+                               nullptr);
       if (st) return st;
+      int2* hc = c_->s_hcands.as<int2>();
       int32_t* hout = c_->s_hout.as<int32_t>();
+      HIP_TRY(hipMemcpyAsync(hc, dc, k * sizeof(int2), hipMemcpyDeviceToHost, st0));
       HIP_TRY(hipMemcpyAsync(hout, dcost, 2 * (size_t)k * sizeof(int32_t), hipMemcpyDeviceToHost,
-                             c_->stream));
-      HIP_TRY(hipStreamSynchronize(c_->stream));
+                             st0));
+      HIP_TRY(hipStreamSynchronize(st0));
       ++n_expanded_;
       n_evaluated_ += k;
       for (int i = 0; i < k; ++i) {
