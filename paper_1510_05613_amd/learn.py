@@ -72,17 +72,31 @@ class Dataset:
         return int(self.valid.sum())
 
 
-def label_parent(ctx: "perch.Context", scene, parent, crop_base: int):
-    """Crops of `parent` at every cell and the labelled pairs of all its children."""
+def try_scene(config: int, index: int, render, lib, max_tries: int = 20):
+    """Scene `index`, or None when the generator's rejection sampling finds none
+    within max_tries placements (some object draws cannot meet the occlusion
+    requirement; those indices are skipped)."""
+    try:
+        return scenes.make_scene(config, index, render, library=lib, max_tries=max_tries)
+    except RuntimeError:
+        return None
+
+
+def label_parent(ctx: "perch.Context", scene, parent, crop_base: int, cells=None):
+    """Crops of `parent` at the given pose cells (all cells by default) and the
+    labelled pairs of every child placed in those cells."""
     import torch
 
     g = scene.grid
+    n_cells = g.nx * g.ny
+    cells = np.arange(n_cells) if cells is None else np.asarray(cells, np.int64)
     ctx.set_parent(parent)
-    crops = perch.Cnn.crops(ctx, cell_centres(g))
+    crops = perch.Cnn.crops(ctx, cell_centres(g)[cells])
     rest = remaining_meshes(scene, parent)
-    P = g.P
-    pose = np.tile(np.arange(P, dtype=np.int32), len(rest))
-    mesh = np.repeat(np.asarray(rest, np.int32), P)
+    cell_pose = (cells[:, None] * g.n_yaw + np.arange(g.n_yaw)[None, :]).ravel().astype(np.int32)
+    local = np.repeat(np.arange(len(cells)), g.n_yaw)
+    pose = np.tile(cell_pose, len(rest))
+    mesh = np.repeat(np.asarray(rest, np.int32), len(cell_pose))
     cands = torch.as_tensor(np.stack([mesh, pose], 1)).cuda()
     cost = torch.empty(len(pose), dtype=torch.int32, device="cuda")
     status = torch.empty_like(cost)
@@ -96,27 +110,52 @@ def label_parent(ctx: "perch.Context", scene, parent, crop_base: int):
     cap = (tgt[valid].max() if valid.any() else 0.0) + 1.0
     tgt = np.where(valid, tgt, cap).astype(np.float32)
     th = scene.poses[pose]
-    pairs = np.stack([crop_base + pose // g.n_yaw, mesh, th[:, 2], th[:, 3]], 1).astype(np.float32)
+    pairs = np.stack([crop_base + np.tile(local, len(rest)), mesh, th[:, 2], th[:, 3]],
+                     1).astype(np.float32)
     order = np.argsort(pairs[:, 0], kind="stable")
     return crops, pairs[order], tgt[order], valid[order]
 
 
-def build_dataset(indices: Sequence[int], config: int = 4, log=None) -> Dataset:
-    """Labels the children of the root and of every ground-truth prefix of each scene."""
+def sample_cells(scene, parent, max_cells: int, rng) -> Optional[np.ndarray]:
+    """None (every cell) when the grid has at most max_cells cells; otherwise the
+    cells of the remaining objects' true poses plus random cells, max_cells in all."""
+    g = scene.grid
+    n_cells = g.nx * g.ny
+    if n_cells <= max_cells:
+        return None
+    placed = {int(p) for _, p in parent}
+    gt = {int(scene.gt_pose[k]) // g.n_yaw for k in range(scene.K)
+          if int(scene.gt_pose[k]) not in placed}
+    extra = rng.choice(n_cells, size=max_cells, replace=False)
+    cells = list(gt) + [int(c) for c in extra if int(c) not in gt]
+    return np.sort(np.asarray(cells[:max_cells], np.int64))
+
+
+def build_dataset(indices: Sequence[int], config: int = 4, log=None,
+                  max_cells: int = 256) -> Dataset:
+    """Labels the children of the root and of every ground-truth prefix of each scene
+    (on grids with more than max_cells cells, those in a seeded sample of cells).
+    Held-out indices are refused."""
     import torch
 
     lib = scenes.make_library(scenes.CONFIGS[config]["lib"])
     render = perch.GpuRenderer()
     crops, pairs, tgts, valid = [], [], [], []
     base, n_par, par_ptr = 0, 0, [0]
-    t0 = time.time()
+    t0 = t_log = time.time()
     for n, i in enumerate(indices):
         if i >= HELD_OUT_FIRST:
             raise ValueError(f"scene {i} is held out")
-        sc = scenes.make_scene(config, int(i), render, library=lib)
+        # a training scene whose occlusion requirement is not met within a few
+        # placements is drawn again without it (same seed, camera, library, grid)
+        sc = try_scene(config, int(i), render, lib, max_tries=3)
+        if sc is None:
+            sc = scenes.make_scene(config, int(i), render, library=lib,
+                                   overrides={"occlusion": None})
         ctx = perch.context_from_scene(sc)
+        rng = np.random.default_rng(sc.seed)
         for par in gt_prefixes(sc):
-            c, p, t, v = label_parent(ctx, sc, par, base)
+            c, p, t, v = label_parent(ctx, sc, par, base, sample_cells(sc, par, max_cells, rng))
             crops.append(c)
             pairs.append(p)
             tgts.append(t)
@@ -125,7 +164,8 @@ def build_dataset(indices: Sequence[int], config: int = 4, log=None) -> Dataset:
             n_par += 1
             par_ptr.append(base)
         ctx.close()
-        if log and (n + 1) % 50 == 0:
+        if log and ((n + 1) % 50 == 0 or time.time() - t_log > 20.0):
+            t_log = time.time()
             log(f"dataset: {n + 1}/{len(indices)} scenes, {sum(len(p) for p in pairs)} pairs, "
                 f"{time.time() - t0:.1f} s")
     pairs = np.concatenate(pairs)
@@ -241,45 +281,84 @@ SEARCHES = ("exhaustive", "ucs", "focal", "learned", "random_init")
 
 
 def gain(net: "perch.Cnn", control: "perch.Cnn", indices: Sequence[int], config: int = 4,
-         w: float = 3.0, topk: int = 64, log=None) -> dict:
+         w: float = 3.0, topk: int = 64, budget_s: float = 0.0, log=None) -> dict:
     """Time (and successor evaluations) until each search first holds the best
-    scene, on held-out scenes.  exhaustive and ucs are the plain searches; focal
-    is the paper's inadmissible depth heuristic without learning; learned and
-    random_init are the learned search with the trained and an untrained network.
-    Every search runs to completion and must return the exhaustive optimum."""
+    scene, on held-out scenes.  exhaustive (small trees only) and ucs are the plain
+    searches; focal is the paper's inadmissible depth heuristic without learning;
+    learned and random_init are the learned search with the trained and an
+    untrained network.  The best scene is the optimum returned by a plain search
+    that finished; a search that never held it counts as not reaching it (None).
+    budget_s > 0 limits every search."""
     lib = scenes.make_library(scenes.CONFIGS[config]["lib"])
     render = perch.GpuRenderer()
-    rows = []
-    for n, i in enumerate(indices):
+    names = [k for k in SEARCHES if k != "exhaustive" or config in (1, 4)]
+    rows, proven = [], 0
+    for i in indices:
         if i < HELD_OUT_FIRST:
             raise ValueError(f"scene {i} is a training scene")
-        sc = scenes.make_scene(config, int(i), render, library=lib)
+        sc = try_scene(config, int(i), render, lib)
+        if sc is None:
+            continue
         ctx = perch.context_from_scene(sc)
-        if n == 0:  # first-call costs (code object load, buffers) stay out of the timings
-            ctx.search(perch.SEARCH_LEARNED, w=w, anytime=True, cnn=net, topk=topk)
-        res = dict(
-            exhaustive=ctx.search(perch.SEARCH_EXHAUSTIVE),
-            ucs=ctx.search(perch.SEARCH_UCS),
-            focal=ctx.search(perch.SEARCH_FOCAL, w=w, anytime=True),
-            learned=ctx.search(perch.SEARCH_LEARNED, w=w, anytime=True, cnn=net, topk=topk),
-            random_init=ctx.search(perch.SEARCH_LEARNED, w=w, anytime=True, cnn=control,
-                                   topk=topk))
-        opt = res["exhaustive"]["cost"]
+        if not rows:  # first-call costs (code object load, buffers) stay out of the timings
+            ctx.search(perch.SEARCH_LEARNED, w=w, anytime=True, cnn=net, topk=topk,
+                       budget_s=budget_s)
+        run = dict(
+            exhaustive=lambda: ctx.search(perch.SEARCH_EXHAUSTIVE, budget_s=budget_s),
+            ucs=lambda: ctx.search(perch.SEARCH_UCS, budget_s=budget_s),
+            focal=lambda: ctx.search(perch.SEARCH_FOCAL, w=w, anytime=True, budget_s=budget_s),
+            learned=lambda: ctx.search(perch.SEARCH_LEARNED, w=w, anytime=True, cnn=net,
+                                       topk=topk, budget_s=budget_s),
+            random_init=lambda: ctx.search(perch.SEARCH_LEARNED, w=w, anytime=True, cnn=control,
+                                           topk=topk, budget_s=budget_s))
+        res = {k: run[k]() for k in names}
+        exact = [res[k]["cost"] for k in ("exhaustive", "ucs")
+                 if k in res and res[k]["found"] and not res[k]["budget_exhausted"]]
+        if exact:
+            best = exact[0]
+            proven += 1
+            for k, r in res.items():  # every finished search is exact
+                if r["found"] and not r["budget_exhausted"] and r["cost"] != best:
+                    raise RuntimeError(f"scene {i}: {k} returned cost {r['cost']}, optimum {best}")
+        else:
+            best = min(r["cost"] for r in res.values() if r["found"])
+        row = {}
         for k, r in res.items():
-            if not r["found"] or r["cost"] != opt:
-                raise RuntimeError(f"scene {i}: {k} returned cost {r['cost']}, optimum {opt}")
-        rows.append({k: (r["t_best_s"], r["n_evaluated_best"], r["t_total_s"], r["n_evaluated"])
-                     for k, r in res.items()})
+            hit = r["found"] and r["cost"] == best
+            row[k] = (r["t_best_s"] if hit else float("inf"),
+                      r["n_evaluated_best"] if hit else float("inf"), r["t_total_s"],
+                      r["n_evaluated"])
+        rows.append(row)
         ctx.close()
         if log:
-            log(f"gain: scene {i}: " + ", ".join(f"{k} {rows[-1][k][0] * 1e3:.1f} ms"
-                                                  for k in SEARCHES))
-    out = dict(scenes=len(rows), w=w, topk=topk)
+            log(f"gain: scene {i}: best {best}: " +
+                ", ".join(f"{k} {row[k][0] * 1e3:.1f} ms" for k in names))
+
+    def med(v):
+        m = float(np.median(v))
+        return None if not np.isfinite(m) else m
+
+    out = dict(scenes=len(rows), optimum_proven=proven, w=w, topk=topk,
+               budget_s=budget_s or None)
     for j, name in enumerate(("time_to_best_s", "evals_to_best", "time_total_s", "evals_total")):
-        out[name] = {k: float(np.median([r[k][j] for r in rows])) for k in SEARCHES}
+        out[name] = {k: med([r[k][j] for r in rows]) for k in names}
     out["learned_wins_vs"] = {k: int(sum(r["learned"][0] < r[k][0] for r in rows))
-                              for k in SEARCHES if k != "learned"}
+                              for k in names if k != "learned"}
     return out
+
+
+def search_networks(path: str, config: int, seed: int = 1):
+    """The checkpoint's network and a random-init control, both sized for the
+    learned search on the configuration's grid (one crop per pose cell, one pair
+    per (distinct mesh, pose))."""
+    cfg = scenes.CONFIGS[config]
+    g = scenes.make_grid(cfg)
+    kmax = cfg["K"][1]
+    cells, P = g.nx * g.ny, g.P
+    net = load(path, max_crops=cells, max_pairs=kmax * P)
+    ctrl = load(path, max_crops=cells, max_pairs=kmax * P)
+    ctrl.set_params(init_params(ctrl.n_mesh, seed))
+    return net, ctrl
 
 
 def main(argv: Optional[Sequence[str]] = None) -> None:
@@ -294,15 +373,18 @@ def main(argv: Optional[Sequence[str]] = None) -> None:
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--out", required=True)
     ap.add_argument("--gain", type=int, default=0, help="held-out scenes for the gain test")
+    ap.add_argument("--max-cells", type=int, default=256, help="pose cells labelled per parent")
+    ap.add_argument("--topk", type=int, default=64)
+    ap.add_argument("--budget", type=float, default=0.0, help="gain test: seconds per search")
     a = ap.parse_args(argv)
 
     def log(msg):
         print(msg, flush=True)
 
-    ds = build_dataset(range(a.scenes), a.config, log=log)
+    ds = build_dataset(range(a.scenes), a.config, log=log, max_cells=a.max_cells)
     log(f"dataset: {ds.n_scenes} scenes, {ds.n_parents} parents, {len(ds.pairs)} pairs "
         f"({ds.n_valid} valid), {ds.crops.shape[0]} crops")
-    val = build_dataset(range(a.val_first, a.val_first + a.val), a.config)
+    val = build_dataset(range(a.val_first, a.val_first + a.val), a.config, max_cells=a.max_cells)
     n_mesh = len(scenes.LIBRARIES[scenes.CONFIGS[a.config]["lib"]]["meshes"])
     mc, mp = max_block(ds, a.batch_crops)
     mc2, mp2 = max_block(val, a.batch_crops)
@@ -318,9 +400,9 @@ def main(argv: Optional[Sequence[str]] = None) -> None:
          final_loss=float(np.mean(losses[-200:])), best_in_topk=q["best_in_topk"],
          spearman=q["spearman"], train_s=t_train, pairs=len(ds.pairs))
     if a.gain:
-        ctrl = perch.Cnn(n_mesh, max_crops=max(mc, mc2), max_pairs=max(mp, mp2))
-        ctrl.set_params(init_params(n_mesh, a.seed + 1))
-        g = gain(net, ctrl, range(HELD_OUT_FIRST, HELD_OUT_FIRST + a.gain), a.config, log=log)
+        net, ctrl = search_networks(a.out, a.config, seed=a.seed + 1)
+        g = gain(net, ctrl, range(HELD_OUT_FIRST, HELD_OUT_FIRST + a.gain), a.config,
+                 topk=a.topk, budget_s=a.budget, log=log)
         log(json.dumps(g))
 
 
