@@ -31,6 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SRC = os.path.join(ROOT, "paper_1510_05613_amd", "csrc", "perch_kernels.hip")
 COUNTERS = os.path.join(ROOT, "profiles", "k_eval_640x480_counters.md")
 CHECKPOINT = os.path.join(ROOT, "paper_1510_05613_amd", "weights", "c4_cnn.npz")
+CHECKPOINT_640 = os.path.join(ROOT, "paper_1510_05613_amd", "weights", "c2_cnn.npz")
 
 
 def kernel_source_hash() -> str:
@@ -74,6 +75,8 @@ def parse_args(argv=None):
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--learned-scenes", type=int, default=20,
                     help="held-out config-4 scenes for the learned-vs-plain search leg (0 = off)")
+    ap.add_argument("--learned-640-scenes", type=int, default=0,
+                    help="held-out 640x480 scenes for a learned-vs-plain leg (minutes; 0 = off)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     return ap.parse_args(argv)
@@ -235,12 +238,26 @@ def learned_leg(n_scenes: int) -> dict:
 
     if not os.path.exists(CHECKPOINT):
         return {"skipped": "no trained checkpoint"}
-    net = learn.load(CHECKPOINT, max_crops=144, max_pairs=3 * 1152)
-    ctrl = learn.load(CHECKPOINT, max_crops=144, max_pairs=3 * 1152)
-    ctrl.set_params(learn.init_params(ctrl.n_mesh, 1))
+    net, ctrl = learn.search_networks(CHECKPOINT, 4)
     g = learn.gain(net, ctrl, range(learn.HELD_OUT_FIRST, learn.HELD_OUT_FIRST + n_scenes))
     g["workload"] = (f"config 4 (160x120, K=2, 1,152 poses/object), held-out scenes "
                      f"{learn.HELD_OUT_FIRST}..{learn.HELD_OUT_FIRST + n_scenes - 1}; medians")
+    return g
+
+
+def learned_leg_640(n_scenes: int, budget_s: float = 10.0) -> dict:
+    """The same comparison on held-out 640x480 scenes (config 2; exhaustive search
+    is out of reach there, every search gets a time budget)."""
+    from paper_1510_05613_amd import learn
+
+    if not os.path.exists(CHECKPOINT_640):
+        return {"skipped": "no trained checkpoint"}
+    net, ctrl = learn.search_networks(CHECKPOINT_640, 2)
+    first = learn.HELD_OUT_FIRST
+    g = learn.gain(net, ctrl, range(first, first + 2 * n_scenes), config=2, topk=256,
+                   budget_s=budget_s, max_scenes=n_scenes)
+    g["workload"] = (f"config 2 (640x480, K=3, 40,000 poses/object), the first {n_scenes} "
+                     f"held-out scenes from {first}; medians, {budget_s:.0f} s per search")
     return g
 
 
@@ -354,6 +371,8 @@ def main(argv=None):
     }
     if args.learned_scenes > 0 and args.config == 2:
         out["learned"] = learned_leg(args.learned_scenes)
+    if args.learned_640_scenes > 0 and args.config == 2:
+        out["learned_640x480"] = learned_leg_640(args.learned_640_scenes)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, work)
     print(json.dumps(out), flush=True)

@@ -281,19 +281,23 @@ SEARCHES = ("exhaustive", "ucs", "focal", "learned", "random_init")
 
 
 def gain(net: "perch.Cnn", control: "perch.Cnn", indices: Sequence[int], config: int = 4,
-         w: float = 3.0, topk: int = 64, budget_s: float = 0.0, log=None) -> dict:
+         w: float = 3.0, topk: int = 64, budget_s: float = 0.0, log=None,
+         max_scenes: int = 0) -> dict:
     """Time (and successor evaluations) until each search first holds the best
     scene, on held-out scenes.  exhaustive (small trees only) and ucs are the plain
     searches; focal is the paper's inadmissible depth heuristic without learning;
     learned and random_init are the learned search with the trained and an
     untrained network.  The best scene is the optimum returned by a plain search
     that finished; a search that never held it counts as not reaching it (None).
-    budget_s > 0 limits every search."""
+    budget_s > 0 limits every search; max_scenes > 0 stops after that many scenes
+    (indices the generator cannot satisfy are skipped)."""
     lib = scenes.make_library(scenes.CONFIGS[config]["lib"])
     render = perch.GpuRenderer()
     names = [k for k in SEARCHES if k != "exhaustive" or config in (1, 4)]
     rows, proven = [], 0
     for i in indices:
+        if max_scenes and len(rows) >= max_scenes:
+            break
         if i < HELD_OUT_FIRST:
             raise ValueError(f"scene {i} is a training scene")
         sc = try_scene(config, int(i), render, lib)
