@@ -805,45 +805,82 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
     __syncthreads();
     if (s_acc[5]) break;
 
-    // ---- dJ_r: new points unexplained by the observed cloud ----
-    // Window mode: the observed point at the same pixel usually decides
-    // "explained"; the dilated depth range decides most "unexplained"; the rest
-    // are scanned over their exact pixel window by the whole wave at once.
-    // Hash mode: range query of the voxel hash.
+    // ---- dJ_r, dJ_o and U: one pass over the core rows ----
+    // Per pixel: the new point q (dR, from the tile) and the observed point p; the
+    // same-pixel test settles most points either way.  dJ_r: an unsettled q is
+    // unexplained when the dilated observed depth range rules every window pixel
+    // out, otherwise the whole wave scans its exact window, two points at a time.
+    // dJ_o / U: p needs the dR window when it lies in V(O) or in U; each lane walks
+    // its own window of the LDS tile with a depth pre-test.  Hash mode: dJ_r by a
+    // range query of the voxel hash.
     {
-      const int k0 = (b0 - t0) * tw, k1 = (b1 - t0 + 1) * tw;
-      for (int base = k0; base < k1; base += NT) {
+      const int nk = (b1 - b0 + 1) * tw;
+      const int kt = (b0 - t0) * tw;  // tile index of the first core pixel
+      const float inv_tw = __builtin_amdgcn_rcpf((float)tw);
+      for (int base = 0; base < nk; base += NT) {
         const int k = base + tid;
-        int state = 0;  // 1 explained, 2 unexplained, 3 undecided
-        float3 q = make_float3(0.0f, 0.0f, 0.0f);
-        int qi = 0, qj = 0;
-        if (k < k1) {
-          const unsigned key = tile[k];
-          if (key != kInfBits) {
-            qi = ca + k % tw;
-            qj = t0 + k / tw;
-            q = backproject(cam, qi, qj, __uint_as_float(key));
+        int state = 0;  // dJ_r: 1 explained, 2 unexplained, 3 undecided
+        bool inV = false, inU = false, expl = false;
+        float zq = 0.0f;
+        int ii = 0, jj = 0;
+        if (k < nk) {
+          // k / tw for k < 2^21: (k + 1/2) / tw is at least 1 / (2 tw) from an integer
+          const int r = (int)(((float)k + 0.5f) * inv_tw);
+          ii = ca + (k - r * tw);
+          jj = b0 + r;
+          const unsigned key = tile[kt + k];
+          const int pix = jj * W + ii;
+          const float zo = obs[pix];
+          const bool hq = key != kInfBits, hp = zo > 0.0f;
+          zq = __uint_as_float(key);
+          // the same arithmetic as the window scans and the voxel hash, so that
+          // every radius mode takes identical decisions
+          const float3 q = backproject(cam, ii, jj, zq);
+          const float3 p = backproject(cam, ii, jj, zo);
+          const float ex = q.x - p.x, ey = q.y - p.y, ez = q.z - p.z;
+          const bool same = hq && hp && ex * ex + ey * ey + ez * ez <= delta2;
+          if (hq) {
             if (ep.radius_mode == 1) {
               state = explained_by_cloud(hs, q.x, q.y, q.z, delta2) ? 1 : 2;
+            } else if (same) {
+              state = 1;
             } else {
-              const int pix = qj * W + qi;
-              const float zo = obs[pix];
-              bool expl = false;
-              if (zo > 0.0f) {
-                const float3 p = backproject(cam, qi, qj, zo);
-                const float dx = p.x - q.x, dy = p.y - q.y, dz = p.z - q.z;
-                expl = dx * dx + dy * dy + dz * dz <= delta2;
-              }
-              if (expl) {
-                state = 1;
-              } else {
-                const float2 zr = obs_range[pix];
-                state = (q.z + ep.dwin < zr.x || q.z - ep.dwin > zr.y) ? 2 : 3;
+              const float2 zr = obs_range[pix];
+              state = (zq + ep.dwin < zr.x || zq - ep.dwin > zr.y) ? 2 : 3;
+            }
+          }
+          if (hp) {
+            inV = in_volume_at(vlo, vhi, vplanes, fr.y, apply_obj_map(om, p));
+            inU = par.goal && ((par.ubits[pix >> 5] >> (pix & 31)) & 1u);
+            expl = same;
+            if ((inV || inU) && !expl) {
+              int ru, rv;
+              window_radius(cam, ep, p, ru, rv);
+              const int wja = max(t0, jj - rv), wjb = min(t1, jj + rv);
+              const int wia = max(ca, ii - ru), wib = min(cb, ii + ru);
+              const float zlo = zo - cam.delta, zhi = zo + cam.delta;
+              // one flat walk over the clipped window, stopping at the first hit
+              const int n = (wib - wia + 1) * (wjb - wja + 1);
+              int iq = wia, jq = wja;
+              int row = (wja - t0) * tw - ca;  // tile index of (0, jq)
+              for (int w = 0; w < n && !expl; ++w) {
+                const float zt = __uint_as_float(tile[row + iq]);
+                if (zt >= zlo && zt <= zhi) {  // also skips +inf (no point)
+                  const float3 q = backproject(cam, iq, jq, zt);
+                  const float ex = q.x - p.x, ey = q.y - p.y, ez = q.z - p.z;
+                  expl = ex * ex + ey * ey + ez * ez <= delta2;
+                }
+                const bool wrap = iq == wib;
+                row += wrap ? tw : 0;
+                jq += wrap ? 1 : 0;
+                iq = wrap ? wia : iq + 1;
               }
             }
           }
         }
         n_dJr += ballot_count(state == 2);
+        n_dJo += ballot_count(inV && !expl);
+        n_rem += ballot_count(inU && (inV || expl));
         unsigned long long und = __ballot(state == 3);
         // wave-uniform: two undecided points at a time, each lane testing one pixel
         // of either window per step, so two observed-depth loads are in flight
@@ -853,12 +890,10 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
           const bool two = und != 0ull;
           const int sb = two ? __ffsll((long long)und) - 1 : sa;
           if (two) und &= und - 1;
-          const int ai = __shfl(qi, sa, 64), aj = __shfl(qj, sa, 64);
-          const int bi = __shfl(qi, sb, 64), bj = __shfl(qj, sb, 64);
-          const float3 aq = make_float3(__shfl(q.x, sa, 64), __shfl(q.y, sa, 64),
-                                        __shfl(q.z, sa, 64));
-          const float3 bq = make_float3(__shfl(q.x, sb, 64), __shfl(q.y, sb, 64),
-                                        __shfl(q.z, sb, 64));
+          const int ai = __shfl(ii, sa, 64), aj = __shfl(jj, sa, 64);
+          const int bi = __shfl(ii, sb, 64), bj = __shfl(jj, sb, 64);
+          const float3 aq = backproject(cam, ai, aj, __shfl(zq, sa, 64));
+          const float3 bq = backproject(cam, bi, bj, __shfl(zq, sb, 64));
           int aru, arv, bru, brv;
           window_radius(cam, ep, aq, aru, arv);
           window_radius(cam, ep, bq, bru, brv);
@@ -900,64 +935,6 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
           }
           n_dJr += (ahit ? 0 : 1) + (bhit ? 0 : 1);
         }
-      }
-    }
-
-    // ---- dJ_o and U: observed points of the core rows ----
-    // A point needs the dR window when it lies in V(O) (dJ_o) or in U (residual);
-    // the new point at its own pixel decides most of them, the rest scan their
-    // exact window with a depth pre-test.
-    {
-      const int nk = (b1 - b0 + 1) * tw;
-      for (int base = 0; base < nk; base += NT) {
-        const int k = base + tid;
-        bool cnt_o = false, cnt_rem = false;
-        if (k < nk) {
-          const int jj = b0 + k / tw, ii = ca + k % tw;
-          const int pix = jj * W + ii;
-          const float z = obs[pix];
-          if (z > 0.0f) {
-            const float3 p = backproject(cam, ii, jj, z);
-            const bool inV = in_volume_at(vlo, vhi, vplanes, fr.y, apply_obj_map(om, p));
-            const bool inU = par.goal && ((par.ubits[pix >> 5] >> (pix & 31)) & 1u);
-            bool expl = false;
-            if (inV || inU) {
-              const unsigned k0 = tile[(jj - t0) * tw + (ii - ca)];
-              if (k0 != kInfBits) {
-                const float3 q = backproject(cam, ii, jj, __uint_as_float(k0));
-                const float dx = q.x - p.x, dy = q.y - p.y, dz = q.z - p.z;
-                expl = dx * dx + dy * dy + dz * dz <= delta2;
-              }
-              if (!expl) {
-                int ru, rv;
-                window_radius(cam, ep, p, ru, rv);
-                const int ja = max(t0, jj - rv), jb = min(t1, jj + rv);
-                const int ia = max(ca, ii - ru), ib = min(cb, ii + ru);
-                const float zlo = z - cam.delta, zhi = z + cam.delta;
-                // one flat walk over the clipped window, stopping at the first hit
-                const int n = (ib - ia + 1) * (jb - ja + 1);
-                int iq = ia, jq = ja;
-                int row = (ja - t0) * tw - ca;  // tile index of (0, jq)
-                for (int w = 0; w < n && !expl; ++w) {
-                  const float zq = __uint_as_float(tile[row + iq]);
-                  if (zq >= zlo && zq <= zhi) {  // also skips +inf (no point)
-                    const float3 q = backproject(cam, iq, jq, zq);
-                    const float dx = q.x - p.x, dy = q.y - p.y, dz = q.z - p.z;
-                    expl = dx * dx + dy * dy + dz * dz <= delta2;
-                  }
-                  const bool wrap = iq == ib;
-                  row += wrap ? tw : 0;
-                  jq += wrap ? 1 : 0;
-                  iq = wrap ? ia : iq + 1;
-                }
-              }
-            }
-            cnt_o = inV && !expl;
-            cnt_rem = inU && (inV || expl);
-          }
-        }
-        n_dJo += ballot_count(cnt_o);
-        n_rem += ballot_count(cnt_rem);
       }
     }
     __syncthreads();  // the next band overwrites the tile
