@@ -781,8 +781,10 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
     {
       int sl = 0, dr = 0;
       bool occ = false;
+      const float inv_tw = __builtin_amdgcn_rcpf((float)tw);
       for (int k = tid; k < tn; k += NT) {
-        const int jj = t0 + k / tw, ii = ca + k % tw;
+        const int r = (int)(((float)k + 0.5f) * inv_tw);  // k / tw, exact for k < 2^21
+        const int jj = t0 + r, ii = ca + (k - r * tw);
         const unsigned key = tile[k];
         const bool cov = key != kInfBits;
         const unsigned pk = par.has_parent ? par.depth[jj * W + ii] : kInfBits;
