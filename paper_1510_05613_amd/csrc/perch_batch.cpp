@@ -153,6 +153,7 @@ perch_status perch_batch_set_parents(perch_batch* b, const perch_parent* parents
     sd[k] = b->ctxs[k]->scene_dev();
     sd[k].ep.tile_px = b->tile();
     sd[k].ep.max_nv = max_nv;
+    sd[k].ep.vpack = vertex_cache_packed(max_nv);
   }
   HIP_TRY(hipMemcpyAsync(b->parents.p, pd.data(), sizeof(ParentDev) * pd.size(),
                          hipMemcpyHostToDevice, b->stream));
@@ -178,16 +179,16 @@ perch_status perch_batch_eval(perch_batch* b, const perch_work* items_dev, int32
     int dev = 0, cus = 0, per_cu = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    HIP_TRY(prepare_eval_batch(b->threads, lds, &per_cu));
+    HIP_TRY(prepare_eval_batch(b->threads, vertex_cache_packed(b->max_nv()), lds, &per_cu));
     if (grid <= 0) grid = std::max(1, cus * std::max(1, per_cu));
   }
   const int4* items = reinterpret_cast<const int4*>(items_dev);
   const SceneDev* scenes = b->scenes.as<SceneDev>();
   const ParentDev* parents = b->parents.as<ParentDev>();
   if (!b->use_graph) {
-    HIP_TRY(launch_eval_batch(b->threads, scenes, parents, b->n_parents, items, n,
-                              b->counter.as<int>(), cost_dev, status_dev, comps_dev, lds, grid,
-                              b->stream));
+    HIP_TRY(launch_eval_batch(b->threads, vertex_cache_packed(b->max_nv()), scenes, parents,
+                              b->n_parents, items, n, b->counter.as<int>(), cost_dev,
+                              status_dev, comps_dev, lds, grid, b->stream));
     return PERCH_OK;
   }
   const bool same = b->exec && b->g_items == items_dev && b->g_n == n && b->g_cost == cost_dev &&
@@ -197,9 +198,9 @@ perch_status perch_batch_eval(perch_batch* b, const perch_work* items_dev, int32
   if (!same) {
     b->drop_graph();
     HIP_TRY(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
-    hipError_t e = launch_eval_batch(b->threads, scenes, parents, b->n_parents, items, n,
-                                     b->counter.as<int>(), cost_dev, status_dev, comps_dev, lds,
-                                     grid, b->capture);
+    hipError_t e = launch_eval_batch(b->threads, vertex_cache_packed(b->max_nv()), scenes,
+                                     parents, b->n_parents, items, n, b->counter.as<int>(),
+                                     cost_dev, status_dev, comps_dev, lds, grid, b->capture);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(b->capture, &g);
     if (e != hipSuccess || e2 != hipSuccess) {

@@ -92,10 +92,17 @@ perch_status cnn_predict_on(perch_cnn* c, const uint16_t* crops, int n_crops, co
   } while (0)
 
 
+// Meshes of up to this many vertices keep full int2 snapped vertices in LDS; the
+// vertex cache of larger ones is packed into 16 + 16 bits relative to the
+// footprint (half the LDS, a second pass over the vertices).
+constexpr int kInt2CacheMaxVerts = 5120;
+inline int vertex_cache_packed(int max_nv) { return max_nv > kInt2CacheMaxVerts ? 1 : 0; }
+
 // Dynamic LDS of the successor kernel: the snapped-vertex cache, the z-tile and
 // one 128-entry triangle queue per wave.
 inline size_t eval_lds_bytes(int max_nv, int tile_px, int threads) {
-  return (size_t)max_nv * sizeof(int2) + (size_t)tile_px * sizeof(unsigned) +
+  const size_t vb = vertex_cache_packed(max_nv) ? sizeof(unsigned) : 2 * sizeof(int);
+  return (size_t)max_nv * vb + (size_t)tile_px * sizeof(unsigned) +
          (size_t)(threads / 64) * 128 * sizeof(unsigned);
 }
 
@@ -180,6 +187,7 @@ struct perch_ctx {
     S.ep = ep;
     S.ep.tile_px = tile();
     S.ep.max_nv = max_nv;
+    S.ep.vpack = vertex_cache_packed(max_nv);
     S.ep.n_mesh = (int)meshes.size();
     S.ep.n_poses = P;
     S.ep.radius_mode = radius_mode;

@@ -62,6 +62,7 @@ struct EvalParams {
   int n_mesh;   // candidates with mesh_id outside [0, n_mesh) or pose_idx outside
   int n_poses;  // [0, n_poses) are rejected with status -4
   int radius_mode;  // dJ_r query: 0 exact pixel window, 1 voxel hash
+  int vpack;        // vertex cache: 0 int2 per vertex, 1 packed 16 + 16 bits (large meshes)
 };
 
 // Everything a successor evaluation reads about one scene.
@@ -108,9 +109,10 @@ hipError_t launch_eval(int threads, const SceneDev& S, const Parent& par, const 
                        hipStream_t s);
 // Raises the kernel's LDS limit and reports resident workgroups per CU (call
 // before launch_eval_batch, outside any graph capture).
-hipError_t prepare_eval_batch(int threads, size_t lds_bytes, int* blocks_per_cu);
+hipError_t prepare_eval_batch(int threads, int vpack, size_t lds_bytes, int* blocks_per_cu);
 // grid = number of persistent workgroups (clamped to n)
-hipError_t launch_eval_batch(int threads, const SceneDev* scenes, const ParentDev* parents,
+hipError_t launch_eval_batch(int threads, int vpack, const SceneDev* scenes,
+                             const ParentDev* parents,
                              int n_parents, const int4* items, int n, int* counter, int* cost,
                              int* status, int* comps, size_t lds_bytes, int grid, hipStream_t s);
 

@@ -88,6 +88,17 @@ __device__ __forceinline__ bool vsnap(const Cam& c, float X, float Y, float Z, i
   return ok;
 }
 
+// The snapped vertex of vcam + vsnap, out of line: the persistent batch kernel
+// calls it only for footprints too wide for its packed vertex cache (inlined
+// there, the rare path costs registers the whole kernel pays for).
+__device__ __noinline__ int2 snapped_vertex(const Cam& c, const float4 pz, const float4 m) {
+  float X, Y, Z;
+  vcam(c, pz, m, X, Y, Z);
+  int U, V;
+  vsnap(c, X, Y, Z, U, V);
+  return make_int2(U, V);
+}
+
 // ---------------------------------------------------------------------------
 // depth: FP64 plane of the triangle's float32 camera-space vertices
 // ---------------------------------------------------------------------------
@@ -621,7 +632,7 @@ __global__ void k_parent_u(Cam cam, Meshes M, const float4* poses, const float* 
 // Evaluates successor s' = parent + (cd.x = mesh, cd.y = pose) of scene S and
 // writes output slot s.  Every thread of the workgroup calls it with the same
 // arguments; it synchronises the workgroup internally.
-template <int NT>
+template <int NT, bool OUTLINE, bool VP>
 __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& par, const int2 cd,
                                                const int s, int* __restrict__ out_cost,
                                                int* __restrict__ out_status,
@@ -650,8 +661,13 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
   const float4 pz = poses[cd.y];
   const ObjMap om = make_obj_map(cam, pz);
   const int4 rg = M.range[mesh];
-  int2* suv = reinterpret_cast<int2*>(smem);
-  unsigned* tile = reinterpret_cast<unsigned*>(smem + (size_t)ep.max_nv * sizeof(int2));
+  // snapped vertices: int2 (ep.vpack = 0) or relative to the footprint's corner in
+  // 16 + 16 bits (ep.vpack = 1, meshes too large for int2)
+  constexpr bool vpack = VP;  // the host picks the instantiation from ep.vpack
+  int2* suv2 = reinterpret_cast<int2*>(smem);
+  unsigned* suv = reinterpret_cast<unsigned*>(smem);
+  unsigned* tile = reinterpret_cast<unsigned*>(
+      smem + (size_t)ep.max_nv * (vpack ? sizeof(unsigned) : sizeof(int2)));
   unsigned* ring = tile + ep.tile_px + (tid >> 6) * 128;  // this wave's triangle queue
   if (tid < 4) s_bb[tid] = tid < 2 ? INT_MAX : INT_MIN;
   if (tid < 8) s_acc[tid] = 0;
@@ -664,7 +680,13 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
   const float4* vplanes = pl_lds ? s_pl : M.planes + fr.x;
   __syncthreads();
 
-  // ---- vertex stage into LDS, footprint bounding box ----
+  // ---- vertex stage: footprint bounding box, then the vertex cache ----
+  // int2 cache: written directly.  Packed cache: the snapped vertices wait in the
+  // z-tile's LDS (free until the first band) when they fit there, so packing them
+  // needs no second vertex stage.
+  int2* stage = vpack ? reinterpret_cast<int2*>(tile) : suv2;
+  const bool staged =
+      !vpack || (size_t)rg.y * sizeof(int2) <= (size_t)ep.tile_px * sizeof(unsigned);
   {
     int xmn = INT_MAX, ymn = INT_MAX, xmx = INT_MIN, ymx = INT_MIN;
     bool bad = false;
@@ -673,7 +695,7 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
       vcam(cam, pz, M.verts[rg.x + v], X, Y, Z);
       int U, V;
       bad |= !vsnap(cam, X, Y, Z, U, V);
-      suv[v] = make_int2(U, V);
+      if (staged) stage[v] = make_int2(U, V);
       xmn = min(xmn, U);
       ymn = min(ymn, V);
       xmx = max(xmx, U);
@@ -702,6 +724,39 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
     }
     return;
   }
+  // Packed cache: a footprint under 256 x 256 pixels packs its snapped vertices
+  // into 32 bits each (from the staged copy, or from the same vertex stage again,
+  // so the values are identical); a larger one is rasterised from vertices
+  // recomputed where they are needed.
+  const int ox = s_bb[0], oy = s_bb[1];
+  const bool packed = vpack && s_bb[2] - ox < 65536 && s_bb[3] - oy < 65536;
+  if (packed) {
+    for (int v = tid; v < rg.y; v += NT) {
+      int2 uv;
+      if (staged) {
+        uv = stage[v];
+      } else {
+        float X, Y, Z;
+        vcam(cam, pz, M.verts[rg.x + v], X, Y, Z);
+        vsnap(cam, X, Y, Z, uv.x, uv.y);
+      }
+      suv[v] = (unsigned)(uv.x - ox) | ((unsigned)(uv.y - oy) << 16);
+    }
+    __syncthreads();  // the staged copy is read before the first band clears the tile
+  }
+  auto vert_uv = [&](int idx) -> int2 {
+    if (!vpack) return suv2[idx];
+    if (packed) {
+      const unsigned w = suv[idx];
+      return make_int2(ox + (int)(w & 0xFFFFu), oy + (int)(w >> 16));
+    }
+    if (OUTLINE) return snapped_vertex(cam, pz, M.verts[rg.x + idx]);
+    float X, Y, Z;
+    vcam(cam, pz, M.verts[rg.x + idx], X, Y, Z);
+    int U, V;
+    vsnap(cam, X, Y, Z, U, V);
+    return make_int2(U, V);
+  };
 
   // observed region: the vertex box (+1 px: every point of V(O) projects inside it),
   // grown by the window halo at the goal level (points of U explained by dR)
@@ -744,7 +799,7 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
         const int4 tr = M.tris[rg.z + t];
         const float4 v0 = M.verts[rg.x + tr.x], v1 = M.verts[rg.x + tr.y];
         const float4 v2 = M.verts[rg.x + tr.z];
-        const int2 a = suv[tr.x], b = suv[tr.y], c = suv[tr.z];
+        const int2 a = vert_uv(tr.x), b = vert_uv(tr.y), c = vert_uv(tr.z);
         float X0, Y0, Z0, X1, Y1, Z1, X2, Y2, Z2;
         map_vertex(pm, v0, X0, Y0, Z0);
         map_vertex(pm, v1, X1, Y1, Z1);
@@ -760,7 +815,7 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
         bool keep = false;
         if (t < rg.w) {
           const int4 tr = M.tris[rg.z + t];
-          const int2 a = suv[tr.x], b = suv[tr.y], c = suv[tr.z];
+          const int2 a = vert_uv(tr.x), b = vert_uv(tr.y), c = vert_uv(tr.z);
           keep = tri_candidate(a.x, a.y, b.x, b.y, c.x, c.y, ca, cb, t0, t1);
         }
         const unsigned long long m = __ballot(keep);
@@ -964,7 +1019,7 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
 }
 
 // One workgroup per successor of one parent.
-template <int NT>
+template <int NT, bool VP>
 __global__ void __launch_bounds__(NT)
     k_eval(SceneDev S, Parent par, const int2* __restrict__ cands, int n,
            int* __restrict__ out_cost, int* __restrict__ out_status, int* __restrict__ out_comps) {
@@ -974,14 +1029,14 @@ __global__ void __launch_bounds__(NT)
   __shared__ float4 s_pl[kLdsPlanes];
   const int s = blockIdx.x;
   if (s >= n) return;
-  eval_successor<NT>(S, par, cands[s], s, out_cost, out_status, out_comps, smem, s_bb, s_acc,
-                     s_pl);
+  eval_successor<NT, false, VP>(S, par, cands[s], s, out_cost, out_status, out_comps, smem,
+                                s_bb, s_acc, s_pl);
 }
 
 // Persistent workgroups over a work queue of (parent slot, mesh, pose) items that
 // may belong to different scenes: each workgroup takes the next item from an
 // atomic counter until the queue is empty, so uneven meshes balance across CUs.
-template <int NT>
+template <int NT, bool VP>
 __global__ void __launch_bounds__(NT, 4)  // at least 4 waves per SIMD: <= 128 VGPRs
     k_eval_batch(const SceneDev* __restrict__ scenes, const ParentDev* __restrict__ parents,
                  int n_parents, const int4* __restrict__ items, int n, int* counter,
@@ -1017,8 +1072,8 @@ __global__ void __launch_bounds__(NT, 4)  // at least 4 waves per SIMD: <= 128 V
     par.has_parent = pd.has_parent;
     par.goal = pd.goal;
     const int scene = __builtin_amdgcn_readfirstlane(pd.scene);
-    eval_successor<NT>(scenes[scene], par, make_int2(w.y, w.z), it, out_cost, out_status,
-                       out_comps, smem, s_bb, s_acc, s_pl);
+    eval_successor<NT, true, VP>(scenes[scene], par, make_int2(w.y, w.z), it, out_cost,
+                                 out_status, out_comps, smem, s_bb, s_acc, s_pl);
   }
 }
 
@@ -1082,85 +1137,112 @@ static hipError_t allow_lds(K kernel, size_t lds) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-template <int NT>
+template <int NT, bool VP>
 static hipError_t launch_eval_t(const SceneDev& S, const Parent& par, const int2* cands, int n,
                                 int* cost, int* status, int* comps, size_t lds, hipStream_t s) {
-  hipError_t e = allow_lds(&k_eval<NT>, lds);
+  hipError_t e = allow_lds(&k_eval<NT, VP>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_eval<NT>, dim3(n), dim3(NT), lds, s, S, par, cands, n, cost, status,
+  hipLaunchKernelGGL((k_eval<NT, VP>), dim3(n), dim3(NT), lds, s, S, par, cands, n, cost, status,
                      comps);
   return hipGetLastError();
+}
+
+template <bool VP>
+static hipError_t launch_eval_vp(int threads, const SceneDev& S, const Parent& par,
+                                 const int2* cands, int n, int* cost, int* status, int* comps,
+                                 size_t lds, hipStream_t s) {
+  switch (threads) {
+    case 64:
+      return launch_eval_t<64, VP>(S, par, cands, n, cost, status, comps, lds, s);
+    case 128:
+      return launch_eval_t<128, VP>(S, par, cands, n, cost, status, comps, lds, s);
+    case 512:
+      return launch_eval_t<512, VP>(S, par, cands, n, cost, status, comps, lds, s);
+    case 1024:
+      return launch_eval_t<1024, VP>(S, par, cands, n, cost, status, comps, lds, s);
+    default:
+      return launch_eval_t<256, VP>(S, par, cands, n, cost, status, comps, lds, s);
+  }
 }
 
 hipError_t launch_eval(int threads, const SceneDev& S, const Parent& par, const int2* cands,
                        int n, int* cost, int* status, int* comps, size_t lds_bytes,
                        hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  switch (threads) {
-    case 64:
-      return launch_eval_t<64>(S, par, cands, n, cost, status, comps, lds_bytes, s);
-    case 128:
-      return launch_eval_t<128>(S, par, cands, n, cost, status, comps, lds_bytes, s);
-    case 512:
-      return launch_eval_t<512>(S, par, cands, n, cost, status, comps, lds_bytes, s);
-    case 1024:
-      return launch_eval_t<1024>(S, par, cands, n, cost, status, comps, lds_bytes, s);
-    default:
-      return launch_eval_t<256>(S, par, cands, n, cost, status, comps, lds_bytes, s);
-  }
+  return S.ep.vpack ? launch_eval_vp<true>(threads, S, par, cands, n, cost, status, comps,
+                                           lds_bytes, s)
+                    : launch_eval_vp<false>(threads, S, par, cands, n, cost, status, comps,
+                                            lds_bytes, s);
 }
 
-template <int NT>
+template <int NT, bool VP>
 static hipError_t prepare_eval_batch_t(size_t lds, int* per_cu) {
-  hipError_t e = allow_lds(&k_eval_batch<NT>, lds);
+  hipError_t e = allow_lds(&k_eval_batch<NT, VP>, lds);
   if (e != hipSuccess) return e;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_eval_batch<NT>, NT, lds);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_eval_batch<NT, VP>, NT, lds);
 }
 
-hipError_t prepare_eval_batch(int threads, size_t lds_bytes, int* blocks_per_cu) {
+template <bool VP>
+static hipError_t prepare_eval_batch_vp(int threads, size_t lds, int* per_cu) {
   switch (threads) {
     case 64:
-      return prepare_eval_batch_t<64>(lds_bytes, blocks_per_cu);
+      return prepare_eval_batch_t<64, VP>(lds, per_cu);
     case 128:
-      return prepare_eval_batch_t<128>(lds_bytes, blocks_per_cu);
+      return prepare_eval_batch_t<128, VP>(lds, per_cu);
     case 512:
-      return prepare_eval_batch_t<512>(lds_bytes, blocks_per_cu);
+      return prepare_eval_batch_t<512, VP>(lds, per_cu);
     default:
-      return prepare_eval_batch_t<256>(lds_bytes, blocks_per_cu);
+      return prepare_eval_batch_t<256, VP>(lds, per_cu);
   }
 }
 
-template <int NT>
+hipError_t prepare_eval_batch(int threads, int vpack, size_t lds_bytes, int* blocks_per_cu) {
+  return vpack ? prepare_eval_batch_vp<true>(threads, lds_bytes, blocks_per_cu)
+               : prepare_eval_batch_vp<false>(threads, lds_bytes, blocks_per_cu);
+}
+
+template <int NT, bool VP>
 static hipError_t launch_eval_batch_t(const SceneDev* scenes, const ParentDev* parents,
                                       int n_parents, const int4* items, int n, int* counter,
                                       int* cost, int* status, int* comps, size_t lds, int grid,
                                       hipStream_t s) {
   grid = std::max(1, std::min(grid, n));
-  hipLaunchKernelGGL(k_eval_batch<NT>, dim3(grid), dim3(NT), lds, s, scenes, parents, n_parents,
-                     items, n, counter, cost, status, comps);
+  hipLaunchKernelGGL((k_eval_batch<NT, VP>), dim3(grid), dim3(NT), lds, s, scenes, parents,
+                     n_parents, items, n, counter, cost, status, comps);
   return hipGetLastError();
 }
 
-hipError_t launch_eval_batch(int threads, const SceneDev* scenes, const ParentDev* parents,
-                             int n_parents, const int4* items, int n, int* counter, int* cost,
-                             int* status, int* comps, size_t lds_bytes, int grid,
-                             hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  launch_fill_i32(counter, 0, 1, s);  // a fill kernel (not a memset): safe in captured graphs
+template <bool VP>
+static hipError_t launch_eval_batch_vp(int threads, const SceneDev* scenes,
+                                       const ParentDev* parents, int n_parents, const int4* items,
+                                       int n, int* counter, int* cost, int* status, int* comps,
+                                       size_t lds, int grid, hipStream_t s) {
   switch (threads) {
     case 64:
-      return launch_eval_batch_t<64>(scenes, parents, n_parents, items, n, counter, cost, status,
-                                     comps, lds_bytes, grid, s);
+      return launch_eval_batch_t<64, VP>(scenes, parents, n_parents, items, n, counter, cost,
+                                         status, comps, lds, grid, s);
     case 128:
-      return launch_eval_batch_t<128>(scenes, parents, n_parents, items, n, counter, cost,
-                                      status, comps, lds_bytes, grid, s);
+      return launch_eval_batch_t<128, VP>(scenes, parents, n_parents, items, n, counter, cost,
+                                          status, comps, lds, grid, s);
     case 512:
-      return launch_eval_batch_t<512>(scenes, parents, n_parents, items, n, counter, cost,
-                                      status, comps, lds_bytes, grid, s);
+      return launch_eval_batch_t<512, VP>(scenes, parents, n_parents, items, n, counter, cost,
+                                          status, comps, lds, grid, s);
     default:
-      return launch_eval_batch_t<256>(scenes, parents, n_parents, items, n, counter, cost,
-                                      status, comps, lds_bytes, grid, s);
+      return launch_eval_batch_t<256, VP>(scenes, parents, n_parents, items, n, counter, cost,
+                                          status, comps, lds, grid, s);
   }
+}
+
+hipError_t launch_eval_batch(int threads, int vpack, const SceneDev* scenes,
+                             const ParentDev* parents, int n_parents, const int4* items, int n,
+                             int* counter, int* cost, int* status, int* comps, size_t lds_bytes,
+                             int grid, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  launch_fill_i32(counter, 0, 1, s);  // a fill kernel (not a memset): safe in captured graphs
+  return vpack ? launch_eval_batch_vp<true>(threads, scenes, parents, n_parents, items, n,
+                                            counter, cost, status, comps, lds_bytes, grid, s)
+               : launch_eval_batch_vp<false>(threads, scenes, parents, n_parents, items, n,
+                                             counter, cost, status, comps, lds_bytes, grid, s);
 }
 
 }  // namespace perch

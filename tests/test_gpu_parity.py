@@ -246,3 +246,50 @@ def test_full_config_levels_sampled(c5):
         r = o.eval([p[0] for p in par], [p[1] for p in par], ms[idx], ps[idx])
         s = compare(tuple(a[idx] for a in g), r, f"c5 level {level + 1}")
         assert s["valid"] > 0
+
+
+@pytest.mark.parametrize("large_library", [False, True])
+def test_footprints_wider_than_256_pixels(c2, large_library):
+    """A 0.8 m box seen at 640x480 spans more than 256 pixels.  With a library of
+    small meshes the kernel caches int2 vertices; with a 20,000-triangle mesh in
+    the library it packs them into 16 + 16 bits, which cannot hold this footprint,
+    and recomputes vertices where it needs them.  Root and one-object parents
+    against the oracle, per-parent and batched launches alike."""
+    import dataclasses
+
+    sc, _, _ = c2
+    big = scenes.make_box((0.8, 0.6, 0.3), 600)
+    extra = [H.c3_library().meshes[-1]] if large_library else []
+    lib = scenes.Library(list(sc.library.meshes) + extra + [big])
+    m_big = len(lib.meshes) - 1
+    sc2 = dataclasses.replace(sc, library=lib,
+                              obj_mesh=np.array([m_big, int(sc.obj_mesh[0])], np.int32))
+    o = Oracle.from_scene(sc2, nthreads=8)
+    ctx = perch.context_from_scene(sc2)
+    g = sc2.grid
+    centre = [g.index(g.nx // 2 + dx, g.ny // 2 + dy, k) for dx in (-2, 0, 2)
+              for dy in (-2, 0, 2) for k in (0, 3, 5)]
+    pd = o.render_objects([m_big], [centre[4]])[0]
+    cols = np.nonzero(np.isfinite(pd).any(0))[0]
+    assert cols.max() - cols.min() > 256  # the case under test
+    rng = np.random.default_rng(4)
+    for par in ([], [(int(sc.obj_mesh[0]), int(sc.gt_pose[0]))]):
+        ps = np.concatenate([centre, rng.choice(g.P, 40, replace=False)])
+        ms = np.full(len(ps), m_big)
+        gres = _gpu_eval(ctx, par, ms, ps)
+        r = o.eval([p[0] for p in par], [p[1] for p in par], ms, ps)
+        s = compare(gres, r, f"big box, parent {par}")
+        assert s["valid"] > 0
+        # the persistent batch kernel takes its own (out-of-line) path for them
+        b = perch.Batch([ctx])
+        b.set_parents([(0, par)])
+        items = np.zeros((len(ps), 4), np.int32)
+        items[:, 1], items[:, 2] = ms, ps
+        n = len(ps)
+        bc = torch.empty(n, dtype=torch.int32, device="cuda")
+        bs = torch.empty(n, dtype=torch.int32, device="cuda")
+        bp = torch.empty((n, 5), dtype=torch.int32, device="cuda")
+        b.eval(torch.as_tensor(items).cuda(), bc, bs, bp)
+        torch.cuda.synchronize()
+        for a, g2 in zip(gres, (bs.cpu().numpy(), bc.cpu().numpy(), bp.cpu().numpy())):
+            assert np.array_equal(a, g2)
