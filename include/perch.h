@@ -130,6 +130,16 @@ perch_status perch_set_parent(perch_ctx* ctx, const perch_object* parent, int32_
 perch_status perch_eval_children(perch_ctx* ctx, const perch_object* cands_dev, int32_t n,
                                  int32_t* cost_dev, int32_t* status_dev, int32_t* comps_dev);
 
+/* The paper's overlap heuristic (Sec. IV-C): h_overlap(s) = |I| - #{p in I : p in V_j},
+ * the observed points outside the union V_j of the placed objects' volumes.  For
+ * each successor of the parent last set, evaluates it as perch_eval_children does
+ * (cost_dev, status_dev) and writes gain_dev[i] = #{p in I : p in V(O) and p not in
+ * V_j}, so that h_overlap(child) = h_overlap(parent) - gain; -1 for a successor that
+ * is not valid.  V(O) is tested in float32 (the oracle's FP64 decision may differ for
+ * points within 1e-5 m of a boundary).  gain_dev: device, n int32.  Asynchronous. */
+perch_status perch_overlap_gain(perch_ctx* ctx, const perch_object* cands_dev, int32_t n,
+                                int32_t* cost_dev, int32_t* status_dev, int32_t* gain_dev);
+
 /* Renders objects (host array objs[0..n)) to depth images (device output, float32,
  * +inf where uncovered): composite != 0 writes one H*W image holding the minimum
  * over the objects (the rendered scene R_n); composite == 0 writes n stand-alone
@@ -265,6 +275,8 @@ perch_status perch_cnn_gradients(perch_cnn* net, const uint16_t* crops_dev, int3
 #define PERCH_SEARCH_LEARNED 3    /* FOCAL whose inadmissible queue only receives the    */
                                   /* top-k children ranked by the learned network; the   */
                                   /* rest wait, keyed at g(parent), in the anchor queue  */
+#define PERCH_SEARCH_MHA 4        /* Focal-MHA* with the paper's h_depth and h_overlap  */
+                                  /* (Sec. IV-C) as two inadmissible queues, round robin */
 
 typedef struct {
   int32_t mode;                /* PERCH_SEARCH_*                                        */

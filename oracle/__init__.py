@@ -57,6 +57,7 @@ def lib():
         L.orc_render_objects.argtypes = [P, C.c_int32, P, P, C.c_int32, P]
         L.orc_eval.argtypes = [P, C.c_int32, P, P, C.c_int32, P, P, P, P, P, P]
         L.orc_jtree.argtypes = [P, C.c_int32, P, P, P]
+        L.orc_overlap.argtypes = [P, C.c_int32, P, P, C.c_int32, P, P, P, P, P]
         for f in (L.orc_search_exhaustive, L.orc_search_ucs, L.orc_bruteforce_joint):
             f.argtypes = [P, C.c_int32, P, P, P, P]
         _lib = L
@@ -156,6 +157,21 @@ class Oracle:
         if rc:
             raise RuntimeError(f"orc_eval failed ({rc})")
         return st, cost, comps, flags
+
+    def overlap(self, parent_mesh, parent_pose, cand_mesh, cand_pose):
+        """Overlap heuristic (Sec. IV-C) of the parent and of each child.
+        Returns (h_parent, h_child (n,), flags (n,))."""
+        pm, pp = _i32(parent_mesh), _i32(parent_pose)
+        cm, cp = _i32(cand_mesh), _i32(cand_pose)
+        n = len(cm)
+        hp = np.zeros(1, np.int64)
+        hc = np.zeros(n, np.int64)
+        fl = np.zeros(n, np.int32)
+        rc = lib().orc_overlap(self.h, len(pm), _ptr(pm), _ptr(pp), n, _ptr(cm), _ptr(cp),
+                               _ptr(hp), _ptr(hc), _ptr(fl))
+        if rc:
+            raise RuntimeError(f"orc_overlap failed ({rc})")
+        return int(hp[0]), hc, fl
 
     def jtree(self, mesh, pose) -> dict:
         m, p = _i32(mesh), _i32(pose)

@@ -668,6 +668,53 @@ int orc_eval(const orc_scene* sc, int32_t j, const int32_t* par_mesh, const int3
 /* one-shot costs of a full assignment                                       */
 /* ------------------------------------------------------------------------- */
 
+/* ------------------------------------------------------------------------- */
+/* overlap heuristic (Sec. IV-C)                                             */
+/* ------------------------------------------------------------------------- */
+
+/* h_overlap(s) = |I| - #{p in I : p in V_j}, V_j the union of the volumes of the j
+ * placed objects: for the parent, and for each child that adds one candidate
+ * object.  flags[c] counts the points whose membership in any of the volumes
+ * involved is decided within FLAG_EPS of a boundary. */
+int orc_overlap(const orc_scene* sc, int32_t j, const int32_t* pm, const int32_t* pp, int32_t n,
+                const int32_t* cm, const int32_t* cp, int64_t* h_parent, int64_t* h_child,
+                int32_t* flags) {
+  if (!sc || j < 0 || n < 0 || (j > 0 && (!pm || !pp)) || (n > 0 && (!cm || !cp)))
+    return -1;
+  if (check_objects(sc, j, pm, pp) || check_objects(sc, n, cm, cp)) return -2;
+  uint8_t* inVj = (uint8_t*)calloc((size_t)sc->nI + 1, 1);
+  uint8_t* nearVj = (uint8_t*)calloc((size_t)sc->nI + 1, 1);
+  if (!inVj || !nearVj) {
+    free(inVj);
+    free(nearVj);
+    return -3;
+  }
+  int64_t inside = 0;
+  for (int i = 0; i < sc->nI; ++i) {
+    for (int k = 0; k < j; ++k) {
+      const double vm = vol_margin(sc, pm[k], pp[k], sc->I_w + 3 * (size_t)i);
+      if (vm <= 0) inVj[i] = 1;
+      if (fabs(vm) <= FLAG_EPS) nearVj[i] = 1;
+    }
+    inside += inVj[i];
+  }
+  *h_parent = sc->nI - inside;
+  for (int c = 0; c < n; ++c) {
+    int64_t in_child = 0;
+    int32_t fl = 0;
+    for (int i = 0; i < sc->nI; ++i) {
+      const double vm = vol_margin(sc, cm[c], cp[c], sc->I_w + 3 * (size_t)i);
+      in_child += (inVj[i] || vm <= 0) ? 1 : 0;
+      fl += (nearVj[i] || fabs(vm) <= FLAG_EPS) ? 1 : 0;
+    }
+    h_child[c] = sc->nI - in_child;
+    flags[c] = fl;
+  }
+  free(inVj);
+  free(nearVj);
+  return 0;
+}
+
 static int cmp_pair(const int32_t* a, const int32_t* b) {
   if (a[0] != b[0]) return a[0] < b[0] ? -1 : 1;
   if (a[1] != b[1]) return a[1] < b[1] ? -1 : 1;

@@ -72,6 +72,15 @@ int orc_eval(const orc_scene* sc, int32_t j, const int32_t* par_mesh,
  * frontmost-owner partition, and the raw J of the problem statement).
  * out[0] valid (occlusion digraph acyclic), out[1] J_tree, out[2] J_raw,
  * out[3] n_flag_delta, out[4] n_flag_vol, out[5] flag_valid (depth ties). */
+/* The overlap heuristic of Sec. IV-C, h_overlap(s) = |I| - #{p in I : p in V_j}:
+ * h_parent for the parent of j objects, h_child[c] for each child adding candidate
+ * (cand_mesh[c], cand_pose[c]); flags[c] = points decided within 1e-6 m of a
+ * volume boundary. */
+int orc_overlap(const orc_scene* sc, int32_t j, const int32_t* par_mesh,
+                const int32_t* par_pose, int32_t n, const int32_t* cand_mesh,
+                const int32_t* cand_pose, int64_t* h_parent, int64_t* h_child,
+                int32_t* flags);
+
 int orc_jtree(const orc_scene* sc, int32_t K, const int32_t* mesh,
               const int32_t* pose, int64_t* out);
 

@@ -200,7 +200,8 @@ void perch_destroy(perch_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   for (DevBuf* b : {&c->verts, &c->tris, &c->planes, &c->range, &c->frange, &c->aabb, &c->poses,
                     &c->obs, &c->obs_range, &c->h_keys, &c->h_cells, &c->h_pts, &c->h_counts, &c->par_depth,
-                    &c->par_ubits, &c->par_ucount, &c->s_cands, &c->s_out, &c->cnn_desc})
+                    &c->par_ubits, &c->par_ucount, &c->par_vbits, &c->s_cands, &c->s_out,
+                    &c->cnn_desc})
     b->release();
   c->s_hcands.release();
   c->s_hout.release();
@@ -358,12 +359,17 @@ perch_status perch_set_parent(perch_ctx* c, const perch_object* parent, int32_t 
   if (!objects_ok(c, parent, j)) return fail(PERCH_E_ARG, "parent object out of range");
   st = materialise_parent(c, parent, j, j + 1 == K);
   if (st) return st;
+  c->parent_objs.assign(parent, parent + j);
+  ++c->parent_serial;
   c->parent_j = j;
   return PERCH_OK;
 }
 
-perch_status perch_eval_children(perch_ctx* c, const perch_object* cands_dev, int32_t n,
-                                 int32_t* cost_dev, int32_t* status_dev, int32_t* comps_dev) {
+// Successor launch over the materialised parent; gain_dev != null also counts, per
+// successor, the observed points its volume adds to V_j.
+static perch_status eval_children_impl(perch_ctx* c, const perch_object* cands_dev, int32_t n,
+                                       int32_t* cost_dev, int32_t* status_dev,
+                                       int32_t* comps_dev, int32_t* gain_dev) {
   if (!c) return fail(PERCH_E_ARG, "null context");
   if (n < 0 || (n > 0 && (!cands_dev || !cost_dev || !status_dev)))
     return fail(PERCH_E_ARG, "bad successor arrays");
@@ -379,11 +385,40 @@ perch_status perch_eval_children(perch_ctx* c, const perch_object* cands_dev, in
   par.depth = c->par_depth.as<unsigned>();
   par.ubits = c->par_ubits.as<unsigned>();
   par.ucount = c->par_ucount.as<int>();
+  par.vbits = nullptr;
   par.has_parent = c->parent_j > 0;
   par.goal = (c->parent_j + 1 == K);
+  if (gain_dev) {
+    if (c->vbits_for != c->parent_serial) {
+      const size_t npx = (size_t)c->cam.W * c->cam.H;
+      HIP_TRY(c->par_vbits.ensure(((npx + 31) / 32) * sizeof(unsigned)));
+      int mp[16];
+      const int j = c->parent_j;
+      for (int k = 0; k < j; ++k) {
+        mp[2 * k] = c->parent_objs[k].mesh_id;
+        mp[2 * k + 1] = c->parent_objs[k].pose_idx;
+      }
+      launch_parent_v(c->cam, c->dev_meshes(), c->poses.as<float4>(), c->obs.as<float>(), mp, j,
+                      c->par_vbits.as<unsigned>(), c->stream);
+      HIP_TRY(hipGetLastError());
+      c->vbits_for = c->parent_serial;
+    }
+    par.vbits = c->par_vbits.as<unsigned>();
+  }
   HIP_TRY(launch_eval(c->threads, c->scene_dev(), par, reinterpret_cast<const int2*>(cands_dev),
-                      n, cost_dev, status_dev, comps_dev, lds, c->stream));
+                      n, cost_dev, status_dev, comps_dev, gain_dev, lds, c->stream));
   return PERCH_OK;
+}
+
+perch_status perch_eval_children(perch_ctx* c, const perch_object* cands_dev, int32_t n,
+                                 int32_t* cost_dev, int32_t* status_dev, int32_t* comps_dev) {
+  return eval_children_impl(c, cands_dev, n, cost_dev, status_dev, comps_dev, nullptr);
+}
+
+perch_status perch_overlap_gain(perch_ctx* c, const perch_object* cands_dev, int32_t n,
+                                int32_t* cost_dev, int32_t* status_dev, int32_t* gain_dev) {
+  if (n > 0 && !gain_dev) return fail(PERCH_E_ARG, "null gain array");
+  return eval_children_impl(c, cands_dev, n, cost_dev, status_dev, nullptr, gain_dev);
 }
 
 perch_status perch_eval_successors(perch_ctx* c, const perch_object* parent, int32_t j,

@@ -150,6 +150,11 @@ struct perch_ctx {
   float cell_over_delta = 2.0f;
   // parent buffers (parent_j = level of the materialised parent, -1 = none)
   DevBuf par_depth, par_ubits, par_ucount;
+  // overlap heuristic: observed pixels inside V_j of the materialised parent,
+  // computed on first use (vbits_for == parent_serial)
+  DevBuf par_vbits;
+  std::vector<perch_object> parent_objs;
+  long parent_serial = 0, vbits_for = -1;
   int parent_j = -1;
   // crop descriptors of the learned heuristic
   DevBuf cnn_desc;

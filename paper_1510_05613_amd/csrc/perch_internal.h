@@ -50,6 +50,7 @@ struct Parent {
   const unsigned* depth;
   const unsigned* ubits;
   const int* ucount;
+  const unsigned* vbits;  // observed pixels inside V_j (overlap heuristic), or null
   int has_parent;
   int goal;
 };
@@ -104,9 +105,14 @@ void launch_parent_u(const Cam& cam, const Meshes& M, const float4* poses, const
                      unsigned* ubits, int* ucount, const EvalParams& ep, hipStream_t s);
 void launch_bits_to_float(const unsigned* bits, float* out, size_t n, hipStream_t s);
 void launch_obs_range(const Cam& cam, const float* obs, float2* out, int R, hipStream_t s);
+// gain (optional): per valid successor, observed points inside V(O) and outside
+// V_j (par.vbits), the decrease of the overlap heuristic; -1 for invalid ones.
 hipError_t launch_eval(int threads, const SceneDev& S, const Parent& par, const int2* cands,
-                       int n, int* cost, int* status, int* comps, size_t lds_bytes,
+                       int n, int* cost, int* status, int* comps, int* gain, size_t lds_bytes,
                        hipStream_t s);
+// vbits |= observed pixels inside the union of the j objects' volumes
+void launch_parent_v(const Cam& cam, const Meshes& M, const float4* poses, const float* obs,
+                     const int* par_mesh_pose, int j, unsigned* vbits, hipStream_t s);
 // Raises the kernel's LDS limit and reports resident workgroups per CU (call
 // before launch_eval_batch, outside any graph capture).
 hipError_t prepare_eval_batch(int threads, int vpack, size_t lds_bytes, int* blocks_per_cu);

@@ -626,6 +626,26 @@ __global__ void k_parent_u(Cam cam, Meshes M, const float4* poses, const float* 
 }
 
 // ---------------------------------------------------------------------------
+// overlap heuristic: observed pixels inside the union V_j of the parent volumes
+// ---------------------------------------------------------------------------
+
+__global__ void k_parent_v(Cam cam, Meshes M, const float4* poses, const float* obs,
+                           ParentObjs po, int j, unsigned* vbits) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int W = cam.W, H = cam.H;
+  bool inV = false;
+  if (k < W * H) {
+    const float z = obs[k];
+    if (z > 0.0f) {
+      const float3 p = backproject(cam, k % W, k / W, z);
+      for (int a = 0; a < j && !inV; ++a)
+        inV = in_volume(M, po.o[a].x, apply_obj_map(make_obj_map(cam, poses[po.o[a].y]), p));
+    }
+  }
+  if (inV) atomicOr(&vbits[k >> 5], 1u << (k & 31));
+}
+
+// ---------------------------------------------------------------------------
 // successor evaluation: one workgroup per successor
 // ---------------------------------------------------------------------------
 
@@ -636,7 +656,8 @@ template <int NT, bool OUTLINE, bool VP>
 __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& par, const int2 cd,
                                                const int s, int* __restrict__ out_cost,
                                                int* __restrict__ out_status,
-                                               int* __restrict__ out_comps, unsigned char* smem,
+                                               int* __restrict__ out_comps,
+                                               int* __restrict__ out_gain, unsigned char* smem,
                                                int* s_bb, int* s_acc, float4* s_pl) {
   const Cam& cam = S.cam;
   const Meshes& M = S.M;
@@ -652,6 +673,7 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
     if (tid == 0) {
       out_status[s] = -4;
       out_cost[s] = -1;
+      if (out_gain) out_gain[s] = -1;
       if (out_comps)
         for (int c = 0; c < 5; ++c) out_comps[5 * s + c] = -1;
     }
@@ -719,6 +741,7 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
     if (tid == 0) {
       out_status[s] = -2;
       out_cost[s] = -1;
+      if (out_gain) out_gain[s] = -1;
       if (out_comps)
         for (int c = 0; c < 5; ++c) out_comps[5 * s + c] = -1;
     }
@@ -771,13 +794,14 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
     if (tid == 0) {
       out_status[s] = -3;
       out_cost[s] = -1;
+      if (out_gain) out_gain[s] = -1;
       if (out_comps)
         for (int c = 0; c < 5; ++c) out_comps[5 * s + c] = -1;
     }
     return;
   }
   const float delta2 = cam.delta2;
-  int n_dJr = 0, n_dJo = 0, n_rem = 0;  // wave-uniform ballot counts
+  int n_dJr = 0, n_dJo = 0, n_rem = 0, n_gain = 0;  // wave-uniform ballot counts
 
   for (int b0 = ra; b0 <= rb && tw > 0; b0 += core) {
     const int b1 = min(rb, b0 + core - 1);
@@ -938,6 +962,11 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
         n_dJr += ballot_count(state == 2);
         n_dJo += ballot_count(inV && !expl);
         n_rem += ballot_count(inU && (inV || expl));
+        if (out_gain) {  // overlap heuristic: points V(O) adds to V_j
+          const int pix = jj * W + ii;
+          const bool inVj = par.vbits && ((par.vbits[pix >> 5] >> (pix & 31)) & 1u);
+          n_gain += ballot_count(inV && !inVj);
+        }
         unsigned long long und = __ballot(state == 3);
         // wave-uniform: two undecided points at a time, each lane testing one pixel
         // of either window per step, so two observed-depth loads are in flight
@@ -1001,6 +1030,7 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
     atomicAdd(&s_acc[2], n_dJr);
     atomicAdd(&s_acc[3], n_dJo);
     atomicAdd(&s_acc[4], n_rem);
+    if (out_gain) atomicAdd(&s_acc[7], n_gain);
   }
   __syncthreads();
   if (tid == 0) {
@@ -1008,6 +1038,7 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
     const int res = par.goal ? (*par.ucount - s_acc[4]) : 0;
     out_status[s] = valid ? 1 : 0;
     out_cost[s] = valid ? s_acc[2] + s_acc[3] + res : -1;
+    if (out_gain) out_gain[s] = valid ? s_acc[7] : -1;
     if (out_comps) {  // an invalid successor stops at its first occluding band
       out_comps[5 * s + 0] = valid ? s_acc[0] : -1;
       out_comps[5 * s + 1] = valid ? s_acc[1] : -1;
@@ -1022,15 +1053,16 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
 template <int NT, bool VP>
 __global__ void __launch_bounds__(NT)
     k_eval(SceneDev S, Parent par, const int2* __restrict__ cands, int n,
-           int* __restrict__ out_cost, int* __restrict__ out_status, int* __restrict__ out_comps) {
+           int* __restrict__ out_cost, int* __restrict__ out_status, int* __restrict__ out_comps,
+           int* __restrict__ out_gain) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_bb[4];
-  __shared__ int s_acc[8];  // S, |dR|, dJ_r, dJ_o, removed-from-U, invalid, near-plane
+  __shared__ int s_acc[8];  // S, |dR|, dJ_r, dJ_o, removed-from-U, invalid, near-plane, gain
   __shared__ float4 s_pl[kLdsPlanes];
   const int s = blockIdx.x;
   if (s >= n) return;
-  eval_successor<NT, false, VP>(S, par, cands[s], s, out_cost, out_status, out_comps, smem,
-                                s_bb, s_acc, s_pl);
+  eval_successor<NT, false, VP>(S, par, cands[s], s, out_cost, out_status, out_comps, out_gain,
+                                smem, s_bb, s_acc, s_pl);
 }
 
 // Persistent workgroups over a work queue of (parent slot, mesh, pose) items that
@@ -1069,11 +1101,12 @@ __global__ void __launch_bounds__(NT, 4)  // at least 4 waves per SIMD: <= 128 V
     par.depth = pd.depth;
     par.ubits = pd.ubits;
     par.ucount = pd.ucount;
+    par.vbits = nullptr;
     par.has_parent = pd.has_parent;
     par.goal = pd.goal;
     const int scene = __builtin_amdgcn_readfirstlane(pd.scene);
     eval_successor<NT, true, VP>(scenes[scene], par, make_int2(w.y, w.z), it, out_cost,
-                                 out_status, out_comps, smem, s_bb, s_acc, s_pl);
+                                 out_status, out_comps, nullptr, smem, s_bb, s_acc, s_pl);
   }
 }
 
@@ -1130,6 +1163,18 @@ void launch_parent_u(const Cam& cam, const Meshes& M, const float4* poses, const
                      j, depth_bits, ubits, ucount, ep);
 }
 
+void launch_parent_v(const Cam& cam, const Meshes& M, const float4* poses, const float* obs,
+                     const int* par_mesh_pose, int j, unsigned* vbits, hipStream_t s) {
+  ParentObjs po;
+  for (int a = 0; a < 8; ++a)
+    po.o[a] = a < j ? make_int2(par_mesh_pose[2 * a], par_mesh_pose[2 * a + 1]) : make_int2(0, 0);
+  const int n = cam.W * cam.H;
+  launch_fill_u32(vbits, 0u, (size_t)(n + 31) / 32, s);
+  if (j > 0)
+    hipLaunchKernelGGL(k_parent_v, dim3((n + 255) / 256), dim3(256), 0, s, cam, M, poses, obs, po,
+                       j, vbits);
+}
+
 template <class K>
 static hipError_t allow_lds(K kernel, size_t lds) {
   if (lds <= 65536) return hipSuccess;
@@ -1139,40 +1184,41 @@ static hipError_t allow_lds(K kernel, size_t lds) {
 
 template <int NT, bool VP>
 static hipError_t launch_eval_t(const SceneDev& S, const Parent& par, const int2* cands, int n,
-                                int* cost, int* status, int* comps, size_t lds, hipStream_t s) {
+                                int* cost, int* status, int* comps, int* gain, size_t lds,
+                                hipStream_t s) {
   hipError_t e = allow_lds(&k_eval<NT, VP>, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_eval<NT, VP>), dim3(n), dim3(NT), lds, s, S, par, cands, n, cost, status,
-                     comps);
+                     comps, gain);
   return hipGetLastError();
 }
 
 template <bool VP>
 static hipError_t launch_eval_vp(int threads, const SceneDev& S, const Parent& par,
                                  const int2* cands, int n, int* cost, int* status, int* comps,
-                                 size_t lds, hipStream_t s) {
+                                 int* gain, size_t lds, hipStream_t s) {
   switch (threads) {
     case 64:
-      return launch_eval_t<64, VP>(S, par, cands, n, cost, status, comps, lds, s);
+      return launch_eval_t<64, VP>(S, par, cands, n, cost, status, comps, gain, lds, s);
     case 128:
-      return launch_eval_t<128, VP>(S, par, cands, n, cost, status, comps, lds, s);
+      return launch_eval_t<128, VP>(S, par, cands, n, cost, status, comps, gain, lds, s);
     case 512:
-      return launch_eval_t<512, VP>(S, par, cands, n, cost, status, comps, lds, s);
+      return launch_eval_t<512, VP>(S, par, cands, n, cost, status, comps, gain, lds, s);
     case 1024:
-      return launch_eval_t<1024, VP>(S, par, cands, n, cost, status, comps, lds, s);
+      return launch_eval_t<1024, VP>(S, par, cands, n, cost, status, comps, gain, lds, s);
     default:
-      return launch_eval_t<256, VP>(S, par, cands, n, cost, status, comps, lds, s);
+      return launch_eval_t<256, VP>(S, par, cands, n, cost, status, comps, gain, lds, s);
   }
 }
 
 hipError_t launch_eval(int threads, const SceneDev& S, const Parent& par, const int2* cands,
-                       int n, int* cost, int* status, int* comps, size_t lds_bytes,
+                       int n, int* cost, int* status, int* comps, int* gain, size_t lds_bytes,
                        hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  return S.ep.vpack ? launch_eval_vp<true>(threads, S, par, cands, n, cost, status, comps,
+  return S.ep.vpack ? launch_eval_vp<true>(threads, S, par, cands, n, cost, status, comps, gain,
                                            lds_bytes, s)
                     : launch_eval_vp<false>(threads, S, par, cands, n, cost, status, comps,
-                                            lds_bytes, s);
+                                            gain, lds_bytes, s);
 }
 
 template <int NT, bool VP>

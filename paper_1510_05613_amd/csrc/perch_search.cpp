@@ -15,6 +15,10 @@
 //     restricted to FOCAL = {g <= w * min g}; a goal chosen from FOCAL costs at
 //     most w * OPT (Theorem 2).  With anytime = 1 the search continues, keeping the
 //     best goal, until the incumbent is no worse than the anchor's min g;
+//   - multi-heuristic (Focal-MHA*, Sec. IV-C): the anchor and two inadmissible
+//     queues restricted to FOCAL, h_depth and h_overlap = |I| - #{p in I : p in V_j}
+//     (kept per state from the per-child decrease the successor kernel counts),
+//     expanded round robin; same bound and anytime rule as focal;
 //   - learned: the focal scheme with a learned network ranking the children of an
 //     expanded state: only the top-k predicted children are evaluated exactly and
 //     enter the inadmissible queue; the remaining children wait as one lazy block
@@ -48,6 +52,7 @@ struct Node {
   perch_object objs[8];  // insertion order
   int64_t key[8];        // canonical: sorted (mesh << 32 | pose)
   int32_t lazy;          // learned search: a block of unevaluated children of `parent`
+  int64_t hov;           // overlap heuristic: observed points outside V_j (MHA search)
 };
 
 int64_t pack(int32_t m, int32_t p) { return ((int64_t)m << 32) | (uint32_t)p; }
@@ -81,7 +86,7 @@ struct KeyEq {
 };
 
 struct Child {
-  int32_t mesh, pose, cost;
+  int32_t mesh, pose, cost, gain;  // gain: observed points the child adds to V_j
 };
 
 // Device buffers of one search call, released when it returns.
@@ -121,9 +126,9 @@ class Searcher {
     distinct_ = distinct;
     const size_t cap = (size_t)distinct * poses_.size();
     HIP_TRY(c_->s_cands.ensure(cap * sizeof(int2)));
-    HIP_TRY(c_->s_out.ensure(cap * 2 * sizeof(int32_t)));
+    HIP_TRY(c_->s_out.ensure(cap * 3 * sizeof(int32_t)));
     HIP_TRY(c_->s_hcands.ensure(cap * sizeof(int2)));
-    HIP_TRY(c_->s_hout.ensure(cap * 2 * sizeof(int32_t)));
+    HIP_TRY(c_->s_hout.ensure(cap * 3 * sizeof(int32_t)));
     t0_ = Clock::now();
     return PERCH_OK;
   }
@@ -149,7 +154,8 @@ class Searcher {
   }
 
   // Materialises n on the GPU and evaluates every child; valid ones go to out.
-  perch_status expand(const Node& n, std::vector<Child>& out) {
+  // with_gain: also the overlap heuristic's decrease per child.
+  perch_status expand(const Node& n, std::vector<Child>& out, bool with_gain = false) {
     out.clear();
     const std::vector<int> rest = remaining(n);
     const int P = (int)poses_.size();
@@ -163,19 +169,21 @@ class Searcher {
     if (st) return st;
     int32_t* dcost = c_->s_out.as<int32_t>();
     int32_t* dstat = dcost + cnt;
-    st = perch_eval_children(c_, reinterpret_cast<const perch_object*>(c_->s_cands.p), cnt, dcost,
-                             dstat, nullptr);
+    int32_t* dgain = dstat + cnt;
+    const perch_object* dc = reinterpret_cast<const perch_object*>(c_->s_cands.p);
+    st = with_gain ? perch_overlap_gain(c_, dc, cnt, dcost, dstat, dgain)
+                   : perch_eval_children(c_, dc, cnt, dcost, dstat, nullptr);
     if (st) return st;
     int32_t* hout = c_->s_hout.as<int32_t>();
-    HIP_TRY(hipMemcpyAsync(hout, dcost, 2 * (size_t)cnt * sizeof(int32_t), hipMemcpyDeviceToHost,
-                           c_->stream));
+    HIP_TRY(hipMemcpyAsync(hout, dcost, (with_gain ? 3 : 2) * (size_t)cnt * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, c_->stream));
     HIP_TRY(hipStreamSynchronize(c_->stream));
     ++n_expanded_;
     n_evaluated_ += cnt;
     for (int i = 0; i < cnt; ++i) {
       const int s = hout[cnt + i];
       if (s == 1)
-        out.push_back({hc[i].x, hc[i].y, hout[i]});
+        out.push_back({hc[i].x, hc[i].y, hout[i], with_gain ? hout[2 * cnt + i] : 0});
       else if (s == 0)
         ++n_invalid_;
       else
@@ -197,6 +205,7 @@ class Searcher {
     m.objs[n.j].pose_idx = ch.pose;
     make_key(m);
     m.lazy = 0;
+    m.hov = n.hov - ch.gain;
     return m;
   }
 
@@ -248,12 +257,16 @@ class Searcher {
   }
 
   // ---- uniform-cost and focal ----
-  perch_status best_first(bool focal) {
+  // n_inad inadmissible queues: 0 uniform-cost, 1 focal (h_depth), 2 Focal-MHA*
+  // (h_depth and h_overlap, round robin).
+  perch_status best_first(int n_inad) {
+    const bool focal = n_inad > 0;
     std::vector<Node> nodes;
     nodes.reserve(1 << 16);
     Node root;
     std::memset(&root, 0, sizeof(root));
     root.parent = -1;
+    root.hov = c_->n_points;  // h_overlap(root) = |I|
     nodes.push_back(root);
     std::unordered_map<int, int, KeyHash, KeyEq> table(1024, KeyHash{&nodes}, KeyEq{&nodes});
     table.emplace(0, 0);
@@ -273,6 +286,14 @@ class Searcher {
       return cmp_key(x, y) > 0;
     };
     std::priority_queue<int, std::vector<int>, decltype(d_less)> focal_q(d_less);
+    // overlap heap: fewer observed points outside V_j first, then smaller g, then key
+    auto o_less = [&](int a, int b) {
+      const Node &x = nodes[a], &y = nodes[b];
+      if (x.hov != y.hov) return x.hov > y.hov;
+      if (x.g != y.g) return x.g > y.g;
+      return cmp_key(x, y) > 0;
+    };
+    std::priority_queue<int, std::vector<int>, decltype(o_less)> over_q(o_less);
     // states waiting for the focal bound, ordered by g
     std::priority_queue<int, std::vector<int>, decltype(g_less)> pending(g_less);
     open.push(0);
@@ -293,13 +314,26 @@ class Searcher {
       int pick = -1;
       if (focal) {
         while (!pending.empty() && (double)nodes[pending.top()].g <= w * (double)gmin) {
-          if (live(pending.top())) focal_q.push(pending.top());
+          if (live(pending.top())) {
+            focal_q.push(pending.top());
+            if (n_inad > 1) over_q.push(pending.top());
+          }
           pending.pop();
         }
         while (!focal_q.empty() && !live(focal_q.top())) focal_q.pop();
-        if (!focal_q.empty() && (expansions_ % 2 == 0 || !o_.anytime)) {
-          pick = focal_q.top();
-          focal_q.pop();
+        while (!over_q.empty() && !live(over_q.top())) over_q.pop();
+        // round robin over the inadmissible queues, and the anchor when anytime
+        const int cycle = n_inad + (o_.anytime ? 1 : 0);
+        const int slot = (int)(expansions_ % cycle);
+        for (int t = 0; t < n_inad && pick < 0 && slot < n_inad; ++t) {
+          const int q = (slot + t) % n_inad;
+          if (q == 0 && !focal_q.empty()) {
+            pick = focal_q.top();
+            focal_q.pop();
+          } else if (q == 1 && !over_q.empty()) {
+            pick = over_q.top();
+            over_q.pop();
+          }
         }
       }
       if (pick < 0) {
@@ -314,7 +348,7 @@ class Searcher {
         if (!focal || !o_.anytime) break;  // first goal popped / chosen from FOCAL
         continue;
       }
-      perch_status st = expand(cur, kids);
+      perch_status st = expand(cur, kids, n_inad > 1);
       if (st) return st;
       for (const Child& ch : kids) {
         Node m = child_of(cur, pick, ch);
@@ -447,7 +481,7 @@ class Searcher {
       for (int i = 0; i < k; ++i) {
         const int s2 = hout[k + i];
         if (s2 == 1)
-          out.push_back({hc[i].x, hc[i].y, hout[i]});
+          out.push_back({hc[i].x, hc[i].y, hout[i], 0});
         else if (s2 == 0)
           ++n_invalid_;
         else
@@ -606,10 +640,10 @@ class Searcher {
 extern "C" perch_status perch_search(perch_ctx* c, const perch_search_opts* opts,
                                      perch_result* out) {
   if (!c || !opts || !out) return fail(PERCH_E_ARG, "null argument");
-  if (opts->mode < PERCH_SEARCH_EXHAUSTIVE || opts->mode > PERCH_SEARCH_LEARNED)
+  if (opts->mode < PERCH_SEARCH_EXHAUSTIVE || opts->mode > PERCH_SEARCH_MHA)
     return fail(PERCH_E_ARG, "unknown search mode %d", opts->mode);
   if (opts->mode >= PERCH_SEARCH_FOCAL && !(opts->w >= 1.0f))
-    return fail(PERCH_E_ARG, "focal and learned searches need w >= 1");
+    return fail(PERCH_E_ARG, "focal, learned and multi-heuristic searches need w >= 1");
   Searcher s(c, opts);
   perch_status st = s.init();
   if (st) return st;
@@ -617,8 +651,10 @@ extern "C" perch_status perch_search(perch_ctx* c, const perch_search_opts* opts
     st = s.exhaustive();
   else if (opts->mode == PERCH_SEARCH_LEARNED)
     st = s.learned();
+  else if (opts->mode == PERCH_SEARCH_MHA)
+    st = s.best_first(2);
   else
-    st = s.best_first(opts->mode == PERCH_SEARCH_FOCAL);
+    st = s.best_first(opts->mode == PERCH_SEARCH_FOCAL ? 1 : 0);
   s.fill(out);
   if (st == PERCH_E_BUDGET) return fail(PERCH_E_BUDGET, "search budget exhausted");
   return st;

@@ -25,14 +25,15 @@ PERCH_SUCC_BAD_INPUT = -4
 # the public symbols declared in include/perch.h
 EXPORTS = ("perch_create", "perch_destroy", "perch_set_observation", "perch_add_mesh",
            "perch_set_poses", "perch_set_objects", "perch_eval_successors", "perch_set_parent",
-           "perch_eval_children", "perch_render", "perch_set_tuning", "perch_get_info",
+           "perch_eval_children", "perch_overlap_gain", "perch_render", "perch_set_tuning",
+           "perch_get_info",
            "perch_search", "perch_batch_create", "perch_batch_destroy",
            "perch_batch_set_parents", "perch_batch_eval", "perch_batch_set_tuning",
            "perch_autotune", "perch_cnn_create", "perch_cnn_destroy", "perch_cnn_param_count",
            "perch_cnn_set_params", "perch_cnn_get_params", "perch_cnn_crops", "perch_cnn_predict",
            "perch_cnn_train_step", "perch_cnn_gradients", "perch_last_error")
 
-SEARCH_EXHAUSTIVE, SEARCH_UCS, SEARCH_FOCAL, SEARCH_LEARNED = 0, 1, 2, 3
+SEARCH_EXHAUSTIVE, SEARCH_UCS, SEARCH_FOCAL, SEARCH_LEARNED, SEARCH_MHA = 0, 1, 2, 3, 4
 
 
 class PerchError(RuntimeError):
@@ -96,6 +97,7 @@ def load(path: str = LIB_PATH):
     L.perch_set_parent.argtypes = [P, P, I32]
     L.perch_eval_children.argtypes = [P, P, I32, P, P, P]
     L.perch_render.argtypes = [P, P, I32, I32, P]
+    L.perch_overlap_gain.argtypes = [P, P, I32, P, P, P]
     L.perch_set_tuning.argtypes = [P, I32, I32, C.c_float, I32]
     L.perch_get_info.argtypes = [P, C.POINTER(I32), C.POINTER(I32)]
     L.perch_search.argtypes = [P, C.POINTER(_SearchOpts), C.POINTER(_Result)]
@@ -250,6 +252,15 @@ class Context:
             self.h, _dev_ptr(cands, "int32", 2 * n), n, _dev_ptr(cost, "int32", n),
             _dev_ptr(status, "int32", n),
             None if comps is None else _dev_ptr(comps, "int32", 5 * n)))
+
+    def overlap_gain(self, cands, cost, status, gain):
+        """Successors of the parent last set (as eval_children) and, per successor,
+        the observed points its volume adds to the parent's V_j (the decrease of the
+        overlap heuristic, Sec. IV-C; -1 when not valid).  Asynchronous."""
+        n = cands.shape[0]
+        _check(load().perch_overlap_gain(
+            self.h, _dev_ptr(cands, "int32", 2 * n), n, _dev_ptr(cost, "int32", n),
+            _dev_ptr(status, "int32", n), _dev_ptr(gain, "int32", n)))
 
     def evaluate(self, parent, cands, with_comps: bool = True):
         """Convenience: allocates outputs, evaluates and returns GPU tensors."""

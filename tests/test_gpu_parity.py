@@ -293,3 +293,34 @@ def test_footprints_wider_than_256_pixels(c2, large_library):
         torch.cuda.synchronize()
         for a, g2 in zip(gres, (bs.cpu().numpy(), bc.cpu().numpy(), bp.cpu().numpy())):
             assert np.array_equal(a, g2)
+
+
+@pytest.mark.parametrize("level", [0, 1])
+def test_overlap_gain_matches_oracle(c1, level):
+    """Per successor, the observed points its volume adds to V_j (the overlap
+    heuristic of Sec. IV-C), against the oracle's h_overlap of parent and child;
+    points within 1e-6 m of a volume boundary are the tolerance."""
+    sc, o, ctx = c1[0]
+    par = [(int(sc.obj_mesh[k]), int(sc.gt_pose[k])) for k in sc.gt_order[:level]]
+    rest = sorted({int(sc.obj_mesh[k]) for k in sc.gt_order[level:]})
+    ps = np.arange(0, sc.grid.P, 3)
+    ms = np.repeat(rest, len(ps))
+    ps = np.tile(ps, len(rest))
+    cands = _cands(ms, ps)
+    n = len(ms)
+    cost = torch.empty(n, dtype=torch.int32, device="cuda")
+    st = torch.empty(n, dtype=torch.int32, device="cuda")
+    gain = torch.empty(n, dtype=torch.int32, device="cuda")
+    ctx.set_parent(par)
+    ctx.overlap_gain(cands, cost, st, gain)
+    torch.cuda.synchronize()
+    st, cost, gain = st.cpu().numpy(), cost.cpu().numpy(), gain.cpu().numpy()
+    # the same evaluation without the gain output
+    ref = _gpu_eval(ctx, par, ms, ps)
+    assert np.array_equal(st, ref[0]) and np.array_equal(cost, ref[1])
+    h0, hc, fl = o.overlap([p[0] for p in par], [p[1] for p in par], ms, ps)
+    valid = st == 1
+    assert valid.sum() > 0 and np.all(gain[~valid] == -1)
+    d = np.abs(gain[valid] - (h0 - hc[valid]))
+    assert np.all(d <= fl[valid]), (np.nonzero(d > fl[valid])[0][:5])
+    assert np.mean(gain[valid] > 0) > 0.05  # the test sees real overlaps

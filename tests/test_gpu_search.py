@@ -85,3 +85,28 @@ def test_budget_returns_incumbent_status():
     ctx = perch.context_from_scene(sc)
     r = ctx.search(perch.SEARCH_UCS, budget_expansions=1)
     assert r["budget_exhausted"] and r["n_expanded"] == 1
+
+
+@pytest.mark.parametrize("w", [1.0, 1.5, 3.0])
+def test_multi_heuristic_cost_within_w_of_optimum(w):
+    """Focal-MHA* with the paper's two inadmissible heuristics (h_depth, h_overlap):
+    the first goal costs at most w * OPT (Theorem 2); run anytime it returns OPT."""
+    sc = H.c1_scene(6)
+    ctx = perch.context_from_scene(sc)
+    opt = ctx.search(perch.SEARCH_UCS)["cost"]
+    f = ctx.search(perch.SEARCH_MHA, w=w)
+    assert f["found"] and f["cost"] <= w * opt + 1e-9
+    a = ctx.search(perch.SEARCH_MHA, w=w, anytime=True)
+    assert a["cost"] == opt and a["lower_bound"] >= opt
+
+
+def test_multi_heuristic_on_pose_subsets_matches_oracle_optimum():
+    sc = H.c2_scene(0)
+    sub = scenes.pose_subset_around(sc, 2, yaw_stride=4)
+    o = Oracle.from_scene(sc, nthreads=NTH)
+    ctx = perch.context_from_scene(sc)
+    opt = o.search_ucs(sub)["cost"]
+    a = ctx.search(perch.SEARCH_MHA, w=3.0, anytime=True, pose_subset=sub)
+    assert a["found"] and a["cost"] == opt
+    f = ctx.search(perch.SEARCH_MHA, w=3.0, pose_subset=sub)
+    assert f["cost"] <= 3.0 * opt
