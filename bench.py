@@ -255,7 +255,8 @@ def learned_leg_640(n_scenes: int, budget_s: float = 10.0) -> dict:
     net, ctrl = learn.search_networks(CHECKPOINT_640, 2)
     first = learn.HELD_OUT_FIRST
     g = learn.gain(net, ctrl, range(first, first + 2 * n_scenes), config=2, topk=256,
-                   budget_s=budget_s, max_scenes=n_scenes)
+                   budget_s=budget_s, max_scenes=n_scenes,
+                   log=lambda m: print(m, file=sys.stderr, flush=True))
     g["workload"] = (f"config 2 (640x480, K=3, 40,000 poses/object), the first {n_scenes} "
                      f"held-out scenes from {first}; medians, {budget_s:.0f} s per search")
     return g

@@ -277,7 +277,7 @@ def max_block(ds: Dataset, crops_per_batch: int) -> tuple:
     return max(crops_per_batch, most_c), max(most_b, most_p)
 
 
-SEARCHES = ("exhaustive", "ucs", "focal", "learned", "random_init")
+SEARCHES = ("exhaustive", "ucs", "focal", "mha", "learned", "random_init")
 
 
 def gain(net: "perch.Cnn", control: "perch.Cnn", indices: Sequence[int], config: int = 4,
@@ -285,7 +285,8 @@ def gain(net: "perch.Cnn", control: "perch.Cnn", indices: Sequence[int], config:
          max_scenes: int = 0) -> dict:
     """Time (and successor evaluations) until each search first holds the best
     scene, on held-out scenes.  exhaustive (small trees only) and ucs are the plain
-    searches; focal is the paper's inadmissible depth heuristic without learning;
+    searches; focal is the paper's inadmissible depth heuristic without learning and
+    mha the paper's own configuration (h_depth and h_overlap, Focal-MHA*);
     learned and random_init are the learned search with the trained and an
     untrained network.  The best scene is the optimum returned by a plain search
     that finished; a search that never held it counts as not reaching it (None).
@@ -311,6 +312,7 @@ def gain(net: "perch.Cnn", control: "perch.Cnn", indices: Sequence[int], config:
             exhaustive=lambda: ctx.search(perch.SEARCH_EXHAUSTIVE, budget_s=budget_s),
             ucs=lambda: ctx.search(perch.SEARCH_UCS, budget_s=budget_s),
             focal=lambda: ctx.search(perch.SEARCH_FOCAL, w=w, anytime=True, budget_s=budget_s),
+            mha=lambda: ctx.search(perch.SEARCH_MHA, w=w, anytime=True, budget_s=budget_s),
             learned=lambda: ctx.search(perch.SEARCH_LEARNED, w=w, anytime=True, cnn=net,
                                        topk=topk, budget_s=budget_s),
             random_init=lambda: ctx.search(perch.SEARCH_LEARNED, w=w, anytime=True, cnn=control,
