@@ -277,6 +277,8 @@ perch_status perch_cnn_gradients(perch_cnn* net, const uint16_t* crops_dev, int3
                                   /* rest wait, keyed at g(parent), in the anchor queue  */
 #define PERCH_SEARCH_MHA 4        /* Focal-MHA* with the paper's h_depth and h_overlap  */
                                   /* (Sec. IV-C) as two inadmissible queues, round robin */
+#define PERCH_SEARCH_LEARNED_MHA 5 /* LEARNED with h_overlap as a second inadmissible    */
+                                  /* queue over the children it evaluates               */
 
 typedef struct {
   int32_t mode;                /* PERCH_SEARCH_*                                        */
@@ -286,7 +288,7 @@ typedef struct {
   int64_t budget_expansions;   /* 0 = none                                              */
   const int32_t* pose_subset;  /* host; NULL = every pose of the table                  */
   int32_t n_pose_subset;
-  perch_cnn* cnn;              /* LEARNED: the network (created with enough capacity   */
+  perch_cnn* cnn;              /* LEARNED(_MHA): the network (created with capacity    */
                                /* for one crop per pose cell and one pair per child)   */
   int32_t topk;                /* LEARNED: children evaluated exactly per expansion    */
 } perch_search_opts;

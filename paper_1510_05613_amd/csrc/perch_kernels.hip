@@ -652,7 +652,9 @@ __global__ void k_parent_v(Cam cam, Meshes M, const float4* poses, const float* 
 // Evaluates successor s' = parent + (cd.x = mesh, cd.y = pose) of scene S and
 // writes output slot s.  Every thread of the workgroup calls it with the same
 // arguments; it synchronises the workgroup internally.
-template <int NT, bool OUTLINE, bool VP>
+// GAIN: also write the overlap gain (points of V(O) outside the parent's V_j) to
+// out_gain, which must then be non-null.
+template <int NT, bool OUTLINE, bool VP, bool GAIN>
 __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& par, const int2 cd,
                                                const int s, int* __restrict__ out_cost,
                                                int* __restrict__ out_status,
@@ -673,7 +675,7 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
     if (tid == 0) {
       out_status[s] = -4;
       out_cost[s] = -1;
-      if (out_gain) out_gain[s] = -1;
+      if (GAIN) out_gain[s] = -1;
       if (out_comps)
         for (int c = 0; c < 5; ++c) out_comps[5 * s + c] = -1;
     }
@@ -741,7 +743,7 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
     if (tid == 0) {
       out_status[s] = -2;
       out_cost[s] = -1;
-      if (out_gain) out_gain[s] = -1;
+      if (GAIN) out_gain[s] = -1;
       if (out_comps)
         for (int c = 0; c < 5; ++c) out_comps[5 * s + c] = -1;
     }
@@ -794,7 +796,7 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
     if (tid == 0) {
       out_status[s] = -3;
       out_cost[s] = -1;
-      if (out_gain) out_gain[s] = -1;
+      if (GAIN) out_gain[s] = -1;
       if (out_comps)
         for (int c = 0; c < 5; ++c) out_comps[5 * s + c] = -1;
     }
@@ -962,7 +964,7 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
         n_dJr += ballot_count(state == 2);
         n_dJo += ballot_count(inV && !expl);
         n_rem += ballot_count(inU && (inV || expl));
-        if (out_gain) {  // overlap heuristic: points V(O) adds to V_j
+        if (GAIN) {  // overlap heuristic: points V(O) adds to V_j
           const int pix = jj * W + ii;
           const bool inVj = par.vbits && ((par.vbits[pix >> 5] >> (pix & 31)) & 1u);
           n_gain += ballot_count(inV && !inVj);
@@ -1030,7 +1032,7 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
     atomicAdd(&s_acc[2], n_dJr);
     atomicAdd(&s_acc[3], n_dJo);
     atomicAdd(&s_acc[4], n_rem);
-    if (out_gain) atomicAdd(&s_acc[7], n_gain);
+    if (GAIN) atomicAdd(&s_acc[7], n_gain);
   }
   __syncthreads();
   if (tid == 0) {
@@ -1038,7 +1040,7 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
     const int res = par.goal ? (*par.ucount - s_acc[4]) : 0;
     out_status[s] = valid ? 1 : 0;
     out_cost[s] = valid ? s_acc[2] + s_acc[3] + res : -1;
-    if (out_gain) out_gain[s] = valid ? s_acc[7] : -1;
+    if (GAIN) out_gain[s] = valid ? s_acc[7] : -1;
     if (out_comps) {  // an invalid successor stops at its first occluding band
       out_comps[5 * s + 0] = valid ? s_acc[0] : -1;
       out_comps[5 * s + 1] = valid ? s_acc[1] : -1;
@@ -1050,7 +1052,7 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
 }
 
 // One workgroup per successor of one parent.
-template <int NT, bool VP>
+template <int NT, bool VP, bool GAIN>
 __global__ void __launch_bounds__(NT)
     k_eval(SceneDev S, Parent par, const int2* __restrict__ cands, int n,
            int* __restrict__ out_cost, int* __restrict__ out_status, int* __restrict__ out_comps,
@@ -1061,8 +1063,8 @@ __global__ void __launch_bounds__(NT)
   __shared__ float4 s_pl[kLdsPlanes];
   const int s = blockIdx.x;
   if (s >= n) return;
-  eval_successor<NT, false, VP>(S, par, cands[s], s, out_cost, out_status, out_comps, out_gain,
-                                smem, s_bb, s_acc, s_pl);
+  eval_successor<NT, false, VP, GAIN>(S, par, cands[s], s, out_cost, out_status, out_comps,
+                                      out_gain, smem, s_bb, s_acc, s_pl);
 }
 
 // Persistent workgroups over a work queue of (parent slot, mesh, pose) items that
@@ -1105,8 +1107,8 @@ __global__ void __launch_bounds__(NT, 4)  // at least 4 waves per SIMD: <= 128 V
     par.has_parent = pd.has_parent;
     par.goal = pd.goal;
     const int scene = __builtin_amdgcn_readfirstlane(pd.scene);
-    eval_successor<NT, true, VP>(scenes[scene], par, make_int2(w.y, w.z), it, out_cost,
-                                 out_status, out_comps, nullptr, smem, s_bb, s_acc, s_pl);
+    eval_successor<NT, true, VP, false>(scenes[scene], par, make_int2(w.y, w.z), it, out_cost,
+                                        out_status, out_comps, nullptr, smem, s_bb, s_acc, s_pl);
   }
 }
 
@@ -1182,15 +1184,23 @@ static hipError_t allow_lds(K kernel, size_t lds) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
+template <int NT, bool VP, bool GAIN>
+static hipError_t launch_eval_g(const SceneDev& S, const Parent& par, const int2* cands, int n,
+                                int* cost, int* status, int* comps, int* gain, size_t lds,
+                                hipStream_t s) {
+  hipError_t e = allow_lds(&k_eval<NT, VP, GAIN>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_eval<NT, VP, GAIN>), dim3(n), dim3(NT), lds, s, S, par, cands, n, cost,
+                     status, comps, gain);
+  return hipGetLastError();
+}
+
 template <int NT, bool VP>
 static hipError_t launch_eval_t(const SceneDev& S, const Parent& par, const int2* cands, int n,
                                 int* cost, int* status, int* comps, int* gain, size_t lds,
                                 hipStream_t s) {
-  hipError_t e = allow_lds(&k_eval<NT, VP>, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_eval<NT, VP>), dim3(n), dim3(NT), lds, s, S, par, cands, n, cost, status,
-                     comps, gain);
-  return hipGetLastError();
+  return gain ? launch_eval_g<NT, VP, true>(S, par, cands, n, cost, status, comps, gain, lds, s)
+              : launch_eval_g<NT, VP, false>(S, par, cands, n, cost, status, comps, gain, lds, s);
 }
 
 template <bool VP>

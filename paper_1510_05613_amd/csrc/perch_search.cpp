@@ -24,7 +24,8 @@
 //     enter the inadmissible queue; the remaining children wait as one lazy block
 //     keyed at g(parent) (a lower bound, edge costs being >= 0) in the anchor queue
 //     and are evaluated when the anchor reaches them, so completeness and the
-//     w-bound are those of the focal search.
+//     w-bound are those of the focal search; the learned multi-heuristic variant
+//     adds h_overlap as a second inadmissible queue over the evaluated children.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -378,7 +379,9 @@ class Searcher {
   }
 
   // ---- learned ----
-  perch_status learned() {
+  // with_overlap: the paper's h_overlap as a second inadmissible queue over the
+  // children the network lets through (and those of popped lazy blocks).
+  perch_status learned(bool with_overlap) {
     if (!o_.cnn) return fail(PERCH_E_ARG, "the learned search needs a network");
     const int topk = o_.topk > 0 ? o_.topk : 64;
     const int P = (int)poses_.size();
@@ -467,21 +470,23 @@ class Searcher {
       launch_child_cands(d_idx2.as<int>(), k, d_dist.as<int>(), P, d_pose.as<int>(), dc, st0);
       int32_t* dcost = c_->s_out.as<int32_t>();
       int32_t* dstat = dcost + k;
-      st = perch_eval_children(c_, reinterpret_cast<const perch_object*>(dc), k, dcost, dstat,
-                               nullptr);
+      int32_t* dgain = dstat + k;
+      const perch_object* dco = reinterpret_cast<const perch_object*>(dc);
+      st = with_overlap ? perch_overlap_gain(c_, dco, k, dcost, dstat, dgain)
+                        : perch_eval_children(c_, dco, k, dcost, dstat, nullptr);
       if (st) return st;
       int2* hc = c_->s_hcands.as<int2>();
       int32_t* hout = c_->s_hout.as<int32_t>();
       HIP_TRY(hipMemcpyAsync(hc, dc, k * sizeof(int2), hipMemcpyDeviceToHost, st0));
-      HIP_TRY(hipMemcpyAsync(hout, dcost, 2 * (size_t)k * sizeof(int32_t), hipMemcpyDeviceToHost,
-                             st0));
+      HIP_TRY(hipMemcpyAsync(hout, dcost, (with_overlap ? 3 : 2) * (size_t)k * sizeof(int32_t),
+                             hipMemcpyDeviceToHost, st0));
       HIP_TRY(hipStreamSynchronize(st0));
       ++n_expanded_;
       n_evaluated_ += k;
       for (int i = 0; i < k; ++i) {
         const int s2 = hout[k + i];
         if (s2 == 1)
-          out.push_back({hc[i].x, hc[i].y, hout[i], 0});
+          out.push_back({hc[i].x, hc[i].y, hout[i], with_overlap ? hout[2 * k + i] : 0});
         else if (s2 == 0)
           ++n_invalid_;
         else
@@ -515,6 +520,14 @@ class Searcher {
     };
     std::priority_queue<int, std::vector<int>, decltype(a_less)> open(a_less), pending(a_less);
     std::priority_queue<int, std::vector<int>, decltype(d_less)> focal_q(d_less);
+    auto o_less = [&](int a, int b) {  // inadmissible: fewer points outside V_j, then g
+      const Node &x = nodes[a], &y = nodes[b];
+      if (x.hov != y.hov) return x.hov > y.hov;
+      if (x.g != y.g) return x.g > y.g;
+      return cmp_key(x, y) > 0;
+    };
+    std::priority_queue<int, std::vector<int>, decltype(o_less)> over_q(o_less);
+    nodes[0].hov = c_->n_points;  // h_overlap(root) = |I|
     auto live = [&](int id) {
       if (closed[id]) return false;
       if (nodes[id].lazy) return true;
@@ -558,15 +571,29 @@ class Searcher {
       if (have_ && !o_.anytime && (double)best_.g <= w * (double)gmin) break;  // w-bound met
       if (over_budget()) return PERCH_E_BUDGET;
       while (!pending.empty() && (double)nodes[pending.top()].g <= w * (double)gmin) {
-        if (live(pending.top())) focal_q.push(pending.top());
+        if (live(pending.top())) {
+          focal_q.push(pending.top());
+          if (with_overlap) over_q.push(pending.top());
+        }
         pending.pop();
       }
       while (!focal_q.empty() && !live(focal_q.top())) focal_q.pop();
+      while (!over_q.empty() && !live(over_q.top())) over_q.pop();
+      // round robin over the inadmissible queues, and the anchor when anytime
+      const int n_inad = with_overlap ? 2 : 1;
+      const int slot = (int)(expansions_ % (n_inad + (o_.anytime ? 1 : 0)));
       int pick = -1;
-      if (!focal_q.empty() && (expansions_ % 2 == 0 || !o_.anytime)) {
-        pick = focal_q.top();
-        focal_q.pop();
-      } else {
+      for (int t = 0; t < n_inad && pick < 0 && slot < n_inad; ++t) {
+        const int q = (slot + t) % n_inad;
+        if (q == 0 && !focal_q.empty()) {
+          pick = focal_q.top();
+          focal_q.pop();
+        } else if (q == 1 && !over_q.empty()) {
+          pick = over_q.top();
+          over_q.pop();
+        }
+      }
+      if (pick < 0) {
         pick = open.top();
         open.pop();
       }
@@ -575,7 +602,7 @@ class Searcher {
       const Node cur = nodes[pick];
       if (cur.lazy) {  // the rest of a parent's children: evaluate them all
         const Node par = nodes[cur.parent];
-        perch_status st = expand(par, kids);
+        perch_status st = expand(par, kids, with_overlap);
         if (st) return st;
         for (const Child& ch : kids) push_child(par, cur.parent, ch);
         continue;
@@ -640,7 +667,7 @@ class Searcher {
 extern "C" perch_status perch_search(perch_ctx* c, const perch_search_opts* opts,
                                      perch_result* out) {
   if (!c || !opts || !out) return fail(PERCH_E_ARG, "null argument");
-  if (opts->mode < PERCH_SEARCH_EXHAUSTIVE || opts->mode > PERCH_SEARCH_MHA)
+  if (opts->mode < PERCH_SEARCH_EXHAUSTIVE || opts->mode > PERCH_SEARCH_LEARNED_MHA)
     return fail(PERCH_E_ARG, "unknown search mode %d", opts->mode);
   if (opts->mode >= PERCH_SEARCH_FOCAL && !(opts->w >= 1.0f))
     return fail(PERCH_E_ARG, "focal, learned and multi-heuristic searches need w >= 1");
@@ -649,8 +676,8 @@ extern "C" perch_status perch_search(perch_ctx* c, const perch_search_opts* opts
   if (st) return st;
   if (opts->mode == PERCH_SEARCH_EXHAUSTIVE)
     st = s.exhaustive();
-  else if (opts->mode == PERCH_SEARCH_LEARNED)
-    st = s.learned();
+  else if (opts->mode == PERCH_SEARCH_LEARNED || opts->mode == PERCH_SEARCH_LEARNED_MHA)
+    st = s.learned(opts->mode == PERCH_SEARCH_LEARNED_MHA);
   else if (opts->mode == PERCH_SEARCH_MHA)
     st = s.best_first(2);
   else

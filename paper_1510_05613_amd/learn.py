@@ -277,7 +277,7 @@ def max_block(ds: Dataset, crops_per_batch: int) -> tuple:
     return max(crops_per_batch, most_c), max(most_b, most_p)
 
 
-SEARCHES = ("exhaustive", "ucs", "focal", "mha", "learned", "random_init")
+SEARCHES = ("exhaustive", "ucs", "focal", "mha", "learned", "learned_mha", "random_init")
 
 
 def gain(net: "perch.Cnn", control: "perch.Cnn", indices: Sequence[int], config: int = 4,
@@ -288,7 +288,8 @@ def gain(net: "perch.Cnn", control: "perch.Cnn", indices: Sequence[int], config:
     searches; focal is the paper's inadmissible depth heuristic without learning and
     mha the paper's own configuration (h_depth and h_overlap, Focal-MHA*);
     learned and random_init are the learned search with the trained and an
-    untrained network.  The best scene is the optimum returned by a plain search
+    untrained network, learned_mha the learned search with h_overlap added as a
+    second inadmissible queue.  The best scene is the optimum returned by a plain search
     that finished; a search that never held it counts as not reaching it (None).
     budget_s > 0 limits every search; max_scenes > 0 stops after that many scenes
     (indices the generator cannot satisfy are skipped)."""
@@ -315,6 +316,8 @@ def gain(net: "perch.Cnn", control: "perch.Cnn", indices: Sequence[int], config:
             mha=lambda: ctx.search(perch.SEARCH_MHA, w=w, anytime=True, budget_s=budget_s),
             learned=lambda: ctx.search(perch.SEARCH_LEARNED, w=w, anytime=True, cnn=net,
                                        topk=topk, budget_s=budget_s),
+            learned_mha=lambda: ctx.search(perch.SEARCH_LEARNED_MHA, w=w, anytime=True, cnn=net,
+                                           topk=topk, budget_s=budget_s),
             random_init=lambda: ctx.search(perch.SEARCH_LEARNED, w=w, anytime=True, cnn=control,
                                            topk=topk, budget_s=budget_s))
         res = {k: run[k]() for k in names}

@@ -34,6 +34,7 @@ EXPORTS = ("perch_create", "perch_destroy", "perch_set_observation", "perch_add_
            "perch_cnn_train_step", "perch_cnn_gradients", "perch_last_error")
 
 SEARCH_EXHAUSTIVE, SEARCH_UCS, SEARCH_FOCAL, SEARCH_LEARNED, SEARCH_MHA = 0, 1, 2, 3, 4
+SEARCH_LEARNED_MHA = 5
 
 
 class PerchError(RuntimeError):

@@ -64,15 +64,20 @@ def test_learned_search_needs_a_network():
         ctx.search(perch.SEARCH_LEARNED, w=2.0)
 
 
+LEARNED_MODES = [perch.SEARCH_LEARNED, perch.SEARCH_LEARNED_MHA]
+
+
+@pytest.mark.parametrize("mode", LEARNED_MODES)
 @pytest.mark.parametrize("k", [0, 1, 2])
 @pytest.mark.parametrize("topk", [1, 64])
-def test_learned_anytime_reaches_the_exhaustive_optimum(k, topk):
+def test_learned_anytime_reaches_the_exhaustive_optimum(k, topk, mode):
     """Any network, any k: run until the anchor's bound meets the incumbent, the
-    learned search returns the optimum of the whole tree."""
+    learned search (with or without the h_overlap queue) returns the optimum of
+    the whole tree."""
     sc = held_out_scene(k)
     ctx = perch.context_from_scene(sc)
     ex = ctx.search(perch.SEARCH_EXHAUSTIVE)
-    r = ctx.search(perch.SEARCH_LEARNED, w=2.0, anytime=True, cnn=random_net(k), topk=topk)
+    r = ctx.search(mode, w=2.0, anytime=True, cnn=random_net(k), topk=topk)
     assert r["found"] and not r["budget_exhausted"]
     assert r["cost"] == ex["cost"]
     assert r["lower_bound"] >= r["cost"]  # the search proved its goal optimal
@@ -80,12 +85,13 @@ def test_learned_anytime_reaches_the_exhaustive_optimum(k, topk):
     assert 0 <= r["n_evaluated_best"] <= r["n_evaluated"]
 
 
+@pytest.mark.parametrize("mode", LEARNED_MODES)
 @pytest.mark.parametrize("w", [1.0, 1.5, 3.0])
-def test_learned_first_goal_within_w(w):
+def test_learned_first_goal_within_w(w, mode):
     sc = held_out_scene(3)
     ctx = perch.context_from_scene(sc)
     opt = ctx.search(perch.SEARCH_UCS)["cost"]
-    r = ctx.search(perch.SEARCH_LEARNED, w=w, anytime=False, cnn=random_net(1), topk=32)
+    r = ctx.search(mode, w=w, anytime=False, cnn=random_net(1), topk=32)
     assert r["found"]
     assert r["cost"] <= w * opt + 1e-9
     assert r["lower_bound"] <= opt
