@@ -165,11 +165,12 @@ __device__ __forceinline__ void map_vertex(const PoseMap& m, const float4 v, flo
 // triangle coverage: integer edge functions, top-left rule, front faces only
 // ---------------------------------------------------------------------------
 
-// floor(e / a) for |e| < 2^29 and 1 <= a < 2^22: the float estimate is off by at
-// most one (|e| rounds by <= 16, the product by a few ulps of a quotient below
-// 2^21), and the exact 24-bit products fix it.
-__device__ __forceinline__ int floor_div(int e, int a) {
-  int q = (int)floorf((float)e * __builtin_amdgcn_rcpf((float)a));
+// floor(e / a) for |e| < 2^29 and 1 <= a < 2^22 with |e / a| < 2^23, given
+// ra = rcp(a): the float estimate is off by at most one (|e| rounds by <= 16, the
+// product by a few ulps of a quotient below 2^21), and the exact 24-bit products
+// fix it.  Quotients outside that range come out wrong and must go unused.
+__device__ __forceinline__ int floor_div(int e, int a, float ra) {
+  int q = (int)floorf((float)e * ra);
   q += (__mul24(q + 1, a) <= e) ? 1 : 0;
   q -= (__mul24(q, a) > e) ? 1 : 0;
   return q;
@@ -202,20 +203,21 @@ __device__ __forceinline__ void edge_dda(int e, int dy, int dx, int ja, int& rlo
   const int s = 256 * dy, t = 256 * dx;
   const int a = abs(s);
   const bool flat = a == 0;
-  const int aa = flat ? 1 : a;
-  const int q = floor_div(e, aa), dq = floor_div(t, aa);
+  // one divisor per edge: |s| for a sloped edge, |t| for a horizontal one (t != 0
+  // for an edge of non-zero length, and both are multiples of 256)
+  const int d = max(1, flat ? abs(t) : a);
+  const float rd = __builtin_amdgcn_rcpf((float)d);
+  const int q = floor_div(e, d, rd), dq = floor_div(t, d, rd);
   g.q = flat ? (1 << 20) : q;
-  g.rem = flat ? 0 : e - q * aa;
+  g.rem = flat ? 0 : e - q * d;
   g.dq = flat ? 0 : dq;
-  g.dr = flat ? 0 : t - dq * aa;
-  g.a = aa;
+  g.dr = flat ? 0 : t - dq * d;
+  g.a = d;
   g.pos = flat || s > 0;
   // horizontal edge: e + (j - ja) t >= 0 on rows j >= ja - floor(e / t) (t > 0) or
-  // j <= ja + floor(e / -t) (t < 0); t != 0 for an edge of non-zero length
-  // (for a sloped edge the quotient below is unused and may be garbage)
-  const int fr = floor_div(e, t != 0 ? abs(t) : 1);  // floor(e / |t|)
-  rlo = (flat && t > 0) ? max(rlo, ja - fr) : rlo;
-  rhi = (flat && t < 0) ? min(rhi, ja + fr) : rhi;
+  // j <= ja + floor(e / -t) (t < 0), with q = floor(e / |t|) here
+  rlo = (flat && t > 0) ? max(rlo, ja - q) : rlo;
+  rhi = (flat && t < 0) ? min(rhi, ja + q) : rhi;
 }
 
 // Calls emit(i, j) for every pixel centre (256 i, 256 j) covered by the triangle
@@ -394,6 +396,12 @@ __device__ __forceinline__ float3 apply_obj_map(const ObjMap& m, float3 p) {
                      fmaf(m.a[6], p.x, fmaf(m.a[7], p.y, fmaf(m.a[8], p.z, m.b[2]))));
 }
 
+// o is on the outer side of face plane (n, w): n.o - w > 0, in fused products (a
+// point within float rounding of the plane may fall on either side).
+__device__ __forceinline__ bool plane_out(const float4 pl, float3 o) {
+  return fmaf(pl.x, o.x, fmaf(pl.y, o.y, fmaf(pl.z, o.z, -pl.w))) > 0.0f;
+}
+
 // p in V(O) as in_volume, with the box corners and the planes already at hand
 // (the planes staged in LDS by the successor kernel).
 __device__ __forceinline__ bool in_volume_at(const float4 lo, const float4 hi,
@@ -401,10 +409,8 @@ __device__ __forceinline__ bool in_volume_at(const float4 lo, const float4 hi,
   if (o.x < lo.x - 1e-5f || o.y < lo.y - 1e-5f || o.z < lo.z - 1e-5f || o.x > hi.x + 1e-5f ||
       o.y > hi.y + 1e-5f || o.z > hi.z + 1e-5f)
     return false;
-  for (int f = 0; f < n_planes; ++f) {
-    const float4 pl = planes[f];
-    if (pl.x * o.x + pl.y * o.y + pl.z * o.z - pl.w > 0.0f) return false;
-  }
+  for (int f = 0; f < n_planes; ++f)
+    if (plane_out(planes[f], o)) return false;
   return true;
 }
 
@@ -412,15 +418,8 @@ __device__ __forceinline__ bool in_volume_at(const float4 lo, const float4 hi,
 // inner side of every plane.
 __device__ __forceinline__ bool in_volume(const Meshes& M, int mesh, float3 o) {
   const float4 lo = M.aabb[2 * mesh], hi = M.aabb[2 * mesh + 1];
-  if (o.x < lo.x - 1e-5f || o.y < lo.y - 1e-5f || o.z < lo.z - 1e-5f || o.x > hi.x + 1e-5f ||
-      o.y > hi.y + 1e-5f || o.z > hi.z + 1e-5f)
-    return false;
   const int2 fr = M.frange[mesh];
-  for (int f = 0; f < fr.y; ++f) {
-    const float4 pl = M.planes[fr.x + f];
-    if (pl.x * o.x + pl.y * o.y + pl.z * o.z - pl.w > 0.0f) return false;
-  }
-  return true;
+  return in_volume_at(lo, hi, M.planes + fr.x, fr.y, o);
 }
 
 // Pixel window radii (columns, rows) that hold every point within dwin of the
