@@ -58,6 +58,9 @@ def lib():
         L.orc_eval.argtypes = [P, C.c_int32, P, P, C.c_int32, P, P, P, P, P, P]
         L.orc_jtree.argtypes = [P, C.c_int32, P, P, P]
         L.orc_overlap.argtypes = [P, C.c_int32, P, P, C.c_int32, P, P, P, P, P]
+        L.orc_icp_step.argtypes = [C.c_int32, P, P, P, P]
+        L.orc_icp.argtypes = [P, C.c_int32, P, P, C.c_int32, P, P, C.c_int32, C.c_double, P, P,
+                              P, P]
         for f in (L.orc_search_exhaustive, L.orc_search_ucs, L.orc_bruteforce_joint):
             f.argtypes = [P, C.c_int32, P, P, P, P]
         _lib = L
@@ -173,6 +176,23 @@ class Oracle:
             raise RuntimeError(f"orc_overlap failed ({rc})")
         return int(hp[0]), hc, fl
 
+    def icp(self, parent_mesh, parent_pose, cand_mesh, cand_pose, iters: int = 10,
+            radius: float = 0.02):
+        """Local ICP (Sec. V-A) of each candidate under the parent.  Returns
+        (poses (n, 4) float64 (x, y, cos, sin), n_match (n,), status (n,), flags (n,))."""
+        pm, pp = _i32(parent_mesh), _i32(parent_pose)
+        cm, cp = _i32(cand_mesh), _i32(cand_pose)
+        n = len(cm)
+        out = np.zeros((max(n, 1), 4), np.float64)
+        nm = np.zeros(max(n, 1), np.int32)
+        st = np.zeros(max(n, 1), np.int32)
+        fl = np.zeros(max(n, 1), np.int32)
+        rc = lib().orc_icp(self.h, len(pm), _ptr(pm), _ptr(pp), n, _ptr(cm), _ptr(cp),
+                           int(iters), float(radius), _ptr(out), _ptr(nm), _ptr(st), _ptr(fl))
+        if rc:
+            raise RuntimeError(f"orc_icp failed ({rc})")
+        return out[:n], nm[:n], st[:n], fl[:n]
+
     def jtree(self, mesh, pose) -> dict:
         m, p = _i32(mesh), _i32(pose)
         out = np.zeros(6, np.int64)
@@ -204,6 +224,19 @@ class Oracle:
         r = self._search(lib().orc_bruteforce_joint, pose_subset)
         r["n_valid"] = r.pop("n_eval")
         return r
+
+
+def icp_step(a, p, nrm):
+    """(phi, tx, ty): the linearised point-to-plane step for pairs a (n, 3) -> p
+    (n, 3) with unit normals nrm (n, 3) at p, world frame."""
+    a = np.ascontiguousarray(a, np.float64).reshape(-1, 3)
+    p = np.ascontiguousarray(p, np.float64).reshape(-1, 3)
+    nrm = np.ascontiguousarray(nrm, np.float64).reshape(-1, 3)
+    out = np.zeros(3, np.float64)
+    rc = lib().orc_icp_step(len(a), _ptr(a), _ptr(p), _ptr(nrm), _ptr(out))
+    if rc:
+        raise RuntimeError(f"orc_icp_step failed ({rc})")
+    return tuple(float(v) for v in out)
 
 
 def render_fn(sensor, library, mesh_ids, pose_idx, poses) -> np.ndarray:

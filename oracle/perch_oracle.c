@@ -15,6 +15,8 @@
  *               successor set Eq.(3) and edge cost Eq.(4).
  *   Sec. IV-B   exhaustive tree search (Theorems 1-2 with w = 1), used here as
  *               exhaustive enumeration and uniform-cost search.
+ *   Sec. V-A    local ICP alignment of each new object's non-occluded part
+ *               (compensating for a coarse pose discretization).
  *
  * Readings where the paper is silent (each one is listed in the design notes):
  *   - a rendered point cloud holds one point per covered pixel centre, at the
@@ -713,6 +715,240 @@ int orc_overlap(const orc_scene* sc, int32_t j, const int32_t* pm, const int32_t
   free(inVj);
   free(nearVj);
   return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* local ICP alignment (Sec. V-A, compensating for discretization)           */
+/* ------------------------------------------------------------------------- */
+
+/* One linearised point-to-plane step (Chen and Medioni's ICP, restricted to the
+ * table-plane motions).  For pairs (a_k, p_k) with unit normals n_k at p_k and
+ * the centroid c of the a_k, a small rotation phi about the vertical axis through
+ * c followed by a translation (tx, ty) leaves the residual n.(a + phi z x (a - c)
+ * + t - p); the step minimises the sum of its squares, with the normal matrix
+ * damped by 1e-6 of its diagonal (plus 1e-12) so that motions the pairs leave
+ * unconstrained stay put.  out = (phi, tx', ty'): the same motion as a rotation
+ * about the world z axis followed by the translation t' = c + t - R(phi) c. */
+int orc_icp_step(int32_t n, const double* a, const double* p, const double* nrm, double* out) {
+  if (n < 1 || !a || !p || !nrm || !out) return -1;
+  double cx = 0, cy = 0;
+  for (int k = 0; k < n; ++k) {
+    cx += a[3 * k];
+    cy += a[3 * k + 1];
+  }
+  cx /= n;
+  cy /= n;
+  double A[3][3] = {{0}}, b[3] = {0};
+  for (int k = 0; k < n; ++k) {
+    const double* ak = a + 3 * k;
+    const double* pk = p + 3 * k;
+    const double* nk = nrm + 3 * k;
+    const double J[3] = {nk[1] * (ak[0] - cx) - nk[0] * (ak[1] - cy), nk[0], nk[1]};
+    const double r = nk[0] * (ak[0] - pk[0]) + nk[1] * (ak[1] - pk[1]) + nk[2] * (ak[2] - pk[2]);
+    for (int u = 0; u < 3; ++u) {
+      for (int v = 0; v < 3; ++v) A[u][v] += J[u] * J[v];
+      b[u] -= J[u] * r;
+    }
+  }
+  for (int u = 0; u < 3; ++u) A[u][u] += 1e-6 * A[u][u] + 1e-12;
+  /* Cramer's rule on the symmetric positive definite 3x3 system */
+  const double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
+                     A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+                     A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+  double x[3];
+  for (int c = 0; c < 3; ++c) {
+    double M[3][3];
+    for (int u = 0; u < 3; ++u)
+      for (int v = 0; v < 3; ++v) M[u][v] = v == c ? b[u] : A[u][v];
+    x[c] = (M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) -
+            M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
+            M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0])) / det;
+  }
+  const double co = cos(x[0]), si = sin(x[0]);
+  out[0] = x[0];
+  out[1] = cx + x[1] - (co * cx - si * cy);
+  out[2] = cy + x[2] - (si * cx + co * cy);
+  return 0;
+}
+
+static int near_half(double f) { /* f within 1e-4 px of a rounding boundary */
+  const double r = f - floor(f);
+  return fabs(r - 0.5) < 1e-4;
+}
+
+/* Surface normal of the observed point at pixel (u, v), world frame, unit length
+ * and facing the camera: the cross product of the central differences of its four
+ * pixel neighbours, which must all be observed and within `radius` of it.
+ * Returns 0 when there is none; *near is set when a neighbour's distance lies
+ * within FLAG_EPS of the radius. */
+static int observed_normal(const orc_scene* sc, int u, int v, double radius, double* n,
+                           int* near) {
+  const int W = sc->W, H = sc->H;
+  if (u < 1 || v < 1 || u > W - 2 || v > H - 2) return 0;
+  const int c = sc->pix2pt[(size_t)v * W + u];
+  const int nb[4] = {sc->pix2pt[(size_t)v * W + u + 1], sc->pix2pt[(size_t)v * W + u - 1],
+                     sc->pix2pt[(size_t)(v + 1) * W + u], sc->pix2pt[(size_t)(v - 1) * W + u]};
+  if (c < 0 || nb[0] < 0 || nb[1] < 0 || nb[2] < 0 || nb[3] < 0) return 0;
+  const double* pc = sc->I_w + 3 * (size_t)c;
+  int ok = 1;
+  for (int k = 0; k < 4; ++k) {
+    const double dk = sqrt(d2(pc, sc->I_w + 3 * (size_t)nb[k]));
+    if (fabs(dk - radius) <= FLAG_EPS) *near = 1;
+    if (dk > radius) ok = 0;
+  }
+  if (!ok) return 0;
+  const double *px1 = sc->I_w + 3 * (size_t)nb[0], *px0 = sc->I_w + 3 * (size_t)nb[1];
+  const double *py1 = sc->I_w + 3 * (size_t)nb[2], *py0 = sc->I_w + 3 * (size_t)nb[3];
+  const double e1[3] = {px1[0] - px0[0], px1[1] - px0[1], px1[2] - px0[2]};
+  const double e2[3] = {py1[0] - py0[0], py1[1] - py0[1], py1[2] - py0[2]};
+  double m[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                 e1[0] * e2[1] - e1[1] * e2[0]};
+  const double len = sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
+  if (!(len > 0)) return 0;
+  /* the camera centre in the world frame is -Rinv t */
+  double cw[3];
+  for (int r = 0; r < 3; ++r)
+    cw[r] = -(sc->Rinv[3 * r] * sc->t[0] + sc->Rinv[3 * r + 1] * sc->t[1] +
+              sc->Rinv[3 * r + 2] * sc->t[2]);
+  const double f = m[0] * (cw[0] - pc[0]) + m[1] * (cw[1] - pc[1]) + m[2] * (cw[2] - pc[2]);
+  const double sg = f < 0 ? -1.0 : 1.0;
+  for (int r = 0; r < 3; ++r) n[r] = sg * m[r] / len;
+  return 1;
+}
+
+/* ICP of candidate (mesh, pose) against I over the non-occluded part of its
+ * render, for `iters` rounds of projective association (the observed point at
+ * the pixel nearest the projection of the moved model point, kept when it has a
+ * normal and lies within `radius`) and a point-to-plane step.  Writes the
+ * adjusted pose (x, y, cos, sin) and the match count of the last association;
+ * status 0 when the candidate occludes the parent (no alignment: the grid pose
+ * is returned). */
+static int icp_one(const orc_scene* sc, const double* Dp, int mesh, int pose, int iters,
+                   double radius, scratch_t* w, double* pose_out, int32_t* n_match,
+                   int32_t* status, int32_t* flags) {
+  const int W = sc->W, H = sc->H;
+  const size_t npx = (size_t)W * H;
+  for (size_t i = 0; i < npx; ++i) w->DO[i] = INFINITY;
+  int rc = render_into(sc, mesh, pose, 1, w->DO, w->cam, w->UV, w->UV + sc->max_v + 1);
+  if (rc) return rc;
+  int valid = 1, fl = 0, nq = 0;
+  for (size_t i = 0; i < npx; ++i) {
+    const double z = w->DO[i];
+    if (!(z < INFINITY)) continue;
+    if (Dp[i] < INFINITY) {
+      if (z < Dp[i]) valid = 0;
+      if (fabs(z - Dp[i]) <= FLAG_EPS) fl = 1;
+    } else {
+      ++nq;
+    }
+  }
+  const float* pz = sc->poses + 4 * (size_t)pose;
+  for (int k = 0; k < 4; ++k) pose_out[k] = pz[k];
+  *n_match = 0;
+  if (!valid) {
+    *status = 0;
+    *flags = fl;
+    return 0;
+  }
+  /* model points: the non-occluded part dR, in the world frame */
+  double* Q = (double*)malloc(sizeof(double) * 3 * (size_t)(nq + 1));
+  double* A = (double*)malloc(sizeof(double) * 9 * (size_t)(nq + 1));
+  if (!Q || !A) {
+    free(Q); free(A);
+    return -3;
+  }
+  double* Pm = A + 3 * (size_t)(nq + 1);
+  double* Nm = Pm + 3 * (size_t)(nq + 1);
+  int m = 0;
+  for (int v = 0; v < H; ++v)
+    for (int u = 0; u < W; ++u) {
+      const size_t i = (size_t)v * W + u;
+      if (!(w->DO[i] < INFINITY) || Dp[i] < INFINITY) continue;
+      double q[3], d[3];
+      backproject(sc, u, v, w->DO[i], q);
+      for (int r = 0; r < 3; ++r) d[r] = q[r] - sc->t[r];
+      for (int r = 0; r < 3; ++r)
+        Q[3 * m + r] = sc->Rinv[3 * r] * d[0] + sc->Rinv[3 * r + 1] * d[1] + sc->Rinv[3 * r + 2] * d[2];
+      ++m;
+    }
+  const float* M = sc->s.cam_from_world;
+  const double r2 = radius * radius;
+  double phi = 0, tx = 0, ty = 0;
+  for (int it = 0; it < iters; ++it) {
+    const double c = cos(phi), s = sin(phi);
+    int nm = 0;
+    for (int k = 0; k < m; ++k) {
+      const double* q = Q + 3 * k;
+      const double a[3] = {c * q[0] - s * q[1] + tx, s * q[0] + c * q[1] + ty, q[2]};
+      double ac[3];
+      for (int r = 0; r < 3; ++r)
+        ac[r] = (double)M[4 * r] * a[0] + (double)M[4 * r + 1] * a[1] +
+                (double)M[4 * r + 2] * a[2] + (double)M[4 * r + 3];
+      if (!(ac[2] > 0)) continue;
+      const double uf = sc->fx * ac[0] / ac[2] + sc->cx, vf = sc->fy * ac[1] / ac[2] + sc->cy;
+      if (near_half(uf) || near_half(vf)) ++fl;
+      const double iu = floor(uf + 0.5), iv = floor(vf + 0.5);
+      if (iu < 0 || iu > W - 1 || iv < 0 || iv > H - 1) continue;
+      const int pt = sc->pix2pt[(size_t)iv * W + (size_t)iu];
+      if (pt < 0) continue;
+      double nrm[3];
+      int near = 0;
+      const int has_n = observed_normal(sc, (int)iu, (int)iv, radius, nrm, &near);
+      fl += near;
+      if (!has_n) continue;
+      const double* p = sc->I_w + 3 * (size_t)pt;
+      const double dd = d2(a, p);
+      if (fabs(sqrt(dd) - radius) <= FLAG_EPS) ++fl;
+      if (dd > r2) continue;
+      for (int r = 0; r < 3; ++r) {
+        A[3 * nm + r] = a[r];
+        Pm[3 * nm + r] = p[r];
+        Nm[3 * nm + r] = nrm[r];
+      }
+      ++nm;
+    }
+    *n_match = nm;
+    if (nm < 3) break;
+    double st[3];
+    orc_icp_step(nm, A, Pm, Nm, st);
+    /* compose: the step after the motion so far */
+    const double cd = cos(st[0]), sd = sin(st[0]);
+    const double nx = cd * tx - sd * ty + st[1], ny = sd * tx + cd * ty + st[2];
+    phi += st[0];
+    tx = nx;
+    ty = ny;
+  }
+  free(Q); free(A);
+  /* adjusted pose: the motion applied after the grid placement */
+  const double c = cos(phi), s = sin(phi);
+  const double x = pz[0], y = pz[1], pc = pz[2], ps = pz[3];
+  pose_out[0] = c * x - s * y + tx;
+  pose_out[1] = s * x + c * y + ty;
+  pose_out[2] = pc * c - ps * s;
+  pose_out[3] = ps * c + pc * s;
+  *status = 1;
+  *flags = fl;
+  return 0;
+}
+
+int orc_icp(const orc_scene* sc, int32_t j, const int32_t* pm, const int32_t* pp, int32_t n,
+            const int32_t* cm, const int32_t* cp, int32_t iters, double radius, double* pose_out,
+            int32_t* n_match, int32_t* status, int32_t* flags) {
+  if (!sc || j < 0 || n < 0 || iters < 0 || !(radius > 0) || (j > 0 && (!pm || !pp)) ||
+      (n > 0 && (!cm || !cp || !pose_out || !n_match || !status || !flags)))
+    return -1;
+  if (!sc->I_w) return -1;
+  if (check_objects(sc, j, pm, pp) || check_objects(sc, n, cm, cp)) return -2;
+  parent_buf_t pb;
+  int rc = parent_build(sc, j, pm, pp, &pb);
+  scratch_t w;
+  scratch_init(sc, &w);
+  for (int c = 0; c < n && !rc; ++c)
+    rc = icp_one(sc, pb.D, cm[c], cp[c], iters, radius, &w, pose_out + 4 * (size_t)c,
+                 n_match + c, status + c, flags + c);
+  scratch_free(&w);
+  parent_free(&pb);
+  return rc;
 }
 
 static int cmp_pair(const int32_t* a, const int32_t* b) {

@@ -81,6 +81,30 @@ int orc_overlap(const orc_scene* sc, int32_t j, const int32_t* par_mesh,
                 const int32_t* cand_pose, int64_t* h_parent, int64_t* h_child,
                 int32_t* flags);
 
+/* One linearised point-to-plane step over n pairs (a_k, p_k) with unit normals
+ * nrm_k at p_k (3 doubles each, world frame): the small table-plane motion (a
+ * rotation about the vertical axis through the centroid of the a_k, then a
+ * translation) minimising sum (n.(moved a - p))^2 to first order, damped by 1e-6
+ * of the normal matrix's diagonal plus 1e-12.  out = (phi, tx, ty) of the same
+ * motion written as a rotation about the world z axis, then a translation. */
+int orc_icp_step(int32_t n, const double* a, const double* p, const double* nrm, double* out);
+
+/* Local ICP (Sec. V-A) of each candidate's non-occluded part under the parent
+ * s = {(par_mesh[k], par_pose[k]) : k < j}: `iters` rounds of projective
+ * association (observed point at the pixel nearest the moved model point, kept
+ * when it has a surface normal and lies within `radius` metres) and a
+ * point-to-plane step (orc_icp_step).  The normal of an observed point is the
+ * cross product of the central differences of its four pixel neighbours, all
+ * observed and within `radius` of it, turned towards the camera.  pose_out (n x 4): adjusted
+ * (x, y, cos, sin); n_match: matches of the last association; status 1 aligned,
+ * 0 the candidate occludes the parent (grid pose returned); flags: associations
+ * decided within 1e-4 px of a rounding boundary or 1e-6 m of the radius (match
+ * or normal neighbourhood), plus 1 for a parent depth tie. */
+int orc_icp(const orc_scene* sc, int32_t j, const int32_t* par_mesh, const int32_t* par_pose,
+            int32_t n, const int32_t* cand_mesh, const int32_t* cand_pose, int32_t iters,
+            double radius, double* pose_out, int32_t* n_match, int32_t* status,
+            int32_t* flags);
+
 int orc_jtree(const orc_scene* sc, int32_t K, const int32_t* mesh,
               const int32_t* pose, int64_t* out);
 
