@@ -101,8 +101,18 @@ perch_status perch_add_mesh(perch_ctx* ctx, int32_t mesh_id, const float* verts,
                             const float* planes, int32_t n_planes);
 
 /* Sets the discretised pose set (Sec. IV-E, the x/y/yaw grid): host, P x 4 rows
- * (x, y, cos theta, sin theta). */
+ * (x, y, cos theta, sin theta).  Empties the pose arena (perch_set_pose_arena). */
 perch_status perch_set_poses(perch_ctx* ctx, const float* poses, int32_t P);
+
+/* Reserves device room for `capacity` poses after the P grid poses: the arena
+ * where perch_icp_children stores the poses it adjusts (indices P, P + 1, ...),
+ * usable wherever a pose index is.  Empties the arena (earlier arena indices become
+ * invalid) and forgets the materialised parent.  Synchronous. */
+perch_status perch_set_pose_arena(perch_ctx* ctx, int32_t capacity);
+
+/* Copies poses [first, first + n) of the table (grid, then arena) to host memory,
+ * n x 4 floats (x, y, cos, sin).  Synchronous. */
+perch_status perch_get_poses(perch_ctx* ctx, int32_t first, int32_t n, float* poses_host);
 
 /* Sets the known multiset of K <= 8 mesh ids in the scene (Sec. III assumptions);
  * the goal level of the tree is K. */
@@ -139,6 +149,27 @@ perch_status perch_eval_children(perch_ctx* ctx, const perch_object* cands_dev, 
  * points within 1e-5 m of a boundary).  gain_dev: device, n int32.  Asynchronous. */
 perch_status perch_overlap_gain(perch_ctx* ctx, const perch_object* cands_dev, int32_t n,
                                 int32_t* cost_dev, int32_t* status_dev, int32_t* gain_dev);
+
+/* Local ICP alignment (Sec. V-A, compensating for discretization): for each
+ * candidate (mesh, pose) of the parent last set, renders it, takes the part not
+ * covered by the parent (dR) and runs `iters` ICP rounds against the observation:
+ * each model point, moved by the motion so far, is paired with the observed point
+ * at the pixel nearest its projection when that point has a surface normal (cross
+ * product of its four pixel neighbours' differences, all observed and within
+ * `radius`) and lies within `radius` metres (2 cm in the paper, Sec. V-B); one
+ * point-to-plane step (Chen and Medioni) then solves for a rotation about the
+ * vertical axis through the pairs' centroid and a table-plane translation (damped
+ * 3 x 3 normal equations).  Fewer than 3 pairs end the rounds.  The adjusted pose
+ * (the motion applied after the grid placement) goes to arena slot arena_used + i,
+ * and adjusted_dev[i] = (mesh, P + arena_used + i) can be evaluated with
+ * perch_eval_children.  status_dev: 1 aligned, 0 the candidate occludes the parent
+ * (Eq. 3; grid pose kept), -2 vertex stage failed, -3 footprint larger than the
+ * ICP tile, -4 candidate out of range; n_match_dev: pairs of the last round.
+ * Candidates, outputs: device arrays of n.  Meshes of at most 5,120 vertices.
+ * PERCH_E_ARG when the arena lacks room for n.  Asynchronous. */
+perch_status perch_icp_children(perch_ctx* ctx, const perch_object* cands_dev, int32_t n,
+                                int32_t iters, float radius, perch_object* adjusted_dev,
+                                int32_t* n_match_dev, int32_t* status_dev);
 
 /* Renders objects (host array objs[0..n)) to depth images (device output, float32,
  * +inf where uncovered): composite != 0 writes one H*W image holding the minimum
@@ -291,6 +322,11 @@ typedef struct {
   perch_cnn* cnn;              /* LEARNED(_MHA): the network (created with capacity    */
                                /* for one crop per pose cell and one pair per child)   */
   int32_t topk;                /* LEARNED: children evaluated exactly per expansion    */
+  int32_t icp_iters;           /* UCS/FOCAL/MHA: > 0 aligns every child by local ICP   */
+                               /* (perch_icp_children) before its edge cost is taken;  */
+                               /* the search empties the pose arena first and needs    */
+                               /* room for every child it evaluates                    */
+  float icp_radius;            /* ICP association radius in metres (0: 0.02)           */
 } perch_search_opts;
 
 typedef struct {

@@ -92,7 +92,7 @@ perch_status upload_meshes(perch_ctx* c) {
 static bool objects_ok(const perch_ctx* c, const perch_object* o, int n) {
   for (int k = 0; k < n; ++k)
     if (o[k].mesh_id < 0 || o[k].mesh_id >= (int)c->meshes.size() || o[k].pose_idx < 0 ||
-        o[k].pose_idx >= c->P)
+        o[k].pose_idx >= c->n_poses())
       return false;
   return true;
 }
@@ -201,7 +201,7 @@ void perch_destroy(perch_ctx* c) {
   for (DevBuf* b : {&c->verts, &c->tris, &c->planes, &c->range, &c->frange, &c->aabb, &c->poses,
                     &c->obs, &c->obs_range, &c->h_keys, &c->h_cells, &c->h_pts, &c->h_counts, &c->par_depth,
                     &c->par_ubits, &c->par_ucount, &c->par_vbits, &c->s_cands, &c->s_out,
-                    &c->cnn_desc})
+                    &c->s_adj, &c->icp_pn, &c->cnn_desc})
     b->release();
   c->s_hcands.release();
   c->s_hout.release();
@@ -267,6 +267,7 @@ static perch_status build_observation(perch_ctx* c) {
   HIP_TRY(hipStreamSynchronize(c->stream));
   if (dev_n != n) return fail(PERCH_E_HIP, "hash build counted %d points, expected %d", dev_n, n);
   c->has_obs = true;
+  ++c->obs_serial;
   return PERCH_OK;
 }
 
@@ -300,11 +301,39 @@ perch_status perch_add_mesh(perch_ctx* c, int32_t mesh_id, const float* verts, i
 
 perch_status perch_set_poses(perch_ctx* c, const float* poses, int32_t P) {
   if (!c || !poses || P <= 0) return fail(PERCH_E_ARG, "bad pose table");
-  HIP_TRY(c->poses.ensure((size_t)P * sizeof(float4)));
+  HIP_TRY(c->poses.ensure(((size_t)P + c->arena_cap) * sizeof(float4)));
   HIP_TRY(hipMemcpy(c->poses.p, poses, (size_t)P * sizeof(float4), hipMemcpyHostToDevice));
   c->P = P;
+  c->arena_used = 0;
   c->h_poses.assign(poses, poses + 4 * (size_t)P);
   c->parent_j = -1;
+  return PERCH_OK;
+}
+
+perch_status perch_set_pose_arena(perch_ctx* c, int32_t capacity) {
+  if (!c || capacity < 0) return fail(PERCH_E_ARG, "bad arena capacity");
+  if (c->P <= 0) return fail(PERCH_E_STATE, "perch_set_poses not called");
+  if ((int64_t)c->P + capacity > INT32_MAX) return fail(PERCH_E_ARG, "arena too large");
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  const size_t need = ((size_t)c->P + capacity) * sizeof(float4);
+  if (need > c->poses.bytes) {
+    HIP_TRY(c->poses.ensure(need));
+    HIP_TRY(hipMemcpy(c->poses.p, c->h_poses.data(), (size_t)c->P * sizeof(float4),
+                      hipMemcpyHostToDevice));
+  }
+  c->arena_cap = capacity;
+  c->arena_used = 0;
+  c->parent_j = -1;  // a materialised parent may use arena poses
+  return PERCH_OK;
+}
+
+perch_status perch_get_poses(perch_ctx* c, int32_t first, int32_t n, float* poses_host) {
+  if (!c || first < 0 || n < 0 || (n > 0 && !poses_host)) return fail(PERCH_E_ARG, "bad range");
+  if ((int64_t)first + n > c->n_poses()) return fail(PERCH_E_ARG, "poses out of range");
+  if (n == 0) return PERCH_OK;
+  HIP_TRY(hipMemcpyAsync(poses_host, c->poses.as<float4>() + first, (size_t)n * sizeof(float4),
+                         hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
   return PERCH_OK;
 }
 
@@ -419,6 +448,56 @@ perch_status perch_overlap_gain(perch_ctx* c, const perch_object* cands_dev, int
                                 int32_t* cost_dev, int32_t* status_dev, int32_t* gain_dev) {
   if (n > 0 && !gain_dev) return fail(PERCH_E_ARG, "null gain array");
   return eval_children_impl(c, cands_dev, n, cost_dev, status_dev, nullptr, gain_dev);
+}
+
+perch_status perch_icp_children(perch_ctx* c, const perch_object* cands_dev, int32_t n,
+                                int32_t iters, float radius, perch_object* adjusted_dev,
+                                int32_t* n_match_dev, int32_t* status_dev) {
+  if (!c) return fail(PERCH_E_ARG, "null context");
+  if (n < 0 || (n > 0 && (!cands_dev || !adjusted_dev || !n_match_dev || !status_dev)))
+    return fail(PERCH_E_ARG, "bad candidate arrays");
+  if (iters < 0 || iters > 1000 || !(radius > 0.0f) || !(radius < 1.0f))
+    return fail(PERCH_E_ARG, "bad ICP iterations or radius");
+  if (c->parent_j < 0) return fail(PERCH_E_STATE, "perch_set_parent not called");
+  if (c->meshes_dirty) return fail(PERCH_E_STATE, "meshes changed since perch_set_parent");
+  if (c->max_nv > kInt2CacheMaxVerts)
+    return fail(PERCH_E_UNSUPPORTED, "ICP needs meshes of at most %d vertices", kInt2CacheMaxVerts);
+  const int tile = icp_tile_px(c->max_nv);
+  if (tile <= 0) return fail(PERCH_E_UNSUPPORTED, "no LDS left for the ICP tile");
+  if ((int64_t)c->arena_used + n > c->arena_cap)
+    return fail(PERCH_E_ARG, "pose arena full (%d of %d used, %d more asked)", c->arena_used,
+                c->arena_cap, n);
+  if (n == 0) return PERCH_OK;
+  const size_t npx = (size_t)c->cam.W * c->cam.H;
+  if (c->icp_pn_obs != c->obs_serial || c->icp_pn_radius != radius) {
+    HIP_TRY(c->icp_pn.ensure(2 * npx * sizeof(float4)));
+    launch_obs_normals(c->cam, c->obs.as<float>(), radius, c->icp_pn.as<float4>(), c->stream);
+    HIP_TRY(hipGetLastError());
+    c->icp_pn_obs = c->obs_serial;
+    c->icp_pn_radius = radius;
+  }
+  const int K = (int)c->objects.size();
+  Parent par;
+  par.depth = c->par_depth.as<unsigned>();
+  par.ubits = c->par_ubits.as<unsigned>();
+  par.ucount = c->par_ucount.as<int>();
+  par.vbits = nullptr;
+  par.has_parent = c->parent_j > 0;
+  par.goal = (c->parent_j + 1 == K);
+  perch::SceneDev S = c->scene_dev();
+  S.ep.tile_px = tile;
+  IcpArgs ia;
+  ia.iters = iters;
+  ia.radius = radius;
+  ia.pn = c->icp_pn.as<float4>();
+  ia.base = c->P + c->arena_used;
+  ia.arena = c->poses.as<float4>() + ia.base;
+  const size_t lds = icp_fixed_lds(c->max_nv) + (size_t)tile * sizeof(unsigned);
+  HIP_TRY(launch_icp(S, par, reinterpret_cast<const int2*>(cands_dev), n, ia,
+                     reinterpret_cast<int2*>(adjusted_dev), n_match_dev, status_dev, lds,
+                     c->stream));
+  c->arena_used += n;
+  return PERCH_OK;
 }
 
 perch_status perch_eval_successors(perch_ctx* c, const perch_object* parent, int32_t j,

@@ -106,6 +106,17 @@ inline size_t eval_lds_bytes(int max_nv, int tile_px, int threads) {
          (size_t)(threads / 64) * 128 * sizeof(unsigned);
 }
 
+// Dynamic LDS and z-tile of the ICP kernel: one workgroup per CU, int2 vertex
+// cache, the largest tile (a multiple of 256 pixels) left over; footprints larger
+// than it are not aligned.
+inline size_t icp_fixed_lds(int max_nv) {
+  return (size_t)max_nv * 2 * sizeof(int) + (size_t)(perch::kIcpThreads / 64) * 128 * sizeof(unsigned);
+}
+inline int icp_tile_px(int max_nv) {
+  const long budget = 160L * 1024 - 4096 - (long)icp_fixed_lds(max_nv);
+  return budget < 4L * 1024 ? 0 : (int)((budget / 4) & ~255L);
+}
+
 // Largest z-tile (a multiple of 256 pixels, at most 36,864) that lets two
 // workgroups share a CU's 160 KB of LDS (four for 256 threads or fewer), else one;
 // rows that do not fit are processed in bands.
@@ -135,10 +146,14 @@ struct perch_ctx {
   bool meshes_dirty = true;
   int max_nv = 0;
   DevBuf verts, tris, planes, range, frange, aabb;
-  // pose table (device, and a host copy for the search driver)
+  // pose table (device, and a host copy of the grid for the search driver): the P
+  // grid poses, then room for arena_cap poses adjusted by the local ICP, of which
+  // the first arena_used are taken
   DevBuf poses;
   std::vector<float> h_poses;
   int P = 0;
+  int arena_cap = 0, arena_used = 0;
+  int n_poses() const { return P + arena_used; }
   // known objects
   std::vector<int32_t> objects;
   // observation and hash
@@ -146,6 +161,10 @@ struct perch_ctx {
   bool has_obs = false;
   int n_points = 0;
   DevBuf h_keys, h_cells, h_pts, h_counts;
+  // observed points with surface normals for the local ICP, for one radius
+  DevBuf icp_pn;
+  long obs_serial = 0, icp_pn_obs = -1;
+  float icp_pn_radius = -1.0f;
   int h_mask = 0;
   float cell_over_delta = 2.0f;
   // parent buffers (parent_j = level of the materialised parent, -1 = none)
@@ -159,7 +178,7 @@ struct perch_ctx {
   // crop descriptors of the learned heuristic
   DevBuf cnn_desc;
   // search scratch: candidate list and outputs of one expansion
-  DevBuf s_cands, s_out;
+  DevBuf s_cands, s_out, s_adj;
   PinnedBuf s_hcands, s_hout;
   // tuning (tile_px 0 = sized automatically, see auto_tile_px)
   int threads = 512;
@@ -194,7 +213,7 @@ struct perch_ctx {
     S.ep.max_nv = max_nv;
     S.ep.vpack = vertex_cache_packed(max_nv);
     S.ep.n_mesh = (int)meshes.size();
-    S.ep.n_poses = P;
+    S.ep.n_poses = n_poses();
     S.ep.radius_mode = radius_mode;
     return S;
   }

@@ -122,6 +122,23 @@ hipError_t launch_eval_batch(int threads, int vpack, const SceneDev* scenes,
                              int n_parents, const int4* items, int n, int* counter, int* cost,
                              int* status, int* comps, size_t lds_bytes, int grid, hipStream_t s);
 
+// ---- local ICP (Sec. V-A) ----
+constexpr int kIcpThreads = 512;
+struct IcpArgs {
+  int iters;
+  float radius;       // association radius (metres)
+  const float4* pn;   // per pixel: world point (w = 1 with a normal), unit normal
+  float4* arena;      // adjusted poses, one per candidate
+  int base;           // pose index of arena[0]
+};
+// pn (2 float4 per pixel) from the observation for association radius `radius`
+void launch_obs_normals(const Cam& cam, const float* obs, float radius, float4* pn,
+                        hipStream_t s);
+// kIcpThreads threads per candidate; lds = vertex cache (int2) + tile + rings
+hipError_t launch_icp(const SceneDev& S, const Parent& par, const int2* cands, int n,
+                      const IcpArgs& ia, int2* out_obj, int* out_match, int* out_status,
+                      size_t lds, hipStream_t s);
+
 // ---- learned search: device-side ranking of children (perch_select.hip) ----
 constexpr int kMaxMeshes = 8;  // distinct meshes of one scene's object multiset
 struct MeshMask {

@@ -1112,6 +1112,347 @@ __global__ void __launch_bounds__(NT, 4)  // at least 4 waves per SIMD: <= 128 V
 }
 
 // ---------------------------------------------------------------------------
+// local ICP (Sec. V-A): compensating for the pose discretization
+// ---------------------------------------------------------------------------
+
+// Per observed pixel: the world point (w = 1 when it has a surface normal, else 0;
+// 0 everywhere for pixels without a return) and its unit normal facing the camera,
+// from the cross product of the central differences of its four pixel neighbours,
+// all observed and within `radius` of it.
+__global__ void k_obs_normals(Cam cam, const float* __restrict__ obs, float radius,
+                              float4* __restrict__ pn) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= cam.W * cam.H) return;
+  const int u = k % cam.W, v = k / cam.W;
+  auto world = [&](int i, int j, float z) {
+    const float3 q = backproject(cam, i, j, z);
+    const float* A = cam.Winv;
+    return make_float3(A[0] * q.x + A[1] * q.y + A[2] * q.z + A[3],
+                       A[4] * q.x + A[5] * q.y + A[6] * q.z + A[7],
+                       A[8] * q.x + A[9] * q.y + A[10] * q.z + A[11]);
+  };
+  const float z = obs[k];
+  float4 P = make_float4(0.f, 0.f, 0.f, 0.f), N = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (z > 0.0f) {
+    const float3 c = world(u, v, z);
+    P = make_float4(c.x, c.y, c.z, 0.0f);
+    if (u >= 1 && v >= 1 && u <= cam.W - 2 && v <= cam.H - 2) {
+      const float z1 = obs[k + 1], z0 = obs[k - 1], z3 = obs[k + cam.W], z2 = obs[k - cam.W];
+      if (z0 > 0.0f && z1 > 0.0f && z2 > 0.0f && z3 > 0.0f) {
+        const float3 a1 = world(u + 1, v, z1), a0 = world(u - 1, v, z0);
+        const float3 b1 = world(u, v + 1, z3), b0 = world(u, v - 1, z2);
+        const float r2 = radius * radius;
+        auto dist2 = [&](float3 p) {
+          const float dx = p.x - c.x, dy = p.y - c.y, dz = p.z - c.z;
+          return dx * dx + dy * dy + dz * dz;
+        };
+        if (dist2(a1) <= r2 && dist2(a0) <= r2 && dist2(b1) <= r2 && dist2(b0) <= r2) {
+          const float ex = a1.x - a0.x, ey = a1.y - a0.y, ez = a1.z - a0.z;
+          const float fx = b1.x - b0.x, fy = b1.y - b0.y, fz = b1.z - b0.z;
+          float nx = ey * fz - ez * fy, ny = ez * fx - ex * fz, nz = ex * fy - ey * fx;
+          const float len = sqrtf(nx * nx + ny * ny + nz * nz);
+          if (len > 0.0f) {
+            // towards the camera centre (world_from_cam's translation)
+            const float tw = nx * (cam.Winv[3] - c.x) + ny * (cam.Winv[7] - c.y) +
+                             nz * (cam.Winv[11] - c.z);
+            const float sg = (tw < 0.0f ? -1.0f : 1.0f) / len;
+            N = make_float4(nx * sg, ny * sg, nz * sg, 0.0f);
+            P.w = 1.0f;
+          }
+        }
+      }
+    }
+  }
+  pn[2 * (size_t)k] = P;
+  pn[2 * (size_t)k + 1] = N;
+}
+
+// Raw sums of one association round, reduced over the workgroup: matches, the
+// moved model points (x, y, relative to the grid position), and the products of
+// g = n_y a_x - n_x a_y, n_x, n_y and the residual r = n.(a - p).
+constexpr int kIcpSums = 12;
+
+// One workgroup per candidate: render it into the LDS tile, composite against the
+// parent (an occluding candidate is not aligned), then `iters` rounds over the
+// non-occluded pixels dR: move each model point by the motion so far, associate it
+// with the observed point at the nearest pixel of its projection when that point
+// has a normal and lies within `radius`, and take one point-to-plane step (a
+// rotation about the vertical axis through the matched points' centroid and a
+// translation, from the damped 3 x 3 normal equations).  Writes the adjusted pose
+// to arena[s] and (mesh, base + s) to out_obj[s].
+template <int NT>
+__global__ void __launch_bounds__(NT)
+    k_icp(SceneDev S, Parent par, const int2* __restrict__ cands, int n, IcpArgs ia,
+          int2* __restrict__ out_obj, int* __restrict__ out_match, int* __restrict__ out_status) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int s_bb[4];
+  __shared__ int s_flag[3];  // vertex stage failed, occludes the parent, stop
+  __shared__ double s_red[NT / 64][kIcpSums];
+  __shared__ float s_T[4];   // cos phi, sin phi, tx, ty of the motion so far
+  __shared__ int s_nm;
+  const int s = blockIdx.x;
+  if (s >= n) return;
+  const Cam& cam = S.cam;
+  const Meshes& M = S.M;
+  const EvalParams& ep = S.ep;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int W = cam.W, H = cam.H;
+  const int2 cd = cands[s];
+  if (cd.x < 0 || cd.x >= ep.n_mesh || cd.y < 0 || cd.y >= ep.n_poses) {
+    if (tid == 0) {
+      out_status[s] = -4;
+      out_match[s] = 0;
+      out_obj[s] = cd;
+      ia.arena[s] = make_float4(0.0f, 0.0f, 1.0f, 0.0f);
+    }
+    return;
+  }
+  const float4 pz = S.poses[cd.y];
+  const int4 rg = M.range[cd.x];
+  int2* suv = reinterpret_cast<int2*>(smem);
+  unsigned* tile = reinterpret_cast<unsigned*>(smem + (size_t)ep.max_nv * sizeof(int2));
+  unsigned* ring = tile + ep.tile_px + (tid >> 6) * 128;
+  if (tid < 4) s_bb[tid] = tid < 2 ? INT_MAX : INT_MIN;
+  if (tid < 3) s_flag[tid] = 0;
+  if (tid == 0) {
+    s_T[0] = 1.0f;
+    s_T[1] = s_T[2] = s_T[3] = 0.0f;
+    s_nm = 0;
+  }
+  __syncthreads();
+  {
+    int xmn = INT_MAX, ymn = INT_MAX, xmx = INT_MIN, ymx = INT_MIN;
+    bool bad = false;
+    for (int v = tid; v < rg.y; v += NT) {
+      float X, Y, Z;
+      vcam(cam, pz, M.verts[rg.x + v], X, Y, Z);
+      int U, V;
+      bad |= !vsnap(cam, X, Y, Z, U, V);
+      suv[v] = make_int2(U, V);
+      xmn = min(xmn, U);
+      ymn = min(ymn, V);
+      xmx = max(xmx, U);
+      ymx = max(ymx, V);
+    }
+    xmn = wave_min(xmn);
+    ymn = wave_min(ymn);
+    xmx = wave_max(xmx);
+    ymx = wave_max(ymx);
+    const bool any_bad = __ballot(bad) != 0;
+    if (lane == 0) {
+      atomicMin(&s_bb[0], xmn);
+      atomicMin(&s_bb[1], ymn);
+      atomicMax(&s_bb[2], xmx);
+      atomicMax(&s_bb[3], ymx);
+      if (any_bad) s_flag[0] = 1;
+    }
+  }
+  __syncthreads();
+  auto finish = [&](int status, int nm, float4 pose) {
+    if (tid == 0) {
+      out_status[s] = status;
+      out_match[s] = nm;
+      out_obj[s] = make_int2(cd.x, ia.base + s);
+      ia.arena[s] = pose;
+    }
+  };
+  if (s_flag[0]) {
+    finish(-2, 0, pz);
+    return;
+  }
+  const int ca = max(0, floor256(s_bb[0]) - 1), cb = min(W - 1, ceil256(s_bb[2]) + 1);
+  const int ra = max(0, floor256(s_bb[1]) - 1), rb = min(H - 1, ceil256(s_bb[3]) + 1);
+  const int tw = cb - ca + 1, nrows = rb - ra + 1;
+  if (tw <= 0 || nrows <= 0) {  // nothing in view: nothing to align
+    finish(1, 0, pz);
+    return;
+  }
+  if (tw * nrows > ep.tile_px) {
+    finish(-3, 0, pz);
+    return;
+  }
+  const int tn = tw * nrows;
+  for (int k = tid; k < tn; k += NT) tile[k] = kInfBits;
+  __syncthreads();
+  // rasterise (front faces queued per wave as in the successor kernel)
+  {
+    const PoseMap pm = make_pose_map(cam, pz);
+    auto raster_one = [&](unsigned t) {
+      const int4 tr = M.tris[rg.z + t];
+      const float4 v0 = M.verts[rg.x + tr.x], v1 = M.verts[rg.x + tr.y];
+      const float4 v2 = M.verts[rg.x + tr.z];
+      const int2 a = suv[tr.x], b = suv[tr.y], c = suv[tr.z];
+      float X0, Y0, Z0, X1, Y1, Z1, X2, Y2, Z2;
+      map_vertex(pm, v0, X0, Y0, Z0);
+      map_vertex(pm, v1, X1, Y1, Z1);
+      map_vertex(pm, v2, X2, Y2, Z2);
+      const Plane64 pl = make_plane(cam, X0, Y0, Z0, X1, Y1, Z1, X2, Y2, Z2);
+      raster_tri(a.x, a.y, b.x, b.y, c.x, c.y, ca, cb, ra, rb, [&](int i, int j) {
+        atomicMin(&tile[(j - ra) * tw + (i - ca)], __float_as_uint(plane_depth(pl, i, j)));
+      });
+    };
+    unsigned head = 0, tail = 0;
+    for (int base = (tid >> 6) * 64; base < rg.w; base += NT) {
+      const int t = base + lane;
+      bool keep = false;
+      if (t < rg.w) {
+        const int4 tr = M.tris[rg.z + t];
+        const int2 a = suv[tr.x], b = suv[tr.y], c = suv[tr.z];
+        keep = tri_candidate(a.x, a.y, b.x, b.y, c.x, c.y, ca, cb, ra, rb);
+      }
+      const unsigned long long m = __ballot(keep);
+      if (keep) ring[(tail + lanes_below(m)) & 127u] = (unsigned)t;
+      tail += (unsigned)__popcll(m);
+      wave_sync();
+      if (tail - head >= 64u) {
+        raster_one(ring[(head + lane) & 127u]);
+        head += 64u;
+        wave_sync();
+      }
+    }
+    if ((unsigned)lane < tail - head) raster_one(ring[(head + lane) & 127u]);
+  }
+  __syncthreads();
+  // composite: validity (Eq. 3) and the non-occluded part dR
+  {
+    bool occ = false;
+    for (int k = tid; k < tn; k += NT) {
+      const int r = k / tw;
+      const int jj = ra + r, ii = ca + (k - r * tw);
+      const unsigned key = tile[k];
+      const bool cov = key != kInfBits;
+      const unsigned pk = par.has_parent ? par.depth[jj * W + ii] : kInfBits;
+      const bool pfin = pk != kInfBits;
+      occ |= cov && pfin && key < pk;
+      tile[k] = (cov && !pfin) ? key : kInfBits;
+    }
+    if (__ballot(occ) != 0ull && lane == 0) s_flag[1] = 1;
+  }
+  __syncthreads();
+  if (s_flag[1]) {
+    finish(0, 0, pz);
+    return;
+  }
+  // ICP rounds; thread 0 keeps the motion in FP64
+  double phi = 0.0, mtx = 0.0, mty = 0.0;
+  const float r2 = ia.radius * ia.radius;
+  const float ox = pz.x, oy = pz.y;  // local origin of the sums
+  const float* Wi = cam.Winv;
+  for (int it = 0; it < ia.iters; ++it) {
+    const float cT = s_T[0], sT = s_T[1], txT = s_T[2], tyT = s_T[3];
+    double acc[kIcpSums];
+    for (int q = 0; q < kIcpSums; ++q) acc[q] = 0.0;
+    for (int k = tid; k < tn; k += NT) {
+      const unsigned key = tile[k];
+      if (key == kInfBits) continue;
+      const int r = k / tw;
+      const int jj = ra + r, ii = ca + (k - r * tw);
+      const float3 q = backproject(cam, ii, jj, __uint_as_float(key));
+      const float wx = Wi[0] * q.x + Wi[1] * q.y + Wi[2] * q.z + Wi[3];
+      const float wy = Wi[4] * q.x + Wi[5] * q.y + Wi[6] * q.z + Wi[7];
+      const float wz = Wi[8] * q.x + Wi[9] * q.y + Wi[10] * q.z + Wi[11];
+      const float ax = cT * wx - sT * wy + txT, ay = sT * wx + cT * wy + tyT, az = wz;
+      const float cx = cam.M[0] * ax + cam.M[1] * ay + cam.M[2] * az + cam.M[3];
+      const float cy = cam.M[4] * ax + cam.M[5] * ay + cam.M[6] * az + cam.M[7];
+      const float cz = cam.M[8] * ax + cam.M[9] * ay + cam.M[10] * az + cam.M[11];
+      if (!(cz > 0.0f)) continue;
+      const float uf = cam.fx * (cx / cz) + cam.cx, vf = cam.fy * (cy / cz) + cam.cy;
+      const float fu = floorf(uf + 0.5f), fv = floorf(vf + 0.5f);
+      if (!(fu >= 0.0f && fu <= (float)(W - 1) && fv >= 0.0f && fv <= (float)(H - 1))) continue;
+      const size_t pix = (size_t)fv * W + (size_t)fu;
+      const float4 P = ia.pn[2 * pix];
+      if (!(P.w > 0.0f)) continue;
+      const float dx = ax - P.x, dy = ay - P.y, dz = az - P.z;
+      if (dx * dx + dy * dy + dz * dz > r2) continue;
+      const float4 N = ia.pn[2 * pix + 1];
+      const float lx = ax - ox, ly = ay - oy;
+      const double g = (double)N.y * lx - (double)N.x * ly;
+      const double res = (double)N.x * dx + (double)N.y * dy + (double)N.z * dz;
+      acc[0] += 1.0;
+      acc[1] += lx;
+      acc[2] += ly;
+      acc[3] += g * g;
+      acc[4] += g * N.x;
+      acc[5] += g * N.y;
+      acc[6] += (double)N.x * N.x;
+      acc[7] += (double)N.x * N.y;
+      acc[8] += (double)N.y * N.y;
+      acc[9] += g * res;
+      acc[10] += N.x * res;
+      acc[11] += N.y * res;
+    }
+    for (int q = 0; q < kIcpSums; ++q) {
+      double v = acc[q];
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+      if (lane == 0) s_red[wv][q] = v;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double t[kIcpSums];
+      for (int q = 0; q < kIcpSums; ++q) {
+        t[q] = 0.0;
+        for (int w = 0; w < NT / 64; ++w) t[q] += s_red[w][q];
+      }
+      const int nm = (int)t[0];
+      s_nm = nm;
+      if (nm < 3) {
+        s_flag[2] = 1;
+      } else {
+        const double cx = t[1] / nm, cy = t[2] / nm;  // centroid, local frame
+        // normal equations of J = (g - (c_x n_y - c_y n_x), n_x, n_y), b = -J r
+        double A[3][3], b[3];
+        A[0][0] = t[3] - 2.0 * (cx * t[5] - cy * t[4]) + cx * cx * t[8] - 2.0 * cx * cy * t[7] +
+                  cy * cy * t[6];
+        A[0][1] = A[1][0] = t[4] - cx * t[7] + cy * t[6];
+        A[0][2] = A[2][0] = t[5] - cx * t[8] + cy * t[7];
+        A[1][1] = t[6];
+        A[1][2] = A[2][1] = t[7];
+        A[2][2] = t[8];
+        b[0] = -(t[9] - cx * t[11] + cy * t[10]);
+        b[1] = -t[10];
+        b[2] = -t[11];
+        for (int u = 0; u < 3; ++u) A[u][u] += 1e-6 * A[u][u] + 1e-12;
+        auto det3 = [](const double (&m)[3][3]) {
+          return m[0][0] * (m[1][1] * m[2][2] - m[1][2] * m[2][1]) -
+                 m[0][1] * (m[1][0] * m[2][2] - m[1][2] * m[2][0]) +
+                 m[0][2] * (m[1][0] * m[2][1] - m[1][1] * m[2][0]);
+        };
+        const double det = det3(A);
+        double x[3];
+        for (int c = 0; c < 3; ++c) {
+          double Mc[3][3];
+          for (int u = 0; u < 3; ++u)
+            for (int v = 0; v < 3; ++v) Mc[u][v] = v == c ? b[u] : A[u][v];
+          x[c] = det3(Mc) / det;
+        }
+        // the step about the world z axis: t' = c_w + t - R c_w
+        const double co = cos(x[0]), si = sin(x[0]);
+        const double cwx = cx + ox, cwy = cy + oy;
+        const double stx = cwx + x[1] - (co * cwx - si * cwy);
+        const double sty = cwy + x[2] - (si * cwx + co * cwy);
+        const double nx = co * mtx - si * mty + stx, ny = si * mtx + co * mty + sty;
+        phi += x[0];
+        mtx = nx;
+        mty = ny;
+        s_T[0] = (float)cos(phi);
+        s_T[1] = (float)sin(phi);
+        s_T[2] = (float)mtx;
+        s_T[3] = (float)mty;
+      }
+    }
+    __syncthreads();
+    if (s_flag[2]) break;
+  }
+  if (tid == 0) {
+    const double co = cos(phi), si = sin(phi);
+    const double x = pz.x, y = pz.y, pc = pz.z, ps = pz.w;
+    finish(1, s_nm,
+           make_float4((float)(co * x - si * y + mtx), (float)(si * x + co * y + mty),
+                       (float)(pc * co - ps * si), (float)(ps * co + pc * si)));
+  }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 
@@ -1298,6 +1639,23 @@ hipError_t launch_eval_batch(int threads, int vpack, const SceneDev* scenes,
                                             counter, cost, status, comps, lds_bytes, grid, s)
                : launch_eval_batch_vp<false>(threads, scenes, parents, n_parents, items, n,
                                              counter, cost, status, comps, lds_bytes, grid, s);
+}
+
+void launch_obs_normals(const Cam& cam, const float* obs, float radius, float4* pn,
+                        hipStream_t s) {
+  const int n = cam.W * cam.H;
+  hipLaunchKernelGGL(k_obs_normals, dim3((n + 255) / 256), dim3(256), 0, s, cam, obs, radius, pn);
+}
+
+hipError_t launch_icp(const SceneDev& S, const Parent& par, const int2* cands, int n,
+                      const IcpArgs& ia, int2* out_obj, int* out_match, int* out_status,
+                      size_t lds, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipError_t e = allow_lds(&k_icp<kIcpThreads>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_icp<kIcpThreads>), dim3(n), dim3(kIcpThreads), lds, s, S, par, cands, n,
+                     ia, out_obj, out_match, out_status);
+  return hipGetLastError();
 }
 
 }  // namespace perch

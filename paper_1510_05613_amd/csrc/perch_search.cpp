@@ -130,9 +130,21 @@ class Searcher {
     HIP_TRY(c_->s_out.ensure(cap * 3 * sizeof(int32_t)));
     HIP_TRY(c_->s_hcands.ensure(cap * sizeof(int2)));
     HIP_TRY(c_->s_hout.ensure(cap * 3 * sizeof(int32_t)));
+    if (o_.icp_iters > 0) {
+      if (o_.mode != PERCH_SEARCH_UCS && o_.mode != PERCH_SEARCH_FOCAL &&
+          o_.mode != PERCH_SEARCH_MHA)
+        return fail(PERCH_E_ARG, "ICP alignment is available to UCS, FOCAL and MHA");
+      if (c_->arena_cap < (int)cap)
+        return fail(PERCH_E_ARG, "pose arena (%d) smaller than one expansion (%zu)",
+                    c_->arena_cap, cap);
+      c_->arena_used = 0;  // this search's adjusted poses start the arena afresh
+      c_->parent_j = -1;
+    }
     t0_ = Clock::now();
     return PERCH_OK;
   }
+
+  float icp_radius() const { return o_.icp_radius > 0.0f ? o_.icp_radius : 0.02f; }
 
   double elapsed() const { return std::chrono::duration<double>(Clock::now() - t0_).count(); }
 
@@ -172,6 +184,16 @@ class Searcher {
     int32_t* dstat = dcost + cnt;
     int32_t* dgain = dstat + cnt;
     const perch_object* dc = reinterpret_cast<const perch_object*>(c_->s_cands.p);
+    int icp_base = -1;
+    if (o_.icp_iters > 0) {  // align every child first; evaluate it at the adjusted pose
+      HIP_TRY(c_->s_adj.ensure((size_t)cnt * (sizeof(int2) + 2 * sizeof(int32_t))));
+      perch_object* adj = c_->s_adj.as<perch_object>();
+      int32_t* nmatch = reinterpret_cast<int32_t*>(adj + cnt);
+      icp_base = c_->P + c_->arena_used;
+      st = perch_icp_children(c_, dc, cnt, o_.icp_iters, icp_radius(), adj, nmatch, nmatch + cnt);
+      if (st) return st;
+      dc = adj;
+    }
     st = with_gain ? perch_overlap_gain(c_, dc, cnt, dcost, dstat, dgain)
                    : perch_eval_children(c_, dc, cnt, dcost, dstat, nullptr);
     if (st) return st;
@@ -184,7 +206,8 @@ class Searcher {
     for (int i = 0; i < cnt; ++i) {
       const int s = hout[cnt + i];
       if (s == 1)
-        out.push_back({hc[i].x, hc[i].y, hout[i], with_gain ? hout[2 * cnt + i] : 0});
+        out.push_back({hc[i].x, icp_base >= 0 ? icp_base + i : hc[i].y, hout[i],
+                       with_gain ? hout[2 * cnt + i] : 0});
       else if (s == 0)
         ++n_invalid_;
       else

@@ -25,7 +25,8 @@ PERCH_SUCC_BAD_INPUT = -4
 # the public symbols declared in include/perch.h
 EXPORTS = ("perch_create", "perch_destroy", "perch_set_observation", "perch_add_mesh",
            "perch_set_poses", "perch_set_objects", "perch_eval_successors", "perch_set_parent",
-           "perch_eval_children", "perch_overlap_gain", "perch_render", "perch_set_tuning",
+           "perch_eval_children", "perch_overlap_gain", "perch_set_pose_arena",
+           "perch_get_poses", "perch_icp_children", "perch_render", "perch_set_tuning",
            "perch_get_info",
            "perch_search", "perch_batch_create", "perch_batch_destroy",
            "perch_batch_set_parents", "perch_batch_eval", "perch_batch_set_tuning",
@@ -64,7 +65,8 @@ class _SearchOpts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("w", C.c_float), ("anytime", C.c_int32),
                 ("budget_s", C.c_double), ("budget_expansions", C.c_int64),
                 ("pose_subset", C.c_void_p), ("n_pose_subset", C.c_int32),
-                ("cnn", C.c_void_p), ("topk", C.c_int32)]
+                ("cnn", C.c_void_p), ("topk", C.c_int32), ("icp_iters", C.c_int32),
+                ("icp_radius", C.c_float)]
 
 
 class _Result(C.Structure):
@@ -99,6 +101,9 @@ def load(path: str = LIB_PATH):
     L.perch_eval_children.argtypes = [P, P, I32, P, P, P]
     L.perch_render.argtypes = [P, P, I32, I32, P]
     L.perch_overlap_gain.argtypes = [P, P, I32, P, P, P]
+    L.perch_set_pose_arena.argtypes = [P, I32]
+    L.perch_get_poses.argtypes = [P, I32, I32, P]
+    L.perch_icp_children.argtypes = [P, P, I32, I32, C.c_float, P, P, P]
     L.perch_set_tuning.argtypes = [P, I32, I32, C.c_float, I32]
     L.perch_get_info.argtypes = [P, C.POINTER(I32), C.POINTER(I32)]
     L.perch_search.argtypes = [P, C.POINTER(_SearchOpts), C.POINTER(_Result)]
@@ -275,9 +280,31 @@ class Context:
         self.eval_successors(parent, cands, cost, status, comps)
         return status, cost, comps
 
+    def set_pose_arena(self, capacity: int):
+        """Room for `capacity` ICP-adjusted poses after the grid (empties it)."""
+        _check(load().perch_set_pose_arena(self.h, int(capacity)))
+
+    def get_poses(self, first: int, n: int) -> np.ndarray:
+        """Poses [first, first + n) of the table (grid, then arena), (n, 4) float32."""
+        out = np.zeros((max(n, 1), 4), np.float32)
+        _check(load().perch_get_poses(self.h, int(first), int(n), out.ctypes.data))
+        return out[:n]
+
+    def icp_children(self, cands, adjusted, n_match, status, iters: int = 10,
+                     radius: float = 0.02):
+        """Local ICP (Sec. V-A) of the successors of the parent last set: cands and
+        adjusted int32 GPU tensors (n, 2) (adjusted = (mesh, arena pose index)),
+        n_match and status int32 GPU tensors (n,).  Asynchronous."""
+        n = cands.shape[0]
+        _check(load().perch_icp_children(
+            self.h, _dev_ptr(cands, "int32", 2 * n), n, int(iters), float(radius),
+            _dev_ptr(adjusted, "int32", 2 * n), _dev_ptr(n_match, "int32", n),
+            _dev_ptr(status, "int32", n)))
+
     def search(self, mode: int = SEARCH_UCS, w: float = 1.0, anytime: bool = False,
                budget_s: float = 0.0, budget_expansions: int = 0, pose_subset=None,
-               cnn: "Optional[Cnn]" = None, topk: int = 64) -> dict:
+               cnn: "Optional[Cnn]" = None, topk: int = 64, icp_iters: int = 0,
+               icp_radius: float = 0.02) -> dict:
         """Tree search of Alg. 1 on this scene (synchronous).  Returns the goal in
         insertion order plus its canonical (sorted) form, cost and statistics."""
         o = _SearchOpts()
@@ -285,6 +312,7 @@ class Context:
         o.budget_s, o.budget_expansions = float(budget_s), int(budget_expansions)
         o.cnn = None if cnn is None else cnn.h.value
         o.topk = int(topk)
+        o.icp_iters, o.icp_radius = int(icp_iters), float(icp_radius)
         sub = None
         if pose_subset is not None:
             sub = np.ascontiguousarray(pose_subset, np.int32)

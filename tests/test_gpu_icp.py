@@ -1,0 +1,190 @@
+"""Local ICP (Sec. V-A) on the GPU against the oracle, through the C ABI.
+
+Rule: the status (Eq. 3 at the grid pose) is equal unless the oracle flags a
+parent depth tie; the adjusted table-plane position agrees within 1e-4 m and,
+for meshes whose yaw the surface fixes, the yaw within 1e-3 rad.  The
+association rounds the projection of a float32 (GPU) or float64 (oracle) point
+to the nearest pixel, so a few of the ~5,000 pairs per round may differ (the
+oracle counts them in its flags); each moves the solution by about 1e-6 m.
+The edge cost at the adjusted pose follows the successor parity rule, the oracle
+evaluating the GPU's float32 pose."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import Oracle  # noqa: E402
+from paper_1510_05613_amd import perch  # noqa: E402
+from tests import helpers as H  # noqa: E402
+from tests.test_gpu_parity import compare  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    perch.load()
+
+
+def _cyl(sc, m):
+    return len(sc.library.meshes[int(m)].planes) == 64  # the libraries' cylinders
+
+
+def _near_gt_candidates(sc, rng, n_rand=12):
+    """GT poses, grid neighbours of the GT poses (where ICP has work to do) and a
+    few random poses, for every mesh of the scene."""
+    g = sc.grid
+    out = []
+    for k in range(sc.K):
+        m, p = int(sc.obj_mesh[k]), int(sc.gt_pose[k])
+        out.append((m, p))
+        for d in (1, -1, g.n_yaw, -g.n_yaw, g.n_yaw + 1, g.ny * g.n_yaw - 1):
+            q = p + d
+            if 0 <= q < g.P:
+                out.append((m, q))
+    for m in sorted(set(int(v) for v in sc.obj_mesh)):
+        for p in rng.choice(g.P, n_rand, replace=False):
+            out.append((m, int(p)))
+    return np.array(out, np.int32)
+
+
+def _gpu_icp(ctx, parent, cands, iters=10, radius=0.02):
+    ctx.set_parent(parent)
+    c = torch.as_tensor(np.ascontiguousarray(cands)).cuda()
+    n = len(cands)
+    adj = torch.empty((n, 2), dtype=torch.int32, device="cuda")
+    nm = torch.empty(n, dtype=torch.int32, device="cuda")
+    st = torch.empty(n, dtype=torch.int32, device="cuda")
+    ctx.icp_children(c, adj, nm, st, iters=iters, radius=radius)
+    torch.cuda.synchronize()
+    return adj, nm.cpu().numpy(), st.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def c2():
+    sc = H.c2_scene(0)
+    return sc, Oracle.from_scene(sc, nthreads=8), perch.context_from_scene(sc)
+
+
+@pytest.mark.parametrize("level", [1, 2])
+def test_icp_poses_match_oracle(c2, level):
+    sc, o, ctx = c2
+    rng = np.random.default_rng(level)
+    order = [int(k) for k in sc.gt_order]
+    parent = [(int(sc.obj_mesh[k]), int(sc.gt_pose[k])) for k in order[:level - 1]]
+    cands = _near_gt_candidates(sc, rng)
+    ctx.set_pose_arena(4 * len(cands))
+    adj, nm_g, st_g = _gpu_icp(ctx, parent, cands)
+    pm = [m for m, _ in parent]
+    pp = [p for _, p in parent]
+    P_o, nm_o, st_o, fl_o = o.icp(pm, pp, cands[:, 0], cands[:, 1], iters=10, radius=0.02)
+    a = adj.cpu().numpy()
+    assert np.array_equal(a[:, 0], cands[:, 0])
+    assert np.array_equal(a[:, 1], sc.grid.P + np.arange(len(cands)))
+    P_g = ctx.get_poses(sc.grid.P, len(cands)).astype(np.float64)
+    assert np.all(st_g >= 0)
+    # validity is Eq. (3) at the grid pose: the oracle's evaluation flags the
+    # parent/candidate depth ties that may go either way
+    st_e, _, _, fl_e = o.eval(pm, pp, cands[:, 0], cands[:, 1])
+    assert np.array_equal(st_o, st_e)
+    tie = fl_e[:, 2] == 1
+    assert np.all((st_g == st_o) | tie)
+    ok = (st_g == 1) & (st_o == 1)
+    assert ok.sum() >= len(cands) // 2
+    dxy = np.hypot(P_g[ok, 0] - P_o[ok, 0], P_g[ok, 1] - P_o[ok, 1])
+    assert dxy.max() < 1e-4, (dxy.max(), np.nonzero(ok)[0][np.argmax(dxy)])
+    yaw = np.angle(np.exp(1j * (np.arctan2(P_g[ok, 3], P_g[ok, 2]) -
+                                np.arctan2(P_o[ok, 3], P_o[ok, 2]))))
+    fixed = np.array([not _cyl(sc, m) for m in cands[ok, 0]])
+    assert np.abs(yaw[fixed]).max() < 1e-3
+    # pairs of the last round: equal up to the flagged associations
+    assert np.all(np.abs(nm_g[ok] - nm_o[ok]) <= np.maximum(2, fl_o[ok]))
+    # the ones that moved did move (the candidates near GT are pulled)
+    g = sc.poses[cands[ok, 1]].astype(np.float64)
+    assert np.hypot(P_g[ok, 0] - g[:, 0], P_g[ok, 1] - g[:, 1]).max() > 1e-3
+    # not aligned: grid pose kept
+    bad = st_g == 0
+    if bad.any():
+        assert np.array_equal(P_g[bad].astype(np.float32), sc.poses[cands[bad, 1]])
+
+
+def test_cost_at_adjusted_pose_matches_oracle(c2):
+    """Edge costs of the ICP-adjusted successors (GPU arena poses, evaluated on
+    the GPU and by the oracle from the same float32 pose values)."""
+    sc, _, ctx = c2
+    rng = np.random.default_rng(7)
+    order = [int(k) for k in sc.gt_order]
+    parent = [(int(sc.obj_mesh[order[0]]), int(sc.gt_pose[order[0]]))]
+    cands = _near_gt_candidates(sc, rng, n_rand=4)
+    ctx.set_pose_arena(len(cands))
+    adj, _, st_i = _gpu_icp(ctx, parent, cands)
+    cost = torch.empty(len(cands), dtype=torch.int32, device="cuda")
+    status = torch.empty_like(cost)
+    comps = torch.empty((len(cands), 5), dtype=torch.int32, device="cuda")
+    ctx.eval_children(adj, cost, status, comps)
+    torch.cuda.synchronize()
+    P_g = ctx.get_poses(sc.grid.P, len(cands))
+    poses = np.concatenate([sc.poses, P_g]).astype(np.float32)
+    o = Oracle(sc.sensor, sc.library, poses, sc.obj_mesh, sc.depth_obs, nthreads=8)
+    a = adj.cpu().numpy()
+    st_o, cost_o, comps_o, flags_o = o.eval([parent[0][0]], [parent[0][1]], a[:, 0], a[:, 1])
+    compare((status.cpu().numpy(), cost.cpu().numpy(), comps.cpu().numpy()),
+            (st_o, cost_o, comps_o, flags_o), "icp cost")
+
+
+def test_icp_edge_cases(c2):
+    sc, _, ctx = c2
+    ctx.set_pose_arena(8)
+    e = torch.empty((0, 2), dtype=torch.int32, device="cuda")
+    e1 = torch.empty(0, dtype=torch.int32, device="cuda")
+    ctx.set_parent([])
+    ctx.icp_children(e, e.clone(), e1, e1.clone())  # empty: nothing launched
+    m, p = int(sc.obj_mesh[0]), int(sc.gt_pose[0])
+    cands = np.array([[m, p], [m, sc.grid.P + 100], [99, p]], np.int32)
+    adj, nm, st = _gpu_icp(ctx, [], cands, iters=0)
+    assert st[0] == 1 and nm[0] == 0 and st[1] == -4 and st[2] == -4
+    P = ctx.get_poses(sc.grid.P, 1)
+    assert np.array_equal(P[0], sc.poses[p])  # zero rounds: the grid pose
+    # the arena holds 8: three more than the five left are refused
+    with pytest.raises(perch.PerchError):
+        _gpu_icp(ctx, [], np.repeat(cands[:1], 6, 0))
+    with pytest.raises(perch.PerchError):
+        _gpu_icp(ctx, [], cands[:1], radius=0.0)
+
+
+@pytest.fixture(scope="module")
+def c1():
+    sc = H.c1_scene(1)
+    return sc, perch.context_from_scene(sc)
+
+
+def test_search_with_icp_is_consistent_and_w_bounded(c1):
+    """UCS and FOCAL over the ICP-adjusted tree (each child aligned before its edge
+    cost is taken): the path's edge costs add up, the arena poses it returns
+    re-evaluate to the same costs, and FOCAL stays within w of UCS (Theorem 2 on
+    the adjusted tree, which depends on I)."""
+    sc, ctx = c1
+    ctx.set_pose_arena(400000)
+    u = ctx.search(perch.SEARCH_UCS, icp_iters=5)
+    assert u["found"] and not u["budget_exhausted"]
+    assert sum(u["edge_cost"]) == u["cost"]
+    assert all(p >= sc.grid.P for _, p in u["objs"])
+    # re-evaluate the path with the arena poses it names
+    objs = u["objs"]
+    for j in range(len(objs)):
+        ctx.set_parent(objs[:j])
+        c = torch.as_tensor(np.array([objs[j]], np.int32)).cuda()
+        cost = torch.empty(1, dtype=torch.int32, device="cuda")
+        st = torch.empty_like(cost)
+        ctx.eval_children(c, cost, st)
+        torch.cuda.synchronize()
+        assert int(st[0]) == 1 and int(cost[0]) == u["edge_cost"][j]
+    for w in (1.5, 3.0):
+        f = ctx.search(perch.SEARCH_FOCAL, w=w, anytime=False, icp_iters=5)
+        assert f["found"] and f["cost"] <= w * u["cost"] + 1e-9
+    plain = ctx.search(perch.SEARCH_UCS)
+    assert plain["found"]
+    with pytest.raises(perch.PerchError):  # not offered with the learned modes
+        ctx.search(perch.SEARCH_LEARNED, w=2.0, icp_iters=5)
