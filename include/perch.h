@@ -324,8 +324,9 @@ typedef struct {
   int32_t topk;                /* LEARNED: children evaluated exactly per expansion    */
   int32_t icp_iters;           /* UCS/FOCAL/MHA: > 0 aligns every child by local ICP   */
                                /* (perch_icp_children) before its edge cost is taken;  */
-                               /* the search empties the pose arena first and needs    */
-                               /* room for every child it evaluates                    */
+                               /* the search empties the pose arena first and stops    */
+                               /* as on a spent budget when it has no room for the     */
+                               /* next expansion's children                            */
   float icp_radius;            /* ICP association radius in metres (0: 0.02)           */
 } perch_search_opts;
 

@@ -186,6 +186,7 @@ class Searcher {
     const perch_object* dc = reinterpret_cast<const perch_object*>(c_->s_cands.p);
     int icp_base = -1;
     if (o_.icp_iters > 0) {  // align every child first; evaluate it at the adjusted pose
+      if ((int64_t)c_->arena_used + cnt > c_->arena_cap) return PERCH_E_BUDGET;  // arena full
       HIP_TRY(c_->s_adj.ensure((size_t)cnt * (sizeof(int2) + 2 * sizeof(int32_t))));
       perch_object* adj = c_->s_adj.as<perch_object>();
       int32_t* nmatch = reinterpret_cast<int32_t*>(adj + cnt);
