@@ -342,6 +342,9 @@ typedef struct {
   int64_t lower_bound;         /* min g over the open list at exit (UCS/FOCAL)          */
   int64_t n_evaluated_best;    /* successors evaluated when the returned cost was first */
                                /* reached (a deterministic time-to-best-scene)          */
+  int64_t n_merged;            /* ICP: valid children dropped because a sibling of the  */
+                               /* same mesh was aligned into the same 1 mm x 1 mm x 0.5 */
+                               /* degree cell at no higher cost                         */
 } perch_result;
 
 /* Runs the tree search of Alg. 1 on the context's scene: root = empty state, goal =

@@ -205,6 +205,7 @@ void perch_destroy(perch_ctx* c) {
     b->release();
   c->s_hcands.release();
   c->s_hout.release();
+  c->s_hposes.release();
   delete c;
 }
 

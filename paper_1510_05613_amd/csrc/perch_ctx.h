@@ -179,7 +179,7 @@ struct perch_ctx {
   DevBuf cnn_desc;
   // search scratch: candidate list and outputs of one expansion
   DevBuf s_cands, s_out, s_adj;
-  PinnedBuf s_hcands, s_hout;
+  PinnedBuf s_hcands, s_hout, s_hposes;
   // tuning (tile_px 0 = sized automatically, see auto_tile_px)
   int threads = 512;
   int tile_px = 0;

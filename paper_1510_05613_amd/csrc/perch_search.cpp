@@ -201,6 +201,13 @@ class Searcher {
     int32_t* hout = c_->s_hout.as<int32_t>();
     HIP_TRY(hipMemcpyAsync(hout, dcost, (with_gain ? 3 : 2) * (size_t)cnt * sizeof(int32_t),
                            hipMemcpyDeviceToHost, c_->stream));
+    float* hpose = nullptr;
+    if (icp_base >= 0) {
+      HIP_TRY(c_->s_hposes.ensure((size_t)cnt * 4 * sizeof(float)));
+      hpose = c_->s_hposes.as<float>();
+      HIP_TRY(hipMemcpyAsync(hpose, c_->poses.as<float4>() + icp_base,
+                             (size_t)cnt * 4 * sizeof(float), hipMemcpyDeviceToHost, c_->stream));
+    }
     HIP_TRY(hipStreamSynchronize(c_->stream));
     ++n_expanded_;
     n_evaluated_ += cnt;
@@ -215,7 +222,39 @@ class Searcher {
         return fail(PERCH_E_UNSUPPORTED, "successor (%d, %d) failed with status %d", hc[i].x,
                     hc[i].y, s);
     }
+    if (hpose) merge_aligned_siblings(out, hpose, icp_base);
     return PERCH_OK;
+  }
+
+  // Local ICP pulls neighbouring grid poses of one object onto the same place:
+  // siblings of one mesh whose adjusted poses fall in one 1 mm x 1 mm x 0.5 degree
+  // cell (well inside the explanation radius) are
+  // one child (the cheapest, then the lowest index), so that the search does not
+  // expand the same state dozens of times.
+  void merge_aligned_siblings(std::vector<Child>& out, const float* hpose, int base) {
+    std::unordered_map<uint64_t, size_t> best;
+    std::vector<Child> kept;
+    kept.reserve(out.size());
+    for (const Child& ch : out) {
+      const float* q = hpose + 4 * (size_t)(ch.pose - base);
+      const int64_t kx = (int64_t)std::llround(q[0] / 1e-3);
+      const int64_t ky = (int64_t)std::llround(q[1] / 1e-3);
+      const double deg = std::atan2((double)q[3], (double)q[2]) * (180.0 / 3.14159265358979323846);
+      const int64_t kt = ((int64_t)std::llround(deg / 0.5) % 720 + 720) % 720;
+      const uint64_t key = ((uint64_t)(ch.mesh & 0xFFF) << 52) ^
+                           ((uint64_t)(kx & 0xFFFFF) << 32) ^ ((uint64_t)(ky & 0xFFFFF) << 12) ^
+                           (uint64_t)kt;
+      auto it = best.find(key);
+      if (it == best.end()) {
+        best.emplace(key, kept.size());
+        kept.push_back(ch);
+      } else {
+        Child& b = kept[it->second];
+        if (ch.cost < b.cost || (ch.cost == b.cost && ch.pose < b.pose)) b = ch;
+        ++n_merged_;
+      }
+    }
+    out.swap(kept);
   }
 
   Node child_of(const Node& n, int32_t id, const Child& ch) const {
@@ -663,6 +702,7 @@ class Searcher {
     r->n_expanded = n_expanded_;
     r->n_evaluated = n_evaluated_;
     r->n_invalid = n_invalid_;
+    r->n_merged = n_merged_;
     r->t_total_s = elapsed();
     r->t_best_s = have_ ? t_best_ : -1.0;
     r->n_evaluated_best = have_ ? n_eval_best_ : -1;
@@ -676,7 +716,7 @@ class Searcher {
   int distinct_ = 0;
   std::vector<int> poses_;
   Clock::time_point t0_;
-  int64_t n_expanded_ = 0, n_evaluated_ = 0, n_invalid_ = 0, expansions_ = 0;
+  int64_t n_expanded_ = 0, n_evaluated_ = 0, n_invalid_ = 0, expansions_ = 0, n_merged_ = 0;
   int64_t lower_bound_ = 0;
   bool have_ = false;
   Node best_{};

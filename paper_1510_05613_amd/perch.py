@@ -74,7 +74,7 @@ class _Result(C.Structure):
                 ("cost", C.c_int64), ("edge_cost", C.c_int32 * 8), ("n_expanded", C.c_int64),
                 ("n_evaluated", C.c_int64), ("n_invalid", C.c_int64), ("t_total_s", C.c_double),
                 ("t_best_s", C.c_double), ("lower_bound", C.c_int64),
-                ("n_evaluated_best", C.c_int64)]
+                ("n_evaluated_best", C.c_int64), ("n_merged", C.c_int64)]
 
 
 _lib = None
@@ -328,7 +328,7 @@ class Context:
                     n_expanded=int(r.n_expanded), n_evaluated=int(r.n_evaluated),
                     n_invalid=int(r.n_invalid), t_total_s=float(r.t_total_s),
                     t_best_s=float(r.t_best_s), lower_bound=int(r.lower_bound),
-                    n_evaluated_best=int(r.n_evaluated_best))
+                    n_evaluated_best=int(r.n_evaluated_best), n_merged=int(r.n_merged))
 
     def render(self, objs, composite: bool = True):
         """Depth images (+inf = empty) of objects [(mesh, pose), ...]."""
