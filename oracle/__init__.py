@@ -59,6 +59,7 @@ def lib():
         L.orc_jtree.argtypes = [P, C.c_int32, P, P, P]
         L.orc_overlap.argtypes = [P, C.c_int32, P, P, C.c_int32, P, P, P, P, P]
         L.orc_icp_step.argtypes = [C.c_int32, P, P, P, P]
+        L.orc_set_symmetric.argtypes = [P, C.c_int32, C.c_int32]
         L.orc_icp.argtypes = [P, C.c_int32, P, P, C.c_int32, P, P, C.c_int32, C.c_double, P, P,
                               P, P]
         for f in (L.orc_search_exhaustive, L.orc_search_ucs, L.orc_bruteforce_joint):
@@ -124,6 +125,11 @@ class Oracle:
     def set_mode(self, radius_mode: int = 0, nthreads: int = 1):
         if lib().orc_set_mode(self.h, radius_mode, nthreads) != 0:
             raise ValueError("bad mode")
+
+    def set_symmetric(self, mesh: int, symmetric: bool = True):
+        """Searches try a symmetric mesh only at the first pose per (x, y)."""
+        if lib().orc_set_symmetric(self.h, int(mesh), int(bool(symmetric))):
+            raise RuntimeError("orc_set_symmetric failed")
 
     @property
     def n_points(self) -> int:

@@ -65,6 +65,7 @@ struct orc_scene {
   int32_t* obj_mesh;
   int radius_mode;
   int nthreads;
+  uint8_t* sym; /* per mesh: rotationally symmetric, searched over (x, y) only */
 };
 
 /* ------------------------------------------------------------------------- */
@@ -352,6 +353,7 @@ orc_scene* orc_create(const orc_sensor* sensor, const float* depth_obs, int32_t 
   if (K) memcpy(sc->obj_mesh, obj_mesh, sizeof(int32_t) * K);
   sc->radius_mode = 0;
   sc->nthreads = 1;
+  sc->sym = (uint8_t*)calloc((size_t)n_mesh + 1, 1);
 
   /* observed cloud I: one point per pixel with a return (Sec. III-A) */
   size_t npx = (size_t)sc->W * sc->H;
@@ -388,7 +390,7 @@ void orc_destroy(orc_scene* sc) {
   free(sc->v_off); free(sc->t_off); free(sc->f_off);
   free(sc->verts); free(sc->tris); free(sc->planes);
   free(sc->poses); free(sc->obj_mesh);
-  free(sc->I_pix); free(sc->I_cam); free(sc->I_w); free(sc->pix2pt);
+  free(sc->I_pix); free(sc->I_cam); free(sc->I_w); free(sc->pix2pt); free(sc->sym);
   free(sc);
 }
 
@@ -1075,6 +1077,32 @@ int orc_jtree(const orc_scene* sc, int32_t K, const int32_t* mesh, const int32_t
 /* ------------------------------------------------------------------------- */
 
 /* distinct mesh ids still to place, given the placed ones (multiset difference) */
+int orc_set_symmetric(orc_scene* sc, int32_t mesh, int32_t symmetric) {
+  if (!sc || mesh < 0 || mesh >= sc->n_mesh) return -1;
+  sc->sym[mesh] = symmetric ? 1 : 0;
+  return 0;
+}
+
+/* The poses a search tries for `mesh`: the subset itself, or for a rotationally
+ * symmetric mesh (Sec. V-A: only (x, y) matters) the first pose of the subset at
+ * each distinct (x, y).  Returns the count written to out. */
+static int mesh_subset(const orc_scene* sc, int mesh, int nsub, const int32_t* sub,
+                       int32_t* out) {
+  int n = 0;
+  for (int b = 0; b < nsub; ++b) {
+    int dup = 0;
+    if (sc->sym[mesh]) {
+      const float* q = sc->poses + 4 * (size_t)sub[b];
+      for (int a = 0; a < n && !dup; ++a) {
+        const float* r = sc->poses + 4 * (size_t)out[a];
+        dup = (q[0] == r[0] && q[1] == r[1]);
+      }
+    }
+    if (!dup) out[n++] = sub[b];
+  }
+  return n;
+}
+
 static int remaining_meshes(const orc_scene* sc, int j, const int32_t* pm, int32_t* out) {
   int32_t left[8];
   int nl = sc->K;
@@ -1111,14 +1139,15 @@ static void exh_rec(exh_t* E, int j, int32_t* pm, int32_t* pp, int64_t g) {
   const orc_scene* sc = E->sc;
   int32_t ids[8];
   int nd = remaining_meshes(sc, j, pm, ids);
-  int n = nd * E->nsub;
-  int32_t* cm = (int32_t*)malloc(sizeof(int32_t) * 4 * (size_t)n);
-  int32_t *cp = cm + n, *st = cm + 2 * n, *cost = cm + 3 * n;
-  for (int a = 0; a < nd; ++a)
-    for (int b = 0; b < E->nsub; ++b) {
-      cm[a * E->nsub + b] = ids[a];
-      cp[a * E->nsub + b] = E->sub[b];
-    }
+  int cap = nd * E->nsub;
+  int32_t* cm = (int32_t*)malloc(sizeof(int32_t) * 4 * (size_t)(cap + 1));
+  int32_t *cp = cm + cap, *st = cm + 2 * cap, *cost = cm + 3 * cap;
+  int n = 0;
+  for (int a = 0; a < nd; ++a) {
+    const int c = mesh_subset(sc, ids[a], E->nsub, E->sub, cp + n);
+    for (int b = 0; b < c; ++b) cm[n + b] = ids[a];
+    n += c;
+  }
   parent_buf_t pb;
   int rc = parent_build(sc, j, pm, pp, &pb);
   if (!rc) rc = eval_batch(sc, &pb.p, n, cm, cp, st, cost, NULL, NULL);
@@ -1315,14 +1344,15 @@ int orc_search_ucs(const orc_scene* sc, int32_t n_sub, const int32_t* pose_sub,
     int32_t pm[8], pp[8], ids[8];
     for (int k = 0; k < cur.j; ++k) { pm[k] = cur.key[2 * k]; pp[k] = cur.key[2 * k + 1]; }
     int nd = remaining_meshes(sc, cur.j, pm, ids);
-    int n = nd * n_sub;
-    int32_t* cm = (int32_t*)malloc(sizeof(int32_t) * 4 * (size_t)n);
-    int32_t *cp = cm + n, *st = cm + 2 * n, *cost = cm + 3 * n;
-    for (int a = 0; a < nd; ++a)
-      for (int b = 0; b < n_sub; ++b) {
-        cm[a * n_sub + b] = ids[a];
-        cp[a * n_sub + b] = sub[b];
-      }
+    int cap = nd * n_sub;
+    int32_t* cm = (int32_t*)malloc(sizeof(int32_t) * 4 * (size_t)(cap + 1));
+    int32_t *cp = cm + cap, *st = cm + 2 * cap, *cost = cm + 3 * cap;
+    int n = 0;
+    for (int a = 0; a < nd; ++a) {
+      const int c = mesh_subset(sc, ids[a], n_sub, sub, cp + n);
+      for (int b = 0; b < c; ++b) cm[n + b] = ids[a];
+      n += c;
+    }
     parent_buf_t pb;
     rc = parent_build(sc, cur.j, pm, pp, &pb);
     if (!rc) rc = eval_batch(sc, &pb.p, n, cm, cp, st, cost, NULL, NULL);
@@ -1381,6 +1411,8 @@ typedef struct {
   const orc_scene* sc;
   int nsub, tid, nth;
   const int32_t* sub;
+  const int32_t* lists; /* per object k: its poses at lists + k * nsub, count cnt[k] */
+  const int32_t* cnt;
   int64_t best;
   int32_t key[16];
   int have;
@@ -1393,14 +1425,14 @@ static void* bf_worker(void* arg) {
   const orc_scene* sc = B->sc;
   int K = sc->K;
   int64_t total = 1;
-  for (int k = 0; k < K; ++k) total *= B->nsub;
+  for (int k = 0; k < K; ++k) total *= B->cnt[k];
   for (int64_t idx = B->tid; idx < total; idx += B->nth) {
     int32_t m[8], p[8];
     int64_t r = idx;
     for (int k = 0; k < K; ++k) {
       m[k] = sc->obj_mesh[k];
-      p[k] = B->sub[r % B->nsub];
-      r /= B->nsub;
+      p[k] = B->lists[(size_t)k * B->nsub + r % B->cnt[k]];
+      r /= B->cnt[k];
     }
     int64_t out[6];
     int rc = orc_jtree(sc, K, m, p, out);
@@ -1426,18 +1458,24 @@ int orc_bruteforce_joint(const orc_scene* sc, int32_t n_sub, const int32_t* pose
   const int32_t* sub = own ? own : pose_sub;
   for (int i = 0; i < n_sub; ++i)
     if (sub[i] < 0 || sub[i] >= sc->P) { free(own); return -1; }
+  int32_t* lists = (int32_t*)malloc(sizeof(int32_t) * (size_t)sc->K * (size_t)(n_sub + 1));
+  int32_t cnt[8];
+  for (int k = 0; k < sc->K; ++k)
+    cnt[k] = mesh_subset(sc, sc->obj_mesh[k], n_sub, sub, lists + (size_t)k * n_sub);
   int nth = sc->nthreads > 256 ? 256 : sc->nthreads;
   bf_t B[256];
   pthread_t th[256];
   for (int t = 0; t < nth; ++t) {
     memset(&B[t], 0, sizeof(bf_t));
     B[t].sc = sc; B[t].nsub = n_sub; B[t].tid = t; B[t].nth = nth; B[t].sub = sub;
+    B[t].lists = lists; B[t].cnt = cnt;
   }
   if (nth == 1) bf_worker(&B[0]);
   else {
     for (int t = 0; t < nth; ++t) pthread_create(&th[t], NULL, bf_worker, &B[t]);
     for (int t = 0; t < nth; ++t) pthread_join(th[t], NULL);
   }
+  free(lists);
   free(own);
   int have = 0;
   int64_t best = 0, nvalid = 0;

@@ -112,6 +112,11 @@ int orc_jtree(const orc_scene* sc, int32_t K, const int32_t* mesh,
  * best_mesh/best_pose receive the goal in canonical order (sorted by
  * (mesh, pose)).  stats: [0] cost, [1] successor evaluations, [2] expansions,
  * [3] goals seen.  Return 0 on success, 1 when no goal exists. */
+/* Marks mesh as rotationally symmetric about the vertical axis (Sec. V-A): the
+ * searches below then try it only at the first pose of the subset at each distinct
+ * (x, y). */
+int orc_set_symmetric(orc_scene* sc, int32_t mesh, int32_t symmetric);
+
 int orc_search_exhaustive(const orc_scene* sc, int32_t n_sub, const int32_t* pose_sub,
                           int32_t* best_mesh, int32_t* best_pose, int64_t* stats);
 int orc_search_ucs(const orc_scene* sc, int32_t n_sub, const int32_t* pose_sub,
