@@ -100,6 +100,14 @@ perch_status perch_add_mesh(perch_ctx* ctx, int32_t mesh_id, const float* verts,
                             int32_t n_verts, const int32_t* tris, int32_t n_tris,
                             const float* planes, int32_t n_planes);
 
+/* Marks a mesh as rotationally symmetric about the vertical axis (Sec. V-A: only
+ * its (x, y) matters).  perch_search then tries it only at the first pose of the
+ * pose list (table or subset, in order) at each distinct (x, y); not with the
+ * learned search modes.  Identical objects need no flag: the object multiset
+ * (perch_set_objects) lists the mesh id once per instance and the searches place
+ * instances of one mesh as a set, not in every order. */
+perch_status perch_set_symmetric(perch_ctx* ctx, int32_t mesh_id, int32_t symmetric);
+
 /* Sets the discretised pose set (Sec. IV-E, the x/y/yaw grid): host, P x 4 rows
  * (x, y, cos theta, sin theta).  Empties the pose arena (perch_set_pose_arena). */
 perch_status perch_set_poses(perch_ctx* ctx, const float* poses, int32_t P);

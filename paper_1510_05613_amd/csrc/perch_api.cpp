@@ -300,6 +300,15 @@ perch_status perch_add_mesh(perch_ctx* c, int32_t mesh_id, const float* verts, i
   return PERCH_OK;
 }
 
+perch_status perch_set_symmetric(perch_ctx* c, int32_t mesh_id, int32_t symmetric) {
+  if (!c) return fail(PERCH_E_ARG, "null context");
+  if (mesh_id < 0 || mesh_id >= (int)c->meshes.size() || !c->meshes[mesh_id].set)
+    return fail(PERCH_E_ARG, "mesh %d not added", mesh_id);
+  if ((int)c->symmetric.size() <= mesh_id) c->symmetric.resize(mesh_id + 1, 0);
+  c->symmetric[mesh_id] = symmetric ? 1 : 0;
+  return PERCH_OK;
+}
+
 perch_status perch_set_poses(perch_ctx* c, const float* poses, int32_t P) {
   if (!c || !poses || P <= 0) return fail(PERCH_E_ARG, "bad pose table");
   HIP_TRY(c->poses.ensure(((size_t)P + c->arena_cap) * sizeof(float4)));

@@ -143,6 +143,7 @@ struct perch_ctx {
   int device = 0;
   // model library
   std::vector<HostMesh> meshes;
+  std::vector<uint8_t> symmetric;  // per mesh id: searched over (x, y) only
   bool meshes_dirty = true;
   int max_nv = 0;
   DevBuf verts, tris, planes, range, frange, aabb;

@@ -125,6 +125,27 @@ class Searcher {
     for (int m : c_->objects)
       if (std::find(seen.begin(), seen.end(), m) == seen.end()) seen.push_back(m), ++distinct;
     distinct_ = distinct;
+    // rotationally symmetric meshes (Sec. V-A) are tried once per (x, y): the
+    // first pose of the list at each distinct position
+    bool any_sym = false;
+    for (int m : seen) {
+      std::vector<int>& L = mesh_poses_[m];
+      const bool sym = m < (int)c_->symmetric.size() && c_->symmetric[m];
+      any_sym |= sym;
+      if (!sym) {
+        L = poses_;
+        continue;
+      }
+      std::unordered_map<uint64_t, int> first;
+      for (int p : poses_) {
+        uint32_t bx, by;
+        std::memcpy(&bx, &c_->h_poses[4 * (size_t)p], 4);
+        std::memcpy(&by, &c_->h_poses[4 * (size_t)p + 1], 4);
+        if (first.emplace(((uint64_t)bx << 32) | by, p).second) L.push_back(p);
+      }
+    }
+    if (any_sym && (o_.mode == PERCH_SEARCH_LEARNED || o_.mode == PERCH_SEARCH_LEARNED_MHA))
+      return fail(PERCH_E_ARG, "symmetric meshes are not available to the learned searches");
     const size_t cap = (size_t)distinct * poses_.size();
     HIP_TRY(c_->s_cands.ensure(cap * sizeof(int2)));
     HIP_TRY(c_->s_out.ensure(cap * 3 * sizeof(int32_t)));
@@ -171,11 +192,10 @@ class Searcher {
   perch_status expand(const Node& n, std::vector<Child>& out, bool with_gain = false) {
     out.clear();
     const std::vector<int> rest = remaining(n);
-    const int P = (int)poses_.size();
-    const int cnt = (int)rest.size() * P;
     int2* hc = c_->s_hcands.as<int2>();
-    for (size_t a = 0; a < rest.size(); ++a)
-      for (int b = 0; b < P; ++b) hc[a * P + b] = make_int2(rest[a], poses_[b]);
+    int cnt = 0;
+    for (int m : rest)
+      for (int p : mesh_poses_.at(m)) hc[cnt++] = make_int2(m, p);
     HIP_TRY(hipMemcpyAsync(c_->s_cands.p, hc, cnt * sizeof(int2), hipMemcpyHostToDevice,
                            c_->stream));
     perch_status st = perch_set_parent(c_, n.objs, n.j);
@@ -715,6 +735,7 @@ class Searcher {
   int K_ = 0;
   int distinct_ = 0;
   std::vector<int> poses_;
+  std::map<int, std::vector<int>> mesh_poses_;  // per object mesh: the poses it is tried at
   Clock::time_point t0_;
   int64_t n_expanded_ = 0, n_evaluated_ = 0, n_invalid_ = 0, expansions_ = 0, n_merged_ = 0;
   int64_t lower_bound_ = 0;

@@ -26,6 +26,7 @@ PERCH_SUCC_BAD_INPUT = -4
 EXPORTS = ("perch_create", "perch_destroy", "perch_set_observation", "perch_add_mesh",
            "perch_set_poses", "perch_set_objects", "perch_eval_successors", "perch_set_parent",
            "perch_eval_children", "perch_overlap_gain", "perch_set_pose_arena",
+           "perch_set_symmetric",
            "perch_get_poses", "perch_icp_children", "perch_render", "perch_set_tuning",
            "perch_get_info",
            "perch_search", "perch_batch_create", "perch_batch_destroy",
@@ -102,6 +103,7 @@ def load(path: str = LIB_PATH):
     L.perch_render.argtypes = [P, P, I32, I32, P]
     L.perch_overlap_gain.argtypes = [P, P, I32, P, P, P]
     L.perch_set_pose_arena.argtypes = [P, I32]
+    L.perch_set_symmetric.argtypes = [P, I32, I32]
     L.perch_get_poses.argtypes = [P, I32, I32, P]
     L.perch_icp_children.argtypes = [P, P, I32, I32, C.c_float, P, P, P]
     L.perch_set_tuning.argtypes = [P, I32, I32, C.c_float, I32]
@@ -279,6 +281,10 @@ class Context:
         comps = torch.empty((n, 5), dtype=torch.int32, device=dev) if with_comps else None
         self.eval_successors(parent, cands, cost, status, comps)
         return status, cost, comps
+
+    def set_symmetric(self, mesh_id: int, symmetric: bool = True):
+        """The searches try a rotationally symmetric mesh once per (x, y)."""
+        _check(load().perch_set_symmetric(self.h, int(mesh_id), int(bool(symmetric))))
 
     def set_pose_arena(self, capacity: int):
         """Room for `capacity` ICP-adjusted poses after the grid (empties it)."""
