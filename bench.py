@@ -79,6 +79,8 @@ def parse_args(argv=None):
                     help="held-out 640x480 scenes for a learned-vs-plain leg (minutes; 0 = off)")
     ap.add_argument("--icp-iters", type=int, default=10,
                     help="local ICP leg: rounds per candidate over the root's successors (0 = off)")
+    ap.add_argument("--prior-scenes", type=int, default=0,
+                    help="held-out 640x480 scenes for the pose-prior queue leg (0 = off)")
     ap.add_argument("--icp-offgrid-scenes", type=int, default=0,
                     help="off-grid scenes searched with and without local ICP (0 = off)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -414,6 +416,22 @@ def icp_offgrid_leg(n_scenes: int, budget_s: float = 10.0, iters: int = 10) -> d
                          "grid, candidates in the 7 x 7 cells around the ground truth; medians")}
 
 
+def prior_leg(n_scenes: int, budget_s: float = 10.0) -> dict:
+    """Focal-MHA* with and without a third queue on the pose-prior heuristic
+    (estimates from the 640x480 network, or the true poses as a reference)."""
+    from paper_1510_05613_amd import learn
+
+    if not os.path.exists(CHECKPOINT_640):
+        return {"skipped": "no trained checkpoint"}
+    net, _ = learn.search_networks(CHECKPOINT_640, 2)
+    first = learn.HELD_OUT_FIRST
+    g = learn.prior_gain(net, range(first, first + 2 * n_scenes), config=2, budget_s=budget_s,
+                         max_scenes=n_scenes, log=lambda m: print(m, file=sys.stderr, flush=True))
+    g["workload"] = (f"config 2 (640x480, K=3, 40,000 poses/object), the first {n_scenes} "
+                     f"held-out scenes from {first}; medians, {budget_s:.0f} s per search")
+    return g
+
+
 def main(argv=None):
     args = parse_args(argv)
     if args.gpus != 1:
@@ -524,6 +542,8 @@ def main(argv=None):
     }
     if args.icp_iters > 0 and args.config == 2:
         out["icp"] = icp_leg(ctx, sc, dev[0], args.icp_iters)
+    if args.prior_scenes > 0 and args.config == 2:
+        out["prior"] = prior_leg(args.prior_scenes)
     if args.icp_offgrid_scenes > 0 and args.config == 2:
         out["icp_offgrid"] = icp_offgrid_leg(args.icp_offgrid_scenes)
     if args.learned_scenes > 0 and args.config == 2:

@@ -319,6 +319,13 @@ perch_status perch_cnn_gradients(perch_cnn* net, const uint16_t* crops_dev, int3
 #define PERCH_SEARCH_LEARNED_MHA 5 /* LEARNED with h_overlap as a second inadmissible    */
                                   /* queue over the children it evaluates               */
 
+/* A discriminative pose estimate O' of one object (Sec. IV-C: e.g. from a feature-
+ * or learning-based detector), for the pose-prior heuristic. */
+typedef struct {
+  int32_t mesh_id;
+  float x, y, theta;           /* table-plane position (m) and yaw (rad)               */
+} perch_pose_prior;
+
 typedef struct {
   int32_t mode;                /* PERCH_SEARCH_*                                        */
   float w;                     /* suboptimality bound for FOCAL (>= 1)                  */
@@ -336,6 +343,14 @@ typedef struct {
                                /* as on a spent budget when it has no room for the     */
                                /* next expansion's children                            */
   float icp_radius;            /* ICP association radius in metres (0: 0.02)           */
+  const perch_pose_prior* priors; /* MHA: pose estimates (host), n_priors > 0 adds a    */
+  int32_t n_priors;            /* third inadmissible queue on h_prior(s) = sum over the */
+                               /* placed objects of the distance to the nearest estimate*/
+                               /* of the same mesh (metres + prior_rad_m per radian of  */
+                               /* yaw, yaw ignored for symmetric meshes), plus          */
+                               /* prior_slot_m per object still to place (Sec. IV-C)    */
+  float prior_rad_m;           /* 0: 0.05 m per radian                                 */
+  float prior_slot_m;          /* 0: 0.1 m                                             */
 } perch_search_opts;
 
 typedef struct {

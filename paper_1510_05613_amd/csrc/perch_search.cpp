@@ -54,6 +54,7 @@ struct Node {
   int64_t key[8];        // canonical: sorted (mesh << 32 | pose)
   int32_t lazy;          // learned search: a block of unevaluated children of `parent`
   int64_t hov;           // overlap heuristic: observed points outside V_j (MHA search)
+  double hpr;            // pose-prior heuristic: sum of distances to the estimates
 };
 
 int64_t pack(int32_t m, int32_t p) { return ((int64_t)m << 32) | (uint32_t)p; }
@@ -88,6 +89,7 @@ struct KeyEq {
 
 struct Child {
   int32_t mesh, pose, cost, gain;  // gain: observed points the child adds to V_j
+  float x, y, c, s;                // the child's pose values (grid or ICP-adjusted)
 };
 
 // Device buffers of one search call, released when it returns.
@@ -233,9 +235,11 @@ class Searcher {
     n_evaluated_ += cnt;
     for (int i = 0; i < cnt; ++i) {
       const int s = hout[cnt + i];
-      if (s == 1)
+      if (s == 1) {
+        const float* q = hpose ? hpose + 4 * (size_t)i : &c_->h_poses[4 * (size_t)hc[i].y];
         out.push_back({hc[i].x, icp_base >= 0 ? icp_base + i : hc[i].y, hout[i],
-                       with_gain ? hout[2 * cnt + i] : 0});
+                       with_gain ? hout[2 * cnt + i] : 0, q[0], q[1], q[2], q[3]});
+      }
       else if (s == 0)
         ++n_invalid_;
       else
@@ -290,8 +294,34 @@ class Searcher {
     make_key(m);
     m.lazy = 0;
     m.hov = n.hov - ch.gain;
+    m.hpr = n.hpr + prior_term(ch);
     return m;
   }
+
+  // ||O - O'|| of the pose-prior heuristic: the smallest distance from the child's
+  // object to an estimate of the same mesh, table-plane metres plus
+  // prior_rad_m metres per radian of yaw (yaw ignored for symmetric meshes); 0
+  // when the mesh has no estimate.
+  double prior_term(const Child& ch) const {
+    double best = -1.0;
+    const bool sym = ch.mesh < (int)c_->symmetric.size() && c_->symmetric[ch.mesh];
+    const double th = std::atan2((double)ch.s, (double)ch.c);
+    for (int k = 0; k < o_.n_priors; ++k) {
+      const perch_pose_prior& q = o_.priors[k];
+      if (q.mesh_id != ch.mesh) continue;
+      double d = std::hypot((double)ch.x - q.x, (double)ch.y - q.y);
+      if (!sym) {
+        double a = std::fabs(th - (double)q.theta);
+        a = std::fmod(a, 2.0 * 3.14159265358979323846);
+        if (a > 3.14159265358979323846) a = 2.0 * 3.14159265358979323846 - a;
+        d += prior_rad_m() * a;
+      }
+      if (best < 0.0 || d < best) best = d;
+    }
+    return best < 0.0 ? 0.0 : best;
+  }
+  double prior_rad_m() const { return o_.prior_rad_m > 0.0f ? o_.prior_rad_m : 0.05; }
+  double prior_slot_m() const { return o_.prior_slot_m > 0.0f ? o_.prior_slot_m : 0.1; }
 
   void offer_goal(const Node& g, const std::vector<Node>* store) {
     if (have_ && (g.g > best_.g || (g.g == best_.g && cmp_key(g, best_) >= 0))) return;
@@ -378,6 +408,17 @@ class Searcher {
       return cmp_key(x, y) > 0;
     };
     std::priority_queue<int, std::vector<int>, decltype(o_less)> over_q(o_less);
+    // pose-prior heap: the sum of distances to the estimates plus prior_slot_m for
+    // each object still to place, then smaller g, then key
+    auto hp = [&](const Node& x) { return x.hpr + prior_slot_m() * (K_ - x.j); };
+    auto p_less = [&](int a, int b) {
+      const Node &x = nodes[a], &y = nodes[b];
+      const double hx = hp(x), hy = hp(y);
+      if (hx != hy) return hx > hy;
+      if (x.g != y.g) return x.g > y.g;
+      return cmp_key(x, y) > 0;
+    };
+    std::priority_queue<int, std::vector<int>, decltype(p_less)> prior_q(p_less);
     // states waiting for the focal bound, ordered by g
     std::priority_queue<int, std::vector<int>, decltype(g_less)> pending(g_less);
     open.push(0);
@@ -401,11 +442,13 @@ class Searcher {
           if (live(pending.top())) {
             focal_q.push(pending.top());
             if (n_inad > 1) over_q.push(pending.top());
+            if (n_inad > 2) prior_q.push(pending.top());
           }
           pending.pop();
         }
         while (!focal_q.empty() && !live(focal_q.top())) focal_q.pop();
         while (!over_q.empty() && !live(over_q.top())) over_q.pop();
+        while (!prior_q.empty() && !live(prior_q.top())) prior_q.pop();
         // round robin over the inadmissible queues, and the anchor when anytime
         const int cycle = n_inad + (o_.anytime ? 1 : 0);
         const int slot = (int)(expansions_ % cycle);
@@ -417,6 +460,9 @@ class Searcher {
           } else if (q == 1 && !over_q.empty()) {
             pick = over_q.top();
             over_q.pop();
+          } else if (q == 2 && !prior_q.empty()) {
+            pick = prior_q.top();
+            prior_q.pop();
           }
         }
       }
@@ -754,6 +800,10 @@ extern "C" perch_status perch_search(perch_ctx* c, const perch_search_opts* opts
   if (!c || !opts || !out) return fail(PERCH_E_ARG, "null argument");
   if (opts->mode < PERCH_SEARCH_EXHAUSTIVE || opts->mode > PERCH_SEARCH_LEARNED_MHA)
     return fail(PERCH_E_ARG, "unknown search mode %d", opts->mode);
+  if (opts->n_priors < 0 || (opts->n_priors > 0 && !opts->priors))
+    return fail(PERCH_E_ARG, "bad pose priors");
+  if (opts->n_priors > 0 && opts->mode != PERCH_SEARCH_MHA)
+    return fail(PERCH_E_ARG, "pose priors are a queue of the multi-heuristic search");
   if (opts->mode >= PERCH_SEARCH_FOCAL && !(opts->w >= 1.0f))
     return fail(PERCH_E_ARG, "focal, learned and multi-heuristic searches need w >= 1");
   Searcher s(c, opts);
@@ -764,7 +814,7 @@ extern "C" perch_status perch_search(perch_ctx* c, const perch_search_opts* opts
   else if (opts->mode == PERCH_SEARCH_LEARNED || opts->mode == PERCH_SEARCH_LEARNED_MHA)
     st = s.learned(opts->mode == PERCH_SEARCH_LEARNED_MHA);
   else if (opts->mode == PERCH_SEARCH_MHA)
-    st = s.best_first(2);
+    st = s.best_first(opts->n_priors > 0 ? 3 : 2);
   else
     st = s.best_first(opts->mode == PERCH_SEARCH_FOCAL ? 1 : 0);
   s.fill(out);

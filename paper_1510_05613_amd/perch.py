@@ -62,12 +62,18 @@ class _Tuning(C.Structure):
                 ("cell_over_delta", C.c_float), ("ms", C.c_float)]
 
 
+class PerchPosePrior(C.Structure):
+    _fields_ = [("mesh_id", C.c_int32), ("x", C.c_float), ("y", C.c_float),
+                ("theta", C.c_float)]
+
+
 class _SearchOpts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("w", C.c_float), ("anytime", C.c_int32),
                 ("budget_s", C.c_double), ("budget_expansions", C.c_int64),
                 ("pose_subset", C.c_void_p), ("n_pose_subset", C.c_int32),
                 ("cnn", C.c_void_p), ("topk", C.c_int32), ("icp_iters", C.c_int32),
-                ("icp_radius", C.c_float)]
+                ("icp_radius", C.c_float), ("priors", C.c_void_p), ("n_priors", C.c_int32),
+                ("prior_rad_m", C.c_float), ("prior_slot_m", C.c_float)]
 
 
 class _Result(C.Structure):
@@ -310,7 +316,8 @@ class Context:
     def search(self, mode: int = SEARCH_UCS, w: float = 1.0, anytime: bool = False,
                budget_s: float = 0.0, budget_expansions: int = 0, pose_subset=None,
                cnn: "Optional[Cnn]" = None, topk: int = 64, icp_iters: int = 0,
-               icp_radius: float = 0.02) -> dict:
+               icp_radius: float = 0.02, priors=None, prior_rad_m: float = 0.0,
+               prior_slot_m: float = 0.0) -> dict:
         """Tree search of Alg. 1 on this scene (synchronous).  Returns the goal in
         insertion order plus its canonical (sorted) form, cost and statistics."""
         o = _SearchOpts()
@@ -319,6 +326,13 @@ class Context:
         o.cnn = None if cnn is None else cnn.h.value
         o.topk = int(topk)
         o.icp_iters, o.icp_radius = int(icp_iters), float(icp_radius)
+        pri = None
+        if priors is not None and len(priors):  # [(mesh, x, y, theta), ...]
+            pri = (PerchPosePrior * len(priors))()
+            for k, (m, x, y, th) in enumerate(priors):
+                pri[k].mesh_id, pri[k].x, pri[k].y, pri[k].theta = int(m), x, y, th
+            o.priors, o.n_priors = C.cast(pri, C.c_void_p), len(priors)
+        o.prior_rad_m, o.prior_slot_m = float(prior_rad_m), float(prior_slot_m)
         sub = None
         if pose_subset is not None:
             sub = np.ascontiguousarray(pose_subset, np.int32)

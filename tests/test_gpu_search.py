@@ -110,3 +110,26 @@ def test_multi_heuristic_on_pose_subsets_matches_oracle_optimum():
     assert a["found"] and a["cost"] == opt
     f = ctx.search(perch.SEARCH_MHA, w=3.0, pose_subset=sub)
     assert f["cost"] <= 3.0 * opt
+
+
+@pytest.mark.parametrize("w", [1.0, 2.0])
+def test_pose_prior_queue_keeps_the_w_bound(w):
+    """A third inadmissible queue on the pose-prior heuristic (Sec. IV-C), with
+    estimates that are right (the true poses) or wrong (shifted across the
+    table): Theorem 2's bound holds whatever the estimates say."""
+    sc = H.c1_scene(2)
+    sub = scenes.pose_subset_around(sc, 2, yaw_stride=2)
+    opt = Oracle.from_scene(sc, nthreads=NTH).search_exhaustive(sub)["cost"]
+    ctx = perch.context_from_scene(sc)
+    true = [(int(m), float(sc.poses[p, 0]), float(sc.poses[p, 1]),
+             float(np.arctan2(sc.poses[p, 3], sc.poses[p, 2])))
+            for m, p in zip(sc.obj_mesh, sc.gt_pose)]
+    wrong = [(m, -x, -y, th + 1.0) for (m, x, y, th) in true]
+    for pri in (true, wrong):
+        r = ctx.search(perch.SEARCH_MHA, w=w, pose_subset=sub, priors=pri)
+        assert r["found"] and r["cost"] <= w * opt + 1e-9
+        assert sum(r["edge_cost"]) == r["cost"]
+        a = ctx.search(perch.SEARCH_MHA, w=w, anytime=True, pose_subset=sub, priors=pri)
+        assert a["cost"] == opt and a["lower_bound"] >= a["cost"]
+    with pytest.raises(perch.PerchError):  # a queue of the multi-heuristic search only
+        ctx.search(perch.SEARCH_FOCAL, w=w, pose_subset=sub, priors=true)
