@@ -79,6 +79,8 @@ def parse_args(argv=None):
                     help="held-out 640x480 scenes for a learned-vs-plain leg (minutes; 0 = off)")
     ap.add_argument("--icp-iters", type=int, default=10,
                     help="local ICP leg: rounds per candidate over the root's successors (0 = off)")
+    ap.add_argument("--chessboard", action="store_true",
+                    help="the twelve-piece chessboard-like stand-in leg")
     ap.add_argument("--prior-scenes", type=int, default=0,
                     help="held-out 640x480 scenes for the pose-prior queue leg (0 = off)")
     ap.add_argument("--icp-offgrid-scenes", type=int, default=0,
@@ -432,6 +434,50 @@ def prior_leg(n_scenes: int, budget_s: float = 10.0) -> dict:
     return g
 
 
+def chessboard_leg(budget_s: float = 10.0) -> dict:
+    """The twelve-piece chessboard-like stand-in (scenes.chessboard_scene): the
+    paper's Focal-MHA* with w = 15, first goal and anytime with a time budget, with
+    the pawns and kings declared rotationally symmetric (tried once per square) and
+    without.  Reports times, costs, evaluations and how many pieces land on their
+    true square (matched per mesh)."""
+    from paper_1510_05613_amd import perch, scenes
+
+    sc = scenes.chessboard_scene(perch.GpuRenderer(), 0)
+    g = sc.grid
+    truth = [(int(m), g.unindex(int(p))[:2]) for m, p in zip(sc.obj_mesh, sc.gt_pose)]
+
+    def correct(objs):
+        left = list(truth)
+        n = 0
+        for m, p in objs:
+            key = (m, g.unindex(p)[:2])
+            if key in left:
+                left.remove(key)
+                n += 1
+        return n
+
+    out = {}
+    for name, sym in (("symmetric", True), ("plain", False)):
+        ctx = perch.context_from_scene(sc)
+        if sym:
+            ctx.set_symmetric(0)
+            ctx.set_symmetric(2)
+        r = ctx.search(perch.SEARCH_MHA, w=15.0, budget_s=budget_s)
+        a = ctx.search(perch.SEARCH_MHA, w=15.0, anytime=True, budget_s=budget_s)
+        out[name] = {"first_goal_s": round(r["t_total_s"], 4) if r["found"] else None,
+                     "first_goal_cost": r["cost"] if r["found"] else None,
+                     "first_goal_evals": r["n_evaluated"],
+                     "first_goal_pieces_on_true_square": correct(r["objs"]) if r["found"] else 0,
+                     "anytime_cost": a["cost"] if a["found"] else None,
+                     "anytime_evals": a["n_evaluated"],
+                     "anytime_pieces_on_true_square": correct(a["objs"]) if a["found"] else 0}
+        ctx.close()
+    out["true_scene_cost"] = 0
+    out["workload"] = (f"12 pieces (8 pawns, 2 rooks, 2 kings) on an 8 x 8 board of 4 cm squares, "
+                       f"512 poses (8 yaws), 640x480, delta 7.5 mm, w = 15, {budget_s:.0f} s budget")
+    return out
+
+
 def main(argv=None):
     args = parse_args(argv)
     if args.gpus != 1:
@@ -542,6 +588,8 @@ def main(argv=None):
     }
     if args.icp_iters > 0 and args.config == 2:
         out["icp"] = icp_leg(ctx, sc, dev[0], args.icp_iters)
+    if args.chessboard and args.config == 2:
+        out["chessboard"] = chessboard_leg()
     if args.prior_scenes > 0 and args.config == 2:
         out["prior"] = prior_leg(args.prior_scenes)
     if args.icp_offgrid_scenes > 0 and args.config == 2:

@@ -122,7 +122,10 @@ perch_status perch_set_pose_arena(perch_ctx* ctx, int32_t capacity);
  * n x 4 floats (x, y, cos, sin).  Synchronous. */
 perch_status perch_get_poses(perch_ctx* ctx, int32_t first, int32_t n, float* poses_host);
 
-/* Sets the known multiset of K <= 8 mesh ids in the scene (Sec. III assumptions);
+/* Most objects in a scene (and placed in a state). */
+#define PERCH_MAX_OBJECTS 16
+
+/* Sets the known multiset of K <= PERCH_MAX_OBJECTS mesh ids in the scene (Sec. III assumptions);
  * the goal level of the tree is K. */
 perch_status perch_set_objects(perch_ctx* ctx, const int32_t* mesh_ids, int32_t K);
 
@@ -228,7 +231,7 @@ typedef struct perch_batch perch_batch;
 typedef struct {
   int32_t ctx;            /* index into the batch's contexts                       */
   int32_t j;              /* number of placed objects (j < K of that context)      */
-  perch_object objs[8];   /* the parent state s = objs[0..j)                       */
+  perch_object objs[PERCH_MAX_OBJECTS]; /* the parent state s = objs[0..j)         */
 } perch_parent;
 
 typedef struct {
@@ -354,11 +357,11 @@ typedef struct {
 } perch_search_opts;
 
 typedef struct {
-  perch_object objs[8];        /* the goal, in insertion order (a valid order)           */
+  perch_object objs[PERCH_MAX_OBJECTS]; /* the goal, in insertion order (valid)      */
   int32_t K;
   int32_t found;               /* 1 if a goal was reached                               */
   int64_t cost;                /* sum of edge costs (Eq. 2)                             */
-  int32_t edge_cost[8];        /* c(s_i, s_{i+1}) along the path                        */
+  int32_t edge_cost[PERCH_MAX_OBJECTS]; /* c(s_i, s_{i+1}) along the path          */
   int64_t n_expanded, n_evaluated, n_invalid;
   double t_total_s;            /* wall time of the call                                 */
   double t_best_s;             /* wall time until the returned cost was first reached   */

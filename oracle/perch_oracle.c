@@ -42,6 +42,7 @@
 #include <string.h>
 
 #define FLAG_EPS 1e-6 /* near-tie band (metres) for the flags */
+#define ORC_MAX_K 16   /* most objects in a scene */
 
 struct orc_scene {
   orc_sensor s;
@@ -308,7 +309,7 @@ orc_scene* orc_create(const orc_sensor* sensor, const float* depth_obs, int32_t 
                       int32_t n_poses, const float* poses, int32_t K,
                       const int32_t* obj_mesh) {
   if (!sensor || sensor->width <= 0 || sensor->height <= 0 || n_mesh <= 0 || n_poses <= 0 ||
-      K < 0 || K > 8)
+      K < 0 || K > ORC_MAX_K)
     return NULL;
   orc_scene* sc = (orc_scene*)calloc(1, sizeof(orc_scene));
   sc->s = *sensor;
@@ -981,21 +982,21 @@ static int cmp_key(int K, const int32_t* a, const int32_t* b) {
 
 int orc_jtree(const orc_scene* sc, int32_t K, const int32_t* mesh, const int32_t* pose,
               int64_t* out) {
-  if (!sc || K < 1 || K > 8 || check_objects(sc, K, mesh, pose)) return -1;
+  if (!sc || K < 1 || K > ORC_MAX_K || check_objects(sc, K, mesh, pose)) return -1;
   const int W = sc->W, H = sc->H;
   const size_t npx = (size_t)W * H;
-  int32_t obj[16];
+  int32_t obj[2 * ORC_MAX_K];
   for (int k = 0; k < K; ++k) { obj[2 * k] = mesh[k]; obj[2 * k + 1] = pose[k]; }
   canon(K, obj);
   double* D = (double*)malloc(sizeof(double) * npx * (K + 2));
   double* RK = D + npx * K;
   double* OW = D + npx * (K + 1);
-  int32_t m[8], p[8];
+  int32_t m[ORC_MAX_K], p[ORC_MAX_K];
   for (int k = 0; k < K; ++k) { m[k] = obj[2 * k]; p[k] = obj[2 * k + 1]; }
   int rc = orc_render_objects(sc, K, m, p, 1, D);
   if (rc) { free(D); return rc; }
   int8_t* owner = (int8_t*)malloc(npx);
-  int occ[8][8];
+  int occ[ORC_MAX_K][ORC_MAX_K];
   memset(occ, 0, sizeof(occ));
   int ftie = 0;
   for (size_t i = 0; i < npx; ++i) {
@@ -1016,7 +1017,7 @@ int orc_jtree(const orc_scene* sc, int32_t K, const int32_t* mesh, const int32_t
       }
   }
   /* the order constraint of Eq.(3) can be met iff "a occludes b" is acyclic */
-  int indeg[8] = {0}, done[8] = {0}, nd = 0;
+  int indeg[ORC_MAX_K] = {0}, done[ORC_MAX_K] = {0}, nd = 0;
   for (int a = 0; a < K; ++a)
     for (int b = 0; b < K; ++b) indeg[b] += occ[a][b];
   for (int it = 0; it < K; ++it)
@@ -1104,7 +1105,7 @@ static int mesh_subset(const orc_scene* sc, int mesh, int nsub, const int32_t* s
 }
 
 static int remaining_meshes(const orc_scene* sc, int j, const int32_t* pm, int32_t* out) {
-  int32_t left[8];
+  int32_t left[ORC_MAX_K];
   int nl = sc->K;
   memcpy(left, sc->obj_mesh, sizeof(int32_t) * sc->K);
   for (int k = 0; k < j; ++k)
@@ -1129,7 +1130,7 @@ typedef struct {
   int nsub;
   const int32_t* sub;
   int64_t best_cost;
-  int32_t best_key[16];
+  int32_t best_key[2 * ORC_MAX_K];
   int have;
   int64_t n_eval, n_exp, n_goal;
   int rc;
@@ -1137,7 +1138,7 @@ typedef struct {
 
 static void exh_rec(exh_t* E, int j, int32_t* pm, int32_t* pp, int64_t g) {
   const orc_scene* sc = E->sc;
-  int32_t ids[8];
+  int32_t ids[ORC_MAX_K];
   int nd = remaining_meshes(sc, j, pm, ids);
   int cap = nd * E->nsub;
   int32_t* cm = (int32_t*)malloc(sizeof(int32_t) * 4 * (size_t)(cap + 1));
@@ -1161,7 +1162,7 @@ static void exh_rec(exh_t* E, int j, int32_t* pm, int32_t* pp, int64_t g) {
     pp[j] = cp[i];
     int64_t g2 = g + cost[i];
     if (j + 1 == sc->K) {
-      int32_t key[16];
+      int32_t key[2 * ORC_MAX_K];
       for (int k = 0; k < sc->K; ++k) { key[2 * k] = pm[k]; key[2 * k + 1] = pp[k]; }
       canon(sc->K, key);
       E->n_goal++;
@@ -1197,7 +1198,7 @@ int orc_search_exhaustive(const orc_scene* sc, int32_t n_sub, const int32_t* pos
   E.sc = sc;
   E.nsub = n_sub;
   E.sub = own ? own : pose_sub;
-  int32_t pm[8], pp[8];
+  int32_t pm[ORC_MAX_K], pp[ORC_MAX_K];
   exh_rec(&E, 0, pm, pp, 0);
   free(own);
   if (E.rc) return E.rc;
@@ -1218,7 +1219,7 @@ int orc_search_exhaustive(const orc_scene* sc, int32_t n_sub, const int32_t* pos
 typedef struct {
   int64_t g;
   int32_t j;
-  int32_t key[16]; /* canonical (mesh, pose) pairs of the placed objects */
+  int32_t key[2 * ORC_MAX_K]; /* canonical (mesh, pose) pairs of the placed objects */
 } node_t;
 
 typedef struct {
@@ -1341,7 +1342,7 @@ int orc_search_ucs(const orc_scene* sc, int32_t n_sub, const int32_t* pose_sub,
     closed[id] = 1;
     if (cur.j == sc->K) { found = id; break; }
     n_exp++;
-    int32_t pm[8], pp[8], ids[8];
+    int32_t pm[ORC_MAX_K], pp[ORC_MAX_K], ids[ORC_MAX_K];
     for (int k = 0; k < cur.j; ++k) { pm[k] = cur.key[2 * k]; pp[k] = cur.key[2 * k + 1]; }
     int nd = remaining_meshes(sc, cur.j, pm, ids);
     int cap = nd * n_sub;
@@ -1414,7 +1415,7 @@ typedef struct {
   const int32_t* lists; /* per object k: its poses at lists + k * nsub, count cnt[k] */
   const int32_t* cnt;
   int64_t best;
-  int32_t key[16];
+  int32_t key[2 * ORC_MAX_K];
   int have;
   int64_t nvalid;
   int rc;
@@ -1427,7 +1428,7 @@ static void* bf_worker(void* arg) {
   int64_t total = 1;
   for (int k = 0; k < K; ++k) total *= B->cnt[k];
   for (int64_t idx = B->tid; idx < total; idx += B->nth) {
-    int32_t m[8], p[8];
+    int32_t m[ORC_MAX_K], p[ORC_MAX_K];
     int64_t r = idx;
     for (int k = 0; k < K; ++k) {
       m[k] = sc->obj_mesh[k];
@@ -1439,7 +1440,7 @@ static void* bf_worker(void* arg) {
     if (rc) { B->rc = rc; return NULL; }
     if (!out[0]) continue;
     B->nvalid++;
-    int32_t key[16];
+    int32_t key[2 * ORC_MAX_K];
     for (int k = 0; k < K; ++k) { key[2 * k] = m[k]; key[2 * k + 1] = p[k]; }
     canon(K, key);
     if (!B->have || out[1] < B->best || (out[1] == B->best && cmp_key(K, key, B->key) < 0)) {
@@ -1459,7 +1460,7 @@ int orc_bruteforce_joint(const orc_scene* sc, int32_t n_sub, const int32_t* pose
   for (int i = 0; i < n_sub; ++i)
     if (sub[i] < 0 || sub[i] >= sc->P) { free(own); return -1; }
   int32_t* lists = (int32_t*)malloc(sizeof(int32_t) * (size_t)sc->K * (size_t)(n_sub + 1));
-  int32_t cnt[8];
+  int32_t cnt[ORC_MAX_K];
   for (int k = 0; k < sc->K; ++k)
     cnt[k] = mesh_subset(sc, sc->obj_mesh[k], n_sub, sub, lists + (size_t)k * n_sub);
   int nth = sc->nthreads > 256 ? 256 : sc->nthreads;
@@ -1479,7 +1480,7 @@ int orc_bruteforce_joint(const orc_scene* sc, int32_t n_sub, const int32_t* pose
   free(own);
   int have = 0;
   int64_t best = 0, nvalid = 0;
-  int32_t key[16];
+  int32_t key[2 * ORC_MAX_K];
   for (int t = 0; t < nth; ++t) {
     if (B[t].rc) return B[t].rc;
     nvalid += B[t].nvalid;

@@ -17,6 +17,7 @@
 #include "perch_ctx.h"
 
 using namespace perch;
+static_assert(kMaxObjects == PERCH_MAX_OBJECTS, "device and ABI object limits differ");
 
 namespace perch {
 
@@ -112,7 +113,7 @@ perch_status materialise_into(perch_ctx* c, const perch_object* parent, int j, b
   if (goal) {
     launch_fill_u32(ubits, 0u, (npx + 31) / 32, st);
     launch_fill_i32(ucount, 0, 1, st);
-    int mp[16];
+    int mp[2 * kMaxObjects];
     for (int k = 0; k < j; ++k) {
       mp[2 * k] = parent[k].mesh_id;
       mp[2 * k + 1] = parent[k].pose_idx;
@@ -348,7 +349,8 @@ perch_status perch_get_poses(perch_ctx* c, int32_t first, int32_t n, float* pose
 }
 
 perch_status perch_set_objects(perch_ctx* c, const int32_t* mesh_ids, int32_t K) {
-  if (!c || (!mesh_ids && K > 0) || K < 1 || K > 8) return fail(PERCH_E_ARG, "bad object list");
+  if (!c || (!mesh_ids && K > 0) || K < 1 || K > PERCH_MAX_OBJECTS)
+    return fail(PERCH_E_ARG, "bad object list");
   c->objects.assign(mesh_ids, mesh_ids + K);
   c->parent_j = -1;
   return PERCH_OK;
@@ -431,7 +433,7 @@ static perch_status eval_children_impl(perch_ctx* c, const perch_object* cands_d
     if (c->vbits_for != c->parent_serial) {
       const size_t npx = (size_t)c->cam.W * c->cam.H;
       HIP_TRY(c->par_vbits.ensure(((npx + 31) / 32) * sizeof(unsigned)));
-      int mp[16];
+      int mp[2 * kMaxObjects];
       const int j = c->parent_j;
       for (int k = 0; k < j; ++k) {
         mp[2 * k] = c->parent_objs[k].mesh_id;

@@ -118,7 +118,7 @@ perch_status perch_batch_set_parents(perch_batch* b, const perch_parent* parents
     if (p.j < 0 || p.j >= K) return fail(PERCH_E_ARG, "parent %d: j=%d with K=%d", k, p.j, K);
     for (int o = 0; o < p.j; ++o)
       if (p.objs[o].mesh_id < 0 || p.objs[o].mesh_id >= (int)c->meshes.size() ||
-          p.objs[o].pose_idx < 0 || p.objs[o].pose_idx >= c->P)
+          p.objs[o].pose_idx < 0 || p.objs[o].pose_idx >= c->n_poses())
         return fail(PERCH_E_ARG, "parent %d: object %d out of range", k, o);
     if (c->meshes_dirty) return fail(PERCH_E_STATE, "context %d meshes changed", p.ctx);
   }

@@ -7,6 +7,8 @@
 namespace perch {
 
 // Sensor in float32 (the vertex stage works in float32; see vstage()).
+constexpr int kMaxObjects = 16;  // objects of a scene / a state (PERCH_MAX_OBJECTS)
+
 struct Cam {
   int W, H;
   float fx, fy, cx, cy;
@@ -140,7 +142,7 @@ hipError_t launch_icp(const SceneDev& S, const Parent& par, const int2* cands, i
                       size_t lds, hipStream_t s);
 
 // ---- learned search: device-side ranking of children (perch_select.hip) ----
-constexpr int kMaxMeshes = 8;  // distinct meshes of one scene's object multiset
+constexpr int kMaxMeshes = 8;  // distinct meshes of one scene's object multiset (learned)
 struct MeshMask {
   int allow[kMaxMeshes];  // 0: the mesh is placed already, its children rank last
 };

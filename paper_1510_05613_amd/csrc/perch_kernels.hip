@@ -583,7 +583,7 @@ __global__ void k_render_object(Cam cam, Meshes M, const float4* poses, int mesh
 // ---------------------------------------------------------------------------
 
 struct ParentObjs {
-  int2 o[8];
+  int2 o[kMaxObjects];
 };
 
 __global__ void k_parent_u(Cam cam, Meshes M, const float4* poses, const float* obs,
@@ -1498,7 +1498,7 @@ void launch_parent_u(const Cam& cam, const Meshes& M, const float4* poses, const
                      const int* par_mesh_pose, int j, const unsigned* depth_bits, unsigned* ubits,
                      int* ucount, const EvalParams& ep, hipStream_t s) {
   ParentObjs po;
-  for (int a = 0; a < 8; ++a)
+  for (int a = 0; a < kMaxObjects; ++a)
     po.o[a] = a < j ? make_int2(par_mesh_pose[2 * a], par_mesh_pose[2 * a + 1]) : make_int2(0, 0);
   const int n = cam.W * cam.H;
   hipLaunchKernelGGL(k_parent_u, dim3((n + 255) / 256), dim3(256), 0, s, cam, M, poses, obs, po,
@@ -1508,7 +1508,7 @@ void launch_parent_u(const Cam& cam, const Meshes& M, const float4* poses, const
 void launch_parent_v(const Cam& cam, const Meshes& M, const float4* poses, const float* obs,
                      const int* par_mesh_pose, int j, unsigned* vbits, hipStream_t s) {
   ParentObjs po;
-  for (int a = 0; a < 8; ++a)
+  for (int a = 0; a < kMaxObjects; ++a)
     po.o[a] = a < j ? make_int2(par_mesh_pose[2 * a], par_mesh_pose[2 * a + 1]) : make_int2(0, 0);
   const int n = cam.W * cam.H;
   launch_fill_u32(vbits, 0u, (size_t)(n + 31) / 32, s);

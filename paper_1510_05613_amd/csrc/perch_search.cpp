@@ -50,8 +50,8 @@ struct Node {
   int32_t j;
   int32_t parent;  // node index, -1 for the root
   int32_t edge;    // cost of the edge from the parent
-  perch_object objs[8];  // insertion order
-  int64_t key[8];        // canonical: sorted (mesh << 32 | pose)
+  perch_object objs[PERCH_MAX_OBJECTS];  // insertion order
+  int64_t key[PERCH_MAX_OBJECTS];        // canonical: sorted (mesh << 32 | pose)
   int32_t lazy;          // learned search: a block of unevaluated children of `parent`
   int64_t hov;           // overlap heuristic: observed points outside V_j (MHA search)
   double hpr;            // pose-prior heuristic: sum of distances to the estimates
@@ -787,7 +787,7 @@ class Searcher {
   int64_t lower_bound_ = 0;
   bool have_ = false;
   Node best_{};
-  int32_t best_edges_[8] = {0};
+  int32_t best_edges_[PERCH_MAX_OBJECTS] = {0};
   std::vector<int32_t> path_edges_;
   double t_best_ = -1.0;
   int64_t n_eval_best_ = -1;

@@ -37,6 +37,7 @@ EXPORTS = ("perch_create", "perch_destroy", "perch_set_observation", "perch_add_
 
 SEARCH_EXHAUSTIVE, SEARCH_UCS, SEARCH_FOCAL, SEARCH_LEARNED, SEARCH_MHA = 0, 1, 2, 3, 4
 SEARCH_LEARNED_MHA = 5
+MAX_OBJECTS = 16  # PERCH_MAX_OBJECTS
 
 
 class PerchError(RuntimeError):
@@ -54,7 +55,7 @@ class PerchObject(C.Structure):
 
 
 class PerchParent(C.Structure):
-    _fields_ = [("ctx", C.c_int32), ("j", C.c_int32), ("objs", PerchObject * 8)]
+    _fields_ = [("ctx", C.c_int32), ("j", C.c_int32), ("objs", PerchObject * MAX_OBJECTS)]
 
 
 class _Tuning(C.Structure):
@@ -77,8 +78,9 @@ class _SearchOpts(C.Structure):
 
 
 class _Result(C.Structure):
-    _fields_ = [("objs", PerchObject * 8), ("K", C.c_int32), ("found", C.c_int32),
-                ("cost", C.c_int64), ("edge_cost", C.c_int32 * 8), ("n_expanded", C.c_int64),
+    _fields_ = [("objs", PerchObject * MAX_OBJECTS), ("K", C.c_int32), ("found", C.c_int32),
+                ("cost", C.c_int64), ("edge_cost", C.c_int32 * MAX_OBJECTS),
+                ("n_expanded", C.c_int64),
                 ("n_evaluated", C.c_int64), ("n_invalid", C.c_int64), ("t_total_s", C.c_double),
                 ("t_best_s", C.c_double), ("lower_bound", C.c_int64),
                 ("n_evaluated_best", C.c_int64), ("n_merged", C.c_int64)]

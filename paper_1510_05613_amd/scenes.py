@@ -630,3 +630,41 @@ def offgrid_truth(scene: Scene, render: RenderFn, shift: float = 0.4, seed: int 
     noisy = gt[hit] + rng.normal(0.0, 0.002, size=int(hit.sum()))
     depth[hit] = (np.round(noisy * 1000.0) / 1000.0).astype(np.float32)
     return true, depth
+
+
+def chessboard_scene(render: RenderFn, seed: int = 0) -> Scene:
+    """A chessboard-like stand-in for the paper's twelve-piece run (Sec. V-C): an
+    8 x 8 board of 4 cm squares with the pose grid on the square centres (8 yaws),
+    twelve pieces of three kinds — eight pawns (cylinders, rotationally symmetric),
+    two rooks (square towers) and two kings (tall cylinders, symmetric) — the
+    pieces on the first rank, the pawns on the second, seen from in front of the
+    first rank (the pieces hide parts of the pawns).  640 x 480, delta = 7.5 mm as
+    in that run; the observation uses the generator's noise recipe.  The seed
+    shuffles the files of the first-rank pieces and the pawns' yaws are 0."""
+    rng = np.random.default_rng(20_000 + seed)
+    lib = Library([make_cylinder((0.030, 0.030, 0.045), 48, 400),   # pawn
+                   make_box((0.032, 0.032, 0.060), 300),             # rook
+                   make_cylinder((0.036, 0.036, 0.090), 48, 600)])   # king
+    cfg = dict(W=640, H=480, f=525.0, table=(0.32, 0.32), delta=0.0075, cam_height=0.45)
+    sensor = make_sensor(cfg)
+    grid = Grid(-0.16, -0.16, 0.04, 8, 8, 8)
+    poses = grid.table()
+    files = rng.permutation(8)[:4]  # first-rank files of rook, rook, king, king
+    mesh_ids = [0] * 8 + [1, 1, 2, 2]
+    gt = [grid.index(ix, 1, 0) for ix in range(8)]
+    gt += [grid.index(int(f), 0, 0) for f in files]
+    mesh_ids = np.array(mesh_ids, np.int32)
+    gt = np.array(gt, np.int32)
+    D = render(sensor, lib, mesh_ids, gt, poses)
+    if not _in_view(D):
+        raise RuntimeError("chessboard pieces out of view")
+    order = _front_to_back_order(_occlusion_matrix(D))
+    if order is None:
+        raise RuntimeError("chessboard occlusion has a cycle")
+    depth_gt = np.min(D, axis=0)
+    depth = np.zeros(depth_gt.shape, np.float32)
+    hit = np.isfinite(depth_gt)
+    noisy = depth_gt[hit] + rng.normal(0.0, 0.002, size=int(hit.sum()))
+    depth[hit] = (np.round(noisy * 1000.0) / 1000.0).astype(np.float32)
+    return Scene(0, 20_000 + seed, sensor, lib, grid, poses, mesh_ids, gt, order, depth,
+                 cfg["table"])

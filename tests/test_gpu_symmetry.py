@@ -73,3 +73,49 @@ def test_replicated_instances_match_oracle(idx):
     ctx = perch.context_from_scene(sc)
     ex_g, uc_g = _compare(sc, o, ctx, sub)
     assert uc_g["n_evaluated"] <= ex_g["n_evaluated"]
+
+
+@pytest.fixture(scope="module")
+def board():
+    return scenes.chessboard_scene(render_fn, 0)
+
+
+def test_twelve_object_parent_matches_oracle(board):
+    """Successors under an 11-object parent (more objects than a state held before
+    the limit was raised): every pose of the last piece's mesh, against the oracle."""
+    from tests.test_gpu_parity import compare
+
+    sc = board
+    order = [int(k) for k in sc.gt_order]
+    parent = [(int(sc.obj_mesh[k]), int(sc.gt_pose[k])) for k in order[:-1]]
+    last = order[-1]
+    m = int(sc.obj_mesh[last])
+    cands = np.stack([np.full(sc.grid.P, m, np.int32), np.arange(sc.grid.P, dtype=np.int32)], 1)
+    ctx = perch.context_from_scene(sc)
+    st, cost, comps = ctx.evaluate(parent, torch.as_tensor(cands).cuda())
+    torch.cuda.synchronize()
+    o = Oracle.from_scene(sc, nthreads=NTH)
+    ref = o.eval([p[0] for p in parent], [p[1] for p in parent], cands[:, 0], cands[:, 1])
+    r = compare((st.cpu().numpy(), cost.cpu().numpy(), comps.cpu().numpy()), ref, "12 objects")
+    assert r["valid"] > 0
+    # the true pose completes the scene at its one-shot cost
+    k = int(np.nonzero(cands[:, 1] == sc.gt_pose[last])[0][0])
+    assert int(st[k]) == 1
+
+
+def test_chessboard_search_within_w(board):
+    """The twelve-piece stand-in with the paper's w = 15: Focal-MHA* returns a goal
+    within w of the lower bound it proves, with symmetric pawns and kings placed at
+    yaw 0 only and the replicated pieces searched as sets."""
+    sc = board
+    ctx = perch.context_from_scene(sc)
+    ctx.set_symmetric(0)
+    ctx.set_symmetric(2)
+    r = ctx.search(perch.SEARCH_MHA, w=15.0, budget_s=60.0)
+    assert r["found"] and not r["budget_exhausted"]
+    assert r["cost"] <= 15.0 * r["lower_bound"] + 1e-9 or r["cost"] == 0
+    assert sum(r["edge_cost"]) == r["cost"] and len(r["objs"]) == 12
+    assert sorted(m for m, _ in r["objs"]) == sorted(int(v) for v in sc.obj_mesh)
+    for m, p in r["objs"]:
+        if m in (0, 2):
+            assert sc.grid.unindex(p)[2] == 0
