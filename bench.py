@@ -41,22 +41,41 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()
 
 
+def _committed_counters():
+    """Key/value lines of the committed counter summary, or {} when it is missing or
+    was taken on a different kernel source."""
+    try:
+        with open(COUNTERS) as f:
+            kv = dict(line.split(":", 1) for line in f
+                      if line.startswith(("source_sha256:", "traffic_bytes_per_launch:",
+                                          "valu_insts_per_launch:")))
+    except OSError:
+        return {}
+    if kv.get("source_sha256", "").strip() != kernel_source_hash():
+        return {}
+    return kv
+
+
 def measured_traffic():
     """HBM bytes per k_eval launch from the committed counter summary (FETCH_SIZE and
     WRITE_SIZE scaled by a plain copy's reading), or None when the summary is missing
     or was taken on a different kernel source."""
     try:
-        with open(COUNTERS) as f:
-            kv = dict(line.split(":", 1) for line in f if line.startswith(("source_sha256:",
-                                                                            "traffic_bytes_per_launch:")))
-    except OSError:
-        return None
-    if kv.get("source_sha256", "").strip() != kernel_source_hash():
-        return None
-    try:
-        return float(kv["traffic_bytes_per_launch"])
+        return float(_committed_counters()["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def valu_issue_frac(launch_s: float):
+    """Share of the CUs' vector-ALU issue slots a k_eval launch of launch_s seconds
+    uses: the committed SQ_INSTS_VALU count per launch (wave instructions) x 4 cycles
+    (a wave64 instruction on a 16-lane SIMD) over 1,024 SIMDs x 2.4 GHz x launch_s; a
+    lower bound (transcendentals take 4 times longer).  None when stale."""
+    try:
+        n = float(_committed_counters()["valu_insts_per_launch"])
+    except (KeyError, ValueError):
+        return None
+    return n * 4.0 / (1024 * 2.4e9 * launch_s)
 
 
 def parse_args(argv=None):
@@ -567,6 +586,7 @@ def main(argv=None):
     default_run = (args.config == 2 and args.scene == 0 and not (args.threads or args.tile or
                                                                  args.cell or args.radius >= 0))
     traffic = measured_traffic() if default_run else None
+    valu = valu_issue_frac(launch_s) if default_run else None
     out = {
         "metric": METRIC, "value": round(evals / wall, 1), "unit": "evals/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 3),
@@ -584,7 +604,8 @@ def main(argv=None):
                      "traffic": None if traffic is None else round(traffic),
                      "kernel": "k_eval", "launches_per_step": launches,
                      "launch_ms": round(launch_s * 1e3, 4),
-                     "algorithmic_bytes_per_launch": round(bytes_per_launch)},
+                     "algorithmic_bytes_per_launch": round(bytes_per_launch),
+                     "valu_issue_frac": None if valu is None else round(valu, 3)},
     }
     if args.icp_iters > 0 and args.config == 2:
         out["icp"] = icp_leg(ctx, sc, dev[0], args.icp_iters)
