@@ -204,6 +204,7 @@ void perch_destroy(perch_ctx* c) {
                     &c->par_ubits, &c->par_ucount, &c->par_vbits, &c->s_cands, &c->s_out,
                     &c->s_adj, &c->icp_pn, &c->cnn_desc})
     b->release();
+  for (DevBuf& b : c->learned_bufs) b.release();
   c->s_hcands.release();
   c->s_hout.release();
   c->s_hposes.release();

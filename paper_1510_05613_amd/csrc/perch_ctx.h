@@ -180,6 +180,8 @@ struct perch_ctx {
   DevBuf cnn_desc;
   // search scratch: candidate list and outputs of one expansion
   DevBuf s_cands, s_out, s_adj;
+  // learned search: crop descriptors, pair table, ranking buffers (kept between calls)
+  DevBuf learned_bufs[10];
   PinnedBuf s_hcands, s_hout, s_hposes;
   // tuning (tile_px 0 = sized automatically, see auto_tile_px)
   int threads = 512;

@@ -92,21 +92,6 @@ struct Child {
   float x, y, c, s;                // the child's pose values (grid or ICP-adjusted)
 };
 
-// Device buffers of one search call, released when it returns.
-struct Scratch {
-  std::vector<DevBuf*> bufs;
-  DevBuf& get() {
-    bufs.push_back(new DevBuf());
-    return *bufs.back();
-  }
-  ~Scratch() {
-    for (DevBuf* b : bufs) {
-      b->release();
-      delete b;
-    }
-  }
-};
-
 class Searcher {
  public:
   Searcher(perch_ctx* c, const perch_search_opts* o) : c_(c), o_(*o) {}
@@ -550,10 +535,11 @@ class Searcher {
         const float* pz = &c_->h_poses[4 * (size_t)poses_[b]];
         hp[(size_t)a * P + b] = perch_cnn_pair{cell_of[b], dist[a], pz[2], pz[3]};
       }
-    Scratch sc;
-    DevBuf &d_desc = sc.get(), &d_pairs = sc.get(), &d_dist = sc.get(), &d_pose = sc.get();
-    DevBuf &d_crops = sc.get(), &d_pred = sc.get(), &d_keys = sc.get(), &d_idx = sc.get();
-    DevBuf &d_idx2 = sc.get(), &d_temp = sc.get();
+    // device buffers kept by the context between searches (grown on demand)
+    DevBuf* lb = c_->learned_bufs;
+    DevBuf &d_desc = lb[0], &d_pairs = lb[1], &d_dist = lb[2], &d_pose = lb[3];
+    DevBuf &d_crops = lb[4], &d_pred = lb[5], &d_keys = lb[6], &d_idx = lb[7];
+    DevBuf &d_idx2 = lb[8], &d_temp = lb[9];
     const size_t temp_bytes = select_temp_bytes((int)maxp);
     HIP_TRY(d_desc.ensure(sizeof(cnn::CropDesc) * n_cells));
     HIP_TRY(d_pairs.ensure(sizeof(perch_cnn_pair) * maxp));
@@ -565,12 +551,15 @@ class Searcher {
     HIP_TRY(d_idx.ensure(sizeof(int) * maxp));
     HIP_TRY(d_idx2.ensure(sizeof(int) * maxp));
     HIP_TRY(d_temp.ensure(temp_bytes));
-    HIP_TRY(hipMemcpy(d_desc.p, hdesc.data(), sizeof(cnn::CropDesc) * n_cells,
-                      hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(d_pairs.p, hp.data(), sizeof(perch_cnn_pair) * maxp, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(d_dist.p, dist.data(), sizeof(int) * nd, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(d_pose.p, poses_.data(), sizeof(int) * P, hipMemcpyHostToDevice));
     hipStream_t st0 = c_->stream;
+    // stream-ordered uploads; the host arrays outlive the search's first synchronisation
+    HIP_TRY(hipMemcpyAsync(d_desc.p, hdesc.data(), sizeof(cnn::CropDesc) * n_cells,
+                           hipMemcpyHostToDevice, st0));
+    HIP_TRY(hipMemcpyAsync(d_pairs.p, hp.data(), sizeof(perch_cnn_pair) * maxp,
+                           hipMemcpyHostToDevice, st0));
+    HIP_TRY(hipMemcpyAsync(d_dist.p, dist.data(), sizeof(int) * nd, hipMemcpyHostToDevice, st0));
+    HIP_TRY(hipMemcpyAsync(d_pose.p, poses_.data(), sizeof(int) * P, hipMemcpyHostToDevice,
+                           st0));
     launch_iota(d_idx.as<int>(), (int)maxp, st0);
 
     // Children of n: materialise n, crop every cell, predict every (mesh, pose),
