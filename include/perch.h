@@ -176,8 +176,8 @@ perch_status perch_overlap_gain(perch_ctx* ctx, const perch_object* cands_dev, i
  * perch_eval_children.  status_dev: 1 aligned, 0 the candidate occludes the parent
  * (Eq. 3; grid pose kept), -2 vertex stage failed, -3 footprint larger than the
  * ICP tile, -4 candidate out of range; n_match_dev: pairs of the last round.
- * Candidates, outputs: device arrays of n.  Meshes of at most 5,120 vertices.
- * PERCH_E_ARG when the arena lacks room for n.  Asynchronous. */
+ * Candidates, outputs: device arrays of n.  PERCH_E_ARG when the arena lacks room
+ * for n.  Asynchronous. */
 perch_status perch_icp_children(perch_ctx* ctx, const perch_object* cands_dev, int32_t n,
                                 int32_t iters, float radius, perch_object* adjusted_dev,
                                 int32_t* n_match_dev, int32_t* status_dev);

@@ -473,8 +473,6 @@ perch_status perch_icp_children(perch_ctx* c, const perch_object* cands_dev, int
     return fail(PERCH_E_ARG, "bad ICP iterations or radius");
   if (c->parent_j < 0) return fail(PERCH_E_STATE, "perch_set_parent not called");
   if (c->meshes_dirty) return fail(PERCH_E_STATE, "meshes changed since perch_set_parent");
-  if (c->max_nv > kInt2CacheMaxVerts)
-    return fail(PERCH_E_UNSUPPORTED, "ICP needs meshes of at most %d vertices", kInt2CacheMaxVerts);
   const int tile = icp_tile_px(c->max_nv);
   if (tile <= 0) return fail(PERCH_E_UNSUPPORTED, "no LDS left for the ICP tile");
   if ((int64_t)c->arena_used + n > c->arena_cap)
@@ -507,8 +505,8 @@ perch_status perch_icp_children(perch_ctx* c, const perch_object* cands_dev, int
   ia.arena = c->poses.as<float4>() + ia.base;
   const size_t lds = icp_fixed_lds(c->max_nv) + (size_t)tile * sizeof(unsigned);
   HIP_TRY(launch_icp(S, par, reinterpret_cast<const int2*>(cands_dev), n, ia,
-                     reinterpret_cast<int2*>(adjusted_dev), n_match_dev, status_dev, lds,
-                     c->stream));
+                     reinterpret_cast<int2*>(adjusted_dev), n_match_dev, status_dev,
+                     icp_vertex_cache(c->max_nv), lds, c->stream));
   c->arena_used += n;
   return PERCH_OK;
 }

@@ -106,11 +106,14 @@ inline size_t eval_lds_bytes(int max_nv, int tile_px, int threads) {
          (size_t)(threads / 64) * 128 * sizeof(unsigned);
 }
 
-// Dynamic LDS and z-tile of the ICP kernel: one workgroup per CU, int2 vertex
-// cache, the largest tile (a multiple of 256 pixels) left over; footprints larger
-// than it are not aligned.
+// Dynamic LDS and z-tile of the ICP kernel: one workgroup per CU, an int2 vertex
+// cache for meshes of at most kInt2CacheMaxVerts vertices (larger ones recompute
+// their snapped vertices), the largest tile (a multiple of 256 pixels) left over;
+// footprints larger than it are not aligned.
+inline bool icp_vertex_cache(int max_nv) { return max_nv <= kInt2CacheMaxVerts; }
 inline size_t icp_fixed_lds(int max_nv) {
-  return (size_t)max_nv * 2 * sizeof(int) + (size_t)(perch::kIcpThreads / 64) * 128 * sizeof(unsigned);
+  return (icp_vertex_cache(max_nv) ? (size_t)max_nv * 2 * sizeof(int) : 0) +
+         (size_t)(perch::kIcpThreads / 64) * 128 * sizeof(unsigned);
 }
 inline int icp_tile_px(int max_nv) {
   const long budget = 160L * 1024 - 4096 - (long)icp_fixed_lds(max_nv);

@@ -136,10 +136,11 @@ struct IcpArgs {
 // pn (2 float4 per pixel) from the observation for association radius `radius`
 void launch_obs_normals(const Cam& cam, const float* obs, float radius, float4* pn,
                         hipStream_t s);
-// kIcpThreads threads per candidate; lds = vertex cache (int2) + tile + rings
+// kIcpThreads threads per candidate; lds = vertex cache (int2, when vertex_cache)
+// + tile + rings
 hipError_t launch_icp(const SceneDev& S, const Parent& par, const int2* cands, int n,
                       const IcpArgs& ia, int2* out_obj, int* out_match, int* out_status,
-                      size_t lds, hipStream_t s);
+                      bool vertex_cache, size_t lds, hipStream_t s);
 
 // ---- learned search: device-side ranking of children (perch_select.hip) ----
 constexpr int kMaxMeshes = 8;  // distinct meshes of one scene's object multiset (learned)

@@ -1179,8 +1179,9 @@ constexpr int kIcpSums = 12;
 // has a normal and lies within `radius`, and take one point-to-plane step (a
 // rotation about the vertical axis through the matched points' centroid and a
 // translation, from the damped 3 x 3 normal equations).  Writes the adjusted pose
-// to arena[s] and (mesh, base + s) to out_obj[s].
-template <int NT>
+// to arena[s] and (mesh, base + s) to out_obj[s].  CACHE: snapped vertices kept in
+// LDS (meshes of at most 5,120 vertices), else recomputed where they are needed.
+template <int NT, bool CACHE>
 __global__ void __launch_bounds__(NT)
     k_icp(SceneDev S, Parent par, const int2* __restrict__ cands, int n, IcpArgs ia,
           int2* __restrict__ out_obj, int* __restrict__ out_match, int* __restrict__ out_status) {
@@ -1210,7 +1211,8 @@ __global__ void __launch_bounds__(NT)
   const float4 pz = S.poses[cd.y];
   const int4 rg = M.range[cd.x];
   int2* suv = reinterpret_cast<int2*>(smem);
-  unsigned* tile = reinterpret_cast<unsigned*>(smem + (size_t)ep.max_nv * sizeof(int2));
+  unsigned* tile =
+      reinterpret_cast<unsigned*>(smem + (CACHE ? (size_t)ep.max_nv * sizeof(int2) : 0));
   unsigned* ring = tile + ep.tile_px + (tid >> 6) * 128;
   if (tid < 4) s_bb[tid] = tid < 2 ? INT_MAX : INT_MIN;
   if (tid < 3) s_flag[tid] = 0;
@@ -1228,7 +1230,7 @@ __global__ void __launch_bounds__(NT)
       vcam(cam, pz, M.verts[rg.x + v], X, Y, Z);
       int U, V;
       bad |= !vsnap(cam, X, Y, Z, U, V);
-      suv[v] = make_int2(U, V);
+      if (CACHE) suv[v] = make_int2(U, V);
       xmn = min(xmn, U);
       ymn = min(ymn, V);
       xmx = max(xmx, U);
@@ -1248,6 +1250,14 @@ __global__ void __launch_bounds__(NT)
     }
   }
   __syncthreads();
+  auto vert_uv = [&](int idx) -> int2 {
+    if (CACHE) return suv[idx];
+    float X, Y, Z;
+    vcam(cam, pz, M.verts[rg.x + idx], X, Y, Z);
+    int U, V;
+    vsnap(cam, X, Y, Z, U, V);
+    return make_int2(U, V);
+  };
   auto finish = [&](int status, int nm, float4 pose) {
     if (tid == 0) {
       out_status[s] = status;
@@ -1281,7 +1291,7 @@ __global__ void __launch_bounds__(NT)
       const int4 tr = M.tris[rg.z + t];
       const float4 v0 = M.verts[rg.x + tr.x], v1 = M.verts[rg.x + tr.y];
       const float4 v2 = M.verts[rg.x + tr.z];
-      const int2 a = suv[tr.x], b = suv[tr.y], c = suv[tr.z];
+      const int2 a = vert_uv(tr.x), b = vert_uv(tr.y), c = vert_uv(tr.z);
       float X0, Y0, Z0, X1, Y1, Z1, X2, Y2, Z2;
       map_vertex(pm, v0, X0, Y0, Z0);
       map_vertex(pm, v1, X1, Y1, Z1);
@@ -1297,7 +1307,7 @@ __global__ void __launch_bounds__(NT)
       bool keep = false;
       if (t < rg.w) {
         const int4 tr = M.tris[rg.z + t];
-        const int2 a = suv[tr.x], b = suv[tr.y], c = suv[tr.z];
+        const int2 a = vert_uv(tr.x), b = vert_uv(tr.y), c = vert_uv(tr.z);
         keep = tri_candidate(a.x, a.y, b.x, b.y, c.x, c.y, ca, cb, ra, rb);
       }
       const unsigned long long m = __ballot(keep);
@@ -1313,11 +1323,13 @@ __global__ void __launch_bounds__(NT)
     if ((unsigned)lane < tail - head) raster_one(ring[(head + lane) & 127u]);
   }
   __syncthreads();
+  // k / tw for k < 2^21: (k + 1/2) / tw is at least 1 / (2 tw) from an integer
+  const float inv_tw = __builtin_amdgcn_rcpf((float)tw);
   // composite: validity (Eq. 3) and the non-occluded part dR
   {
     bool occ = false;
     for (int k = tid; k < tn; k += NT) {
-      const int r = k / tw;
+      const int r = (int)(((float)k + 0.5f) * inv_tw);
       const int jj = ra + r, ii = ca + (k - r * tw);
       const unsigned key = tile[k];
       const bool cov = key != kInfBits;
@@ -1345,7 +1357,7 @@ __global__ void __launch_bounds__(NT)
     for (int k = tid; k < tn; k += NT) {
       const unsigned key = tile[k];
       if (key == kInfBits) continue;
-      const int r = k / tw;
+      const int r = (int)(((float)k + 0.5f) * inv_tw);
       const int jj = ra + r, ii = ca + (k - r * tw);
       const float3 q = backproject(cam, ii, jj, __uint_as_float(key));
       const float wx = Wi[0] * q.x + Wi[1] * q.y + Wi[2] * q.z + Wi[3];
@@ -1647,15 +1659,24 @@ void launch_obs_normals(const Cam& cam, const float* obs, float radius, float4* 
   hipLaunchKernelGGL(k_obs_normals, dim3((n + 255) / 256), dim3(256), 0, s, cam, obs, radius, pn);
 }
 
+template <bool CACHE>
+static hipError_t launch_icp_t(const SceneDev& S, const Parent& par, const int2* cands, int n,
+                               const IcpArgs& ia, int2* out_obj, int* out_match,
+                               int* out_status, size_t lds, hipStream_t s) {
+  hipError_t e = allow_lds(&k_icp<kIcpThreads, CACHE>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_icp<kIcpThreads, CACHE>), dim3(n), dim3(kIcpThreads), lds, s, S, par,
+                     cands, n, ia, out_obj, out_match, out_status);
+  return hipGetLastError();
+}
+
 hipError_t launch_icp(const SceneDev& S, const Parent& par, const int2* cands, int n,
                       const IcpArgs& ia, int2* out_obj, int* out_match, int* out_status,
-                      size_t lds, hipStream_t s) {
+                      bool vertex_cache, size_t lds, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipError_t e = allow_lds(&k_icp<kIcpThreads>, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_icp<kIcpThreads>), dim3(n), dim3(kIcpThreads), lds, s, S, par, cands, n,
-                     ia, out_obj, out_match, out_status);
-  return hipGetLastError();
+  return vertex_cache
+             ? launch_icp_t<true>(S, par, cands, n, ia, out_obj, out_match, out_status, lds, s)
+             : launch_icp_t<false>(S, par, cands, n, ia, out_obj, out_match, out_status, lds, s);
 }
 
 }  // namespace perch

@@ -68,22 +68,18 @@ def c2():
     return sc, Oracle.from_scene(sc, nthreads=8), perch.context_from_scene(sc)
 
 
-@pytest.mark.parametrize("level", [1, 2])
-def test_icp_poses_match_oracle(c2, level):
-    sc, o, ctx = c2
-    rng = np.random.default_rng(level)
-    order = [int(k) for k in sc.gt_order]
-    parent = [(int(sc.obj_mesh[k]), int(sc.gt_pose[k])) for k in order[:level - 1]]
-    cands = _near_gt_candidates(sc, rng)
+def _check_icp(sc, o, ctx, parent, cands):
+    """GPU ICP of cands under parent against the oracle's, by the module's rule."""
     ctx.set_pose_arena(4 * len(cands))
     adj, nm_g, st_g = _gpu_icp(ctx, parent, cands)
     pm = [m for m, _ in parent]
     pp = [p for _, p in parent]
     P_o, nm_o, st_o, fl_o = o.icp(pm, pp, cands[:, 0], cands[:, 1], iters=10, radius=0.02)
     a = adj.cpu().numpy()
+    P = len(sc.poses)
     assert np.array_equal(a[:, 0], cands[:, 0])
-    assert np.array_equal(a[:, 1], sc.grid.P + np.arange(len(cands)))
-    P_g = ctx.get_poses(sc.grid.P, len(cands)).astype(np.float64)
+    assert np.array_equal(a[:, 1], P + np.arange(len(cands)))
+    P_g = ctx.get_poses(P, len(cands)).astype(np.float64)
     assert np.all(st_g >= 0)
     # validity is Eq. (3) at the grid pose: the oracle's evaluation flags the
     # parent/candidate depth ties that may go either way
@@ -98,16 +94,39 @@ def test_icp_poses_match_oracle(c2, level):
     yaw = np.angle(np.exp(1j * (np.arctan2(P_g[ok, 3], P_g[ok, 2]) -
                                 np.arctan2(P_o[ok, 3], P_o[ok, 2]))))
     fixed = np.array([not _cyl(sc, m) for m in cands[ok, 0]])
-    assert np.abs(yaw[fixed]).max() < 1e-3
+    if fixed.any():
+        assert np.abs(yaw[fixed]).max() < 1e-3
     # pairs of the last round: equal up to the flagged associations
     assert np.all(np.abs(nm_g[ok] - nm_o[ok]) <= np.maximum(2, fl_o[ok]))
-    # the ones that moved did move (the candidates near GT are pulled)
+    # the ones near the truth did move
     g = sc.poses[cands[ok, 1]].astype(np.float64)
     assert np.hypot(P_g[ok, 0] - g[:, 0], P_g[ok, 1] - g[:, 1]).max() > 1e-3
     # not aligned: grid pose kept
     bad = st_g == 0
     if bad.any():
         assert np.array_equal(P_g[bad].astype(np.float32), sc.poses[cands[bad, 1]])
+
+
+@pytest.mark.parametrize("level", [1, 2])
+def test_icp_poses_match_oracle(c2, level):
+    sc, o, ctx = c2
+    rng = np.random.default_rng(level)
+    order = [int(k) for k in sc.gt_order]
+    parent = [(int(sc.obj_mesh[k]), int(sc.gt_pose[k])) for k in order[:level - 1]]
+    _check_icp(sc, o, ctx, parent, _near_gt_candidates(sc, rng))
+
+
+def test_icp_large_meshes_match_oracle():
+    """The full configuration's library (meshes of up to 20,000 triangles, too many
+    vertices for the LDS vertex cache: the kernel recomputes snapped vertices)."""
+    sc = H.c5_scene(0)
+    assert max(len(m.verts) for m in sc.library.meshes) > 5120
+    o = Oracle.from_scene(sc, nthreads=8)
+    ctx = perch.context_from_scene(sc)
+    rng = np.random.default_rng(5)
+    cands = _near_gt_candidates(sc, rng, n_rand=2)
+    keep = rng.choice(len(cands), min(len(cands), 40), replace=False)
+    _check_icp(sc, o, ctx, [], cands[np.sort(keep)])
 
 
 def test_cost_at_adjusted_pose_matches_oracle(c2):
