@@ -496,17 +496,30 @@ perch_status perch_icp_children(perch_ctx* c, const perch_object* cands_dev, int
   par.has_parent = c->parent_j > 0;
   par.goal = (c->parent_j + 1 == K);
   perch::SceneDev S = c->scene_dev();
-  S.ep.tile_px = tile;
   IcpArgs ia;
   ia.iters = iters;
   ia.radius = radius;
   ia.pn = c->icp_pn.as<float4>();
   ia.base = c->P + c->arena_used;
   ia.arena = c->poses.as<float4>() + ia.base;
-  const size_t lds = icp_fixed_lds(c->max_nv) + (size_t)tile * sizeof(unsigned);
+  ia.retry = 0;
+  const bool vc = icp_vertex_cache(c->max_nv);
+  // a first pass whose tile lets two workgroups share a CU; the footprints it cannot
+  // hold (status -3) go through a second pass with the largest tile
+  const int tile2 = icp_tile_px(c->max_nv, 2);
+  const bool two_pass = tile2 >= 4096 && tile2 < tile;
+  S.ep.tile_px = two_pass ? tile2 : tile;
   HIP_TRY(launch_icp(S, par, reinterpret_cast<const int2*>(cands_dev), n, ia,
-                     reinterpret_cast<int2*>(adjusted_dev), n_match_dev, status_dev,
-                     icp_vertex_cache(c->max_nv), lds, c->stream));
+                     reinterpret_cast<int2*>(adjusted_dev), n_match_dev, status_dev, vc,
+                     icp_fixed_lds(c->max_nv) + (size_t)S.ep.tile_px * sizeof(unsigned),
+                     c->stream));
+  if (two_pass) {
+    ia.retry = 1;
+    S.ep.tile_px = tile;
+    HIP_TRY(launch_icp(S, par, reinterpret_cast<const int2*>(cands_dev), n, ia,
+                       reinterpret_cast<int2*>(adjusted_dev), n_match_dev, status_dev, vc,
+                       icp_fixed_lds(c->max_nv) + (size_t)tile * sizeof(unsigned), c->stream));
+  }
   c->arena_used += n;
   return PERCH_OK;
 }

@@ -115,8 +115,8 @@ inline size_t icp_fixed_lds(int max_nv) {
   return (icp_vertex_cache(max_nv) ? (size_t)max_nv * 2 * sizeof(int) : 0) +
          (size_t)(perch::kIcpThreads / 64) * 128 * sizeof(unsigned);
 }
-inline int icp_tile_px(int max_nv) {
-  const long budget = 160L * 1024 - 4096 - (long)icp_fixed_lds(max_nv);
+inline int icp_tile_px(int max_nv, int per_cu = 1) {
+  const long budget = 160L * 1024 / per_cu - 4096 - (long)icp_fixed_lds(max_nv);
   return budget < 4L * 1024 ? 0 : (int)((budget / 4) & ~255L);
 }
 

@@ -132,6 +132,8 @@ struct IcpArgs {
   const float4* pn;   // per pixel: world point (w = 1 with a normal), unit normal
   float4* arena;      // adjusted poses, one per candidate
   int base;           // pose index of arena[0]
+  int retry;          // 1: only candidates whose status is -3 (footprint beyond the
+                      // previous pass's tile); the others exit at once
 };
 // pn (2 float4 per pixel) from the observation for association radius `radius`
 void launch_obs_normals(const Cam& cam, const float* obs, float radius, float4* pn,

@@ -1182,7 +1182,7 @@ constexpr int kIcpSums = 12;
 // to arena[s] and (mesh, base + s) to out_obj[s].  CACHE: snapped vertices kept in
 // LDS (meshes of at most 5,120 vertices), else recomputed where they are needed.
 template <int NT, bool CACHE>
-__global__ void __launch_bounds__(NT)
+__global__ void __launch_bounds__(NT, 4)  // at least 4 waves per SIMD: two workgroups per CU
     k_icp(SceneDev S, Parent par, const int2* __restrict__ cands, int n, IcpArgs ia,
           int2* __restrict__ out_obj, int* __restrict__ out_match, int* __restrict__ out_status) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1193,6 +1193,7 @@ __global__ void __launch_bounds__(NT)
   __shared__ int s_nm;
   const int s = blockIdx.x;
   if (s >= n) return;
+  if (ia.retry && out_status[s] != -3) return;  // settled by the pass with the smaller tile
   const Cam& cam = S.cam;
   const Meshes& M = S.M;
   const EvalParams& ep = S.ep;
