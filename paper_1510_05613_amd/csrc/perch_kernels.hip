@@ -1353,8 +1353,10 @@ __global__ void __launch_bounds__(NT, 4)  // at least 4 waves per SIMD: two work
   const float* Wi = cam.Winv;
   for (int it = 0; it < ia.iters; ++it) {
     const float cT = s_T[0], sT = s_T[1], txT = s_T[2], tyT = s_T[3];
-    double acc[kIcpSums];
-    for (int q = 0; q < kIcpSums; ++q) acc[q] = 0.0;
+    // per-lane partial sums of about a dozen points in float32; FP64 from the wave
+    // reduction on
+    float acc[kIcpSums];
+    for (int q = 0; q < kIcpSums; ++q) acc[q] = 0.0f;
     for (int k = tid; k < tn; k += NT) {
       const unsigned key = tile[k];
       if (key == kInfBits) continue;
@@ -1379,17 +1381,17 @@ __global__ void __launch_bounds__(NT, 4)  // at least 4 waves per SIMD: two work
       if (dx * dx + dy * dy + dz * dz > r2) continue;
       const float4 N = ia.pn[2 * pix + 1];
       const float lx = ax - ox, ly = ay - oy;
-      const double g = (double)N.y * lx - (double)N.x * ly;
-      const double res = (double)N.x * dx + (double)N.y * dy + (double)N.z * dz;
-      acc[0] += 1.0;
+      const float g = N.y * lx - N.x * ly;
+      const float res = N.x * dx + N.y * dy + N.z * dz;
+      acc[0] += 1.0f;
       acc[1] += lx;
       acc[2] += ly;
       acc[3] += g * g;
       acc[4] += g * N.x;
       acc[5] += g * N.y;
-      acc[6] += (double)N.x * N.x;
-      acc[7] += (double)N.x * N.y;
-      acc[8] += (double)N.y * N.y;
+      acc[6] += N.x * N.x;
+      acc[7] += N.x * N.y;
+      acc[8] += N.y * N.y;
       acc[9] += g * res;
       acc[10] += N.x * res;
       acc[11] += N.y * res;
