@@ -119,8 +119,12 @@ __global__ void __launch_bounds__(256)
   using D = KDim<CIN>;
   constexpr int HO = HIN / S, NPIX = HO * HO;
   __shared__ __align__(16) bf16_t w[kC * D::LDSROW];
-  for (int i = threadIdx.x; i < kC * D::KP; i += blockDim.x)
-    w[(i / D::KP) * D::LDSROW + i % D::KP] = Wb[i];
+  // 16-byte staging: rows of KP (a multiple of 8) elements, 16-byte aligned in HBM
+  // and in LDS (LDSROW is a multiple of 8 too)
+  constexpr int V = D::KP / 8;
+  const uint4* __restrict__ src = reinterpret_cast<const uint4*>(Wb);
+  for (int i = threadIdx.x; i < kC * V; i += blockDim.x)
+    *reinterpret_cast<uint4*>(w + (i / V) * D::LDSROW + (i % V) * 8) = src[i];
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int total = n_img * NPIX;
