@@ -296,6 +296,21 @@ perch_status perch_cnn_crops(perch_ctx* ctx, const float* xy, int32_t n, uint16_
  * Asynchronous on the network's stream. */
 perch_status perch_cnn_predict(perch_cnn* net, const uint16_t* crops_dev, int32_t n_crops,
                                const perch_cnn_pair* pairs_dev, int32_t n_pairs, float* pred_dev);
+/* The learned search's ranking step (Sec. IV-C: only the children the learned
+ * heuristic ranks best enter the inadmissible queue).  pred_dev (device, read
+ * only): n_meshes x n_poses predictions, child u * n_poses + b = mesh position u,
+ * pose position b.  Writes to out_dev (device, k entries) {mesh_ids_dev[u],
+ * pose_ids_dev[b]} of the k children with the smallest prediction, in increasing
+ * prediction, equal predictions (-0 equal to +0) in increasing child index: the
+ * first k of a stable sort.  Children of a mesh position u with allow_host[u] == 0
+ * rank as +inf.  Needs 1 <= n_meshes <= 8 and 1 <= k <= n_meshes * n_poses.  Up
+ * to 8192 children and k <= 1024 one workgroup selects them; otherwise a device
+ * radix sort runs in temporary memory the context keeps.  Synchronous on the
+ * context's stream. */
+perch_status perch_rank_children(perch_ctx* ctx, const float* pred_dev, int32_t n_poses,
+                                 int32_t n_meshes, const int32_t* allow_host, int32_t k,
+                                 const int32_t* mesh_ids_dev, const int32_t* pose_ids_dev,
+                                 perch_object* out_dev);
 /* One Adam step on the mean squared error against target_dev (device, log(1 +
  * cost)); loss_host (nullable) receives the batch loss before the step (then the
  * call is synchronous). */

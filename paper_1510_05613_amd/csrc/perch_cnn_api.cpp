@@ -1,5 +1,6 @@
 // perch_cnn_api.cpp -- C ABI of the learned successor-cost network (see
 // perch_cnn.hip for the kernels and include/perch.h for the contract).
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -88,6 +89,31 @@ perch_status cnn_predict_on(perch_cnn* c, const uint16_t* crops, int n_crops, co
 }
 
 }  // namespace perch
+
+perch_status rank_children(perch_ctx* c, const float* pred, int n_poses, int n_meshes,
+                           const MeshMask& mask, int k, const int* mesh_ids, const int* pose_ids,
+                           int2* out, hipStream_t st) {
+  if (k < 1 || (int64_t)k > (int64_t)n_poses * n_meshes || n_meshes > kMaxMeshes)
+    return fail(PERCH_E_ARG, "ranking: k = %d of %d x %d children", k, n_meshes, n_poses);
+  if (launch_select_topk(pred, n_poses, n_meshes, mask, k, mesh_ids, pose_ids, out, st))
+    return PERCH_OK;
+  const int n = n_poses * n_meshes;
+  DevBuf &d_keys = c->learned_bufs[6], &d_idx = c->learned_bufs[7];
+  DevBuf &d_idx2 = c->learned_bufs[8], &d_temp = c->learned_bufs[9];
+  DevBuf& d_masked = c->learned_bufs[10];
+  const size_t temp_bytes = select_temp_bytes(n);
+  HIP_TRY(d_masked.ensure(sizeof(float) * n));
+  HIP_TRY(d_keys.ensure(sizeof(float) * n));
+  HIP_TRY(d_idx.ensure(sizeof(int) * n));
+  HIP_TRY(d_idx2.ensure(sizeof(int) * n));
+  HIP_TRY(d_temp.ensure(temp_bytes));
+  launch_iota(d_idx.as<int>(), n, st);
+  launch_mask_children(pred, d_masked.as<float>(), n_poses, n_meshes, mask, st);
+  HIP_TRY(sort_predictions(d_temp.p, temp_bytes, d_masked.as<float>(), d_keys.as<float>(),
+                           d_idx.as<int>(), d_idx2.as<int>(), n, st));
+  launch_child_cands(d_idx2.as<int>(), k, mesh_ids, n_poses, pose_ids, out, st);
+  return PERCH_OK;
+}
 
 extern "C" {
 
@@ -205,6 +231,27 @@ perch_status perch_cnn_crops(perch_ctx* ctx, const float* xy, int32_t n, uint16_
                ctx->cnn_desc.as<CropDesc>(), n, crops_dev, ctx->stream);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(ctx->stream));  // the host descriptors die here
+  return PERCH_OK;
+}
+
+perch_status perch_rank_children(perch_ctx* ctx, const float* pred_dev, int32_t n_poses,
+                                 int32_t n_meshes, const int32_t* allow_host, int32_t k,
+                                 const int32_t* mesh_ids_dev, const int32_t* pose_ids_dev,
+                                 perch_object* out_dev) {
+  if (!ctx || !pred_dev || !allow_host || !mesh_ids_dev || !pose_ids_dev || !out_dev)
+    return fail(PERCH_E_ARG, "null argument");
+  if (n_poses < 1 || n_meshes < 1 || n_meshes > kMaxMeshes)
+    return fail(PERCH_E_ARG, "need 1 <= n_poses and 1 <= n_meshes <= %d", kMaxMeshes);
+  if ((int64_t)n_poses * n_meshes > INT32_MAX) return fail(PERCH_E_ARG, "too many children");
+  const int n = n_poses * n_meshes;
+  if (k < 1 || k > n) return fail(PERCH_E_ARG, "need 1 <= k <= %d", n);
+  MeshMask mask{};
+  for (int u = 0; u < n_meshes; ++u) mask.allow[u] = allow_host[u] ? 1 : 0;
+  perch_status st = rank_children(ctx, pred_dev, n_poses, n_meshes, mask, k, mesh_ids_dev,
+                                  pose_ids_dev, reinterpret_cast<int2*>(out_dev), ctx->stream);
+  if (st) return st;
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
   return PERCH_OK;
 }
 

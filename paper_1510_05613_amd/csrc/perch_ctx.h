@@ -184,7 +184,7 @@ struct perch_ctx {
   // search scratch: candidate list and outputs of one expansion
   DevBuf s_cands, s_out, s_adj;
   // learned search: crop descriptors, pair table, ranking buffers (kept between calls)
-  DevBuf learned_bufs[10];
+  DevBuf learned_bufs[11];
   PinnedBuf s_hcands, s_hout, s_hposes;
   // tuning (tile_px 0 = sized automatically, see auto_tile_px)
   int threads = 512;
@@ -240,3 +240,11 @@ struct perch_ctx {
 perch_status upload_meshes(perch_ctx* c);
 perch_status materialise_into(perch_ctx* c, const perch_object* parent, int j, bool goal,
                               unsigned* depth, unsigned* ubits, int* ucount, hipStream_t st);
+// The learned search's ranking step: out[0..k) = the children of the k smallest
+// predictions (pred[u n_poses + b]; mesh positions with mask.allow[u] == 0 last),
+// ties in index order, as {mesh_ids[u], pose_ids[b]}.  One workgroup selects up to
+// kTopkMaxN children; beyond, a radix sort in the context's learned buffers.
+// Asynchronous on st.
+perch_status rank_children(perch_ctx* c, const float* pred, int n_poses, int n_meshes,
+                           const perch::MeshMask& mask, int k, const int* mesh_ids,
+                           const int* pose_ids, int2* out, hipStream_t st);

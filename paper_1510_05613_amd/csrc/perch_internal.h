@@ -149,14 +149,24 @@ constexpr int kMaxMeshes = 8;  // distinct meshes of one scene's object multiset
 struct MeshMask {
   int allow[kMaxMeshes];  // 0: the mesh is placed already, its children rank last
 };
-// pred[u n_poses + b] = +inf for every mesh position u < n_meshes with allow[u] == 0
-void launch_mask_children(float* pred, int n_poses, int n_meshes, MeshMask mask, hipStream_t s);
+// masked = pred, with +inf at u n_poses + b for every mesh position u < n_meshes
+// with allow[u] == 0
+void launch_mask_children(const float* pred, float* masked, int n_poses, int n_meshes,
+                          MeshMask mask, hipStream_t s);
 size_t select_temp_bytes(int n);
 // Stable sort of n predicted costs with their indices (ascending; NaN last).
 hipError_t sort_predictions(void* temp, size_t temp_bytes, const float* keys, float* keys_sorted,
                             const int* idx, int* idx_sorted, int n, hipStream_t s);
 void launch_iota(int* idx, int n, hipStream_t s);
 // cands[i] = (rest[id / n_poses], pose_ids[id % n_poses]) for id = idx_sorted[i], i < k
+// One-workgroup top-k for small child counts: cands[0..k) = the children of the
+// k smallest predictions (masked as above; ties by index), in that order, exactly
+// what sorting and taking the first k gives.  False (nothing launched) when n or k
+// exceed the limits below or k > n.
+constexpr int kTopkMaxN = 8192;
+constexpr int kTopkMaxK = 1024;
+bool launch_select_topk(const float* pred, int n_poses, int n_meshes, MeshMask mask, int k,
+                        const int* rest, const int* pose_ids, int2* cands, hipStream_t s);
 void launch_child_cands(const int* idx_sorted, int k, const int* rest, int n_poses,
                         const int* pose_ids, int2* cands, hipStream_t s);
 

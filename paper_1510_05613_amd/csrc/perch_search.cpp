@@ -538,19 +538,13 @@ class Searcher {
     // device buffers kept by the context between searches (grown on demand)
     DevBuf* lb = c_->learned_bufs;
     DevBuf &d_desc = lb[0], &d_pairs = lb[1], &d_dist = lb[2], &d_pose = lb[3];
-    DevBuf &d_crops = lb[4], &d_pred = lb[5], &d_keys = lb[6], &d_idx = lb[7];
-    DevBuf &d_idx2 = lb[8], &d_temp = lb[9];
-    const size_t temp_bytes = select_temp_bytes((int)maxp);
+    DevBuf &d_crops = lb[4], &d_pred = lb[5];  // lb[6..10]: the ranking's sort (rank_children)
     HIP_TRY(d_desc.ensure(sizeof(cnn::CropDesc) * n_cells));
     HIP_TRY(d_pairs.ensure(sizeof(perch_cnn_pair) * maxp));
     HIP_TRY(d_dist.ensure(sizeof(int) * nd));
     HIP_TRY(d_pose.ensure(sizeof(int) * P));
     HIP_TRY(d_crops.ensure((size_t)n_cells * 64 * 64 * 2 * sizeof(uint16_t)));
     HIP_TRY(d_pred.ensure(sizeof(float) * maxp));
-    HIP_TRY(d_keys.ensure(sizeof(float) * maxp));
-    HIP_TRY(d_idx.ensure(sizeof(int) * maxp));
-    HIP_TRY(d_idx2.ensure(sizeof(int) * maxp));
-    HIP_TRY(d_temp.ensure(temp_bytes));
     hipStream_t st0 = c_->stream;
     // stream-ordered uploads; the host arrays outlive the search's first synchronisation
     HIP_TRY(hipMemcpyAsync(d_desc.p, hdesc.data(), sizeof(cnn::CropDesc) * n_cells,
@@ -560,7 +554,6 @@ class Searcher {
     HIP_TRY(hipMemcpyAsync(d_dist.p, dist.data(), sizeof(int) * nd, hipMemcpyHostToDevice, st0));
     HIP_TRY(hipMemcpyAsync(d_pose.p, poses_.data(), sizeof(int) * P, hipMemcpyHostToDevice,
                            st0));
-    launch_iota(d_idx.as<int>(), (int)maxp, st0);
 
     // Children of n: materialise n, crop every cell, predict every (mesh, pose),
     // rank on the device (children of meshes already placed rank last), evaluate
@@ -579,13 +572,12 @@ class Searcher {
       st = cnn_predict_on(o_.cnn, d_crops.as<uint16_t>(), n_cells, d_pairs.p, (int)maxp,
                           d_pred.as<float>(), st0);
       if (st) return st;
-      launch_mask_children(d_pred.as<float>(), P, nd, mask, st0);
-      HIP_TRY(sort_predictions(d_temp.p, temp_bytes, d_pred.as<float>(), d_keys.as<float>(),
-                               d_idx.as<int>(), d_idx2.as<int>(), (int)maxp, st0));
       const int k = std::min(topk, cnt);
       all = k == cnt;
       int2* dc = c_->s_cands.as<int2>();
-      launch_child_cands(d_idx2.as<int>(), k, d_dist.as<int>(), P, d_pose.as<int>(), dc, st0);
+      st = rank_children(c_, d_pred.as<float>(), P, nd, mask, k, d_dist.as<int>(),
+                         d_pose.as<int>(), dc, st0);
+      if (st) return st;
       int32_t* dcost = c_->s_out.as<int32_t>();
       int32_t* dstat = dcost + k;
       int32_t* dgain = dstat + k;

@@ -1,9 +1,11 @@
 // perch_select.hip -- device-side ranking of a state's children for the learned
 // search (arXiv:1510.05613 Sec. IV-C: an inadmissible queue fed by a learned
-// heuristic): the predicted costs are sorted with their child indices (a stable
-// LSD radix sort, so equal predictions keep index order) and the first k indices
-// become (mesh, pose) candidates for the exact evaluation, without a round trip
-// through the host.
+// heuristic): the k children with the smallest predicted cost (equal predictions
+// in index order, -0 equal to +0) become (mesh, pose) candidates for the exact
+// evaluation, in that order, without a round trip through the host.  Up to
+// kTopkMaxN children one workgroup selects them (radix select plus a rank count);
+// beyond that the predictions are sorted with their indices (a stable LSD radix
+// sort) and the first k taken.
 #include <hip/hip_runtime.h>
 
 #include <hipcub/hipcub.hpp>
@@ -19,9 +21,10 @@ __global__ void k_iota(int* idx, int n) {
   if (i < n) idx[i] = i;
 }
 
-__global__ void k_mask_children(float* pred, int n_poses, int n, MeshMask mask) {
+__global__ void k_mask_children(const float* pred, float* masked, int n_poses, int n,
+                                MeshMask mask) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n && !mask.allow[i / n_poses]) pred[i] = __builtin_inff();
+  if (i < n) masked[i] = mask.allow[i / n_poses] ? pred[i] : __builtin_inff();
 }
 
 // child index i = (position of the mesh in the list) * P + (position of the pose)
@@ -33,7 +36,119 @@ __global__ void k_child_cands(const int* idx_sorted, int k, const int* rest, int
   cands[i] = make_int2(rest[id / n_poses], pose_ids[id % n_poses]);
 }
 
+// Order-preserving map of a float to an unsigned key (negative values flipped,
+// positive ones with the sign bit set); -0 maps like +0.
+__device__ inline unsigned order_key(float v) {
+  unsigned b = __float_as_uint(v);
+  if (b == 0x80000000u) b = 0u;
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+// Inclusive prefix sum over one 64-lane wavefront.
+__device__ inline unsigned wave_incl_scan(unsigned x, int lane) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const unsigned v = __shfl_up(x, off, 64);
+    if (lane >= off) x += v;
+  }
+  return x;
+}
+
+constexpr int kSelThreads = 1024;
+constexpr int kSelPer = kTopkMaxN / kSelThreads;  // keys held per thread, in registers
+
+// One workgroup: thread t holds the keys of children [t*per, t*per + per).
+// Four 8-bit radix-select passes (most significant digit first) find T, the k-th
+// smallest key, and how many keys equal to T the first k hold; a block scan of
+// the per-thread tie counts gives each tie its index-order rank; the k chosen
+// (key, index) pairs go to LDS, and each one's rank among them is its output slot.
+__global__ void __launch_bounds__(kSelThreads) k_select_topk(
+    const float* __restrict__ pred, int n_poses, int n, MeshMask mask, int k,
+    const int* __restrict__ rest, const int* __restrict__ pose_ids, int2* __restrict__ cands) {
+  __shared__ unsigned hist[256];
+  __shared__ unsigned s_wsum[kSelThreads / 64];
+  __shared__ unsigned long long s_sel[kTopkMaxK];
+  __shared__ unsigned s_prefix, s_krem, s_nsel;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int per = (n + kSelThreads - 1) / kSelThreads;  // <= kSelPer, checked by the host
+  const int i0 = tid * per;
+  unsigned r[kSelPer];
+#pragma unroll
+  for (int j = 0; j < kSelPer; ++j) {
+    const int i = i0 + j;
+    r[j] = 0xFFFFFFFFu;
+    if (j < per && i < n)
+      r[j] = mask.allow[i / n_poses] ? order_key(pred[i]) : order_key(__builtin_inff());
+  }
+  if (tid == 0) {
+    s_prefix = 0u;
+    s_krem = (unsigned)k;
+    s_nsel = 0u;
+  }
+  for (int pass = 0; pass < 4; ++pass) {
+    const int shift = 24 - 8 * pass;
+    if (tid < 256) hist[tid] = 0u;
+    __syncthreads();
+    const unsigned pre = s_prefix;
+    const unsigned hmask = pass ? (0xFFFFFFFFu << (shift + 8)) : 0u;
+#pragma unroll
+    for (int j = 0; j < kSelPer; ++j)
+      if (j < per && i0 + j < n && (r[j] & hmask) == pre) atomicAdd(&hist[(r[j] >> shift) & 255u], 1u);
+    __syncthreads();
+    if (wave == 0) {
+      const unsigned h0 = hist[4 * lane], h1 = hist[4 * lane + 1], h2 = hist[4 * lane + 2],
+                     h3 = hist[4 * lane + 3];
+      const unsigned sum = h0 + h1 + h2 + h3;
+      const unsigned incl = wave_incl_scan(sum, lane);
+      const unsigned krem = s_krem;
+      unsigned acc = incl - sum;
+      if (acc < krem && incl >= krem) {  // exactly one lane holds the k-th key's digit
+        const unsigned h[4] = {h0, h1, h2, h3};
+        int b = 0;
+        while (acc + h[b] < krem) acc += h[b++];
+        s_prefix = pre | ((unsigned)(4 * lane + b) << shift);
+        s_krem = krem - acc;
+      }
+    }
+    __syncthreads();
+  }
+  const unsigned T = s_prefix, krem = s_krem;
+  unsigned ties = 0;
+#pragma unroll
+  for (int j = 0; j < kSelPer; ++j) ties += (j < per && i0 + j < n && r[j] == T) ? 1u : 0u;
+  const unsigned wincl = wave_incl_scan(ties, lane);
+  if (lane == 63) s_wsum[wave] = wincl;
+  __syncthreads();
+  unsigned base = wincl - ties;
+  for (int w = 0; w < wave; ++w) base += s_wsum[w];
+#pragma unroll
+  for (int j = 0; j < kSelPer; ++j) {
+    const int i = i0 + j;
+    if (j >= per || i >= n) continue;
+    bool take = r[j] < T;
+    if (r[j] == T) take = base++ < krem;
+    if (take) s_sel[atomicAdd(&s_nsel, 1u)] = ((unsigned long long)r[j] << 32) | (unsigned)i;
+  }
+  __syncthreads();
+  for (int t = tid; t < k; t += kSelThreads) {
+    const unsigned long long me = s_sel[t];
+    int rank = 0;
+    for (int q = 0; q < k; ++q) rank += s_sel[q] < me ? 1 : 0;
+    const int id = (int)(me & 0xFFFFFFFFull);
+    cands[rank] = make_int2(rest[id / n_poses], pose_ids[id % n_poses]);
+  }
+}
+
 }  // namespace
+
+bool launch_select_topk(const float* pred, int n_poses, int n_meshes, MeshMask mask, int k,
+                        const int* rest, const int* pose_ids, int2* cands, hipStream_t s) {
+  const long n = (long)n_poses * n_meshes;
+  if (n <= 0 || n > kTopkMaxN || k <= 0 || k > kTopkMaxK || k > n) return false;
+  hipLaunchKernelGGL(k_select_topk, dim3(1), dim3(kSelThreads), 0, s, pred, n_poses, (int)n,
+                     mask, k, rest, pose_ids, cands);
+  return true;
+}
 
 size_t select_temp_bytes(int n) {
   size_t bytes = 0;
@@ -53,11 +168,12 @@ void launch_iota(int* idx, int n, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_iota, dim3((n + 255) / 256), dim3(256), 0, s, idx, n);
 }
 
-void launch_mask_children(float* pred, int n_poses, int n_meshes, MeshMask mask, hipStream_t s) {
+void launch_mask_children(const float* pred, float* masked, int n_poses, int n_meshes,
+                          MeshMask mask, hipStream_t s) {
   const int n = n_poses * n_meshes;
   if (n > 0)
-    hipLaunchKernelGGL(k_mask_children, dim3((n + 255) / 256), dim3(256), 0, s, pred, n_poses, n,
-                       mask);
+    hipLaunchKernelGGL(k_mask_children, dim3((n + 255) / 256), dim3(256), 0, s, pred, masked,
+                       n_poses, n, mask);
 }
 
 void launch_child_cands(const int* idx_sorted, int k, const int* rest, int n_poses,

@@ -33,7 +33,7 @@ EXPORTS = ("perch_create", "perch_destroy", "perch_set_observation", "perch_add_
            "perch_batch_set_parents", "perch_batch_eval", "perch_batch_set_tuning",
            "perch_autotune", "perch_cnn_create", "perch_cnn_destroy", "perch_cnn_param_count",
            "perch_cnn_set_params", "perch_cnn_get_params", "perch_cnn_crops", "perch_cnn_predict",
-           "perch_cnn_train_step", "perch_cnn_gradients", "perch_last_error")
+           "perch_rank_children", "perch_cnn_train_step", "perch_cnn_gradients", "perch_last_error")
 
 SEARCH_EXHAUSTIVE, SEARCH_UCS, SEARCH_FOCAL, SEARCH_LEARNED, SEARCH_MHA = 0, 1, 2, 3, 4
 SEARCH_LEARNED_MHA = 5
@@ -126,6 +126,7 @@ def load(path: str = LIB_PATH):
     L.perch_cnn_get_params.argtypes = [P, P, C.c_int64]
     L.perch_cnn_crops.argtypes = [P, P, I32, P]
     L.perch_cnn_predict.argtypes = [P, P, I32, P, I32, P]
+    L.perch_rank_children.argtypes = [P, P, I32, I32, P, I32, P, P, P]
     L.perch_cnn_train_step.argtypes = [P, P, I32, P, P, I32, C.c_float, C.POINTER(C.c_float)]
     L.perch_cnn_gradients.argtypes = [P, P, I32, P, P, I32, P, C.POINTER(C.c_float)]
     L.perch_batch_create.argtypes = [P, I32, P, C.POINTER(P)]
@@ -303,6 +304,24 @@ class Context:
         out = np.zeros((max(n, 1), 4), np.float32)
         _check(load().perch_get_poses(self.h, int(first), int(n), out.ctypes.data))
         return out[:n]
+
+    def rank_children(self, pred, n_poses: int, allow, k: int, mesh_ids, pose_ids):
+        """The learned search's ranking step: (k, 2) int32 GPU tensor of (mesh, pose)
+        for the k smallest of the n_meshes x n_poses predictions pred (float32 GPU
+        tensor, child u * n_poses + b), ties by child index, mesh positions with
+        allow[u] == 0 last; mesh_ids / pose_ids: int32 GPU tensors."""
+        import torch
+
+        allow = np.ascontiguousarray(allow, np.int32)
+        n_meshes = len(allow)
+        n = n_meshes * int(n_poses)
+        out = torch.empty((max(int(k), 1), 2), dtype=torch.int32, device="cuda")
+        _check(load().perch_rank_children(self.h, _dev_ptr(pred, "float32", n), int(n_poses),
+                                          n_meshes, allow.ctypes.data, int(k),
+                                          _dev_ptr(mesh_ids, "int32", n_meshes),
+                                          _dev_ptr(pose_ids, "int32", int(n_poses)),
+                                          out.data_ptr()))
+        return out[:int(k)]
 
     def icp_children(self, cands, adjusted, n_match, status, iters: int = 10,
                      radius: float = 0.02):
