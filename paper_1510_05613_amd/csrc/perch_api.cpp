@@ -361,7 +361,6 @@ perch_status perch_set_tuning(perch_ctx* c, int32_t threads, int32_t tile_px,
                               float cell_over_delta, int32_t radius_mode) {
   if (!c) return fail(PERCH_E_ARG, "null context");
   if (radius_mode < -1 || radius_mode > 1) return fail(PERCH_E_ARG, "radius_mode must be -1, 0 or 1");
-  if (radius_mode >= 0) c->radius_mode = radius_mode;
   if (threads && threads != 64 && threads != 128 && threads != 256 && threads != 512 &&
       threads != 1024)
     return fail(PERCH_E_ARG, "threads must be 64, 128, 256, 512 or 1024");
@@ -369,6 +368,8 @@ perch_status perch_set_tuning(perch_ctx* c, int32_t threads, int32_t tile_px,
     return fail(PERCH_E_ARG, "bad tile_px");
   if (cell_over_delta != 0.0f && !(cell_over_delta >= 1.0f && cell_over_delta <= 8.0f))
     return fail(PERCH_E_ARG, "cell_over_delta must be in [1, 8]");
+  // every argument is checked before any is applied
+  if (radius_mode >= 0) c->radius_mode = radius_mode;
   if (threads) c->threads = threads;
   if (tile_px) c->tile_px = tile_px < 0 ? 0 : tile_px;
   if (cell_over_delta != 0.0f && cell_over_delta != c->cell_over_delta) {

@@ -20,6 +20,7 @@ struct perch_batch {
   hipStream_t capture = nullptr;  // private stream used only to capture graphs
   DevBuf scenes, parents, slot_depth, slot_ubits, slot_ucount, counter;
   int n_parents = 0;
+  int hash = 0;  // some scene of the table answers dJ_r by the voxel hash
   size_t npx_max = 0;
   int threads = 512;
   int tile_px = 0;  // 0 = sized automatically (auto_tile_px)
@@ -31,7 +32,7 @@ struct perch_batch {
   const void* g_items = nullptr;
   int g_n = -1;
   const void *g_cost = nullptr, *g_status = nullptr, *g_comps = nullptr;
-  int g_threads = 0, g_tile = 0, g_grid = 0, g_parents = -1;
+  int g_threads = 0, g_tile = 0, g_grid = 0, g_parents = -1, g_hash = -1;
   const void* g_ptab = nullptr;
 
   int max_nv() const {
@@ -149,11 +150,13 @@ perch_status perch_batch_set_parents(perch_batch* b, const perch_parent* parents
   }
   std::vector<SceneDev> sd(b->ctxs.size());
   const int max_nv = b->max_nv();
+  int hash = 0;
   for (size_t k = 0; k < b->ctxs.size(); ++k) {
     sd[k] = b->ctxs[k]->scene_dev();
     sd[k].ep.tile_px = b->tile();
     sd[k].ep.max_nv = max_nv;
     sd[k].ep.vpack = vertex_cache_packed(max_nv);
+    hash |= sd[k].ep.radius_mode == 1 ? 1 : 0;
   }
   HIP_TRY(hipMemcpyAsync(b->parents.p, pd.data(), sizeof(ParentDev) * pd.size(),
                          hipMemcpyHostToDevice, b->stream));
@@ -162,6 +165,7 @@ perch_status perch_batch_set_parents(perch_batch* b, const perch_parent* parents
   // the host vectors die here: the copies must complete first
   HIP_TRY(hipStreamSynchronize(b->stream));
   b->n_parents = n;
+  b->hash = hash;
   return PERCH_OK;
 }
 
@@ -179,28 +183,31 @@ perch_status perch_batch_eval(perch_batch* b, const perch_work* items_dev, int32
     int dev = 0, cus = 0, per_cu = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    HIP_TRY(prepare_eval_batch(b->threads, vertex_cache_packed(b->max_nv()), lds, &per_cu));
+    HIP_TRY(prepare_eval_batch(b->threads, vertex_cache_packed(b->max_nv()), b->hash, lds,
+                               &per_cu));
     if (grid <= 0) grid = std::max(1, cus * std::max(1, per_cu));
   }
   const int4* items = reinterpret_cast<const int4*>(items_dev);
   const SceneDev* scenes = b->scenes.as<SceneDev>();
   const ParentDev* parents = b->parents.as<ParentDev>();
   if (!b->use_graph) {
-    HIP_TRY(launch_eval_batch(b->threads, vertex_cache_packed(b->max_nv()), scenes, parents,
-                              b->n_parents, items, n, b->counter.as<int>(), cost_dev,
+    HIP_TRY(launch_eval_batch(b->threads, vertex_cache_packed(b->max_nv()), b->hash, scenes,
+                              parents, b->n_parents, items, n, b->counter.as<int>(), cost_dev,
                               status_dev, comps_dev, lds, grid, b->stream));
     return PERCH_OK;
   }
   const bool same = b->exec && b->g_items == items_dev && b->g_n == n && b->g_cost == cost_dev &&
                     b->g_status == status_dev && b->g_comps == comps_dev &&
                     b->g_threads == b->threads && b->g_tile == b->tile() && b->g_grid == grid &&
-                    b->g_parents == b->n_parents && b->g_ptab == b->parents.p;
+                    b->g_parents == b->n_parents && b->g_ptab == b->parents.p &&
+                    b->g_hash == b->hash;
   if (!same) {
     b->drop_graph();
     HIP_TRY(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
-    hipError_t e = launch_eval_batch(b->threads, vertex_cache_packed(b->max_nv()), scenes,
-                                     parents, b->n_parents, items, n, b->counter.as<int>(),
-                                     cost_dev, status_dev, comps_dev, lds, grid, b->capture);
+    hipError_t e = launch_eval_batch(b->threads, vertex_cache_packed(b->max_nv()), b->hash,
+                                     scenes, parents, b->n_parents, items, n,
+                                     b->counter.as<int>(), cost_dev, status_dev, comps_dev, lds,
+                                     grid, b->capture);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(b->capture, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
@@ -220,6 +227,7 @@ perch_status perch_batch_eval(perch_batch* b, const perch_work* items_dev, int32
     b->g_grid = grid;
     b->g_parents = b->n_parents;
     b->g_ptab = b->parents.p;
+    b->g_hash = b->hash;
   }
   HIP_TRY(hipGraphLaunch(b->exec, b->stream));
   return PERCH_OK;

@@ -116,13 +116,15 @@ hipError_t launch_eval(int threads, const SceneDev& S, const Parent& par, const 
 void launch_parent_v(const Cam& cam, const Meshes& M, const float4* poses, const float* obs,
                      const int* par_mesh_pose, int j, unsigned* vbits, hipStream_t s);
 // Raises the kernel's LDS limit and reports resident workgroups per CU (call
-// before launch_eval_batch, outside any graph capture).
-hipError_t prepare_eval_batch(int threads, int vpack, size_t lds_bytes, int* blocks_per_cu);
+// before launch_eval_batch, outside any graph capture).  hash != 0: some scene of
+// the table answers dJ_r by the voxel hash (radius mode 1).
+hipError_t prepare_eval_batch(int threads, int vpack, int hash, size_t lds_bytes,
+                              int* blocks_per_cu);
 // grid = number of persistent workgroups (clamped to n)
-hipError_t launch_eval_batch(int threads, int vpack, const SceneDev* scenes,
-                             const ParentDev* parents,
-                             int n_parents, const int4* items, int n, int* counter, int* cost,
-                             int* status, int* comps, size_t lds_bytes, int grid, hipStream_t s);
+hipError_t launch_eval_batch(int threads, int vpack, int hash, const SceneDev* scenes,
+                             const ParentDev* parents, int n_parents, const int4* items, int n,
+                             int* counter, int* cost, int* status, int* comps, size_t lds_bytes,
+                             int grid, hipStream_t s);
 
 // ---- local ICP (Sec. V-A) ----
 constexpr int kIcpThreads = 512;

@@ -654,7 +654,10 @@ __global__ void k_parent_v(Cam cam, Meshes M, const float4* poses, const float* 
 // arguments; it synchronises the workgroup internally.
 // GAIN: also write the overlap gain (points of V(O) outside the parent's V_j) to
 // out_gain, which must then be non-null.
-template <int NT, bool OUTLINE, bool VP, bool GAIN>
+// HQ: the scene may answer dJ_r by the voxel hash (radius mode 1).  The window
+// scan's instantiation (HQ false) carries no hash code, which measurably shortens
+// the kernel's critical loops.
+template <int NT, bool OUTLINE, bool VP, bool GAIN, bool HQ>
 __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& par, const int2 cd,
                                                const int s, int* __restrict__ out_cost,
                                                int* __restrict__ out_status,
@@ -923,7 +926,7 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
           const float ex = q.x - p.x, ey = q.y - p.y, ez = q.z - p.z;
           const bool same = hq && hp && ex * ex + ey * ey + ez * ez <= delta2;
           if (hq) {
-            if (ep.radius_mode == 1) {
+            if (HQ && ep.radius_mode == 1) {
               state = explained_by_cloud(hs, q.x, q.y, q.z, delta2) ? 1 : 2;
             } else if (same) {
               state = 1;
@@ -1052,7 +1055,7 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
 }
 
 // One workgroup per successor of one parent.
-template <int NT, bool VP, bool GAIN>
+template <int NT, bool VP, bool GAIN, bool HQ>
 __global__ void __launch_bounds__(NT)
     k_eval(SceneDev S, Parent par, const int2* __restrict__ cands, int n,
            int* __restrict__ out_cost, int* __restrict__ out_status, int* __restrict__ out_comps,
@@ -1063,14 +1066,14 @@ __global__ void __launch_bounds__(NT)
   __shared__ float4 s_pl[kLdsPlanes];
   const int s = blockIdx.x;
   if (s >= n) return;
-  eval_successor<NT, false, VP, GAIN>(S, par, cands[s], s, out_cost, out_status, out_comps,
-                                      out_gain, smem, s_bb, s_acc, s_pl);
+  eval_successor<NT, false, VP, GAIN, HQ>(S, par, cands[s], s, out_cost, out_status, out_comps,
+                                          out_gain, smem, s_bb, s_acc, s_pl);
 }
 
 // Persistent workgroups over a work queue of (parent slot, mesh, pose) items that
 // may belong to different scenes: each workgroup takes the next item from an
 // atomic counter until the queue is empty, so uneven meshes balance across CUs.
-template <int NT, bool VP>
+template <int NT, bool VP, bool HQ>
 __global__ void __launch_bounds__(NT, 4)  // at least 4 waves per SIMD: <= 128 VGPRs
     k_eval_batch(const SceneDev* __restrict__ scenes, const ParentDev* __restrict__ parents,
                  int n_parents, const int4* __restrict__ items, int n, int* counter,
@@ -1107,8 +1110,9 @@ __global__ void __launch_bounds__(NT, 4)  // at least 4 waves per SIMD: <= 128 V
     par.has_parent = pd.has_parent;
     par.goal = pd.goal;
     const int scene = __builtin_amdgcn_readfirstlane(pd.scene);
-    eval_successor<NT, true, VP, false>(scenes[scene], par, make_int2(w.y, w.z), it, out_cost,
-                                        out_status, out_comps, nullptr, smem, s_bb, s_acc, s_pl);
+    eval_successor<NT, true, VP, false, HQ>(scenes[scene], par, make_int2(w.y, w.z), it,
+                                            out_cost, out_status, out_comps, nullptr, smem, s_bb,
+                                            s_acc, s_pl);
   }
 }
 
@@ -1540,121 +1544,147 @@ static hipError_t allow_lds(K kernel, size_t lds) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-template <int NT, bool VP, bool GAIN>
+template <int NT, bool VP, bool GAIN, bool HQ>
 static hipError_t launch_eval_g(const SceneDev& S, const Parent& par, const int2* cands, int n,
                                 int* cost, int* status, int* comps, int* gain, size_t lds,
                                 hipStream_t s) {
-  hipError_t e = allow_lds(&k_eval<NT, VP, GAIN>, lds);
+  hipError_t e = allow_lds(&k_eval<NT, VP, GAIN, HQ>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_eval<NT, VP, GAIN>), dim3(n), dim3(NT), lds, s, S, par, cands, n, cost,
-                     status, comps, gain);
+  hipLaunchKernelGGL((k_eval<NT, VP, GAIN, HQ>), dim3(n), dim3(NT), lds, s, S, par, cands, n,
+                     cost, status, comps, gain);
   return hipGetLastError();
 }
 
-template <int NT, bool VP>
+template <int NT, bool VP, bool HQ>
 static hipError_t launch_eval_t(const SceneDev& S, const Parent& par, const int2* cands, int n,
                                 int* cost, int* status, int* comps, int* gain, size_t lds,
                                 hipStream_t s) {
-  return gain ? launch_eval_g<NT, VP, true>(S, par, cands, n, cost, status, comps, gain, lds, s)
-              : launch_eval_g<NT, VP, false>(S, par, cands, n, cost, status, comps, gain, lds, s);
+  return gain
+             ? launch_eval_g<NT, VP, true, HQ>(S, par, cands, n, cost, status, comps, gain, lds, s)
+             : launch_eval_g<NT, VP, false, HQ>(S, par, cands, n, cost, status, comps, gain, lds,
+                                                s);
 }
 
-template <bool VP>
+template <bool VP, bool HQ>
 static hipError_t launch_eval_vp(int threads, const SceneDev& S, const Parent& par,
                                  const int2* cands, int n, int* cost, int* status, int* comps,
                                  int* gain, size_t lds, hipStream_t s) {
   switch (threads) {
     case 64:
-      return launch_eval_t<64, VP>(S, par, cands, n, cost, status, comps, gain, lds, s);
+      return launch_eval_t<64, VP, HQ>(S, par, cands, n, cost, status, comps, gain, lds, s);
     case 128:
-      return launch_eval_t<128, VP>(S, par, cands, n, cost, status, comps, gain, lds, s);
+      return launch_eval_t<128, VP, HQ>(S, par, cands, n, cost, status, comps, gain, lds, s);
     case 512:
-      return launch_eval_t<512, VP>(S, par, cands, n, cost, status, comps, gain, lds, s);
+      return launch_eval_t<512, VP, HQ>(S, par, cands, n, cost, status, comps, gain, lds, s);
     case 1024:
-      return launch_eval_t<1024, VP>(S, par, cands, n, cost, status, comps, gain, lds, s);
+      return launch_eval_t<1024, VP, HQ>(S, par, cands, n, cost, status, comps, gain, lds, s);
     default:
-      return launch_eval_t<256, VP>(S, par, cands, n, cost, status, comps, gain, lds, s);
+      return launch_eval_t<256, VP, HQ>(S, par, cands, n, cost, status, comps, gain, lds, s);
   }
+}
+
+template <bool VP>
+static hipError_t launch_eval_hq(int threads, const SceneDev& S, const Parent& par,
+                                 const int2* cands, int n, int* cost, int* status, int* comps,
+                                 int* gain, size_t lds, hipStream_t s) {
+  return S.ep.radius_mode == 1
+             ? launch_eval_vp<VP, true>(threads, S, par, cands, n, cost, status, comps, gain, lds,
+                                        s)
+             : launch_eval_vp<VP, false>(threads, S, par, cands, n, cost, status, comps, gain,
+                                         lds, s);
 }
 
 hipError_t launch_eval(int threads, const SceneDev& S, const Parent& par, const int2* cands,
                        int n, int* cost, int* status, int* comps, int* gain, size_t lds_bytes,
                        hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  return S.ep.vpack ? launch_eval_vp<true>(threads, S, par, cands, n, cost, status, comps, gain,
+  return S.ep.vpack ? launch_eval_hq<true>(threads, S, par, cands, n, cost, status, comps, gain,
                                            lds_bytes, s)
-                    : launch_eval_vp<false>(threads, S, par, cands, n, cost, status, comps,
+                    : launch_eval_hq<false>(threads, S, par, cands, n, cost, status, comps,
                                             gain, lds_bytes, s);
 }
 
-template <int NT, bool VP>
+template <int NT, bool VP, bool HQ>
 static hipError_t prepare_eval_batch_t(size_t lds, int* per_cu) {
-  hipError_t e = allow_lds(&k_eval_batch<NT, VP>, lds);
+  hipError_t e = allow_lds(&k_eval_batch<NT, VP, HQ>, lds);
   if (e != hipSuccess) return e;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_eval_batch<NT, VP>, NT, lds);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_eval_batch<NT, VP, HQ>, NT, lds);
 }
 
-template <bool VP>
+template <bool VP, bool HQ>
 static hipError_t prepare_eval_batch_vp(int threads, size_t lds, int* per_cu) {
   switch (threads) {
     case 64:
-      return prepare_eval_batch_t<64, VP>(lds, per_cu);
+      return prepare_eval_batch_t<64, VP, HQ>(lds, per_cu);
     case 128:
-      return prepare_eval_batch_t<128, VP>(lds, per_cu);
+      return prepare_eval_batch_t<128, VP, HQ>(lds, per_cu);
     case 512:
-      return prepare_eval_batch_t<512, VP>(lds, per_cu);
+      return prepare_eval_batch_t<512, VP, HQ>(lds, per_cu);
     default:
-      return prepare_eval_batch_t<256, VP>(lds, per_cu);
+      return prepare_eval_batch_t<256, VP, HQ>(lds, per_cu);
   }
 }
 
-hipError_t prepare_eval_batch(int threads, int vpack, size_t lds_bytes, int* blocks_per_cu) {
-  return vpack ? prepare_eval_batch_vp<true>(threads, lds_bytes, blocks_per_cu)
-               : prepare_eval_batch_vp<false>(threads, lds_bytes, blocks_per_cu);
+hipError_t prepare_eval_batch(int threads, int vpack, int hash, size_t lds_bytes,
+                              int* blocks_per_cu) {
+  if (hash)
+    return vpack ? prepare_eval_batch_vp<true, true>(threads, lds_bytes, blocks_per_cu)
+                 : prepare_eval_batch_vp<false, true>(threads, lds_bytes, blocks_per_cu);
+  return vpack ? prepare_eval_batch_vp<true, false>(threads, lds_bytes, blocks_per_cu)
+               : prepare_eval_batch_vp<false, false>(threads, lds_bytes, blocks_per_cu);
 }
 
-template <int NT, bool VP>
+template <int NT, bool VP, bool HQ>
 static hipError_t launch_eval_batch_t(const SceneDev* scenes, const ParentDev* parents,
                                       int n_parents, const int4* items, int n, int* counter,
                                       int* cost, int* status, int* comps, size_t lds, int grid,
                                       hipStream_t s) {
   grid = std::max(1, std::min(grid, n));
-  hipLaunchKernelGGL((k_eval_batch<NT, VP>), dim3(grid), dim3(NT), lds, s, scenes, parents,
+  hipLaunchKernelGGL((k_eval_batch<NT, VP, HQ>), dim3(grid), dim3(NT), lds, s, scenes, parents,
                      n_parents, items, n, counter, cost, status, comps);
   return hipGetLastError();
 }
 
-template <bool VP>
+template <bool VP, bool HQ>
 static hipError_t launch_eval_batch_vp(int threads, const SceneDev* scenes,
                                        const ParentDev* parents, int n_parents, const int4* items,
                                        int n, int* counter, int* cost, int* status, int* comps,
                                        size_t lds, int grid, hipStream_t s) {
   switch (threads) {
     case 64:
-      return launch_eval_batch_t<64, VP>(scenes, parents, n_parents, items, n, counter, cost,
-                                         status, comps, lds, grid, s);
+      return launch_eval_batch_t<64, VP, HQ>(scenes, parents, n_parents, items, n, counter, cost,
+                                             status, comps, lds, grid, s);
     case 128:
-      return launch_eval_batch_t<128, VP>(scenes, parents, n_parents, items, n, counter, cost,
-                                          status, comps, lds, grid, s);
+      return launch_eval_batch_t<128, VP, HQ>(scenes, parents, n_parents, items, n, counter,
+                                              cost, status, comps, lds, grid, s);
     case 512:
-      return launch_eval_batch_t<512, VP>(scenes, parents, n_parents, items, n, counter, cost,
-                                          status, comps, lds, grid, s);
+      return launch_eval_batch_t<512, VP, HQ>(scenes, parents, n_parents, items, n, counter,
+                                              cost, status, comps, lds, grid, s);
     default:
-      return launch_eval_batch_t<256, VP>(scenes, parents, n_parents, items, n, counter, cost,
-                                          status, comps, lds, grid, s);
+      return launch_eval_batch_t<256, VP, HQ>(scenes, parents, n_parents, items, n, counter,
+                                              cost, status, comps, lds, grid, s);
   }
 }
 
-hipError_t launch_eval_batch(int threads, int vpack, const SceneDev* scenes,
+hipError_t launch_eval_batch(int threads, int vpack, int hash, const SceneDev* scenes,
                              const ParentDev* parents, int n_parents, const int4* items, int n,
                              int* counter, int* cost, int* status, int* comps, size_t lds_bytes,
                              int grid, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   launch_fill_i32(counter, 0, 1, s);  // a fill kernel (not a memset): safe in captured graphs
-  return vpack ? launch_eval_batch_vp<true>(threads, scenes, parents, n_parents, items, n,
-                                            counter, cost, status, comps, lds_bytes, grid, s)
-               : launch_eval_batch_vp<false>(threads, scenes, parents, n_parents, items, n,
-                                             counter, cost, status, comps, lds_bytes, grid, s);
+  if (hash)
+    return vpack ? launch_eval_batch_vp<true, true>(threads, scenes, parents, n_parents, items, n,
+                                                    counter, cost, status, comps, lds_bytes,
+                                                    grid, s)
+                 : launch_eval_batch_vp<false, true>(threads, scenes, parents, n_parents, items,
+                                                     n, counter, cost, status, comps, lds_bytes,
+                                                     grid, s);
+  return vpack ? launch_eval_batch_vp<true, false>(threads, scenes, parents, n_parents, items, n,
+                                                   counter, cost, status, comps, lds_bytes, grid,
+                                                   s)
+               : launch_eval_batch_vp<false, false>(threads, scenes, parents, n_parents, items, n,
+                                                    counter, cost, status, comps, lds_bytes,
+                                                    grid, s);
 }
 
 void launch_obs_normals(const Cam& cam, const float* obs, float radius, float4* pn,

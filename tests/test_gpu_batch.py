@@ -105,6 +105,44 @@ def test_batch_equals_per_parent_evaluation_and_replays(mixed):
     b.close()
 
 
+def test_batch_with_hash_mode_scenes_matches(mixed):
+    """Scenes answering dJ_r by the voxel hash (radius mode 1) next to window-scan
+    scenes: the batch switches to its hash-capable kernel (and recaptures its graph),
+    and the results equal per-parent evaluation in either mode."""
+    scs, ctxs = mixed
+    rng = np.random.default_rng(5)
+    parents = []
+    for ci, sc in enumerate(scs):
+        parents += _gt_parents(sc, ci)
+    items = np.ascontiguousarray(_items_for(parents, scs, rng, 120))
+    ref = _reference(ctxs, parents, items)
+    n = len(items)
+    dev_items = torch.as_tensor(items).cuda()
+    cost = torch.empty(n, dtype=torch.int32, device="cuda")
+    st = torch.empty(n, dtype=torch.int32, device="cuda")
+    comps = torch.empty((n, 5), dtype=torch.int32, device="cuda")
+    b = perch.Batch(ctxs)
+    try:
+        for modes in ((0, 1, 1, 0), (0, 0, 0, 0), (1, 1, 1, 1)):
+            for c, m in zip(ctxs, modes):
+                c.set_tuning(0, 0, 0, m)
+            b.set_parents(parents)  # the scene table takes each context's mode
+            for _ in range(2):  # capture, then replay
+                cost.fill_(-7)
+                b.eval(dev_items, cost, st, comps)
+                torch.cuda.synchronize()
+                got = (st.cpu().numpy(), cost.cpu().numpy(), comps.cpu().numpy())
+                for a, g in zip(ref, got):
+                    assert np.array_equal(a, g), modes
+            # per-parent launches in the same modes agree too
+            for a, g in zip(ref, _reference(ctxs, parents, items)):
+                assert np.array_equal(a, g), modes
+    finally:
+        for c in ctxs:
+            c.set_tuning(0, 0, 0, 0)
+        b.close()
+
+
 def test_batch_rejects_bad_parent_slots(mixed):
     scs, ctxs = mixed
     b = perch.Batch(ctxs[:1])
