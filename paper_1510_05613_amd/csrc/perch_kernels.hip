@@ -654,10 +654,11 @@ __global__ void k_parent_v(Cam cam, Meshes M, const float4* poses, const float* 
 // arguments; it synchronises the workgroup internally.
 // GAIN: also write the overlap gain (points of V(O) outside the parent's V_j) to
 // out_gain, which must then be non-null.
-// HQ: the scene may answer dJ_r by the voxel hash (radius mode 1).  The window
-// scan's instantiation (HQ false) carries no hash code, which measurably shortens
-// the kernel's critical loops.
-template <int NT, bool OUTLINE, bool VP, bool GAIN, bool HQ>
+// HQ: the scene may answer dJ_r by the voxel hash (radius mode 1).  G: the parent
+// may be at the goal level (the set U and the residual).  Instantiations without
+// the hash or the goal-level code (HQ, G false) measurably shorten the kernel's
+// critical loops; G false requires a parent below the goal level.
+template <int NT, bool OUTLINE, bool VP, bool GAIN, bool HQ, bool G>
 __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& par, const int2 cd,
                                                const int s, int* __restrict__ out_cost,
                                                int* __restrict__ out_status,
@@ -788,7 +789,8 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
 
   // observed region: the vertex box (+1 px: every point of V(O) projects inside it),
   // grown by the window halo at the goal level (points of U explained by dR)
-  const int ext = par.goal ? max(1, ep.halo) : 1;
+  const bool goal = G && par.goal;
+  const int ext = goal ? max(1, ep.halo) : 1;
   const int ca = max(0, floor256(s_bb[0]) - ext), cb = min(W - 1, ceil256(s_bb[2]) + ext);
   const int ra = max(0, floor256(s_bb[1]) - ext), rb = min(H - 1, ceil256(s_bb[3]) + ext);
   const int tw = cb - ca + 1;
@@ -937,7 +939,7 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
           }
           if (hp) {
             inV = in_volume_at(vlo, vhi, vplanes, fr.y, apply_obj_map(om, p));
-            inU = par.goal && ((par.ubits[pix >> 5] >> (pix & 31)) & 1u);
+            inU = goal && ((par.ubits[pix >> 5] >> (pix & 31)) & 1u);
             expl = same;
             if ((inV || inU) && !expl) {
               int ru, rv;
@@ -1040,7 +1042,7 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
   __syncthreads();
   if (tid == 0) {
     const bool valid = s_acc[5] == 0;
-    const int res = par.goal ? (*par.ucount - s_acc[4]) : 0;
+    const int res = goal ? (*par.ucount - s_acc[4]) : 0;
     out_status[s] = valid ? 1 : 0;
     out_cost[s] = valid ? s_acc[2] + s_acc[3] + res : -1;
     if (GAIN) out_gain[s] = valid ? s_acc[7] : -1;
@@ -1055,7 +1057,7 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
 }
 
 // One workgroup per successor of one parent.
-template <int NT, bool VP, bool GAIN, bool HQ>
+template <int NT, bool VP, bool GAIN, bool HQ, bool G>
 __global__ void __launch_bounds__(NT)
     k_eval(SceneDev S, Parent par, const int2* __restrict__ cands, int n,
            int* __restrict__ out_cost, int* __restrict__ out_status, int* __restrict__ out_comps,
@@ -1066,8 +1068,8 @@ __global__ void __launch_bounds__(NT)
   __shared__ float4 s_pl[kLdsPlanes];
   const int s = blockIdx.x;
   if (s >= n) return;
-  eval_successor<NT, false, VP, GAIN, HQ>(S, par, cands[s], s, out_cost, out_status, out_comps,
-                                          out_gain, smem, s_bb, s_acc, s_pl);
+  eval_successor<NT, false, VP, GAIN, HQ, G>(S, par, cands[s], s, out_cost, out_status,
+                                             out_comps, out_gain, smem, s_bb, s_acc, s_pl);
 }
 
 // Persistent workgroups over a work queue of (parent slot, mesh, pose) items that
@@ -1110,7 +1112,7 @@ __global__ void __launch_bounds__(NT, 4)  // at least 4 waves per SIMD: <= 128 V
     par.has_parent = pd.has_parent;
     par.goal = pd.goal;
     const int scene = __builtin_amdgcn_readfirstlane(pd.scene);
-    eval_successor<NT, true, VP, false, HQ>(scenes[scene], par, make_int2(w.y, w.z), it,
+    eval_successor<NT, true, VP, false, HQ, true>(scenes[scene], par, make_int2(w.y, w.z), it,
                                             out_cost, out_status, out_comps, nullptr, smem, s_bb,
                                             s_acc, s_pl);
   }
@@ -1544,54 +1546,58 @@ static hipError_t allow_lds(K kernel, size_t lds) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-template <int NT, bool VP, bool GAIN, bool HQ>
+template <int NT, bool VP, bool GAIN, bool HQ, bool G>
 static hipError_t launch_eval_g(const SceneDev& S, const Parent& par, const int2* cands, int n,
                                 int* cost, int* status, int* comps, int* gain, size_t lds,
                                 hipStream_t s) {
-  hipError_t e = allow_lds(&k_eval<NT, VP, GAIN, HQ>, lds);
+  hipError_t e = allow_lds(&k_eval<NT, VP, GAIN, HQ, G>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_eval<NT, VP, GAIN, HQ>), dim3(n), dim3(NT), lds, s, S, par, cands, n,
+  hipLaunchKernelGGL((k_eval<NT, VP, GAIN, HQ, G>), dim3(n), dim3(NT), lds, s, S, par, cands, n,
                      cost, status, comps, gain);
   return hipGetLastError();
 }
 
-template <int NT, bool VP, bool HQ>
+template <int NT, bool VP, bool HQ, bool G>
 static hipError_t launch_eval_t(const SceneDev& S, const Parent& par, const int2* cands, int n,
                                 int* cost, int* status, int* comps, int* gain, size_t lds,
                                 hipStream_t s) {
-  return gain
-             ? launch_eval_g<NT, VP, true, HQ>(S, par, cands, n, cost, status, comps, gain, lds, s)
-             : launch_eval_g<NT, VP, false, HQ>(S, par, cands, n, cost, status, comps, gain, lds,
-                                                s);
+  return gain ? launch_eval_g<NT, VP, true, HQ, G>(S, par, cands, n, cost, status, comps, gain,
+                                                   lds, s)
+              : launch_eval_g<NT, VP, false, HQ, G>(S, par, cands, n, cost, status, comps, gain,
+                                                    lds, s);
 }
 
-template <bool VP, bool HQ>
+template <bool VP, bool HQ, bool G>
 static hipError_t launch_eval_vp(int threads, const SceneDev& S, const Parent& par,
                                  const int2* cands, int n, int* cost, int* status, int* comps,
                                  int* gain, size_t lds, hipStream_t s) {
   switch (threads) {
     case 64:
-      return launch_eval_t<64, VP, HQ>(S, par, cands, n, cost, status, comps, gain, lds, s);
+      return launch_eval_t<64, VP, HQ, G>(S, par, cands, n, cost, status, comps, gain, lds, s);
     case 128:
-      return launch_eval_t<128, VP, HQ>(S, par, cands, n, cost, status, comps, gain, lds, s);
+      return launch_eval_t<128, VP, HQ, G>(S, par, cands, n, cost, status, comps, gain, lds, s);
     case 512:
-      return launch_eval_t<512, VP, HQ>(S, par, cands, n, cost, status, comps, gain, lds, s);
+      return launch_eval_t<512, VP, HQ, G>(S, par, cands, n, cost, status, comps, gain, lds, s);
     case 1024:
-      return launch_eval_t<1024, VP, HQ>(S, par, cands, n, cost, status, comps, gain, lds, s);
+      return launch_eval_t<1024, VP, HQ, G>(S, par, cands, n, cost, status, comps, gain, lds, s);
     default:
-      return launch_eval_t<256, VP, HQ>(S, par, cands, n, cost, status, comps, gain, lds, s);
+      return launch_eval_t<256, VP, HQ, G>(S, par, cands, n, cost, status, comps, gain, lds, s);
   }
 }
 
+// Hash-mode scenes take the instantiation with both the hash and the goal-level
+// code; window-scan scenes the one with the goal-level code only at the goal level.
 template <bool VP>
 static hipError_t launch_eval_hq(int threads, const SceneDev& S, const Parent& par,
                                  const int2* cands, int n, int* cost, int* status, int* comps,
                                  int* gain, size_t lds, hipStream_t s) {
-  return S.ep.radius_mode == 1
-             ? launch_eval_vp<VP, true>(threads, S, par, cands, n, cost, status, comps, gain, lds,
-                                        s)
-             : launch_eval_vp<VP, false>(threads, S, par, cands, n, cost, status, comps, gain,
-                                         lds, s);
+  if (S.ep.radius_mode == 1)
+    return launch_eval_vp<VP, true, true>(threads, S, par, cands, n, cost, status, comps, gain,
+                                          lds, s);
+  return par.goal ? launch_eval_vp<VP, false, true>(threads, S, par, cands, n, cost, status,
+                                                    comps, gain, lds, s)
+                  : launch_eval_vp<VP, false, false>(threads, S, par, cands, n, cost, status,
+                                                     comps, gain, lds, s);
 }
 
 hipError_t launch_eval(int threads, const SceneDev& S, const Parent& par, const int2* cands,
