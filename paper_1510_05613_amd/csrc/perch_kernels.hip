@@ -655,10 +655,12 @@ __global__ void k_parent_v(Cam cam, Meshes M, const float4* poses, const float* 
 // GAIN: also write the overlap gain (points of V(O) outside the parent's V_j) to
 // out_gain, which must then be non-null.
 // HQ: the scene may answer dJ_r by the voxel hash (radius mode 1).  G: the parent
-// may be at the goal level (the set U and the residual).  Instantiations without
-// the hash or the goal-level code (HQ, G false) measurably shorten the kernel's
-// critical loops; G false requires a parent below the goal level.
-template <int NT, bool OUTLINE, bool VP, bool GAIN, bool HQ, bool G>
+// may be at the goal level (the set U and the residual).  P: there may be a parent
+// (below the root); without one dR is the silhouette, so the composite pass is
+// skipped and the dJ pass counts the covered pixels.  Instantiations without the
+// hash, the goal-level or the parent code measurably shorten the kernel's critical
+// loops; G false requires a parent below the goal level, P false the root.
+template <int NT, bool OUTLINE, bool VP, bool GAIN, bool HQ, bool G, bool P>
 __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& par, const int2 cd,
                                                const int s, int* __restrict__ out_cost,
                                                int* __restrict__ out_status,
@@ -809,6 +811,7 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
   }
   const float delta2 = cam.delta2;
   int n_dJr = 0, n_dJo = 0, n_rem = 0, n_gain = 0;  // wave-uniform ballot counts
+  int n_cov = 0;  // covered core pixels (the silhouette), counted in the dJ pass when !P
 
   for (int b0 = ra; b0 <= rb && tw > 0; b0 += core) {
     const int b1 = min(rb, b0 + core - 1);
@@ -864,7 +867,7 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
     __syncthreads();
 
     // ---- composite against the parent: validity (Eq. 3) and dR ----
-    {
+    if (P) {
       int sl = 0, dr = 0;
       bool occ = false;
       const float inv_tw = __builtin_amdgcn_rcpf((float)tw);
@@ -873,13 +876,15 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
         const int jj = t0 + r, ii = ca + (k - r * tw);
         const unsigned key = tile[k];
         const bool cov = key != kInfBits;
-        const unsigned pk = par.has_parent ? par.depth[jj * W + ii] : kInfBits;
+        // only a covered pixel needs the parent, and only one the parent also
+        // covers changes (it leaves dR)
+        const unsigned pk = (cov && par.has_parent) ? par.depth[jj * W + ii] : kInfBits;
         const bool pfin = pk != kInfBits;
         occ |= cov && pfin && key < pk;  // positive floats order like their bits
         const bool core_row = jj >= b0 && jj <= b1;
         sl += (cov && core_row);
         dr += (cov && !pfin && core_row);
-        tile[k] = (cov && !pfin) ? key : kInfBits;
+        if (pfin) tile[k] = kInfBits;
       }
       sl = wave_sum(sl);
       dr = wave_sum(dr);
@@ -889,9 +894,9 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
         atomicAdd(&s_acc[1], dr);
         if (any_occ) atomicOr(&s_acc[5], 1);
       }
+      __syncthreads();
+      if (s_acc[5]) break;
     }
-    __syncthreads();
-    if (s_acc[5]) break;
 
     // ---- dJ_r, dJ_o and U: one pass over the core rows ----
     // Per pixel: the new point q (dR, from the tile) and the observed point p; the
@@ -911,6 +916,7 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
         bool inV = false, inU = false, expl = false;
         float zq = 0.0f;
         int ii = 0, jj = 0;
+        bool hqv = false;
         if (k < nk) {
           // k / tw for k < 2^21: (k + 1/2) / tw is at least 1 / (2 tw) from an integer
           const int r = (int)(((float)k + 0.5f) * inv_tw);
@@ -920,6 +926,7 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
           const int pix = jj * W + ii;
           const float zo = obs[pix];
           const bool hq = key != kInfBits, hp = zo > 0.0f;
+          hqv = hq;
           zq = __uint_as_float(key);
           // the same arithmetic as the window scans and the voxel hash, so that
           // every radius mode takes identical decisions
@@ -966,6 +973,7 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
             }
           }
         }
+        if (!P) n_cov += ballot_count(hqv);
         n_dJr += ballot_count(state == 2);
         n_dJo += ballot_count(inV && !expl);
         n_rem += ballot_count(inU && (inV || expl));
@@ -1034,6 +1042,10 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
   }
 
   if (lane == 0) {
+    if (!P) {
+      atomicAdd(&s_acc[0], n_cov);
+      atomicAdd(&s_acc[1], n_cov);
+    }
     atomicAdd(&s_acc[2], n_dJr);
     atomicAdd(&s_acc[3], n_dJo);
     atomicAdd(&s_acc[4], n_rem);
@@ -1057,7 +1069,7 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
 }
 
 // One workgroup per successor of one parent.
-template <int NT, bool VP, bool GAIN, bool HQ, bool G>
+template <int NT, bool VP, bool GAIN, bool HQ, bool G, bool P>
 __global__ void __launch_bounds__(NT)
     k_eval(SceneDev S, Parent par, const int2* __restrict__ cands, int n,
            int* __restrict__ out_cost, int* __restrict__ out_status, int* __restrict__ out_comps,
@@ -1068,8 +1080,8 @@ __global__ void __launch_bounds__(NT)
   __shared__ float4 s_pl[kLdsPlanes];
   const int s = blockIdx.x;
   if (s >= n) return;
-  eval_successor<NT, false, VP, GAIN, HQ, G>(S, par, cands[s], s, out_cost, out_status,
-                                             out_comps, out_gain, smem, s_bb, s_acc, s_pl);
+  eval_successor<NT, false, VP, GAIN, HQ, G, P>(S, par, cands[s], s, out_cost, out_status,
+                                                out_comps, out_gain, smem, s_bb, s_acc, s_pl);
 }
 
 // Persistent workgroups over a work queue of (parent slot, mesh, pose) items that
@@ -1112,7 +1124,8 @@ __global__ void __launch_bounds__(NT, 4)  // at least 4 waves per SIMD: <= 128 V
     par.has_parent = pd.has_parent;
     par.goal = pd.goal;
     const int scene = __builtin_amdgcn_readfirstlane(pd.scene);
-    eval_successor<NT, true, VP, false, HQ, true>(scenes[scene], par, make_int2(w.y, w.z), it,
+    eval_successor<NT, true, VP, false, HQ, true, true>(scenes[scene], par, make_int2(w.y, w.z),
+                                                        it,
                                             out_cost, out_status, out_comps, nullptr, smem, s_bb,
                                             s_acc, s_pl);
   }
@@ -1546,58 +1559,66 @@ static hipError_t allow_lds(K kernel, size_t lds) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-template <int NT, bool VP, bool GAIN, bool HQ, bool G>
+template <int NT, bool VP, bool GAIN, bool HQ, bool G, bool P>
 static hipError_t launch_eval_g(const SceneDev& S, const Parent& par, const int2* cands, int n,
                                 int* cost, int* status, int* comps, int* gain, size_t lds,
                                 hipStream_t s) {
-  hipError_t e = allow_lds(&k_eval<NT, VP, GAIN, HQ, G>, lds);
+  hipError_t e = allow_lds(&k_eval<NT, VP, GAIN, HQ, G, P>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_eval<NT, VP, GAIN, HQ, G>), dim3(n), dim3(NT), lds, s, S, par, cands, n,
-                     cost, status, comps, gain);
+  hipLaunchKernelGGL((k_eval<NT, VP, GAIN, HQ, G, P>), dim3(n), dim3(NT), lds, s, S, par, cands,
+                     n, cost, status, comps, gain);
   return hipGetLastError();
 }
 
-template <int NT, bool VP, bool HQ, bool G>
+template <int NT, bool VP, bool HQ, bool G, bool P>
 static hipError_t launch_eval_t(const SceneDev& S, const Parent& par, const int2* cands, int n,
                                 int* cost, int* status, int* comps, int* gain, size_t lds,
                                 hipStream_t s) {
-  return gain ? launch_eval_g<NT, VP, true, HQ, G>(S, par, cands, n, cost, status, comps, gain,
-                                                   lds, s)
-              : launch_eval_g<NT, VP, false, HQ, G>(S, par, cands, n, cost, status, comps, gain,
-                                                    lds, s);
+  return gain ? launch_eval_g<NT, VP, true, HQ, G, P>(S, par, cands, n, cost, status, comps, gain,
+                                                      lds, s)
+              : launch_eval_g<NT, VP, false, HQ, G, P>(S, par, cands, n, cost, status, comps,
+                                                       gain, lds, s);
 }
 
-template <bool VP, bool HQ, bool G>
+template <bool VP, bool HQ, bool G, bool P>
 static hipError_t launch_eval_vp(int threads, const SceneDev& S, const Parent& par,
                                  const int2* cands, int n, int* cost, int* status, int* comps,
                                  int* gain, size_t lds, hipStream_t s) {
   switch (threads) {
     case 64:
-      return launch_eval_t<64, VP, HQ, G>(S, par, cands, n, cost, status, comps, gain, lds, s);
+      return launch_eval_t<64, VP, HQ, G, P>(S, par, cands, n, cost, status, comps, gain, lds, s);
     case 128:
-      return launch_eval_t<128, VP, HQ, G>(S, par, cands, n, cost, status, comps, gain, lds, s);
+      return launch_eval_t<128, VP, HQ, G, P>(S, par, cands, n, cost, status, comps, gain, lds,
+                                              s);
     case 512:
-      return launch_eval_t<512, VP, HQ, G>(S, par, cands, n, cost, status, comps, gain, lds, s);
+      return launch_eval_t<512, VP, HQ, G, P>(S, par, cands, n, cost, status, comps, gain, lds,
+                                              s);
     case 1024:
-      return launch_eval_t<1024, VP, HQ, G>(S, par, cands, n, cost, status, comps, gain, lds, s);
+      return launch_eval_t<1024, VP, HQ, G, P>(S, par, cands, n, cost, status, comps, gain, lds,
+                                               s);
     default:
-      return launch_eval_t<256, VP, HQ, G>(S, par, cands, n, cost, status, comps, gain, lds, s);
+      return launch_eval_t<256, VP, HQ, G, P>(S, par, cands, n, cost, status, comps, gain, lds,
+                                              s);
   }
 }
 
-// Hash-mode scenes take the instantiation with both the hash and the goal-level
-// code; window-scan scenes the one with the goal-level code only at the goal level.
+// Hash-mode scenes and goal-level parents take instantiations with the goal-level
+// and parent code; below the goal, the root takes the one without a parent.
 template <bool VP>
 static hipError_t launch_eval_hq(int threads, const SceneDev& S, const Parent& par,
                                  const int2* cands, int n, int* cost, int* status, int* comps,
                                  int* gain, size_t lds, hipStream_t s) {
   if (S.ep.radius_mode == 1)
-    return launch_eval_vp<VP, true, true>(threads, S, par, cands, n, cost, status, comps, gain,
-                                          lds, s);
-  return par.goal ? launch_eval_vp<VP, false, true>(threads, S, par, cands, n, cost, status,
-                                                    comps, gain, lds, s)
-                  : launch_eval_vp<VP, false, false>(threads, S, par, cands, n, cost, status,
-                                                     comps, gain, lds, s);
+    return launch_eval_vp<VP, true, true, true>(threads, S, par, cands, n, cost, status, comps,
+                                                gain, lds, s);
+  if (par.goal)
+    return launch_eval_vp<VP, false, true, true>(threads, S, par, cands, n, cost, status, comps,
+                                                 gain, lds, s);
+  return par.has_parent ? launch_eval_vp<VP, false, false, true>(threads, S, par, cands, n, cost,
+                                                                 status, comps, gain, lds, s)
+                        : launch_eval_vp<VP, false, false, false>(threads, S, par, cands, n,
+                                                                  cost, status, comps, gain,
+                                                                  lds, s);
 }
 
 hipError_t launch_eval(int threads, const SceneDev& S, const Parent& par, const int2* cands,
