@@ -410,7 +410,17 @@ __device__ __forceinline__ bool in_volume_at(const float4 lo, const float4 hi,
   if (o.x < lo.x - 1e-5f || o.y < lo.y - 1e-5f || o.z < lo.z - 1e-5f || o.x > hi.x + 1e-5f ||
       o.y > hi.y + 1e-5f || o.z > hi.z + 1e-5f)
     return false;
-  for (int f = 0; f < n_planes; ++f)
+  int f = 0;
+  for (; f + 8 <= n_planes; f += 8)  // eight planes per test: the answer is their OR
+    if (plane_out(planes[f], o) | plane_out(planes[f + 1], o) | plane_out(planes[f + 2], o) |
+        plane_out(planes[f + 3], o) | plane_out(planes[f + 4], o) | plane_out(planes[f + 5], o) |
+        plane_out(planes[f + 6], o) | plane_out(planes[f + 7], o))
+      return false;
+  for (; f + 4 <= n_planes; f += 4)
+    if (plane_out(planes[f], o) | plane_out(planes[f + 1], o) | plane_out(planes[f + 2], o) |
+        plane_out(planes[f + 3], o))
+      return false;
+  for (; f < n_planes; ++f)
     if (plane_out(planes[f], o)) return false;
   return true;
 }
