@@ -301,14 +301,21 @@ __device__ __forceinline__ void raster_tri(int x0, int y0, int x1, int y1, int x
 // triangles raster_tri can emit for.
 __device__ __forceinline__ bool tri_candidate(int x0, int y0, int x1, int y1, int x2, int y2,
                                               int c0, int c1, int r0, int r1) {
+  // evaluated without early exits: the scan runs it for every triangle
   const int xmin = min(x0, min(x1, x2)), xmax = max(x0, max(x1, x2));
   const int ymin = min(y0, min(y1, y2)), ymax = max(y0, max(y1, y2));
-  if (max(c0, ceil256(xmin)) > min(c1, floor256(xmax))) return false;
-  if (max(r0, ceil256(ymin)) > min(r1, floor256(ymax))) return false;
-  if (xmax - xmin < 16384 && ymax - ymin < 16384)  // products below 2^28: int32 is exact
-    return (x1 - x0) * (y2 - y0) - (y1 - y0) * (x2 - x0) < 0;
-  const long long area = (long long)(x1 - x0) * (y2 - y0) - (long long)(y1 - y0) * (x2 - x0);
-  return area < 0;
+  const bool inb = (max(c0, ceil256(xmin)) <= min(c1, floor256(xmax))) &
+                   (max(r0, ceil256(ymin)) <= min(r1, floor256(ymax)));
+  const bool small = (xmax - xmin < 16384) & (ymax - ymin < 16384);
+  // wrapping 32-bit products: exact when small (products below 2^28)
+  const unsigned a32 = (unsigned)(x1 - x0) * (unsigned)(y2 - y0) -
+                       (unsigned)(y1 - y0) * (unsigned)(x2 - x0);
+  bool front = (int)a32 < 0;
+  if (!small) {
+    const long long area = (long long)(x1 - x0) * (y2 - y0) - (long long)(y1 - y0) * (x2 - x0);
+    front = area < 0;
+  }
+  return inb & front;
 }
 
 // ---------------------------------------------------------------------------
@@ -964,21 +971,37 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
               const int wja = max(t0, jj - rv), wjb = min(t1, jj + rv);
               const int wia = max(ca, ii - ru), wib = min(cb, ii + ru);
               const float zlo = zo - cam.delta, zhi = zo + cam.delta;
-              // one flat walk over the clipped window, stopping at the first hit
+              // one flat walk over the clipped window, two pixels per step, stopping
+              // after the first hit; the depth pre-test also skips +inf (no point)
               const int n = (wib - wia + 1) * (wjb - wja + 1);
               int iq = wia, jq = wja;
               int row = (wja - t0) * tw - ca;  // tile index of (0, jq)
-              for (int w = 0; w < n && !expl; ++w) {
-                const float zt = __uint_as_float(tile[row + iq]);
-                if (zt >= zlo && zt <= zhi) {  // also skips +inf (no point)
-                  const float3 q = backproject(cam, iq, jq, zt);
-                  const float ex = q.x - p.x, ey = q.y - p.y, ez = q.z - p.z;
-                  expl = ex * ex + ey * ey + ez * ez <= delta2;
+              for (int w = 0; w < n && !expl; w += 2) {
+                const bool wrap = iq == wib;  // (ib, jb): the pixel after (iq, jq)
+                const int rowb = row + (wrap ? tw : 0), jb = jq + (wrap ? 1 : 0);
+                const int ib = wrap ? wia : iq + 1;
+                const bool two = w + 1 < n;
+                const float za = __uint_as_float(tile[row + iq]);
+                const float zb = two ? __uint_as_float(tile[rowb + ib]) : __builtin_inff();
+                const bool ina = za >= zlo && za <= zhi, inb = zb >= zlo && zb <= zhi;
+                if (ina | inb) {
+                  bool h = false;
+                  if (ina) {
+                    const float3 q = backproject(cam, iq, jq, za);
+                    const float ex = q.x - p.x, ey = q.y - p.y, ez = q.z - p.z;
+                    h = ex * ex + ey * ey + ez * ez <= delta2;
+                  }
+                  if (inb) {
+                    const float3 q = backproject(cam, ib, jb, zb);
+                    const float ex = q.x - p.x, ey = q.y - p.y, ez = q.z - p.z;
+                    h = h || ex * ex + ey * ey + ez * ez <= delta2;
+                  }
+                  expl = h;
                 }
-                const bool wrap = iq == wib;
-                row += wrap ? tw : 0;
-                jq += wrap ? 1 : 0;
-                iq = wrap ? wia : iq + 1;
+                const bool wrap2 = ib == wib;
+                row = rowb + (wrap2 ? tw : 0);
+                jq = jb + (wrap2 ? 1 : 0);
+                iq = wrap2 ? wia : ib + 1;
               }
             }
           }
