@@ -20,7 +20,7 @@ struct perch_batch {
   hipStream_t capture = nullptr;  // private stream used only to capture graphs
   DevBuf scenes, parents, slot_depth, slot_ubits, slot_ucount, counter;
   int n_parents = 0;
-  int hash = 0;  // some scene of the table answers dJ_r by the voxel hash
+  int flags = 0;  // kBatchHash | kBatchGoal | kBatchParent over the current tables
   size_t npx_max = 0;
   int threads = 512;
   int tile_px = 0;  // 0 = sized automatically (auto_tile_px)
@@ -32,7 +32,7 @@ struct perch_batch {
   const void* g_items = nullptr;
   int g_n = -1;
   const void *g_cost = nullptr, *g_status = nullptr, *g_comps = nullptr;
-  int g_threads = 0, g_tile = 0, g_grid = 0, g_parents = -1, g_hash = -1;
+  int g_threads = 0, g_tile = 0, g_grid = 0, g_parents = -1, g_flags = -1;
   const void* g_ptab = nullptr;
 
   int max_nv() const {
@@ -131,6 +131,7 @@ perch_status perch_batch_set_parents(perch_batch* b, const perch_parent* parents
   HIP_TRY(b->slot_ucount.ensure(std::max<size_t>(1, n) * sizeof(int)));
   HIP_TRY(b->parents.ensure(std::max<size_t>(1, n) * sizeof(ParentDev)));
   std::vector<ParentDev> pd(std::max(1, n));
+  int flags = 0;
   for (int k = 0; k < n; ++k) {
     const perch_parent& p = parents[k];
     perch_ctx* c = b->ctxs[p.ctx];
@@ -145,18 +146,18 @@ perch_status perch_batch_set_parents(perch_batch* b, const perch_parent* parents
     pd[k].ucount = ucount;
     pd[k].has_parent = p.j > 0;
     pd[k].goal = goal;
+    flags |= (goal ? kBatchGoal : 0) | (p.j > 0 ? kBatchParent : 0);
     pd[k].scene = p.ctx;
     pd[k].pad = 0;
   }
   std::vector<SceneDev> sd(b->ctxs.size());
   const int max_nv = b->max_nv();
-  int hash = 0;
   for (size_t k = 0; k < b->ctxs.size(); ++k) {
     sd[k] = b->ctxs[k]->scene_dev();
     sd[k].ep.tile_px = b->tile();
     sd[k].ep.max_nv = max_nv;
     sd[k].ep.vpack = vertex_cache_packed(max_nv);
-    hash |= sd[k].ep.radius_mode == 1 ? 1 : 0;
+    flags |= sd[k].ep.radius_mode == 1 ? kBatchHash : 0;
   }
   HIP_TRY(hipMemcpyAsync(b->parents.p, pd.data(), sizeof(ParentDev) * pd.size(),
                          hipMemcpyHostToDevice, b->stream));
@@ -165,7 +166,7 @@ perch_status perch_batch_set_parents(perch_batch* b, const perch_parent* parents
   // the host vectors die here: the copies must complete first
   HIP_TRY(hipStreamSynchronize(b->stream));
   b->n_parents = n;
-  b->hash = hash;
+  b->flags = flags;
   return PERCH_OK;
 }
 
@@ -183,7 +184,7 @@ perch_status perch_batch_eval(perch_batch* b, const perch_work* items_dev, int32
     int dev = 0, cus = 0, per_cu = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    HIP_TRY(prepare_eval_batch(b->threads, vertex_cache_packed(b->max_nv()), b->hash, lds,
+    HIP_TRY(prepare_eval_batch(b->threads, vertex_cache_packed(b->max_nv()), b->flags, lds,
                                &per_cu));
     if (grid <= 0) grid = std::max(1, cus * std::max(1, per_cu));
   }
@@ -191,7 +192,7 @@ perch_status perch_batch_eval(perch_batch* b, const perch_work* items_dev, int32
   const SceneDev* scenes = b->scenes.as<SceneDev>();
   const ParentDev* parents = b->parents.as<ParentDev>();
   if (!b->use_graph) {
-    HIP_TRY(launch_eval_batch(b->threads, vertex_cache_packed(b->max_nv()), b->hash, scenes,
+    HIP_TRY(launch_eval_batch(b->threads, vertex_cache_packed(b->max_nv()), b->flags, scenes,
                               parents, b->n_parents, items, n, b->counter.as<int>(), cost_dev,
                               status_dev, comps_dev, lds, grid, b->stream));
     return PERCH_OK;
@@ -200,11 +201,11 @@ perch_status perch_batch_eval(perch_batch* b, const perch_work* items_dev, int32
                     b->g_status == status_dev && b->g_comps == comps_dev &&
                     b->g_threads == b->threads && b->g_tile == b->tile() && b->g_grid == grid &&
                     b->g_parents == b->n_parents && b->g_ptab == b->parents.p &&
-                    b->g_hash == b->hash;
+                    b->g_flags == b->flags;
   if (!same) {
     b->drop_graph();
     HIP_TRY(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
-    hipError_t e = launch_eval_batch(b->threads, vertex_cache_packed(b->max_nv()), b->hash,
+    hipError_t e = launch_eval_batch(b->threads, vertex_cache_packed(b->max_nv()), b->flags,
                                      scenes, parents, b->n_parents, items, n,
                                      b->counter.as<int>(), cost_dev, status_dev, comps_dev, lds,
                                      grid, b->capture);
@@ -227,7 +228,7 @@ perch_status perch_batch_eval(perch_batch* b, const perch_work* items_dev, int32
     b->g_grid = grid;
     b->g_parents = b->n_parents;
     b->g_ptab = b->parents.p;
-    b->g_hash = b->hash;
+    b->g_flags = b->flags;
   }
   HIP_TRY(hipGraphLaunch(b->exec, b->stream));
   return PERCH_OK;

@@ -115,13 +115,16 @@ hipError_t launch_eval(int threads, const SceneDev& S, const Parent& par, const 
 // vbits |= observed pixels inside the union of the j objects' volumes
 void launch_parent_v(const Cam& cam, const Meshes& M, const float4* poses, const float* obs,
                      const int* par_mesh_pose, int j, unsigned* vbits, hipStream_t s);
+// What a batch's tables hold (flags of prepare/launch_eval_batch): some scene
+// answers dJ_r by the voxel hash (radius mode 1), some parent is at its scene's goal
+// level, some parent has a parent (is below the root).
+constexpr int kBatchHash = 1, kBatchGoal = 2, kBatchParent = 4;
 // Raises the kernel's LDS limit and reports resident workgroups per CU (call
-// before launch_eval_batch, outside any graph capture).  hash != 0: some scene of
-// the table answers dJ_r by the voxel hash (radius mode 1).
-hipError_t prepare_eval_batch(int threads, int vpack, int hash, size_t lds_bytes,
+// before launch_eval_batch, outside any graph capture).
+hipError_t prepare_eval_batch(int threads, int vpack, int flags, size_t lds_bytes,
                               int* blocks_per_cu);
 // grid = number of persistent workgroups (clamped to n)
-hipError_t launch_eval_batch(int threads, int vpack, int hash, const SceneDev* scenes,
+hipError_t launch_eval_batch(int threads, int vpack, int flags, const SceneDev* scenes,
                              const ParentDev* parents, int n_parents, const int4* items, int n,
                              int* counter, int* cost, int* status, int* comps, size_t lds_bytes,
                              int grid, hipStream_t s);

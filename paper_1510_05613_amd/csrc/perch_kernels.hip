@@ -1120,7 +1120,7 @@ __global__ void __launch_bounds__(NT)
 // Persistent workgroups over a work queue of (parent slot, mesh, pose) items that
 // may belong to different scenes: each workgroup takes the next item from an
 // atomic counter until the queue is empty, so uneven meshes balance across CUs.
-template <int NT, bool VP, bool HQ>
+template <int NT, bool VP, bool HQ, bool G, bool P>
 __global__ void __launch_bounds__(NT, 4)  // at least 4 waves per SIMD: <= 128 VGPRs
     k_eval_batch(const SceneDev* __restrict__ scenes, const ParentDev* __restrict__ parents,
                  int n_parents, const int4* __restrict__ items, int n, int* counter,
@@ -1157,7 +1157,7 @@ __global__ void __launch_bounds__(NT, 4)  // at least 4 waves per SIMD: <= 128 V
     par.has_parent = pd.has_parent;
     par.goal = pd.goal;
     const int scene = __builtin_amdgcn_readfirstlane(pd.scene);
-    eval_successor<NT, true, VP, false, HQ, true, true>(scenes[scene], par, make_int2(w.y, w.z),
+    eval_successor<NT, true, VP, false, HQ, G, P>(scenes[scene], par, make_int2(w.y, w.z),
                                                         it,
                                             out_cost, out_status, out_comps, nullptr, smem, s_bb,
                                             s_acc, s_pl);
@@ -1664,87 +1664,109 @@ hipError_t launch_eval(int threads, const SceneDev& S, const Parent& par, const 
                                             gain, lds_bytes, s);
 }
 
-template <int NT, bool VP, bool HQ>
+template <int NT, bool VP, bool HQ, bool G, bool P>
 static hipError_t prepare_eval_batch_t(size_t lds, int* per_cu) {
-  hipError_t e = allow_lds(&k_eval_batch<NT, VP, HQ>, lds);
+  hipError_t e = allow_lds(&k_eval_batch<NT, VP, HQ, G, P>, lds);
   if (e != hipSuccess) return e;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_eval_batch<NT, VP, HQ>, NT, lds);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_eval_batch<NT, VP, HQ, G, P>, NT,
+                                                      lds);
 }
 
-template <bool VP, bool HQ>
+template <bool VP, bool HQ, bool G, bool P>
 static hipError_t prepare_eval_batch_vp(int threads, size_t lds, int* per_cu) {
   switch (threads) {
     case 64:
-      return prepare_eval_batch_t<64, VP, HQ>(lds, per_cu);
+      return prepare_eval_batch_t<64, VP, HQ, G, P>(lds, per_cu);
     case 128:
-      return prepare_eval_batch_t<128, VP, HQ>(lds, per_cu);
+      return prepare_eval_batch_t<128, VP, HQ, G, P>(lds, per_cu);
     case 512:
-      return prepare_eval_batch_t<512, VP, HQ>(lds, per_cu);
+      return prepare_eval_batch_t<512, VP, HQ, G, P>(lds, per_cu);
     default:
-      return prepare_eval_batch_t<256, VP, HQ>(lds, per_cu);
+      return prepare_eval_batch_t<256, VP, HQ, G, P>(lds, per_cu);
   }
 }
 
-hipError_t prepare_eval_batch(int threads, int vpack, int hash, size_t lds_bytes,
-                              int* blocks_per_cu) {
-  if (hash)
-    return vpack ? prepare_eval_batch_vp<true, true>(threads, lds_bytes, blocks_per_cu)
-                 : prepare_eval_batch_vp<false, true>(threads, lds_bytes, blocks_per_cu);
-  return vpack ? prepare_eval_batch_vp<true, false>(threads, lds_bytes, blocks_per_cu)
-               : prepare_eval_batch_vp<false, false>(threads, lds_bytes, blocks_per_cu);
+template <bool VP>
+static hipError_t prepare_eval_batch_f(int threads, int flags, size_t lds, int* per_cu) {
+  if (flags & kBatchHash) return prepare_eval_batch_vp<VP, true, true, true>(threads, lds, per_cu);
+  if (flags & kBatchGoal) return prepare_eval_batch_vp<VP, false, true, true>(threads, lds, per_cu);
+  if (flags & kBatchParent)
+    return prepare_eval_batch_vp<VP, false, false, true>(threads, lds, per_cu);
+  return prepare_eval_batch_vp<VP, false, false, false>(threads, lds, per_cu);
 }
 
-template <int NT, bool VP, bool HQ>
+hipError_t prepare_eval_batch(int threads, int vpack, int flags, size_t lds_bytes,
+                              int* blocks_per_cu) {
+  return vpack ? prepare_eval_batch_f<true>(threads, flags, lds_bytes, blocks_per_cu)
+               : prepare_eval_batch_f<false>(threads, flags, lds_bytes, blocks_per_cu);
+}
+
+template <int NT, bool VP, bool HQ, bool G, bool P>
 static hipError_t launch_eval_batch_t(const SceneDev* scenes, const ParentDev* parents,
                                       int n_parents, const int4* items, int n, int* counter,
                                       int* cost, int* status, int* comps, size_t lds, int grid,
                                       hipStream_t s) {
   grid = std::max(1, std::min(grid, n));
-  hipLaunchKernelGGL((k_eval_batch<NT, VP, HQ>), dim3(grid), dim3(NT), lds, s, scenes, parents,
-                     n_parents, items, n, counter, cost, status, comps);
+  hipLaunchKernelGGL((k_eval_batch<NT, VP, HQ, G, P>), dim3(grid), dim3(NT), lds, s, scenes,
+                     parents, n_parents, items, n, counter, cost, status, comps);
   return hipGetLastError();
 }
 
-template <bool VP, bool HQ>
+template <bool VP, bool HQ, bool G, bool P>
 static hipError_t launch_eval_batch_vp(int threads, const SceneDev* scenes,
                                        const ParentDev* parents, int n_parents, const int4* items,
                                        int n, int* counter, int* cost, int* status, int* comps,
                                        size_t lds, int grid, hipStream_t s) {
   switch (threads) {
     case 64:
-      return launch_eval_batch_t<64, VP, HQ>(scenes, parents, n_parents, items, n, counter, cost,
-                                             status, comps, lds, grid, s);
+      return launch_eval_batch_t<64, VP, HQ, G, P>(scenes, parents, n_parents, items, n, counter,
+                                                   cost, status, comps, lds, grid, s);
     case 128:
-      return launch_eval_batch_t<128, VP, HQ>(scenes, parents, n_parents, items, n, counter,
-                                              cost, status, comps, lds, grid, s);
+      return launch_eval_batch_t<128, VP, HQ, G, P>(scenes, parents, n_parents, items, n,
+                                                    counter, cost, status, comps, lds, grid, s);
     case 512:
-      return launch_eval_batch_t<512, VP, HQ>(scenes, parents, n_parents, items, n, counter,
-                                              cost, status, comps, lds, grid, s);
+      return launch_eval_batch_t<512, VP, HQ, G, P>(scenes, parents, n_parents, items, n,
+                                                    counter, cost, status, comps, lds, grid, s);
     default:
-      return launch_eval_batch_t<256, VP, HQ>(scenes, parents, n_parents, items, n, counter,
-                                              cost, status, comps, lds, grid, s);
+      return launch_eval_batch_t<256, VP, HQ, G, P>(scenes, parents, n_parents, items, n,
+                                                    counter, cost, status, comps, lds, grid, s);
   }
 }
 
-hipError_t launch_eval_batch(int threads, int vpack, int hash, const SceneDev* scenes,
+// The batch's flags (over its whole parent table) pick the leanest instantiation
+// that covers every item, as for single-parent launches.
+template <bool VP>
+static hipError_t launch_eval_batch_f(int threads, int flags, const SceneDev* scenes,
+                                      const ParentDev* parents, int n_parents, const int4* items,
+                                      int n, int* counter, int* cost, int* status, int* comps,
+                                      size_t lds, int grid, hipStream_t s) {
+  if (flags & kBatchHash)
+    return launch_eval_batch_vp<VP, true, true, true>(threads, scenes, parents, n_parents, items,
+                                                      n, counter, cost, status, comps, lds, grid,
+                                                      s);
+  if (flags & kBatchGoal)
+    return launch_eval_batch_vp<VP, false, true, true>(threads, scenes, parents, n_parents, items,
+                                                       n, counter, cost, status, comps, lds,
+                                                       grid, s);
+  if (flags & kBatchParent)
+    return launch_eval_batch_vp<VP, false, false, true>(threads, scenes, parents, n_parents,
+                                                        items, n, counter, cost, status, comps,
+                                                        lds, grid, s);
+  return launch_eval_batch_vp<VP, false, false, false>(threads, scenes, parents, n_parents, items,
+                                                       n, counter, cost, status, comps, lds, grid,
+                                                       s);
+}
+
+hipError_t launch_eval_batch(int threads, int vpack, int flags, const SceneDev* scenes,
                              const ParentDev* parents, int n_parents, const int4* items, int n,
                              int* counter, int* cost, int* status, int* comps, size_t lds_bytes,
                              int grid, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   launch_fill_i32(counter, 0, 1, s);  // a fill kernel (not a memset): safe in captured graphs
-  if (hash)
-    return vpack ? launch_eval_batch_vp<true, true>(threads, scenes, parents, n_parents, items, n,
-                                                    counter, cost, status, comps, lds_bytes,
-                                                    grid, s)
-                 : launch_eval_batch_vp<false, true>(threads, scenes, parents, n_parents, items,
-                                                     n, counter, cost, status, comps, lds_bytes,
-                                                     grid, s);
-  return vpack ? launch_eval_batch_vp<true, false>(threads, scenes, parents, n_parents, items, n,
-                                                   counter, cost, status, comps, lds_bytes, grid,
-                                                   s)
-               : launch_eval_batch_vp<false, false>(threads, scenes, parents, n_parents, items, n,
-                                                    counter, cost, status, comps, lds_bytes,
-                                                    grid, s);
+  return vpack ? launch_eval_batch_f<true>(threads, flags, scenes, parents, n_parents, items, n,
+                                           counter, cost, status, comps, lds_bytes, grid, s)
+               : launch_eval_batch_f<false>(threads, flags, scenes, parents, n_parents, items, n,
+                                            counter, cost, status, comps, lds_bytes, grid, s);
 }
 
 void launch_obs_normals(const Cam& cam, const float* obs, float radius, float4* pn,

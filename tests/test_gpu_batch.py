@@ -143,6 +143,40 @@ def test_batch_with_hash_mode_scenes_matches(mixed):
         b.close()
 
 
+def test_batch_level_tables_match(mixed):
+    """Parent tables that hold only roots, or only parents between the root and the
+    goal level, run the batch's leaner kernels (no parent code, no goal-level code);
+    results equal per-parent evaluation, captured and replayed."""
+    scs, ctxs = mixed
+    rng = np.random.default_rng(9)
+    allp = []
+    for ci, sc in enumerate(scs):
+        allp += _gt_parents(sc, ci)
+    roots = [p for p in allp if len(p[1]) == 0]
+    mids = [p for p in allp if 0 < len(p[1]) < scs[p[0]].K - 1]
+    assert roots and mids
+    for parents in (roots, mids, roots):
+        items = np.ascontiguousarray(_items_for(parents, scs, rng, 150))
+        ref = _reference(ctxs, parents, items)
+        n = len(items)
+        dev_items = torch.as_tensor(items).cuda()
+        cost = torch.empty(n, dtype=torch.int32, device="cuda")
+        st = torch.empty(n, dtype=torch.int32, device="cuda")
+        comps = torch.empty((n, 5), dtype=torch.int32, device="cuda")
+        b = perch.Batch(ctxs)
+        try:
+            b.set_parents(parents)
+            for _ in range(2):  # capture, then replay
+                cost.fill_(-7)
+                b.eval(dev_items, cost, st, comps)
+                torch.cuda.synchronize()
+                got = (st.cpu().numpy(), cost.cpu().numpy(), comps.cpu().numpy())
+                for a, g in zip(ref, got):
+                    assert np.array_equal(a, g), len(parents)
+        finally:
+            b.close()
+
+
 def test_batch_rejects_bad_parent_slots(mixed):
     scs, ctxs = mixed
     b = perch.Batch(ctxs[:1])
