@@ -724,7 +724,6 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
   const bool pl_lds = fr.y <= kLdsPlanes;
   if (pl_lds)
     for (int f = tid; f < fr.y; f += NT) s_pl[f] = M.planes[fr.x + f];
-  const float4* vplanes = pl_lds ? s_pl : M.planes + fr.x;
   __syncthreads();
 
   // ---- vertex stage: footprint bounding box, then the vertex cache ----
@@ -962,7 +961,10 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
             }
           }
           if (hp) {
-            inV = in_volume_at(vlo, vhi, vplanes, fr.y, apply_obj_map(om, p));
+            // separate calls, so that the staged copy is read as LDS (not flat)
+            const float3 o = apply_obj_map(om, p);
+            inV = pl_lds ? in_volume_at(vlo, vhi, s_pl, fr.y, o)
+                         : in_volume_at(vlo, vhi, M.planes + fr.x, fr.y, o);
             inU = goal && ((par.ubits[pix >> 5] >> (pix & 31)) & 1u);
             expl = same;
             if ((inV || inU) && !expl) {
