@@ -107,17 +107,17 @@ perch_status materialise_into(perch_ctx* c, const perch_object* parent, int j, b
   const Meshes M = c->dev_meshes();
   const float4* poses = c->poses.as<float4>();
   launch_fill_u32(depth, kInfBits, npx, st);
-  for (int k = 0; k < j; ++k)
-    launch_render_object(c->cam, M, poses, parent[k].mesh_id, parent[k].pose_idx,
-                         (int)c->meshes[parent[k].mesh_id].tris.size() / 3, depth, st);
+  int mp[2 * kMaxObjects];
+  int max_tris = 0;
+  for (int k = 0; k < j; ++k) {
+    mp[2 * k] = parent[k].mesh_id;
+    mp[2 * k + 1] = parent[k].pose_idx;
+    max_tris = std::max(max_tris, (int)c->meshes[parent[k].mesh_id].tris.size() / 3);
+  }
+  launch_render_objects(c->cam, M, poses, mp, j, max_tris, depth, st);
   if (goal) {
     launch_fill_u32(ubits, 0u, (npx + 31) / 32, st);
     launch_fill_i32(ucount, 0, 1, st);
-    int mp[2 * kMaxObjects];
-    for (int k = 0; k < j; ++k) {
-      mp[2 * k] = parent[k].mesh_id;
-      mp[2 * k + 1] = parent[k].pose_idx;
-    }
     launch_parent_u(c->cam, M, poses, c->obs.as<float>(), mp, j, depth, ubits, ucount, c->ep,
                     st);
   }

@@ -102,6 +102,11 @@ void launch_hash_scatter(const Cam& cam, const float* depth, const unsigned long
                          hipStream_t s);
 void launch_render_object(const Cam& cam, const Meshes& M, const float4* poses, int mesh,
                           int pose, int n_tris, unsigned* depth_bits, hipStream_t s);
+// The composite of j objects (mesh_pose: host, 2 j ints; j <= kMaxObjects) in one
+// launch; max_tris = the largest triangle count among them.
+void launch_render_objects(const Cam& cam, const Meshes& M, const float4* poses,
+                           const int* mesh_pose, int j, int max_tris, unsigned* depth_bits,
+                           hipStream_t s);
 void launch_parent_u(const Cam& cam, const Meshes& M, const float4* poses, const float* obs,
                      const int* par_mesh_pose, int j, const unsigned* depth_bits,
                      unsigned* ubits, int* ucount, const EvalParams& ep, hipStream_t s);

@@ -570,10 +570,15 @@ __global__ void k_hash_scatter(Cam cam, const float* depth, const unsigned long 
 // full-frame render of one object (parent composites, perch_render)
 // ---------------------------------------------------------------------------
 
-__global__ void k_render_object(Cam cam, Meshes M, const float4* poses, int mesh, int pose,
-                                unsigned* depth) {
+struct ParentObjs {
+  int2 o[kMaxObjects];
+};
+
+// One triangle of one object per thread, into a full-frame depth image.
+__device__ __forceinline__ void render_triangle(const Cam& cam, const Meshes& M,
+                                                const float4* poses, int mesh, int pose, int t,
+                                                unsigned* depth) {
   const int4 rg = M.range[mesh];
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= rg.w) return;
   const float4 pz = poses[pose];
   const int4 tr = M.tris[rg.z + t];
@@ -595,14 +600,27 @@ __global__ void k_render_object(Cam cam, Meshes M, const float4* poses, int mesh
              });
 }
 
+__global__ void k_render_object(Cam cam, Meshes M, const float4* poses, int mesh, int pose,
+                                unsigned* depth) {
+  render_triangle(cam, M, poses, mesh, pose, blockIdx.x * blockDim.x + threadIdx.x, depth);
+}
+
+// All j objects of a parent in one launch (blockIdx.y = object): the composite is
+// the same minimum as j single-object launches, without their launch latency.
+__global__ void k_render_objects(Cam cam, Meshes M, const float4* poses, ParentObjs po, int j,
+                                 unsigned* depth) {
+  const int k = blockIdx.y;
+  if (k >= j) return;
+  render_triangle(cam, M, poses, po.o[k].x, po.o[k].y, blockIdx.x * blockDim.x + threadIdx.x,
+                  depth);
+}
+
 // ---------------------------------------------------------------------------
 // goal-level parent set U: observed points outside every parent volume and
 // unexplained by the parent composite R_{K-1}
 // ---------------------------------------------------------------------------
 
-struct ParentObjs {
-  int2 o[kMaxObjects];
-};
+
 
 __global__ void k_parent_u(Cam cam, Meshes M, const float4* poses, const float* obs,
                            ParentObjs po, int j, const unsigned* pdepth, unsigned* ubits,
@@ -1562,6 +1580,17 @@ void launch_render_object(const Cam& cam, const Meshes& M, const float4* poses, 
   if (n_tris <= 0) return;
   hipLaunchKernelGGL(k_render_object, dim3((n_tris + 127) / 128), dim3(128), 0, s, cam, M,
                      poses, mesh, pose, depth_bits);
+}
+
+void launch_render_objects(const Cam& cam, const Meshes& M, const float4* poses,
+                           const int* mesh_pose, int j, int max_tris, unsigned* depth_bits,
+                           hipStream_t s) {
+  if (j <= 0 || max_tris <= 0) return;
+  ParentObjs po;
+  for (int a = 0; a < kMaxObjects; ++a)
+    po.o[a] = a < j ? make_int2(mesh_pose[2 * a], mesh_pose[2 * a + 1]) : make_int2(0, 0);
+  hipLaunchKernelGGL(k_render_objects, dim3((max_tris + 127) / 128, j), dim3(128), 0, s, cam, M,
+                     poses, po, j, depth_bits);
 }
 
 void launch_parent_u(const Cam& cam, const Meshes& M, const float4* poses, const float* obs,
