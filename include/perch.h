@@ -190,7 +190,8 @@ perch_status perch_render(perch_ctx* ctx, const perch_object* objs, int32_t n,
                           int32_t composite, float* depth_dev);
 
 /* Tuning knobs of the successor kernel: threads per successor (64, 128, 256, 512
- * or 1024; default 512), z-tile capacity in pixels (LDS; -1 = sized automatically
+ * or 1024; until set, 512, and 1024 for launches of at most four successors per
+ * compute unit while the z-tile is sized automatically), z-tile capacity in pixels (LDS; -1 = sized automatically
  * from the largest mesh so that two workgroups share a CU, the default), voxel cell
  * size in units of delta (>= 1), and the radius query behind dJ_r (0 = exact pixel
  * window over the observed depth, 1 = uniform voxel hash of the observed cloud).

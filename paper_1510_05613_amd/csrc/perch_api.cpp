@@ -370,7 +370,10 @@ perch_status perch_set_tuning(perch_ctx* c, int32_t threads, int32_t tile_px,
     return fail(PERCH_E_ARG, "cell_over_delta must be in [1, 8]");
   // every argument is checked before any is applied
   if (radius_mode >= 0) c->radius_mode = radius_mode;
-  if (threads) c->threads = threads;
+  if (threads) {
+    c->threads = threads;
+    c->threads_auto = false;
+  }
   if (tile_px) c->tile_px = tile_px < 0 ? 0 : tile_px;
   if (cell_over_delta != 0.0f && cell_over_delta != c->cell_over_delta) {
     c->cell_over_delta = cell_over_delta;
@@ -418,10 +421,17 @@ static perch_status eval_children_impl(perch_ctx* c, const perch_object* cands_d
     return fail(PERCH_E_ARG, "bad successor arrays");
   if (c->parent_j < 0) return fail(PERCH_E_STATE, "perch_set_parent not called");
   if (c->meshes_dirty) return fail(PERCH_E_STATE, "meshes changed since perch_set_parent");
-  const size_t lds = c->eval_lds();
+  if (c->n_cus == 0) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&c->n_cus, hipDeviceAttributeMultiprocessorCount, dev));
+  }
+  const int nt = c->launch_threads(n);
+  const int tile = c->tile_for(nt);
+  const size_t lds = eval_lds_bytes(c->max_nv, tile, nt);
   if (lds > 160 * 1024 - 256)
     return fail(PERCH_E_UNSUPPORTED, "LDS need %zu B exceeds the CU (max_nv=%d, tile=%d)", lds,
-                c->max_nv, c->tile());
+                c->max_nv, tile);
   if (n == 0) return PERCH_OK;
   const int K = (int)c->objects.size();
   Parent par;
@@ -448,8 +458,10 @@ static perch_status eval_children_impl(perch_ctx* c, const perch_object* cands_d
     }
     par.vbits = c->par_vbits.as<unsigned>();
   }
-  HIP_TRY(launch_eval(c->threads, c->scene_dev(), par, reinterpret_cast<const int2*>(cands_dev),
-                      n, cost_dev, status_dev, comps_dev, gain_dev, lds, c->stream));
+  perch::SceneDev S = c->scene_dev();
+  S.ep.tile_px = tile;
+  HIP_TRY(launch_eval(nt, S, par, reinterpret_cast<const int2*>(cands_dev), n, cost_dev,
+                      status_dev, comps_dev, gain_dev, lds, c->stream));
   return PERCH_OK;
 }
 

@@ -102,6 +102,7 @@ extern "C" perch_status perch_autotune(perch_ctx* c, const perch_object* parent,
     }
   cfgs.push_back({512, -1, 1, 1.0f});
   const int keep_threads = c->threads, keep_tile = c->tile_px, keep_mode = c->radius_mode;
+  const bool keep_auto = c->threads_auto;
   const float keep_cell = c->cell_over_delta;
   perch_tuning bestt{};
   bestt.ms = 1e30f;
@@ -147,6 +148,7 @@ extern "C" perch_status perch_autotune(perch_ctx* c, const perch_object* parent,
   out.release();
   if (err || bestt.ms >= 1e30f) {
     (void)perch_set_tuning(c, keep_threads, keep_tile > 0 ? keep_tile : -1, keep_cell, keep_mode);
+    c->threads_auto = keep_auto;
     return err ? err : fail(PERCH_E_UNSUPPORTED, "no tuning candidate fits the LDS");
   }
   st = perch_set_tuning(c, bestt.threads, bestt.tile_px, bestt.cell_over_delta, bestt.radius_mode);
