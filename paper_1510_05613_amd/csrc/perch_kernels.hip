@@ -625,6 +625,10 @@ __global__ void k_render_objects(Cam cam, Meshes M, const float4* poses, ParentO
 __global__ void k_parent_u(Cam cam, Meshes M, const float4* poses, const float* obs,
                            ParentObjs po, int j, const unsigned* pdepth, unsigned* ubits,
                            int* ucount, EvalParams ep) {
+  // the parent objects' camera-to-object maps, once per workgroup (j <= 16 threads)
+  __shared__ ObjMap s_om[kMaxObjects];
+  if ((int)threadIdx.x < j) s_om[threadIdx.x] = make_obj_map(cam, poses[po.o[threadIdx.x].y]);
+  __syncthreads();
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   const int W = cam.W, H = cam.H;
   bool inU = false;
@@ -635,7 +639,7 @@ __global__ void k_parent_u(Cam cam, Meshes M, const float4* poses, const float* 
       const float3 p = backproject(cam, i, jj, z);
       bool inV = false;
       for (int a = 0; a < j && !inV; ++a)
-        inV = in_volume(M, po.o[a].x, apply_obj_map(make_obj_map(cam, poses[po.o[a].y]), p));
+        inV = in_volume(M, po.o[a].x, apply_obj_map(s_om[a], p));
       if (!inV) {
         int ru, rv;
         window_radius(cam, ep, p, ru, rv);
@@ -666,6 +670,9 @@ __global__ void k_parent_u(Cam cam, Meshes M, const float4* poses, const float* 
 
 __global__ void k_parent_v(Cam cam, Meshes M, const float4* poses, const float* obs,
                            ParentObjs po, int j, unsigned* vbits) {
+  __shared__ ObjMap s_om[kMaxObjects];  // as in k_parent_u
+  if ((int)threadIdx.x < j) s_om[threadIdx.x] = make_obj_map(cam, poses[po.o[threadIdx.x].y]);
+  __syncthreads();
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   const int W = cam.W, H = cam.H;
   bool inV = false;
@@ -673,8 +680,7 @@ __global__ void k_parent_v(Cam cam, Meshes M, const float4* poses, const float* 
     const float z = obs[k];
     if (z > 0.0f) {
       const float3 p = backproject(cam, k % W, k / W, z);
-      for (int a = 0; a < j && !inV; ++a)
-        inV = in_volume(M, po.o[a].x, apply_obj_map(make_obj_map(cam, poses[po.o[a].y]), p));
+      for (int a = 0; a < j && !inV; ++a) inV = in_volume(M, po.o[a].x, apply_obj_map(s_om[a], p));
     }
   }
   if (inV) atomicOr(&vbits[k >> 5], 1u << (k & 31));
