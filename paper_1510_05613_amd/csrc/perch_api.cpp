@@ -560,9 +560,17 @@ perch_status perch_render(perch_ctx* c, const perch_object* objs, int32_t n, int
   const Meshes M = c->dev_meshes();
   if (composite) {
     launch_fill_u32(out, kInfBits, npx, c->stream);
-    for (int k = 0; k < n; ++k)
-      launch_render_object(c->cam, M, c->poses.as<float4>(), objs[k].mesh_id, objs[k].pose_idx,
-                           (int)c->meshes[objs[k].mesh_id].tris.size() / 3, out, c->stream);
+    for (int k0 = 0; k0 < n; k0 += kMaxObjects) {  // up to kMaxObjects objects per launch
+      const int m = std::min(kMaxObjects, n - k0);
+      int mp[2 * kMaxObjects];
+      int max_tris = 0;
+      for (int k = 0; k < m; ++k) {
+        mp[2 * k] = objs[k0 + k].mesh_id;
+        mp[2 * k + 1] = objs[k0 + k].pose_idx;
+        max_tris = std::max(max_tris, (int)c->meshes[objs[k0 + k].mesh_id].tris.size() / 3);
+      }
+      launch_render_objects(c->cam, M, c->poses.as<float4>(), mp, m, max_tris, out, c->stream);
+    }
   } else {
     launch_fill_u32(out, kInfBits, npx * (size_t)n, c->stream);
     for (int k = 0; k < n; ++k)

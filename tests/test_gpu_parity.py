@@ -83,6 +83,20 @@ def test_render_matches_oracle_coverage_and_depth(c1):
     assert worst < 1e-5
 
 
+def test_composite_render_is_the_minimum_of_object_renders(c1):
+    """A composite of several objects (in launches of up to 16 objects) equals the
+    elementwise minimum of their stand-alone renders, bit for bit; 20 objects take
+    two launches."""
+    sc, _, ctx = c1[0]
+    rng = np.random.default_rng(11)
+    for n in (3, 20):
+        objs = [(int(rng.choice(sc.obj_mesh)), int(rng.integers(sc.grid.P))) for _ in range(n)]
+        comp = ctx.render(objs).cpu().numpy()
+        sep = ctx.render(objs, composite=False).cpu().numpy()
+        assert comp.shape == sep.shape[1:]
+        assert np.array_equal(comp.view(np.uint32), sep.min(axis=0).view(np.uint32)), n
+
+
 def test_render_matches_oracle_640x480():
     sc = H.c2_scene(0)
     o = Oracle.from_scene(sc)
