@@ -3,6 +3,7 @@ from __future__ import annotations
 
 import os
 import subprocess
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -20,20 +21,29 @@ HOST_FLAGS = ["--offload-arch=gfx950", "-O2", "-std=c++17", "-fPIC", "-Wall", "-
               "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, jobs: int | None = None) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
-    for src, flags in (("perch_kernels.hip", DEVICE_FLAGS), ("perch_cnn.hip", DEVICE_FLAGS),
-                       ("perch_select.hip", DEVICE_FLAGS),
-                       ("perch_cnn_api.cpp", HOST_FLAGS), ("perch_api.cpp", HOST_FLAGS),
-                       ("perch_search.cpp", HOST_FLAGS), ("perch_batch.cpp", HOST_FLAGS),
-                       ("perch_tune.cpp", HOST_FLAGS)):
+    units = (("perch_kernels.hip", DEVICE_FLAGS), ("perch_cnn.hip", DEVICE_FLAGS),
+             ("perch_select.hip", DEVICE_FLAGS),
+             ("perch_cnn_api.cpp", HOST_FLAGS), ("perch_api.cpp", HOST_FLAGS),
+             ("perch_search.cpp", HOST_FLAGS), ("perch_batch.cpp", HOST_FLAGS),
+             ("perch_tune.cpp", HOST_FLAGS))
+    cmds, objs = [], []
+    for src, flags in units:
         obj = os.path.join(BUILD, src.rsplit(".", 1)[0] + ".o")
-        cmd = [HIPCC, *flags, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmds.append([HIPCC, *flags, "-c", os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
+
+    def run(cmd):
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
-        objs.append(obj)
+
+    # one compiler process per source file, at most `jobs` at a time
+    n = jobs or min(len(cmds), max(1, min(8, os.cpu_count() or 1)))
+    with ThreadPoolExecutor(max_workers=n) as ex:
+        for f in [ex.submit(run, c) for c in cmds]:
+            f.result()
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:
