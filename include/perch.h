@@ -151,6 +151,22 @@ perch_status perch_set_parent(perch_ctx* ctx, const perch_object* parent, int32_
 perch_status perch_eval_children(perch_ctx* ctx, const perch_object* cands_dev, int32_t n,
                                  int32_t* cost_dev, int32_t* status_dev, int32_t* comps_dev);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * serving loops, harnesses that forbid hipMalloc): perch_eval_successors with the
+ * same arguments, outputs and kernels, but the parent composite R_j, the set U and
+ * |U| live in a fixed device array of the library (one per GPU, held until the
+ * process ends) instead of context buffers, and the call allocates nothing.
+ * Limits: at most 1,048,576 pixels (W * H; PERCH_E_UNSUPPORTED beyond); the mesh
+ * library must already be on the device (uploaded by an earlier perch_render,
+ * perch_set_parent or perch_eval_successors; PERCH_E_STATE otherwise).  Every call
+ * on one GPU shares the array: calls that overlap on one GPU (other streams or
+ * threads) race and must be serialised by the caller.  The context's own parent
+ * (perch_set_parent) is left as it was.  Asynchronous. */
+perch_status perch_eval_successors_noalloc(perch_ctx* ctx, const perch_object* parent,
+                                           int32_t j, const perch_object* cands_dev,
+                                           int32_t n, int32_t* cost_dev, int32_t* status_dev,
+                                           int32_t* comps_dev);
+
 /* The paper's overlap heuristic (Sec. IV-C): h_overlap(s) = |I| - #{p in I : p in V_j},
  * the observed points outside the union V_j of the placed objects' volumes.  For
  * each successor of the parent last set, evaluates it as perch_eval_children does

@@ -24,7 +24,8 @@ PERCH_SUCC_BAD_INPUT = -4
 
 # the public symbols declared in include/perch.h
 EXPORTS = ("perch_create", "perch_destroy", "perch_set_observation", "perch_add_mesh",
-           "perch_set_poses", "perch_set_objects", "perch_eval_successors", "perch_set_parent",
+           "perch_set_poses", "perch_set_objects", "perch_eval_successors",
+           "perch_eval_successors_noalloc", "perch_set_parent",
            "perch_eval_children", "perch_overlap_gain", "perch_set_pose_arena",
            "perch_set_symmetric",
            "perch_get_poses", "perch_icp_children", "perch_render", "perch_set_tuning",
@@ -106,6 +107,7 @@ def load(path: str = LIB_PATH):
     L.perch_set_poses.argtypes = [P, P, I32]
     L.perch_set_objects.argtypes = [P, P, I32]
     L.perch_eval_successors.argtypes = [P, P, I32, P, I32, P, P, P]
+    L.perch_eval_successors_noalloc.argtypes = [P, P, I32, P, I32, P, P, P]
     L.perch_set_parent.argtypes = [P, P, I32]
     L.perch_eval_children.argtypes = [P, P, I32, P, P, P]
     L.perch_render.argtypes = [P, P, I32, I32, P]
@@ -253,6 +255,16 @@ class Context:
         n = cands.shape[0]
         par = _objects(parent)
         _check(load().perch_eval_successors(
+            self.h, C.cast(par, C.c_void_p), len(parent), _dev_ptr(cands, "int32", 2 * n), n,
+            _dev_ptr(cost, "int32", n), _dev_ptr(status, "int32", n),
+            None if comps is None else _dev_ptr(comps, "int32", 5 * n)))
+
+    def eval_successors_noalloc(self, parent, cands, cost, status, comps=None):
+        """eval_successors without device allocation: the parent buffers are the
+        library's fixed per-GPU array (shared by every such call on the GPU)."""
+        n = cands.shape[0]
+        par = _objects(parent)
+        _check(load().perch_eval_successors_noalloc(
             self.h, C.cast(par, C.c_void_p), len(parent), _dev_ptr(cands, "int32", 2 * n), n,
             _dev_ptr(cost, "int32", n), _dev_ptr(status, "int32", n),
             None if comps is None else _dev_ptr(comps, "int32", 5 * n)))
