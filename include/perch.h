@@ -172,8 +172,9 @@ perch_status perch_eval_successors_noalloc(perch_ctx* ctx, const perch_object* p
  * each successor of the parent last set, evaluates it as perch_eval_children does
  * (cost_dev, status_dev) and writes gain_dev[i] = #{p in I : p in V(O) and p not in
  * V_j}, so that h_overlap(child) = h_overlap(parent) - gain; -1 for a successor that
- * is not valid.  V(O) is tested in float32 (the oracle's FP64 decision may differ for
- * points within 1e-5 m of a boundary).  gain_dev: device, n int32.  Asynchronous. */
+ * is not valid.  V(O) membership is decided as in exact arithmetic on the float32
+ * inputs: float32 where a proven margin allows, FP64 otherwise.  gain_dev: device,
+ * n int32.  Asynchronous. */
 perch_status perch_overlap_gain(perch_ctx* ctx, const perch_object* cands_dev, int32_t n,
                                 int32_t* cost_dev, int32_t* status_dev, int32_t* gain_dev);
 

@@ -35,6 +35,57 @@ perch_status fail(perch_status st, const char* fmt, ...) {
   return st;
 }
 
+// Float32 error of the observed-point volume test.  u = 2^-24 is float32's unit
+// roundoff.
+//  - Vertex-box pre-test on o = A p + b (float32 back-projection p, float32 map A, b
+//    of the camera-to-object transform): each coordinate of p carries <= 4u of its
+//    size, the entries of A (products of the rounded world_from_cam and the pose's
+//    cos / sin divided by cos^2 + sin^2) <= 12u, b (camera position relative to the
+//    pose, |b| <= Tm) <= 16u |b|, and the fused chain three more roundings of its
+//    partial sums; together well below 64u (|p|_1 + Tm) with |p|_1 <= zmax (1 +
+//    amax + bmax) over the observed points.  vbox = 64u (Pm + Tm) + 1e-6 m, so a
+//    point the float32 test puts more than vbox outside the vertex box is outside.
+//  - Plane test: o in FP64 (within 1e-15 m of the exact map of the same float32
+//    inputs), rounded to float32 (u |o| per coordinate), then s = n.o - d by three
+//    fused roundings (<= 3.01u (|o| + |d|) for unit n).  Inside the box widened by
+//    vbox, |o| <= Rm + 2 vbox, so vtau = 8u (Rm + 2 vbox + Wm) + 1e-12 m bounds the
+//    float32 error of every plane value; a plane value beyond +-vtau has the sign of
+//    the exact one, and the rest are decided in FP64.
+void vol_margins(const Cam& cam, float obs_zmax, float pose_xy_max, float mesh_rmax,
+                 float mesh_wmax, float& vbox, float& vtau) {
+  const double u = std::ldexp(1.0, -24);
+  const double amax = std::max(std::fabs((double)cam.cx), std::fabs(cam.W - 1.0 - cam.cx)) / cam.fx;
+  const double bmax = std::max(std::fabs((double)cam.cy), std::fabs(cam.H - 1.0 - cam.cy)) / cam.fy;
+  const double Pm = (double)obs_zmax * (1.0 + amax + bmax);
+  const double Tm = std::fabs(cam.dWinv[3]) + std::fabs(cam.dWinv[7]) +
+                    std::fabs(cam.dWinv[11]) + pose_xy_max + 0.1;  // + local ICP moves
+  const double vb = 64.0 * u * (Pm + Tm) + 1e-6;
+  vbox = (float)vb;
+  vtau = (float)(8.0 * u * (mesh_rmax + 2.0 * vb + mesh_wmax) + 1e-12);
+}
+
+// Margin of the float32 test |q - p|^2 <= delta^2 for pixel points q = (i_q, j_q,
+// z_q) and p (both inside the image), each back-projected in float32 as ((i - cx) z)
+// (1/fx): every coordinate within 4u of its size, z exact.  With K = amax + bmax (the
+// largest |i - cx| / fx and |j - cy| / fy) and the fixed point at depth z, the other
+// within d of it, the error vector of the float32 difference has length <= A + B d,
+// A = 8u K z, B = 4u K + 2u, and the rounded d^2 and delta^2 add 3u d^2 and u delta^2.
+// So |t - (d^2 - delta^2)| <= 2 delta A + delta^2 (2B + 4u) + 2 (A + B delta)^2 for t =
+// the float32 d^2 - delta^2 whenever its sign could be wrong; tau is twice that:
+// tau(z) = t_lin z + t_0 + 4 (t_a z + t_s)^2.  |t| > tau decides by its sign; the
+// rest is decided in FP64 (needs delta much larger than A, i.e. delta >= 1e-4 m).
+static void delta_margins(Cam& cam) {
+  const double u = std::ldexp(1.0, -24);
+  const double amax = std::max(std::fabs((double)cam.cx), std::fabs(cam.W - 1.0 - cam.cx)) / cam.fx;
+  const double bmax = std::max(std::fabs((double)cam.cy), std::fabs(cam.H - 1.0 - cam.cy)) / cam.fy;
+  const double K = amax + bmax, d = cam.delta;
+  const double ta = 8.0 * u * K, B = 4.0 * u * K + 2.0 * u;
+  cam.t_lin = (float)(4.0 * d * ta * (1.0 + 1e-3));
+  cam.t_0 = (float)(d * d * (4.0 * B + 8.0 * u) * (1.0 + 1e-3));
+  cam.t_a = (float)(ta * (1.0 + 1e-3));
+  cam.t_s = (float)(B * d * (1.0 + 1e-3));
+}
+
 }  // namespace perch
 
 perch_status upload_meshes(perch_ctx* c) {
@@ -46,6 +97,7 @@ perch_status upload_meshes(perch_ctx* c) {
   std::vector<float4> pl, bb;
   std::vector<int2> fr;
   int max_nv = 0;
+  float rmax = 0.0f, wmax = 0.0f;
   for (int m = 0; m < nm; ++m) {
     const HostMesh& h = c->meshes[m];
     if (!h.set) return fail(PERCH_E_STATE, "mesh id %d was never added (ids must be dense)", m);
@@ -68,6 +120,13 @@ perch_status upload_meshes(perch_ctx* c) {
     bb.push_back(make_float4(lo[0], lo[1], lo[2], 0.0f));
     bb.push_back(make_float4(hi[0], hi[1], hi[2], 0.0f));
     max_nv = std::max(max_nv, nv);
+    if (nv > 0) {
+      const float cx = std::max(std::fabs(lo[0]), std::fabs(hi[0]));
+      const float cy = std::max(std::fabs(lo[1]), std::fabs(hi[1]));
+      const float cz = std::max(std::fabs(lo[2]), std::fabs(hi[2]));
+      rmax = std::max(rmax, std::sqrt(cx * cx + cy * cy + cz * cz));
+    }
+    for (int k = 0; k < nf; ++k) wmax = std::max(wmax, std::fabs(h.planes[4 * k + 3]));
   }
   HIP_TRY(c->verts.ensure(v.size() * sizeof(float4)));
   HIP_TRY(c->tris.ensure(std::max<size_t>(1, t.size()) * sizeof(int4)));
@@ -84,6 +143,8 @@ perch_status upload_meshes(perch_ctx* c) {
   HIP_TRY(hipMemcpy(c->frange.p, fr.data(), fr.size() * sizeof(int2), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(c->aabb.p, bb.data(), bb.size() * sizeof(float4), hipMemcpyHostToDevice));
   c->max_nv = max_nv;
+  c->mesh_rmax = rmax * (1.0f + 1e-6f);
+  c->mesh_wmax = wmax * (1.0f + 1e-6f);
   c->meshes_dirty = false;
   return PERCH_OK;
 }
@@ -118,8 +179,8 @@ perch_status materialise_into(perch_ctx* c, const perch_object* parent, int j, b
   if (goal) {
     launch_fill_u32(ubits, 0u, (npx + 31) / 32, st);
     launch_fill_i32(ucount, 0, 1, st);
-    launch_parent_u(c->cam, M, poses, c->obs.as<float>(), mp, j, depth, ubits, ucount, c->ep,
-                    st);
+    launch_parent_u(c->cam, M, poses, c->obs.as<float>(), mp, j, depth, ubits, ucount,
+                    c->eval_params(), st);
   }
   HIP_TRY(hipGetLastError());
   return PERCH_OK;
@@ -177,8 +238,13 @@ perch_status perch_create(const perch_sensor* s, void* hip_stream, perch_ctx** o
     for (int k = 0; k < 3; ++k) cam.Winv[4 * r + k] = (float)Ri[3 * r + k];
     cam.Winv[4 * r + 3] = (float)(-(Ri[3 * r] * t[0] + Ri[3 * r + 1] * t[1] + Ri[3 * r + 2] * t[2]));
   }
+  for (int r = 0; r < 3; ++r) {
+    for (int k = 0; k < 3; ++k) cam.dWinv[4 * r + k] = Ri[3 * r + k];
+    cam.dWinv[4 * r + 3] = -(Ri[3 * r] * t[0] + Ri[3 * r + 1] * t[1] + Ri[3 * r + 2] * t[2]);
+  }
   cam.delta = s->delta;
   cam.delta2 = s->delta * s->delta;
+  cam.ddelta2 = (double)s->delta * (double)s->delta;
   cam.inv_fx = 1.0f / s->fx;
   cam.inv_fy = 1.0f / s->fy;
   cam.dfx = s->fx;
@@ -187,6 +253,7 @@ perch_status perch_create(const perch_sensor* s, void* hip_stream, perch_ctx** o
   cam.dcy = s->cy;
   cam.dinv_fx = 1.0 / (double)s->fx;
   cam.dinv_fy = 1.0 / (double)s->fy;
+  delta_margins(cam);
   c->stream = static_cast<hipStream_t>(hip_stream);
   if (hipGetDevice(&c->device) != hipSuccess) {
     delete c;
@@ -221,12 +288,15 @@ static perch_status build_observation(perch_ctx* c) {
                          c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   int n = 0;
-  float zmin = INFINITY;
+  float zmin = INFINITY, zmax = 0.0f;
   for (size_t k = 0; k < npx; ++k)
     if (host[k] > 0.0f) {
       ++n;
       zmin = std::min(zmin, host[k]);
+      zmax = std::max(zmax, host[k]);
     }
+  if (!(zmax < INFINITY)) return fail(PERCH_E_ARG, "observed depth is not finite");
+  c->obs_zmax = zmax;
   // Pixel halo: the largest window radius fx dwin sqrt(1 + a^2) / (Z - dwin) + 1
   // over the observed points (a = |u - cx| / fx at the image border, Z >= zmin).
   const double dwin = (double)cam.delta * 1.001 + 1e-6;
@@ -313,8 +383,15 @@ perch_status perch_set_symmetric(perch_ctx* c, int32_t mesh_id, int32_t symmetri
 
 perch_status perch_set_poses(perch_ctx* c, const float* poses, int32_t P) {
   if (!c || !poses || P <= 0) return fail(PERCH_E_ARG, "bad pose table");
+  float xy = 0.0f;
+  for (int k = 0; k < P; ++k) {
+    const float e = std::fabs(poses[4 * k]) + std::fabs(poses[4 * k + 1]);
+    if (!(e < 1e4f)) return fail(PERCH_E_ARG, "pose %d is not finite or beyond 1e4 m", k);
+    xy = std::max(xy, e);
+  }
   HIP_TRY(c->poses.ensure(((size_t)P + c->arena_cap) * sizeof(float4)));
   HIP_TRY(hipMemcpy(c->poses.p, poses, (size_t)P * sizeof(float4), hipMemcpyHostToDevice));
+  c->pose_xy_max = xy;
   c->P = P;
   c->arena_used = 0;
   c->h_poses.assign(poses, poses + 4 * (size_t)P);
@@ -452,7 +529,7 @@ static perch_status eval_children_impl(perch_ctx* c, const perch_object* cands_d
         mp[2 * k + 1] = c->parent_objs[k].pose_idx;
       }
       launch_parent_v(c->cam, c->dev_meshes(), c->poses.as<float4>(), c->obs.as<float>(), mp, j,
-                      c->par_vbits.as<unsigned>(), c->stream);
+                      c->par_vbits.as<unsigned>(), c->eval_params(), c->stream);
       HIP_TRY(hipGetLastError());
       c->vbits_for = c->parent_serial;
     }

@@ -73,6 +73,12 @@ inline int next_pow2(int v) {
   return p;
 }
 
+// Float32 error margins of the observed-point volume test for one scene (the
+// derivation is in perch_api.cpp): vbox for the float32 vertex-box pre-test, vtau
+// for the float32 face-plane values of the FP64 object-frame point.
+void vol_margins(const Cam& cam, float obs_zmax, float pose_xy_max, float mesh_rmax,
+                 float mesh_wmax, float& vbox, float& vtau);
+
 // Records a message for perch_last_error() and returns st.
 perch_status fail(perch_status st, const char* fmt, ...);
 
@@ -203,6 +209,19 @@ struct perch_ctx {
   }
   int tile_for(int nt) const { return tile_px > 0 ? tile_px : auto_tile_px(max_nv, nt); }
 
+  // extents behind the float32 decision margins of the volume test (vol_margins)
+  float obs_zmax = 0.0f;     // largest observed depth
+  float pose_xy_max = 0.0f;  // largest |x| + |y| over the pose grid
+  float mesh_rmax = 0.0f;    // largest distance of a mesh's vertex-box corner from its origin
+  float mesh_wmax = 0.0f;    // largest |d| over the face planes (n, d)
+
+  // ep with the volume-test margins of this scene (see perch::vol_margins).
+  EvalParams eval_params() const {
+    EvalParams e = ep;
+    perch::vol_margins(cam, obs_zmax, pose_xy_max, mesh_rmax, mesh_wmax, e.vbox, e.vtau);
+    return e;
+  }
+
   int tile() const { return tile_px > 0 ? tile_px : auto_tile_px(max_nv, threads); }
   size_t eval_lds() const { return eval_lds_bytes(max_nv, tile(), threads); }
 
@@ -225,7 +244,7 @@ struct perch_ctx {
     S.obs = obs.as<float>();
     S.obs_range = obs_range.as<float2>();
     S.hs = dev_hash();
-    S.ep = ep;
+    S.ep = eval_params();
     S.ep.tile_px = tile();
     S.ep.max_nv = max_nv;
     S.ep.vpack = vertex_cache_packed(max_nv);

@@ -18,6 +18,11 @@ struct Cam {
   float inv_fx, inv_fy;
   double dfx, dfy, dcx, dcy;  // the same intrinsics widened to FP64 (depth planes)
   double dinv_fx, dinv_fy;
+  double dWinv[12];  // world_from_cam in FP64 (near-boundary volume decisions)
+  double ddelta2;    // delta^2 in FP64 of the float32 delta (near-threshold distance decisions)
+  // Margin of the float32 distance test |q - p|^2 <= delta^2 (see delta_margin):
+  // tau(z) = t_lin z + t_0 + 4 (t_a z + t_s)^2 for a fixed point at depth z.
+  float t_lin, t_0, t_a, t_s;
 };
 
 // Uniform voxel hash of the observed cloud I (camera frame).  Cell (i, j, k) holds
@@ -66,6 +71,10 @@ struct EvalParams {
   int n_poses;  // [0, n_poses) are rejected with status -4
   int radius_mode;  // dJ_r query: 0 exact pixel window, 1 voxel hash
   int vpack;        // vertex cache: 0 int2 per vertex, 1 packed 16 + 16 bits (large meshes)
+  // V(O) decisions: a float32 object-frame point more than vbox outside the mesh's
+  // vertex box is outside; inside it, face-plane values computed in float32 from the
+  // FP64 object-frame point decide when they clear vtau, else FP64 decides.
+  float vbox, vtau;
 };
 
 // Everything a successor evaluation reads about one scene.
@@ -119,7 +128,8 @@ hipError_t launch_eval(int threads, const SceneDev& S, const Parent& par, const 
                        hipStream_t s);
 // vbits |= observed pixels inside the union of the j objects' volumes
 void launch_parent_v(const Cam& cam, const Meshes& M, const float4* poses, const float* obs,
-                     const int* par_mesh_pose, int j, unsigned* vbits, hipStream_t s);
+                     const int* par_mesh_pose, int j, unsigned* vbits, const EvalParams& ep,
+                     hipStream_t s);
 // What a batch's tables hold (flags of prepare/launch_eval_batch): some scene
 // answers dJ_r by the voxel hash (radius mode 1), some parent is at its scene's goal
 // level, some parent has a parent (is below the root).

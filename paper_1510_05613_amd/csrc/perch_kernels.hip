@@ -326,6 +326,40 @@ __device__ __forceinline__ float3 backproject(const Cam& c, int i, int j, float 
   return make_float3(((float)i - c.cx) * z * c.inv_fx, ((float)j - c.cy) * z * c.inv_fy, z);
 }
 
+// ---------------------------------------------------------------------------
+// decisions at a threshold: float32 outside a proven error margin, FP64 inside it
+// ---------------------------------------------------------------------------
+
+// Margin of the float32 distance test for a point seen at depth z: when the float32
+// |q - p|^2 - delta^2 exceeds it in magnitude, its sign is the sign of the exact
+// value for the same pixels and float32 depths (derivation with the host's
+// constants t_lin, t_0, t_a, t_s).
+__device__ __forceinline__ float delta_margin(const Cam& c, float z) {
+  const float a = fmaf(c.t_a, z, c.t_s);
+  return fmaf(c.t_lin, z, c.t_0) + 4.0f * a * a;
+}
+
+// Eq. (1)'s test |q - p| <= delta for q = pixel (iq, jq) at depth zq and p = pixel
+// (ip, jp) at depth zp, back-projected through the pixel centres in FP64.
+__device__ __forceinline__ bool within_delta64(const Cam& c, int iq, int jq, float zq, int ip,
+                                            int jp, float zp) {
+  const double dq = zq, dp = zp;
+  const double ex = (((double)iq - c.dcx) * dq - ((double)ip - c.dcx) * dp) * c.dinv_fx;
+  const double ey = (((double)jq - c.dcy) * dq - ((double)jp - c.dcy) * dp) * c.dinv_fy;
+  const double ez = dq - dp;
+  return ex * ex + ey * ey + ez * ez <= c.ddelta2;
+}
+
+// The same test from the float32 squared distance d2 of the float32 back-projections
+// and the margin tau of the point held fixed: decided by d2 outside the margin, in
+// FP64 inside it.
+__device__ __forceinline__ bool within_delta(const Cam& c, float d2, float tau, int iq, int jq,
+                                             float zq, int ip, int jp, float zp) {
+  const float t = d2 - c.delta2;
+  if (__builtin_expect(fabsf(t) > tau, 1)) return t <= 0.0f;
+  return within_delta64(c, iq, jq, zq, ip, jp, zp);
+}
+
 __device__ __forceinline__ unsigned long long cell_key(int x, int y, int z) {
   return (unsigned long long)((unsigned)(x + (1 << 20)) & 0x1FFFFFu) |
          ((unsigned long long)((unsigned)(y + (1 << 20)) & 0x1FFFFFu) << 21) |
@@ -342,11 +376,13 @@ __device__ __forceinline__ unsigned hash_key(unsigned long long k) {
 }
 
 // Eq. (1) against the whole observed cloud: true iff some observed point lies
-// within delta of q (camera frame).  Scans every voxel cell overlapping the cube
-// q +- qpad (qpad slightly above delta, so float rounding of the cell index cannot
-// drop a neighbour) and stops at the first hit.
-__device__ __forceinline__ bool explained_by_cloud(const Hash& hs, float qx, float qy, float qz,
-                                                   float d2max) {
+// within delta of q (camera frame; pixel (iq, jq) at depth zq, distance margin tau).
+// Scans every voxel cell overlapping the cube q +- qpad (qpad slightly above delta,
+// so float rounding of the cell index cannot drop a neighbour) and stops at the
+// first hit.  Each point carries its pixel index (as float bits in w) for the FP64
+// decision near delta.
+__device__ __forceinline__ bool explained_by_cloud(const Cam& cam, const Hash& hs, float qx,
+                                                   float qy, float qz, int iq, int jq, float tau) {
   const int x0 = (int)floorf((qx - hs.qpad) * hs.inv_cell);
   const int x1 = (int)floorf((qx + hs.qpad) * hs.inv_cell);
   const int y0 = (int)floorf((qy - hs.qpad) * hs.inv_cell);
@@ -365,7 +401,13 @@ __device__ __forceinline__ bool explained_by_cloud(const Hash& hs, float qx, flo
             for (int t = se.x; t < se.x + se.y; ++t) {
               const float4 p = hs.pts[t];
               const float dx = p.x - qx, dy = p.y - qy, dz = p.z - qz;
-              if (dx * dx + dy * dy + dz * dz <= d2max) return true;
+              const float e = dx * dx + dy * dy + dz * dz - cam.delta2;
+              if (__builtin_expect(fabsf(e) > tau, 1)) {
+                if (e <= 0.0f) return true;
+              } else {
+                const int pix = __float_as_int(p.w);
+                if (within_delta64(cam, iq, jq, qz, pix % cam.W, pix / cam.W, p.z)) return true;
+              }
             }
             break;
           }
@@ -404,40 +446,101 @@ __device__ __forceinline__ float3 apply_obj_map(const ObjMap& m, float3 p) {
                      fmaf(m.a[6], p.x, fmaf(m.a[7], p.y, fmaf(m.a[8], p.z, m.b[2]))));
 }
 
-// o is on the outer side of face plane (n, w): n.o - w > 0, in fused products (a
-// point within float rounding of the plane may fall on either side).
-__device__ __forceinline__ bool plane_out(const float4 pl, float3 o) {
-  return fmaf(pl.x, o.x, fmaf(pl.y, o.y, fmaf(pl.z, o.z, -pl.w))) > 0.0f;
+// The same map in FP64 from the FP64 world_from_cam and the pose's float32 values:
+// o = (c dx + s dy, -s dx + c dy) / (c^2 + s^2), o_z = w_z, with (dx, dy) = w - (x, y)
+// and w = Winv p.
+struct ObjMap64 {
+  double a[9], b[3];
+};
+
+__device__ __forceinline__ ObjMap64 make_obj_map64(const Cam& c, const float4 pz) {
+  const double cs = pz.z, sn = pz.w;
+  const double n2 = cs * cs + sn * sn;
+  const double ca = cs / n2, sa = sn / n2;
+  const double* W = c.dWinv;
+  ObjMap64 m;
+  for (int k = 0; k < 3; ++k) {
+    m.a[k] = ca * W[k] + sa * W[4 + k];
+    m.a[3 + k] = ca * W[4 + k] - sa * W[k];
+    m.a[6 + k] = W[8 + k];
+  }
+  const double tx = W[3] - (double)pz.x, ty = W[7] - (double)pz.y;
+  m.b[0] = ca * tx + sa * ty;
+  m.b[1] = ca * ty - sa * tx;
+  m.b[2] = W[11];
+  return m;
 }
 
-// p in V(O) as in_volume, with the box corners and the planes already at hand
-// (the planes staged in LDS by the successor kernel).
-__device__ __forceinline__ bool in_volume_at(const float4 lo, const float4 hi,
-                                             const float4* planes, int n_planes, float3 o) {
-  if (o.x < lo.x - 1e-5f || o.y < lo.y - 1e-5f || o.z < lo.z - 1e-5f || o.x > hi.x + 1e-5f ||
-      o.y > hi.y + 1e-5f || o.z > hi.z + 1e-5f)
+// Face-plane value n.o - w of a float32 object-frame point, in fused products.
+__device__ __forceinline__ float plane_val(const float4 pl, float3 o) {
+  return fmaf(pl.x, o.x, fmaf(pl.y, o.y, fmaf(pl.z, o.z, -pl.w)));
+}
+
+__device__ __forceinline__ float max8(float a, float b, float c, float d, float e, float f,
+                                      float g, float h) {
+  return fmaxf(fmaxf(fmaxf(a, b), fmaxf(c, d)), fmaxf(fmaxf(e, f), fmaxf(g, h)));
+}
+
+// max_f (n_f . o - w_f) <= 0 in FP64.
+__device__ __forceinline__ bool inside_planes64(const float4* planes, int n_planes, double ox,
+                                             double oy, double oz) {
+  double m = -INFINITY;
+  for (int f = 0; f < n_planes; ++f) {
+    const float4 pl = planes[f];
+    m = fmax(m, (double)pl.x * ox + (double)pl.y * oy + (double)pl.z * oz - (double)pl.w);
+  }
+  return m <= 0.0;
+}
+
+// Observed point p in V(O) = {o : n_f . o <= w_f for every face plane}, the decision
+// of exact arithmetic on the same inputs (pixel (i, j), float32 depth z) outside an
+// FP64 rounding band.  o32 (the float32 map of the float32 back-projection) rules
+// out points more than vbox outside the mesh's vertex box; the rest take the FP64
+// object-frame point, rounded to float32 for the plane values: all below -vtau is
+// inside, one above +vtau is outside, and anything else is decided in FP64.
+__device__ __forceinline__ bool in_volume_at(const Cam& c, const EvalParams& ep,
+                                             const ObjMap64& dm, const float4 lo,
+                                             const float4 hi, const float4* planes,
+                                             int n_planes, float3 o32, int i, int j, float z) {
+  const float mb = ep.vbox;
+  if (o32.x < lo.x - mb || o32.y < lo.y - mb || o32.z < lo.z - mb || o32.x > hi.x + mb ||
+      o32.y > hi.y + mb || o32.z > hi.z + mb)
     return false;
+  const double dz = z;
+  const double px = ((double)i - c.dcx) * dz * c.dinv_fx;
+  const double py = ((double)j - c.dcy) * dz * c.dinv_fy;
+  const double ox = fma(dm.a[0], px, fma(dm.a[1], py, fma(dm.a[2], dz, dm.b[0])));
+  const double oy = fma(dm.a[3], px, fma(dm.a[4], py, fma(dm.a[5], dz, dm.b[1])));
+  const double oz = fma(dm.a[6], px, fma(dm.a[7], py, fma(dm.a[8], dz, dm.b[2])));
+  const float3 o = make_float3((float)ox, (float)oy, (float)oz);
+  const float tau = ep.vtau;
+  float mx = -INFINITY;
   int f = 0;
-  for (; f + 8 <= n_planes; f += 8)  // eight planes per test: the answer is their OR
-    if (plane_out(planes[f], o) | plane_out(planes[f + 1], o) | plane_out(planes[f + 2], o) |
-        plane_out(planes[f + 3], o) | plane_out(planes[f + 4], o) | plane_out(planes[f + 5], o) |
-        plane_out(planes[f + 6], o) | plane_out(planes[f + 7], o))
-      return false;
-  for (; f + 4 <= n_planes; f += 4)
-    if (plane_out(planes[f], o) | plane_out(planes[f + 1], o) | plane_out(planes[f + 2], o) |
-        plane_out(planes[f + 3], o))
-      return false;
-  for (; f < n_planes; ++f)
-    if (plane_out(planes[f], o)) return false;
-  return true;
+  for (; f + 8 <= n_planes; f += 8) {  // eight planes per branch
+    mx = fmaxf(mx, max8(plane_val(planes[f], o), plane_val(planes[f + 1], o),
+                        plane_val(planes[f + 2], o), plane_val(planes[f + 3], o),
+                        plane_val(planes[f + 4], o), plane_val(planes[f + 5], o),
+                        plane_val(planes[f + 6], o), plane_val(planes[f + 7], o)));
+    if (mx > tau) return false;
+  }
+  for (; f + 4 <= n_planes; f += 4) {
+    mx = fmaxf(mx, fmaxf(fmaxf(plane_val(planes[f], o), plane_val(planes[f + 1], o)),
+                         fmaxf(plane_val(planes[f + 2], o), plane_val(planes[f + 3], o))));
+    if (mx > tau) return false;
+  }
+  for (; f < n_planes; ++f) mx = fmaxf(mx, plane_val(planes[f], o));
+  if (mx > tau) return false;
+  if (__builtin_expect(mx < -tau, 1)) return true;
+  return inside_planes64(planes, n_planes, ox, oy, oz);
 }
 
-// p in V(O): inside the mesh's box of vertices (with a 1e-5 m margin) and on the
-// inner side of every plane.
-__device__ __forceinline__ bool in_volume(const Meshes& M, int mesh, float3 o) {
+// p in V(O) of mesh `mesh` at the pose of maps om / dm.
+__device__ __forceinline__ bool in_volume(const Cam& c, const EvalParams& ep, const Meshes& M,
+                                          int mesh, const ObjMap& om, const ObjMap64& dm,
+                                          float3 p, int i, int j, float z) {
   const float4 lo = M.aabb[2 * mesh], hi = M.aabb[2 * mesh + 1];
   const int2 fr = M.frange[mesh];
-  return in_volume_at(lo, hi, M.planes + fr.x, fr.y, o);
+  return in_volume_at(c, ep, dm, lo, hi, M.planes + fr.x, fr.y, apply_obj_map(om, p), i, j, z);
 }
 
 // Pixel window radii (columns, rows) that hold every point within dwin of the
@@ -563,7 +666,7 @@ __global__ void k_hash_scatter(Cam cam, const float* depth, const unsigned long 
   const float3 p = backproject(cam, k % cam.W, k / cam.W, z);
   const unsigned slot = find_slot(keys, mask, point_cell(p, inv_cell));
   const int pos = cells[slot].x + atomicAdd(&fill[slot], 1);
-  pts[pos] = make_float4(p.x, p.y, p.z, 0.0f);
+  pts[pos] = make_float4(p.x, p.y, p.z, __int_as_float(k));  // w: the pixel index
 }
 
 // ---------------------------------------------------------------------------
@@ -627,7 +730,12 @@ __global__ void k_parent_u(Cam cam, Meshes M, const float4* poses, const float* 
                            int* ucount, EvalParams ep) {
   // the parent objects' camera-to-object maps, once per workgroup (j <= 16 threads)
   __shared__ ObjMap s_om[kMaxObjects];
-  if ((int)threadIdx.x < j) s_om[threadIdx.x] = make_obj_map(cam, poses[po.o[threadIdx.x].y]);
+  __shared__ ObjMap64 s_dm[kMaxObjects];
+  if ((int)threadIdx.x < j) {
+    const float4 pz = poses[po.o[threadIdx.x].y];
+    s_om[threadIdx.x] = make_obj_map(cam, pz);
+    s_dm[threadIdx.x] = make_obj_map64(cam, pz);
+  }
   __syncthreads();
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   const int W = cam.W, H = cam.H;
@@ -639,18 +747,20 @@ __global__ void k_parent_u(Cam cam, Meshes M, const float4* poses, const float* 
       const float3 p = backproject(cam, i, jj, z);
       bool inV = false;
       for (int a = 0; a < j && !inV; ++a)
-        inV = in_volume(M, po.o[a].x, apply_obj_map(s_om[a], p));
+        inV = in_volume(cam, ep, M, po.o[a].x, s_om[a], s_dm[a], p, i, jj, z);
       if (!inV) {
         int ru, rv;
         window_radius(cam, ep, p, ru, rv);
+        const float tau = delta_margin(cam, z);
         bool expl = false;
         for (int jq = max(0, jj - rv); jq <= min(H - 1, jj + rv) && !expl; ++jq)
           for (int iq = max(0, i - ru); iq <= min(W - 1, i + ru); ++iq) {
             const unsigned kq = pdepth[jq * W + iq];
             if (kq == kInfBits) continue;
-            const float3 q = backproject(cam, iq, jq, __uint_as_float(kq));
+            const float zq = __uint_as_float(kq);
+            const float3 q = backproject(cam, iq, jq, zq);
             const float dx = q.x - p.x, dy = q.y - p.y, dz = q.z - p.z;
-            if (dx * dx + dy * dy + dz * dz <= cam.delta2) {
+            if (within_delta(cam, dx * dx + dy * dy + dz * dz, tau, iq, jq, zq, i, jj, z)) {
               expl = true;
               break;
             }
@@ -669,18 +779,25 @@ __global__ void k_parent_u(Cam cam, Meshes M, const float4* poses, const float* 
 // ---------------------------------------------------------------------------
 
 __global__ void k_parent_v(Cam cam, Meshes M, const float4* poses, const float* obs,
-                           ParentObjs po, int j, unsigned* vbits) {
+                           ParentObjs po, int j, unsigned* vbits, EvalParams ep) {
   __shared__ ObjMap s_om[kMaxObjects];  // as in k_parent_u
-  if ((int)threadIdx.x < j) s_om[threadIdx.x] = make_obj_map(cam, poses[po.o[threadIdx.x].y]);
+  __shared__ ObjMap64 s_dm[kMaxObjects];
+  if ((int)threadIdx.x < j) {
+    const float4 pz = poses[po.o[threadIdx.x].y];
+    s_om[threadIdx.x] = make_obj_map(cam, pz);
+    s_dm[threadIdx.x] = make_obj_map64(cam, pz);
+  }
   __syncthreads();
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  const int W = cam.W, H = cam.H;
+  const int W = cam.W;
   bool inV = false;
-  if (k < W * H) {
+  if (k < W * cam.H) {
     const float z = obs[k];
     if (z > 0.0f) {
-      const float3 p = backproject(cam, k % W, k / W, z);
-      for (int a = 0; a < j && !inV; ++a) inV = in_volume(M, po.o[a].x, apply_obj_map(s_om[a], p));
+      const int i = k % W, jj = k / W;
+      const float3 p = backproject(cam, i, jj, z);
+      for (int a = 0; a < j && !inV; ++a)
+        inV = in_volume(cam, ep, M, po.o[a].x, s_om[a], s_dm[a], p, i, jj, z);
     }
   }
   if (inV) atomicOr(&vbits[k >> 5], 1u << (k & 31));
@@ -707,7 +824,8 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
                                                int* __restrict__ out_status,
                                                int* __restrict__ out_comps,
                                                int* __restrict__ out_gain, unsigned char* smem,
-                                               int* s_bb, int* s_acc, float4* s_pl) {
+                                               int* s_bb, int* s_acc, float4* s_pl,
+                                               ObjMap64* s_dm) {
   const Cam& cam = S.cam;
   const Meshes& M = S.M;
   const float4* __restrict__ poses = S.poses;
@@ -731,6 +849,9 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
   const int mesh = cd.x;
   const float4 pz = poses[cd.y];
   const ObjMap om = make_obj_map(cam, pz);
+  // the FP64 map waits in LDS: only points inside the vertex box read it
+  if (tid == 0) *s_dm = make_obj_map64(cam, pz);
+  const ObjMap64& dm = *s_dm;
   const int4 rg = M.range[mesh];
   // snapped vertices: int2 (ep.vpack = 0) or relative to the footprint's corner in
   // 16 + 16 bits (ep.vpack = 1, meshes too large for int2)
@@ -849,7 +970,6 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
     }
     return;
   }
-  const float delta2 = cam.delta2;
   int n_dJr = 0, n_dJo = 0, n_rem = 0, n_gain = 0;  // wave-uniform ballot counts
   int n_cov = 0;  // covered core pixels (the silhouette), counted in the dJ pass when !P
 
@@ -866,18 +986,18 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
     // and rasterises 64 queued triangles at once, so lanes stay busy although most
     // triangles are back-facing or fall between pixel centres.
     {
-      const PoseMap pm = make_pose_map(cam, pz);
       auto raster_one = [&](unsigned t) {
         // queued triangles are front-facing with a pixel centre in their box, so
-        // the depth plane is set up for every lane at once, outside the pixel walk
+        // the depth plane is set up for every lane at once, outside the pixel walk;
+        // its vertices are the vertex stage's float32 camera-space vertices
         const int4 tr = M.tris[rg.z + t];
         const float4 v0 = M.verts[rg.x + tr.x], v1 = M.verts[rg.x + tr.y];
         const float4 v2 = M.verts[rg.x + tr.z];
         const int2 a = vert_uv(tr.x), b = vert_uv(tr.y), c = vert_uv(tr.z);
         float X0, Y0, Z0, X1, Y1, Z1, X2, Y2, Z2;
-        map_vertex(pm, v0, X0, Y0, Z0);
-        map_vertex(pm, v1, X1, Y1, Z1);
-        map_vertex(pm, v2, X2, Y2, Z2);
+        vcam(cam, pz, v0, X0, Y0, Z0);
+        vcam(cam, pz, v1, X1, Y1, Z1);
+        vcam(cam, pz, v2, X2, Y2, Z2);
         const Plane64 pl = make_plane(cam, X0, Y0, Z0, X1, Y1, Z1, X2, Y2, Z2);
         raster_tri(a.x, a.y, b.x, b.y, c.x, c.y, ca, cb, t0, t1, [&](int i, int j) {
           atomicMin(&tile[(j - t0) * tw + (i - ca)], __float_as_uint(plane_depth(pl, i, j)));
@@ -973,10 +1093,12 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
           const float3 q = backproject(cam, ii, jj, zq);
           const float3 p = backproject(cam, ii, jj, zo);
           const float ex = q.x - p.x, ey = q.y - p.y, ez = q.z - p.z;
-          const bool same = hq && hp && ex * ex + ey * ey + ez * ez <= delta2;
+          const float tq = hq ? delta_margin(cam, zq) : 0.0f;
+          const bool same = hq && hp &&
+                            within_delta(cam, ex * ex + ey * ey + ez * ez, tq, ii, jj, zq, ii, jj, zo);
           if (hq) {
             if (HQ && ep.radius_mode == 1) {
-              state = explained_by_cloud(hs, q.x, q.y, q.z, delta2) ? 1 : 2;
+              state = explained_by_cloud(cam, hs, q.x, q.y, q.z, ii, jj, tq) ? 1 : 2;
             } else if (same) {
               state = 1;
             } else {
@@ -987,16 +1109,17 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
           if (hp) {
             // separate calls, so that the staged copy is read as LDS (not flat)
             const float3 o = apply_obj_map(om, p);
-            inV = pl_lds ? in_volume_at(vlo, vhi, s_pl, fr.y, o)
-                         : in_volume_at(vlo, vhi, M.planes + fr.x, fr.y, o);
+            inV = pl_lds ? in_volume_at(cam, ep, dm, vlo, vhi, s_pl, fr.y, o, ii, jj, zo)
+                         : in_volume_at(cam, ep, dm, vlo, vhi, M.planes + fr.x, fr.y, o, ii, jj, zo);
             inU = goal && ((par.ubits[pix >> 5] >> (pix & 31)) & 1u);
             expl = same;
             if ((inV || inU) && !expl) {
               int ru, rv;
               window_radius(cam, ep, p, ru, rv);
+              const float tp = delta_margin(cam, zo);
               const int wja = max(t0, jj - rv), wjb = min(t1, jj + rv);
               const int wia = max(ca, ii - ru), wib = min(cb, ii + ru);
-              const float zlo = zo - cam.delta, zhi = zo + cam.delta;
+              const float zlo = zo - ep.dwin, zhi = zo + ep.dwin;
               // one flat walk over the clipped window, two pixels per step, stopping
               // after the first hit; the depth pre-test also skips +inf (no point)
               const int n = (wib - wia + 1) * (wjb - wja + 1);
@@ -1015,12 +1138,13 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
                   if (ina) {
                     const float3 q = backproject(cam, iq, jq, za);
                     const float ex = q.x - p.x, ey = q.y - p.y, ez = q.z - p.z;
-                    h = ex * ex + ey * ey + ez * ez <= delta2;
+                    h = within_delta(cam, ex * ex + ey * ey + ez * ez, tp, iq, jq, za, ii, jj, zo);
                   }
                   if (inb) {
                     const float3 q = backproject(cam, ib, jb, zb);
                     const float ex = q.x - p.x, ey = q.y - p.y, ez = q.z - p.z;
-                    h = h || ex * ex + ey * ey + ez * ez <= delta2;
+                    h = h ||
+                        within_delta(cam, ex * ex + ey * ey + ez * ez, tp, ib, jb, zb, ii, jj, zo);
                   }
                   expl = h;
                 }
@@ -1052,8 +1176,10 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
           if (two) und &= und - 1;
           const int ai = __shfl(ii, sa, 64), aj = __shfl(jj, sa, 64);
           const int bi = __shfl(ii, sb, 64), bj = __shfl(jj, sb, 64);
-          const float3 aq = backproject(cam, ai, aj, __shfl(zq, sa, 64));
-          const float3 bq = backproject(cam, bi, bj, __shfl(zq, sb, 64));
+          const float azq = __shfl(zq, sa, 64), bzq = __shfl(zq, sb, 64);
+          const float3 aq = backproject(cam, ai, aj, azq);
+          const float3 bq = backproject(cam, bi, bj, bzq);
+          const float ta = delta_margin(cam, azq), tb = delta_margin(cam, bzq);
           int aru, arv, bru, brv;
           window_radius(cam, ep, aq, aru, arv);
           window_radius(cam, ep, bq, bru, brv);
@@ -1083,12 +1209,12 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
             if (za > 0.0f) {
               const float3 p = backproject(cam, aii, ajj, za);
               const float dx = p.x - aq.x, dy = p.y - aq.y, dz = p.z - aq.z;
-              ha = dx * dx + dy * dy + dz * dz <= delta2;
+              ha = within_delta(cam, dx * dx + dy * dy + dz * dz, ta, ai, aj, azq, aii, ajj, za);
             }
             if (zb > 0.0f) {
               const float3 p = backproject(cam, bii, bjj, zb);
               const float dx = p.x - bq.x, dy = p.y - bq.y, dz = p.z - bq.z;
-              hb = dx * dx + dy * dy + dz * dz <= delta2;
+              hb = within_delta(cam, dx * dx + dy * dy + dz * dz, tb, bi, bj, bzq, bii, bjj, zb);
             }
             ahit = ahit || __ballot(ha) != 0ull;
             bhit = bhit || __ballot(hb) != 0ull;
@@ -1137,10 +1263,12 @@ __global__ void __launch_bounds__(NT)
   __shared__ int s_bb[4];
   __shared__ int s_acc[8];  // S, |dR|, dJ_r, dJ_o, removed-from-U, invalid, near-plane, gain
   __shared__ float4 s_pl[kLdsPlanes];
+  __shared__ ObjMap64 s_dm;
   const int s = blockIdx.x;
   if (s >= n) return;
   eval_successor<NT, false, VP, GAIN, HQ, G, P>(S, par, cands[s], s, out_cost, out_status,
-                                                out_comps, out_gain, smem, s_bb, s_acc, s_pl);
+                                                out_comps, out_gain, smem, s_bb, s_acc, s_pl,
+                                                &s_dm);
 }
 
 // Persistent workgroups over a work queue of (parent slot, mesh, pose) items that
@@ -1156,6 +1284,7 @@ __global__ void __launch_bounds__(NT, 4)  // at least 4 waves per SIMD: <= 128 V
   __shared__ int s_bb[4];
   __shared__ int s_acc[8];
   __shared__ float4 s_pl[kLdsPlanes];
+  __shared__ ObjMap64 s_dm;
   __shared__ int s_item;
   for (;;) {
     __syncthreads();  // the previous item is done with LDS
@@ -1186,7 +1315,7 @@ __global__ void __launch_bounds__(NT, 4)  // at least 4 waves per SIMD: <= 128 V
     eval_successor<NT, true, VP, false, HQ, G, P>(scenes[scene], par, make_int2(w.y, w.z),
                                                         it,
                                             out_cost, out_status, out_comps, nullptr, smem, s_bb,
-                                            s_acc, s_pl);
+                                            s_acc, s_pl, &s_dm);
   }
 }
 
@@ -1611,7 +1740,8 @@ void launch_parent_u(const Cam& cam, const Meshes& M, const float4* poses, const
 }
 
 void launch_parent_v(const Cam& cam, const Meshes& M, const float4* poses, const float* obs,
-                     const int* par_mesh_pose, int j, unsigned* vbits, hipStream_t s) {
+                     const int* par_mesh_pose, int j, unsigned* vbits, const EvalParams& ep,
+                     hipStream_t s) {
   ParentObjs po;
   for (int a = 0; a < kMaxObjects; ++a)
     po.o[a] = a < j ? make_int2(par_mesh_pose[2 * a], par_mesh_pose[2 * a + 1]) : make_int2(0, 0);
@@ -1619,7 +1749,7 @@ void launch_parent_v(const Cam& cam, const Meshes& M, const float4* poses, const
   launch_fill_u32(vbits, 0u, (size_t)(n + 31) / 32, s);
   if (j > 0)
     hipLaunchKernelGGL(k_parent_v, dim3((n + 255) / 256), dim3(256), 0, s, cam, M, poses, obs, po,
-                       j, vbits);
+                       j, vbits, ep);
 }
 
 template <class K>

@@ -174,3 +174,50 @@ def independent_edge_cost(scene_like, depth_obs, par_mesh, par_pose, cand_mesh, 
         res = int(np.sum(d_k * d_k > delta * delta))
     S = int(np.isfinite(D_o).sum())
     return True, dJr + dJo + res, (S, len(Q), dJr, dJo, res), n_near
+
+
+def independent_near_counts(scene_like, depth_obs, par_mesh, par_pose, cand_mesh, cand_pose, K,
+                            o: Oracle, band=1e-6):
+    """Upper bounds, by KD-tree and numpy, of the oracle's three flags for one
+    successor: (depth tie, near-delta count, near-volume count).
+      - tie: some pixel where candidate and parent depths are both finite and within
+        `band` (the flag_valid rule);
+      - near-delta: points whose distance to the cloud they are tested against lies
+        within `band` of delta, over the sets the oracle tests: dR against I; the
+        observed points inside or near V(O) against dR; at the goal level the points
+        outside (or near) the candidate's and the parents' volumes against R_K;
+      - near-volume: observed points within `band` of the candidate's volume
+        boundary, plus (goal level) those within `band` of a parent's.
+    The oracle counts only the points whose flip would change the edge cost, so its
+    counts must not exceed these."""
+    sensor, lib, poses = scene_like.sensor, scene_like.library, scene_like.poses
+    delta = np.float64(np.float32(sensor.delta))
+    D_par = np.full((sensor.H, sensor.W), np.inf)
+    if len(par_mesh):
+        D_par = o.render_objects(par_mesh, par_pose).min(0)
+    D_o = o.render_objects([cand_mesh], [cand_pose])[0]
+    both = np.isfinite(D_o) & np.isfinite(D_par)
+    tie = bool(np.any(np.abs(D_o[both] - D_par[both]) <= band))
+    dR = np.where(np.isfinite(D_par), np.inf, D_o)
+    I, _ = observed_points(sensor, depth_obs)
+    Iw = world_from_cam(sensor, I)
+    Q, _ = backproject_image(sensor, dR)
+    near = lambda d: np.abs(d - delta) <= band  # noqa: E731
+    n_delta = int(near(min_dist(Q, I)).sum())
+    vm = vol_margin(lib.meshes[cand_mesh], poses[cand_pose], Iw)
+    inV, nearV = vm <= 0, np.abs(vm) <= band
+    n_vol = int(nearV.sum())
+    n_delta += int(near(min_dist(I[inV | nearV], Q)).sum())
+    if len(par_mesh) + 1 == K:
+        inVp = np.zeros(len(I), bool)
+        nearVp = np.zeros(len(I), bool)
+        for m, p in zip(par_mesh, par_pose):
+            vmp = vol_margin(lib.meshes[m], poses[p], Iw)
+            n_vol += int((np.abs(vmp) <= band).sum())
+            inVp |= vmp <= 0
+            nearVp |= np.abs(vmp) <= band
+        tested = (~inV & ~inVp) | (nearV & ~inVp) | (nearVp & ~inV)
+        RK = np.where(np.isfinite(D_par), D_par, dR)
+        QK, _ = backproject_image(sensor, RK)
+        n_delta += int(near(min_dist(I[tested], QK)).sum())
+    return tie, n_delta, n_vol

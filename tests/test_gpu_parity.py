@@ -52,8 +52,14 @@ def compare(g, o, label=""):
     cov = both & np.any(comps_g[:, :2] != comps_o[:, :2], axis=1)
     assert not cov.any(), f"{label}: coverage counts differ at {np.nonzero(cov)[0][:10]}"
     assert np.all(st_g >= 0), f"{label}: error status {np.unique(st_g)}"
-    return dict(n=len(st_g), valid=int(both.sum()), flagged=int((both & (tol > 0)).sum()),
-                flag_diff=int((both & (d > 0)).sum()))
+    flagged = int((both & (tol > 0)).sum())
+    flag_diff = int((both & (d > 0)).sum())
+    # a difference only where the oracle flags a near-tie, and flags stay rare (the
+    # oracle's flags are pinned against independent near counts on the CPU)
+    assert flag_diff <= flagged
+    nv = int(both.sum())  # about 1-2 % at 640 x 480; binomial slack for small samples
+    assert flagged <= 0.03 * nv + 4.0 * np.sqrt(0.03 * nv) + 3, (label, flagged, nv)
+    return dict(n=len(st_g), valid=int(both.sum()), flagged=flagged, flag_diff=flag_diff)
 
 
 @pytest.fixture(scope="module")
@@ -207,6 +213,11 @@ def test_640x480_levels_sampled(c2):
         s = compare(tuple(a[idx] for a in g), r, f"c2 level {level + 1}")
         assert s["valid"] > 0
         assert g[0][gt_idx[0]] == 1
+        # the voxel-hash radius query (radius mode 1) on the same sample
+        ctx.set_tuning(0, 0, 0.0, 1)
+        gh = _gpu_eval(ctx, par, ms[idx], ps[idx])
+        ctx.set_tuning(0, 0, 0.0, 0)
+        compare(gh, r, f"c2 level {level + 1}, voxel hash")
 
 
 def test_640x480_banded_tiles_match(c2):
@@ -260,6 +271,10 @@ def test_full_config_levels_sampled(c5):
         r = o.eval([p[0] for p in par], [p[1] for p in par], ms[idx], ps[idx])
         s = compare(tuple(a[idx] for a in g), r, f"c5 level {level + 1}")
         assert s["valid"] > 0
+        ctx.set_tuning(0, 0, 0.0, 1)  # voxel-hash radius query on the sample
+        gh = _gpu_eval(ctx, par, ms[idx], ps[idx])
+        ctx.set_tuning(0, 0, 0.0, 0)
+        compare(gh, r, f"c5 level {level + 1}, voxel hash")
 
 
 @pytest.mark.parametrize("large_library", [False, True])
@@ -338,3 +353,40 @@ def test_overlap_gain_matches_oracle(c1, level):
     d = np.abs(gain[valid] - (h0 - hc[valid]))
     assert np.all(d <= fl[valid]), (np.nonzero(d > fl[valid])[0][:5])
     assert np.mean(gain[valid] > 0) > 0.05  # the test sees real overlaps
+
+
+def test_status_near_plane_and_too_wide():
+    """Status -2: a vertex within 1 cm of the camera plane (a box taller than the
+    camera's height above the table, seen straight down); status -3: a footprint
+    wider than the z-tile allows (a 256-pixel tile).  Both leave cost and components
+    at -1; the other successors of the launch are unaffected."""
+    cam = H.down_camera(W=160, H=120, f=100.0, height=0.30, delta=0.01)
+    tall = scenes.make_box((0.05, 0.05, 0.35), 48)
+    low = scenes.make_box((0.05, 0.05, 0.05), 48)
+    lib = scenes.Library([tall, low])
+    poses = np.array([[0.0, 0.0, 1.0, 0.0], [0.1, 0.0, 1.0, 0.0]], np.float32)
+    depth = np.full((cam.H, cam.W), 0.30, np.float32)
+    ctx = perch.Context(cam)
+    for m, mesh in enumerate(lib.meshes):
+        ctx.add_mesh(m, mesh.verts, mesh.tris, mesh.planes)
+    ctx.set_poses(poses)
+    ctx.set_objects([0, 1])
+    ctx.set_observation(torch.as_tensor(depth).cuda())
+    st, cost, comps = _gpu_eval(ctx, [], [0, 1, 0], [0, 1, 1])
+    assert st.tolist() == [perch.PERCH_SUCC_NEAR_PLANE, 1, perch.PERCH_SUCC_NEAR_PLANE]
+    assert cost[0] == -1 and np.all(comps[0] == -1) and cost[1] >= 0
+    # the oracle refuses the same vertex stage (its near-plane error)
+    o = Oracle(cam, lib, poses, [0, 1], depth)
+    with pytest.raises(Exception):
+        o.eval([], [], [0], [0])
+    # a 640 x 480 footprint cannot fit a 256-pixel tile with the window halo
+    sc = H.c2_scene(0)
+    ctx2 = perch.context_from_scene(sc)
+    m = int(sc.obj_mesh[sc.gt_order[0]])
+    gtp = int(sc.gt_pose[sc.gt_order[0]])
+    ref = _gpu_eval(ctx2, [], [m, m], [gtp, 0])
+    ctx2.set_tuning(0, 256, 0.0, -1)
+    st2, cost2, comps2 = _gpu_eval(ctx2, [], [m, m], [gtp, 0])
+    ctx2.set_tuning(0, -1, 0.0, -1)
+    assert ref[0][0] == 1
+    assert st2[0] == perch.PERCH_SUCC_TOO_WIDE and cost2[0] == -1 and np.all(comps2[0] == -1)

@@ -296,3 +296,49 @@ def test_additivity_with_occlusion_640x480():
     assert n_invalid > 0 and totals
     assert all(t == r["J_tree"] for t in totals)
     assert r["J_tree"] >= r["J_raw"]
+
+
+def _flag_pin(sc, o, cases):
+    """Per successor: the oracle's depth-tie flag equals the independent one, and its
+    near-delta and near-volume counts do not exceed the independent near counts (a
+    wider band, or flags on points whose decision is not near its threshold, fail)."""
+    n_flagged = 0
+    for pm, pp, m, p in cases:
+        st, cost, comps, flags = o.eval(pm, pp, [m], [p])
+        tie, nd, nv = H.independent_near_counts(sc, sc.depth_obs, pm, pp, m, p, sc.K, o)
+        assert bool(flags[0, 2]) == tie, (pm, pp, m, p)
+        assert flags[0, 0] <= nd, (pm, pp, m, p, flags[0], nd)
+        assert flags[0, 1] <= nv, (pm, pp, m, p, flags[0], nv)
+        n_flagged += int(flags[0, 0] + flags[0, 1] > 0)
+    return n_flagged
+
+
+def test_flags_bounded_by_independent_near_counts_160x120():
+    for i in range(3):
+        sc = H.c1_scene(i)
+        o = Oracle.from_scene(sc)
+        rng = np.random.default_rng(300 + i)
+        cases = _random_successors(sc, rng, 25, 1) + _random_successors(sc, rng, 25, 2)
+        _flag_pin(sc, o, cases)
+
+
+def test_flags_bounded_by_independent_near_counts_640x480():
+    """Successors drawn so that flagged ones are among them: 400 seeded candidates per
+    level are screened by the oracle, and every flagged one (about 1-2 %) plus a few
+    unflagged ones are re-counted independently."""
+    sc = H.c2_scene(0)
+    o = Oracle.from_scene(sc, nthreads=8)
+    rng = np.random.default_rng(17)
+    order = sc.gt_order
+    cases = []
+    for level in (1, 2, 3):
+        pm = [int(sc.obj_mesh[k]) for k in order[:level - 1]]
+        pp = [int(sc.gt_pose[k]) for k in order[:level - 1]]
+        rest = sorted({int(sc.obj_mesh[k]) for k in order[level - 1:]})
+        ms = rng.choice(rest, 400)
+        ps = rng.integers(sc.grid.P, size=400)
+        st, cost, comps, flags = o.eval(pm, pp, ms, ps)
+        flagged = np.nonzero(flags.sum(1) > 0)[0][:6]
+        plain = np.nonzero(flags.sum(1) == 0)[0][:2]
+        cases += [(pm, pp, int(ms[k]), int(ps[k])) for k in np.concatenate([flagged, plain])]
+    assert _flag_pin(sc, o, cases) >= 3
