@@ -42,6 +42,11 @@
 #include <string.h>
 
 #define FLAG_EPS 1e-6 /* near-tie band (metres) for the flags */
+/* ICP association near-ties, in metres (radius tests) and pixels (rounding of a
+ * projection to the nearest pixel): the association is FP64 on both sides, which
+ * differ only by FP64 rounding, far inside these bands */
+#define ICP_FLAG_EPS 1e-9
+#define ICP_FLAG_PX 1e-9
 #define ORC_MAX_K 16   /* most objects in a scene */
 
 struct orc_scene {
@@ -774,16 +779,16 @@ int orc_icp_step(int32_t n, const double* a, const double* p, const double* nrm,
   return 0;
 }
 
-static int near_half(double f) { /* f within 1e-4 px of a rounding boundary */
+static int near_half(double f) { /* f within ICP_FLAG_PX of a rounding boundary */
   const double r = f - floor(f);
-  return fabs(r - 0.5) < 1e-4;
+  return fabs(r - 0.5) < ICP_FLAG_PX;
 }
 
 /* Surface normal of the observed point at pixel (u, v), world frame, unit length
  * and facing the camera: the cross product of the central differences of its four
  * pixel neighbours, which must all be observed and within `radius` of it.
  * Returns 0 when there is none; *near is set when a neighbour's distance lies
- * within FLAG_EPS of the radius. */
+ * within ICP_FLAG_EPS of the radius. */
 static int observed_normal(const orc_scene* sc, int u, int v, double radius, double* n,
                            int* near) {
   const int W = sc->W, H = sc->H;
@@ -796,7 +801,7 @@ static int observed_normal(const orc_scene* sc, int u, int v, double radius, dou
   int ok = 1;
   for (int k = 0; k < 4; ++k) {
     const double dk = sqrt(d2(pc, sc->I_w + 3 * (size_t)nb[k]));
-    if (fabs(dk - radius) <= FLAG_EPS) *near = 1;
+    if (fabs(dk - radius) <= ICP_FLAG_EPS) *near = 1;
     if (dk > radius) ok = 0;
   }
   if (!ok) return 0;
@@ -853,7 +858,10 @@ static int icp_one(const orc_scene* sc, const double* Dp, int mesh, int pose, in
     *flags = fl;
     return 0;
   }
-  /* model points: the non-occluded part dR, in the world frame */
+  /* model points: the non-occluded part dR, in the world frame, back-projected from
+   * the rendered depth as a float32 depth image holds it (reading: Sec. V-A aligns
+   * the rendered object, and a rendered depth image is float32 like the observed
+   * one) */
   double* Q = (double*)malloc(sizeof(double) * 3 * (size_t)(nq + 1));
   double* A = (double*)malloc(sizeof(double) * 9 * (size_t)(nq + 1));
   if (!Q || !A) {
@@ -868,7 +876,7 @@ static int icp_one(const orc_scene* sc, const double* Dp, int mesh, int pose, in
       const size_t i = (size_t)v * W + u;
       if (!(w->DO[i] < INFINITY) || Dp[i] < INFINITY) continue;
       double q[3], d[3];
-      backproject(sc, u, v, w->DO[i], q);
+      backproject(sc, u, v, (double)(float)w->DO[i], q);
       for (int r = 0; r < 3; ++r) d[r] = q[r] - sc->t[r];
       for (int r = 0; r < 3; ++r)
         Q[3 * m + r] = sc->Rinv[3 * r] * d[0] + sc->Rinv[3 * r + 1] * d[1] + sc->Rinv[3 * r + 2] * d[2];
@@ -901,7 +909,7 @@ static int icp_one(const orc_scene* sc, const double* Dp, int mesh, int pose, in
       if (!has_n) continue;
       const double* p = sc->I_w + 3 * (size_t)pt;
       const double dd = d2(a, p);
-      if (fabs(sqrt(dd) - radius) <= FLAG_EPS) ++fl;
+      if (fabs(sqrt(dd) - radius) <= ICP_FLAG_EPS) ++fl;
       if (dd > r2) continue;
       for (int r = 0; r < 3; ++r) {
         A[3 * nm + r] = a[r];

@@ -233,7 +233,10 @@ perch_status perch_create(const perch_sensor* s, void* hip_stream, perch_ctx** o
   cam.fy = s->fy;
   cam.cx = s->cx;
   cam.cy = s->cy;
-  for (int k = 0; k < 12; ++k) cam.M[k] = s->cam_from_world[k];
+  for (int k = 0; k < 12; ++k) {
+    cam.M[k] = s->cam_from_world[k];
+    cam.dM[k] = s->cam_from_world[k];
+  }
   for (int r = 0; r < 3; ++r) {
     for (int k = 0; k < 3; ++k) cam.Winv[4 * r + k] = (float)Ri[3 * r + k];
     cam.Winv[4 * r + 3] = (float)(-(Ri[3 * r] * t[0] + Ri[3 * r + 1] * t[1] + Ri[3 * r + 2] * t[2]));
@@ -571,8 +574,8 @@ perch_status perch_icp_children(perch_ctx* c, const perch_object* cands_dev, int
   if (n == 0) return PERCH_OK;
   const size_t npx = (size_t)c->cam.W * c->cam.H;
   if (c->icp_pn_obs != c->obs_serial || c->icp_pn_radius != radius) {
-    HIP_TRY(c->icp_pn.ensure(2 * npx * sizeof(float4)));
-    launch_obs_normals(c->cam, c->obs.as<float>(), radius, c->icp_pn.as<float4>(), c->stream);
+    HIP_TRY(c->icp_pn.ensure(2 * npx * sizeof(double4)));
+    launch_obs_normals(c->cam, c->obs.as<float>(), radius, c->icp_pn.as<double4>(), c->stream);
     HIP_TRY(hipGetLastError());
     c->icp_pn_obs = c->obs_serial;
     c->icp_pn_radius = radius;
@@ -589,7 +592,7 @@ perch_status perch_icp_children(perch_ctx* c, const perch_object* cands_dev, int
   IcpArgs ia;
   ia.iters = iters;
   ia.radius = radius;
-  ia.pn = c->icp_pn.as<float4>();
+  ia.pn = c->icp_pn.as<double4>();
   ia.base = c->P + c->arena_used;
   ia.arena = c->poses.as<float4>() + ia.base;
   ia.retry = 0;

@@ -21,6 +21,7 @@ struct perch_batch {
   DevBuf scenes, parents, slot_depth, slot_ubits, slot_ucount, counter;
   int n_parents = 0;
   int flags = 0;  // kBatchHash | kBatchGoal | kBatchParent over the current tables
+  int table_tile = -1;  // z-tile the uploaded scene table carries (-1: none uploaded)
   size_t npx_max = 0;
   int threads = 512;
   int tile_px = 0;  // 0 = sized automatically (auto_tile_px)
@@ -35,6 +36,7 @@ struct perch_batch {
   int g_threads = 0, g_tile = 0, g_grid = 0, g_parents = -1, g_flags = -1;
   const void* g_ptab = nullptr;
 
+  std::vector<SceneDev> h_scenes;  // host copy of the scene table (kept: copies are async)
   int max_nv() const {
     int m = 0;
     for (perch_ctx* c : ctxs) m = std::max(m, c->max_nv);
@@ -50,6 +52,27 @@ struct perch_batch {
     g_items = nullptr;
   }
 };
+
+// Uploads the scene table with the tuning now in force (the z-tile the kernel
+// places in LDS travels in each scene's parameters); *flags gets kBatchHash when a
+// scene answers dJ_r by the voxel hash.  Asynchronous on the batch's stream.
+static perch_status upload_scene_table(perch_batch* b, int* flags) {
+  std::vector<SceneDev>& sd = b->h_scenes;
+  sd.resize(b->ctxs.size());
+  const int max_nv = b->max_nv();
+  *flags = 0;
+  for (size_t k = 0; k < b->ctxs.size(); ++k) {
+    sd[k] = b->ctxs[k]->scene_dev();
+    sd[k].ep.tile_px = b->tile();
+    sd[k].ep.max_nv = max_nv;
+    sd[k].ep.vpack = vertex_cache_packed(max_nv);
+    *flags |= sd[k].ep.radius_mode == 1 ? kBatchHash : 0;
+  }
+  HIP_TRY(hipMemcpyAsync(b->scenes.p, sd.data(), sizeof(SceneDev) * sd.size(),
+                         hipMemcpyHostToDevice, b->stream));
+  b->table_tile = b->tile();
+  return PERCH_OK;
+}
 
 extern "C" {
 
@@ -150,23 +173,15 @@ perch_status perch_batch_set_parents(perch_batch* b, const perch_parent* parents
     pd[k].scene = p.ctx;
     pd[k].pad = 0;
   }
-  std::vector<SceneDev> sd(b->ctxs.size());
-  const int max_nv = b->max_nv();
-  for (size_t k = 0; k < b->ctxs.size(); ++k) {
-    sd[k] = b->ctxs[k]->scene_dev();
-    sd[k].ep.tile_px = b->tile();
-    sd[k].ep.max_nv = max_nv;
-    sd[k].ep.vpack = vertex_cache_packed(max_nv);
-    flags |= sd[k].ep.radius_mode == 1 ? kBatchHash : 0;
-  }
   HIP_TRY(hipMemcpyAsync(b->parents.p, pd.data(), sizeof(ParentDev) * pd.size(),
                          hipMemcpyHostToDevice, b->stream));
-  HIP_TRY(hipMemcpyAsync(b->scenes.p, sd.data(), sizeof(SceneDev) * sd.size(),
-                         hipMemcpyHostToDevice, b->stream));
+  int hash = 0;
+  perch_status st = upload_scene_table(b, &hash);
+  if (st) return st;
   // the host vectors die here: the copies must complete first
   HIP_TRY(hipStreamSynchronize(b->stream));
   b->n_parents = n;
-  b->flags = flags;
+  b->flags = flags | hash;
   return PERCH_OK;
 }
 
@@ -176,8 +191,17 @@ perch_status perch_batch_eval(perch_batch* b, const perch_work* items_dev, int32
   if (n < 0 || (n > 0 && (!items_dev || !cost_dev || !status_dev)))
     return fail(PERCH_E_ARG, "bad work arrays");
   if (n == 0) return PERCH_OK;
+  if (b->table_tile < 0) return fail(PERCH_E_STATE, "perch_batch_set_parents not called");
   const size_t lds = b->lds_bytes();
   if (lds > 160 * 1024 - 256) return fail(PERCH_E_UNSUPPORTED, "LDS need %zu B too large", lds);
+  if (b->table_tile != b->tile()) {
+    // the tuning changed the z-tile since the scene table was written: the kernel
+    // must place its tile in the LDS this launch gives it
+    int hash = 0;
+    perch_status st = upload_scene_table(b, &hash);
+    if (st) return st;
+    HIP_TRY(hipStreamSynchronize(b->stream));  // the host table is reused by the next upload
+  }
   // resolve the persistent grid and the LDS limit outside any capture
   int grid = b->grid;
   {

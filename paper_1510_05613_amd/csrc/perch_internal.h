@@ -19,6 +19,7 @@ struct Cam {
   double dfx, dfy, dcx, dcy;  // the same intrinsics widened to FP64 (depth planes)
   double dinv_fx, dinv_fy;
   double dWinv[12];  // world_from_cam in FP64 (near-boundary volume decisions)
+  double dM[12];     // cam_from_world widened to FP64 (the ICP association)
   double ddelta2;    // delta^2 in FP64 of the float32 delta (near-threshold distance decisions)
   // Margin of the float32 distance test |q - p|^2 <= delta^2 (see delta_margin):
   // tau(z) = t_lin z + t_0 + 4 (t_a z + t_s)^2 for a fixed point at depth z.
@@ -149,14 +150,14 @@ constexpr int kIcpThreads = 512;
 struct IcpArgs {
   int iters;
   float radius;       // association radius (metres)
-  const float4* pn;   // per pixel: world point (w = 1 with a normal), unit normal
+  const double4* pn;  // per pixel: world point (w = 1 with a normal), unit normal (FP64)
   float4* arena;      // adjusted poses, one per candidate
   int base;           // pose index of arena[0]
   int retry;          // 1: only candidates whose status is -3 (footprint beyond the
                       // previous pass's tile); the others exit at once
 };
-// pn (2 float4 per pixel) from the observation for association radius `radius`
-void launch_obs_normals(const Cam& cam, const float* obs, float radius, float4* pn,
+// pn (2 double4 per pixel) from the observation for association radius `radius`
+void launch_obs_normals(const Cam& cam, const float* obs, float radius, double4* pn,
                         hipStream_t s);
 // kIcpThreads threads per candidate; lds = vertex cache (int2, when vertex_cache)
 // + tile + rings

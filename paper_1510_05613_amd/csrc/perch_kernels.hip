@@ -1323,49 +1323,54 @@ __global__ void __launch_bounds__(NT, 4)  // at least 4 waves per SIMD: <= 128 V
 // local ICP (Sec. V-A): compensating for the pose discretization
 // ---------------------------------------------------------------------------
 
-// Per observed pixel: the world point (w = 1 when it has a surface normal, else 0;
-// 0 everywhere for pixels without a return) and its unit normal facing the camera,
-// from the cross product of the central differences of its four pixel neighbours,
-// all observed and within `radius` of it.
+// Per observed pixel, in FP64: the world point p = Rinv (q - t) of its
+// back-projection q (w = 1 when it has a surface normal, else 0; 0 everywhere for
+// pixels without a return) and its unit normal facing the camera, from the cross
+// product of the central differences of its four pixel neighbours, all observed
+// and within `radius` of it.  FP64 keeps the association of the ICP rounds the
+// same decisions as exact arithmetic, up to FP64 rounding.
+__device__ __forceinline__ double3 world_point64(const Cam& cam, int i, int j, float z) {
+  const double dz = z;
+  const double q0 = ((double)i - cam.dcx) * dz * cam.dinv_fx - cam.dM[3];
+  const double q1 = ((double)j - cam.dcy) * dz * cam.dinv_fy - cam.dM[7];
+  const double q2 = dz - cam.dM[11];
+  const double* R = cam.dWinv;
+  return make_double3(R[0] * q0 + R[1] * q1 + R[2] * q2, R[4] * q0 + R[5] * q1 + R[6] * q2,
+                      R[8] * q0 + R[9] * q1 + R[10] * q2);
+}
+
 __global__ void k_obs_normals(Cam cam, const float* __restrict__ obs, float radius,
-                              float4* __restrict__ pn) {
+                              double4* __restrict__ pn) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= cam.W * cam.H) return;
   const int u = k % cam.W, v = k / cam.W;
-  auto world = [&](int i, int j, float z) {
-    const float3 q = backproject(cam, i, j, z);
-    const float* A = cam.Winv;
-    return make_float3(A[0] * q.x + A[1] * q.y + A[2] * q.z + A[3],
-                       A[4] * q.x + A[5] * q.y + A[6] * q.z + A[7],
-                       A[8] * q.x + A[9] * q.y + A[10] * q.z + A[11]);
-  };
   const float z = obs[k];
-  float4 P = make_float4(0.f, 0.f, 0.f, 0.f), N = make_float4(0.f, 0.f, 0.f, 0.f);
+  double4 P = make_double4(0.0, 0.0, 0.0, 0.0), N = make_double4(0.0, 0.0, 0.0, 0.0);
   if (z > 0.0f) {
-    const float3 c = world(u, v, z);
-    P = make_float4(c.x, c.y, c.z, 0.0f);
+    const double3 c = world_point64(cam, u, v, z);
+    P = make_double4(c.x, c.y, c.z, 0.0);
     if (u >= 1 && v >= 1 && u <= cam.W - 2 && v <= cam.H - 2) {
       const float z1 = obs[k + 1], z0 = obs[k - 1], z3 = obs[k + cam.W], z2 = obs[k - cam.W];
       if (z0 > 0.0f && z1 > 0.0f && z2 > 0.0f && z3 > 0.0f) {
-        const float3 a1 = world(u + 1, v, z1), a0 = world(u - 1, v, z0);
-        const float3 b1 = world(u, v + 1, z3), b0 = world(u, v - 1, z2);
-        const float r2 = radius * radius;
-        auto dist2 = [&](float3 p) {
-          const float dx = p.x - c.x, dy = p.y - c.y, dz = p.z - c.z;
-          return dx * dx + dy * dy + dz * dz;
+        const double3 a1 = world_point64(cam, u + 1, v, z1), a0 = world_point64(cam, u - 1, v, z0);
+        const double3 b1 = world_point64(cam, u, v + 1, z3), b0 = world_point64(cam, u, v - 1, z2);
+        const double r = radius;
+        auto dist = [&](double3 p) {
+          const double dx = c.x - p.x, dy = c.y - p.y, dz = c.z - p.z;
+          return sqrt(dx * dx + dy * dy + dz * dz);
         };
-        if (dist2(a1) <= r2 && dist2(a0) <= r2 && dist2(b1) <= r2 && dist2(b0) <= r2) {
-          const float ex = a1.x - a0.x, ey = a1.y - a0.y, ez = a1.z - a0.z;
-          const float fx = b1.x - b0.x, fy = b1.y - b0.y, fz = b1.z - b0.z;
-          float nx = ey * fz - ez * fy, ny = ez * fx - ex * fz, nz = ex * fy - ey * fx;
-          const float len = sqrtf(nx * nx + ny * ny + nz * nz);
-          if (len > 0.0f) {
+        if (dist(a1) <= r && dist(a0) <= r && dist(b1) <= r && dist(b0) <= r) {
+          const double ex = a1.x - a0.x, ey = a1.y - a0.y, ez = a1.z - a0.z;
+          const double fx = b1.x - b0.x, fy = b1.y - b0.y, fz = b1.z - b0.z;
+          const double nx = ey * fz - ez * fy, ny = ez * fx - ex * fz, nz = ex * fy - ey * fx;
+          const double len = sqrt(nx * nx + ny * ny + nz * nz);
+          if (len > 0.0) {
             // towards the camera centre (world_from_cam's translation)
-            const float tw = nx * (cam.Winv[3] - c.x) + ny * (cam.Winv[7] - c.y) +
-                             nz * (cam.Winv[11] - c.z);
-            const float sg = (tw < 0.0f ? -1.0f : 1.0f) / len;
-            N = make_float4(nx * sg, ny * sg, nz * sg, 0.0f);
-            P.w = 1.0f;
+            const double tw = nx * (cam.dWinv[3] - c.x) + ny * (cam.dWinv[7] - c.y) +
+                              nz * (cam.dWinv[11] - c.z);
+            const double sg = tw < 0.0 ? -1.0 : 1.0;
+            N = make_double4(sg * nx / len, sg * ny / len, sg * nz / len, 0.0);
+            P.w = 1.0;
           }
         }
       }
@@ -1373,6 +1378,34 @@ __global__ void k_obs_normals(Cam cam, const float* __restrict__ obs, float radi
   }
   pn[2 * (size_t)k] = P;
   pn[2 * (size_t)k + 1] = N;
+}
+
+// cos and sin of x in FP64 without a library call: x is halved until |x| <= 1/4,
+// the Taylor series of both (to x^17, truncation below 1e-20) is summed, and the
+// double-angle formulas undo the halvings (each at most doubles the relative
+// rounding error: a few 1e-15 for ICP's steps).
+__device__ __forceinline__ void cos_sin64(double x, double& c, double& s) {
+  int h = 0;
+  while (fabs(x) > 0.25 && h < 64) {
+    x *= 0.5;
+    ++h;
+  }
+  const double x2 = x * x;
+  double cs = 1.0, sn = 1.0, tc = 1.0, ts = 1.0;
+  for (int k = 1; k <= 8; ++k) {  // terms x^(2k) / (2k)! and x^(2k+1) / (2k+1)!
+    tc *= -x2 / ((2.0 * k - 1.0) * (2.0 * k));
+    ts *= -x2 / ((2.0 * k) * (2.0 * k + 1.0));
+    cs += tc;
+    sn += ts;
+  }
+  sn *= x;
+  for (int k = 0; k < h; ++k) {
+    const double c2 = cs * cs - sn * sn, s2 = 2.0 * sn * cs;
+    cs = c2;
+    sn = s2;
+  }
+  c = cs;
+  s = sn;
 }
 
 // Raw sums of one association round, reduced over the workgroup: matches, the
@@ -1397,7 +1430,7 @@ __global__ void __launch_bounds__(NT, 4)  // at least 4 waves per SIMD: two work
   __shared__ int s_bb[4];
   __shared__ int s_flag[3];  // vertex stage failed, occludes the parent, stop
   __shared__ double s_red[NT / 64][kIcpSums];
-  __shared__ float s_T[4];   // cos phi, sin phi, tx, ty of the motion so far
+  __shared__ double s_T[4];  // cos phi, sin phi, tx, ty of the motion so far
   __shared__ int s_nm;
   const int s = blockIdx.x;
   if (s >= n) return;
@@ -1426,8 +1459,8 @@ __global__ void __launch_bounds__(NT, 4)  // at least 4 waves per SIMD: two work
   if (tid < 4) s_bb[tid] = tid < 2 ? INT_MAX : INT_MIN;
   if (tid < 3) s_flag[tid] = 0;
   if (tid == 0) {
-    s_T[0] = 1.0f;
-    s_T[1] = s_T[2] = s_T[3] = 0.0f;
+    s_T[0] = 1.0;
+    s_T[1] = s_T[2] = s_T[3] = 0.0;
     s_nm = 0;
   }
   __syncthreads();
@@ -1495,16 +1528,15 @@ __global__ void __launch_bounds__(NT, 4)  // at least 4 waves per SIMD: two work
   __syncthreads();
   // rasterise (front faces queued per wave as in the successor kernel)
   {
-    const PoseMap pm = make_pose_map(cam, pz);
     auto raster_one = [&](unsigned t) {
       const int4 tr = M.tris[rg.z + t];
       const float4 v0 = M.verts[rg.x + tr.x], v1 = M.verts[rg.x + tr.y];
       const float4 v2 = M.verts[rg.x + tr.z];
       const int2 a = vert_uv(tr.x), b = vert_uv(tr.y), c = vert_uv(tr.z);
       float X0, Y0, Z0, X1, Y1, Z1, X2, Y2, Z2;
-      map_vertex(pm, v0, X0, Y0, Z0);
-      map_vertex(pm, v1, X1, Y1, Z1);
-      map_vertex(pm, v2, X2, Y2, Z2);
+      vcam(cam, pz, v0, X0, Y0, Z0);
+      vcam(cam, pz, v1, X1, Y1, Z1);
+      vcam(cam, pz, v2, X2, Y2, Z2);
       const Plane64 pl = make_plane(cam, X0, Y0, Z0, X1, Y1, Z1, X2, Y2, Z2);
       raster_tri(a.x, a.y, b.x, b.y, c.x, c.y, ca, cb, ra, rb, [&](int i, int j) {
         atomicMin(&tile[(j - ra) * tw + (i - ca)], __float_as_uint(plane_depth(pl, i, j)));
@@ -1554,44 +1586,44 @@ __global__ void __launch_bounds__(NT, 4)  // at least 4 waves per SIMD: two work
     finish(0, 0, pz);
     return;
   }
-  // ICP rounds; thread 0 keeps the motion in FP64
-  double phi = 0.0, mtx = 0.0, mty = 0.0;
-  const float r2 = ia.radius * ia.radius;
-  const float ox = pz.x, oy = pz.y;  // local origin of the sums
-  const float* Wi = cam.Winv;
+  // ICP rounds in FP64, as exact arithmetic up to FP64 rounding: each model point
+  // (the back-projection of its float32 depth, world frame) is moved by the
+  // motion so far, projected, and paired with the observed point at the nearest
+  // pixel; thread 0 solves for the step
+  double cphi = 1.0, sphi = 0.0, mtx = 0.0, mty = 0.0;  // the motion so far
+  const double r2 = (double)ia.radius * (double)ia.radius;
+  const double ox = pz.x, oy = pz.y;  // local origin of the sums
   for (int it = 0; it < ia.iters; ++it) {
-    const float cT = s_T[0], sT = s_T[1], txT = s_T[2], tyT = s_T[3];
-    // per-lane partial sums of about a dozen points in float32; FP64 from the wave
-    // reduction on
-    float acc[kIcpSums];
-    for (int q = 0; q < kIcpSums; ++q) acc[q] = 0.0f;
+    const double cT = s_T[0], sT = s_T[1], txT = s_T[2], tyT = s_T[3];
+    double acc[kIcpSums];
+    for (int q = 0; q < kIcpSums; ++q) acc[q] = 0.0;
+#pragma unroll 1
     for (int k = tid; k < tn; k += NT) {
       const unsigned key = tile[k];
       if (key == kInfBits) continue;
       const int r = (int)(((float)k + 0.5f) * inv_tw);
       const int jj = ra + r, ii = ca + (k - r * tw);
-      const float3 q = backproject(cam, ii, jj, __uint_as_float(key));
-      const float wx = Wi[0] * q.x + Wi[1] * q.y + Wi[2] * q.z + Wi[3];
-      const float wy = Wi[4] * q.x + Wi[5] * q.y + Wi[6] * q.z + Wi[7];
-      const float wz = Wi[8] * q.x + Wi[9] * q.y + Wi[10] * q.z + Wi[11];
-      const float ax = cT * wx - sT * wy + txT, ay = sT * wx + cT * wy + tyT, az = wz;
-      const float cx = cam.M[0] * ax + cam.M[1] * ay + cam.M[2] * az + cam.M[3];
-      const float cy = cam.M[4] * ax + cam.M[5] * ay + cam.M[6] * az + cam.M[7];
-      const float cz = cam.M[8] * ax + cam.M[9] * ay + cam.M[10] * az + cam.M[11];
-      if (!(cz > 0.0f)) continue;
-      const float uf = cam.fx * (cx / cz) + cam.cx, vf = cam.fy * (cy / cz) + cam.cy;
-      const float fu = floorf(uf + 0.5f), fv = floorf(vf + 0.5f);
-      if (!(fu >= 0.0f && fu <= (float)(W - 1) && fv >= 0.0f && fv <= (float)(H - 1))) continue;
+      const double3 w = world_point64(cam, ii, jj, __uint_as_float(key));
+      const double ax = cT * w.x - sT * w.y + txT, ay = sT * w.x + cT * w.y + tyT, az = w.z;
+      const double* Md = cam.dM;
+      const double cx = Md[0] * ax + Md[1] * ay + Md[2] * az + Md[3];
+      const double cy = Md[4] * ax + Md[5] * ay + Md[6] * az + Md[7];
+      const double cz = Md[8] * ax + Md[9] * ay + Md[10] * az + Md[11];
+      if (!(cz > 0.0)) continue;
+      const double iz = 1.0 / cz;
+      const double uf = cam.dfx * cx * iz + cam.dcx, vf = cam.dfy * cy * iz + cam.dcy;
+      const double fu = floor(uf + 0.5), fv = floor(vf + 0.5);
+      if (!(fu >= 0.0 && fu <= (double)(W - 1) && fv >= 0.0 && fv <= (double)(H - 1))) continue;
       const size_t pix = (size_t)fv * W + (size_t)fu;
-      const float4 P = ia.pn[2 * pix];
-      if (!(P.w > 0.0f)) continue;
-      const float dx = ax - P.x, dy = ay - P.y, dz = az - P.z;
+      const double4 P = ia.pn[2 * pix];
+      if (!(P.w > 0.0)) continue;
+      const double dx = ax - P.x, dy = ay - P.y, dz = az - P.z;
       if (dx * dx + dy * dy + dz * dz > r2) continue;
-      const float4 N = ia.pn[2 * pix + 1];
-      const float lx = ax - ox, ly = ay - oy;
-      const float g = N.y * lx - N.x * ly;
-      const float res = N.x * dx + N.y * dy + N.z * dz;
-      acc[0] += 1.0f;
+      const double4 N = ia.pn[2 * pix + 1];
+      const double lx = ax - ox, ly = ay - oy;
+      const double g = N.y * lx - N.x * ly;
+      const double res = N.x * dx + N.y * dy + N.z * dz;
+      acc[0] += 1.0;
       acc[1] += lx;
       acc[2] += ly;
       acc[3] += g * g;
@@ -1648,26 +1680,30 @@ __global__ void __launch_bounds__(NT, 4)  // at least 4 waves per SIMD: two work
             for (int v = 0; v < 3; ++v) Mc[u][v] = v == c ? b[u] : A[u][v];
           x[c] = det3(Mc) / det;
         }
-        // the step about the world z axis: t' = c_w + t - R c_w
-        const double co = cos(x[0]), si = sin(x[0]);
+        // the step about the world z axis: t' = c_w + t - R c_w; composed after the
+        // motion so far (rotations compose by the angle-sum formulas)
+        double co, si;
+        cos_sin64(x[0], co, si);
         const double cwx = cx + ox, cwy = cy + oy;
         const double stx = cwx + x[1] - (co * cwx - si * cwy);
         const double sty = cwy + x[2] - (si * cwx + co * cwy);
         const double nx = co * mtx - si * mty + stx, ny = si * mtx + co * mty + sty;
-        phi += x[0];
+        const double nc = co * cphi - si * sphi, ns = si * cphi + co * sphi;
+        cphi = nc;
+        sphi = ns;
         mtx = nx;
         mty = ny;
-        s_T[0] = (float)cos(phi);
-        s_T[1] = (float)sin(phi);
-        s_T[2] = (float)mtx;
-        s_T[3] = (float)mty;
+        s_T[0] = cphi;
+        s_T[1] = sphi;
+        s_T[2] = mtx;
+        s_T[3] = mty;
       }
     }
     __syncthreads();
     if (s_flag[2]) break;
   }
   if (tid == 0) {
-    const double co = cos(phi), si = sin(phi);
+    const double co = cphi, si = sphi;
     const double x = pz.x, y = pz.y, pc = pz.z, ps = pz.w;
     finish(1, s_nm,
            make_float4((float)(co * x - si * y + mtx), (float)(si * x + co * y + mty),
@@ -1936,7 +1972,7 @@ hipError_t launch_eval_batch(int threads, int vpack, int flags, const SceneDev* 
                                             counter, cost, status, comps, lds_bytes, grid, s);
 }
 
-void launch_obs_normals(const Cam& cam, const float* obs, float radius, float4* pn,
+void launch_obs_normals(const Cam& cam, const float* obs, float radius, double4* pn,
                         hipStream_t s) {
   const int n = cam.W * cam.H;
   hipLaunchKernelGGL(k_obs_normals, dim3((n + 255) / 256), dim3(256), 0, s, cam, obs, radius, pn);

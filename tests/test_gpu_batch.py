@@ -242,3 +242,42 @@ def test_autotuner_picks_a_setting_and_caches_it(tmp_path):
         {k: t[k] for k in ("threads", "tile_px", "radius_mode", "cell_over_delta")}
     assert abs(again["ms"] - t["ms"]) <= 1e-3 * t["ms"]
     assert open(cache).read().count("\n") == 1
+
+
+def test_tuning_after_set_parents_matches_a_fresh_batch(mixed):
+    """perch_batch_set_tuning after perch_batch_set_parents (a thread count that
+    changes the automatic z-tile, then an explicit tile) gives the same outputs as a
+    batch tuned before its parents were set: the scene table follows the tuning in
+    force at launch."""
+    scs, ctxs = mixed
+    rng = np.random.default_rng(21)
+    parents = []
+    for ci, sc in enumerate(scs):
+        parents += _gt_parents(sc, ci)
+    items = _items_for(parents, scs, rng, 60)
+    dev_items = torch.as_tensor(items).cuda()
+    n = len(items)
+
+    def run(b):
+        cost = torch.full((n,), -7, dtype=torch.int32, device="cuda")
+        st = torch.full((n,), -7, dtype=torch.int32, device="cuda")
+        comps = torch.full((n, 5), -7, dtype=torch.int32, device="cuda")
+        b.eval(dev_items, cost, st, comps)
+        torch.cuda.synchronize()
+        return st.cpu().numpy(), cost.cpu().numpy(), comps.cpu().numpy()
+
+    ref = _reference(ctxs, parents, items)
+    late = perch.Batch(ctxs)
+    late.set_parents(parents)
+    run(late)  # captures a graph with the default tuning
+    for threads, tile in ((256, 0), (512, 3000), (256, -1)):
+        late.set_tuning(threads, tile)
+        got = run(late)
+        fresh = perch.Batch(ctxs)
+        fresh.set_tuning(threads, tile)
+        fresh.set_parents(parents)
+        for a, g, f in zip(ref, got, run(fresh)):
+            assert np.array_equal(a, g), (threads, tile)
+            assert np.array_equal(a, f), (threads, tile)
+        fresh.close()
+    late.close()
