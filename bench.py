@@ -32,6 +32,8 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1510_05613_amd", "csrc", "perch_kernels.h
 COUNTERS = os.path.join(ROOT, "profiles", "k_eval_640x480_counters.md")
 CHECKPOINT = os.path.join(ROOT, "paper_1510_05613_amd", "weights", "c4_cnn.npz")
 CHECKPOINT_640 = os.path.join(ROOT, "paper_1510_05613_amd", "weights", "c2_cnn.npz")
+LEARNED_BATCH = 4  # states per step of the learned + batched search
+CHECKPOINT_C5 = os.path.join(ROOT, "paper_1510_05613_amd", "weights", "c5_cnn.npz")
 
 
 def kernel_source_hash() -> str:
@@ -62,6 +64,18 @@ def measured_traffic():
     or was taken on a different kernel source."""
     try:
         return float(_committed_counters()["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+SIMDS, CLOCK_HZ = 1024, 2.4e9          # MI355X: 256 CUs x 4 SIMDs, peak engine clock
+VALU_PEAK_G = SIMDS * 16 * CLOCK_HZ / 1e9  # lane-instructions/s: a wave64 op takes 4 cycles
+
+
+def valu_insts_per_launch():
+    """The committed SQ_INSTS_VALU count per k_eval launch, or None when stale."""
+    try:
+        return float(_committed_counters()["valu_insts_per_launch"])
     except (KeyError, ValueError):
         return None
 
@@ -104,6 +118,12 @@ def parse_args(argv=None):
                     help="held-out 640x480 scenes for the pose-prior queue leg (0 = off)")
     ap.add_argument("--icp-offgrid-scenes", type=int, default=0,
                     help="off-grid scenes searched with and without local ICP (0 = off)")
+    ap.add_argument("--other-configs", type=int, default=1,
+                    help="also time the full (5) and batched (3) configurations (0 = off)")
+    ap.add_argument("--full-scenes", type=int, default=0,
+                    help="held-out config-5 scenes for the full-pipeline anytime leg (0 = off)")
+    ap.add_argument("--full-budget", type=float, default=20.0,
+                    help="seconds per search in the full-pipeline leg")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     return ap.parse_args(argv)
@@ -123,20 +143,25 @@ def level_work(scene):
     return out
 
 
-def algorithmic_bytes(scene, level, ms, S):
+def algorithmic_bytes(scene, level, ms, S, r_delta=0):
     """Compulsory bytes of evaluating each successor in isolation: candidate mesh
-    (12 B per vertex, 12 B per triangle), parent depth under the silhouette (below
-    the root), observed depth under the silhouette (4 B per pixel; the dilated
-    footprint is larger, so this is a lower bound), the goal-level U bits, and the
-    two int32 outputs."""
+    (12 B per vertex, 12 B per triangle), parent depth under the silhouette S (below
+    the root; the root has no parent), observed depth (4 B per pixel), the goal-level
+    U bits over the same pixels, and the two int32 outputs.  r_delta = 0: the
+    observed depth under the silhouette only (a lower bound); r_delta > 0: under the
+    silhouette dilated by r_delta pixels, S_delta estimated as (sqrt(S) + 2 r_delta)^2
+    (a square of S pixels grown by r_delta on every side).  Successors that are not
+    valid report no silhouette and count their mesh and outputs only."""
     V = np.array([len(m.verts) for m in scene.library.meshes], np.int64)[ms]
     T = np.array([len(m.tris) for m in scene.library.meshes], np.int64)[ms]
-    S = S.astype(np.int64)
-    b = 12 * V + 12 * T + 4 * S + 8
+    S = np.maximum(S.astype(np.int64), 0)
+    Sd = S if r_delta <= 0 else np.where(
+        S > 0, np.ceil((np.sqrt(S) + 2 * r_delta) ** 2).astype(np.int64), 0)
+    b = 12 * V + 12 * T + 4 * Sd + 8
     if level > 0:
         b += 4 * S
     if level + 1 == scene.K:
-        b += (S + 7) // 8
+        b += (Sd + 7) // 8
     return int(b.sum())
 
 
@@ -225,6 +250,114 @@ def run_batched(args):
                        "kernel_ms_per_step": round(kernel_ms / args.steps, 3)}}
 
 
+def level_throughput(config: int, scene_idx: int, steps: int, warmup: int) -> dict:
+    """Successor evaluations per second of one configuration's ground-truth path (every
+    successor of every level, one k_eval launch per level), inputs resident."""
+    import torch
+
+    from paper_1510_05613_amd import perch, scenes
+
+    cfg = scenes.CONFIGS[config]
+    sc = scenes.make_scene(config, scene_idx, perch.GpuRenderer(), scenes.make_library(cfg["lib"]))
+    ctx = perch.context_from_scene(sc)
+    dev = []
+    for parent, ms, ps in level_work(sc):
+        n = len(ms)
+        dev.append((parent, torch.as_tensor(np.ascontiguousarray(np.stack([ms, ps], 1))).cuda(),
+                    torch.empty(n, dtype=torch.int32, device="cuda"),
+                    torch.empty(n, dtype=torch.int32, device="cuda")))
+    n_step = sum(d[1].shape[0] for d in dev)
+
+    def step():
+        for parent, cands, cost, status in dev:
+            ctx.set_parent(parent)
+            ctx.eval_children(cands, cost, status)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    if any(bool((d[3] < 0).any()) for d in dev):
+        raise RuntimeError(f"config {config}: error status")
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.close()
+    return {"value": round(n_step * steps / wall, 1), "unit": "evals/s", "steps": steps,
+            "ms_per_step": round(wall / steps * 1e3, 3), "successors_per_step": n_step,
+            "workload": (f"config {config} ({cfg['name']}), scene {scene_idx}: K={sc.K}, "
+                         f"{sc.grid.P} poses/object; every successor of every level of the "
+                         f"ground-truth path")}
+
+
+def full_pipeline_leg(n_scenes: int, budget_s: float) -> dict:
+    """Config 5 (the full pipeline): anytime search on held-out 6-object scenes, the
+    plain searches (uniform-cost, the paper's Focal-MHA*) against the learned search
+    one state per step and LEARNED_BATCH states per step (network trained on
+    config-5 scenes).  Each search gets budget_s seconds; reported per search: the
+    anytime trace (seconds, incumbent cost, anchor lower bound min g), the final
+    cost and bound, and the time to the best cost any search reached; medians over
+    scenes.  The ground-truth scene's own cost (Eq. 4 along its valid order) is the
+    reference."""
+    from paper_1510_05613_amd import learn, perch, scenes
+
+    if not os.path.exists(CHECKPOINT_C5):
+        return {"skipped": "no trained checkpoint"}
+    cfg = scenes.CONFIGS[5]
+    lib = scenes.make_library(cfg["lib"])
+    render = perch.GpuRenderer()
+    net = learn.batched_network(CHECKPOINT_C5, 5, 1)
+    bnet = learn.batched_network(CHECKPOINT_C5, 5, LEARNED_BATCH)
+    names = ("ucs", "mha", "learned", "learned_batched")
+    rows, traces = [], {k: [] for k in names}
+    i = learn.HELD_OUT_FIRST
+    while len(rows) < n_scenes and i < learn.HELD_OUT_FIRST + 10 * n_scenes:
+        sc = learn.try_scene(5, i, render, lib)
+        i += 1
+        if sc is None:
+            continue
+        ctx = perch.context_from_scene(sc)
+        truth = _path_cost(ctx, [(int(sc.obj_mesh[k]), int(sc.gt_pose[k])) for k in sc.gt_order])
+        run = dict(
+            ucs=lambda: ctx.search(perch.SEARCH_UCS, budget_s=budget_s),
+            mha=lambda: ctx.search(perch.SEARCH_MHA, w=3.0, anytime=True, budget_s=budget_s),
+            learned=lambda: ctx.search(perch.SEARCH_LEARNED, w=3.0, anytime=True, cnn=net,
+                                       topk=256, budget_s=budget_s),
+            learned_batched=lambda: ctx.search(perch.SEARCH_LEARNED, w=3.0, anytime=True,
+                                               cnn=bnet, topk=256, budget_s=budget_s,
+                                               batch=LEARNED_BATCH))
+        res = {k: run[k]() for k in names}
+        best = min([r["cost"] for r in res.values() if r["found"]] + [truth])
+        row = {"truth": truth, "best": best}
+        for k, r in res.items():
+            row[k] = dict(cost=r["cost"] if r["found"] else None, lower_bound=r["lower_bound"],
+                          t_best=r["t_best_s"] if r["found"] and r["cost"] == best else None,
+                          evals=r["n_evaluated"], expanded=r["n_expanded"])
+            traces[k].append([(round(t, 3), c, lb) for t, c, lb in r["trace"]])
+        rows.append(row)
+        ctx.close()
+        print(f"full pipeline: scene {i - 1}: truth {truth}, " +
+              ", ".join(f"{k} {row[k]['cost']} (lb {row[k]['lower_bound']})" for k in names),
+              file=sys.stderr, flush=True)
+
+    def med(v):
+        v = [x for x in v if x is not None]
+        return float(np.median(v)) if v else None
+
+    return {"scenes": len(rows), "budget_s": budget_s, "w": 3.0, "topk": 256,
+            "batch": LEARNED_BATCH, "truth_cost": med([r["truth"] for r in rows]),
+            "final_cost": {k: med([r[k]["cost"] for r in rows]) for k in names},
+            "final_lower_bound": {k: med([r[k]["lower_bound"] for r in rows]) for k in names},
+            "reached_best": {k: sum(r[k]["t_best"] is not None for r in rows) for k in names},
+            "time_to_best_s": {k: med([r[k]["t_best"] for r in rows]) for k in names},
+            "evals": {k: med([r[k]["evals"] for r in rows]) for k in names},
+            "traces": traces,
+            "workload": (f"config 5 (640x480, 1.5x1.0 m table, K=6, 480,000 poses/object), the "
+                         f"first {len(rows)} held-out scenes from {learn.HELD_OUT_FIRST} the "
+                         f"generator builds; {budget_s:.0f} s per search")}
+
+
 def cpu_baseline(args, work_gpu):
     """The oracle, as it stands, on a seeded sample of this step's successors."""
     import oracle
@@ -237,25 +370,43 @@ def cpu_baseline(args, work_gpu):
     except AttributeError:
         cores = os.cpu_count() or 1
     cores = max(1, min(16, cores))
-    o = oracle.Oracle.from_scene(sc, nthreads=cores)
     work = level_work(sc)
     sizes = np.array([len(w[1]) for w in work], np.float64)
-    rng = np.random.default_rng(12345)
-    n_done, t_used, chunk = 0, 0.0, 4 * cores
-    while t_used < args.cpu_seconds:
-        lv = int(rng.choice(len(work), p=sizes / sizes.sum()))
-        parent, ms, ps = work[lv]
-        idx = rng.integers(len(ms), size=chunk)
-        t0 = time.perf_counter()
-        o.eval([p[0] for p in parent], [p[1] for p in parent], ms[idx], ps[idx])
-        t_used += time.perf_counter() - t0
-        n_done += chunk
-        chunk = min(4096, chunk * 2)
+
+    def rate(threads, seconds, seed):
+        o = oracle.Oracle.from_scene(sc, nthreads=threads)
+        rng = np.random.default_rng(seed)
+        n_done, t_used, chunk = 0, 0.0, 4 * threads
+        while t_used < seconds:
+            lv = int(rng.choice(len(work), p=sizes / sizes.sum()))
+            parent, ms, ps = work[lv]
+            idx = rng.integers(len(ms), size=chunk)
+            t0 = time.perf_counter()
+            o.eval([p[0] for p in parent], [p[1] for p in parent], ms[idx], ps[idx])
+            t_used += time.perf_counter() - t0
+            n_done += chunk
+            chunk = min(4096, chunk * 2)
+        o.close()
+        return n_done, t_used
+
+    n_done, t_used = rate(cores, args.cpu_seconds, 12345)
+    n1, t1 = rate(1, args.cpu_seconds / 2, 54321)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")),
+                         "")
+    except OSError:
+        pass
     return {"value": round(n_done / t_used, 1), "unit": "evals/s", "cores": cores,
             "kind": "oracle",
+            "value_1_thread": round(n1 / t1, 1),
+            "host": {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0))
+                     if hasattr(os, "sched_getaffinity") else None, "cpu_model": model},
             "sample": (f"{n_done} successors drawn uniformly (level-weighted) from the step's "
                        f"{int(sizes.sum())}, scene regenerated with the oracle renderer, "
-                       f"{t_used:.1f} s on {cores} threads")}
+                       f"{t_used:.1f} s on {cores} threads; {n1} more in {t1:.1f} s on one "
+                       f"thread")}
 
 
 def learned_leg(n_scenes: int) -> dict:
@@ -266,7 +417,9 @@ def learned_leg(n_scenes: int) -> dict:
     if not os.path.exists(CHECKPOINT):
         return {"skipped": "no trained checkpoint"}
     net, ctrl = learn.search_networks(CHECKPOINT, 4)
-    g = learn.gain(net, ctrl, range(learn.HELD_OUT_FIRST, learn.HELD_OUT_FIRST + n_scenes))
+    bnet = learn.batched_network(CHECKPOINT, 4, LEARNED_BATCH)
+    g = learn.gain(net, ctrl, range(learn.HELD_OUT_FIRST, learn.HELD_OUT_FIRST + n_scenes),
+                   batched=bnet, batch=LEARNED_BATCH)
     g["workload"] = (f"config 4 (160x120, K=2, 1,152 poses/object), held-out scenes "
                      f"{learn.HELD_OUT_FIRST}..{learn.HELD_OUT_FIRST + n_scenes - 1}; medians")
     return g
@@ -280,17 +433,19 @@ def learned_leg_640(n_scenes: int, budget_s: float = 10.0) -> dict:
     if not os.path.exists(CHECKPOINT_640):
         return {"skipped": "no trained checkpoint"}
     net, ctrl = learn.search_networks(CHECKPOINT_640, 2)
+    bnet = learn.batched_network(CHECKPOINT_640, 2, LEARNED_BATCH)
     first = learn.HELD_OUT_FIRST
     g = learn.gain(net, ctrl, range(first, first + 2 * n_scenes), config=2, topk=256,
                    budget_s=budget_s, max_scenes=n_scenes,
-                   log=lambda m: print(m, file=sys.stderr, flush=True))
+                   log=lambda m: print(m, file=sys.stderr, flush=True), batched=bnet,
+                   batch=LEARNED_BATCH)
     g["workload"] = (f"config 2 (640x480, K=3, 40,000 poses/object), the first {n_scenes} "
                      f"held-out scenes from {first}; medians, {budget_s:.0f} s per search")
     return g
 
 
 def icp_leg(ctx, sc, d, iters: int, reps: int = 3) -> dict:
-    """Local ICP (Sec. V-A) of every root successor (one launch), then the edge
+    """Local ICP (Sec. IV-E) of every root successor (one launch), then the edge
     costs at the adjusted poses (one k_eval launch): HIP-event times on the
     context's stream, best of `reps`."""
     import torch
@@ -371,7 +526,7 @@ def _best_children(ctx, parent, cands, icp_iters):
 
 
 def icp_offgrid_leg(n_scenes: int, budget_s: float = 10.0, iters: int = 10) -> dict:
-    """The paper's reason for the local ICP (Sec. V-A): objects placed off the pose
+    """The paper's reason for the local ICP (Sec. IV-E): objects placed off the pose
     grid (up to 0.4 of a cell and of a yaw step), the candidates restricted to the 7
     x 7 grid cells (every yaw) around the ground truth.  Along the true insertion
     order, each level's cheapest child of the true mesh (grid pose, or after ICP):
@@ -537,7 +692,9 @@ def main(argv=None):
         ctx.eval_children(d["cands"], d["cost"], d["status"], d["comps"])
     torch.cuda.synchronize()
     bytes_per_step = 0
+    bytes_sdelta_step = 0
     valid = 0
+    halo = ctx.info()["halo"]  # the window radius r_delta (pixels) bound of the scene
     for lv, (d, (parent, ms, ps)) in enumerate(zip(dev, work)):
         S = d["comps"][:, 0].cpu().numpy()
         st = d["status"].cpu().numpy()
@@ -545,6 +702,7 @@ def main(argv=None):
             raise RuntimeError(f"error status {np.unique(st)} at level {lv + 1}")
         valid += int((st == 1).sum())
         bytes_per_step += algorithmic_bytes(sc, lv, ms, S)
+        bytes_sdelta_step += algorithmic_bytes(sc, lv, ms, S, r_delta=halo)
 
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in dev]
@@ -582,11 +740,43 @@ def main(argv=None):
     launch_s = kernel_ms / 1e3 / (args.steps * launches)  # mean k_eval launch duration
     bytes_per_launch = bytes_per_step / launches           # mean algorithmic bytes per launch
     achieved = bytes_per_launch / launch_s / 1e9
+    achieved_sd = bytes_sdelta_step / launches / launch_s / 1e9
     # the committed counters describe the default workload at default settings only
     default_run = (args.config == 2 and args.scene == 0 and not (args.threads or args.tile or
                                                                  args.cell or args.radius >= 0))
     traffic = measured_traffic() if default_run else None
     valu = valu_issue_frac(launch_s) if default_run else None
+    hbm = {"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4),
+           "algorithmic_bytes_per_launch": round(bytes_per_launch),
+           "definition": "12V + 12T + 4S (+4S parent below the root, +S/8 U at the goal) + 8"}
+    hbm_sd = {"achieved": round(achieved_sd, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+              "frac": round(achieved_sd / HBM_PEAK_GBS, 4),
+              "algorithmic_bytes_per_launch": round(bytes_sdelta_step / launches),
+              "definition": ("as hbm_algorithmic with the observed depth and U over the "
+                             f"silhouette dilated by r_delta = {halo} px, "
+                             "S_delta = (sqrt(S) + 2 r_delta)^2")}
+    if valu is not None:
+        # the kernel is bound by vector-ALU issue: its roofline is the SIMDs' issue rate
+        vi = valu_insts_per_launch()
+        roof = {"bound": "alu", "achieved": round(vi * 64 / launch_s / 1e9, 1),
+                "peak": round(VALU_PEAK_G, 1), "unit": "G lane-instr/s",
+                "frac": round(valu, 4),
+                "traffic": None if traffic is None else round(traffic),
+                "kernel": "k_eval", "launches_per_step": launches,
+                "launch_ms": round(launch_s * 1e3, 4),
+                "valu_insts_per_launch": round(vi),
+                "hbm_algorithmic": hbm, "hbm_algorithmic_sdelta": hbm_sd,
+                "hbm_measured": None if traffic is None else {
+                    "achieved": round(traffic / launch_s / 1e9, 2), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(traffic / launch_s / 1e9 / HBM_PEAK_GBS, 5)}}
+    else:
+        # counters not taken on this kernel source: the algorithmic HBM roofline alone
+        roof = {"bound": "hbm", "achieved": hbm["achieved"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": hbm["frac"], "traffic": None, "kernel": "k_eval",
+                "launches_per_step": launches, "launch_ms": round(launch_s * 1e3, 4),
+                "algorithmic_bytes_per_launch": round(bytes_per_launch),
+                "hbm_algorithmic_sdelta": hbm_sd, "valu_issue_frac": None}
     out = {
         "metric": METRIC, "value": round(evals / wall, 1), "unit": "evals/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 3),
@@ -599,16 +789,17 @@ def main(argv=None):
                    "successors_per_step": n_step, "valid_per_step": valid,
                    "threads_per_successor": args.threads or 512,
                    "tile_px": args.tile or "auto"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None if traffic is None else round(traffic),
-                     "kernel": "k_eval", "launches_per_step": launches,
-                     "launch_ms": round(launch_s * 1e3, 4),
-                     "algorithmic_bytes_per_launch": round(bytes_per_launch),
-                     "valu_issue_frac": None if valu is None else round(valu, 3)},
+        "roofline": roof,
     }
     if args.icp_iters > 0 and args.config == 2:
         out["icp"] = icp_leg(ctx, sc, dev[0], args.icp_iters)
+    if args.other_configs and args.config == 2:
+        out["config5"] = level_throughput(5, 0, steps=3, warmup=1)
+        c3 = run_batched(argparse.Namespace(config=3, threads=0, tile=0, warmup=1, steps=2))
+        out["config3"] = {k: c3[k] for k in ("value", "unit", "steps", "ms_per_step")}
+        out["config3"].update(c3["config"])
+    if args.full_scenes > 0 and args.config == 2:
+        out["full_pipeline"] = full_pipeline_leg(args.full_scenes, args.full_budget)
     if args.chessboard and args.config == 2:
         out["chessboard"] = chessboard_leg()
     if args.prior_scenes > 0 and args.config == 2:

@@ -100,7 +100,7 @@ perch_status perch_add_mesh(perch_ctx* ctx, int32_t mesh_id, const float* verts,
                             int32_t n_verts, const int32_t* tris, int32_t n_tris,
                             const float* planes, int32_t n_planes);
 
-/* Marks a mesh as rotationally symmetric about the vertical axis (Sec. V-A: only
+/* Marks a mesh as rotationally symmetric about the vertical axis (Sec. IV-E: only
  * its (x, y) matters).  perch_search then tries it only at the first pose of the
  * pose list (table or subset, in order) at each distinct (x, y); not with the
  * learned search modes.  Identical objects need no flag: the object multiset
@@ -178,7 +178,7 @@ perch_status perch_eval_successors_noalloc(perch_ctx* ctx, const perch_object* p
 perch_status perch_overlap_gain(perch_ctx* ctx, const perch_object* cands_dev, int32_t n,
                                 int32_t* cost_dev, int32_t* status_dev, int32_t* gain_dev);
 
-/* Local ICP alignment (Sec. V-A, compensating for discretization): for each
+/* Local ICP alignment (Sec. IV-E, compensating for discretization): for each
  * candidate (mesh, pose) of the parent last set, renders it, takes the part not
  * covered by the parent (dR) and runs `iters` ICP rounds against the observation:
  * each model point, moved by the motion so far, is paired with the observed point
@@ -387,7 +387,16 @@ typedef struct {
                                /* prior_slot_m per object still to place (Sec. IV-C)    */
   float prior_rad_m;           /* 0: 0.05 m per radian                                 */
   float prior_slot_m;          /* 0: 0.1 m                                             */
+  int32_t batch;               /* LEARNED: states expanded per step (<= 1: one).  With */
+                               /* B > 1 the search picks up to B states by its usual   */
+                               /* rule, runs the network for all of them, and evaluates*/
+                               /* every chosen child (and every popped lazy block) in  */
+                               /* one persistent batched launch with one host          */
+                               /* synchronisation; the network needs capacity for B    */
+                               /* crops per pose cell and B pairs per child            */
 } perch_search_opts;
+
+#define PERCH_TRACE 64 /* entries of a search's anytime trace */
 
 typedef struct {
   perch_object objs[PERCH_MAX_OBJECTS]; /* the goal, in insertion order (valid)      */
@@ -404,6 +413,10 @@ typedef struct {
   int64_t n_merged;            /* ICP: valid children dropped because a sibling of the  */
                                /* same mesh was aligned into the same 1 mm x 1 mm x 0.5 */
                                /* degree cell at no higher cost                         */
+  int32_t n_trace;             /* entries of the anytime trace below (<= 64)            */
+  double trace_t[PERCH_TRACE]; /* seconds since the call: whenever the incumbent cost    */
+  int64_t trace_cost[PERCH_TRACE]; /* improves, and every 0.25 s: incumbent cost (-1 =  */
+  int64_t trace_lb[PERCH_TRACE];   /* none yet) and the anchor's lower bound min g      */
 } perch_result;
 
 /* Runs the tree search of Alg. 1 on the context's scene: root = empty state, goal =

@@ -15,7 +15,8 @@ from typing import Optional, Sequence
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboracle.so")
+# PERCH_ORACLE_LIB: another build of the same source (the sanitizer test's)
+LIB_PATH = os.environ.get("PERCH_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 SOURCES = [os.path.join(HERE, "perch_oracle.c")]
 
 
@@ -184,7 +185,7 @@ class Oracle:
 
     def icp(self, parent_mesh, parent_pose, cand_mesh, cand_pose, iters: int = 10,
             radius: float = 0.02):
-        """Local ICP (Sec. V-A) of each candidate under the parent.  Returns
+        """Local ICP (Sec. IV-E) of each candidate under the parent.  Returns
         (poses (n, 4) float64 (x, y, cos, sin), n_match (n,), status (n,), flags (n,))."""
         pm, pp = _i32(parent_mesh), _i32(parent_pose)
         cm, cp = _i32(cand_mesh), _i32(cand_pose)

@@ -15,7 +15,7 @@
  *               successor set Eq.(3) and edge cost Eq.(4).
  *   Sec. IV-B   exhaustive tree search (Theorems 1-2 with w = 1), used here as
  *               exhaustive enumeration and uniform-cost search.
- *   Sec. V-A    local ICP alignment of each new object's non-occluded part
+ *   Sec. IV-E    local ICP alignment of each new object's non-occluded part
  *               (compensating for a coarse pose discretization).
  *
  * Readings where the paper is silent (each one is listed in the design notes):
@@ -726,7 +726,7 @@ int orc_overlap(const orc_scene* sc, int32_t j, const int32_t* pm, const int32_t
 }
 
 /* ------------------------------------------------------------------------- */
-/* local ICP alignment (Sec. V-A, compensating for discretization)           */
+/* local ICP alignment (Sec. IV-E, compensating for discretization)           */
 /* ------------------------------------------------------------------------- */
 
 /* One linearised point-to-plane step (Chen and Medioni's ICP, restricted to the
@@ -859,7 +859,7 @@ static int icp_one(const orc_scene* sc, const double* Dp, int mesh, int pose, in
     return 0;
   }
   /* model points: the non-occluded part dR, in the world frame, back-projected from
-   * the rendered depth as a float32 depth image holds it (reading: Sec. V-A aligns
+   * the rendered depth as a float32 depth image holds it (reading: Sec. IV-E aligns
    * the rendered object, and a rendered depth image is float32 like the observed
    * one) */
   double* Q = (double*)malloc(sizeof(double) * 3 * (size_t)(nq + 1));
@@ -1093,7 +1093,7 @@ int orc_set_symmetric(orc_scene* sc, int32_t mesh, int32_t symmetric) {
 }
 
 /* The poses a search tries for `mesh`: the subset itself, or for a rotationally
- * symmetric mesh (Sec. V-A: only (x, y) matters) the first pose of the subset at
+ * symmetric mesh (Sec. IV-E: only (x, y) matters) the first pose of the subset at
  * each distinct (x, y).  Returns the count written to out. */
 static int mesh_subset(const orc_scene* sc, int mesh, int nsub, const int32_t* sub,
                        int32_t* out) {

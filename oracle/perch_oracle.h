@@ -89,7 +89,7 @@ int orc_overlap(const orc_scene* sc, int32_t j, const int32_t* par_mesh,
  * motion written as a rotation about the world z axis, then a translation. */
 int orc_icp_step(int32_t n, const double* a, const double* p, const double* nrm, double* out);
 
-/* Local ICP (Sec. V-A) of each candidate's non-occluded part under the parent
+/* Local ICP (Sec. IV-E) of each candidate's non-occluded part under the parent
  * s = {(par_mesh[k], par_pose[k]) : k < j}: `iters` rounds of projective
  * association (observed point at the pixel nearest the moved model point, kept
  * when it has a surface normal and lies within `radius` metres) and a
@@ -112,7 +112,7 @@ int orc_jtree(const orc_scene* sc, int32_t K, const int32_t* mesh,
  * best_mesh/best_pose receive the goal in canonical order (sorted by
  * (mesh, pose)).  stats: [0] cost, [1] successor evaluations, [2] expansions,
  * [3] goals seen.  Return 0 on success, 1 when no goal exists. */
-/* Marks mesh as rotationally symmetric about the vertical axis (Sec. V-A): the
+/* Marks mesh as rotationally symmetric about the vertical axis (Sec. IV-E): the
  * searches below then try it only at the first pose of the subset at each distinct
  * (x, y). */
 int orc_set_symmetric(orc_scene* sc, int32_t mesh, int32_t symmetric);

@@ -7,7 +7,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <cstdlib>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -24,6 +26,21 @@ namespace perch {
 namespace {
 thread_local std::string g_err;
 }
+
+namespace {
+std::atomic<long long> g_dev_bytes{0};
+}
+
+bool dev_mem_admit(size_t n) {
+  const char* cap = std::getenv("PERCH_DEVICE_MEM_CAP");
+  if (!cap || !*cap) return true;
+  char* end = nullptr;
+  const unsigned long long c = std::strtoull(cap, &end, 10);
+  if (end == cap) return true;  // not a number: no cap
+  return (unsigned long long)g_dev_bytes.load() + n <= c;
+}
+
+void dev_mem_account(long long delta) { g_dev_bytes += delta; }
 
 perch_status fail(perch_status st, const char* fmt, ...) {
   char buf[512];
@@ -275,6 +292,12 @@ void perch_destroy(perch_ctx* c) {
                     &c->s_adj, &c->icp_pn, &c->cnn_desc})
     b->release();
   for (DevBuf& b : c->learned_bufs) b.release();
+  if (c->s_batch) perch_batch_destroy(c->s_batch);
+  for (DevBuf* b : {&c->s_items, &c->s_bout, &c->s_bcrops, &c->s_bpairs, &c->s_bpred,
+                    &c->s_bcands})
+    b->release();
+  c->s_hitems.release();
+  c->s_hbout.release();
   c->s_hcands.release();
   c->s_hout.release();
   c->s_hposes.release();

@@ -74,6 +74,10 @@ static perch_status upload_scene_table(perch_batch* b, int* flags) {
   return PERCH_OK;
 }
 
+const unsigned* batch_slot_depth(const perch_batch* b, int slot) {
+  return b->slot_depth.as<unsigned>() + (size_t)slot * b->npx_max;
+}
+
 extern "C" {
 
 perch_status perch_batch_create(perch_ctx* const* ctxs, int32_t n_ctx, void* hip_stream,

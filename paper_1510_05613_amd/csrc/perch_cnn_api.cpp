@@ -75,6 +75,13 @@ bool crop_descriptors(const float M[12], float fx, float fy, float cx, float cy,
 
 }  // namespace cnn
 
+perch_status cnn_capacity(const perch_cnn* c, int* max_crops, int* max_pairs) {
+  if (!c) return fail(PERCH_E_ARG, "null network");
+  *max_crops = c->max_crops;
+  *max_pairs = c->max_pairs;
+  return PERCH_OK;
+}
+
 perch_status cnn_predict_on(perch_cnn* c, const uint16_t* crops, int n_crops, const void* pairs,
                             int n_pairs, float* pred, hipStream_t s) {
   if (!c || n_crops < 1 || n_pairs < 1 || n_crops > c->max_crops || n_pairs > c->max_pairs)

@@ -12,21 +12,37 @@
 
 namespace perch {
 
+// Device memory the library holds (all contexts, batches and networks of the
+// process).  With the environment variable PERCH_DEVICE_MEM_CAP set to a byte
+// count, an allocation that would take the total above it fails as out of memory
+// (PERCH_E_OOM) without reaching the runtime: a budget for processes that share a
+// GPU, and the way the error path is tested.
+bool dev_mem_admit(size_t n);
+void dev_mem_account(long long delta);
+
 // A device allocation owned by the context.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
   hipError_t ensure(size_t n) {
     if (n <= bytes && p) return hipSuccess;
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    bytes = 0;
-    hipError_t e = hipMalloc(&p, n ? n : 16);
-    if (e == hipSuccess) bytes = n;
+    release();
+    const size_t want = n ? n : 16;
+    if (!dev_mem_admit(want)) return hipErrorOutOfMemory;
+    hipError_t e = hipMalloc(&p, want);
+    if (e == hipSuccess) {
+      bytes = n;
+      dev_mem_account((long long)want);
+    } else {
+      p = nullptr;
+    }
     return e;
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      (void)hipFree(p);
+      dev_mem_account(-(long long)(bytes ? bytes : 16));
+    }
     p = nullptr;
     bytes = 0;
   }
@@ -81,6 +97,9 @@ void vol_margins(const Cam& cam, float obs_zmax, float pose_xy_max, float mesh_r
 
 // Records a message for perch_last_error() and returns st.
 perch_status fail(perch_status st, const char* fmt, ...);
+
+// The largest batch (crops, pairs) the network was created for (perch_cnn_api.cpp).
+perch_status cnn_capacity(const perch_cnn* c, int* max_crops, int* max_pairs);
 
 // Runs the learned network (forward pass and head) on stream s, the context's
 // stream in the learned search (perch_cnn_api.cpp).
@@ -192,6 +211,11 @@ struct perch_ctx {
   // learned search: crop descriptors, pair table, ranking buffers (kept between calls)
   DevBuf learned_bufs[11];
   PinnedBuf s_hcands, s_hout, s_hposes;
+  // learned search with several states per step: a batch over this context, its
+  // work items, outputs and the replicated crop / pair / prediction buffers
+  perch_batch* s_batch = nullptr;
+  DevBuf s_items, s_bout, s_bcrops, s_bpairs, s_bpred, s_bcands;
+  PinnedBuf s_hitems, s_hbout;
   // tuning (tile_px 0 = sized automatically, see auto_tile_px)
   int threads = 512;
   bool threads_auto = true;  // threads never set explicitly: small launches widen
@@ -265,6 +289,10 @@ struct perch_ctx {
     return h;
   }
 };
+
+// The composite depth (float bits) of parent slot `slot` of a batch, valid after
+// perch_batch_set_parents (perch_batch.cpp).
+const unsigned* batch_slot_depth(const perch_batch* b, int slot);
 
 // Shared with the batch and search code (perch_api.cpp).
 perch_status upload_meshes(perch_ctx* c);

@@ -145,7 +145,7 @@ hipError_t launch_eval_batch(int threads, int vpack, int flags, const SceneDev* 
                              int* counter, int* cost, int* status, int* comps, size_t lds_bytes,
                              int grid, hipStream_t s);
 
-// ---- local ICP (Sec. V-A) ----
+// ---- local ICP (Sec. IV-E) ----
 constexpr int kIcpThreads = 512;
 struct IcpArgs {
   int iters;
@@ -190,5 +190,13 @@ bool launch_select_topk(const float* pred, int n_poses, int n_meshes, MeshMask m
                         const int* rest, const int* pose_ids, int2* cands, hipStream_t s);
 void launch_child_cands(const int* idx_sorted, int k, const int* rest, int n_poses,
                         const int* pose_ids, int2* cands, hipStream_t s);
+// Work items (slot, mesh, pose, 0) of a batched search step: items[i] = (slot,
+// cands[i]) for i < k; or every (meshes.id[u], pose_ids[b]) child, mesh-major.
+struct MeshList {
+  int id[kMaxMeshes];
+};
+void launch_items_from_cands(const int2* cands, int k, int slot, int4* items, hipStream_t s);
+void launch_items_all(int slot, const MeshList& meshes, int n_meshes, const int* pose_ids,
+                      int n_poses, int4* items, hipStream_t s);
 
 }  // namespace perch

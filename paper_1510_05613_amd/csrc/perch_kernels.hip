@@ -296,6 +296,49 @@ __device__ __forceinline__ void raster_tri(int x0, int y0, int x1, int y1, int x
   }
 }
 
+// raster_tri by rows: calls row(j, i0, i1) for each row j of the triangle with its
+// covered columns i0..i1 (non-empty), restricted as raster_tri is.  Same coverage.
+template <class Row>
+__device__ __forceinline__ void raster_tri_rows(int x0, int y0, int x1, int y1, int x2, int y2,
+                                                int c0, int c1, int r0, int r1, Row&& row) {
+  const int xmin = min(x0, min(x1, x2)), xmax = max(x0, max(x1, x2));
+  const int ymin = min(y0, min(y1, y2)), ymax = max(y0, max(y1, y2));
+  const int ia = max(c0, ceil256(xmin)), ib = min(c1, floor256(xmax));
+  const int ja = max(r0, ceil256(ymin)), jb = min(r1, floor256(ymax));
+  if (ia > ib || ja > jb) return;
+  if (xmax - xmin < 16384 && ymax - ymin < 16384) {
+    int bx = x1 - x0, by = y1 - y0, cx = x2 - x0, cy = y2 - y0;
+    const int area = bx * cy - by * cx;
+    if (area >= 0) return;
+    int t = bx; bx = cx; cx = t;
+    t = by; by = cy; cy = t;
+    const int d0x = bx, d0y = by, d1x = cx - bx, d1y = cy - by, d2x = -cx, d2y = -cy;
+    const int b0 = (d0y < 0 || (d0y == 0 && d0x > 0)) ? 0 : -1;
+    const int b1 = (d1y < 0 || (d1y == 0 && d1x > 0)) ? 0 : -1;
+    const int b2 = (d2y < 0 || (d2y == 0 && d2x > 0)) ? 0 : -1;
+    const int py = 256 * ja - y0, px0 = 256 * ia - x0;
+    const int w = ib - ia + 1;
+    int rlo = ja, rhi = jb;
+    EdgeDDA g0, g1, g2;
+    edge_dda(d0x * py - d0y * px0 + b0, d0y, d0x, ja, rlo, rhi, g0);
+    edge_dda(d1x * (py - by) - d1y * (px0 - bx) + b1, d1y, d1x, ja, rlo, rhi, g1);
+    edge_dda(d2x * (py - cy) - d2y * (px0 - cx) + b2, d2y, d2x, ja, rlo, rhi, g2);
+    for (int j = ja; j <= jb; ++j) {
+      int lo = 0, hi = (j >= rlo && j <= rhi) ? w - 1 : -1;
+      g0.bound(lo, hi);
+      g1.bound(lo, hi);
+      g2.bound(lo, hi);
+      if (lo <= hi) row(j, ia + lo, ia + hi);
+      g0.step();
+      g1.step();
+      g2.step();
+    }
+  } else {
+    // large boxes: per-pixel 64-bit edge functions, as raster_tri
+    raster_tri(x0, y0, x1, y1, x2, y2, c0, c1, r0, r1, [&](int i, int j) { row(j, i, i); });
+  }
+}
+
 // True when the triangle is front-facing (negative snapped area) and its box
 // holds at least one pixel centre inside columns [c0, c1] and rows [r0, r1]: the
 // triangles raster_tri can emit for.
@@ -999,8 +1042,16 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
         vcam(cam, pz, v1, X1, Y1, Z1);
         vcam(cam, pz, v2, X2, Y2, Z2);
         const Plane64 pl = make_plane(cam, X0, Y0, Z0, X1, Y1, Z1, X2, Y2, Z2);
-        raster_tri(a.x, a.y, b.x, b.y, c.x, c.y, ca, cb, t0, t1, [&](int i, int j) {
-          atomicMin(&tile[(j - t0) * tw + (i - ca)], __float_as_uint(plane_depth(pl, i, j)));
+        // the plane's denominator A i + B j + C steps by A along a row (FP64: the
+        // accumulated rounding stays near 1e-14 of it, far below float32's)
+        raster_tri_rows(a.x, a.y, b.x, b.y, c.x, c.y, ca, cb, t0, t1, [&](int j, int i0, int i1) {
+          double den = fma(pl.A, (double)i0, fma(pl.B, (double)j, pl.C));
+          unsigned* t = tile + (j - t0) * tw + (i0 - ca);
+          for (int i = i0; i <= i1; ++i, ++t, den += pl.A) {
+            double r = __builtin_amdgcn_rcp(den);
+            r = fma(r, fma(-den, r, 1.0), r);
+            atomicMin(t, __float_as_uint((float)(pl.N * r)));
+          }
         });
       };
       unsigned head = 0, tail = 0;  // wave-uniform ring positions
@@ -1064,8 +1115,9 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
     // unexplained when the dilated observed depth range rules every window pixel
     // out, otherwise the whole wave scans its exact window, two points at a time.
     // dJ_o / U: p needs the dR window when it lies in V(O) or in U; each lane walks
-    // its own window of the LDS tile with a depth pre-test.  Hash mode: dJ_r by a
-    // range query of the voxel hash.
+    // its own window of the LDS tile with a depth pre-test (walks come in bunches:
+    // measured slower walked by the whole wave).  Hash mode: dJ_r by a range query
+    // of the voxel hash.
     {
       const int nk = (b1 - b0 + 1) * tw;
       const int kt = (b0 - t0) * tw;  // tile index of the first core pixel
@@ -1320,7 +1372,7 @@ __global__ void __launch_bounds__(NT, 4)  // at least 4 waves per SIMD: <= 128 V
 }
 
 // ---------------------------------------------------------------------------
-// local ICP (Sec. V-A): compensating for the pose discretization
+// local ICP (Sec. IV-E): compensating for the pose discretization
 // ---------------------------------------------------------------------------
 
 // Per observed pixel, in FP64: the world point p = Rinv (q - t) of its

@@ -112,7 +112,7 @@ class Searcher {
     for (int m : c_->objects)
       if (std::find(seen.begin(), seen.end(), m) == seen.end()) seen.push_back(m), ++distinct;
     distinct_ = distinct;
-    // rotationally symmetric meshes (Sec. V-A) are tried once per (x, y): the
+    // rotationally symmetric meshes (Sec. IV-E) are tried once per (x, y): the
     // first pose of the list at each distinct position
     bool any_sym = false;
     for (int m : seen) {
@@ -308,6 +308,17 @@ class Searcher {
   double prior_rad_m() const { return o_.prior_rad_m > 0.0f ? o_.prior_rad_m : 0.05; }
   double prior_slot_m() const { return o_.prior_slot_m > 0.0f ? o_.prior_slot_m : 0.1; }
 
+  // Anytime trace: an entry whenever the incumbent cost improves (force) and at
+  // most every 0.25 s otherwise; the last slot is kept for the end of the search.
+  void trace(bool force) {
+    const double t = elapsed();
+    if (!force && n_trace_ > 0 && t - trace_t_[n_trace_ - 1] < 0.25) return;
+    const int k = n_trace_ < PERCH_TRACE ? n_trace_++ : PERCH_TRACE - 1;
+    trace_t_[k] = t;
+    trace_cost_[k] = have_ ? best_.g : -1;
+    trace_lb_[k] = lower_bound_;
+  }
+
   void offer_goal(const Node& g, const std::vector<Node>* store) {
     if (have_ && (g.g > best_.g || (g.g == best_.g && cmp_key(g, best_) >= 0))) return;
     const bool cost_improved = !have_ || g.g < best_.g;
@@ -316,6 +327,7 @@ class Searcher {
     if (cost_improved) {
       t_best_ = elapsed();
       n_eval_best_ = n_evaluated_;
+      trace(true);
     }
     // edge costs along the path
     std::memset(best_edges_, 0, sizeof(best_edges_));
@@ -419,6 +431,7 @@ class Searcher {
       if (open.empty()) break;
       const int64_t gmin = nodes[open.top()].g;
       lower_bound_ = gmin;
+      trace(false);
       if (have_ && best_.g <= gmin) break;  // incumbent proven optimal
       if (over_budget()) return PERCH_E_BUDGET;
       int pick = -1;
@@ -669,6 +682,204 @@ class Searcher {
     pending.push(0);
     std::vector<Child> kids;
     const double w = std::max(1.0f, o_.w);
+    const int n_inad = with_overlap ? 2 : 1;
+    // Next state to expand, as the single-state search picks it (round robin over
+    // the inadmissible queues restricted to FOCAL, and the anchor when anytime);
+    // -1 when the open list is empty.
+    auto next_pick = [&]() -> int {
+      while (!open.empty() && !live(open.top())) open.pop();
+      if (open.empty()) return -1;
+      const int64_t gmin = nodes[open.top()].g;
+      while (!pending.empty() && (double)nodes[pending.top()].g <= w * (double)gmin) {
+        if (live(pending.top())) {
+          focal_q.push(pending.top());
+          if (with_overlap) over_q.push(pending.top());
+        }
+        pending.pop();
+      }
+      while (!focal_q.empty() && !live(focal_q.top())) focal_q.pop();
+      while (!over_q.empty() && !live(over_q.top())) over_q.pop();
+      const int slot = (int)(expansions_ % (n_inad + (o_.anytime ? 1 : 0)));
+      int pick = -1;
+      for (int t = 0; t < n_inad && pick < 0 && slot < n_inad; ++t) {
+        const int q = (slot + t) % n_inad;
+        if (q == 0 && !focal_q.empty()) {
+          pick = focal_q.top();
+          focal_q.pop();
+        } else if (q == 1 && !over_q.empty()) {
+          pick = over_q.top();
+          over_q.pop();
+        }
+      }
+      if (pick < 0) {
+        pick = open.top();
+        open.pop();
+      }
+      ++expansions_;
+      closed[pick] = 1;
+      return pick;
+    };
+    const int B = o_.batch > 1 ? o_.batch : 1;
+    if (B > 1) {
+      // Several states per step: the learned part (crops, network, ranking) of every
+      // picked state and the exact evaluation of all their chosen children, and of
+      // every popped lazy block's children, in one persistent batched launch, with
+      // one synchronisation.  The queues, the selection rule and the stopping rules
+      // are those of the single-state search, applied between steps.
+      if (with_overlap)
+        return fail(PERCH_E_ARG, "the learned search with h_overlap expands one state per step");
+      int cap_crops = 0, cap_pairs = 0;
+      perch_status cst = cnn_capacity(o_.cnn, &cap_crops, &cap_pairs);
+      if (cst) return cst;
+      if ((int64_t)cap_crops < (int64_t)B * n_cells || (int64_t)cap_pairs < (int64_t)B * maxp)
+        return fail(PERCH_E_ARG,
+                    "network capacity (%d crops, %d pairs) below %d states per step (%lld, %lld)",
+                    cap_crops, cap_pairs, B, (long long)B * n_cells, (long long)B * maxp);
+      const size_t crop_elems = (size_t)64 * 64 * 2;
+      const size_t max_items = (size_t)B * maxp;
+      HIP_TRY(c_->s_bcrops.ensure((size_t)B * n_cells * crop_elems * sizeof(uint16_t)));
+      HIP_TRY(c_->s_bpairs.ensure((size_t)B * maxp * sizeof(perch_cnn_pair)));
+      HIP_TRY(c_->s_bpred.ensure((size_t)B * maxp * sizeof(float)));
+      HIP_TRY(c_->s_bcands.ensure((size_t)B * topk * sizeof(int2)));
+      HIP_TRY(c_->s_items.ensure(max_items * sizeof(int4)));
+      HIP_TRY(c_->s_bout.ensure(max_items * 2 * sizeof(int32_t)));
+      HIP_TRY(c_->s_hitems.ensure(max_items * sizeof(int4)));
+      HIP_TRY(c_->s_hbout.ensure(max_items * 2 * sizeof(int32_t)));
+      // the pair table once per state slot, crop indices offset by the slot's crops
+      std::vector<perch_cnn_pair> hpb((size_t)B * maxp);
+      for (int k = 0; k < B; ++k)
+        for (size_t i = 0; i < maxp; ++i) {
+          hpb[(size_t)k * maxp + i] = hp[i];
+          hpb[(size_t)k * maxp + i].crop += k * n_cells;
+        }
+      HIP_TRY(hipMemcpyAsync(c_->s_bpairs.p, hpb.data(), hpb.size() * sizeof(perch_cnn_pair),
+                             hipMemcpyHostToDevice, st0));
+      HIP_TRY(hipStreamSynchronize(st0));  // hpb is freed at the end of this block
+      if (!c_->s_batch) {
+        perch_ctx* self = c_;
+        perch_status st = perch_batch_create(&self, 1, st0, &c_->s_batch);
+        if (st) return st;
+      }
+      perch_batch* bat = c_->s_batch;
+      perch_status st = perch_batch_set_tuning(bat, 0, 0, 0, -1);  // sizes vary: no graph
+      if (st) return st;
+      int4* d_items = c_->s_items.as<int4>();
+      int32_t* d_out = c_->s_bout.as<int32_t>();
+      uint16_t* d_bcrops = c_->s_bcrops.as<uint16_t>();
+      float* d_bpred = c_->s_bpred.as<float>();
+      int2* d_bcands = c_->s_bcands.as<int2>();
+      int4* h_items = c_->s_hitems.as<int4>();
+      int32_t* h_out = c_->s_hbout.as<int32_t>();
+      std::vector<int> learn, lazy, owner;  // owner[slot]: node whose children the slot holds
+      std::vector<perch_parent> pars;
+      std::vector<char> full;  // learned slots whose top-k covered every child
+      for (;;) {
+        while (!open.empty() && !live(open.top())) open.pop();
+        if (open.empty()) {
+          if (have_) lower_bound_ = best_.g;
+          break;
+        }
+        const int64_t gmin = nodes[open.top()].g;
+        lower_bound_ = gmin;
+        trace(false);
+      trace(false);
+        if (have_ && best_.g <= gmin) break;
+        if (have_ && !o_.anytime && (double)best_.g <= w * (double)gmin) break;
+        if (over_budget()) return PERCH_E_BUDGET;
+        learn.clear();
+        lazy.clear();
+        while ((int)(learn.size() + lazy.size()) < B) {
+          const int pick = next_pick();
+          if (pick < 0) break;
+          if (nodes[pick].lazy)
+            lazy.push_back(pick);
+          else if (nodes[pick].j < K_)  // goals were offered when generated
+            learn.push_back(pick);
+        }
+        if (learn.empty() && lazy.empty()) continue;
+        const int L = (int)learn.size(), Z = (int)lazy.size();
+        pars.assign(L + Z, perch_parent{});
+        owner.assign(L + Z, -1);
+        for (int k = 0; k < L + Z; ++k) {
+          owner[k] = k < L ? learn[k] : nodes[lazy[k - L]].parent;
+          const Node& n = nodes[owner[k]];
+          pars[k].ctx = 0;
+          pars[k].j = n.j;
+          std::memcpy(pars[k].objs, n.objs, sizeof(perch_object) * n.j);
+        }
+        st = perch_batch_set_parents(bat, pars.data(), L + Z);
+        if (st) return st;
+        // the learned part of the picked states
+        for (int k = 0; k < L; ++k)
+          cnn::launch_crops(c_->obs.as<float>(), batch_slot_depth(bat, k), cam.W, cam.H,
+                            d_desc.as<cnn::CropDesc>(), n_cells, d_bcrops + (size_t)k * n_cells * crop_elems,
+                            st0);
+        if (L > 0) {
+          st = cnn_predict_on(o_.cnn, d_bcrops, L * n_cells, c_->s_bpairs.p, (int)(L * maxp),
+                              d_bpred, st0);
+          if (st) return st;
+        }
+        size_t n_items = 0;
+        full.assign(L, 0);
+        for (int k = 0; k < L; ++k) {
+          const std::vector<int> rest = remaining(nodes[learn[k]]);
+          const int cnt = (int)rest.size() * P;
+          MeshMask mask{};
+          for (int a = 0; a < nd; ++a)
+            mask.allow[a] = std::find(rest.begin(), rest.end(), dist[a]) != rest.end() ? 1 : 0;
+          const int kk = std::min(topk, cnt);
+          full[k] = kk == cnt;
+          st = rank_children(c_, d_bpred + (size_t)k * maxp, P, nd, mask, kk, d_dist.as<int>(),
+                             d_pose.as<int>(), d_bcands + (size_t)k * topk, st0);
+          if (st) return st;
+          launch_items_from_cands(d_bcands + (size_t)k * topk, kk, k, d_items + n_items, st0);
+          n_items += kk;
+        }
+        for (int z = 0; z < Z; ++z) {  // every child of a popped lazy block's parent
+          const std::vector<int> rest = remaining(nodes[owner[L + z]]);
+          MeshList ml{};
+          for (size_t a = 0; a < rest.size(); ++a) ml.id[a] = rest[a];
+          launch_items_all(L + z, ml, (int)rest.size(), d_pose.as<int>(), P, d_items + n_items,
+                           st0);
+          n_items += rest.size() * (size_t)P;
+        }
+        HIP_TRY(hipGetLastError());
+        st = perch_batch_eval(bat, reinterpret_cast<const perch_work*>(d_items), (int)n_items,
+                              d_out, d_out + n_items, nullptr);
+        if (st) return st;
+        HIP_TRY(hipMemcpyAsync(h_items, d_items, n_items * sizeof(int4), hipMemcpyDeviceToHost,
+                               st0));
+        HIP_TRY(hipMemcpyAsync(h_out, d_out, n_items * 2 * sizeof(int32_t),
+                               hipMemcpyDeviceToHost, st0));
+        HIP_TRY(hipStreamSynchronize(st0));
+        n_expanded_ += L + Z;
+        n_evaluated_ += (int64_t)n_items;
+        for (size_t i = 0; i < n_items; ++i) {
+          const int4 it = h_items[i];
+          const int s2 = h_out[n_items + i];
+          if (s2 == 1) {
+            const int pid = owner[it.x];
+            const Node par = nodes[pid];
+            push_child(par, pid, Child{it.y, it.z, h_out[i], 0});
+          } else if (s2 == 0) {
+            ++n_invalid_;
+          } else {
+            return fail(PERCH_E_UNSUPPORTED, "successor (%d, %d) failed with status %d", it.y,
+                        it.z, s2);
+          }
+        }
+        for (int k = 0; k < L; ++k) {  // the rest of each picked state's children wait
+          if (full[k]) continue;
+          Node lz = nodes[learn[k]];
+          lz.lazy = 1;
+          lz.parent = learn[k];
+          nodes.push_back(lz);
+          closed.push_back(0);
+          open.push((int)nodes.size() - 1);
+        }
+      }
+      return PERCH_OK;
+    }
     for (;;) {
       while (!open.empty() && !live(open.top())) open.pop();
       if (open.empty()) {  // every state was expanded: the incumbent is optimal
@@ -677,6 +888,7 @@ class Searcher {
       }
       const int64_t gmin = nodes[open.top()].g;
       lower_bound_ = gmin;
+      trace(false);
       if (have_ && best_.g <= gmin) break;  // incumbent proven optimal
       if (have_ && !o_.anytime && (double)best_.g <= w * (double)gmin) break;  // w-bound met
       if (over_budget()) return PERCH_E_BUDGET;
@@ -754,6 +966,12 @@ class Searcher {
     r->t_best_s = have_ ? t_best_ : -1.0;
     r->n_evaluated_best = have_ ? n_eval_best_ : -1;
     r->lower_bound = lower_bound_;
+    r->n_trace = n_trace_;
+    for (int k = 0; k < n_trace_; ++k) {
+      r->trace_t[k] = trace_t_[k];
+      r->trace_cost[k] = trace_cost_[k];
+      r->trace_lb[k] = trace_lb_[k];
+    }
   }
 
  private:
@@ -772,6 +990,9 @@ class Searcher {
   std::vector<int32_t> path_edges_;
   double t_best_ = -1.0;
   int64_t n_eval_best_ = -1;
+  int n_trace_ = 0;
+  double trace_t_[PERCH_TRACE] = {0};
+  int64_t trace_cost_[PERCH_TRACE] = {0}, trace_lb_[PERCH_TRACE] = {0};
 };
 
 }  // namespace
@@ -790,6 +1011,7 @@ extern "C" perch_status perch_search(perch_ctx* c, const perch_search_opts* opts
   Searcher s(c, opts);
   perch_status st = s.init();
   if (st) return st;
+
   if (opts->mode == PERCH_SEARCH_EXHAUSTIVE)
     st = s.exhaustive();
   else if (opts->mode == PERCH_SEARCH_LEARNED || opts->mode == PERCH_SEARCH_LEARNED_MHA)
@@ -798,6 +1020,7 @@ extern "C" perch_status perch_search(perch_ctx* c, const perch_search_opts* opts
     st = s.best_first(opts->n_priors > 0 ? 3 : 2);
   else
     st = s.best_first(opts->mode == PERCH_SEARCH_FOCAL ? 1 : 0);
+  s.trace(true);  // the trace's last entry: the state the search ends in
   s.fill(out);
   if (st == PERCH_E_BUDGET) return fail(PERCH_E_BUDGET, "search budget exhausted");
   return st;

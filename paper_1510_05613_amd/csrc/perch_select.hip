@@ -36,6 +36,22 @@ __global__ void k_child_cands(const int* idx_sorted, int k, const int* rest, int
   cands[i] = make_int2(rest[id / n_poses], pose_ids[id % n_poses]);
 }
 
+// Work items of a batched step: ranked candidates of parent slot `slot`.
+__global__ void k_items_from_cands(const int2* cands, int k, int slot, int4* items) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < k) items[i] = make_int4(slot, cands[i].x, cands[i].y, 0);
+}
+
+// Work items of a batched step: every child (meshes[u], pose_ids[b]) of parent slot
+// `slot`, u < n_meshes, b < n_poses, mesh-major.
+__global__ void k_items_all(int slot, MeshList meshes, int n_meshes, const int* pose_ids,
+                            int n_poses, int4* items) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i >= (long)n_meshes * n_poses) return;
+  const int u = (int)(i / n_poses), b = (int)(i - (long)u * n_poses);
+  items[i] = make_int4(slot, meshes.id[u], pose_ids[b], 0);
+}
+
 // Order-preserving map of a float to an unsigned key (negative values flipped,
 // positive ones with the sign bit set); -0 maps like +0.
 __device__ inline unsigned order_key(float v) {
@@ -181,6 +197,20 @@ void launch_child_cands(const int* idx_sorted, int k, const int* rest, int n_pos
   if (k > 0)
     hipLaunchKernelGGL(k_child_cands, dim3((k + 255) / 256), dim3(256), 0, s, idx_sorted, k,
                        rest, n_poses, pose_ids, cands);
+}
+
+void launch_items_from_cands(const int2* cands, int k, int slot, int4* items, hipStream_t s) {
+  if (k > 0)
+    hipLaunchKernelGGL(k_items_from_cands, dim3((k + 255) / 256), dim3(256), 0, s, cands, k,
+                       slot, items);
+}
+
+void launch_items_all(int slot, const MeshList& meshes, int n_meshes, const int* pose_ids,
+                      int n_poses, int4* items, hipStream_t s) {
+  const long n = (long)n_meshes * n_poses;
+  if (n > 0)
+    hipLaunchKernelGGL(k_items_all, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, slot,
+                       meshes, n_meshes, pose_ids, n_poses, items);
 }
 
 }  // namespace perch

@@ -277,25 +277,29 @@ def max_block(ds: Dataset, crops_per_batch: int) -> tuple:
     return max(crops_per_batch, most_c), max(most_b, most_p)
 
 
-SEARCHES = ("exhaustive", "ucs", "focal", "mha", "learned", "learned_mha", "random_init")
+SEARCHES = ("exhaustive", "ucs", "focal", "mha", "learned", "learned_mha", "learned_batched",
+            "random_init")
 
 
 def gain(net: "perch.Cnn", control: "perch.Cnn", indices: Sequence[int], config: int = 4,
          w: float = 3.0, topk: int = 64, budget_s: float = 0.0, log=None,
-         max_scenes: int = 0) -> dict:
+         max_scenes: int = 0, batched: "Optional[perch.Cnn]" = None, batch: int = 4) -> dict:
     """Time (and successor evaluations) until each search first holds the best
     scene, on held-out scenes.  exhaustive (small trees only) and ucs are the plain
     searches; focal is the paper's inadmissible depth heuristic without learning and
     mha the paper's own configuration (h_depth and h_overlap, Focal-MHA*);
     learned and random_init are the learned search with the trained and an
     untrained network, learned_mha the learned search with h_overlap added as a
-    second inadmissible queue.  The best scene is the optimum returned by a plain search
+    second inadmissible queue, learned_batched the learned search expanding `batch`
+    states per step with one batched exact launch (`batched`: the same network
+    sized for it; left out when None).  The best scene is the optimum returned by a plain search
     that finished; a search that never held it counts as not reaching it (None).
     budget_s > 0 limits every search; max_scenes > 0 stops after that many scenes
     (indices the generator cannot satisfy are skipped)."""
     lib = scenes.make_library(scenes.CONFIGS[config]["lib"])
     render = perch.GpuRenderer()
-    names = [k for k in SEARCHES if k != "exhaustive" or config in (1, 4)]
+    names = [k for k in SEARCHES if (k != "exhaustive" or config in (1, 4)) and
+             (k != "learned_batched" or batched is not None)]
     rows, proven = [], 0
     for i in indices:
         if max_scenes and len(rows) >= max_scenes:
@@ -318,6 +322,9 @@ def gain(net: "perch.Cnn", control: "perch.Cnn", indices: Sequence[int], config:
                                        topk=topk, budget_s=budget_s),
             learned_mha=lambda: ctx.search(perch.SEARCH_LEARNED_MHA, w=w, anytime=True, cnn=net,
                                            topk=topk, budget_s=budget_s),
+            learned_batched=lambda: ctx.search(perch.SEARCH_LEARNED, w=w, anytime=True,
+                                               cnn=batched, topk=topk, budget_s=budget_s,
+                                               batch=batch),
             random_init=lambda: ctx.search(perch.SEARCH_LEARNED, w=w, anytime=True, cnn=control,
                                            topk=topk, budget_s=budget_s))
         res = {k: run[k]() for k in names}
@@ -351,8 +358,12 @@ def gain(net: "perch.Cnn", control: "perch.Cnn", indices: Sequence[int], config:
                budget_s=budget_s or None)
     for j, name in enumerate(("time_to_best_s", "evals_to_best", "time_total_s", "evals_total")):
         out[name] = {k: med([r[k][j] for r in rows]) for k in names}
-    out["learned_wins_vs"] = {k: int(sum(r["learned"][0] < r[k][0] for r in rows))
-                              for k in names if k != "learned"}
+    for lk in ("learned", "learned_batched"):
+        if lk in names:
+            out[lk + "_wins_vs"] = {k: int(sum(r[lk][0] < r[k][0] for r in rows))
+                                    for k in names if k != lk}
+    if batched is not None:
+        out["batch"] = batch
     return out
 
 
@@ -435,6 +446,14 @@ def prior_gain(net: "perch.Cnn", indices: Sequence[int], config: int = 2, w: flo
                 wins_vs_mha={k: int(sum(r[k][0] < r["mha"][0] for r in rows))
                              for k in names[1:]},
                 network_prior_error_m=med([r["prior_error_m"] for r in rows]))
+
+
+def batched_network(path: str, config: int, batch: int) -> "perch.Cnn":
+    """The checkpoint's network sized for the learned search expanding `batch`
+    states per step."""
+    cfg = scenes.CONFIGS[config]
+    g = scenes.make_grid(cfg)
+    return load(path, max_crops=g.nx * g.ny * batch, max_pairs=cfg["K"][1] * g.P * batch)
 
 
 def search_networks(path: str, config: int, seed: int = 1):

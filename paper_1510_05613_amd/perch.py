@@ -75,7 +75,7 @@ class _SearchOpts(C.Structure):
                 ("pose_subset", C.c_void_p), ("n_pose_subset", C.c_int32),
                 ("cnn", C.c_void_p), ("topk", C.c_int32), ("icp_iters", C.c_int32),
                 ("icp_radius", C.c_float), ("priors", C.c_void_p), ("n_priors", C.c_int32),
-                ("prior_rad_m", C.c_float), ("prior_slot_m", C.c_float)]
+                ("prior_rad_m", C.c_float), ("prior_slot_m", C.c_float), ("batch", C.c_int32)]
 
 
 class _Result(C.Structure):
@@ -84,7 +84,9 @@ class _Result(C.Structure):
                 ("n_expanded", C.c_int64),
                 ("n_evaluated", C.c_int64), ("n_invalid", C.c_int64), ("t_total_s", C.c_double),
                 ("t_best_s", C.c_double), ("lower_bound", C.c_int64),
-                ("n_evaluated_best", C.c_int64), ("n_merged", C.c_int64)]
+                ("n_evaluated_best", C.c_int64), ("n_merged", C.c_int64),
+                ("n_trace", C.c_int32), ("trace_t", C.c_double * 64),
+                ("trace_cost", C.c_int64 * 64), ("trace_lb", C.c_int64 * 64)]
 
 
 _lib = None
@@ -337,7 +339,7 @@ class Context:
 
     def icp_children(self, cands, adjusted, n_match, status, iters: int = 10,
                      radius: float = 0.02):
-        """Local ICP (Sec. V-A) of the successors of the parent last set: cands and
+        """Local ICP (Sec. IV-E) of the successors of the parent last set: cands and
         adjusted int32 GPU tensors (n, 2) (adjusted = (mesh, arena pose index)),
         n_match and status int32 GPU tensors (n,).  Asynchronous."""
         n = cands.shape[0]
@@ -350,7 +352,7 @@ class Context:
                budget_s: float = 0.0, budget_expansions: int = 0, pose_subset=None,
                cnn: "Optional[Cnn]" = None, topk: int = 64, icp_iters: int = 0,
                icp_radius: float = 0.02, priors=None, prior_rad_m: float = 0.0,
-               prior_slot_m: float = 0.0) -> dict:
+               prior_slot_m: float = 0.0, batch: int = 1) -> dict:
         """Tree search of Alg. 1 on this scene (synchronous).  Returns the goal in
         insertion order plus its canonical (sorted) form, cost and statistics."""
         o = _SearchOpts()
@@ -359,6 +361,7 @@ class Context:
         o.cnn = None if cnn is None else cnn.h.value
         o.topk = int(topk)
         o.icp_iters, o.icp_radius = int(icp_iters), float(icp_radius)
+        o.batch = int(batch)
         pri = None
         if priors is not None and len(priors):  # [(mesh, x, y, theta), ...]
             pri = (PerchPosePrior * len(priors))()
@@ -381,7 +384,9 @@ class Context:
                     n_expanded=int(r.n_expanded), n_evaluated=int(r.n_evaluated),
                     n_invalid=int(r.n_invalid), t_total_s=float(r.t_total_s),
                     t_best_s=float(r.t_best_s), lower_bound=int(r.lower_bound),
-                    n_evaluated_best=int(r.n_evaluated_best), n_merged=int(r.n_merged))
+                    n_evaluated_best=int(r.n_evaluated_best), n_merged=int(r.n_merged),
+                    trace=[(float(r.trace_t[k]), int(r.trace_cost[k]), int(r.trace_lb[k]))
+                           for k in range(r.n_trace)])
 
     def render(self, objs, composite: bool = True):
         """Depth images (+inf = empty) of objects [(mesh, pose), ...]."""

@@ -611,7 +611,7 @@ def offgrid_truth(scene: Scene, render: RenderFn, shift: float = 0.4, seed: int 
     generator's noise recipe (N(0, 2 mm), quantised to 1 mm).  Returns (true poses
     (K, 4) float32, depth_obs).  The nearest grid pose of each object stays its
     ground-truth pose; the grid can no longer express the scene exactly, which is
-    what the local ICP of Sec. V-A compensates for."""
+    what the local ICP of Sec. IV-E compensates for."""
     rng = np.random.default_rng(10_000 + scene.seed + seed)
     g = scene.grid
     true = []

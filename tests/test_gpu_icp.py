@@ -1,4 +1,4 @@
-"""Local ICP (Sec. V-A) on the GPU against the oracle, through the C ABI.
+"""Local ICP (Sec. IV-E) on the GPU against the oracle, through the C ABI.
 
 Rule: the status (Eq. 3 at the grid pose) is equal unless the oracle flags a
 parent depth tie.  Both sides associate in FP64 from the same float32 depth
@@ -219,7 +219,7 @@ def test_search_with_icp_is_consistent_and_w_bounded(c1):
 
 
 def test_icp_compensates_for_an_off_grid_object():
-    """Sec. V-A's purpose: with the objects moved off the grid (scenes.offgrid_truth),
+    """Sec. IV-E's purpose: with the objects moved off the grid (scenes.offgrid_truth),
     the cheapest aligned child of the front object costs a fraction of the cheapest
     grid child, and its pose lands within 2 mm of the true one."""
     from paper_1510_05613_amd import scenes

@@ -128,3 +128,56 @@ def test_trained_network_finds_the_best_scene_sooner():
         pl.append(ex["n_evaluated_best"])
     assert np.median(ln) < np.median(pl)
     assert np.median(ln) < np.median(rc)
+
+
+def batched_net(seed, B):
+    net = perch.Cnn(3, max_crops=144 * B, max_pairs=3 * 1152 * B)
+    net.set_params(learn.init_params(3, seed))
+    return net
+
+
+@pytest.mark.parametrize("B", [2, 8])
+@pytest.mark.parametrize("k", [0, 1])
+@pytest.mark.parametrize("topk", [1, 64])
+def test_learned_batched_anytime_reaches_the_exhaustive_optimum(k, topk, B):
+    """Several states per step (one batched exact launch per step): run to the end,
+    the search still returns the optimum of the whole tree, proved by its bound."""
+    sc = held_out_scene(k)
+    ctx = perch.context_from_scene(sc)
+    ex = ctx.search(perch.SEARCH_EXHAUSTIVE)
+    r = ctx.search(perch.SEARCH_LEARNED, w=2.0, anytime=True, cnn=batched_net(k, B), topk=topk,
+                   batch=B)
+    assert r["found"] and not r["budget_exhausted"]
+    assert r["cost"] == ex["cost"]
+    assert r["lower_bound"] >= r["cost"]
+    assert sum(r["edge_cost"]) == r["cost"]
+    # the path re-evaluates to its edge costs through the single-parent entry point
+    objs = r["objs"]
+    for j in range(len(objs)):
+        c = torch.as_tensor(np.array([objs[j]], np.int32)).cuda()
+        st, cost, _ = ctx.evaluate(objs[:j], c)
+        torch.cuda.synchronize()
+        assert int(st[0]) == 1 and int(cost[0]) == r["edge_cost"][j]
+
+
+@pytest.mark.parametrize("w", [1.0, 3.0])
+def test_learned_batched_first_goal_within_w(w):
+    sc = held_out_scene(3)
+    ctx = perch.context_from_scene(sc)
+    opt = ctx.search(perch.SEARCH_UCS)["cost"]
+    r = ctx.search(perch.SEARCH_LEARNED, w=w, anytime=False, cnn=batched_net(1, 4), topk=32,
+                   batch=4)
+    assert r["found"]
+    assert r["cost"] <= w * opt + 1e-9
+    assert r["lower_bound"] <= opt
+
+
+def test_learned_batched_needs_network_capacity():
+    """A network sized for one state per step is refused for a batched search (the
+    crops of B states do not fit), and h_overlap is a single-state queue."""
+    sc = held_out_scene(0)
+    ctx = perch.context_from_scene(sc)
+    with pytest.raises(perch.PerchError):
+        ctx.search(perch.SEARCH_LEARNED, w=2.0, anytime=True, cnn=random_net(0), batch=4)
+    with pytest.raises(perch.PerchError):
+        ctx.search(perch.SEARCH_LEARNED_MHA, w=2.0, anytime=True, cnn=batched_net(0, 4), batch=4)

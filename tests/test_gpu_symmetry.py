@@ -1,4 +1,4 @@
-"""Searches with rotationally symmetric objects (tried once per (x, y), Sec. V-A)
+"""Searches with rotationally symmetric objects (tried once per (x, y), Sec. IV-E)
 and with replicated instances (one mesh id several times in the multiset),
 GPU-evaluated through the C ABI, against the oracle's searches under the same
 rules: same optimum, same goal, same evaluation counts."""

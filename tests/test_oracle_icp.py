@@ -1,4 +1,4 @@
-"""Pins of the oracle's local ICP (Sec. V-A, compensating for a coarse pose
+"""Pins of the oracle's local ICP (Sec. IV-E, compensating for a coarse pose
 discretization) against what the geometry fixes: a first-order step recovers a
 known small motion of exact planar correspondences, a translation exactly; an
 object already at its observed pose stays there; an object observed off the

@@ -1,5 +1,5 @@
 """Pins of the oracle's searches with rotationally symmetric objects and with
-replicated instances (Sec. V-A: a symmetric object only needs (x, y); identical
+replicated instances (Sec. IV-E: a symmetric object only needs (x, y); identical
 objects are one mesh id placed several times).  Tree search (exhaustive and
 uniform-cost) must equal brute force over joint assignments under the same pose
 restriction, the restriction must try exactly one pose per (x, y) cell, and a
