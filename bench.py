@@ -104,10 +104,15 @@ def parse_args(argv=None):
     ap.add_argument("--cell", type=float, default=0.0, help="voxel cell / delta (0 = default)")
     ap.add_argument("--radius", type=int, default=-1,
                     help="dJ_r query: 0 pixel window, 1 voxel hash (-1 = default)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="config 3: keep the default batch tuning instead of autotuning it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--learned-scenes", type=int, default=20,
                     help="held-out config-4 scenes for the learned-vs-plain search leg (0 = off)")
+    ap.add_argument("--learned-only", action="store_true",
+                    help="print only the learned legs and the network kernels' rates "
+                         "(for profiling the learned expansion)")
     ap.add_argument("--learned-640-scenes", type=int, default=0,
                     help="held-out 640x480 scenes for a learned-vs-plain leg (minutes; 0 = off)")
     ap.add_argument("--icp-iters", type=int, default=10,
@@ -199,11 +204,13 @@ def run_batched(args):
     cfg = scenes.CONFIGS[args.config]
     lib = scenes.make_library(cfg["lib"])
     rend = perch.GpuRenderer()
-    scs = [scenes.make_scene(args.config, i, rend, lib) for i in range(cfg.get("n_scenes", 64))]
+    scs = []
+    for i in range(cfg.get("n_scenes", 64)):
+        scs.append(scenes.make_scene(args.config, i, rend, lib))
+        if i % 16 == 15:
+            print(f"config 3: {i + 1} scenes built", file=sys.stderr, flush=True)
     ctxs = [perch.context_from_scene(sc) for sc in scs]
     batch = perch.Batch(ctxs)
-    if args.threads or args.tile:
-        batch.set_tuning(args.threads, args.tile)
     levels = batched_levels(scs)
     dev = []
     for parents, items in levels:
@@ -211,6 +218,25 @@ def run_batched(args):
         dev.append(dict(parents=parents, items=torch.as_tensor(items).cuda(),
                         cost=torch.empty(n, dtype=torch.int32, device="cuda"),
                         status=torch.empty(n, dtype=torch.int32, device="cuda")))
+    tuning = None
+    if args.threads or args.tile:
+        batch.set_tuning(args.threads, args.tile)
+        tuning = {"threads": args.threads, "tile_px": args.tile, "source": "command line"}
+    elif not args.no_autotune:
+        # calibrate on an ordered uniform sample of the level with the most successors
+        # (outputs are bit-identical across settings; the untimed autotune precedes
+        # the warm-up)
+        cal = max(dev, key=lambda d: d["items"].shape[0])
+        n_cal = min(cal["items"].shape[0], 1 << 18)
+        pick = np.sort(np.random.default_rng(0).choice(cal["items"].shape[0], n_cal,
+                                                       replace=False))
+        batch.set_parents(cal["parents"])
+        t0 = time.perf_counter()
+        best = batch.autotune(cal["items"][torch.as_tensor(pick).cuda()].contiguous(), reps=3)
+        tuning = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in best.items()}
+        tuning.update(source="perch_batch_autotune", calibration_items=n_cal)
+        print(f"config 3: autotuned in {time.perf_counter() - t0:.1f} s: {tuning}",
+              file=sys.stderr, flush=True)
     n_step = sum(len(it) for _, it in levels)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in dev]
     kernel_ms = 0.0
@@ -230,6 +256,7 @@ def run_batched(args):
 
     for _ in range(args.warmup):
         step(False)
+    print("config 3: warm-up done", file=sys.stderr, flush=True)
     for d in dev:
         st = d["status"].cpu().numpy()
         if np.any(st < 0):
@@ -247,7 +274,8 @@ def run_batched(args):
                                     f"200-20k triangles; one step = every level's successors of "
                                     f"all scenes, one launch per level ({n_step})"),
                        "successors_per_step": n_step,
-                       "kernel_ms_per_step": round(kernel_ms / args.steps, 3)}}
+                       "kernel_ms_per_step": round(kernel_ms / args.steps, 3),
+                       "tuning": tuning}}
 
 
 def level_throughput(config: int, scene_idx: int, steps: int, warmup: int) -> dict:
@@ -407,6 +435,67 @@ def cpu_baseline(args, work_gpu):
                        f"{int(sizes.sum())}, scene regenerated with the oracle renderer, "
                        f"{t_used:.1f} s on {cores} threads; {n1} more in {t1:.1f} s on one "
                        f"thread")}
+
+
+# Algorithmic FLOPs of the network per 64 x 64 crop (multiply-adds counted twice;
+# conv l has HO x HO output pixels, 32 output channels and 9 * C_in taps, C_in = 2
+# for the first layer and 32 after it).
+CNN_CONV_FLOPS = [2 * 64 * 64 * 32 * 18, 2 * 32 * 32 * 32 * 288, 2 * 16 * 16 * 32 * 288,
+                  2 * 8 * 8 * 32 * 288]
+CNN_FWD_FLOPS = sum(CNN_CONV_FLOPS)  # 29,491,200
+# a training step: forward, weight gradients of every layer, data gradients of layers 2-4
+CNN_TRAIN_FLOPS = 2 * CNN_FWD_FLOPS + CNN_FWD_FLOPS - CNN_CONV_FLOPS[0]
+PEAK_BF16_TFLOPS = 2500.0
+
+
+def cnn_leg(sizes=(64, 256, 1024, 4096), reps: int = 10) -> dict:
+    """The learned ranker's bf16 MFMA kernels: forward (4 convolutions, pooling and
+    the head, one pair per crop) and one training step on n random crops, HIP events
+    on the network's stream, median of `reps`; TFLOP/s from the convolutions'
+    algorithmic FLOPs against the dense bf16 MFMA peak."""
+    import torch
+
+    from paper_1510_05613_amd import learn, perch
+
+    n_mesh = 12
+    net = perch.Cnn(n_mesh, max_crops=max(sizes), max_pairs=max(sizes))
+    net.set_params(learn.init_params(n_mesh, 0))
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    rows = []
+    for n in sizes:
+        crops = torch.rand((n, 64, 64, 2), generator=g, device="cuda").to(torch.bfloat16)
+        crops = crops.view(torch.int16)
+        yaw = np.linspace(0.0, 2 * np.pi, n, endpoint=False)
+        pairs = perch.Cnn.pairs(np.arange(n), np.arange(n) % n_mesh, np.cos(yaw), np.sin(yaw))
+        target = torch.rand(n, generator=g, device="cuda")
+
+        def timed(fn):
+            for _ in range(2):
+                fn()
+            out = []
+            for _ in range(reps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(net.stream)
+                fn()
+                e1.record(net.stream)
+                e1.synchronize()
+                out.append(e0.elapsed_time(e1))
+            return float(np.median(out))
+
+        f_ms = timed(lambda: net.predict(crops, pairs))
+        t_ms = timed(lambda: net.train_step(crops, pairs, target, 1e-9, want_loss=False))
+        f_tf = CNN_FWD_FLOPS * n / (f_ms * 1e-3) / 1e12
+        t_tf = CNN_TRAIN_FLOPS * n / (t_ms * 1e-3) / 1e12
+        rows.append({"crops": n, "forward_ms": round(f_ms, 4), "forward_tflops": round(f_tf, 2),
+                     "forward_frac": round(f_tf / PEAK_BF16_TFLOPS, 4),
+                     "train_step_ms": round(t_ms, 4), "train_tflops": round(t_tf, 2),
+                     "train_frac": round(t_tf / PEAK_BF16_TFLOPS, 4)})
+    net.close()
+    return {"bound": "mfma", "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s", "dtype": "bf16",
+            "fwd_flops_per_crop": CNN_FWD_FLOPS, "train_flops_per_crop": CNN_TRAIN_FLOPS,
+            "sizes": rows,
+            "note": "an expansion ranks 64-128 crops (160x120) or up to 256 (640x480)"}
 
 
 def learned_leg(n_scenes: int) -> dict:
@@ -669,6 +758,14 @@ def main(argv=None):
     if args.config == 3:
         print(json.dumps(run_batched(args)), flush=True)
         return 0
+    if args.learned_only:
+        out = {"cnn": cnn_leg()}
+        if args.learned_scenes > 0:
+            out["learned"] = learned_leg(args.learned_scenes)
+        if args.learned_640_scenes > 0:
+            out["learned_640x480"] = learned_leg_640(args.learned_640_scenes)
+        print(json.dumps(out), flush=True)
+        return 0
     cfg = scenes.CONFIGS[args.config]
     lib = scenes.make_library(cfg["lib"])
     sc = scenes.make_scene(args.config, args.scene, perch.GpuRenderer(), lib)
@@ -795,7 +892,8 @@ def main(argv=None):
         out["icp"] = icp_leg(ctx, sc, dev[0], args.icp_iters)
     if args.other_configs and args.config == 2:
         out["config5"] = level_throughput(5, 0, steps=3, warmup=1)
-        c3 = run_batched(argparse.Namespace(config=3, threads=0, tile=0, warmup=1, steps=2))
+        c3 = run_batched(argparse.Namespace(config=3, threads=0, tile=0, no_autotune=False,
+                                              warmup=1, steps=2))
         out["config3"] = {k: c3[k] for k in ("value", "unit", "steps", "ms_per_step")}
         out["config3"].update(c3["config"])
     if args.full_scenes > 0 and args.config == 2:
@@ -808,6 +906,7 @@ def main(argv=None):
         out["icp_offgrid"] = icp_offgrid_leg(args.icp_offgrid_scenes)
     if args.learned_scenes > 0 and args.config == 2:
         out["learned"] = learned_leg(args.learned_scenes)
+        out["cnn"] = cnn_leg()
     if args.learned_640_scenes > 0 and args.config == 2:
         out["learned_640x480"] = learned_leg_640(args.learned_640_scenes)
     if not args.no_cpu_baseline:

@@ -277,6 +277,30 @@ perch_status perch_batch_eval(perch_batch* b, const perch_work* items_dev, int32
 perch_status perch_batch_set_tuning(perch_batch* b, int32_t threads, int32_t tile_px,
                                     int32_t use_graph, int32_t grid);
 
+typedef struct {
+  int32_t threads;        /* threads per workgroup of the batched launch             */
+  int32_t tile_px;        /* z-tile pixels                                           */
+  int32_t radius_mode;    /* dJ_r query of every context: 0 pixel window, 1 voxel hash */
+  float cell_over_delta;  /* voxel cell / delta of every context (radius_mode 1)     */
+  float ms;               /* median time of the calibration launch with this setting */
+  float default_ms;       /* the same for the setting in force before tuning (0 when */
+                          /* taken from the cache)                                   */
+} perch_batch_tuning;
+
+/* Autotuner of the batched launch (the tile shapes and radius query of Sec. IV-E's
+ * parallel successor generation): times each candidate setting (threads per
+ * workgroup 512 / 256, z-tile sized automatically or 8,192 / 12,288 pixels, radius
+ * query window or voxel hash with cells of 2 and 1 delta) on the calibration work
+ * list items_dev[0..n) (device) over the parents last set, reps timed launches each
+ * after a warm-up, checks that every setting reproduces the first one's costs and
+ * statuses bit for bit, applies the fastest to the batch (and the radius query to
+ * its contexts) and records it in the JSON-lines cache at cache_path (nullable)
+ * keyed by device, contexts and work shape; a cache hit is applied without timing.
+ * Needs perch_batch_set_parents first (PERCH_E_STATE).  Synchronous. */
+perch_status perch_batch_autotune(perch_batch* b, const perch_work* items_dev, int32_t n,
+                                  int32_t reps, const char* cache_path,
+                                  perch_batch_tuning* best);
+
 /* ---- learned successor-cost network (an inadmissible heuristic, Sec. IV-C) ---- */
 
 /* A small CNN predicting log(1 + c(s, s')) of a successor from a 64 x 64 x 2 depth

@@ -8,6 +8,10 @@
 // atomic counter.  The launch (counter reset + persistent kernel) is captured in
 // a hipGraph on a private stream and replayed on the caller's stream.
 #include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <string>
 #include <vector>
 
 #include "perch_ctx.h"
@@ -263,3 +267,161 @@ perch_status perch_batch_eval(perch_batch* b, const perch_work* items_dev, int32
 }
 
 }  // extern "C"
+
+namespace {
+
+std::string batch_fingerprint(const perch_batch* b, int n) {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  std::memset(&prop, 0, sizeof(prop));
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipGetDeviceProperties(&prop, dev);
+  long long tris = 0, px = 0;
+  for (const perch_ctx* c : b->ctxs) {
+    for (const HostMesh& m : c->meshes) tris += (long long)m.tris.size() / 3;
+    px += (long long)c->cam.W * c->cam.H;
+  }
+  char buf[512];
+  snprintf(buf, sizeof buf, "batch|%s/%d|c%zu|px%lld|t%lld|v%d|p%d|n%d", prop.gcnArchName,
+           prop.multiProcessorCount, b->ctxs.size(), px, tris, b->max_nv(), b->n_parents, n);
+  return buf;
+}
+
+bool batch_cache_lookup(const char* path, const std::string& key, perch_batch_tuning* t) {
+  if (!path) return false;
+  std::ifstream f(path);
+  std::string line;
+  bool found = false;
+  const std::string tag = "\"key\": \"" + key + "\"";
+  while (std::getline(f, line)) {
+    if (line.find(tag) == std::string::npos) continue;
+    perch_batch_tuning r{};
+    const char* q = strstr(line.c_str(), "\"threads\":");
+    if (!q || sscanf(q, "\"threads\": %d, \"tile_px\": %d, \"radius_mode\": %d, "
+                        "\"cell_over_delta\": %f, \"ms\": %f",
+                     &r.threads, &r.tile_px, &r.radius_mode, &r.cell_over_delta, &r.ms) != 5)
+      continue;
+    *t = r;  // the last matching line wins
+    found = true;
+  }
+  return found;
+}
+
+void batch_cache_store(const char* path, const std::string& key, const perch_batch_tuning& t) {
+  if (!path) return;
+  std::ofstream f(path, std::ios::app);
+  f << "{\"key\": \"" << key << "\", \"threads\": " << t.threads << ", \"tile_px\": " << t.tile_px
+    << ", \"radius_mode\": " << t.radius_mode << ", \"cell_over_delta\": " << t.cell_over_delta
+    << ", \"ms\": " << t.ms << "}\n";
+}
+
+// Applies a radius query (and cell size) to every context of the batch and
+// rewrites the scene table and the kernel flags to match.
+perch_status batch_apply_radius(perch_batch* b, int mode, float cell) {
+  for (perch_ctx* c : b->ctxs) {
+    perch_status st = perch_set_tuning(c, 0, 0, cell, mode);
+    if (st) return st;
+  }
+  int hash = 0;
+  perch_status st = upload_scene_table(b, &hash);
+  if (st) return st;
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  b->flags = (b->flags & ~kBatchHash) | hash;
+  return PERCH_OK;
+}
+
+}  // namespace
+
+extern "C" perch_status perch_batch_autotune(perch_batch* b, const perch_work* items_dev,
+                                             int32_t n, int32_t reps, const char* cache_path,
+                                             perch_batch_tuning* best) {
+  if (!b || !best || !items_dev || n <= 0 || reps < 1) return fail(PERCH_E_ARG, "bad arguments");
+  if (b->table_tile < 0) return fail(PERCH_E_STATE, "perch_batch_set_parents not called");
+  const std::string key = batch_fingerprint(b, n);
+  perch_batch_tuning t{};
+  if (batch_cache_lookup(cache_path, key, &t)) {
+    perch_status st = batch_apply_radius(b, t.radius_mode, t.cell_over_delta);
+    if (!st) st = perch_batch_set_tuning(b, t.threads, t.tile_px, -1, -1);
+    if (st) return st;
+    t.default_ms = 0.0f;
+    *best = t;
+    return PERCH_OK;
+  }
+  DevBuf out;
+  HIP_TRY(out.ensure((size_t)n * 2 * sizeof(int32_t)));
+  int32_t* cost = out.as<int32_t>();
+  int32_t* status = cost + n;
+  std::vector<int32_t> ref, got((size_t)n * 2);
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  struct Cfg {
+    int threads, tile, mode;
+    float cell;
+  };
+  // the setting in force first (the default), then the candidates
+  const perch_ctx* c0 = b->ctxs[0];
+  const Cfg keep{b->threads, b->tile_px > 0 ? b->tile_px : -1, c0->radius_mode,
+                 c0->cell_over_delta};
+  std::vector<Cfg> cfgs{keep};
+  for (int th : {512, 256})
+    for (int tile : {-1, 8192, 12288}) {
+      cfgs.push_back({th, tile, 0, keep.cell});
+      cfgs.push_back({th, tile, 1, 2.0f});
+      cfgs.push_back({th, tile, 1, 1.0f});
+    }
+  perch_batch_tuning bestt{};
+  bestt.ms = 1e30f;
+  float default_ms = 0.0f;
+  perch_status err = PERCH_OK;
+  for (size_t k = 0; k < cfgs.size() && !err; ++k) {
+    const Cfg& g = cfgs[k];
+    err = batch_apply_radius(b, g.mode, g.cell);
+    if (!err) err = perch_batch_set_tuning(b, g.threads, g.tile, -1, -1);
+    if (err) break;
+    if (b->lds_bytes() > 160 * 1024 - 2304) continue;  // with the static LDS
+    err = perch_batch_eval(b, items_dev, n, cost, status, nullptr);  // warm-up (graph capture)
+    if (err) break;
+    std::vector<float> ms;
+    for (int r = 0; r < reps && !err; ++r) {
+      if (hipEventRecord(e0, b->stream) != hipSuccess) err = fail(PERCH_E_HIP, "event record");
+      if (!err) err = perch_batch_eval(b, items_dev, n, cost, status, nullptr);
+      if (!err && hipEventRecord(e1, b->stream) != hipSuccess) err = fail(PERCH_E_HIP, "event");
+      if (!err && hipEventSynchronize(e1) != hipSuccess) err = fail(PERCH_E_HIP, "event sync");
+      float v = 0;
+      if (!err && hipEventElapsedTime(&v, e0, e1) != hipSuccess) err = fail(PERCH_E_HIP, "timing");
+      ms.push_back(v);
+    }
+    if (err) break;
+    if (hipMemcpy(got.data(), cost, got.size() * sizeof(int32_t), hipMemcpyDeviceToHost) !=
+        hipSuccess) {
+      err = fail(PERCH_E_HIP, "copy of tuning outputs failed");
+      break;
+    }
+    if (ref.empty()) {
+      ref = got;
+    } else if (ref != got) {
+      err = fail(PERCH_E_STATE, "setting threads=%d tile=%d mode=%d cell=%.1f changed the results",
+                 g.threads, g.tile, g.mode, g.cell);
+      break;
+    }
+    std::sort(ms.begin(), ms.end());
+    const float med = ms[ms.size() / 2];
+    if (k == 0) default_ms = med;
+    if (med < bestt.ms) bestt = perch_batch_tuning{g.threads, b->tile(), g.mode, g.cell, med, 0.0f};
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  out.release();
+  if (err || bestt.ms >= 1e30f) {
+    (void)batch_apply_radius(b, keep.mode, keep.cell);
+    (void)perch_batch_set_tuning(b, keep.threads, keep.tile, -1, -1);
+    return err ? err : fail(PERCH_E_UNSUPPORTED, "no tuning candidate fits the LDS");
+  }
+  perch_status st = batch_apply_radius(b, bestt.radius_mode, bestt.cell_over_delta);
+  if (!st) st = perch_batch_set_tuning(b, bestt.threads, bestt.tile_px, -1, -1);
+  if (st) return st;
+  bestt.default_ms = default_ms;
+  batch_cache_store(cache_path, key, bestt);
+  *best = bestt;
+  return PERCH_OK;
+}

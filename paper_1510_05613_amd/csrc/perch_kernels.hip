@@ -5,11 +5,14 @@
 // parent s (Sec. IV-A): it transforms the candidate's vertices into LDS, rasterises
 // its front faces into an LDS z-tile over the footprint, composites against the
 // parent depth (the non-occlusion test of Eq. 3 and the new points dR), counts
-// dR points unexplained by the observed cloud through a uniform voxel hash
-// (dJ_r), counts observed points inside the candidate's volume unexplained by dR
+// dR points unexplained by the observed cloud (dJ_r) by an exact pixel-window scan
+// of the observed depth image (or, in radius mode 1, a uniform voxel hash of the
+// cloud), counts observed points inside the candidate's volume unexplained by dR
 // through an exact pixel window over the LDS tile (dJ_o), and at the goal level
 // updates the parent's residual set U (Eq. 2, residual(K)).  Counts are wave
-// ballot/popcount reductions.
+// ballot/popcount reductions.  The distance tests of Eq. 1 and the volume test are
+// taken in float32 where a derived rounding margin proves the sign and in FP64
+// otherwise, so every decision is that of exact arithmetic on the same inputs.
 //
 // Built with -ffp-contract=off: the float32 vertex stage is part of the
 // rasterisation rule and must not have products fused into adds.

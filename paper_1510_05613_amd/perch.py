@@ -32,6 +32,7 @@ EXPORTS = ("perch_create", "perch_destroy", "perch_set_observation", "perch_add_
            "perch_get_info",
            "perch_search", "perch_batch_create", "perch_batch_destroy",
            "perch_batch_set_parents", "perch_batch_eval", "perch_batch_set_tuning",
+           "perch_batch_autotune",
            "perch_autotune", "perch_cnn_create", "perch_cnn_destroy", "perch_cnn_param_count",
            "perch_cnn_set_params", "perch_cnn_get_params", "perch_cnn_crops", "perch_cnn_predict",
            "perch_rank_children", "perch_cnn_train_step", "perch_cnn_gradients", "perch_last_error")
@@ -62,6 +63,11 @@ class PerchParent(C.Structure):
 class _Tuning(C.Structure):
     _fields_ = [("threads", C.c_int32), ("tile_px", C.c_int32), ("radius_mode", C.c_int32),
                 ("cell_over_delta", C.c_float), ("ms", C.c_float)]
+
+
+class _BatchTuning(C.Structure):
+    _fields_ = [("threads", C.c_int32), ("tile_px", C.c_int32), ("radius_mode", C.c_int32),
+                ("cell_over_delta", C.c_float), ("ms", C.c_float), ("default_ms", C.c_float)]
 
 
 class PerchPosePrior(C.Structure):
@@ -139,6 +145,7 @@ def load(path: str = LIB_PATH):
     L.perch_batch_set_parents.argtypes = [P, P, I32]
     L.perch_batch_eval.argtypes = [P, P, I32, P, P, P]
     L.perch_batch_set_tuning.argtypes = [P, I32, I32, I32, I32]
+    L.perch_batch_autotune.argtypes = [P, P, I32, I32, C.c_char_p, C.POINTER(_BatchTuning)]
     L.perch_cnn_param_count.restype = C.c_int64
     L.perch_last_error.restype = C.c_char_p
     for name in EXPORTS:
@@ -428,6 +435,19 @@ class Batch:
 
     def set_tuning(self, threads: int = 0, tile_px: int = 0, use_graph: int = -1, grid: int = -1):
         _check(load().perch_batch_set_tuning(self.h, threads, tile_px, use_graph, grid))
+
+    def autotune(self, items, reps: int = 3, cache_path: Optional[str] = None) -> dict:
+        """Times the batched launch's settings on the calibration work list `items`
+        (int32 GPU tensor (n, 4)) over the parents last set, applies the fastest
+        (outputs bit-identical across settings) and returns it with the time of the
+        setting in force before."""
+        t = _BatchTuning()
+        n = items.shape[0]
+        _check(load().perch_batch_autotune(self.h, _dev_ptr(items, "int32", 4 * n), n, reps,
+                                           None if cache_path is None else cache_path.encode(),
+                                           C.byref(t)))
+        return dict(threads=t.threads, tile_px=t.tile_px, radius_mode=t.radius_mode,
+                    cell_over_delta=t.cell_over_delta, ms=t.ms, default_ms=t.default_ms)
 
     def set_parents(self, parents):
         """parents: list of (context index, [(mesh, pose), ...])."""

@@ -281,3 +281,44 @@ def test_tuning_after_set_parents_matches_a_fresh_batch(mixed):
             assert np.array_equal(a, f), (threads, tile)
         fresh.close()
     late.close()
+
+
+def test_batch_autotuner_keeps_outputs_and_is_no_slower(mixed, tmp_path):
+    """perch_batch_autotune on a mixed batch: the chosen setting times no slower
+    than the setting in force before (both timed in the same call), the batch's
+    outputs after tuning equal the per-parent evaluation bit for bit, and a second
+    call with the same work shape is a cache hit that applies the same setting."""
+    scs, ctxs = mixed
+    rng = np.random.default_rng(33)
+    parents = []
+    for ci, sc in enumerate(scs):
+        parents += _gt_parents(sc, ci)
+    items = _items_for(parents, scs, rng, 80)
+    dev_items = torch.as_tensor(items).cuda()
+    n = len(items)
+    ref = _reference(ctxs, parents, items)
+    b = perch.Batch(ctxs)
+    b.set_parents(parents)
+    cache = str(tmp_path / "batch_tune.jsonl")
+    try:
+        best = b.autotune(dev_items, reps=2, cache_path=cache)
+        assert best["threads"] in (256, 512)
+        assert best["radius_mode"] in (0, 1)
+        assert 0 < best["ms"] <= best["default_ms"]
+        cost = torch.full((n,), -7, dtype=torch.int32, device="cuda")
+        st = torch.full((n,), -7, dtype=torch.int32, device="cuda")
+        comps = torch.full((n, 5), -7, dtype=torch.int32, device="cuda")
+        b.eval(dev_items, cost, st, comps)
+        torch.cuda.synchronize()
+        for a, g in zip(ref, (st.cpu().numpy(), cost.cpu().numpy(), comps.cpu().numpy())):
+            assert np.array_equal(a, g), best
+        hit = b.autotune(dev_items, reps=2, cache_path=cache)
+        assert hit["default_ms"] == 0.0  # applied from the cache, not timed
+        for k in ("threads", "tile_px", "radius_mode"):
+            assert hit[k] == best[k], k
+        with open(cache) as f:
+            assert len(f.read().splitlines()) == 1
+    finally:
+        b.close()
+        for c in ctxs:  # the shared contexts go back to the window scan
+            c.set_tuning(0, 0, 2.0, 0)
