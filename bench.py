@@ -113,6 +113,8 @@ def parse_args(argv=None):
     ap.add_argument("--learned-only", action="store_true",
                     help="print only the learned legs and the network kernels' rates "
                          "(for profiling the learned expansion)")
+    ap.add_argument("--no-cnn-leg", action="store_true",
+                    help="skip the network kernels' rate leg")
     ap.add_argument("--learned-640-scenes", type=int, default=0,
                     help="held-out 640x480 scenes for a learned-vs-plain leg (minutes; 0 = off)")
     ap.add_argument("--icp-iters", type=int, default=10,
@@ -759,7 +761,7 @@ def main(argv=None):
         print(json.dumps(run_batched(args)), flush=True)
         return 0
     if args.learned_only:
-        out = {"cnn": cnn_leg()}
+        out = {} if args.no_cnn_leg else {"cnn": cnn_leg()}
         if args.learned_scenes > 0:
             out["learned"] = learned_leg(args.learned_scenes)
         if args.learned_640_scenes > 0:
@@ -906,7 +908,8 @@ def main(argv=None):
         out["icp_offgrid"] = icp_offgrid_leg(args.icp_offgrid_scenes)
     if args.learned_scenes > 0 and args.config == 2:
         out["learned"] = learned_leg(args.learned_scenes)
-        out["cnn"] = cnn_leg()
+        if not args.no_cnn_leg:
+            out["cnn"] = cnn_leg()
     if args.learned_640_scenes > 0 and args.config == 2:
         out["learned_640x480"] = learned_leg_640(args.learned_640_scenes)
     if not args.no_cpu_baseline:

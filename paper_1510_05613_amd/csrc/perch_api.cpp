@@ -105,6 +105,100 @@ static void delta_margins(Cam& cam) {
 
 }  // namespace perch
 
+// A box inside the volume V(O) = {o : n_f . o <= w_f for every face f}: the vertex
+// box's z range (less a margin) with its x/y half-extents scaled about the centre as
+// far as every plane allows, or, when that leaves less than a quarter, the whole
+// vertex box scaled uniformly.  Computed in FP64 on the planes' float32 values with
+// its corners rounded inward to float32, and checked corner by corner: every point
+// of it lies at least 1e-9 m inside every plane.  Empty (min > max) when there is no
+// such box (a mesh whose planes do not enclose its vertex-box centre).
+static void inner_box(const std::vector<float>& planes, const float lo[3], const float hi[3],
+                      float a[3], float b[3]) {
+  const double m = 1e-9;
+  const int nf = (int)planes.size() / 4;
+  double c[3], h[3];
+  for (int k = 0; k < 3; ++k) {
+    c[k] = 0.5 * ((double)lo[k] + (double)hi[k]);
+    h[k] = 0.5 * ((double)hi[k] - (double)lo[k]);
+  }
+  for (int k = 0; k < 3; ++k) {  // empty
+    a[k] = 1.0f;
+    b[k] = -1.0f;
+  }
+  if (nf == 0) return;
+  auto slack = [&](int f) {  // w - m - n . c
+    const float* p = &planes[4 * (size_t)f];
+    return (double)p[3] - m - ((double)p[0] * c[0] + (double)p[1] * c[1] + (double)p[2] * c[2]);
+  };
+  // (a) x/y scaled by la, z half-extent shrunk by 2 m
+  const double hz = std::max(0.0, h[2] - 2.0 * m);
+  double la = 1.0;
+  for (int f = 0; f < nf && la >= 0.0; ++f) {
+    const float* p = &planes[4 * (size_t)f];
+    const double rest = slack(f) - std::fabs((double)p[2]) * hz;
+    const double den = std::fabs((double)p[0]) * h[0] + std::fabs((double)p[1]) * h[1];
+    if (den > 0.0) la = std::min(la, rest / den);
+    else if (rest < 0.0) la = -1.0;
+  }
+  double e[3] = {la * h[0], la * h[1], hz};
+  if (!(la >= 0.25)) {  // (b) uniform scaling
+    double lb = 1.0;
+    for (int f = 0; f < nf; ++f) {
+      const float* p = &planes[4 * (size_t)f];
+      const double den = std::fabs((double)p[0]) * h[0] + std::fabs((double)p[1]) * h[1] +
+                         std::fabs((double)p[2]) * h[2];
+      if (den > 0.0) lb = std::min(lb, slack(f) / den);
+      else if (slack(f) < 0.0) lb = -1.0;
+    }
+    if (!(lb > 0.0)) return;
+    for (int k = 0; k < 3; ++k) e[k] = lb * h[k];
+  }
+  float ra[3], rb[3];
+  for (int k = 0; k < 3; ++k) {
+    ra[k] = (float)(c[k] - e[k]);
+    if ((double)ra[k] < c[k] - e[k]) ra[k] = std::nextafter(ra[k], INFINITY);
+    rb[k] = (float)(c[k] + e[k]);
+    if ((double)rb[k] > c[k] + e[k]) rb[k] = std::nextafter(rb[k], -INFINITY);
+    if (!(ra[k] <= rb[k])) return;
+  }
+  for (int f = 0; f < nf; ++f) {  // the rounded corners, checked
+    const float* p = &planes[4 * (size_t)f];
+    double v = -(double)p[3];
+    for (int k = 0; k < 3; ++k) v += (double)p[k] * (p[k] > 0.0f ? (double)rb[k] : (double)ra[k]);
+    if (!(v <= -0.5 * m)) return;
+  }
+  for (int k = 0; k < 3; ++k) {
+    a[k] = ra[k];
+    b[k] = rb[k];
+  }
+}
+
+// The volume test's boxes of one mesh (the layout of Meshes::aabb): the vertex box's
+// centre (float32), its half-extents rounded up so that centre +- them holds
+// [lo, hi], and the inner box's half-extents about that centre rounded down (-1 when
+// the inner box is empty).
+static void volume_boxes(const std::vector<float>& planes, const float lo[3], const float hi[3],
+                         std::vector<float4>& out) {
+  float a[3], b[3];
+  inner_box(planes, lo, hi, a, b);
+  float ctr[3], ho[3], hi_[3];
+  for (int k = 0; k < 3; ++k) {
+    ctr[k] = (float)(0.5 * ((double)lo[k] + (double)hi[k]));
+    const double o = std::max((double)hi[k] - ctr[k], (double)ctr[k] - lo[k]);
+    ho[k] = (float)o;
+    if ((double)ho[k] < o) ho[k] = std::nextafter(ho[k], INFINITY);
+    const double in = std::min((double)b[k] - ctr[k], (double)ctr[k] - a[k]);
+    hi_[k] = (float)in;
+    if ((double)hi_[k] > in) hi_[k] = std::nextafter(hi_[k], -INFINITY);
+  }
+  const bool empty = !(hi_[0] > 0.0f && hi_[1] > 0.0f && hi_[2] > 0.0f);
+  out.push_back(make_float4(ctr[0], ctr[1], ctr[2], 0.0f));
+  out.push_back(make_float4(ho[0], ho[1], ho[2], 0.0f));
+  out.push_back(empty ? make_float4(-1.0f, -1.0f, -1.0f, 0.0f)
+                      : make_float4(hi_[0], hi_[1], hi_[2], 0.0f));
+  out.push_back(make_float4(0.0f, 0.0f, 0.0f, 0.0f));
+}
+
 perch_status upload_meshes(perch_ctx* c) {
   if (!c->meshes_dirty) return PERCH_OK;
   const int nm = (int)c->meshes.size();
@@ -134,8 +228,7 @@ perch_status upload_meshes(perch_ctx* c) {
     for (int k = 0; k < nf; ++k)
       pl.push_back(make_float4(h.planes[4 * k], h.planes[4 * k + 1], h.planes[4 * k + 2],
                                h.planes[4 * k + 3]));
-    bb.push_back(make_float4(lo[0], lo[1], lo[2], 0.0f));
-    bb.push_back(make_float4(hi[0], hi[1], hi[2], 0.0f));
+    volume_boxes(h.planes, lo, hi, bb);
     max_nv = std::max(max_nv, nv);
     if (nv > 0) {
       const float cx = std::max(std::fabs(lo[0]), std::fabs(hi[0]));

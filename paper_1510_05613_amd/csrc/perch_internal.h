@@ -48,7 +48,11 @@ struct Meshes {
   const float4* planes;
   const int4* range;
   const int2* frange;
-  const float4* aabb;  // 2 per mesh: min and max corner of the vertices (model frame)
+  // 4 per mesh (model frame): the centre c of the vertices' box, its half-extents
+  // (rounded up, so c +- them holds every vertex), the half-extents of a box about
+  // c inside the volume V(O) (every point of it at least 1e-9 m inside every face
+  // plane; -1 when there is none), and a zero pad
+  const float4* aabb;
 };
 
 // Materialised parent state R_j (Sec. III-A): composite depth as float bits

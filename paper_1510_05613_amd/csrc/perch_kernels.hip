@@ -30,6 +30,12 @@ namespace perch {
 constexpr int kLdsPlanes = 64;   // V(O) planes staged in LDS per successor (more: read from HBM)
 
 __device__ __forceinline__ int floor256(int x) { return x >> 8; }
+
+// Product of two ints through the full-rate 24-bit multiplier: exact when both
+// factors lie within +-2^23 and the product within +-2^31.  Image-space products
+// qualify (images are at most 16,384 pixels wide and high), and so do the
+// rasteriser's small-triangle edge terms (differences below 2^15 in 1/256 pixel).
+__device__ __forceinline__ int imul(int a, int b) { return __mul24(a, b); }
 __device__ __forceinline__ int ceil256(int x) { return -((-x) >> 8); }
 
 __device__ __forceinline__ int wave_sum(int v) {
@@ -213,9 +219,9 @@ __device__ __forceinline__ void edge_dda(int e, int dy, int dx, int ja, int& rlo
   const float rd = __builtin_amdgcn_rcpf((float)d);
   const int q = floor_div(e, d, rd), dq = floor_div(t, d, rd);
   g.q = flat ? (1 << 20) : q;
-  g.rem = flat ? 0 : e - q * d;
+  g.rem = flat ? 0 : e - imul(q, d);
   g.dq = flat ? 0 : dq;
-  g.dr = flat ? 0 : t - dq * d;
+  g.dr = flat ? 0 : t - imul(dq, d);
   g.a = d;
   g.pos = flat || s > 0;
   // horizontal edge: e + (j - ja) t >= 0 on rows j >= ja - floor(e / t) (t > 0) or
@@ -241,7 +247,7 @@ __device__ __forceinline__ void raster_tri(int x0, int y0, int x1, int y1, int x
   if (xmax - xmin < 16384 && ymax - ymin < 16384) {
     // all products below 2^28: int32 is exact
     int bx = x1 - x0, by = y1 - y0, cx = x2 - x0, cy = y2 - y0;
-    const int area = bx * cy - by * cx;
+    const int area = imul(bx, cy) - imul(by, cx);
     if (area >= 0) return;
     int t = bx; bx = cx; cx = t;
     t = by; by = cy; cy = t;
@@ -259,9 +265,9 @@ __device__ __forceinline__ void raster_tri(int x0, int y0, int x1, int y1, int x
     const int w = ib - ia + 1;
     int rlo = ja, rhi = jb;
     EdgeDDA g0, g1, g2;
-    edge_dda(d0x * py - d0y * px0 + b0, d0y, d0x, ja, rlo, rhi, g0);
-    edge_dda(d1x * (py - by) - d1y * (px0 - bx) + b1, d1y, d1x, ja, rlo, rhi, g1);
-    edge_dda(d2x * (py - cy) - d2y * (px0 - cx) + b2, d2y, d2x, ja, rlo, rhi, g2);
+    edge_dda(imul(d0x, py) - imul(d0y, px0) + b0, d0y, d0x, ja, rlo, rhi, g0);
+    edge_dda(imul(d1x, py - by) - imul(d1y, px0 - bx) + b1, d1y, d1x, ja, rlo, rhi, g1);
+    edge_dda(imul(d2x, py - cy) - imul(d2y, px0 - cx) + b2, d2y, d2x, ja, rlo, rhi, g2);
     for (int j = ja; j <= jb; ++j) {
       int lo = 0, hi = (j >= rlo && j <= rhi) ? w - 1 : -1;
       g0.bound(lo, hi);
@@ -311,7 +317,7 @@ __device__ __forceinline__ void raster_tri_rows(int x0, int y0, int x1, int y1, 
   if (ia > ib || ja > jb) return;
   if (xmax - xmin < 16384 && ymax - ymin < 16384) {
     int bx = x1 - x0, by = y1 - y0, cx = x2 - x0, cy = y2 - y0;
-    const int area = bx * cy - by * cx;
+    const int area = imul(bx, cy) - imul(by, cx);
     if (area >= 0) return;
     int t = bx; bx = cx; cx = t;
     t = by; by = cy; cy = t;
@@ -323,9 +329,9 @@ __device__ __forceinline__ void raster_tri_rows(int x0, int y0, int x1, int y1, 
     const int w = ib - ia + 1;
     int rlo = ja, rhi = jb;
     EdgeDDA g0, g1, g2;
-    edge_dda(d0x * py - d0y * px0 + b0, d0y, d0x, ja, rlo, rhi, g0);
-    edge_dda(d1x * (py - by) - d1y * (px0 - bx) + b1, d1y, d1x, ja, rlo, rhi, g1);
-    edge_dda(d2x * (py - cy) - d2y * (px0 - cx) + b2, d2y, d2x, ja, rlo, rhi, g2);
+    edge_dda(imul(d0x, py) - imul(d0y, px0) + b0, d0y, d0x, ja, rlo, rhi, g0);
+    edge_dda(imul(d1x, py - by) - imul(d1y, px0 - bx) + b1, d1y, d1x, ja, rlo, rhi, g1);
+    edge_dda(imul(d2x, py - cy) - imul(d2y, px0 - cx) + b2, d2y, d2x, ja, rlo, rhi, g2);
     for (int j = ja; j <= jb; ++j) {
       int lo = 0, hi = (j >= rlo && j <= rhi) ? w - 1 : -1;
       g0.bound(lo, hi);
@@ -353,10 +359,10 @@ __device__ __forceinline__ bool tri_candidate(int x0, int y0, int x1, int y1, in
   const bool inb = (max(c0, ceil256(xmin)) <= min(c1, floor256(xmax))) &
                    (max(r0, ceil256(ymin)) <= min(r1, floor256(ymax)));
   const bool small = (xmax - xmin < 16384) & (ymax - ymin < 16384);
-  // wrapping 32-bit products: exact when small (products below 2^28)
-  const unsigned a32 = (unsigned)(x1 - x0) * (unsigned)(y2 - y0) -
-                       (unsigned)(y1 - y0) * (unsigned)(x2 - x0);
-  bool front = (int)a32 < 0;
+  // 24-bit products: exact when small (factors below 2^14, products below 2^28);
+  // larger triangles are decided in 64 bits below
+  const int a32 = imul(x1 - x0, y2 - y0) - imul(y1 - y0, x2 - x0);
+  bool front = a32 < 0;
   if (!small) {
     const long long area = (long long)(x1 - x0) * (y2 - y0) - (long long)(y1 - y0) * (x2 - x0);
     front = area < 0;
@@ -538,20 +544,38 @@ __device__ __forceinline__ bool inside_planes64(const float4* planes, int n_plan
   return m <= 0.0;
 }
 
+// The mesh's boxes about its vertex-box centre ctr for the volume test, widened
+// (outer) and narrowed (inner) by the float32 object point's error bound vbox.
+struct VolBoxes {
+  float3 outer;  // vertex-box half-extents + vbox
+  float3 inner;  // inner-box half-extents - vbox (negative: no inner box)
+};
+
+__device__ __forceinline__ VolBoxes vol_boxes(const EvalParams& ep, const float4 hout,
+                                              const float4 hin) {
+  const float mb = ep.vbox;
+  VolBoxes b;
+  b.outer = make_float3(hout.x + mb, hout.y + mb, hout.z + mb);
+  b.inner = make_float3(hin.x - mb, hin.y - mb, hin.z - mb);
+  return b;
+}
+
 // Observed point p in V(O) = {o : n_f . o <= w_f for every face plane}, the decision
 // of exact arithmetic on the same inputs (pixel (i, j), float32 depth z) outside an
-// FP64 rounding band.  o32 (the float32 map of the float32 back-projection) rules
-// out points more than vbox outside the mesh's vertex box; the rest take the FP64
-// object-frame point, rounded to float32 for the plane values: all below -vtau is
-// inside, one above +vtau is outside, and anything else is decided in FP64.
+// FP64 rounding band.  o32 (the float32 map of the float32 back-projection, within
+// vbox of the exact object-frame point in every coordinate, the 1e-6 m slack in vbox
+// covering the rounding of o32 - ctr) rules out points more than vbox outside the
+// mesh's vertex box and rules in points more than vbox inside its inner box
+// (strictly inside every face plane); the rest take the FP64 object-frame point,
+// rounded to float32 for the plane values: all below -vtau is inside, one above
+// +vtau is outside, and anything else is decided in FP64.
 __device__ __forceinline__ bool in_volume_at(const Cam& c, const EvalParams& ep,
-                                             const ObjMap64& dm, const float4 lo,
-                                             const float4 hi, const float4* planes,
+                                             const ObjMap64& dm, const float4 ctr,
+                                             const VolBoxes& bx, const float4* planes,
                                              int n_planes, float3 o32, int i, int j, float z) {
-  const float mb = ep.vbox;
-  if (o32.x < lo.x - mb || o32.y < lo.y - mb || o32.z < lo.z - mb || o32.x > hi.x + mb ||
-      o32.y > hi.y + mb || o32.z > hi.z + mb)
-    return false;
+  const float ax = fabsf(o32.x - ctr.x), ay = fabsf(o32.y - ctr.y), az = fabsf(o32.z - ctr.z);
+  if (ax > bx.outer.x || ay > bx.outer.y || az > bx.outer.z) return false;
+  if (ax <= bx.inner.x && ay <= bx.inner.y && az <= bx.inner.z) return true;
   const double dz = z;
   const double px = ((double)i - c.dcx) * dz * c.dinv_fx;
   const double py = ((double)j - c.dcy) * dz * c.dinv_fy;
@@ -584,9 +608,10 @@ __device__ __forceinline__ bool in_volume_at(const Cam& c, const EvalParams& ep,
 __device__ __forceinline__ bool in_volume(const Cam& c, const EvalParams& ep, const Meshes& M,
                                           int mesh, const ObjMap& om, const ObjMap64& dm,
                                           float3 p, int i, int j, float z) {
-  const float4 lo = M.aabb[2 * mesh], hi = M.aabb[2 * mesh + 1];
+  const VolBoxes bx = vol_boxes(ep, M.aabb[4 * mesh + 1], M.aabb[4 * mesh + 2]);
   const int2 fr = M.frange[mesh];
-  return in_volume_at(c, ep, dm, lo, hi, M.planes + fr.x, fr.y, apply_obj_map(om, p), i, j, z);
+  return in_volume_at(c, ep, dm, M.aabb[4 * mesh], bx, M.planes + fr.x, fr.y,
+                      apply_obj_map(om, p), i, j, z);
 }
 
 // Pixel window radii (columns, rows) that hold every point within dwin of the
@@ -911,7 +936,8 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
   if (tid < 8) s_acc[tid] = 0;
   // V(O): box corners in registers, planes in LDS when they fit
   const int2 fr = M.frange[mesh];
-  const float4 vlo = M.aabb[2 * mesh], vhi = M.aabb[2 * mesh + 1];
+  const float4 vctr = M.aabb[4 * mesh];
+  const VolBoxes vbx = vol_boxes(ep, M.aabb[4 * mesh + 1], M.aabb[4 * mesh + 2]);
   const bool pl_lds = fr.y <= kLdsPlanes;
   if (pl_lds)
     for (int f = tid; f < fr.y; f += NT) s_pl[f] = M.planes[fr.x + f];
@@ -1049,7 +1075,7 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
         // accumulated rounding stays near 1e-14 of it, far below float32's)
         raster_tri_rows(a.x, a.y, b.x, b.y, c.x, c.y, ca, cb, t0, t1, [&](int j, int i0, int i1) {
           double den = fma(pl.A, (double)i0, fma(pl.B, (double)j, pl.C));
-          unsigned* t = tile + (j - t0) * tw + (i0 - ca);
+          unsigned* t = tile + imul(j - t0, tw) + (i0 - ca);
           for (int i = i0; i <= i1; ++i, ++t, den += pl.A) {
             double r = __builtin_amdgcn_rcp(den);
             r = fma(r, fma(-den, r, 1.0), r);
@@ -1087,12 +1113,12 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
       const float inv_tw = __builtin_amdgcn_rcpf((float)tw);
       for (int k = tid; k < tn; k += NT) {
         const int r = (int)(((float)k + 0.5f) * inv_tw);  // k / tw, exact for k < 2^21
-        const int jj = t0 + r, ii = ca + (k - r * tw);
+        const int jj = t0 + r, ii = ca + (k - imul(r, tw));
         const unsigned key = tile[k];
         const bool cov = key != kInfBits;
         // only a covered pixel needs the parent, and only one the parent also
         // covers changes (it leaves dR)
-        const unsigned pk = (cov && par.has_parent) ? par.depth[jj * W + ii] : kInfBits;
+        const unsigned pk = (cov && par.has_parent) ? par.depth[imul(jj, W) + ii] : kInfBits;
         const bool pfin = pk != kInfBits;
         occ |= cov && pfin && key < pk;  // positive floats order like their bits
         const bool core_row = jj >= b0 && jj <= b1;
@@ -1135,10 +1161,10 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
         if (k < nk) {
           // k / tw for k < 2^21: (k + 1/2) / tw is at least 1 / (2 tw) from an integer
           const int r = (int)(((float)k + 0.5f) * inv_tw);
-          ii = ca + (k - r * tw);
+          ii = ca + (k - imul(r, tw));
           jj = b0 + r;
           const unsigned key = tile[kt + k];
-          const int pix = jj * W + ii;
+          const int pix = imul(jj, W) + ii;
           const float zo = obs[pix];
           const bool hq = key != kInfBits, hp = zo > 0.0f;
           hqv = hq;
@@ -1164,8 +1190,9 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
           if (hp) {
             // separate calls, so that the staged copy is read as LDS (not flat)
             const float3 o = apply_obj_map(om, p);
-            inV = pl_lds ? in_volume_at(cam, ep, dm, vlo, vhi, s_pl, fr.y, o, ii, jj, zo)
-                         : in_volume_at(cam, ep, dm, vlo, vhi, M.planes + fr.x, fr.y, o, ii, jj, zo);
+            inV = pl_lds ? in_volume_at(cam, ep, dm, vctr, vbx, s_pl, fr.y, o, ii, jj, zo)
+                         : in_volume_at(cam, ep, dm, vctr, vbx, M.planes + fr.x, fr.y, o, ii, jj,
+                                        zo);
             inU = goal && ((par.ubits[pix >> 5] >> (pix & 31)) & 1u);
             expl = same;
             if ((inV || inU) && !expl) {
@@ -1177,9 +1204,9 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
               const float zlo = zo - ep.dwin, zhi = zo + ep.dwin;
               // one flat walk over the clipped window, two pixels per step, stopping
               // after the first hit; the depth pre-test also skips +inf (no point)
-              const int n = (wib - wia + 1) * (wjb - wja + 1);
+              const int n = imul(wib - wia + 1, wjb - wja + 1);
               int iq = wia, jq = wja;
-              int row = (wja - t0) * tw - ca;  // tile index of (0, jq)
+              int row = imul(wja - t0, tw) - ca;  // tile index of (0, jq)
               for (int w = 0; w < n && !expl; w += 2) {
                 const bool wrap = iq == wib;  // (ib, jb): the pixel after (iq, jq)
                 const int rowb = row + (wrap ? tw : 0), jb = jq + (wrap ? 1 : 0);
@@ -1216,7 +1243,7 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
         n_dJo += ballot_count(inV && !expl);
         n_rem += ballot_count(inU && (inV || expl));
         if (GAIN) {  // overlap heuristic: points V(O) adds to V_j
-          const int pix = jj * W + ii;
+          const int pix = imul(jj, W) + ii;
           const bool inVj = par.vbits && ((par.vbits[pix >> 5] >> (pix & 31)) & 1u);
           n_gain += ballot_count(inV && !inVj);
         }
@@ -1238,8 +1265,8 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
           int aru, arv, bru, brv;
           window_radius(cam, ep, aq, aru, arv);
           window_radius(cam, ep, bq, bru, brv);
-          const int awu = 2 * aru + 1, anw = awu * (2 * arv + 1);
-          const int bwu = 2 * bru + 1, bnw = two ? bwu * (2 * brv + 1) : 0;
+          const int awu = 2 * aru + 1, anw = imul(awu, 2 * arv + 1);
+          const int bwu = 2 * bru + 1, bnw = two ? imul(bwu, 2 * brv + 1) : 0;
           // w / wu for w < 2^21: (w + 1/2) / wu is at least 1 / (2 wu) from an integer
           const float ainv = __builtin_amdgcn_rcpf((float)awu);
           const float binv = __builtin_amdgcn_rcpf((float)bwu);
@@ -1250,15 +1277,15 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
             int aii = 0, ajj = 0, bii = 0, bjj = 0;
             if (!ahit && w < anw) {
               const int r = (int)(((float)w + 0.5f) * ainv);
-              aii = ai - aru + (w - r * awu);
+              aii = ai - aru + (w - imul(r, awu));
               ajj = aj - arv + r;
-              if (aii >= 0 && aii < W && ajj >= 0 && ajj < H) za = obs[ajj * W + aii];
+              if (aii >= 0 && aii < W && ajj >= 0 && ajj < H) za = obs[imul(ajj, W) + aii];
             }
             if (!bhit && w < bnw) {
               const int r = (int)(((float)w + 0.5f) * binv);
-              bii = bi - bru + (w - r * bwu);
+              bii = bi - bru + (w - imul(r, bwu));
               bjj = bj - brv + r;
-              if (bii >= 0 && bii < W && bjj >= 0 && bjj < H) zb = obs[bjj * W + bii];
+              if (bii >= 0 && bii < W && bjj >= 0 && bjj < H) zb = obs[imul(bjj, W) + bii];
             }
             bool ha = false, hb = false;
             if (za > 0.0f) {
