@@ -443,6 +443,81 @@ typedef struct {
   int64_t trace_lb[PERCH_TRACE];   /* none yet) and the anchor's lower bound min g      */
 } perch_result;
 
+/* ---- per-object pose regressor (discriminative pose priors, Sec. IV-C) ---- */
+
+/* The estimator behind the pose-prior heuristic: Sec. IV-C lists, as a second kind
+ * of inadmissible guidance, how far a state's objects lie from the poses a
+ * discriminative estimator proposes.  The network has the successor-cost
+ * network's convolution trunk (own weights) on 64 x 64 x 2 crops around anchor
+ * points of the table, a 16-d mesh embedding and a 64-unit head with 3 + n_yaw
+ * outputs per (crop, mesh) pair: objectness logit, offset (dx, dy) of the object
+ * from the anchor in units of the anchor spacing, logits of the n_yaw yaw bins
+ * (yaw 2 pi k / n_yaw).  Loss per pair: log(1 + e^s) - label s + label (10 |offset
+ * error|^2 + cross-entropy of the yaw logits against a target spread evenly over
+ * the bins that are congruent to the true one modulo the mesh's symmetry period);
+ * the batch loss is the mean.  Parameters: one flat FP32 array cW0 cb0 cW1 cb1 cW2
+ * cb2 cW3 cb3 (as perch_cnn) emb [n_mesh][16] W1 [64][80] (over [pooled 64,
+ * embedding 16]) b1 [64] W2 [3 + n_yaw][64] b2 [3 + n_yaw]. */
+typedef struct perch_posenet perch_posenet;
+
+typedef struct {
+  int32_t crop;      /* crop index within the batch */
+  int32_t mesh_id;
+} perch_posenet_pair;
+
+typedef struct {
+  float label;       /* 1: the object stands in this crop's anchor cell, else 0      */
+  float dx, dy;      /* its offset from the anchor / spacing (used when label = 1)  */
+  float yaw_bin;     /* true yaw bin (an integer value)                             */
+  float period;      /* bins between yaws the mesh's symmetry makes equal (integer; */
+                     /* n_yaw: one bin, 1: every bin)                              */
+} perch_posenet_target;
+
+/* 1 <= n_yaw <= 32.  Parameters start at zero: set them before use.  Synchronous. */
+perch_status perch_posenet_create(int32_t n_mesh, int32_t n_yaw, int32_t max_crops,
+                                  int32_t max_pairs, void* hip_stream, perch_posenet** out);
+void perch_posenet_destroy(perch_posenet* net);
+int64_t perch_posenet_param_count(const perch_posenet* net);
+/* host FP32 parameters in / out (set also resets the Adam state).  Synchronous. */
+perch_status perch_posenet_set_params(perch_posenet* net, const float* params, int64_t n);
+perch_status perch_posenet_get_params(perch_posenet* net, float* params, int64_t n);
+/* Crops as perch_cnn_crops, sampling every `step` pixels (step >= 1: the crop
+ * spans 64 step pixels).  Synchronous. */
+perch_status perch_cnn_crops_step(perch_ctx* ctx, const float* xy, int32_t n, int32_t step,
+                                  uint16_t* crops_dev);
+/* Raw outputs (device, n_pairs x (3 + n_yaw) floats); NaN rows for pairs whose
+ * crop or mesh index is out of range.  Asynchronous on the network's stream. */
+perch_status perch_posenet_predict(perch_posenet* net, const uint16_t* crops_dev,
+                                   int32_t n_crops, const perch_posenet_pair* pairs_dev,
+                                   int32_t n_pairs, float* out_dev);
+/* One Adam step on the mean loss against target_dev (device, n_pairs entries);
+ * loss_host (nullable) receives the batch loss before the step (then the call is
+ * synchronous). */
+perch_status perch_posenet_train_step(perch_posenet* net, const uint16_t* crops_dev,
+                                      int32_t n_crops, const perch_posenet_pair* pairs_dev,
+                                      const perch_posenet_target* target_dev, int32_t n_pairs,
+                                      float lr, float* loss_host);
+/* Loss and gradients (host, perch_posenet_param_count floats) without a step.
+ * Synchronous. */
+perch_status perch_posenet_gradients(perch_posenet* net, const uint16_t* crops_dev,
+                                     int32_t n_crops, const perch_posenet_pair* pairs_dev,
+                                     const perch_posenet_target* target_dev, int32_t n_pairs,
+                                     float* grads_host, float* loss_host);
+/* Pose estimates O' from crops_dev (device, one crop per anchor, n_anchors of them
+ * at anchor_xy_host, n_anchors x 2 metres): for mesh mesh_ids_host[u] (u <
+ * n_meshes), counts_host[u] estimates, picked by decreasing objectness (ties: the
+ * lower anchor) among anchors at least nms_m from the mesh's earlier picks, each
+ * decoded to (x, y) = anchor + spacing (dx, dy) and the yaw of its largest yaw
+ * logit.  Writes them to out_host in query order (at most max_out; *n_out = the
+ * number written; a mesh with fewer free anchors than its count gets fewer).
+ * Needs n_anchors <= max_crops and n_anchors * n_meshes <= max_pairs, counts
+ * 0..64.  Synchronous. */
+perch_status perch_posenet_estimate(perch_posenet* net, const uint16_t* crops_dev,
+                                    int32_t n_anchors, const float* anchor_xy_host, float spacing,
+                                    float nms_m, const int32_t* mesh_ids_host,
+                                    const int32_t* counts_host, int32_t n_meshes,
+                                    perch_pose_prior* out_host, int32_t max_out, int32_t* n_out);
+
 /* Runs the tree search of Alg. 1 on the context's scene: root = empty state, goal =
  * all K objects placed, successors and edge costs from perch_set_parent /
  * perch_eval_children on the GPU (one launch per expansion).  Synchronous.

@@ -25,6 +25,7 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     os.makedirs(BUILD, exist_ok=True)
     units = (("perch_kernels.hip", DEVICE_FLAGS), ("perch_cnn.hip", DEVICE_FLAGS),
              ("perch_select.hip", DEVICE_FLAGS), ("perch_noalloc.hip", DEVICE_FLAGS),
+             ("perch_posenet.hip", DEVICE_FLAGS), ("perch_posenet_api.cpp", HOST_FLAGS),
              ("perch_cnn_api.cpp", HOST_FLAGS), ("perch_api.cpp", HOST_FLAGS),
              ("perch_search.cpp", HOST_FLAGS), ("perch_batch.cpp", HOST_FLAGS),
              ("perch_tune.cpp", HOST_FLAGS))

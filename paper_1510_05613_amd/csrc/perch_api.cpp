@@ -68,8 +68,12 @@ perch_status fail(perch_status st, const char* fmt, ...) {
 //    vbox, |o| <= Rm + 2 vbox, so vtau = 8u (Rm + 2 vbox + Wm) + 1e-12 m bounds the
 //    float32 error of every plane value; a plane value beyond +-vtau has the sign of
 //    the exact one, and the rest are decided in FP64.
+//  - Plane test on the float32 point o32 itself: each coordinate within vbox of the
+//    exact point, so a unit normal moves the plane value by at most sqrt(3) vbox,
+//    and the fused chain rounds as above: vtau32 = sqrt(3) vbox + vtau (inflated by
+//    1e-3) bounds its error, and only values within it need the FP64 point.
 void vol_margins(const Cam& cam, float obs_zmax, float pose_xy_max, float mesh_rmax,
-                 float mesh_wmax, float& vbox, float& vtau) {
+                 float mesh_wmax, float& vbox, float& vtau, float& vtau32) {
   const double u = std::ldexp(1.0, -24);
   const double amax = std::max(std::fabs((double)cam.cx), std::fabs(cam.W - 1.0 - cam.cx)) / cam.fx;
   const double bmax = std::max(std::fabs((double)cam.cy), std::fabs(cam.H - 1.0 - cam.cy)) / cam.fy;
@@ -78,7 +82,9 @@ void vol_margins(const Cam& cam, float obs_zmax, float pose_xy_max, float mesh_r
                     std::fabs(cam.dWinv[11]) + pose_xy_max + 0.1;  // + local ICP moves
   const double vb = 64.0 * u * (Pm + Tm) + 1e-6;
   vbox = (float)vb;
-  vtau = (float)(8.0 * u * (mesh_rmax + 2.0 * vb + mesh_wmax) + 1e-12);
+  const double vt = 8.0 * u * (mesh_rmax + 2.0 * vb + mesh_wmax) + 1e-12;
+  vtau = (float)vt;
+  vtau32 = (float)((std::sqrt(3.0) * vb + vt) * (1.0 + 1e-3));
 }
 
 // Margin of the float32 test |q - p|^2 <= delta^2 for pixel points q = (i_q, j_q,

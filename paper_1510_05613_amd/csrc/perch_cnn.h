@@ -17,7 +17,7 @@ constexpr int kIn = kFeat + kEmb + 2;    // head input: features, embedding, cos
 struct CropDesc {
   int u0, v0;  // crop centre pixel
   float zref;  // camera depth of the table point under the candidate
-  int pad;
+  int step;    // pixel step between crop samples (0 or 1: every pixel)
 };
 
 struct Pair {
@@ -56,7 +56,7 @@ void launch_crops(const float* obs, const unsigned* pdepth, int W, int H, const 
 // Crop centres of table points (x, y): nearest pixel of the projection and the
 // camera depth of the point; false when a point lies behind the camera.
 bool crop_descriptors(const float M[12], float fx, float fy, float cx, float cy, const float* xy,
-                      int n, CropDesc* out);
+                      int n, CropDesc* out, int step = 1);
 void launch_forward(const Net& net, int n_crops, hipStream_t s);
 // Pairs whose crop index is outside [0, n_crops) or mesh outside [0, n_mesh) are
 // ignored by the backward pass and predicted as NaN.
@@ -67,9 +67,59 @@ void launch_predict(const Net& net, int n_crops, int n_mesh, const Pair* pairs, 
                     float* pred, hipStream_t s);
 void launch_backward(const Net& net, int n_crops, int n_mesh, const Pair* pairs,
                      const float* target, int n_pairs, hipStream_t s);
+// The trunk's backward pass from net.dfeat (pooled-feature gradients of n_crops
+// crops): conv weight and bias gradients into net.G, activations' gradients in net.d.
+void launch_trunk_backward(const Net& net, int n_crops, hipStream_t s);
 void launch_adam(float* p, const float* g, float* m, float* v, int n, float lr, int step,
                  hipStream_t s);
 void launch_pack(const Net& net, hipStream_t s);
+
+// ---- per-object pose regressor (the same trunk, its own weights and head) ----
+// Head: [feat (64), mesh embedding (16)] -> 64 (ReLU) -> 3 + n_yaw outputs:
+// objectness logit, position offset (dx, dy) from the crop's table point in units
+// of the anchor spacing, and logits of the n_yaw yaw bins (yaw 2 pi k / n_yaw).
+constexpr int kPoseIn = kFeat + kEmb;
+constexpr int kMaxYaw = 32;
+constexpr float kPoseWxy = 10.0f;  // weight of the position term of the loss
+constexpr float kPoseWyaw = 1.0f;  // weight of the yaw term
+
+struct PoseParams {
+  float* emb;  // [n_mesh][16]
+  float* W1;   // [64][80]
+  float* b1;   // [64]
+  float* W2;   // [3 + n_yaw][64]
+  float* b2;   // [3 + n_yaw]
+};
+
+struct PosePair {
+  int crop, mesh;
+};
+
+// Targets per pair: label (1: this crop's anchor holds the object), dx, dy (used
+// when label is 1), the true yaw bin and the period (in bins) of the mesh's yaw
+// symmetry: the target yaw distribution is uniform over the bins congruent to the
+// true one modulo the period.
+struct PoseTarget {
+  float label, dx, dy, yaw_bin, period;
+};
+
+// Pose queries of the decoder: mesh, instances wanted, first output slot.
+struct PoseQuery {
+  int mesh, count, first, pad;
+};
+
+// hid must hold (n_crops + n_mesh) x 64 floats.
+void launch_pose_predict(const Net& net, const PoseParams& P, int n_yaw, int n_crops, int n_mesh,
+                         const PosePair* pairs, int n_pairs, float* out, hipStream_t s);
+void launch_pose_backward(const Net& net, const PoseParams& P, const PoseParams& G, int n_yaw,
+                          int n_crops, int n_mesh, const PosePair* pairs,
+                          const PoseTarget* target, int n_pairs, hipStream_t s);
+// Per query q: out rows q * n_anchors .. + n_anchors - 1 are its pairs; picks
+// `count` anchors by decreasing objectness (ties: lower index), each at least
+// nms_m from the earlier picks, and writes (mesh, x, y, theta) per pick.
+void launch_pose_decode(const float* out, int n_yaw, int n_anchors, const float2* anchors,
+                        float spacing, float nms_m, const PoseQuery* q, int n_q, float4* res,
+                        hipStream_t s);
 
 }  // namespace cnn
 }  // namespace perch

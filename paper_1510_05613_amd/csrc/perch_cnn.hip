@@ -46,17 +46,19 @@ __device__ __forceinline__ int acc_row(int e, int lane) {
 // crops
 // ---------------------------------------------------------------------------
 
-// One crop per workgroup: 64 x 64 pixels centred on (u0, v0); channel 0 the
-// observed depth, channel 1 the parent composite, both as (z - zref) / 0.25 clipped
-// to [-1, 1], +1 where there is no return / no parent point or outside the image.
+// One crop per workgroup: 64 x 64 samples every `step` pixels around (u0, v0);
+// channel 0 the observed depth, channel 1 the parent composite, both as (z - zref)
+// / 0.25 clipped to [-1, 1], +1 where there is no return / no parent point or
+// outside the image.
 __global__ void k_crops(const float* obs, const unsigned* pdepth, int W, int H,
                         const CropDesc* desc, int n, bf16_t* out) {
   const int c = blockIdx.x;
   if (c >= n) return;
   const CropDesc d = desc[c];
+  const int st = d.step > 1 ? d.step : 1;
   for (int t = threadIdx.x; t < kCrop * kCrop; t += blockDim.x) {
     const int cy = t / kCrop, cx = t % kCrop;
-    const int u = d.u0 - kCrop / 2 + cx, v = d.v0 - kCrop / 2 + cy;
+    const int u = d.u0 + (cx - kCrop / 2) * st, v = d.v0 + (cy - kCrop / 2) * st;
     float a = 1.0f, b = 1.0f;
     if (u >= 0 && u < W && v >= 0 && v < H) {
       const float z = obs[v * W + u];
@@ -517,6 +519,10 @@ void launch_backward(const Net& net, int n_crops, int n_mesh, const Pair* pairs,
                      const float* target, int n_pairs, hipStream_t s) {
   hipLaunchKernelGGL(k_head_bwd, dim3((n_pairs + 63) / 64), dim3(64), 0, s, net.feat, net.P,
                      pairs, target, n_pairs, n_crops, n_mesh, net.G, net.dfeat, net.loss);
+  launch_trunk_backward(net, n_crops, s);
+}
+
+void launch_trunk_backward(const Net& net, int n_crops, hipStream_t s) {
   hipLaunchKernelGGL(k_pool_bwd, dim3(n_crops), dim3(256), 0, s, net.dfeat, net.a[4], n_crops,
                      net.d[4]);
   wgrad<32, 2, 16>(net.d[4], net.a[3], net.G.cW[3], net.G.cb[3], n_crops, s);

@@ -58,7 +58,7 @@ namespace perch {
 namespace cnn {
 
 bool crop_descriptors(const float M[12], float fx, float fy, float cx, float cy, const float* xy,
-                      int n, CropDesc* out) {
+                      int n, CropDesc* out, int step) {
   // crop centre: the table point (x, y, 0) projected to the nearest pixel
   for (int k = 0; k < n; ++k) {
     double p[3];
@@ -68,7 +68,7 @@ bool crop_descriptors(const float M[12], float fx, float fy, float cx, float cy,
     out[k].u0 = (int)std::lround(fx * p[0] / p[2] + cx);
     out[k].v0 = (int)std::lround(fy * p[1] / p[2] + cy);
     out[k].zref = (float)p[2];
-    out[k].pad = 0;
+    out[k].step = step;
   }
   return true;
 }

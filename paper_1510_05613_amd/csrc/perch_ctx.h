@@ -93,7 +93,7 @@ inline int next_pow2(int v) {
 // derivation is in perch_api.cpp): vbox for the float32 vertex-box pre-test, vtau
 // for the float32 face-plane values of the FP64 object-frame point.
 void vol_margins(const Cam& cam, float obs_zmax, float pose_xy_max, float mesh_rmax,
-                 float mesh_wmax, float& vbox, float& vtau);
+                 float mesh_wmax, float& vbox, float& vtau, float& vtau32);
 
 // Records a message for perch_last_error() and returns st.
 perch_status fail(perch_status st, const char* fmt, ...);
@@ -242,7 +242,8 @@ struct perch_ctx {
   // ep with the volume-test margins of this scene (see perch::vol_margins).
   EvalParams eval_params() const {
     EvalParams e = ep;
-    perch::vol_margins(cam, obs_zmax, pose_xy_max, mesh_rmax, mesh_wmax, e.vbox, e.vtau);
+    perch::vol_margins(cam, obs_zmax, pose_xy_max, mesh_rmax, mesh_wmax, e.vbox, e.vtau,
+                       e.vtau32);
     return e;
   }
 

@@ -77,9 +77,10 @@ struct EvalParams {
   int radius_mode;  // dJ_r query: 0 exact pixel window, 1 voxel hash
   int vpack;        // vertex cache: 0 int2 per vertex, 1 packed 16 + 16 bits (large meshes)
   // V(O) decisions: a float32 object-frame point more than vbox outside the mesh's
-  // vertex box is outside; inside it, face-plane values computed in float32 from the
-  // FP64 object-frame point decide when they clear vtau, else FP64 decides.
-  float vbox, vtau;
+  // vertex box is outside; inside it, face-plane values of that float32 point decide
+  // when they clear vtau32, then those of the FP64 object-frame point rounded to
+  // float32 when they clear vtau, else FP64 decides.
+  float vbox, vtau, vtau32;
 };
 
 // Everything a successor evaluation reads about one scene.

@@ -560,30 +560,11 @@ __device__ __forceinline__ VolBoxes vol_boxes(const EvalParams& ep, const float4
   return b;
 }
 
-// Observed point p in V(O) = {o : n_f . o <= w_f for every face plane}, the decision
-// of exact arithmetic on the same inputs (pixel (i, j), float32 depth z) outside an
-// FP64 rounding band.  o32 (the float32 map of the float32 back-projection, within
-// vbox of the exact object-frame point in every coordinate, the 1e-6 m slack in vbox
-// covering the rounding of o32 - ctr) rules out points more than vbox outside the
-// mesh's vertex box and rules in points more than vbox inside its inner box
-// (strictly inside every face plane); the rest take the FP64 object-frame point,
-// rounded to float32 for the plane values: all below -vtau is inside, one above
-// +vtau is outside, and anything else is decided in FP64.
-__device__ __forceinline__ bool in_volume_at(const Cam& c, const EvalParams& ep,
-                                             const ObjMap64& dm, const float4 ctr,
-                                             const VolBoxes& bx, const float4* planes,
-                                             int n_planes, float3 o32, int i, int j, float z) {
-  const float ax = fabsf(o32.x - ctr.x), ay = fabsf(o32.y - ctr.y), az = fabsf(o32.z - ctr.z);
-  if (ax > bx.outer.x || ay > bx.outer.y || az > bx.outer.z) return false;
-  if (ax <= bx.inner.x && ay <= bx.inner.y && az <= bx.inner.z) return true;
-  const double dz = z;
-  const double px = ((double)i - c.dcx) * dz * c.dinv_fx;
-  const double py = ((double)j - c.dcy) * dz * c.dinv_fy;
-  const double ox = fma(dm.a[0], px, fma(dm.a[1], py, fma(dm.a[2], dz, dm.b[0])));
-  const double oy = fma(dm.a[3], px, fma(dm.a[4], py, fma(dm.a[5], dz, dm.b[1])));
-  const double oz = fma(dm.a[6], px, fma(dm.a[7], py, fma(dm.a[8], dz, dm.b[2])));
-  const float3 o = make_float3((float)ox, (float)oy, (float)oz);
-  const float tau = ep.vtau;
+// Sign of max_f (n_f . o - w_f) for a float32 point whose plane values are within
+// tau of the exact ones: -1 all below -tau (inside), +1 one above +tau (outside), 0
+// undecided.
+__device__ __forceinline__ int plane_side(const float4* planes, int n_planes, float3 o,
+                                          float tau) {
   float mx = -INFINITY;
   int f = 0;
   for (; f + 8 <= n_planes; f += 8) {  // eight planes per branch
@@ -591,16 +572,45 @@ __device__ __forceinline__ bool in_volume_at(const Cam& c, const EvalParams& ep,
                         plane_val(planes[f + 2], o), plane_val(planes[f + 3], o),
                         plane_val(planes[f + 4], o), plane_val(planes[f + 5], o),
                         plane_val(planes[f + 6], o), plane_val(planes[f + 7], o)));
-    if (mx > tau) return false;
+    if (mx > tau) return 1;
   }
   for (; f + 4 <= n_planes; f += 4) {
     mx = fmaxf(mx, fmaxf(fmaxf(plane_val(planes[f], o), plane_val(planes[f + 1], o)),
                          fmaxf(plane_val(planes[f + 2], o), plane_val(planes[f + 3], o))));
-    if (mx > tau) return false;
+    if (mx > tau) return 1;
   }
   for (; f < n_planes; ++f) mx = fmaxf(mx, plane_val(planes[f], o));
-  if (mx > tau) return false;
-  if (__builtin_expect(mx < -tau, 1)) return true;
+  if (mx > tau) return 1;
+  return __builtin_expect(mx < -tau, 1) ? -1 : 0;
+}
+
+// Observed point p in V(O) = {o : n_f . o <= w_f for every face plane}, the decision
+// of exact arithmetic on the same inputs (pixel (i, j), float32 depth z) outside an
+// FP64 rounding band.  o32 (the float32 map of the float32 back-projection, within
+// vbox of the exact object-frame point in every coordinate, the 1e-6 m slack in vbox
+// covering the rounding of o32 - ctr) rules out points more than vbox outside the
+// mesh's vertex box and rules in points more than vbox inside its inner box
+// (strictly inside every face plane).  The rest take the face-plane values of o32:
+// all below -vtau32 is inside, one above +vtau32 is outside; what stays undecided
+// takes the FP64 object-frame point rounded to float32 with the tighter vtau, and
+// anything still undecided is decided in FP64.
+__device__ __forceinline__ bool in_volume_at(const Cam& c, const EvalParams& ep,
+                                             const ObjMap64& dm, const float4 ctr,
+                                             const VolBoxes& bx, const float4* planes,
+                                             int n_planes, float3 o32, int i, int j, float z) {
+  const float ax = fabsf(o32.x - ctr.x), ay = fabsf(o32.y - ctr.y), az = fabsf(o32.z - ctr.z);
+  if (ax > bx.outer.x || ay > bx.outer.y || az > bx.outer.z) return false;
+  if (ax <= bx.inner.x && ay <= bx.inner.y && az <= bx.inner.z) return true;
+  const int s32 = plane_side(planes, n_planes, o32, ep.vtau32);
+  if (__builtin_expect(s32 != 0, 1)) return s32 < 0;
+  const double dz = z;
+  const double px = ((double)i - c.dcx) * dz * c.dinv_fx;
+  const double py = ((double)j - c.dcy) * dz * c.dinv_fy;
+  const double ox = fma(dm.a[0], px, fma(dm.a[1], py, fma(dm.a[2], dz, dm.b[0])));
+  const double oy = fma(dm.a[3], px, fma(dm.a[4], py, fma(dm.a[5], dz, dm.b[1])));
+  const double oz = fma(dm.a[6], px, fma(dm.a[7], py, fma(dm.a[8], dz, dm.b[2])));
+  const int s = plane_side(planes, n_planes, make_float3((float)ox, (float)oy, (float)oz), ep.vtau);
+  if (s != 0) return s < 0;
   return inside_planes64(planes, n_planes, ox, oy, oz);
 }
 
@@ -992,8 +1002,13 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
   // into 32 bits each (from the staged copy, or from the same vertex stage again,
   // so the values are identical); a larger one is rasterised from vertices
   // recomputed where they are needed.
-  const int ox = s_bb[0], oy = s_bb[1];
-  const bool packed = vpack && s_bb[2] - ox < 65536 && s_bb[3] - oy < 65536;
+  // the footprint box is workgroup-uniform: scalar registers
+  const int bb0 = __builtin_amdgcn_readfirstlane(s_bb[0]);
+  const int bb1 = __builtin_amdgcn_readfirstlane(s_bb[1]);
+  const int bb2 = __builtin_amdgcn_readfirstlane(s_bb[2]);
+  const int bb3 = __builtin_amdgcn_readfirstlane(s_bb[3]);
+  const int ox = bb0, oy = bb1;
+  const bool packed = vpack && bb2 - ox < 65536 && bb3 - oy < 65536;
   if (packed) {
     for (int v = tid; v < rg.y; v += NT) {
       int2 uv;
@@ -1026,8 +1041,8 @@ __device__ __forceinline__ void eval_successor(const SceneDev& S, const Parent& 
   // grown by the window halo at the goal level (points of U explained by dR)
   const bool goal = G && par.goal;
   const int ext = goal ? max(1, ep.halo) : 1;
-  const int ca = max(0, floor256(s_bb[0]) - ext), cb = min(W - 1, ceil256(s_bb[2]) + ext);
-  const int ra = max(0, floor256(s_bb[1]) - ext), rb = min(H - 1, ceil256(s_bb[3]) + ext);
+  const int ca = max(0, floor256(bb0) - ext), cb = min(W - 1, ceil256(bb2) + ext);
+  const int ra = max(0, floor256(bb1) - ext), rb = min(H - 1, ceil256(bb3) + ext);
   const int tw = cb - ca + 1;
   const int nrows = rb - ra + 1;
   int core = nrows;

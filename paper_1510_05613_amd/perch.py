@@ -35,7 +35,11 @@ EXPORTS = ("perch_create", "perch_destroy", "perch_set_observation", "perch_add_
            "perch_batch_autotune",
            "perch_autotune", "perch_cnn_create", "perch_cnn_destroy", "perch_cnn_param_count",
            "perch_cnn_set_params", "perch_cnn_get_params", "perch_cnn_crops", "perch_cnn_predict",
-           "perch_rank_children", "perch_cnn_train_step", "perch_cnn_gradients", "perch_last_error")
+           "perch_rank_children", "perch_cnn_train_step", "perch_cnn_gradients",
+           "perch_posenet_create", "perch_posenet_destroy", "perch_posenet_param_count",
+           "perch_posenet_set_params", "perch_posenet_get_params", "perch_cnn_crops_step",
+           "perch_posenet_predict", "perch_posenet_train_step", "perch_posenet_gradients",
+           "perch_posenet_estimate", "perch_last_error")
 
 SEARCH_EXHAUSTIVE, SEARCH_UCS, SEARCH_FOCAL, SEARCH_LEARNED, SEARCH_MHA = 0, 1, 2, 3, 4
 SEARCH_LEARNED_MHA = 5
@@ -139,6 +143,20 @@ def load(path: str = LIB_PATH):
     L.perch_rank_children.argtypes = [P, P, I32, I32, P, I32, P, P, P]
     L.perch_cnn_train_step.argtypes = [P, P, I32, P, P, I32, C.c_float, C.POINTER(C.c_float)]
     L.perch_cnn_gradients.argtypes = [P, P, I32, P, P, I32, P, C.POINTER(C.c_float)]
+    L.perch_posenet_create.argtypes = [I32, I32, I32, I32, P, C.POINTER(P)]
+    L.perch_posenet_destroy.argtypes = [P]
+    L.perch_posenet_destroy.restype = None
+    L.perch_posenet_param_count.argtypes = [P]
+    L.perch_posenet_param_count.restype = C.c_int64
+    L.perch_posenet_set_params.argtypes = [P, P, C.c_int64]
+    L.perch_posenet_get_params.argtypes = [P, P, C.c_int64]
+    L.perch_cnn_crops_step.argtypes = [P, P, I32, I32, P]
+    L.perch_posenet_predict.argtypes = [P, P, I32, P, I32, P]
+    L.perch_posenet_train_step.argtypes = [P, P, I32, P, P, I32, C.c_float,
+                                           C.POINTER(C.c_float)]
+    L.perch_posenet_gradients.argtypes = [P, P, I32, P, P, I32, P, C.POINTER(C.c_float)]
+    L.perch_posenet_estimate.argtypes = [P, P, I32, P, C.c_float, C.c_float, P, P, I32, P, I32,
+                                         C.POINTER(I32)]
     L.perch_batch_create.argtypes = [P, I32, P, C.POINTER(P)]
     L.perch_batch_destroy.argtypes = [P]
     L.perch_batch_destroy.restype = None
@@ -150,7 +168,8 @@ def load(path: str = LIB_PATH):
     L.perch_last_error.restype = C.c_char_p
     for name in EXPORTS:
         if name not in ("perch_destroy", "perch_batch_destroy", "perch_cnn_destroy",
-                        "perch_cnn_param_count", "perch_last_error"):
+                        "perch_cnn_param_count", "perch_posenet_destroy",
+                        "perch_posenet_param_count", "perch_last_error"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -577,6 +596,141 @@ class Cnn:
                                           pairs.data_ptr(), _dev_ptr(target, "float32"),
                                           pairs.shape[0], g.ctypes.data, C.byref(loss)))
         return loss.value, self.unpack(g)
+
+
+# flat parameter order of the pose regressor (sizes depend on meshes and yaw bins)
+POSENET_TENSORS = ("cW0", "cb0", "cW1", "cb1", "cW2", "cb2", "cW3", "cb3", "emb", "W1", "b1",
+                   "W2", "b2")
+
+
+def posenet_shapes(n_mesh: int, n_yaw: int):
+    shp = {}
+    cin = 2
+    for l in range(4):
+        shp[f"cW{l}"] = (32, 3, 3, cin)
+        shp[f"cb{l}"] = (32,)
+        cin = 32
+    shp.update(emb=(n_mesh, 16), W1=(64, 80), b1=(64,), W2=(3 + n_yaw, 64), b2=(3 + n_yaw,))
+    return shp
+
+
+class PoseNet:
+    """The per-object pose regressor on the GPU (inference, estimates, training)."""
+
+    def __init__(self, n_mesh: int, n_yaw: int, max_crops: int = 256, max_pairs: int = 2048,
+                 stream=None):
+        import torch
+
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.n_mesh, self.n_yaw = n_mesh, n_yaw
+        self.max_crops, self.max_pairs = max_crops, max_pairs
+        h = C.c_void_p()
+        _check(load().perch_posenet_create(n_mesh, n_yaw, max_crops, max_pairs,
+                                           C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+        self.n_params = int(load().perch_posenet_param_count(self.h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().perch_posenet_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def pack(self, params: dict) -> np.ndarray:
+        return np.concatenate([np.asarray(params[k], np.float32).reshape(-1)
+                               for k in POSENET_TENSORS])
+
+    def unpack(self, flat: np.ndarray) -> dict:
+        out, o = {}, 0
+        shp = posenet_shapes(self.n_mesh, self.n_yaw)
+        for k in POSENET_TENSORS:
+            n = int(np.prod(shp[k]))
+            out[k] = flat[o:o + n].reshape(shp[k])
+            o += n
+        return out
+
+    def set_params(self, params):
+        flat = np.ascontiguousarray(self.pack(params) if isinstance(params, dict) else params,
+                                    np.float32)
+        _check(load().perch_posenet_set_params(self.h, flat.ctypes.data, self.n_params))
+
+    def get_params(self) -> dict:
+        flat = np.zeros(self.n_params, np.float32)
+        _check(load().perch_posenet_get_params(self.h, flat.ctypes.data, self.n_params))
+        return self.unpack(flat)
+
+    @staticmethod
+    def crops(ctx: "Context", xy, step: int = 1):
+        """bfloat16 crops (int16 GPU tensor n x 64 x 64 x 2) of ctx's parent, one sample
+        every `step` pixels."""
+        import torch
+
+        xy = np.ascontiguousarray(xy, np.float32).reshape(-1, 2)
+        out = torch.empty((len(xy), 64, 64, 2), dtype=torch.int16, device="cuda")
+        _check(load().perch_cnn_crops_step(ctx.h, xy.ctypes.data, len(xy), int(step),
+                                           out.data_ptr()))
+        return out
+
+    @staticmethod
+    def pairs(crop, mesh):
+        """int32 GPU tensor (n, 2) of (crop, mesh)."""
+        import torch
+
+        a = np.stack([np.asarray(crop, np.int32), np.asarray(mesh, np.int32)], 1)
+        return torch.as_tensor(np.ascontiguousarray(a)).cuda()
+
+    @staticmethod
+    def targets(t):
+        """float32 GPU tensor (n, 5) of (label, dx, dy, yaw bin, period)."""
+        import torch
+
+        return torch.as_tensor(np.ascontiguousarray(t, np.float32).reshape(-1, 5)).cuda()
+
+    def predict(self, crops, pairs):
+        import torch
+
+        out = torch.empty((pairs.shape[0], 3 + self.n_yaw), dtype=torch.float32, device="cuda")
+        _check(load().perch_posenet_predict(self.h, crops.data_ptr(), crops.shape[0],
+                                            _dev_ptr(pairs, "int32", 2 * pairs.shape[0]),
+                                            pairs.shape[0], out.data_ptr()))
+        return out
+
+    def train_step(self, crops, pairs, target, lr: float, want_loss: bool = True):
+        loss = C.c_float(0.0)
+        _check(load().perch_posenet_train_step(self.h, crops.data_ptr(), crops.shape[0],
+                                               _dev_ptr(pairs, "int32", 2 * pairs.shape[0]),
+                                               _dev_ptr(target, "float32", 5 * pairs.shape[0]),
+                                               pairs.shape[0], lr,
+                                               C.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def gradients(self, crops, pairs, target):
+        g = np.zeros(self.n_params, np.float32)
+        loss = C.c_float(0.0)
+        _check(load().perch_posenet_gradients(self.h, crops.data_ptr(), crops.shape[0],
+                                              _dev_ptr(pairs, "int32", 2 * pairs.shape[0]),
+                                              _dev_ptr(target, "float32", 5 * pairs.shape[0]),
+                                              pairs.shape[0], g.ctypes.data, C.byref(loss)))
+        return loss.value, self.unpack(g)
+
+    def estimate(self, crops, anchor_xy, spacing: float, meshes, counts, nms_m: float):
+        """[(mesh, x, y, theta), ...] from one crop per anchor (perch_posenet_estimate)."""
+        xy = np.ascontiguousarray(anchor_xy, np.float32).reshape(-1, 2)
+        m = np.ascontiguousarray(meshes, np.int32)
+        c = np.ascontiguousarray(counts, np.int32)
+        cap = int(c.sum())
+        out = (PerchPosePrior * max(1, cap))()
+        n = C.c_int32(0)
+        _check(load().perch_posenet_estimate(self.h, crops.data_ptr(), len(xy), xy.ctypes.data,
+                                             float(spacing), float(nms_m), m.ctypes.data,
+                                             c.ctypes.data, len(m), out, cap, C.byref(n)))
+        return [(int(out[k].mesh_id), float(out[k].x), float(out[k].y), float(out[k].theta))
+                for k in range(n.value)]
 
 
 def context_from_scene(scene, depth=None, stream=None) -> Context:
