@@ -32,8 +32,10 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1510_05613_amd", "csrc", "perch_kernels.h
 COUNTERS = os.path.join(ROOT, "profiles", "k_eval_640x480_counters.md")
 CHECKPOINT = os.path.join(ROOT, "paper_1510_05613_amd", "weights", "c4_cnn.npz")
 CHECKPOINT_640 = os.path.join(ROOT, "paper_1510_05613_amd", "weights", "c2_cnn.npz")
+POSE_CHECKPOINT_640 = os.path.join(ROOT, "paper_1510_05613_amd", "weights", "c2_pose.npz")
 LEARNED_BATCH = 4  # states per step of the learned + batched search
 CHECKPOINT_C5 = os.path.join(ROOT, "paper_1510_05613_amd", "weights", "c5_cnn.npz")
+POSE_CHECKPOINT_C5 = os.path.join(ROOT, "paper_1510_05613_amd", "weights", "c5_pose.npz")
 
 
 def kernel_source_hash() -> str:
@@ -113,6 +115,9 @@ def parse_args(argv=None):
     ap.add_argument("--learned-only", action="store_true",
                     help="print only the learned legs and the network kernels' rates "
                          "(for profiling the learned expansion)")
+    ap.add_argument("--learned-expansion", action="store_true",
+                    help="print only the stage times of one learned expansion (160x120 and "
+                         "640x480)")
     ap.add_argument("--no-cnn-leg", action="store_true",
                     help="skip the network kernels' rate leg")
     ap.add_argument("--learned-640-scenes", type=int, default=0,
@@ -330,7 +335,7 @@ def full_pipeline_leg(n_scenes: int, budget_s: float) -> dict:
     cost and bound, and the time to the best cost any search reached; medians over
     scenes.  The ground-truth scene's own cost (Eq. 4 along its valid order) is the
     reference."""
-    from paper_1510_05613_amd import learn, perch, scenes
+    from paper_1510_05613_amd import learn, perch, posenet, scenes
 
     if not os.path.exists(CHECKPOINT_C5):
         return {"skipped": "no trained checkpoint"}
@@ -339,7 +344,10 @@ def full_pipeline_leg(n_scenes: int, budget_s: float) -> dict:
     render = perch.GpuRenderer()
     net = learn.batched_network(CHECKPOINT_C5, 5, 1)
     bnet = learn.batched_network(CHECKPOINT_C5, 5, LEARNED_BATCH)
-    names = ("ucs", "mha", "learned", "learned_batched")
+    pnet = posenet.for_config(POSE_CHECKPOINT_C5, 5) if os.path.exists(POSE_CHECKPOINT_C5) \
+        else None
+    names = ("ucs", "mha", "learned", "learned_batched") + \
+        (("mha_prior_regressor",) if pnet is not None else ())
     rows, traces = [], {k: [] for k in names}
     i = learn.HELD_OUT_FIRST
     while len(rows) < n_scenes and i < learn.HELD_OUT_FIRST + 10 * n_scenes:
@@ -349,6 +357,7 @@ def full_pipeline_leg(n_scenes: int, budget_s: float) -> dict:
             continue
         ctx = perch.context_from_scene(sc)
         truth = _path_cost(ctx, [(int(sc.obj_mesh[k]), int(sc.gt_pose[k])) for k in sc.gt_order])
+        est, t_est = posenet.estimate(pnet, ctx, sc) if pnet is not None else (None, 0.0)
         run = dict(
             ucs=lambda: ctx.search(perch.SEARCH_UCS, budget_s=budget_s),
             mha=lambda: ctx.search(perch.SEARCH_MHA, w=3.0, anytime=True, budget_s=budget_s),
@@ -356,15 +365,19 @@ def full_pipeline_leg(n_scenes: int, budget_s: float) -> dict:
                                        topk=256, budget_s=budget_s),
             learned_batched=lambda: ctx.search(perch.SEARCH_LEARNED, w=3.0, anytime=True,
                                                cnn=bnet, topk=256, budget_s=budget_s,
-                                               batch=LEARNED_BATCH))
+                                               batch=LEARNED_BATCH),
+            mha_prior_regressor=lambda: ctx.search(perch.SEARCH_MHA, w=3.0, anytime=True,
+                                                   budget_s=max(1e-3, budget_s - t_est),
+                                                   priors=est))
         res = {k: run[k]() for k in names}
         best = min([r["cost"] for r in res.values() if r["found"]] + [truth])
         row = {"truth": truth, "best": best}
         for k, r in res.items():
+            t0 = t_est if k == "mha_prior_regressor" else 0.0  # the estimate runs first
             row[k] = dict(cost=r["cost"] if r["found"] else None, lower_bound=r["lower_bound"],
-                          t_best=r["t_best_s"] if r["found"] and r["cost"] == best else None,
-                          evals=r["n_evaluated"], expanded=r["n_expanded"])
-            traces[k].append([(round(t, 3), c, lb) for t, c, lb in r["trace"]])
+                          t_best=(r["t_best_s"] + t0) if r["found"] and r["cost"] == best
+                          else None, evals=r["n_evaluated"], expanded=r["n_expanded"])
+            traces[k].append([(round(t + t0, 3), c, lb) for t, c, lb in r["trace"]])
         rows.append(row)
         ctx.close()
         print(f"full pipeline: scene {i - 1}: truth {truth}, " +
@@ -500,6 +513,75 @@ def cnn_leg(sizes=(64, 256, 1024, 4096), reps: int = 10) -> dict:
             "note": "an expansion ranks 64-128 crops (160x120) or up to 256 (640x480)"}
 
 
+def learned_expansion_leg(reps: int = 20) -> dict:
+    """One expansion of the learned search at the root of a held-out scene, stage by
+    stage (HIP events on the context's stream, median of `reps`): crops of every
+    pose cell, the network's forward pass and predictions for every (mesh, pose)
+    child, the device top-k ranking, and the exact evaluation of the top-k.  At
+    160x120 (config 4, 144 crops, 2,304 children, top 64) and 640x480 (config 2,
+    2,500 crops, 120,000 children, top 256).  TFLOP/s from the convolutions'
+    algorithmic FLOPs against the dense bf16 MFMA peak."""
+    import torch
+
+    from paper_1510_05613_amd import learn, perch, scenes
+
+    out = {}
+    for config, path, topk in ((4, CHECKPOINT, 64), (2, CHECKPOINT_640, 256)):
+        if not os.path.exists(path):
+            out[f"config_{config}"] = {"skipped": "no trained checkpoint"}
+            continue
+        net, _ = learn.search_networks(path, config)
+        cfg = scenes.CONFIGS[config]
+        sc = learn.try_scene(config, learn.HELD_OUT_FIRST, perch.GpuRenderer(),
+                             scenes.make_library(cfg["lib"]))
+        ctx = perch.context_from_scene(sc)
+        g = sc.grid
+        cells = learn.cell_centres(g)
+        meshes = sorted(set(int(m) for m in sc.obj_mesh))
+        P = g.P
+        cell = np.arange(P) // g.n_yaw
+        pairs = perch.Cnn.pairs(np.tile(cell, len(meshes)), np.repeat(meshes, P),
+                                np.tile(sc.poses[:, 2], len(meshes)),
+                                np.tile(sc.poses[:, 3], len(meshes)))
+        mids = torch.as_tensor(np.asarray(meshes, np.int32)).cuda()
+        pids = torch.as_tensor(np.arange(P, dtype=np.int32)).cuda()
+        allow = np.ones(len(meshes), np.int32)
+        cost = torch.empty(topk, dtype=torch.int32, device="cuda")
+        status = torch.empty_like(cost)
+        stream = torch.cuda.current_stream()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        times = []
+        for rep in range(reps + 2):
+            ctx.set_parent([])
+            torch.cuda.synchronize()
+            ev[0].record(stream)
+            crops = perch.Cnn.crops(ctx, cells)
+            ev[1].record(stream)
+            pred = net.predict(crops, pairs)
+            ev[2].record(stream)
+            top = ctx.rank_children(pred, P, allow, topk, mids, pids)
+            ev[3].record(stream)
+            ctx.eval_children(top.contiguous(), cost, status)
+            ev[4].record(stream)
+            torch.cuda.synchronize()
+            if rep >= 2:
+                times.append([ev[k].elapsed_time(ev[k + 1]) for k in range(4)])
+        t = np.median(np.asarray(times), 0)
+        tf = CNN_FWD_FLOPS * len(cells) / (t[1] * 1e-3) / 1e12
+        out[f"config_{config}"] = {
+            "crops": len(cells), "children": len(meshes) * P, "topk": topk,
+            "crops_ms": round(float(t[0]), 4), "network_ms": round(float(t[1]), 4),
+            "rank_ms": round(float(t[2]), 4), "exact_topk_ms": round(float(t[3]), 4),
+            "expansion_ms": round(float(t.sum()), 4), "network_tflops": round(tf, 2),
+            "network_frac": round(tf / PEAK_BF16_TFLOPS, 4)}
+        ctx.close()
+        net.close()
+    out["workload"] = ("root expansion of held-out scene 10000: crops of every pose cell, "
+                       "network predictions of every child, device top-k, exact evaluation "
+                       f"of the top-k; medians of {reps}")
+    return out
+
+
 def learned_leg(n_scenes: int) -> dict:
     """Time-to-best-scene of the learned search (committed checkpoint) against the
     plain searches and a random-init control, on held-out 160x120 scenes (config 4)."""
@@ -535,13 +617,13 @@ def learned_leg_640(n_scenes: int, budget_s: float = 10.0) -> dict:
     return g
 
 
-def icp_leg(ctx, sc, d, iters: int, reps: int = 3) -> dict:
-    """Local ICP (Sec. IV-E) of every root successor (one launch), then the edge
-    costs at the adjusted poses (one k_eval launch): HIP-event times on the
-    context's stream, best of `reps`."""
+def _icp_timed(ctx, parent, cands, cost, status, n_poses, iters: int, reps: int):
+    """Best-of-reps HIP-event times of one ICP launch over cands and one k_eval
+    launch at the adjusted poses; returns (times, ICP statuses, pair counts, shifts
+    in the table plane of the aligned candidates)."""
     import torch
 
-    n = d["cands"].shape[0]
+    n = cands.shape[0]
     adj = torch.empty((n, 2), dtype=torch.int32, device="cuda")
     nm = torch.empty(n, dtype=torch.int32, device="cuda")
     st = torch.empty(n, dtype=torch.int32, device="cuda")
@@ -549,26 +631,59 @@ def icp_leg(ctx, sc, d, iters: int, reps: int = 3) -> dict:
     best = None
     for _ in range(reps + 1):  # the first pass loads the code object and the normals
         ctx.set_pose_arena(n)
-        ctx.set_parent(d["parent"])
+        ctx.set_parent(parent)
         e[0].record()
-        ctx.icp_children(d["cands"], adj, nm, st, iters=iters, radius=0.02)
+        ctx.icp_children(cands, adj, nm, st, iters=iters, radius=0.02)
         e[1].record()
-        ctx.eval_children(adj, d["cost"], d["status"])
+        ctx.eval_children(adj, cost[:n], status[:n])
         e[2].record()
         torch.cuda.synchronize()
         t = (e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]))
         best = t if best is None or sum(t) < sum(best) else best
     s_icp = st.cpu().numpy()
-    P = ctx.get_poses(sc.grid.P, n).astype(np.float64)
-    g = sc.poses[d["cands"][:, 1].cpu().numpy()].astype(np.float64)
-    moved = np.hypot(P[:, 0] - g[:, 0], P[:, 1] - g[:, 1])[s_icp == 1]
-    return {"candidates": n, "iters": iters, "radius_m": 0.02, "icp_ms": round(best[0], 3),
-            "eval_at_adjusted_ms": round(best[1], 3),
-            "aligned_per_s": round(n / (best[0] / 1e3), 1),
-            "aligned": int((s_icp == 1).sum()), "occluding": int((s_icp == 0).sum()),
-            "too_large": int((s_icp == -3).sum()),
-            "median_shift_mm": round(float(np.median(moved)) * 1e3, 3) if len(moved) else None,
-            "workload": "root successors of the timed scene (every mesh x every pose)"}
+    P = ctx.get_poses(n_poses, n).astype(np.float64)
+    return best, s_icp, nm.cpu().numpy(), P
+
+
+def icp_leg(ctx, sc, d, iters: int, reps: int = 3) -> dict:
+    """Local ICP (Sec. IV-E), one launch, then the edge costs at the adjusted poses
+    (one k_eval launch): HIP-event times on the context's stream, best of `reps`.
+    Two workloads: every root successor (most lie far from any object and stop
+    after a round with too few pairs), and the candidates of the true meshes in the
+    7 x 7 cells around their true positions, all yaws (the ones that align)."""
+    import torch
+
+    out = {}
+    g = sc.grid
+    near = []
+    for m, p in zip(sc.obj_mesh, sc.gt_pose):
+        ix, iy, _ = g.unindex(int(p))
+        for a in range(max(0, ix - 3), min(g.nx, ix + 4)):
+            for b in range(max(0, iy - 3), min(g.ny, iy + 4)):
+                for k in range(g.n_yaw):
+                    near.append((int(m), g.index(a, b, k)))
+    near = torch.as_tensor(np.asarray(near, np.int32)).cuda()
+    for name, cands in (("all_root", d["cands"]), ("near_truth", near)):
+        n = cands.shape[0]
+        (t_icp, t_eval), s_icp, nm, P = _icp_timed(ctx, d["parent"], cands, d["cost"],
+                                                   d["status"], g.P, iters, reps)
+        gp = sc.poses[cands[:, 1].cpu().numpy()].astype(np.float64)
+        moved = np.hypot(P[:, 0] - gp[:, 0], P[:, 1] - gp[:, 1])[s_icp == 1]
+        ok = s_icp == 1
+        out[name] = {"candidates": n, "icp_ms": round(t_icp, 3),
+                     "eval_at_adjusted_ms": round(t_eval, 3),
+                     "aligned_per_s": round(n / (t_icp / 1e3), 1),
+                     "aligned": int(ok.sum()), "occluding": int((s_icp == 0).sum()),
+                     "too_large": int((s_icp == -3).sum()),
+                     "median_pairs": int(np.median(nm[ok])) if ok.any() else None,
+                     "moved": int((moved > 1e-6).sum()),
+                     "median_shift_mm": (round(float(np.median(moved)) * 1e3, 3)
+                                         if len(moved) else None)}
+    out.update(iters=iters, radius_m=0.02,
+               workload=("all_root: every mesh x every pose at the root of the timed scene; "
+                         "near_truth: the scene's meshes in the 7 x 7 cells around their true "
+                         "positions, every yaw"))
+    return out
 
 
 def _path_cost(ctx, objs):
@@ -684,16 +799,18 @@ def icp_offgrid_leg(n_scenes: int, budget_s: float = 10.0, iters: int = 10) -> d
 
 
 def prior_leg(n_scenes: int, budget_s: float = 10.0) -> dict:
-    """Focal-MHA* with and without a third queue on the pose-prior heuristic
-    (estimates from the 640x480 network, or the true poses as a reference)."""
-    from paper_1510_05613_amd import learn
+    """Focal-MHA* with and without a third queue on the pose-prior heuristic, the
+    estimates coming from the per-object pose regressor (its estimate time added to
+    that search's times) or, as a reference, from the true poses."""
+    from paper_1510_05613_amd import learn, posenet
 
-    if not os.path.exists(CHECKPOINT_640):
-        return {"skipped": "no trained checkpoint"}
-    net, _ = learn.search_networks(CHECKPOINT_640, 2)
+    if not os.path.exists(POSE_CHECKPOINT_640):
+        return {"skipped": "no trained pose regressor"}
+    net = posenet.for_config(POSE_CHECKPOINT_640, 2)
     first = learn.HELD_OUT_FIRST
-    g = learn.prior_gain(net, range(first, first + 2 * n_scenes), config=2, budget_s=budget_s,
-                         max_scenes=n_scenes, log=lambda m: print(m, file=sys.stderr, flush=True))
+    g = posenet.prior_gain(net, range(first, first + 2 * n_scenes), config=2, budget_s=budget_s,
+                           max_scenes=n_scenes,
+                           log=lambda m: print(m, file=sys.stderr, flush=True))
     g["workload"] = (f"config 2 (640x480, K=3, 40,000 poses/object), the first {n_scenes} "
                      f"held-out scenes from {first}; medians, {budget_s:.0f} s per search")
     return g
@@ -759,6 +876,9 @@ def main(argv=None):
         return 3
     if args.config == 3:
         print(json.dumps(run_batched(args)), flush=True)
+        return 0
+    if args.learned_expansion:
+        print(json.dumps({"learned_expansion": learned_expansion_leg()}), flush=True)
         return 0
     if args.learned_only:
         out = {} if args.no_cnn_leg else {"cnn": cnn_leg()}

@@ -782,7 +782,6 @@ class Searcher {
         const int64_t gmin = nodes[open.top()].g;
         lower_bound_ = gmin;
         trace(false);
-      trace(false);
         if (have_ && best_.g <= gmin) break;
         if (have_ && !o_.anytime && (double)best_.g <= w * (double)gmin) break;
         if (over_budget()) return PERCH_E_BUDGET;

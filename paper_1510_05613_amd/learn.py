@@ -367,87 +367,6 @@ def gain(net: "perch.Cnn", control: "perch.Cnn", indices: Sequence[int], config:
     return out
 
 
-def network_priors(net: "perch.Cnn", ctx: "perch.Context", scene: "scenes.Scene"):
-    """Discriminative pose estimates O' from the network (Sec. IV-C's pose-prior
-    heuristic): at the root, for each mesh of the object multiset, the poses it
-    predicts cheapest, one per instance, in different cells at least two cells
-    apart.  Returns [(mesh, x, y, theta), ...]."""
-    import torch
-
-    g = scene.grid
-    ctx.set_parent([])
-    crops = perch.Cnn.crops(ctx, cell_centres(g))
-    cell = np.arange(g.P) // g.n_yaw
-    out = []
-    for m in sorted(set(int(v) for v in scene.obj_mesh)):
-        pairs = perch.Cnn.pairs(cell, np.full(g.P, m, np.int32), scene.poses[:, 2],
-                                scene.poses[:, 3])
-        pred = net.predict(crops, pairs)
-        torch.cuda.synchronize()
-        order = np.argsort(pred.cpu().numpy(), kind="stable")
-        taken = []
-        for p in order:
-            ix, iy, _ = g.unindex(int(p))
-            if all(max(abs(ix - a), abs(iy - b)) >= 2 for a, b in taken):
-                taken.append((ix, iy))
-                x, y, c, s = (float(v) for v in scene.poses[int(p)])
-                out.append((m, x, y, float(np.arctan2(s, c))))
-            if len(taken) == int(np.sum(scene.obj_mesh == m)):
-                break
-    return out
-
-
-def prior_gain(net: "perch.Cnn", indices: Sequence[int], config: int = 2, w: float = 3.0,
-               budget_s: float = 10.0, max_scenes: int = 0, log=None) -> dict:
-    """The paper's Focal-MHA* (h_depth, h_overlap) against the same search with a
-    third queue on the pose-prior heuristic, the estimates O' coming from the
-    network (network_priors) or, as an upper reference, from the true poses.
-    Anytime, `budget_s` per search; time until each search first holds the best
-    cost any of them reached, and the cost it ends with.  Medians over scenes."""
-    lib = scenes.make_library(scenes.CONFIGS[config]["lib"])
-    render = perch.GpuRenderer()
-    names = ("mha", "mha_prior_net", "mha_prior_true")
-    rows = []
-    for i in indices:
-        if max_scenes and len(rows) >= max_scenes:
-            break
-        sc = try_scene(config, int(i), render, lib)
-        if sc is None:
-            continue
-        ctx = perch.context_from_scene(sc)
-        true = [(int(m), float(sc.poses[p, 0]), float(sc.poses[p, 1]),
-                 float(np.arctan2(sc.poses[p, 3], sc.poses[p, 2])))
-                for m, p in zip(sc.obj_mesh, sc.gt_pose)]
-        net_pri = network_priors(net, ctx, sc)
-        res = {}
-        for name, pri in zip(names, (None, net_pri, true)):
-            res[name] = ctx.search(perch.SEARCH_MHA, w=w, anytime=True, budget_s=budget_s,
-                                   priors=pri)
-        best = min(r["cost"] for r in res.values() if r["found"])
-        row = {k: (r["t_best_s"] if r["found"] and r["cost"] == best else float("inf"),
-                   r["cost"] if r["found"] else None) for k, r in res.items()}
-        row["prior_error_m"] = float(np.median([min(np.hypot(x - tx, y - ty)
-                                                    for (tm, tx, ty, _) in true if tm == m)
-                                                for (m, x, y, _) in net_pri]))
-        rows.append(row)
-        ctx.close()
-        if log:
-            log(f"prior gain: scene {i}: best {best}: " +
-                ", ".join(f"{k} {row[k][0] * 1e3:.1f} ms" for k in names))
-
-    def med(v):
-        v = [x for x in v if x is not None]
-        m = float(np.median(v)) if v else float("nan")
-        return None if not np.isfinite(m) else m
-
-    return dict(scenes=len(rows), w=w, budget_s=budget_s,
-                time_to_best_s={k: med([r[k][0] for r in rows]) for k in names},
-                final_cost={k: med([r[k][1] for r in rows]) for k in names},
-                wins_vs_mha={k: int(sum(r[k][0] < r["mha"][0] for r in rows))
-                             for k in names[1:]},
-                network_prior_error_m=med([r["prior_error_m"] for r in rows]))
-
-
 def batched_network(path: str, config: int, batch: int) -> "perch.Cnn":
     """The checkpoint's network sized for the learned search expanding `batch`
     states per step."""

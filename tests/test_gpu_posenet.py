@@ -187,8 +187,12 @@ def test_trained_regressor_priors_keep_the_w_bound():
     """The checkpoint's estimates on a held-out 640x480 scene lie near the true
     poses, and Focal-MHA* with them as a third queue returns a scene within w of the
     optimum (Theorem 2); its goal equals UCS's when run to completion."""
-    sc = posenet.try_scene(2, posenet.HELD_OUT_FIRST + 1, perch.GpuRenderer(),
-                           H.c2_library())
+    render = perch.GpuRenderer()
+    sc = None
+    for i in range(posenet.HELD_OUT_FIRST + 1, posenet.HELD_OUT_FIRST + 10):
+        sc = posenet.try_scene(2, i, render, H.c2_library())  # some seeds are unsatisfiable
+        if sc is not None:
+            break
     assert sc is not None
     net = posenet.for_config(WEIGHTS, 2)
     ctx = perch.context_from_scene(sc)
