@@ -96,6 +96,19 @@ __device__ __forceinline__ uint4 patch8(const bf16_t* __restrict__ in, bool vali
     const size_t off = ok ? (((size_t)n * HIN + iy) * HIN + ix) * CIN + ci0 : 0;
     const uint4 v = *reinterpret_cast<const uint4*>(in + off);
     return ok ? v : make_uint4(0u, 0u, 0u, 0u);
+  } else if (CIN == 2) {
+    // four taps of both channels: one 4-byte load per tap (k = 2 tap + ci)
+    unsigned v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int tap = k0 / 2 + q;
+      const int iy = oy * S + tap / 3 - 1, ix = ox * S + tap % 3 - 1;
+      const bool ok = valid && tap < 9 && iy >= 0 && iy < HIN && ix >= 0 && ix < HIN;
+      const size_t off = ok ? (((size_t)n * HIN + iy) * HIN + ix) * 2 : 0;
+      const unsigned x = *reinterpret_cast<const unsigned*>(in + off);
+      v[q] = ok ? x : 0u;
+    }
+    return make_uint4(v[0], v[1], v[2], v[3]);
   } else {
     unsigned v[8];
 #pragma unroll
@@ -113,42 +126,47 @@ __device__ __forceinline__ uint4 patch8(const bf16_t* __restrict__ in, bool vali
   }
 }
 
-// 4 waves per workgroup, each a 32-pixel x 32-channel output tile.
+// Each wave owns all 32 output channels and keeps their weights as MFMA B fragments
+// in registers (KP / 16 of them, loaded once), then walks 32-pixel output tiles
+// tile = wave, wave + total waves, ...: per tile KP / 16 MFMA steps whose A fragments
+// are im2col patches read straight from the input, in increasing k as a single
+// accumulation chain (the same sums in the same order for any grid).
 template <int CIN, int S, int HIN>
 __global__ void __launch_bounds__(256)
     k_conv_fwd(const bf16_t* __restrict__ in, const bf16_t* __restrict__ Wb,
                const float* __restrict__ bias, bf16_t* __restrict__ out, int n_img) {
   using D = KDim<CIN>;
-  constexpr int HO = HIN / S, NPIX = HO * HO;
-  __shared__ __align__(16) bf16_t w[kC * D::LDSROW];
-  // 16-byte staging: rows of KP (a multiple of 8) elements, 16-byte aligned in HBM
-  // and in LDS (LDSROW is a multiple of 8 too)
-  constexpr int V = D::KP / 8;
-  const uint4* __restrict__ src = reinterpret_cast<const uint4*>(Wb);
-  for (int i = threadIdx.x; i < kC * V; i += blockDim.x)
-    *reinterpret_cast<uint4*>(w + (i / V) * D::LDSROW + (i % V) * 8) = src[i];
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int HO = HIN / S, NPIX = HO * HO, NK = D::KP / 16;
+  const int lane = threadIdx.x & 63;
+  const int co = lane & 31, kh = 8 * (lane >> 5);
   const int total = n_img * NPIX;
-  const int m0 = (blockIdx.x * 4 + wave) * 32;
-  if (m0 >= total) return;
-  const int m = m0 + (lane & 31);
-  const bool mv = m < total;
-  const int n = m / NPIX, pix = m % NPIX, oy = pix / HO, ox = pix % HO;
-  const int kh = 8 * (lane >> 5);
-  f32x16 acc = {};
-  for (int kc = 0; kc < D::KP / 16; ++kc) {
-    const int k0 = kc * 16 + kh;
-    const uint4 a = patch8<CIN, S, HIN>(in, mv, n, oy, ox, k0);
-    const uint4 b = *reinterpret_cast<const uint4*>(w + (lane & 31) * D::LDSROW + k0);
-    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(a), as_bf16x8(b), acc, 0, 0, 0);
-  }
-  const int co = lane & 31;
-  const float bb = bias[co];
+  const int n_tiles = (total + 31) / 32;
+  const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int n_waves = gridDim.x * 4;
+  if (wave >= n_tiles) return;
+  // B fragments: W[co][16 kc + kh .. + 8] (rows of KP elements, 16-byte aligned)
+  uint4 bw[NK];
 #pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    const int mm = m0 + acc_row(e, lane);
-    if (mm < total) out[(size_t)mm * kC + co] = f2bf(fmaxf(acc[e] + bb, 0.0f));
+  for (int kc = 0; kc < NK; ++kc)
+    bw[kc] = *reinterpret_cast<const uint4*>(Wb + (size_t)co * D::KP + kc * 16 + kh);
+  const float bb = bias[co];
+  for (int t = wave; t < n_tiles; t += n_waves) {
+    const int m0 = t * 32;
+    const int m = m0 + (lane & 31);
+    const bool mv = m < total;
+    const int n = m / NPIX, pix = m % NPIX, oy = pix / HO, ox = pix % HO;
+    f32x16 acc = {};
+#pragma unroll
+    for (int kc = 0; kc < NK; ++kc) {
+      const uint4 a = patch8<CIN, S, HIN>(in, mv, n, oy, ox, kc * 16 + kh);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(a), as_bf16x8(bw[kc]), acc, 0, 0,
+                                                     0);
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int mm = m0 + acc_row(e, lane);
+      if (mm < total) out[(size_t)mm * kC + co] = f2bf(fmaxf(acc[e] + bb, 0.0f));
+    }
   }
 }
 
@@ -483,14 +501,22 @@ void launch_crops(const float* obs, const unsigned* pdepth, int W, int H, const 
 
 static int conv_blocks(int n_img, int npix) { return (n_img * npix + 127) / 128; }
 
+// Forward grid: about eight 32-pixel tiles per wave (the weight fragments a wave
+// loads are reused across them), at least 512 workgroups while there are tiles.
+static int conv_fwd_blocks(int n_img, int npix) {
+  const int tiles = (n_img * npix + 31) / 32;
+  const int full = (tiles + 3) / 4;  // one tile per wave
+  return std::max(1, std::min(full, std::max(512, (tiles + 31) / 32)));
+}
+
 void launch_forward(const Net& net, int n_crops, hipStream_t s) {
-  hipLaunchKernelGGL((k_conv_fwd<2, 1, 64>), dim3(conv_blocks(n_crops, 64 * 64)), dim3(256), 0, s,
+  hipLaunchKernelGGL((k_conv_fwd<2, 1, 64>), dim3(conv_fwd_blocks(n_crops, 64 * 64)), dim3(256), 0, s,
                      net.crops, net.Wb[0], net.P.cb[0], net.a[1], n_crops);
-  hipLaunchKernelGGL((k_conv_fwd<32, 2, 64>), dim3(conv_blocks(n_crops, 32 * 32)), dim3(256), 0,
+  hipLaunchKernelGGL((k_conv_fwd<32, 2, 64>), dim3(conv_fwd_blocks(n_crops, 32 * 32)), dim3(256), 0,
                      s, net.a[1], net.Wb[1], net.P.cb[1], net.a[2], n_crops);
-  hipLaunchKernelGGL((k_conv_fwd<32, 2, 32>), dim3(conv_blocks(n_crops, 16 * 16)), dim3(256), 0,
+  hipLaunchKernelGGL((k_conv_fwd<32, 2, 32>), dim3(conv_fwd_blocks(n_crops, 16 * 16)), dim3(256), 0,
                      s, net.a[2], net.Wb[2], net.P.cb[2], net.a[3], n_crops);
-  hipLaunchKernelGGL((k_conv_fwd<32, 2, 16>), dim3(conv_blocks(n_crops, 8 * 8)), dim3(256), 0, s,
+  hipLaunchKernelGGL((k_conv_fwd<32, 2, 16>), dim3(conv_fwd_blocks(n_crops, 8 * 8)), dim3(256), 0, s,
                      net.a[3], net.Wb[3], net.P.cb[3], net.a[4], n_crops);
   hipLaunchKernelGGL(k_pool_fwd, dim3(n_crops), dim3(kC), 0, s, net.a[4], n_crops, net.feat);
 }
