@@ -50,18 +50,46 @@ struct Node {
   int32_t j;
   int32_t parent;  // node index, -1 for the root
   int32_t edge;    // cost of the edge from the parent
-  perch_object objs[PERCH_MAX_OBJECTS];  // insertion order
-  int64_t key[PERCH_MAX_OBJECTS];        // canonical: sorted (mesh << 32 | pose)
-  int32_t lazy;          // learned search: a block of unevaluated children of `parent`
-  int64_t hov;           // overlap heuristic: observed points outside V_j (MHA search)
-  double hpr;            // pose-prior heuristic: sum of distances to the estimates
+  int32_t lazy;    // learned search: a block of unevaluated children of `parent`
+  uint64_t h;      // hash of the canonical key (key_hash)
+  int64_t hov;     // overlap heuristic: observed points outside V_j (MHA search)
+  double hpr;      // pose-prior heuristic: sum of distances to the estimates
+  perch_object last;  // the object this state added to its parent's (not for the root)
+  int64_t key[PERCH_MAX_OBJECTS];  // canonical: sorted (mesh << 32 | pose) (first j)
 };
+
+// Room for n more elements, growing geometrically (reserve alone would allocate the
+// exact size and copy the whole vector on every call).
+template <class T>
+void grow_for(std::vector<T>& v, size_t n) {
+  if (v.size() + n > v.capacity()) v.reserve(std::max(2 * v.capacity(), v.size() + n));
+}
+
+// The state's objects in canonical order (materialising a state depends on the set
+// only: the composite is a per-pixel minimum).
+void objs_of(const Node& n, perch_object* out) {
+  for (int k = 0; k < n.j; ++k)
+    out[k] = perch_object{(int32_t)(n.key[k] >> 32), (int32_t)(uint32_t)n.key[k]};
+}
 
 int64_t pack(int32_t m, int32_t p) { return ((int64_t)m << 32) | (uint32_t)p; }
 
-void make_key(Node& n) {
-  for (int k = 0; k < n.j; ++k) n.key[k] = pack(n.objs[k].mesh_id, n.objs[k].pose_idx);
-  std::sort(n.key, n.key + n.j);
+uint64_t key_hash(const Node& n) {
+  uint64_t h = 1469598103934665603ull ^ (uint64_t)n.j;
+  for (int k = 0; k < n.j; ++k) {
+    h ^= (uint64_t)n.key[k];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+// The empty state (the root), with its key hash.
+Node root_node() {
+  Node r;
+  std::memset(&r, 0, sizeof(r));
+  r.parent = -1;
+  r.h = key_hash(r);
+  return r;
 }
 
 int cmp_key(const Node& a, const Node& b) {
@@ -70,21 +98,58 @@ int cmp_key(const Node& a, const Node& b) {
   return a.j == b.j ? 0 : (a.j < b.j ? -1 : 1);
 }
 
-struct KeyHash {
-  const std::vector<Node>* nodes;
-  size_t operator()(int id) const {
-    const Node& n = (*nodes)[id];
-    uint64_t h = 1469598103934665603ull ^ (uint64_t)n.j;
-    for (int k = 0; k < n.j; ++k) {
-      h ^= (uint64_t)n.key[k];
-      h *= 1099511628211ull;
-    }
+// Open-addressing table of the states reached so far: per canonical key the node
+// id that currently holds it.  Keys are compared by their hash, then in full; an
+// entry is only ever replaced (a cheaper path re-opens the state), never removed.
+// The key hash's low bits do not see the mesh ids (bits 32 and up of every key), so
+// slots come from the hash after a 64-bit finaliser that mixes all its bits.
+class StateTable {
+ public:
+  static size_t home(uint64_t h) {
+    h ^= h >> 33;
+    h *= 0xff51afd7ed558ccdull;
+    h ^= h >> 33;
+    h *= 0xc4ceb9fe1a85ec53ull;
+    h ^= h >> 33;
     return (size_t)h;
   }
-};
-struct KeyEq {
-  const std::vector<Node>* nodes;
-  bool operator()(int a, int b) const { return cmp_key((*nodes)[a], (*nodes)[b]) == 0; }
+  explicit StateTable(const std::vector<Node>* nodes) : nodes_(nodes), slots_(1024, -1) {}
+  // the slot holding node id's state, or the empty slot where it would go
+  size_t slot_of(int id) const {
+    const Node& n = (*nodes_)[id];
+    const size_t mask = slots_.size() - 1;
+    for (size_t s = home(n.h) & mask;; s = (s + 1) & mask) {
+      const int e = slots_[s];
+      if (e < 0) return s;
+      const Node& m = (*nodes_)[e];
+      if (m.h == n.h && cmp_key(m, n) == 0) return s;
+    }
+  }
+  int at(size_t s) const { return slots_[s]; }
+  // stores id at slot s (from slot_of(id)); the table may grow, moving slots
+  void put(size_t s, int id) {
+    const bool fresh = slots_[s] < 0;
+    slots_[s] = id;
+    if (fresh && 2 * ++used_ > slots_.size()) grow();
+  }
+  bool holds(int id) const { return slots_[slot_of(id)] == id; }
+
+ private:
+  void grow() {
+    std::vector<int> old;
+    old.swap(slots_);
+    slots_.assign(2 * old.size(), -1);
+    const size_t mask = slots_.size() - 1;
+    for (int e : old) {
+      if (e < 0) continue;
+      size_t s = home((*nodes_)[e].h) & mask;
+      while (slots_[s] >= 0) s = (s + 1) & mask;
+      slots_[s] = e;
+    }
+  }
+  const std::vector<Node>* nodes_;
+  std::vector<int> slots_;
+  size_t used_ = 0;
 };
 
 struct Child {
@@ -166,7 +231,7 @@ class Searcher {
   std::vector<int> remaining(const Node& n) const {
     std::vector<int> left(c_->objects.begin(), c_->objects.end());
     for (int k = 0; k < n.j; ++k) {
-      auto it = std::find(left.begin(), left.end(), n.objs[k].mesh_id);
+      auto it = std::find(left.begin(), left.end(), (int32_t)(n.key[k] >> 32));
       if (it != left.end()) left.erase(it);
     }
     std::sort(left.begin(), left.end());
@@ -185,7 +250,9 @@ class Searcher {
       for (int p : mesh_poses_.at(m)) hc[cnt++] = make_int2(m, p);
     HIP_TRY(hipMemcpyAsync(c_->s_cands.p, hc, cnt * sizeof(int2), hipMemcpyHostToDevice,
                            c_->stream));
-    perch_status st = perch_set_parent(c_, n.objs, n.j);
+    perch_object po[PERCH_MAX_OBJECTS];
+    objs_of(n, po);
+    perch_status st = perch_set_parent(c_, po, n.j);
     if (st) return st;
     int32_t* dcost = c_->s_out.as<int32_t>();
     int32_t* dstat = dcost + cnt;
@@ -268,16 +335,22 @@ class Searcher {
 
   Node child_of(const Node& n, int32_t id, const Child& ch) const {
     Node m;
-    std::memset(&m, 0, sizeof(m));
     m.j = n.j + 1;
     m.g = n.g + ch.cost;
     m.parent = id;
     m.edge = ch.cost;
-    std::memcpy(m.objs, n.objs, sizeof(perch_object) * n.j);
-    m.objs[n.j].mesh_id = ch.mesh;
-    m.objs[n.j].pose_idx = ch.pose;
-    make_key(m);
     m.lazy = 0;
+    m.last = perch_object{ch.mesh, ch.pose};
+    // the parent's sorted key with the new object inserted in place
+    const int64_t nk = pack(ch.mesh, ch.pose);
+    int k = n.j;
+    while (k > 0 && n.key[k - 1] > nk) {
+      m.key[k] = n.key[k - 1];
+      --k;
+    }
+    m.key[k] = nk;
+    std::memcpy(m.key, n.key, sizeof(int64_t) * k);
+    m.h = key_hash(m);
     m.hov = n.hov - ch.gain;
     m.hpr = n.hpr + prior_term(ch);
     return m;
@@ -329,21 +402,24 @@ class Searcher {
       n_eval_best_ = n_evaluated_;
       trace(true);
     }
-    // edge costs along the path
+    // objects in insertion order and edge costs along the path (without a store
+    // the caller fills them in)
     std::memset(best_edges_, 0, sizeof(best_edges_));
     if (store) {
       best_edges_[g.j - 1] = g.edge;
-      for (int id = g.parent, k = g.j - 2; id >= 0 && k >= 0; id = (*store)[id].parent, --k)
+      best_objs_[g.j - 1] = g.last;
+      for (int id = g.parent, k = g.j - 2; id >= 0 && k >= 0; id = (*store)[id].parent, --k) {
         best_edges_[k] = (*store)[id].edge;
+        best_objs_[k] = (*store)[id].last;
+      }
     }
   }
 
   // ---- exhaustive ----
   perch_status exhaustive() {
-    Node root;
-    std::memset(&root, 0, sizeof(root));
-    root.parent = -1;
+    const Node root = root_node();
     path_edges_.assign(K_, 0);
+    path_objs_.assign(K_, perch_object{0, 0});
     return dfs(root);
   }
 
@@ -355,10 +431,14 @@ class Searcher {
     for (const Child& ch : kids) {
       Node m = child_of(n, -1, ch);
       path_edges_[n.j] = ch.cost;
+      path_objs_[n.j] = m.last;
       if (m.j == K_) {
         const bool better = !have_ || m.g < best_.g || (m.g == best_.g && cmp_key(m, best_) < 0);
         offer_goal(m, nullptr);
-        if (better) std::copy(path_edges_.begin(), path_edges_.end(), best_edges_);
+        if (better) {
+          std::copy(path_edges_.begin(), path_edges_.end(), best_edges_);
+          std::copy(path_objs_.begin(), path_objs_.end(), best_objs_);
+        }
       } else {
         st = dfs(m);
         if (st) return st;
@@ -374,21 +454,25 @@ class Searcher {
     const bool focal = n_inad > 0;
     std::vector<Node> nodes;
     nodes.reserve(1 << 16);
-    Node root;
-    std::memset(&root, 0, sizeof(root));
-    root.parent = -1;
+    Node root = root_node();
     root.hov = c_->n_points;  // h_overlap(root) = |I|
     nodes.push_back(root);
-    std::unordered_map<int, int, KeyHash, KeyEq> table(1024, KeyHash{&nodes}, KeyEq{&nodes});
-    table.emplace(0, 0);
+    StateTable table(&nodes);
+    table.put(table.slot_of(0), 0);
     std::vector<char> closed(1, 0);
-    auto g_less = [&](int a, int b) {  // priority: smaller g, deeper, smaller key
-      const Node &x = nodes[a], &y = nodes[b];
-      if (x.g != y.g) return x.g > y.g;
-      if (x.j != y.j) return x.j < y.j;
-      return cmp_key(x, y) > 0;
+    // priority: smaller g, deeper, smaller key; entries carry g and depth so that
+    // most comparisons need not read the nodes
+    struct GEntry {
+      int64_t g;
+      int32_t j, id;
     };
-    std::priority_queue<int, std::vector<int>, decltype(g_less)> open(g_less);
+    auto g_less = [&](const GEntry& a, const GEntry& b) {
+      if (a.g != b.g) return a.g > b.g;
+      if (a.j != b.j) return a.j < b.j;
+      return cmp_key(nodes[a.id], nodes[b.id]) > 0;
+    };
+    auto g_entry = [&](int id) { return GEntry{nodes[id].g, nodes[id].j, id}; };
+    std::priority_queue<GEntry, std::vector<GEntry>, decltype(g_less)> open(g_less);
     // focal heap: deeper first (h_depth = K - |s|), then smaller g, then key
     auto d_less = [&](int a, int b) {
       const Node &x = nodes[a], &y = nodes[b];
@@ -417,30 +501,28 @@ class Searcher {
     };
     std::priority_queue<int, std::vector<int>, decltype(p_less)> prior_q(p_less);
     // states waiting for the focal bound, ordered by g
-    std::priority_queue<int, std::vector<int>, decltype(g_less)> pending(g_less);
-    open.push(0);
-    if (focal) pending.push(0);
+    std::priority_queue<GEntry, std::vector<GEntry>, decltype(g_less)> pending(g_less);
+    open.push(g_entry(0));
+    if (focal) pending.push(g_entry(0));
     std::vector<Child> kids;
-    auto live = [&](int id) {
-      auto it = table.find(id);
-      return it != table.end() && it->second == id && !closed[id];
-    };
+    auto live = [&](int id) { return !closed[id] && table.holds(id); };
     const double w = std::max(1.0f, o_.w);
     for (;;) {
-      while (!open.empty() && !live(open.top())) open.pop();
+      while (!open.empty() && !live(open.top().id)) open.pop();
       if (open.empty()) break;
-      const int64_t gmin = nodes[open.top()].g;
+      const int64_t gmin = open.top().g;
       lower_bound_ = gmin;
       trace(false);
       if (have_ && best_.g <= gmin) break;  // incumbent proven optimal
       if (over_budget()) return PERCH_E_BUDGET;
       int pick = -1;
       if (focal) {
-        while (!pending.empty() && (double)nodes[pending.top()].g <= w * (double)gmin) {
-          if (live(pending.top())) {
-            focal_q.push(pending.top());
-            if (n_inad > 1) over_q.push(pending.top());
-            if (n_inad > 2) prior_q.push(pending.top());
+        while (!pending.empty() && (double)pending.top().g <= w * (double)gmin) {
+          const int id = pending.top().id;
+          if (live(id)) {
+            focal_q.push(id);
+            if (n_inad > 1) over_q.push(id);
+            if (n_inad > 2) prior_q.push(id);
           }
           pending.pop();
         }
@@ -465,11 +547,11 @@ class Searcher {
         }
       }
       if (pick < 0) {
-        pick = open.top();
+        pick = open.top().id;
         open.pop();
       }
       ++expansions_;
-      Node cur = nodes[pick];
+      const Node cur = nodes[pick];
       closed[pick] = 1;
       if (cur.j == K_) {
         offer_goal(cur, &nodes);
@@ -478,28 +560,27 @@ class Searcher {
       }
       perch_status st = expand(cur, kids, n_inad > 1);
       if (st) return st;
+      grow_for(nodes, kids.size());  // one reallocation for the whole batch of children
+      grow_for(closed, kids.size());
       for (const Child& ch : kids) {
-        Node m = child_of(cur, pick, ch);
-        if (have_ && m.g >= best_.g) continue;  // cannot improve the incumbent
-        nodes.push_back(m);
+        if (have_ && cur.g + ch.cost >= best_.g) continue;  // cannot improve the incumbent
+        nodes.push_back(child_of(cur, pick, ch));
         closed.push_back(0);
         const int id = (int)nodes.size() - 1;
-        auto it = table.find(id);
-        if (it != table.end()) {
-          // a cheaper path re-opens the state, also after its expansion: a state
-          // closed from FOCAL may carry a g above its optimum, and the anchor's
-          // min g stays a lower bound on the optimum only if it is re-opened
-          if (!(m.g < nodes[it->second].g)) {
-            nodes.pop_back();
-            closed.pop_back();
-            continue;
-          }
-          table.erase(it);
+        const size_t slot = table.slot_of(id);
+        const int prev = table.at(slot);
+        // a cheaper path re-opens the state, also after its expansion: a state closed
+        // from FOCAL may carry a g above its optimum, and the anchor's min g stays a
+        // lower bound on the optimum only if it is re-opened
+        if (prev >= 0 && !(nodes[id].g < nodes[prev].g)) {
+          nodes.pop_back();
+          closed.pop_back();
+          continue;
         }
-        table.emplace(id, id);
-        open.push(id);
-        if (focal) pending.push(id);
-        if (m.j == K_ && focal && o_.anytime) offer_goal(m, &nodes);
+        table.put(slot, id);
+        open.push(g_entry(id));
+        if (focal) pending.push(g_entry(id));
+        if (nodes[id].j == K_ && focal && o_.anytime) offer_goal(nodes[id], &nodes);
       }
     }
     return PERCH_OK;
@@ -578,7 +659,9 @@ class Searcher {
       MeshMask mask{};
       for (int a = 0; a < nd; ++a)
         mask.allow[a] = std::find(rest.begin(), rest.end(), dist[a]) != rest.end() ? 1 : 0;
-      perch_status st = perch_set_parent(c_, n.objs, n.j);
+      perch_object po[PERCH_MAX_OBJECTS];
+      objs_of(n, po);
+      perch_status st = perch_set_parent(c_, po, n.j);
       if (st) return st;
       cnn::launch_crops(c_->obs.as<float>(), c_->par_depth.as<unsigned>(), cam.W, cam.H,
                         d_desc.as<cnn::CropDesc>(), n_cells, d_crops.as<uint16_t>(), st0);
@@ -621,12 +704,9 @@ class Searcher {
 
     std::vector<Node> nodes;
     nodes.reserve(1 << 16);
-    Node root;
-    std::memset(&root, 0, sizeof(root));
-    root.parent = -1;
-    nodes.push_back(root);
-    std::unordered_map<int, int, KeyHash, KeyEq> table(1024, KeyHash{&nodes}, KeyEq{&nodes});
-    table.emplace(0, 0);
+    nodes.push_back(root_node());
+    StateTable table(&nodes);
+    table.put(table.slot_of(0), 0);
     std::vector<char> closed(1, 0);
     auto a_less = [&](int a, int b) {  // anchor: smaller key g, deeper, states before blocks
       const Node &x = nodes[a], &y = nodes[b];
@@ -654,27 +734,23 @@ class Searcher {
     auto live = [&](int id) {
       if (closed[id]) return false;
       if (nodes[id].lazy) return true;
-      auto it = table.find(id);
-      return it != table.end() && it->second == id;
+      return table.holds(id);
     };
     auto push_child = [&](const Node& parent, int pid, const Child& ch) {
       Node m = child_of(parent, pid, ch);
-      m.lazy = 0;
       if (m.j == K_) offer_goal(m, &nodes);
       if (have_ && m.g >= best_.g) return;  // cannot improve the incumbent
       nodes.push_back(m);
       closed.push_back(0);
       const int id = (int)nodes.size() - 1;
-      auto it = table.find(id);
-      if (it != table.end()) {
-        if (!(m.g < nodes[it->second].g)) {  // re-open on a cheaper path, as above
-          nodes.pop_back();
-          closed.pop_back();
-          return;
-        }
-        table.erase(it);
+      const size_t slot = table.slot_of(id);
+      const int prev = table.at(slot);
+      if (prev >= 0 && !(m.g < nodes[prev].g)) {  // re-open on a cheaper path, as above
+        nodes.pop_back();
+        closed.pop_back();
+        return;
       }
-      table.emplace(id, id);
+      table.put(slot, id);
       open.push(id);
       pending.push(id);
     };
@@ -804,7 +880,7 @@ class Searcher {
           const Node& n = nodes[owner[k]];
           pars[k].ctx = 0;
           pars[k].j = n.j;
-          std::memcpy(pars[k].objs, n.objs, sizeof(perch_object) * n.j);
+          objs_of(n, pars[k].objs);
         }
         st = perch_batch_set_parents(bat, pars.data(), L + Z);
         if (st) return st;
@@ -951,7 +1027,7 @@ class Searcher {
     if (have_) {
       r->cost = best_.g;
       for (int k = 0; k < best_.j; ++k) {
-        r->objs[k] = best_.objs[k];
+        r->objs[k] = best_objs_[k];
         r->edge_cost[k] = best_edges_[k];
       }
     } else {
@@ -986,7 +1062,9 @@ class Searcher {
   bool have_ = false;
   Node best_{};
   int32_t best_edges_[PERCH_MAX_OBJECTS] = {0};
+  perch_object best_objs_[PERCH_MAX_OBJECTS] = {};
   std::vector<int32_t> path_edges_;
+  std::vector<perch_object> path_objs_;
   double t_best_ = -1.0;
   int64_t n_eval_best_ = -1;
   int n_trace_ = 0;
