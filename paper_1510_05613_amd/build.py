@@ -16,6 +16,9 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
                 "-fhip-fp32-correctly-rounded-divide-sqrt", "-Xclang", "-target-feature",
                 "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-result"]
+# roctx ranges (search expansions, parent materialisation, successor launches) for
+# rocprofv3 --marker-trace
+LINK_FLAGS = ["-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
 # host-only sources still go through hipcc: pin the offload target to gfx950 too
 HOST_FLAGS = ["--offload-arch=gfx950", "-O2", "-std=c++17", "-fPIC", "-Wall", "-Xclang",
               "-target-feature", "-Xclang", "-packed-fp32-ops"]
@@ -46,7 +49,7 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
         for f in [ex.submit(run, c) for c in cmds]:
             f.result()
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs, *LINK_FLAGS]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

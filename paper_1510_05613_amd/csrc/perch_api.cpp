@@ -16,6 +16,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "perch_ctx.h"
 
 using namespace perch;
@@ -605,7 +607,9 @@ perch_status perch_set_parent(perch_ctx* c, const perch_object* parent, int32_t 
   perch_status st = upload_meshes(c);
   if (st) return st;
   if (!objects_ok(c, parent, j)) return fail(PERCH_E_ARG, "parent object out of range");
+  roctxRangePushA("perch_set_parent");
   st = materialise_parent(c, parent, j, j + 1 == K);
+  roctxRangePop();
   if (st) return st;
   c->parent_objs.assign(parent, parent + j);
   ++c->parent_serial;
@@ -669,7 +673,11 @@ static perch_status eval_children_impl(perch_ctx* c, const perch_object* cands_d
 
 perch_status perch_eval_children(perch_ctx* c, const perch_object* cands_dev, int32_t n,
                                  int32_t* cost_dev, int32_t* status_dev, int32_t* comps_dev) {
-  return eval_children_impl(c, cands_dev, n, cost_dev, status_dev, comps_dev, nullptr);
+  roctxRangePushA("perch_eval_children");
+  const perch_status st = eval_children_impl(c, cands_dev, n, cost_dev, status_dev, comps_dev,
+                                             nullptr);
+  roctxRangePop();
+  return st;
 }
 
 perch_status perch_overlap_gain(perch_ctx* c, const perch_object* cands_dev, int32_t n,

@@ -33,8 +33,13 @@
 #include <map>
 #include <numeric>
 #include <queue>
+#include <cstdio>
+#include <cstdlib>
+#include <mutex>
 #include <unordered_map>
 #include <vector>
+
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include "perch_cnn.h"
 #include "perch_ctx.h"
@@ -242,6 +247,13 @@ class Searcher {
   // Materialises n on the GPU and evaluates every child; valid ones go to out.
   // with_gain: also the overlap heuristic's decrease per child.
   perch_status expand(const Node& n, std::vector<Child>& out, bool with_gain = false) {
+    roctxRangePushA("perch_search: expand");
+    perch_status st = expand_impl(n, out, with_gain);
+    roctxRangePop();
+    return st;
+  }
+
+  perch_status expand_impl(const Node& n, std::vector<Child>& out, bool with_gain) {
     out.clear();
     const std::vector<int> rest = remaining(n);
     int2* hc = c_->s_hcands.as<int2>();
@@ -1074,6 +1086,39 @@ class Searcher {
 
 }  // namespace
 
+// One JSON line per search appended to the file named by PERCH_SEARCH_LOG (when set
+// and non-empty): the options, the outcome and the anytime trace.  A file that cannot
+// be opened is skipped silently; the search's result does not depend on it.
+static void log_search(const perch_search_opts* o, const perch_result& r, perch_status st) {
+  const char* path = std::getenv("PERCH_SEARCH_LOG");
+  if (!path || !*path) return;
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lock(mu);
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f,
+               "{\"mode\": %d, \"w\": %.9g, \"anytime\": %d, \"budget_s\": %.9g, "
+               "\"budget_expansions\": %lld, \"topk\": %d, \"batch\": %d, \"icp_iters\": %d, "
+               "\"n_priors\": %d, \"status\": %d, \"K\": %d, \"found\": %d, \"cost\": %lld, "
+               "\"lower_bound\": %lld, \"n_expanded\": %lld, \"n_evaluated\": %lld, "
+               "\"n_invalid\": %lld, \"n_merged\": %lld, \"n_evaluated_best\": %lld, "
+               "\"t_total_s\": %.9g, \"t_best_s\": %.9g, \"objs\": [",
+               o->mode, (double)o->w, o->anytime, o->budget_s, (long long)o->budget_expansions,
+               o->topk, o->batch, o->icp_iters, o->n_priors, (int)st, r.K, r.found,
+               (long long)r.cost, (long long)r.lower_bound, (long long)r.n_expanded,
+               (long long)r.n_evaluated, (long long)r.n_invalid, (long long)r.n_merged,
+               (long long)r.n_evaluated_best, r.t_total_s, r.t_best_s);
+  for (int k = 0; r.found && k < r.K; ++k)
+    std::fprintf(f, "%s[%d, %d, %d]", k ? ", " : "", r.objs[k].mesh_id, r.objs[k].pose_idx,
+                 r.edge_cost[k]);
+  std::fprintf(f, "], \"trace\": [");
+  for (int k = 0; k < r.n_trace; ++k)
+    std::fprintf(f, "%s[%.6g, %lld, %lld]", k ? ", " : "", r.trace_t[k],
+                 (long long)r.trace_cost[k], (long long)r.trace_lb[k]);
+  std::fprintf(f, "]}\n");
+  std::fclose(f);
+}
+
 extern "C" perch_status perch_search(perch_ctx* c, const perch_search_opts* opts,
                                      perch_result* out) {
   if (!c || !opts || !out) return fail(PERCH_E_ARG, "null argument");
@@ -1089,6 +1134,7 @@ extern "C" perch_status perch_search(perch_ctx* c, const perch_search_opts* opts
   perch_status st = s.init();
   if (st) return st;
 
+  roctxRangePushA("perch_search");
   if (opts->mode == PERCH_SEARCH_EXHAUSTIVE)
     st = s.exhaustive();
   else if (opts->mode == PERCH_SEARCH_LEARNED || opts->mode == PERCH_SEARCH_LEARNED_MHA)
@@ -1097,8 +1143,10 @@ extern "C" perch_status perch_search(perch_ctx* c, const perch_search_opts* opts
     st = s.best_first(opts->n_priors > 0 ? 3 : 2);
   else
     st = s.best_first(opts->mode == PERCH_SEARCH_FOCAL ? 1 : 0);
+  roctxRangePop();
   s.trace(true);  // the trace's last entry: the state the search ends in
   s.fill(out);
+  log_search(opts, *out, st);
   if (st == PERCH_E_BUDGET) return fail(PERCH_E_BUDGET, "search budget exhausted");
   return st;
 }

@@ -133,3 +133,28 @@ def test_pose_prior_queue_keeps_the_w_bound(w):
         assert a["cost"] == opt and a["lower_bound"] >= a["cost"]
     with pytest.raises(perch.PerchError):  # a queue of the multi-heuristic search only
         ctx.search(perch.SEARCH_FOCAL, w=w, pose_subset=sub, priors=true)
+
+
+def test_search_log_records_each_search(tmp_path, monkeypatch):
+    """PERCH_SEARCH_LOG: one JSON line per search with its options and outcome."""
+    import json
+
+    path = tmp_path / "searches.jsonl"
+    monkeypatch.setenv("PERCH_SEARCH_LOG", str(path))
+    sc = H.c1_scene(0)
+    ctx = perch.context_from_scene(sc)
+    sub = scenes.pose_subset_around(sc, 2, yaw_stride=2)
+    r1 = ctx.search(perch.SEARCH_UCS, pose_subset=sub)
+    r2 = ctx.search(perch.SEARCH_FOCAL, w=3.0, anytime=True, pose_subset=sub)
+    monkeypatch.delenv("PERCH_SEARCH_LOG")
+    ctx.search(perch.SEARCH_UCS, pose_subset=sub)  # not logged
+    rows = [json.loads(line) for line in path.read_text().splitlines()]
+    assert len(rows) == 2
+    for row, r, mode in zip(rows, (r1, r2), (perch.SEARCH_UCS, perch.SEARCH_FOCAL)):
+        assert row["mode"] == mode and row["found"] == int(r["found"])
+        assert row["cost"] == r["cost"] and row["n_evaluated"] == r["n_evaluated"]
+        assert row["n_expanded"] == r["n_expanded"] and row["lower_bound"] == r["lower_bound"]
+        assert [tuple(o[:2]) for o in row["objs"]] == [tuple(o) for o in r["objs"]]
+        assert sum(o[2] for o in row["objs"]) == r["cost"]
+        assert len(row["trace"]) == len(r["trace"])
+    assert rows[1]["w"] == 3.0 and rows[1]["anytime"] == 1
