@@ -469,8 +469,8 @@ typedef struct {
   float label;       /* 1: the object stands in this crop's anchor cell, else 0      */
   float dx, dy;      /* its offset from the anchor / spacing (used when label = 1)  */
   float yaw_bin;     /* true yaw bin (an integer value)                             */
-  float period;      /* bins between yaws the mesh's symmetry makes equal (integer; */
-                     /* n_yaw: one bin, 1: every bin)                              */
+  float period;      /* bins between yaws the mesh's symmetry makes equal: a       */
+                     /* divisor of n_yaw (n_yaw: one bin, 1: every bin)            */
 } perch_posenet_target;
 
 /* 1 <= n_yaw <= 32.  Parameters start at zero: set them before use.  Synchronous. */

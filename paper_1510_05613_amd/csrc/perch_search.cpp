@@ -157,6 +157,20 @@ class StateTable {
   size_t used_ = 0;
 };
 
+// A roctx range for rocprofv3 --marker-trace, closed by end() or at scope exit.
+class Range {
+ public:
+  explicit Range(const char* msg) { roctxRangePushA(msg); }
+  ~Range() { end(); }
+  void end() {
+    if (on_) roctxRangePop();
+    on_ = false;
+  }
+
+ private:
+  bool on_ = true;
+};
+
 struct Child {
   int32_t mesh, pose, cost, gain;  // gain: observed points the child adds to V_j
   float x, y, c, s;                // the child's pose values (grid or ICP-adjusted)
@@ -247,10 +261,8 @@ class Searcher {
   // Materialises n on the GPU and evaluates every child; valid ones go to out.
   // with_gain: also the overlap heuristic's decrease per child.
   perch_status expand(const Node& n, std::vector<Child>& out, bool with_gain = false) {
-    roctxRangePushA("perch_search: expand");
-    perch_status st = expand_impl(n, out, with_gain);
-    roctxRangePop();
-    return st;
+    Range r("perch_search: expand");
+    return expand_impl(n, out, with_gain);
   }
 
   perch_status expand_impl(const Node& n, std::vector<Child>& out, bool with_gain) {
@@ -665,6 +677,7 @@ class Searcher {
     // rank on the device (children of meshes already placed rank last), evaluate
     // the k best exactly; one synchronisation.  all = nothing is left over.
     auto learned_expand = [&](const Node& n, std::vector<Child>& out, bool& all) -> perch_status {
+      Range r("learned: expansion");
       out.clear();
       const std::vector<int> rest = remaining(n);
       const int cnt = (int)rest.size() * P;
@@ -894,9 +907,12 @@ class Searcher {
           pars[k].j = n.j;
           objs_of(n, pars[k].objs);
         }
+        Range r_par("learned batch: parents");
         st = perch_batch_set_parents(bat, pars.data(), L + Z);
+        r_par.end();
         if (st) return st;
         // the learned part of the picked states
+        Range r_net("learned batch: network");
         for (int k = 0; k < L; ++k)
           cnn::launch_crops(c_->obs.as<float>(), batch_slot_depth(bat, k), cam.W, cam.H,
                             d_desc.as<cnn::CropDesc>(), n_cells, d_bcrops + (size_t)k * n_cells * crop_elems,
@@ -906,6 +922,8 @@ class Searcher {
                               d_bpred, st0);
           if (st) return st;
         }
+        r_net.end();
+        Range r_rank("learned batch: ranking");
         size_t n_items = 0;
         full.assign(L, 0);
         for (int k = 0; k < L; ++k) {
@@ -931,6 +949,8 @@ class Searcher {
           n_items += rest.size() * (size_t)P;
         }
         HIP_TRY(hipGetLastError());
+        r_rank.end();
+        Range r_exact("learned batch: exact evaluation");
         st = perch_batch_eval(bat, reinterpret_cast<const perch_work*>(d_items), (int)n_items,
                               d_out, d_out + n_items, nullptr);
         if (st) return st;
@@ -939,6 +959,8 @@ class Searcher {
         HIP_TRY(hipMemcpyAsync(h_out, d_out, n_items * 2 * sizeof(int32_t),
                                hipMemcpyDeviceToHost, st0));
         HIP_TRY(hipStreamSynchronize(st0));
+        r_exact.end();
+        Range r_q("learned batch: queues");
         n_expanded_ += L + Z;
         n_evaluated_ += (int64_t)n_items;
         for (size_t i = 0; i < n_items; ++i) {
@@ -1134,7 +1156,7 @@ extern "C" perch_status perch_search(perch_ctx* c, const perch_search_opts* opts
   perch_status st = s.init();
   if (st) return st;
 
-  roctxRangePushA("perch_search");
+  Range r("perch_search");
   if (opts->mode == PERCH_SEARCH_EXHAUSTIVE)
     st = s.exhaustive();
   else if (opts->mode == PERCH_SEARCH_LEARNED || opts->mode == PERCH_SEARCH_LEARNED_MHA)
@@ -1143,7 +1165,7 @@ extern "C" perch_status perch_search(perch_ctx* c, const perch_search_opts* opts
     st = s.best_first(opts->n_priors > 0 ? 3 : 2);
   else
     st = s.best_first(opts->mode == PERCH_SEARCH_FOCAL ? 1 : 0);
-  roctxRangePop();
+  r.end();
   s.trace(true);  // the trace's last entry: the state the search ends in
   s.fill(out);
   log_search(opts, *out, st);
