@@ -562,7 +562,7 @@ def learned_expansion_leg(reps: int = 20) -> dict:
             ctx.set_parent([])
             torch.cuda.synchronize()
             ev[0].record(stream)
-            crops = perch.Cnn.crops(ctx, cells)
+            crops = perch.Cnn.crops(ctx, cells, net.crop_step)
             ev[1].record(stream)
             pred = net.predict(crops, pairs)
             ev[2].record(stream)

@@ -326,6 +326,9 @@ perch_status perch_cnn_create(int32_t n_mesh, int32_t max_crops, int32_t max_pai
                               void* hip_stream, perch_cnn** out);
 void perch_cnn_destroy(perch_cnn* net);
 int64_t perch_cnn_param_count(const perch_cnn* net);
+/* The learned search's crops for this network sample every `step` pixels (1..64;
+ * default 1): a network trained on crops of step s must be searched with step s. */
+perch_status perch_cnn_set_crop_step(perch_cnn* net, int32_t step);
 /* host FP32 parameters in / out (set also resets the Adam state).  Synchronous. */
 perch_status perch_cnn_set_params(perch_cnn* net, const float* params, int64_t n);
 perch_status perch_cnn_get_params(perch_cnn* net, float* params, int64_t n);

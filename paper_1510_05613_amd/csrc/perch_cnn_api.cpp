@@ -13,6 +13,7 @@ using namespace perch::cnn;
 
 struct perch_cnn {
   int n_mesh = 0, max_crops = 0, max_pairs = 0;
+  int crop_step = 1;  // pixel step of the crops the learned search takes for this network
   hipStream_t stream = nullptr;
   int64_t n_params = 0;
   int step = 0;
@@ -74,6 +75,8 @@ bool crop_descriptors(const float M[12], float fx, float fy, float cx, float cy,
 }
 
 }  // namespace cnn
+
+int cnn_crop_step(const perch_cnn* c) { return c ? c->crop_step : 1; }
 
 perch_status cnn_capacity(const perch_cnn* c, int* max_crops, int* max_pairs) {
   if (!c) return fail(PERCH_E_ARG, "null network");
@@ -203,6 +206,12 @@ void perch_cnn_destroy(perch_cnn* c) {
 }
 
 int64_t perch_cnn_param_count(const perch_cnn* c) { return c ? c->n_params : -1; }
+
+perch_status perch_cnn_set_crop_step(perch_cnn* c, int32_t step) {
+  if (!c || step < 1 || step > 64) return fail(PERCH_E_ARG, "bad crop step");
+  c->crop_step = step;
+  return PERCH_OK;
+}
 
 perch_status perch_cnn_set_params(perch_cnn* c, const float* host, int64_t n) {
   if (!c || !host || n != c->n_params) return fail(PERCH_E_ARG, "parameter count mismatch");

@@ -100,6 +100,8 @@ perch_status fail(perch_status st, const char* fmt, ...);
 
 // The largest batch (crops, pairs) the network was created for (perch_cnn_api.cpp).
 perch_status cnn_capacity(const perch_cnn* c, int* max_crops, int* max_pairs);
+// Pixel step of the crops the learned search takes for network c (1: every pixel).
+int cnn_crop_step(const perch_cnn* c);
 
 // Runs the learned network (forward pass and head) on stream s, the context's
 // stream in the learned search (perch_cnn_api.cpp).

@@ -645,7 +645,7 @@ class Searcher {
     std::vector<cnn::CropDesc> hdesc(n_cells);
     const Cam& cam = c_->cam;
     if (!cnn::crop_descriptors(cam.M, cam.fx, cam.fy, cam.cx, cam.cy, cells.data(), n_cells,
-                               hdesc.data()))
+                               hdesc.data(), cnn_crop_step(o_.cnn)))
       return fail(PERCH_E_ARG, "a pose cell lies behind the camera");
     std::vector<perch_cnn_pair> hp(maxp);
     for (int a = 0; a < nd; ++a)

@@ -82,16 +82,17 @@ def try_scene(config: int, index: int, render, lib, max_tries: int = 20):
         return None
 
 
-def label_parent(ctx: "perch.Context", scene, parent, crop_base: int, cells=None):
-    """Crops of `parent` at the given pose cells (all cells by default) and the
-    labelled pairs of every child placed in those cells."""
+def label_parent(ctx: "perch.Context", scene, parent, crop_base: int, cells=None,
+                 crop_step: int = 1):
+    """Crops of `parent` at the given pose cells (all cells by default; one sample every
+    crop_step pixels) and the labelled pairs of every child placed in those cells."""
     import torch
 
     g = scene.grid
     n_cells = g.nx * g.ny
     cells = np.arange(n_cells) if cells is None else np.asarray(cells, np.int64)
     ctx.set_parent(parent)
-    crops = perch.Cnn.crops(ctx, cell_centres(g)[cells])
+    crops = perch.Cnn.crops(ctx, cell_centres(g)[cells], crop_step)
     rest = remaining_meshes(scene, parent)
     cell_pose = (cells[:, None] * g.n_yaw + np.arange(g.n_yaw)[None, :]).ravel().astype(np.int32)
     local = np.repeat(np.arange(len(cells)), g.n_yaw)
@@ -132,7 +133,7 @@ def sample_cells(scene, parent, max_cells: int, rng) -> Optional[np.ndarray]:
 
 
 def build_dataset(indices: Sequence[int], config: int = 4, log=None,
-                  max_cells: int = 256) -> Dataset:
+                  max_cells: int = 256, crop_step: int = 1) -> Dataset:
     """Labels the children of the root and of every ground-truth prefix of each scene
     (on grids with more than max_cells cells, those in a seeded sample of cells).
     Held-out indices are refused."""
@@ -155,7 +156,8 @@ def build_dataset(indices: Sequence[int], config: int = 4, log=None,
         ctx = perch.context_from_scene(sc)
         rng = np.random.default_rng(sc.seed)
         for par in gt_prefixes(sc):
-            c, p, t, v = label_parent(ctx, sc, par, base, sample_cells(sc, par, max_cells, rng))
+            c, p, t, v = label_parent(ctx, sc, par, base, sample_cells(sc, par, max_cells, rng),
+                                      crop_step)
             crops.append(c)
             pairs.append(p)
             tgts.append(t)
@@ -228,19 +230,23 @@ def train(net: "perch.Cnn", ds: Dataset, steps: int, batch_crops: int = 64, lr: 
 
 
 def save(net: "perch.Cnn", path: str, **meta) -> None:
-    """Checkpoint: every parameter tensor plus scalar metadata (plain .npz)."""
+    """Checkpoint: every parameter tensor, the crop step plus scalar metadata (plain
+    .npz)."""
     p = net.get_params()
     extra = {f"meta_{k}": np.asarray(v) for k, v in meta.items()}
-    np.savez(path, n_mesh=np.asarray(net.n_mesh), **p, **extra)
+    np.savez(path, n_mesh=np.asarray(net.n_mesh), crop_step=np.asarray(net.crop_step), **p,
+             **extra)
 
 
 def load(path: str, max_crops: int = 256, max_pairs: int = 8192) -> "perch.Cnn":
     """A network with the checkpoint's parameters (no pickled objects are read)."""
     with np.load(path, allow_pickle=False) as z:
         n_mesh = int(z["n_mesh"])
+        step = int(z["crop_step"]) if "crop_step" in z.files else 1
         params = {k: z[k] for k in perch.CNN_TENSORS}
     net = perch.Cnn(n_mesh, max_crops=max_crops, max_pairs=max_pairs)
     net.set_params(params)
+    net.set_crop_step(step)
     return net
 
 
@@ -404,20 +410,25 @@ def main(argv: Optional[Sequence[str]] = None) -> None:
     ap.add_argument("--max-cells", type=int, default=256, help="pose cells labelled per parent")
     ap.add_argument("--topk", type=int, default=64)
     ap.add_argument("--budget", type=float, default=0.0, help="gain test: seconds per search")
+    ap.add_argument("--crop-step", type=int, default=1,
+                    help="pixel step of the crops (4 gives 640x480 crops the 160x120 field)")
     a = ap.parse_args(argv)
 
     def log(msg):
         print(msg, flush=True)
 
-    ds = build_dataset(range(a.scenes), a.config, log=log, max_cells=a.max_cells)
+    ds = build_dataset(range(a.scenes), a.config, log=log, max_cells=a.max_cells,
+                       crop_step=a.crop_step)
     log(f"dataset: {ds.n_scenes} scenes, {ds.n_parents} parents, {len(ds.pairs)} pairs "
         f"({ds.n_valid} valid), {ds.crops.shape[0]} crops")
-    val = build_dataset(range(a.val_first, a.val_first + a.val), a.config, max_cells=a.max_cells)
+    val = build_dataset(range(a.val_first, a.val_first + a.val), a.config, max_cells=a.max_cells,
+                        crop_step=a.crop_step)
     n_mesh = len(scenes.LIBRARIES[scenes.CONFIGS[a.config]["lib"]]["meshes"])
     mc, mp = max_block(ds, a.batch_crops)
     mc2, mp2 = max_block(val, a.batch_crops)
     net = perch.Cnn(n_mesh, max_crops=max(mc, mc2), max_pairs=max(mp, mp2))
     net.set_params(init_params(n_mesh, a.seed))
+    net.set_crop_step(a.crop_step)
     log(f"before: {ranking_quality(net, val)}")
     t0 = time.time()
     losses = train(net, ds, a.steps, a.batch_crops, a.lr, a.seed, log=log)

@@ -35,6 +35,7 @@ EXPORTS = ("perch_create", "perch_destroy", "perch_set_observation", "perch_add_
            "perch_batch_autotune",
            "perch_autotune", "perch_cnn_create", "perch_cnn_destroy", "perch_cnn_param_count",
            "perch_cnn_set_params", "perch_cnn_get_params", "perch_cnn_crops", "perch_cnn_predict",
+           "perch_cnn_set_crop_step",
            "perch_rank_children", "perch_cnn_train_step", "perch_cnn_gradients",
            "perch_posenet_create", "perch_posenet_destroy", "perch_posenet_param_count",
            "perch_posenet_set_params", "perch_posenet_get_params", "perch_cnn_crops_step",
@@ -139,6 +140,7 @@ def load(path: str = LIB_PATH):
     L.perch_cnn_set_params.argtypes = [P, P, C.c_int64]
     L.perch_cnn_get_params.argtypes = [P, P, C.c_int64]
     L.perch_cnn_crops.argtypes = [P, P, I32, P]
+    L.perch_cnn_set_crop_step.argtypes = [P, I32]
     L.perch_cnn_predict.argtypes = [P, P, I32, P, I32, P]
     L.perch_rank_children.argtypes = [P, P, I32, I32, P, I32, P, P, P]
     L.perch_cnn_train_step.argtypes = [P, P, I32, P, P, I32, C.c_float, C.POINTER(C.c_float)]
@@ -516,6 +518,7 @@ class Cnn:
                                        C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         self.h = h
         self.n_params = int(load().perch_cnn_param_count(self.h))
+        self.crop_step = 1
 
     def close(self):
         if getattr(self, "h", None):
@@ -551,14 +554,24 @@ class Cnn:
         _check(load().perch_cnn_get_params(self.h, flat.ctypes.data, self.n_params))
         return self.unpack(flat)
 
+    def set_crop_step(self, step: int):
+        """Pixel step of the crops the learned search takes for this network."""
+        _check(load().perch_cnn_set_crop_step(self.h, int(step)))
+        self.crop_step = int(step)
+
     @staticmethod
-    def crops(ctx: "Context", xy):
-        """bfloat16 crops (as an int16 GPU tensor n x 64 x 64 x 2) of ctx's parent."""
+    def crops(ctx: "Context", xy, step: int = 1):
+        """bfloat16 crops (as an int16 GPU tensor n x 64 x 64 x 2) of ctx's parent, one
+        sample every `step` pixels."""
         import torch
 
         xy = np.ascontiguousarray(xy, np.float32).reshape(-1, 2)
         out = torch.empty((len(xy), 64, 64, 2), dtype=torch.int16, device="cuda")
-        _check(load().perch_cnn_crops(ctx.h, xy.ctypes.data, len(xy), out.data_ptr()))
+        if step == 1:
+            _check(load().perch_cnn_crops(ctx.h, xy.ctypes.data, len(xy), out.data_ptr()))
+        else:
+            _check(load().perch_cnn_crops_step(ctx.h, xy.ctypes.data, len(xy), int(step),
+                                               out.data_ptr()))
         return out
 
     @staticmethod

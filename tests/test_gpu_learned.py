@@ -181,3 +181,26 @@ def test_learned_batched_needs_network_capacity():
         ctx.search(perch.SEARCH_LEARNED, w=2.0, anytime=True, cnn=random_net(0), batch=4)
     with pytest.raises(perch.PerchError):
         ctx.search(perch.SEARCH_LEARNED_MHA, w=2.0, anytime=True, cnn=batched_net(0, 4), batch=4)
+
+
+def test_crop_step_is_the_networks_and_keeps_the_optimum():
+    """A network's crop step reaches the learned search's crops (strided crops equal
+    perch_cnn_crops_step's), bad steps are refused, and the search stays exact."""
+    net = random_net(3)
+    assert net.crop_step == 1
+    with pytest.raises(perch.PerchError):
+        net.set_crop_step(0)
+    with pytest.raises(perch.PerchError):
+        net.set_crop_step(65)
+    net.set_crop_step(3)
+    sc = held_out_scene(2)
+    ctx = perch.context_from_scene(sc)
+    ctx.set_parent([])
+    xy = learn.cell_centres(sc.grid)[:5]
+    a = perch.Cnn.crops(ctx, xy, 3).cpu().numpy()
+    b = perch.PoseNet.crops(ctx, xy, 3).cpu().numpy()
+    assert np.array_equal(a, b)
+    assert not np.array_equal(a, perch.Cnn.crops(ctx, xy).cpu().numpy())
+    ex = ctx.search(perch.SEARCH_EXHAUSTIVE)
+    r = ctx.search(perch.SEARCH_LEARNED, w=2.0, anytime=True, cnn=net, topk=16)
+    assert r["found"] and r["cost"] == ex["cost"] and r["lower_bound"] >= r["cost"]
