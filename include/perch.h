@@ -337,7 +337,8 @@ perch_status perch_cnn_get_params(perch_cnn* net, float* params, int64_t n);
  * Synchronous. */
 perch_status perch_cnn_crops(perch_ctx* ctx, const float* xy, int32_t n, uint16_t* crops_dev);
 /* Predictions (device, n_pairs floats) of log(1 + cost); a pair whose crop or
- * mesh index is out of range gets NaN (and is ignored by training).
+ * mesh index is out of range gets NaN (and is ignored by training).  crops_dev
+ * must be 16-byte aligned here and in the training calls (PERCH_E_ARG otherwise).
  * Asynchronous on the network's stream. */
 perch_status perch_cnn_predict(perch_cnn* net, const uint16_t* crops_dev, int32_t n_crops,
                                const perch_cnn_pair* pairs_dev, int32_t n_pairs, float* pred_dev);
@@ -489,7 +490,9 @@ perch_status perch_posenet_get_params(perch_posenet* net, float* params, int64_t
 perch_status perch_cnn_crops_step(perch_ctx* ctx, const float* xy, int32_t n, int32_t step,
                                   uint16_t* crops_dev);
 /* Raw outputs (device, n_pairs x (3 + n_yaw) floats); NaN rows for pairs whose
- * crop or mesh index is out of range.  Asynchronous on the network's stream. */
+ * crop or mesh index is out of range.  crops_dev must be 16-byte aligned here, in
+ * the training calls and in perch_posenet_estimate (PERCH_E_ARG otherwise).
+ * Asynchronous on the network's stream. */
 perch_status perch_posenet_predict(perch_posenet* net, const uint16_t* crops_dev,
                                    int32_t n_crops, const perch_posenet_pair* pairs_dev,
                                    int32_t n_pairs, float* out_dev);

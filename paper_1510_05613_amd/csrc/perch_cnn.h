@@ -57,7 +57,13 @@ void launch_crops(const float* obs, const unsigned* pdepth, int W, int H, const 
 // camera depth of the point; false when a point lies behind the camera.
 bool crop_descriptors(const float M[12], float fx, float fy, float cx, float cy, const float* xy,
                       int n, CropDesc* out, int step = 1);
+// Forward pass of the trunk for training: every activation a[1..4] is kept for the
+// backward pass.
 void launch_forward(const Net& net, int n_crops, hipStream_t s);
+// The same forward pass for inference (bit-identical features): conv1 + conv2 and
+// conv3 + conv4 + pooling run as two fused kernels; of the activations only a[2]
+// is written.
+void launch_infer(const Net& net, int n_crops, hipStream_t s);
 // Pairs whose crop index is outside [0, n_crops) or mesh outside [0, n_mesh) are
 // ignored by the backward pass and predicted as NaN.
 // The first head layer splits into a per-crop part (features), a per-mesh part

@@ -126,17 +126,62 @@ __device__ __forceinline__ uint4 patch8(const bf16_t* __restrict__ in, bool vali
   }
 }
 
-// Each wave owns all 32 output channels and keeps their weights as MFMA B fragments
-// in registers (KP / 16 of them, loaded once), then walks 32-pixel output tiles
-// tile = wave, wave + total waves, ...: per tile KP / 16 MFMA steps whose A fragments
-// are im2col patches read straight from the input, in increasing k as a single
-// accumulation chain (the same sums in the same order for any grid).
+// Forward tiles are computed transposed, out^T = W x patch^T: the weights are the
+// MFMA's A operand (lane l: W[l % 32][16 kc + 8 (l / 32) .. + 8]) and the im2col
+// patches its B operand (lane l: pixel l % 32), so lane l ends with pixel l % 32's
+// channels 8 g + 4 (l / 32) + i in accumulator element 4 g + i (g, i = 0..3), and
+// the bias, ReLU and bfloat16 rounding give four packed 8-byte stores per lane.
+__device__ __forceinline__ unsigned pack_bf16(float lo, float hi) {
+  typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+  const bf16x2_t v = {(__bf16)lo, (__bf16)hi};  // v_cvt_pk_bf16_f32: round to nearest even
+  return __builtin_bit_cast(unsigned, v);
+}
+
+// dst[8 g + 4 (lane / 32) .. + 4] of the lane's pixel = bf16(relu(acc + bias)); bias
+// is a 16-byte aligned table of the 32 channel biases.
+template <typename Ptr>
+__device__ __forceinline__ void store_relu_bf16(const f32x16& acc, const float* bias, int lane,
+                                                Ptr dst) {
+  const int h4 = 4 * (lane >> 5);
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const float4 b = *reinterpret_cast<const float4*>(bias + 8 * g + h4);
+    const uint2 v = make_uint2(pack_bf16(fmaxf(acc[4 * g] + b.x, 0.0f), fmaxf(acc[4 * g + 1] + b.y, 0.0f)),
+                               pack_bf16(fmaxf(acc[4 * g + 2] + b.z, 0.0f), fmaxf(acc[4 * g + 3] + b.w, 0.0f)));
+    *reinterpret_cast<uint2*>(dst + 8 * g + h4) = v;
+  }
+}
+
+// An empty use of v's registers: the compiler waits for v's load here.
+__device__ __forceinline__ void settle(const uint4& v) {
+  asm volatile("" ::"v"(v.x), "v"(v.y), "v"(v.z), "v"(v.w));
+}
+
+// Workgroup barrier ordering LDS accesses only: global stores stay in flight.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+__device__ __forceinline__ f32x16 mfma_bf16(uint4 a, uint4 b, const f32x16& c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(a), as_bf16x8(b), c, 0, 0, 0);
+}
+
+// Each wave keeps the 32 output channels' weights as MFMA fragments in registers
+// (KP / 16 of them, loaded once), then walks 32-pixel output tiles tile = wave,
+// wave + total waves, ...: per tile KP / 16 MFMA steps whose patch fragments are read
+// straight from the input, in increasing k as a single accumulation chain (the same
+// sums in the same order for any grid).
 template <int CIN, int S, int HIN>
 __global__ void __launch_bounds__(256)
     k_conv_fwd(const bf16_t* __restrict__ in, const bf16_t* __restrict__ Wb,
                const float* __restrict__ bias, bf16_t* __restrict__ out, int n_img) {
   using D = KDim<CIN>;
   constexpr int HO = HIN / S, NPIX = HO * HO, NK = D::KP / 16;
+  __shared__ __align__(16) float sb[kC];
+  if (threadIdx.x < kC) sb[threadIdx.x] = bias[threadIdx.x];
+  __syncthreads();
   const int lane = threadIdx.x & 63;
   const int co = lane & 31, kh = 8 * (lane >> 5);
   const int total = n_img * NPIX;
@@ -144,28 +189,220 @@ __global__ void __launch_bounds__(256)
   const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int n_waves = gridDim.x * 4;
   if (wave >= n_tiles) return;
-  // B fragments: W[co][16 kc + kh .. + 8] (rows of KP elements, 16-byte aligned)
-  uint4 bw[NK];
+  uint4 wf[NK];  // W[co][16 kc + kh .. + 8] (rows of KP elements, 16-byte aligned)
 #pragma unroll
   for (int kc = 0; kc < NK; ++kc)
-    bw[kc] = *reinterpret_cast<const uint4*>(Wb + (size_t)co * D::KP + kc * 16 + kh);
-  const float bb = bias[co];
+    wf[kc] = *reinterpret_cast<const uint4*>(Wb + (size_t)co * D::KP + kc * 16 + kh);
   for (int t = wave; t < n_tiles; t += n_waves) {
-    const int m0 = t * 32;
-    const int m = m0 + (lane & 31);
+    const int m = t * 32 + (lane & 31);
     const bool mv = m < total;
     const int n = m / NPIX, pix = m % NPIX, oy = pix / HO, ox = pix % HO;
     f32x16 acc = {};
 #pragma unroll
-    for (int kc = 0; kc < NK; ++kc) {
-      const uint4 a = patch8<CIN, S, HIN>(in, mv, n, oy, ox, kc * 16 + kh);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(a), as_bf16x8(bw[kc]), acc, 0, 0,
-                                                     0);
-    }
+    for (int kc = 0; kc < NK; ++kc)
+      acc = mfma_bf16(wf[kc], patch8<CIN, S, HIN>(in, mv, n, oy, ox, kc * 16 + kh), acc);
+    if (mv) store_relu_bf16(acc, sb, lane, out + (size_t)m * kC);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// inference: conv1 and conv2 fused over bands of conv2 output rows
+// ---------------------------------------------------------------------------
+
+// conv1's 64 x 64 x 32 activation never reaches HBM: a work item is one crop's band
+// of kBandRows conv2 output rows.  The item's 2 kBandRows + 3 input rows are staged
+// in LDS (loaded during the previous item), conv1 computes the 2 kBandRows + 1 rows
+// that the band's stride-2 3 x 3 windows read into an LDS band, and conv2 reads its
+// patches from there.  Both LDS tiles carry zero padding (a column left of the image,
+// and right of it for the input; conv1's row -1), so no patch read is masked.
+// Tiles, fragments, the accumulation chain, bias, ReLU and rounding are those of
+// k_conv_fwd for each layer (a conv1 tile is half a row, a conv2 tile one output
+// row), so the output equals the two unfused launches bit for bit.  Work items are
+// taken grid-stride; each wave loads both layers' weight fragments once.
+constexpr int kBandRows = 4;                // conv2 output rows per work item (one per wave)
+constexpr int kBandIn = 2 * kBandRows + 1;  // conv1 rows a band reads
+constexpr int kInRows = kBandIn + 2;        // input rows those read
+constexpr int kInSlots = 72;                // input row: col x at slot x + 4, pads at 3 and 68
+constexpr int kBandSlots = kCrop + 1;       // band row: col x at slot x + 1, pad at 0
+constexpr int kPixStride = kC + 8;          // bfloat16 per LDS pixel (80 B spreads the banks)
+constexpr int kConv12Items = kCrop / 2 / kBandRows;  // work items per crop
+
+__global__ void __launch_bounds__(256)
+    k_conv12_fwd(const bf16_t* __restrict__ in, const bf16_t* __restrict__ W1,
+                 const float* __restrict__ b1, const bf16_t* __restrict__ W2,
+                 const float* __restrict__ b2, bf16_t* __restrict__ out, int n_img) {
+  constexpr int NK1 = KDim<2>::KP / 16, KP1 = KDim<2>::KP;
+  constexpr int NK2 = KDim<kC>::KP / 16, KP2 = KDim<kC>::KP;
+  constexpr int H2 = kCrop / 2;
+  constexpr int IN_U4 = kInRows * kCrop * 2 * 2 / 16;  // 16-byte pieces of an item's input
+  __shared__ __align__(16) unsigned sin[kInRows * kInSlots];  // two bfloat16 channels per slot
+  __shared__ __align__(16) bf16_t band[kBandIn * kBandSlots * kPixStride];
+  __shared__ __align__(16) float sb[2 * kC];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int co = lane & 31, kh = 8 * (lane >> 5), h = lane >> 5;
+  if (tid < 2 * kC) sb[tid] = tid < kC ? b1[tid] : b2[tid - kC];
+  for (int r = tid; r < kInRows; r += blockDim.x) sin[r * kInSlots + 3] = sin[r * kInSlots + 68] = 0u;
+  for (int i = tid; i < kBandIn * kPixStride / 8; i += blockDim.x)  // slot 0 of every band row
+    *reinterpret_cast<uint4*>(band + (i / (kPixStride / 8)) * kBandSlots * kPixStride +
+                              8 * (i % (kPixStride / 8))) = make_uint4(0u, 0u, 0u, 0u);
+  uint4 w1[NK1], w2[NK2];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int mm = m0 + acc_row(e, lane);
-      if (mm < total) out[(size_t)mm * kC + co] = f2bf(fmaxf(acc[e] + bb, 0.0f));
+  for (int kc = 0; kc < NK1; ++kc)
+    w1[kc] = *reinterpret_cast<const uint4*>(W1 + (size_t)co * KP1 + kc * 16 + kh);
+#pragma unroll
+  for (int kc = 0; kc < NK2; ++kc)
+    w2[kc] = *reinterpret_cast<const uint4*>(W2 + (size_t)co * KP2 + kc * 16 + kh);
+  const int n_items = n_img * kConv12Items;
+  // 16 bytes of item `it`'s input rows: the load is clamped into the input and issued
+  // by every thread; `ok` says whether they are the item's (else zero padding)
+  auto fetch = [&](int it, bool& ok) {
+    const int itc = min(it, n_items - 1);
+    const int yi = 2 * (itc % kConv12Items) * kBandRows - 2 + (tid % IN_U4) / 16;
+    const int yc = min(max(yi, 0), kCrop - 1);
+    ok = it < n_items && yi == yc;
+    return *reinterpret_cast<const uint4*>(
+        in + (((size_t)(itc / kConv12Items) * kCrop + yc) * kCrop + 4 * (tid % 16)) * 2);
+  };
+  bool pre_ok;
+  uint4 pre = fetch(blockIdx.x, pre_ok);
+  // the weight fragments land before the loop, whose waits then count only its own
+  // loads and stores (a weight load pending at the loop entry would make the
+  // compiler wait for every outstanding store in each iteration)
+#pragma unroll
+  for (int kc = 0; kc < NK1; ++kc) settle(w1[kc]);
+#pragma unroll
+  for (int kc = 0; kc < NK2; ++kc) settle(w2[kc]);
+  // the input of the next item goes to LDS during conv2 (conv1 is done with it),
+  // long after its load was issued
+  auto stage = [&]() {
+    if (tid < IN_U4)
+      *reinterpret_cast<uint4*>(sin + (tid / 16) * kInSlots + 4 + 4 * (tid % 16)) =
+          pre_ok ? pre : make_uint4(0u, 0u, 0u, 0u);
+  };
+  stage();
+  for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
+    const int n = item / kConv12Items, r0 = (item % kConv12Items) * kBandRows;
+    const int y0 = 2 * r0 - 1;  // conv1 row of band row 0
+    lds_barrier();
+    pre = fetch(item + gridDim.x, pre_ok);
+    // conv1: two 32-pixel tiles per band row; row -1 is conv2's zero padding
+    for (int t = wave; t < 2 * kBandIn; t += 4) {
+      const int yl = t >> 1, ox = (t & 1) * 32 + (lane & 31);
+      bf16_t* dst = band + (yl * kBandSlots + ox + 1) * kPixStride;
+      if (y0 + yl < 0) {
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+          *reinterpret_cast<uint2*>(dst + 8 * g + 4 * h) = make_uint2(0u, 0u);
+        continue;
+      }
+      // taps (ky, kx) of input (y0 + yl + ky - 1, ox + kx - 1): sin row yl + ky, slot ox + kx + 3
+      const unsigned* sp = sin + yl * kInSlots + ox + 3;
+      const unsigned t0 = sp[0], t1 = sp[1], t2 = sp[2], t3 = sp[kInSlots],
+                     t4 = sp[kInSlots + 1], t5 = sp[kInSlots + 2], t6 = sp[2 * kInSlots],
+                     t7 = sp[2 * kInSlots + 1], t8 = sp[2 * kInSlots + 2];
+      // k = 2 tap + channel: lanes 0-31 hold taps 0-3 and 8, lanes 32-63 taps 4-7
+      const uint4 p0 = h ? make_uint4(t4, t5, t6, t7) : make_uint4(t0, t1, t2, t3);
+      const uint4 p1 = make_uint4(h ? 0u : t8, 0u, 0u, 0u);
+      f32x16 acc = {};
+      acc = mfma_bf16(w1[0], p0, acc);
+      acc = mfma_bf16(w1[1], p1, acc);
+      store_relu_bf16(acc, sb, lane, dst);
+    }
+    lds_barrier();
+    stage();
+    // conv2: output row r0 + wave; tap (ky, kx) of pixel ox reads band row
+    // 2 wave + ky, slot 2 ox + kx
+    {
+      const int oy = r0 + wave, ox = lane & 31;
+      const bf16_t* bp = band + (2 * wave * kBandSlots + 2 * ox) * kPixStride + kh;
+      f32x16 acc = {};
+#pragma unroll
+      for (int kc = 0; kc < NK2; ++kc) {
+        const int tap = kc / 2, ky = tap / 3, kx = tap % 3;
+        const uint4 a = *reinterpret_cast<const uint4*>(
+            bp + (ky * kBandSlots + kx) * kPixStride + 16 * (kc % 2));
+        acc = mfma_bf16(w2[kc], a, acc);
+      }
+      store_relu_bf16(acc, sb + kC, lane, out + (((size_t)n * H2 + oy) * H2 + ox) * kC);
+    }
+  }
+}
+
+// conv3, conv4 and the pooling fused per crop for inference: a3 (16 x 16) and a4
+// (8 x 8) stay in LDS, only the 64 pooled features are written.  conv3's tiles
+// (two output rows, one per wave of the 512-thread workgroup) and conv4's (four
+// rows) are k_conv_fwd's, the pooling sums in k_pool_fwd's order, so the features
+// equal the unfused launches' bit for bit.  Both layers' weight fragments are read
+// from LDS copies, which leaves a wave the registers to issue all eighteen patch
+// loads of its conv3 tile at once.  a3 in LDS has a zero row and column before the
+// image (slot (y + 1) 17 + x + 1).
+constexpr int kConv34Threads = 512;
+
+__global__ void __launch_bounds__(kConv34Threads)
+    k_conv34_pool(const bf16_t* __restrict__ a2, const bf16_t* __restrict__ W3,
+                  const float* __restrict__ b3, const bf16_t* __restrict__ W4,
+                  const float* __restrict__ b4, float* __restrict__ feat, int n_img) {
+  constexpr int NK = KDim<kC>::KP / 16, KP = KDim<kC>::KP, WROW = KP + 8;
+  __shared__ __align__(16) bf16_t s3[17 * 17 * kPixStride];
+  __shared__ __align__(16) bf16_t s4[8 * 8 * kC];
+  __shared__ __align__(16) bf16_t sw[2][kC * WROW];
+  __shared__ __align__(16) float sb[2 * kC];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int co = lane & 31, kh = 8 * (lane >> 5);
+  if (tid < 2 * kC) sb[tid] = tid < kC ? b3[tid] : b4[tid - kC];
+  for (int i = tid; i < 2 * kC * KP / 8; i += blockDim.x) {
+    const int l = i / (kC * KP / 8), j = i % (kC * KP / 8), r = j / (KP / 8), c8 = j % (KP / 8);
+    *reinterpret_cast<uint4*>(&sw[l][r * WROW + c8 * 8]) =
+        *reinterpret_cast<const uint4*>((l ? W4 : W3) + (size_t)r * KP + c8 * 8);
+  }
+  for (int i = tid; i < 33 * kPixStride / 8; i += blockDim.x) {  // row 0 and column 0
+    const int slot = i / (kPixStride / 8), q = i % (kPixStride / 8);
+    const int sl = slot < 17 ? slot : (slot - 16) * 17;
+    *reinterpret_cast<uint4*>(s3 + sl * kPixStride + 8 * q) = make_uint4(0u, 0u, 0u, 0u);
+  }
+  lds_barrier();
+  const bf16_t* wrow3 = &sw[0][co * WROW + kh];
+  const bf16_t* wrow4 = &sw[1][co * WROW + kh];
+  for (int n = blockIdx.x; n < n_img; n += gridDim.x) {
+    // conv3: tile `wave` (pixels 32 wave ..), patches from a2 in global memory
+    {
+      const int m = wave * 32 + (lane & 31), oy = m / 16, ox = m % 16;
+      uint4 pf[NK];
+#pragma unroll
+      for (int kc = 0; kc < NK; ++kc) pf[kc] = patch8<kC, 2, 32>(a2, true, n, oy, ox, kc * 16 + kh);
+      f32x16 acc = {};
+#pragma unroll
+      for (int kc = 0; kc < NK; ++kc)
+        acc = mfma_bf16(*reinterpret_cast<const uint4*>(wrow3 + kc * 16), pf[kc], acc);
+      store_relu_bf16(acc, sb, lane, s3 + ((oy + 1) * 17 + ox + 1) * kPixStride);
+    }
+    lds_barrier();
+    // conv4: two tiles; tap (ky, kx) of pixel (oy, ox) reads slot (2 oy + ky) 17 + 2 ox + kx
+    if (wave < 2) {
+      const int m = wave * 32 + (lane & 31), oy = m / 8, ox = m % 8;
+      const bf16_t* bp = s3 + (2 * oy * 17 + 2 * ox) * kPixStride + kh;
+      f32x16 acc = {};
+#pragma unroll
+      for (int kc = 0; kc < NK; ++kc) {
+        const int tap = kc / 2, ky = tap / 3, kx = tap % 3;
+        const uint4 a = *reinterpret_cast<const uint4*>(bp + (ky * 17 + kx) * kPixStride + 16 * (kc % 2));
+        acc = mfma_bf16(*reinterpret_cast<const uint4*>(wrow4 + kc * 16), a, acc);
+      }
+      store_relu_bf16(acc, sb + kC, lane, s4 + m * kC);
+    }
+    lds_barrier();
+    // pooling (one lane per channel); s4 is rewritten only after the next crop's
+    // first barrier, which these lanes reach after this loop
+    if (tid < kC) {
+      float sm = 0.0f, sc = 0.0f;
+      for (int p = 0; p < 64; ++p) {
+        const float v = bf2f(s4[p * kC + tid]);
+        sm += v;
+        const int y = p / 8, x = p % 8;
+        if (y >= 3 && y <= 4 && x >= 3 && x <= 4) sc += v;
+      }
+      feat[n * kFeat + tid] = sm / 64.0f;
+      feat[n * kFeat + kC + tid] = sc / 4.0f;
     }
   }
 }
@@ -519,6 +756,18 @@ void launch_forward(const Net& net, int n_crops, hipStream_t s) {
   hipLaunchKernelGGL((k_conv_fwd<32, 2, 16>), dim3(conv_fwd_blocks(n_crops, 8 * 8)), dim3(256), 0, s,
                      net.a[3], net.Wb[3], net.P.cb[3], net.a[4], n_crops);
   hipLaunchKernelGGL(k_pool_fwd, dim3(n_crops), dim3(kC), 0, s, net.a[4], n_crops, net.feat);
+}
+
+// Grid of the fused first two layers: one workgroup per work item when they are
+// few, else as many as are resident at once (three per CU, bound by the 45 KB band,
+// on 256 CUs), each taking its share of the items.
+static int conv12_blocks(int n_crops) { return std::max(1, std::min(n_crops * kConv12Items, 768)); }
+
+void launch_infer(const Net& net, int n_crops, hipStream_t s) {
+  hipLaunchKernelGGL(k_conv12_fwd, dim3(conv12_blocks(n_crops)), dim3(256), 0, s, net.crops,
+                     net.Wb[0], net.P.cb[0], net.Wb[1], net.P.cb[1], net.a[2], n_crops);
+  hipLaunchKernelGGL(k_conv34_pool, dim3(std::max(1, std::min(n_crops, 512))), dim3(kConv34Threads), 0, s,
+                     net.a[2], net.Wb[2], net.P.cb[2], net.Wb[3], net.P.cb[3], net.feat, n_crops);
 }
 
 void launch_predict(const Net& net, int n_crops, int n_mesh, const Pair* pairs, int n_pairs,

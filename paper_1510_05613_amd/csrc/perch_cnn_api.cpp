@@ -91,7 +91,7 @@ perch_status cnn_predict_on(perch_cnn* c, const uint16_t* crops, int n_crops, co
     return fail(PERCH_E_ARG, "batch (%d crops, %d pairs) above the network's capacity (%d, %d)",
                 n_crops, n_pairs, c ? c->max_crops : 0, c ? c->max_pairs : 0);
   c->net.crops = crops;
-  launch_forward(c->net, n_crops, s);
+  launch_infer(c->net, n_crops, s);
   launch_predict(c->net, n_crops, c->n_mesh, reinterpret_cast<const Pair*>(pairs), n_pairs, pred,
                  s);
   HIP_TRY(hipGetLastError());
@@ -275,6 +275,8 @@ static perch_status check_batch(perch_cnn* c, const uint16_t* crops, int32_t n_c
                                 const perch_cnn_pair* pairs, int32_t n_pairs) {
   if (!c || !crops || !pairs || n_crops < 1 || n_pairs < 1)
     return fail(PERCH_E_ARG, "empty or null batch");
+  if (reinterpret_cast<uintptr_t>(crops) % 16 != 0)
+    return fail(PERCH_E_ARG, "crops must be 16-byte aligned");
   if (n_crops > c->max_crops || n_pairs > c->max_pairs)
     return fail(PERCH_E_ARG, "batch (%d crops, %d pairs) above the network's capacity (%d, %d)",
                 n_crops, n_pairs, c->max_crops, c->max_pairs);
@@ -287,7 +289,7 @@ perch_status perch_cnn_predict(perch_cnn* c, const uint16_t* crops_dev, int32_t 
   if (st) return st;
   if (!pred_dev) return fail(PERCH_E_ARG, "null output");
   c->net.crops = crops_dev;
-  launch_forward(c->net, n_crops, c->stream);
+  launch_infer(c->net, n_crops, c->stream);
   launch_predict(c->net, n_crops, c->n_mesh, reinterpret_cast<const Pair*>(pairs_dev), n_pairs,
                  pred_dev, c->stream);
   HIP_TRY(hipGetLastError());

@@ -62,6 +62,8 @@ perch_status check_batch(perch_posenet* c, const uint16_t* crops, int32_t n_crop
                          const perch_posenet_pair* pairs, int32_t n_pairs) {
   if (!c || !crops || !pairs || n_crops < 1 || n_pairs < 1)
     return fail(PERCH_E_ARG, "empty or null batch");
+  if (reinterpret_cast<uintptr_t>(crops) % 16 != 0)
+    return fail(PERCH_E_ARG, "crops must be 16-byte aligned");
   if (n_crops > c->max_crops || n_pairs > c->max_pairs)
     return fail(PERCH_E_ARG, "batch (%d crops, %d pairs) above the network's capacity (%d, %d)",
                 n_crops, n_pairs, c->max_crops, c->max_pairs);
@@ -229,7 +231,7 @@ perch_status perch_posenet_predict(perch_posenet* c, const uint16_t* crops_dev, 
   if (st) return st;
   if (!out_dev) return fail(PERCH_E_ARG, "null output");
   c->net.crops = crops_dev;
-  launch_forward(c->net, n_crops, c->stream);
+  launch_infer(c->net, n_crops, c->stream);
   launch_pose_predict(c->net, c->P, c->n_yaw, n_crops, c->n_mesh,
                       reinterpret_cast<const PosePair*>(pairs_dev), n_pairs, out_dev, c->stream);
   HIP_TRY(hipGetLastError());
@@ -281,6 +283,8 @@ perch_status perch_posenet_estimate(perch_posenet* c, const uint16_t* crops_dev,
     return fail(PERCH_E_ARG, "%d anchors x %d meshes above the network's capacity (%d, %d)",
                 n_anchors, n_meshes, c->max_crops, c->max_pairs);
   if (!(spacing > 0.0f) || !(nms_m >= 0.0f)) return fail(PERCH_E_ARG, "bad spacing or nms_m");
+  if (reinterpret_cast<uintptr_t>(crops_dev) % 16 != 0)
+    return fail(PERCH_E_ARG, "crops must be 16-byte aligned");
   std::vector<PoseQuery> q(n_meshes);
   int total = 0;
   for (int u = 0; u < n_meshes; ++u) {
@@ -307,7 +311,7 @@ perch_status perch_posenet_estimate(perch_posenet* c, const uint16_t* crops_dev,
   HIP_TRY(hipMemcpyAsync(c->queries.p, q.data(), sizeof(PoseQuery) * n_meshes,
                          hipMemcpyHostToDevice, c->stream));
   c->net.crops = crops_dev;
-  launch_forward(c->net, n_anchors, c->stream);
+  launch_infer(c->net, n_anchors, c->stream);
   launch_pose_predict(c->net, c->P, c->n_yaw, n_anchors, c->n_mesh, c->pairs.as<PosePair>(), np,
                       c->out.as<float>(), c->stream);
   launch_pose_decode(c->out.as<float>(), c->n_yaw, n_anchors, c->anchors.as<float2>(), spacing,

@@ -109,6 +109,43 @@ def test_forward_matches_oracle():
     assert np.max(np.abs(got - want)) <= 1e-2 * (1.0 + np.max(np.abs(want)))
 
 
+def test_inference_trunk_matches_training_trunk_and_oracle():
+    """Inference runs conv1 + conv2 and conv3 + conv4 + pooling fused, grid-stride: on
+    100 crops (more conv1 + conv2 work items than resident workgroups) its
+    predictions give the loss that the training forward pass (unfused, every
+    activation kept) reports, and the first and last crops' predictions agree with
+    the oracle; misaligned crops are refused."""
+    sc = H.c1_scene(2)
+    ctx = perch.context_from_scene(sc)
+    ctx.set_parent([])
+    g = sc.grid
+    rng = np.random.default_rng(11)
+    n = 100
+    xy = np.stack([rng.uniform(g.x0, g.x0 + g.nx * g.step, n),
+                   rng.uniform(g.y0, g.y0 + g.ny * g.step, n)], 1).astype(np.float32)
+    crops = perch.Cnn.crops(ctx, xy)
+    mi = rng.integers(3, size=n)
+    th = rng.uniform(0, 2 * np.pi, size=n)
+    c, s_ = np.cos(th).astype(np.float32), np.sin(th).astype(np.float32)
+    pairs = perch.Cnn.pairs(np.arange(n), mi, c, s_)
+    target = rng.uniform(0, 5, size=n).astype(np.float32)
+    p = _params(7)
+    net = perch.Cnn(3, max_crops=128, max_pairs=128)
+    net.set_params(p)
+    pred = net.predict(crops, pairs).cpu().numpy().astype(np.float64)
+    loss, _ = net.gradients(crops, pairs, torch.as_tensor(target).cuda())
+    want_loss = float(np.mean((pred - target) ** 2))
+    assert abs(loss - want_loss) <= 1e-5 * want_loss, (loss, want_loss)
+    buf = torch.empty(crops.numel() + 1, dtype=crops.dtype, device=crops.device)
+    buf[1:] = crops.reshape(-1)
+    with pytest.raises(perch.PerchError):  # crops 2 bytes off a 16-byte boundary
+        net.predict(buf[1:].view(crops.shape), pairs)
+    sel = np.r_[0:4, n - 4:n]
+    pairs_np = np.stack([np.arange(len(sel)), mi[sel], c[sel], s_[sel]], 1)
+    want = cnn.forward(p, bf16_to_f64(crops)[sel], pairs_np)
+    assert np.max(np.abs(pred[sel] - want)) <= 1e-2 * (1.0 + np.max(np.abs(want)))
+
+
 def test_gradients_match_oracle():
     crops, pairs, pairs_np, target = _small_batch(1)
     p = _params(5)
