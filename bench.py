@@ -94,6 +94,17 @@ def valu_issue_frac(launch_s: float):
     return n * 4.0 / (1024 * 2.4e9 * launch_s)
 
 
+def copy_probe(mb: int) -> None:
+    """A plain device copy of `mb` MiB, whose FETCH_SIZE / WRITE_SIZE readings scale
+    the counters of the same run to bytes."""
+    import torch
+
+    a = torch.empty(mb << 20, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+
+
 def parse_args(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -886,6 +897,8 @@ def main(argv=None):
         return 0
     if args.learned_expansion:
         print(json.dumps({"learned_expansion": learned_expansion_leg()}), flush=True)
+        if args.copy_probe_mb:
+            copy_probe(args.copy_probe_mb)
         return 0
     if args.learned_only:
         out = {} if args.no_cnn_leg else {"cnn": cnn_leg()}
@@ -956,10 +969,7 @@ def main(argv=None):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     if args.copy_probe_mb:
-        a = torch.empty(args.copy_probe_mb << 20, dtype=torch.uint8, device="cuda")
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
+        copy_probe(args.copy_probe_mb)
 
     evals = n_step * args.steps
     launches = len(dev)

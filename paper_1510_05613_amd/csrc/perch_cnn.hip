@@ -129,25 +129,52 @@ __device__ __forceinline__ uint4 patch8(const bf16_t* __restrict__ in, bool vali
 // Forward tiles are computed transposed, out^T = W x patch^T: the weights are the
 // MFMA's A operand (lane l: W[l % 32][16 kc + 8 (l / 32) .. + 8]) and the im2col
 // patches its B operand (lane l: pixel l % 32), so lane l ends with pixel l % 32's
-// channels 8 g + 4 (l / 32) + i in accumulator element 4 g + i (g, i = 0..3), and
-// the bias, ReLU and bfloat16 rounding give four packed 8-byte stores per lane.
+// channels 8 g + 4 (l / 32) + i in accumulator element 4 g + i (g, i = 0..3).  The
+// accumulation chain starts from the bias, and the ReLU and bfloat16 rounding give
+// four packed 8-byte stores per lane.
 __device__ __forceinline__ unsigned pack_bf16(float lo, float hi) {
   typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
   const bf16x2_t v = {(__bf16)lo, (__bf16)hi};  // v_cvt_pk_bf16_f32: round to nearest even
   return __builtin_bit_cast(unsigned, v);
 }
 
-// dst[8 g + 4 (lane / 32) .. + 4] of the lane's pixel = bf16(relu(acc + bias)); bias
-// is a 16-byte aligned table of the 32 channel biases.
+// The bias of the lane's accumulator elements: acc[4 g + i] = b[8 g + 4 (lane / 32) + i]
+// (b: 16-byte aligned, 32 channel biases).
+__device__ __forceinline__ f32x16 bias_acc(const float* b, int lane) {
+  const int h4 = 4 * (lane >> 5);
+  f32x16 a;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const float4 v = *reinterpret_cast<const float4*>(b + 8 * g + h4);
+    a[4 * g] = v.x;
+    a[4 * g + 1] = v.y;
+    a[4 * g + 2] = v.z;
+    a[4 * g + 3] = v.w;
+  }
+  return a;
+}
+
+// bf16(relu(lo)) | bf16(relu(hi)) << 16: the ReLU after the rounding, as a signed
+// 16-bit max with 0 (a negative value, -0 included, has its sign bit set), gives
+// the same bits as rounding the ReLU's result.
+__device__ __forceinline__ unsigned pack_relu_bf16(float lo, float hi) {
+  typedef short short2_t __attribute__((ext_vector_type(2)));
+  typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+  typedef float float2_t __attribute__((ext_vector_type(2)));
+  const float2_t f = {lo, hi};
+  const short2_t v = __builtin_bit_cast(short2_t, __builtin_convertvector(f, bf16x2_t));
+  const short2_t z = {0, 0};
+  return __builtin_bit_cast(unsigned, __builtin_elementwise_max(v, z));
+}
+
+// dst[8 g + 4 (lane / 32) .. + 4] of the lane's pixel = bf16(relu(acc)).
 template <typename Ptr>
-__device__ __forceinline__ void store_relu_bf16(const f32x16& acc, const float* bias, int lane,
-                                                Ptr dst) {
+__device__ __forceinline__ void store_relu_bf16(const f32x16& acc, int lane, Ptr dst) {
   const int h4 = 4 * (lane >> 5);
 #pragma unroll
   for (int g = 0; g < 4; ++g) {
-    const float4 b = *reinterpret_cast<const float4*>(bias + 8 * g + h4);
-    const uint2 v = make_uint2(pack_bf16(fmaxf(acc[4 * g] + b.x, 0.0f), fmaxf(acc[4 * g + 1] + b.y, 0.0f)),
-                               pack_bf16(fmaxf(acc[4 * g + 2] + b.z, 0.0f), fmaxf(acc[4 * g + 3] + b.w, 0.0f)));
+    const uint2 v = make_uint2(pack_relu_bf16(acc[4 * g], acc[4 * g + 1]),
+                               pack_relu_bf16(acc[4 * g + 2], acc[4 * g + 3]));
     *reinterpret_cast<uint2*>(dst + 8 * g + h4) = v;
   }
 }
@@ -197,11 +224,11 @@ __global__ void __launch_bounds__(256)
     const int m = t * 32 + (lane & 31);
     const bool mv = m < total;
     const int n = m / NPIX, pix = m % NPIX, oy = pix / HO, ox = pix % HO;
-    f32x16 acc = {};
+    f32x16 acc = bias_acc(sb, lane);
 #pragma unroll
     for (int kc = 0; kc < NK; ++kc)
       acc = mfma_bf16(wf[kc], patch8<CIN, S, HIN>(in, mv, n, oy, ox, kc * 16 + kh), acc);
-    if (mv) store_relu_bf16(acc, sb, lane, out + (size_t)m * kC);
+    if (mv) store_relu_bf16(acc, lane, out + (size_t)m * kC);
   }
 }
 
@@ -237,10 +264,14 @@ __global__ void __launch_bounds__(256)
   constexpr int IN_U4 = kInRows * kCrop * 2 * 2 / 16;  // 16-byte pieces of an item's input
   __shared__ __align__(16) unsigned sin[kInRows * kInSlots];  // two bfloat16 channels per slot
   __shared__ __align__(16) bf16_t band[kBandIn * kBandSlots * kPixStride];
-  __shared__ __align__(16) float sb[2 * kC];
+  __shared__ __align__(16) float sb[kC];  // conv2's bias
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int co = lane & 31, kh = 8 * (lane >> 5), h = lane >> 5;
-  if (tid < 2 * kC) sb[tid] = tid < kC ? b1[tid] : b2[tid - kC];
+  const int tap_base = h ? kInSlots + 1 : 0, tap_2 = h ? kInSlots - 1 : 2;
+  if (tid < kC) sb[tid] = b2[tid];
+  f32x16 bias1;  // conv1's bias, kept in registers for its eighteen tiles per item
+#pragma unroll
+  for (int e = 0; e < 16; ++e) bias1[e] = b1[8 * (e >> 2) + 4 * h + (e & 3)];
   for (int r = tid; r < kInRows; r += blockDim.x) sin[r * kInSlots + 3] = sin[r * kInSlots + 68] = 0u;
   for (int i = tid; i < kBandIn * kPixStride / 8; i += blockDim.x)  // slot 0 of every band row
     *reinterpret_cast<uint4*>(band + (i / (kPixStride / 8)) * kBandSlots * kPixStride +
@@ -272,6 +303,8 @@ __global__ void __launch_bounds__(256)
   for (int kc = 0; kc < NK1; ++kc) settle(w1[kc]);
 #pragma unroll
   for (int kc = 0; kc < NK2; ++kc) settle(w2[kc]);
+#pragma unroll
+  for (int e = 0; e < 16; ++e) asm volatile("" ::"v"(bias1[e]));
   // the input of the next item goes to LDS during conv2 (conv1 is done with it),
   // long after its load was issued
   auto stage = [&]() {
@@ -295,18 +328,18 @@ __global__ void __launch_bounds__(256)
           *reinterpret_cast<uint2*>(dst + 8 * g + 4 * h) = make_uint2(0u, 0u);
         continue;
       }
-      // taps (ky, kx) of input (y0 + yl + ky - 1, ox + kx - 1): sin row yl + ky, slot ox + kx + 3
+      // tap (ky, kx) of input (y0 + yl + ky - 1, ox + kx - 1): sin row yl + ky, slot
+      // ox + kx + 3.  k = 2 tap + channel: lanes 0-31 hold taps 0-3 and 8 (offsets
+      // 0, 1, 2, 72, 146), lanes 32-63 taps 4-7 (73, 74, 144, 145)
       const unsigned* sp = sin + yl * kInSlots + ox + 3;
-      const unsigned t0 = sp[0], t1 = sp[1], t2 = sp[2], t3 = sp[kInSlots],
-                     t4 = sp[kInSlots + 1], t5 = sp[kInSlots + 2], t6 = sp[2 * kInSlots],
-                     t7 = sp[2 * kInSlots + 1], t8 = sp[2 * kInSlots + 2];
-      // k = 2 tap + channel: lanes 0-31 hold taps 0-3 and 8, lanes 32-63 taps 4-7
-      const uint4 p0 = h ? make_uint4(t4, t5, t6, t7) : make_uint4(t0, t1, t2, t3);
+      const unsigned* sq = sp + tap_base;
+      const uint4 p0 = make_uint4(sq[0], sq[1], sq[tap_2], sq[kInSlots]);
+      const unsigned t8 = sp[2 * kInSlots + 2];
       const uint4 p1 = make_uint4(h ? 0u : t8, 0u, 0u, 0u);
-      f32x16 acc = {};
+      f32x16 acc = bias1;
       acc = mfma_bf16(w1[0], p0, acc);
       acc = mfma_bf16(w1[1], p1, acc);
-      store_relu_bf16(acc, sb, lane, dst);
+      store_relu_bf16(acc, lane, dst);
     }
     lds_barrier();
     stage();
@@ -315,7 +348,7 @@ __global__ void __launch_bounds__(256)
     {
       const int oy = r0 + wave, ox = lane & 31;
       const bf16_t* bp = band + (2 * wave * kBandSlots + 2 * ox) * kPixStride + kh;
-      f32x16 acc = {};
+      f32x16 acc = bias_acc(sb, lane);
 #pragma unroll
       for (int kc = 0; kc < NK2; ++kc) {
         const int tap = kc / 2, ky = tap / 3, kx = tap % 3;
@@ -323,7 +356,7 @@ __global__ void __launch_bounds__(256)
             bp + (ky * kBandSlots + kx) * kPixStride + 16 * (kc % 2));
         acc = mfma_bf16(w2[kc], a, acc);
       }
-      store_relu_bf16(acc, sb + kC, lane, out + (((size_t)n * H2 + oy) * H2 + ox) * kC);
+      store_relu_bf16(acc, lane, out + (((size_t)n * H2 + oy) * H2 + ox) * kC);
     }
   }
 }
@@ -370,25 +403,25 @@ __global__ void __launch_bounds__(kConv34Threads)
       uint4 pf[NK];
 #pragma unroll
       for (int kc = 0; kc < NK; ++kc) pf[kc] = patch8<kC, 2, 32>(a2, true, n, oy, ox, kc * 16 + kh);
-      f32x16 acc = {};
+      f32x16 acc = bias_acc(sb, lane);
 #pragma unroll
       for (int kc = 0; kc < NK; ++kc)
         acc = mfma_bf16(*reinterpret_cast<const uint4*>(wrow3 + kc * 16), pf[kc], acc);
-      store_relu_bf16(acc, sb, lane, s3 + ((oy + 1) * 17 + ox + 1) * kPixStride);
+      store_relu_bf16(acc, lane, s3 + ((oy + 1) * 17 + ox + 1) * kPixStride);
     }
     lds_barrier();
     // conv4: two tiles; tap (ky, kx) of pixel (oy, ox) reads slot (2 oy + ky) 17 + 2 ox + kx
     if (wave < 2) {
       const int m = wave * 32 + (lane & 31), oy = m / 8, ox = m % 8;
       const bf16_t* bp = s3 + (2 * oy * 17 + 2 * ox) * kPixStride + kh;
-      f32x16 acc = {};
+      f32x16 acc = bias_acc(sb + kC, lane);
 #pragma unroll
       for (int kc = 0; kc < NK; ++kc) {
         const int tap = kc / 2, ky = tap / 3, kx = tap % 3;
         const uint4 a = *reinterpret_cast<const uint4*>(bp + (ky * 17 + kx) * kPixStride + 16 * (kc % 2));
         acc = mfma_bf16(*reinterpret_cast<const uint4*>(wrow4 + kc * 16), a, acc);
       }
-      store_relu_bf16(acc, sb + kC, lane, s4 + m * kC);
+      store_relu_bf16(acc, lane, s4 + m * kC);
     }
     lds_barrier();
     // pooling (one lane per channel); s4 is rewritten only after the next crop's
