@@ -333,8 +333,8 @@ perch_status perch_cnn_set_crop_step(perch_cnn* net, int32_t step);
 perch_status perch_cnn_set_params(perch_cnn* net, const float* params, int64_t n);
 perch_status perch_cnn_get_params(perch_cnn* net, float* params, int64_t n);
 /* Crops of the context's current parent (perch_set_parent) for n table points
- * xy (host, n x 2 metres): device output n x 64 x 64 x 2 bfloat16 (NHWC).
- * Synchronous. */
+ * xy (host, n x 2 metres): device output n x 64 x 64 x 2 bfloat16 (NHWC, 16-byte
+ * aligned: PERCH_E_ARG otherwise).  Synchronous. */
 perch_status perch_cnn_crops(perch_ctx* ctx, const float* xy, int32_t n, uint16_t* crops_dev);
 /* Predictions (device, n_pairs floats) of log(1 + cost); a pair whose crop or
  * mesh index is out of range gets NaN (and is ignored by training).  crops_dev

@@ -16,6 +16,9 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
                 "-fhip-fp32-correctly-rounded-divide-sqrt", "-Xclang", "-target-feature",
                 "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-result"]
+# The network's kernels keep MFMA accumulators in ordinary VGPRs, so the bias can
+# seed the accumulation and the epilogue reads the results without AGPR moves.
+CNN_FLAGS = DEVICE_FLAGS + ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]
 # roctx ranges (search expansions, parent materialisation, successor launches) for
 # rocprofv3 --marker-trace
 LINK_FLAGS = ["-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
@@ -26,7 +29,7 @@ HOST_FLAGS = ["--offload-arch=gfx950", "-O2", "-std=c++17", "-fPIC", "-Wall", "-
 
 def build(verbose: bool = False, jobs: int | None = None) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    units = (("perch_kernels.hip", DEVICE_FLAGS), ("perch_cnn.hip", DEVICE_FLAGS),
+    units = (("perch_kernels.hip", DEVICE_FLAGS), ("perch_cnn.hip", CNN_FLAGS),
              ("perch_select.hip", DEVICE_FLAGS), ("perch_noalloc.hip", DEVICE_FLAGS),
              ("perch_posenet.hip", DEVICE_FLAGS), ("perch_posenet_api.cpp", HOST_FLAGS),
              ("perch_cnn_api.cpp", HOST_FLAGS), ("perch_api.cpp", HOST_FLAGS),

@@ -50,12 +50,15 @@ __device__ __forceinline__ int acc_row(int e, int lane) {
 // channel 0 the observed depth, channel 1 the parent composite, both as (z - zref)
 // / 0.25 clipped to [-1, 1], +1 where there is no return / no parent point or
 // outside the image.
-__global__ void k_crops(const float* obs, const unsigned* pdepth, int W, int H,
-                        const CropDesc* desc, int n, bf16_t* out) {
+__global__ void __launch_bounds__(256)
+    k_crops(const float* obs, const unsigned* pdepth, int W, int H, const CropDesc* desc, int n,
+            bf16_t* out) {
   const int c = blockIdx.x;
   if (c >= n) return;
   const CropDesc d = desc[c];
   const int st = d.step > 1 ? d.step : 1;
+  unsigned* o = reinterpret_cast<unsigned*>(out) + (size_t)c * kCrop * kCrop;  // both channels
+#pragma unroll 4
   for (int t = threadIdx.x; t < kCrop * kCrop; t += blockDim.x) {
     const int cy = t / kCrop, cx = t % kCrop;
     const int u = d.u0 + (cx - kCrop / 2) * st, v = d.v0 + (cy - kCrop / 2) * st;
@@ -68,8 +71,7 @@ __global__ void k_crops(const float* obs, const unsigned* pdepth, int W, int H,
         if (k != 0x7f800000u) b = fminf(1.0f, fmaxf(-1.0f, (__uint_as_float(k) - d.zref) * 4.0f));
       }
     }
-    out[((size_t)c * kCrop * kCrop + t) * 2 + 0] = f2bf(a);
-    out[((size_t)c * kCrop * kCrop + t) * 2 + 1] = f2bf(b);
+    o[t] = (unsigned)f2bf(a) | ((unsigned)f2bf(b) << 16);
   }
 }
 

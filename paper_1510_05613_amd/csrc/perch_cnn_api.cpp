@@ -233,6 +233,8 @@ perch_status perch_cnn_get_params(perch_cnn* c, float* host, int64_t n) {
 
 perch_status perch_cnn_crops(perch_ctx* ctx, const float* xy, int32_t n, uint16_t* crops_dev) {
   if (!ctx || n < 0 || (n > 0 && (!xy || !crops_dev))) return fail(PERCH_E_ARG, "bad arguments");
+  if (reinterpret_cast<uintptr_t>(crops_dev) % 16 != 0)
+    return fail(PERCH_E_ARG, "crops must be 16-byte aligned");
   if (!ctx->has_obs) return fail(PERCH_E_STATE, "perch_set_observation not called");
   if (ctx->parent_j < 0) return fail(PERCH_E_STATE, "perch_set_parent not called");
   if (n == 0) return PERCH_OK;
