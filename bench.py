@@ -528,7 +528,7 @@ def cnn_leg(sizes=(64, 256, 1024, 4096), reps: int = 10) -> dict:
     return {"bound": "mfma", "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s", "dtype": "bf16",
             "fwd_flops_per_crop": CNN_FWD_FLOPS, "train_flops_per_crop": CNN_TRAIN_FLOPS,
             "sizes": rows,
-            "note": "an expansion ranks 64-128 crops (160x120) or up to 256 (640x480)"}
+            "note": "a learned expansion runs one crop per pose cell: 144 (160x120), 2,500 (640x480)"}
 
 
 def learned_expansion_leg(reps: int = 20) -> dict:

@@ -50,7 +50,7 @@ __device__ __forceinline__ int acc_row(int e, int lane) {
 // channel 0 the observed depth, channel 1 the parent composite, both as (z - zref)
 // / 0.25 clipped to [-1, 1], +1 where there is no return / no parent point or
 // outside the image.
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(1024)
     k_crops(const float* obs, const unsigned* pdepth, int W, int H, const CropDesc* desc, int n,
             bf16_t* out) {
   const int c = blockIdx.x;
@@ -768,7 +768,9 @@ __global__ void k_pack(const float* master, int K, int KP, bf16_t* Wb) {
 
 void launch_crops(const float* obs, const unsigned* pdepth, int W, int H, const CropDesc* desc,
                   int n, bf16_t* out, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_crops, dim3(n), dim3(256), 0, s, obs, pdepth, W, H, desc, n, out);
+  // 1,024 threads per crop: a few samples each, so that even a small batch keeps
+  // enough loads in flight
+  if (n > 0) hipLaunchKernelGGL(k_crops, dim3(n), dim3(1024), 0, s, obs, pdepth, W, H, desc, n, out);
 }
 
 static int conv_blocks(int n_img, int npix) { return (n_img * npix + 127) / 128; }
