@@ -459,12 +459,14 @@ __global__ void __launch_bounds__(256)
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int total = n_img * NPIX;
-  const int m0 = (blockIdx.x * 4 + wave) * 32;
-  if (m0 >= total) return;
+  const int n_tiles = (total + 31) / 32;
+  const int kh = 8 * (lane >> 5);
+  // tiles grid-stride: the weights staged above serve every tile of the workgroup
+  for (int tile = blockIdx.x * 4 + wave; tile < n_tiles; tile += gridDim.x * 4) {
+  const int m0 = tile * 32;
   const int m = m0 + (lane & 31);
   const bool mv = m < total;
   const int n = m / NPIX, pix = m % NPIX, iy = pix / HIN, ix = pix % HIN;
-  const int kh = 8 * (lane >> 5);
   f32x16 acc = {};
   for (int kc = 0; kc < K / 16; ++kc) {
     const int k0 = kc * 16 + kh;
@@ -486,6 +488,7 @@ __global__ void __launch_bounds__(256)
       din[(size_t)mm * kC + ci] = f2bf(on ? acc[e] : 0.0f);
     }
   }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -493,17 +496,19 @@ __global__ void __launch_bounds__(256)
 // ---------------------------------------------------------------------------
 
 // Workgroup (kt, chunk): k columns [32 kt, 32 kt + 32), output pixels
-// [chunk * 64 * PW, ...); each wave reduces PW groups of 16 pixels with MFMAs and
-// adds its 32 x 32 partial to dW with atomics.
-template <int CIN, int S, int HIN, int PW>
+// [chunk * 64 * pw, ...); each wave reduces pw groups of 16 pixels with MFMAs and
+// adds its 32 x 32 partial to dW with atomics (pw is chosen so that the atomics
+// stay few).  The kt = 0 workgroups also sum the pre-activation gradients they load
+// into the bias gradient db[co] = sum_m dpre[m][co].
+template <int CIN, int S, int HIN>
 __global__ void __launch_bounds__(256)
     k_conv_wgrad(const bf16_t* __restrict__ dpre, const bf16_t* __restrict__ in,
-                 float* __restrict__ dW, int n_img) {
+                 float* __restrict__ dW, float* __restrict__ db, int n_img, int pw) {
   constexpr int HO = HIN / S, NPIX = HO * HO, K = 9 * CIN;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int total = n_img * NPIX;
   const int kt = blockIdx.x;
-  const int pbase = (blockIdx.y * 4 + wave) * 16 * PW;
+  const int pbase = (blockIdx.y * 4 + wave) * 16 * pw;
   if (pbase >= total) return;
   const int co = lane & 31;
   const int kk = kt * 32 + (lane & 31);
@@ -511,7 +516,9 @@ __global__ void __launch_bounds__(256)
   const int ky = tap / 3, kx = tap % 3;
   const int ph = 8 * (lane >> 5);
   f32x16 acc = {};
-  for (int g = 0; g < PW; ++g) {
+  float bsum = 0.0f;
+  const int n_groups = min(pw, (total - pbase + 15) / 16);
+  for (int g = 0; g < n_groups; ++g) {
     const int p0 = pbase + g * 16 + ph;
     unsigned short av[8], bv[8];
 #pragma unroll
@@ -529,6 +536,9 @@ __global__ void __launch_bounds__(256)
         }
       }
     }
+    if (kt == 0)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) bsum += bf2f(av[q]);
     uint4 a, b;
     a.x = av[0] | ((unsigned)av[1] << 16); a.y = av[2] | ((unsigned)av[3] << 16);
     a.z = av[4] | ((unsigned)av[5] << 16); a.w = av[6] | ((unsigned)av[7] << 16);
@@ -536,26 +546,15 @@ __global__ void __launch_bounds__(256)
     b.z = bv[4] | ((unsigned)bv[5] << 16); b.w = bv[6] | ((unsigned)bv[7] << 16);
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(a), as_bf16x8(b), acc, 0, 0, 0);
   }
+  if (kt == 0) {
+    bsum += __shfl_xor(bsum, 32);  // the two pixel halves of channel co
+    if (lane < 32) atomicAdd(&db[co], bsum);
+  }
   // D[row = co][col = k]
   const int col = kt * 32 + (lane & 31);
   if (col < K) {
 #pragma unroll
     for (int e = 0; e < 16; ++e) atomicAdd(&dW[acc_row(e, lane) * K + col], acc[e]);
-  }
-}
-
-// db[co] += sum_m dpre[m][co]
-__global__ void k_bias_grad(const bf16_t* dpre, int total, float* db) {
-  __shared__ float part[256];
-  const int co = threadIdx.x & 31, grp = threadIdx.x >> 5;
-  float s = 0.0f;
-  for (int m = blockIdx.x * 8 + grp; m < total; m += gridDim.x * 8) s += bf2f(dpre[(size_t)m * kC + co]);
-  part[threadIdx.x] = s;
-  __syncthreads();
-  if (threadIdx.x < 32) {
-    float t = 0.0f;
-    for (int g = 0; g < 8; ++g) t += part[g * 32 + threadIdx.x];
-    atomicAdd(&db[threadIdx.x], t);
   }
 }
 
@@ -773,7 +772,11 @@ void launch_crops(const float* obs, const unsigned* pdepth, int W, int H, const 
   if (n > 0) hipLaunchKernelGGL(k_crops, dim3(n), dim3(1024), 0, s, obs, pdepth, W, H, desc, n, out);
 }
 
-static int conv_blocks(int n_img, int npix) { return (n_img * npix + 127) / 128; }
+// Input-gradient grid: one workgroup per four 32-pixel tiles up to 2,048 workgroups,
+// which then take several tiles each (each workgroup stages the weights once).
+static int dgrad_blocks(int n_img, int npix) {
+  return std::max(1, std::min(2048, (n_img * npix + 127) / 128));
+}
 
 // Forward grid: about eight 32-pixel tiles per wave (the weight fragments a wave
 // loads are reused across them), at least 512 workgroups while there are tiles.
@@ -819,12 +822,14 @@ void launch_predict(const Net& net, int n_crops, int n_mesh, const Pair* pairs, 
 template <int CIN, int S, int HIN>
 static void wgrad(const bf16_t* dpre, const bf16_t* in, float* dW, float* db, int n_img,
                   hipStream_t s) {
-  constexpr int HO = HIN / S, K = 9 * CIN, PW = 8;
+  constexpr int HO = HIN / S, K = 9 * CIN, KT = (K + 31) / 32;
   const int total = n_img * HO * HO;
-  const dim3 grid((K + 31) / 32, (total + 64 * PW - 1) / (64 * PW));
-  hipLaunchKernelGGL((k_conv_wgrad<CIN, S, HIN, PW>), grid, dim3(256), 0, s, dpre, in, dW, n_img);
-  const int bb = std::min(1024, (total + 7) / 8);
-  hipLaunchKernelGGL(k_bias_grad, dim3(bb), dim3(256), 0, s, dpre, total, db);
+  // about 2,048 workgroups over the k columns, at least 8 pixel groups per wave
+  const int gy = std::max(1, 2048 / KT);
+  const int pw = std::max(8, (total + 64 * gy - 1) / (64 * gy));
+  const dim3 grid(KT, (total + 64 * pw - 1) / (64 * pw));
+  hipLaunchKernelGGL((k_conv_wgrad<CIN, S, HIN>), grid, dim3(256), 0, s, dpre, in, dW, db, n_img,
+                     pw);
 }
 
 void launch_backward(const Net& net, int n_crops, int n_mesh, const Pair* pairs,
@@ -838,13 +843,13 @@ void launch_trunk_backward(const Net& net, int n_crops, hipStream_t s) {
   hipLaunchKernelGGL(k_pool_bwd, dim3(n_crops), dim3(256), 0, s, net.dfeat, net.a[4], n_crops,
                      net.d[4]);
   wgrad<32, 2, 16>(net.d[4], net.a[3], net.G.cW[3], net.G.cb[3], n_crops, s);
-  hipLaunchKernelGGL((k_conv_dgrad<2, 16>), dim3(conv_blocks(n_crops, 16 * 16)), dim3(256), 0, s,
+  hipLaunchKernelGGL((k_conv_dgrad<2, 16>), dim3(dgrad_blocks(n_crops, 16 * 16)), dim3(256), 0, s,
                      net.d[4], net.Wb[3], net.a[3], net.d[3], n_crops);
   wgrad<32, 2, 32>(net.d[3], net.a[2], net.G.cW[2], net.G.cb[2], n_crops, s);
-  hipLaunchKernelGGL((k_conv_dgrad<2, 32>), dim3(conv_blocks(n_crops, 32 * 32)), dim3(256), 0, s,
+  hipLaunchKernelGGL((k_conv_dgrad<2, 32>), dim3(dgrad_blocks(n_crops, 32 * 32)), dim3(256), 0, s,
                      net.d[3], net.Wb[2], net.a[2], net.d[2], n_crops);
   wgrad<32, 2, 64>(net.d[2], net.a[1], net.G.cW[1], net.G.cb[1], n_crops, s);
-  hipLaunchKernelGGL((k_conv_dgrad<2, 64>), dim3(conv_blocks(n_crops, 64 * 64)), dim3(256), 0, s,
+  hipLaunchKernelGGL((k_conv_dgrad<2, 64>), dim3(dgrad_blocks(n_crops, 64 * 64)), dim3(256), 0, s,
                      net.d[2], net.Wb[1], net.a[1], net.d[1], n_crops);
   wgrad<2, 1, 64>(net.d[1], net.crops, net.G.cW[0], net.G.cb[0], n_crops, s);
 }
