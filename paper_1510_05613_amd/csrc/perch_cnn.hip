@@ -446,11 +446,21 @@ __global__ void __launch_bounds__(kConv34Threads)
 // convolution input gradient: din[m][ci] = mask(m, ci) sum_{tap, co} dpre[o(m,tap)][co] W[co][tap][ci]
 // ---------------------------------------------------------------------------
 
+// The layers with an input gradient have stride 2, so an input pixel (iy, ix)
+// receives from tap (ky, kx) only when iy + 1 - ky and ix + 1 - kx are even: one
+// tap row for even iy (ky = 1), two for odd iy (ky = 0, 2), and the same for the
+// columns.  Tiles therefore hold 32 pixels of one parity class (iy % 2, ix % 2) of
+// one image, at (iy, ix) = (2 a + py, 2 b + px) for 32 consecutive (a, b), and run
+// the MFMAs of their 1, 2 or 4 taps only (the taps that only add zeros are left out;
+// the sums keep the increasing tap order).
 template <int S, int HIN>
 __global__ void __launch_bounds__(256)
     k_conv_dgrad(const bf16_t* __restrict__ dpre, const bf16_t* __restrict__ Wb,
                  const bf16_t* __restrict__ act_in, bf16_t* __restrict__ din, int n_img) {
-  constexpr int HO = HIN / S, NPIX = HIN * HIN, K = 9 * kC, ROW = K + 8;
+  static_assert(S == 2, "input gradients of stride-2 layers only");
+  constexpr int HO = HIN / 2, CLS = HO * HO, K = 9 * kC, ROW = K + 8;
+  constexpr int TPC = CLS / 32;  // tiles per (image, parity class)
+  static_assert(CLS % 32 == 0, "a parity class holds whole tiles");
   __shared__ __align__(16) bf16_t wt[kC * ROW];  // wt[ci][tap * 32 + co]
   for (int i = threadIdx.x; i < kC * K; i += blockDim.x) {
     const int co = i / K, r = i % K, tap = r / kC, ci = r % kC;
@@ -458,36 +468,38 @@ __global__ void __launch_bounds__(256)
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int total = n_img * NPIX;
-  const int n_tiles = (total + 31) / 32;
-  const int kh = 8 * (lane >> 5);
+  const int n_tiles = n_img * 4 * TPC;
+  const int kh = 8 * (lane >> 5), ci = lane & 31;
   // tiles grid-stride: the weights staged above serve every tile of the workgroup
   for (int tile = blockIdx.x * 4 + wave; tile < n_tiles; tile += gridDim.x * 4) {
-  const int m0 = tile * 32;
-  const int m = m0 + (lane & 31);
-  const bool mv = m < total;
-  const int n = m / NPIX, pix = m % NPIX, iy = pix / HIN, ix = pix % HIN;
-  f32x16 acc = {};
-  for (int kc = 0; kc < K / 16; ++kc) {
-    const int k0 = kc * 16 + kh;
-    const int tap = k0 / kC, co0 = k0 % kC;
-    const int ny = iy + 1 - tap / 3, nx = ix + 1 - tap % 3;  // = o * S when o is a tap source
-    uint4 a = make_uint4(0u, 0u, 0u, 0u);
-    if (mv && ny >= 0 && nx >= 0 && ny % S == 0 && nx % S == 0 && ny / S < HO && nx / S < HO)
-      a = *reinterpret_cast<const uint4*>(dpre +
-                                          (((size_t)n * HO + ny / S) * HO + nx / S) * kC + co0);
-    const uint4 b = *reinterpret_cast<const uint4*>(wt + (lane & 31) * ROW + k0);
-    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(a), as_bf16x8(b), acc, 0, 0, 0);
-  }
-  const int ci = lane & 31;
+    const int n = tile / (4 * TPC), cls = (tile / TPC) % 4, t = tile % TPC;
+    const int py = cls >> 1, px = cls & 1;
+    const int q = t * 32 + (lane & 31), a = q / HO, b = q % HO;
+    f32x16 acc = {};
+    for (int ky = py ? 0 : 1; ky <= (py ? 2 : 1); ky += 2) {
+      const int oy = a + (py + 1 - ky) / 2;  // (iy + 1 - ky) / 2
+      for (int kx = px ? 0 : 1; kx <= (px ? 2 : 1); kx += 2) {
+        const int ox = b + (px + 1 - kx) / 2;
+        const bool ok = oy < HO && ox < HO;  // both are >= 0
+        const int tap = ky * 3 + kx;
 #pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    const int mm = m0 + acc_row(e, lane);
-    if (mm < total) {
-      const bool on = bf2f(act_in[(size_t)mm * kC + ci]) > 0.0f;  // ReLU of the previous layer
-      din[(size_t)mm * kC + ci] = f2bf(on ? acc[e] : 0.0f);
+        for (int h = 0; h < 2; ++h) {
+          const int co0 = 16 * h + kh;
+          uint4 av = make_uint4(0u, 0u, 0u, 0u);
+          if (ok)
+            av = *reinterpret_cast<const uint4*>(dpre + (((size_t)n * HO + oy) * HO + ox) * kC + co0);
+          const uint4 bv = *reinterpret_cast<const uint4*>(wt + ci * ROW + tap * kC + co0);
+          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(av), as_bf16x8(bv), acc, 0, 0, 0);
+        }
+      }
     }
-  }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int qq = t * 32 + acc_row(e, lane);
+      const size_t mm = ((size_t)n * HIN + 2 * (qq / HO) + py) * HIN + 2 * (qq % HO) + px;
+      const bool on = bf2f(act_in[mm * kC + ci]) > 0.0f;  // ReLU of the previous layer
+      din[mm * kC + ci] = f2bf(on ? acc[e] : 0.0f);
+    }
   }
 }
 
