@@ -452,6 +452,7 @@ def cpu_baseline(args, work_gpu):
 
     n_done, t_used = rate(cores, args.cpu_seconds, 12345)
     n1, t1 = rate(1, args.cpu_seconds / 2, 54321)
+    network = network_oracle_rate()
     model = ""
     try:
         with open("/proc/cpuinfo") as f:
@@ -467,7 +468,33 @@ def cpu_baseline(args, work_gpu):
             "sample": (f"{n_done} successors drawn uniformly (level-weighted) from the step's "
                        f"{int(sizes.sum())}, scene regenerated with the oracle renderer, "
                        f"{t_used:.1f} s on {cores} threads; {n1} more in {t1:.1f} s on one "
-                       f"thread")}
+                       f"thread"),
+            "network": network}
+
+
+def network_oracle_rate(n: int = 64) -> dict:
+    """The learned ranker's forward pass as the oracle computes it (FP64 numpy, the
+    BLAS library's threads) on n random crops with one pair each, next to the GPU's
+    inference pass."""
+    from oracle import cnn as ocnn
+
+    p = ocnn.init_params(12, 0)
+    rng = np.random.default_rng(7)
+    crops = rng.uniform(-1.0, 1.0, size=(n, 64, 64, 2))
+    pairs = np.stack([np.arange(n), np.arange(n) % 12, np.ones(n), np.zeros(n)], 1)
+    t0 = time.perf_counter()
+    ocnn.forward(p, crops, pairs)
+    t = time.perf_counter() - t0
+    threads = None
+    try:
+        import threadpoolctl
+
+        threads = max((d.get("num_threads", 0) for d in threadpoolctl.threadpool_info()
+                       if d.get("user_api") == "blas"), default=None)
+    except Exception:
+        pass
+    return {"value": round(n / t, 1), "unit": "crops/s", "kind": "oracle", "blas_threads": threads,
+            "sample": f"{n} random 64 x 64 x 2 crops, one pair each, in {t:.2f} s"}
 
 
 # Algorithmic FLOPs of the network per 64 x 64 crop (multiply-adds counted twice;
