@@ -350,9 +350,11 @@ perch_status perch_cnn_predict(perch_cnn* net, const uint16_t* crops_dev, int32_
  * prediction, equal predictions (-0 equal to +0) in increasing child index: the
  * first k of a stable sort.  Children of a mesh position u with allow_host[u] == 0
  * rank as +inf.  Needs 1 <= n_meshes <= 8 and 1 <= k <= n_meshes * n_poses.  Up
- * to 8192 children and k <= 1024 one workgroup selects them; otherwise a device
- * radix sort runs in temporary memory the context keeps.  Synchronous on the
- * context's stream. */
+ * to 8192 children and k <= 1024 one workgroup selects them; beyond 8192 children,
+ * while the 8192-child chunks' k candidates number at most 8192, each chunk's
+ * workgroup selects its k best and one more workgroup merges them; otherwise a
+ * device radix sort runs.  Both use temporary memory the context keeps.
+ * Synchronous on the context's stream. */
 perch_status perch_rank_children(perch_ctx* ctx, const float* pred_dev, int32_t n_poses,
                                  int32_t n_meshes, const int32_t* allow_host, int32_t k,
                                  const int32_t* mesh_ids_dev, const int32_t* pose_ids_dev,

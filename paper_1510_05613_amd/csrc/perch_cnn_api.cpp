@@ -109,6 +109,12 @@ perch_status rank_children(perch_ctx* c, const float* pred, int n_poses, int n_m
     return PERCH_OK;
   const int n = n_poses * n_meshes;
   DevBuf &d_keys = c->learned_bufs[6], &d_idx = c->learned_bufs[7];
+  if (const int chunks = select_chunks(n, k)) {
+    HIP_TRY(d_keys.ensure(sizeof(unsigned long long) * chunks * k));
+    launch_select_topk2(pred, n_poses, n_meshes, mask, k, mesh_ids, pose_ids, out,
+                        d_keys.as<unsigned long long>(), st);
+    return PERCH_OK;
+  }
   DevBuf &d_idx2 = c->learned_bufs[8], &d_temp = c->learned_bufs[9];
   DevBuf& d_masked = c->learned_bufs[10];
   const size_t temp_bytes = select_temp_bytes(n);

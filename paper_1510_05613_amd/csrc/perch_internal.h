@@ -193,6 +193,14 @@ constexpr int kTopkMaxN = 8192;
 constexpr int kTopkMaxK = 1024;
 bool launch_select_topk(const float* pred, int n_poses, int n_meshes, MeshMask mask, int k,
                         const int* rest, const int* pose_ids, int2* cands, hipStream_t s);
+// The same selection in two levels for more children: the number of kTopkMaxN-child
+// chunks when their k candidates each fit one more selection (n > kTopkMaxN,
+// k <= kTopkMaxK, chunks * k <= kTopkMaxN), else 0.  launch_select_topk2 then needs
+// buf = chunks * k device entries.
+int select_chunks(long n, int k);
+void launch_select_topk2(const float* pred, int n_poses, int n_meshes, MeshMask mask, int k,
+                         const int* rest, const int* pose_ids, int2* cands,
+                         unsigned long long* buf, hipStream_t s);
 void launch_child_cands(const int* idx_sorted, int k, const int* rest, int n_poses,
                         const int* pose_ids, int2* cands, hipStream_t s);
 // Work items (slot, mesh, pose, 0) of a batched search step: items[i] = (slot,

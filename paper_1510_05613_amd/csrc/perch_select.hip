@@ -73,32 +73,53 @@ __device__ inline unsigned wave_incl_scan(unsigned x, int lane) {
 constexpr int kSelThreads = 1024;
 constexpr int kSelPer = kTopkMaxN / kSelThreads;  // keys held per thread, in registers
 
-// One workgroup: thread t holds the keys of children [t*per, t*per + per).
-// Four 8-bit radix-select passes (most significant digit first) find T, the k-th
-// smallest key, and how many keys equal to T the first k hold; a block scan of
-// the per-thread tie counts gives each tie its index-order rank; the k chosen
-// (key, index) pairs go to LDS, and each one's rank among them is its output slot.
+// Selection modes: kSelAll, one workgroup over every child, writes cands; kSelChunk,
+// workgroup c over children [c L, c L + L) (L = kTopkMaxN), writes its first k (or
+// all of them when fewer) as (key << 32 | child) to buf[c k ..] in rank order,
+// sentinel entries (all ones) after them; kSelMerge, one workgroup over the chunks'
+// buf entries, writes cands.  The k smallest (key, child) of the children are among
+// their chunks' k smallest, and the merge's position order among equal keys is the
+// children's index order (chunks cover increasing children, each in rank order), so
+// the two levels give what one selection over all children gives.
+enum { kSelAll = 0, kSelChunk = 1, kSelMerge = 2 };
+
+// Thread t holds the keys of positions [t*per, t*per + per) of the workgroup's
+// range.  Four 8-bit radix-select passes (most significant digit first) find T, the
+// k-th smallest key, and how many keys equal to T the first k hold; a block scan of
+// the per-thread tie counts gives each tie its position-order rank; the k chosen
+// (key, position) pairs go to LDS, and each one's rank among them is its output slot.
+template <int MODE>
 __global__ void __launch_bounds__(kSelThreads) k_select_topk(
-    const float* __restrict__ pred, int n_poses, int n, MeshMask mask, int k,
-    const int* __restrict__ rest, const int* __restrict__ pose_ids, int2* __restrict__ cands) {
+    const float* __restrict__ pred, const unsigned long long* __restrict__ buf_in, int n_poses,
+    int n, MeshMask mask, int k, const int* __restrict__ rest, const int* __restrict__ pose_ids,
+    int2* __restrict__ cands, unsigned long long* __restrict__ buf_out) {
   __shared__ unsigned hist[256];
   __shared__ unsigned s_wsum[kSelThreads / 64];
   __shared__ unsigned long long s_sel[kTopkMaxK];
   __shared__ unsigned s_prefix, s_krem, s_nsel;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int per = (n + kSelThreads - 1) / kSelThreads;  // <= kSelPer, checked by the host
+  const int base = MODE == kSelChunk ? blockIdx.x * kTopkMaxN : 0;  // first child of the range
+  const int nl = MODE == kSelChunk ? min(kTopkMaxN, n - base) : n;  // positions in the range
+  const int kl = min(k, nl);                                          // keys to select
+  const int per = (nl + kSelThreads - 1) / kSelThreads;  // <= kSelPer, checked by the host
   const int i0 = tid * per;
   unsigned r[kSelPer];
 #pragma unroll
   for (int j = 0; j < kSelPer; ++j) {
     const int i = i0 + j;
     r[j] = 0xFFFFFFFFu;
-    if (j < per && i < n)
-      r[j] = mask.allow[i / n_poses] ? order_key(pred[i]) : order_key(__builtin_inff());
+    if (j < per && i < nl) {
+      if (MODE == kSelMerge) {
+        r[j] = (unsigned)(buf_in[i] >> 32);
+      } else {
+        const int c = base + i;
+        r[j] = mask.allow[c / n_poses] ? order_key(pred[c]) : order_key(__builtin_inff());
+      }
+    }
   }
   if (tid == 0) {
     s_prefix = 0u;
-    s_krem = (unsigned)k;
+    s_krem = (unsigned)kl;
     s_nsel = 0u;
   }
   for (int pass = 0; pass < 4; ++pass) {
@@ -109,7 +130,7 @@ __global__ void __launch_bounds__(kSelThreads) k_select_topk(
     const unsigned hmask = pass ? (0xFFFFFFFFu << (shift + 8)) : 0u;
 #pragma unroll
     for (int j = 0; j < kSelPer; ++j)
-      if (j < per && i0 + j < n && (r[j] & hmask) == pre) atomicAdd(&hist[(r[j] >> shift) & 255u], 1u);
+      if (j < per && i0 + j < nl && (r[j] & hmask) == pre) atomicAdd(&hist[(r[j] >> shift) & 255u], 1u);
     __syncthreads();
     if (wave == 0) {
       const unsigned h0 = hist[4 * lane], h1 = hist[4 * lane + 1], h2 = hist[4 * lane + 2],
@@ -131,27 +152,36 @@ __global__ void __launch_bounds__(kSelThreads) k_select_topk(
   const unsigned T = s_prefix, krem = s_krem;
   unsigned ties = 0;
 #pragma unroll
-  for (int j = 0; j < kSelPer; ++j) ties += (j < per && i0 + j < n && r[j] == T) ? 1u : 0u;
+  for (int j = 0; j < kSelPer; ++j) ties += (j < per && i0 + j < nl && r[j] == T) ? 1u : 0u;
   const unsigned wincl = wave_incl_scan(ties, lane);
   if (lane == 63) s_wsum[wave] = wincl;
   __syncthreads();
-  unsigned base = wincl - ties;
-  for (int w = 0; w < wave; ++w) base += s_wsum[w];
+  unsigned tb = wincl - ties;
+  for (int w = 0; w < wave; ++w) tb += s_wsum[w];
 #pragma unroll
   for (int j = 0; j < kSelPer; ++j) {
     const int i = i0 + j;
-    if (j >= per || i >= n) continue;
+    if (j >= per || i >= nl) continue;
     bool take = r[j] < T;
-    if (r[j] == T) take = base++ < krem;
+    if (r[j] == T) take = tb++ < krem;
     if (take) s_sel[atomicAdd(&s_nsel, 1u)] = ((unsigned long long)r[j] << 32) | (unsigned)i;
   }
   __syncthreads();
   for (int t = tid; t < k; t += kSelThreads) {
+    if (MODE == kSelChunk && t >= kl) {  // fewer children than k in this chunk
+      buf_out[(size_t)blockIdx.x * k + t] = ~0ull;
+      continue;
+    }
     const unsigned long long me = s_sel[t];
     int rank = 0;
-    for (int q = 0; q < k; ++q) rank += s_sel[q] < me ? 1 : 0;
-    const int id = (int)(me & 0xFFFFFFFFull);
-    cands[rank] = make_int2(rest[id / n_poses], pose_ids[id % n_poses]);
+    for (int q = 0; q < kl; ++q) rank += s_sel[q] < me ? 1 : 0;
+    const unsigned pos = (unsigned)(me & 0xFFFFFFFFull);
+    if (MODE == kSelChunk) {
+      buf_out[(size_t)blockIdx.x * k + rank] = (me & 0xFFFFFFFF00000000ull) | (unsigned)(base + pos);
+    } else {
+      const int id = MODE == kSelMerge ? (int)(unsigned)(buf_in[pos] & 0xFFFFFFFFull) : (int)pos;
+      cands[rank] = make_int2(rest[id / n_poses], pose_ids[id % n_poses]);
+    }
   }
 }
 
@@ -161,9 +191,25 @@ bool launch_select_topk(const float* pred, int n_poses, int n_meshes, MeshMask m
                         const int* rest, const int* pose_ids, int2* cands, hipStream_t s) {
   const long n = (long)n_poses * n_meshes;
   if (n <= 0 || n > kTopkMaxN || k <= 0 || k > kTopkMaxK || k > n) return false;
-  hipLaunchKernelGGL(k_select_topk, dim3(1), dim3(kSelThreads), 0, s, pred, n_poses, (int)n,
-                     mask, k, rest, pose_ids, cands);
+  hipLaunchKernelGGL(k_select_topk<kSelAll>, dim3(1), dim3(kSelThreads), 0, s, pred, nullptr,
+                     n_poses, (int)n, mask, k, rest, pose_ids, cands, nullptr);
   return true;
+}
+
+int select_chunks(long n, int k) {
+  if (n <= kTopkMaxN || k <= 0 || k > kTopkMaxK || k > n) return 0;
+  const long c = (n + kTopkMaxN - 1) / kTopkMaxN;
+  return c * k <= kTopkMaxN ? (int)c : 0;
+}
+
+void launch_select_topk2(const float* pred, int n_poses, int n_meshes, MeshMask mask, int k,
+                         const int* rest, const int* pose_ids, int2* cands,
+                         unsigned long long* buf, hipStream_t s) {
+  const int n = n_poses * n_meshes, c = select_chunks(n, k);
+  hipLaunchKernelGGL(k_select_topk<kSelChunk>, dim3(c), dim3(kSelThreads), 0, s, pred, nullptr,
+                     n_poses, n, mask, k, nullptr, nullptr, nullptr, buf);
+  hipLaunchKernelGGL(k_select_topk<kSelMerge>, dim3(1), dim3(kSelThreads), 0, s, nullptr, buf,
+                     n_poses, c * k, mask, k, rest, pose_ids, cands, nullptr);
 }
 
 size_t select_temp_bytes(int n) {

@@ -2,9 +2,11 @@
 heuristic ranks best reach the inadmissible queue), through the C ABI, against
 its plain definition: the first k entries of a stable ascending sort of the
 predictions, with the children of meshes already placed ranked as +inf and -0
-equal to +0.  Up to 8192 children one workgroup selects them, beyond that a
-device radix sort does; both sides of the limit are covered, with heavy ties,
-signed zeros, masks and k up to the selection's limit."""
+equal to +0.  Up to 8192 children one workgroup selects them; beyond that
+workgroups select each 8192-child chunk's k best and one more selection merges
+them while those candidates fit it, and a device radix sort does the rest; every
+path is covered, with heavy ties, signed zeros, masks and k up to the selection's
+limit."""
 import numpy as np
 import pytest
 
@@ -53,8 +55,11 @@ CASES = [
     (3, 700, 1024, (1, 0, 1), "ties"),
     (8, 1024, 1024, (1, 1, 0, 1, 1, 1, 1, 0), "normal"),  # n = 8192, the limit
     (8, 1024, 8192, (1,) * 8, "ties"),  # k above the selection's limit: sorted
-    (1, 8193, 64, (1,), "ties"),  # one child over the limit: sorted
+    (1, 8193, 64, (1,), "ties"),  # one child over the limit: two chunks
+    (1, 8292, 200, (1,), "ties"),  # the second chunk holds fewer children than k
+    (5, 20000, 400, (1, 0, 1, 1, 0), "ties"),  # 13 chunks, heavy ties across them
     (3, 40000, 256, (1, 0, 1), "costs"),  # the 640 x 480 scenes' child count
+    (3, 40000, 1024, (1, 1, 1), "costs"),  # too many chunk candidates: sorted
 ]
 
 
