@@ -364,7 +364,7 @@ def gain(net: "perch.Cnn", control: "perch.Cnn", indices: Sequence[int], config:
                budget_s=budget_s or None)
     for j, name in enumerate(("time_to_best_s", "evals_to_best", "time_total_s", "evals_total")):
         out[name] = {k: med([r[k][j] for r in rows]) for k in names}
-    for lk in ("learned", "learned_batched"):
+    for lk in ("learned", "learned_mha", "learned_batched"):
         if lk in names:
             out[lk + "_wins_vs"] = {k: int(sum(r[lk][0] < r[k][0] for r in rows))
                                     for k in names if k != lk}
