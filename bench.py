@@ -921,6 +921,8 @@ def main(argv=None):
         return 3
     if args.config == 3:
         print(json.dumps(run_batched(args)), flush=True)
+        if args.copy_probe_mb:
+            copy_probe(args.copy_probe_mb)
         return 0
     if args.learned_expansion:
         print(json.dumps({"learned_expansion": learned_expansion_leg()}), flush=True)
