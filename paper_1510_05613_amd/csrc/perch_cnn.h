@@ -64,13 +64,13 @@ void launch_forward(const Net& net, int n_crops, hipStream_t s);
 // conv3 + conv4 + pooling run as two fused kernels; of the activations only a[2]
 // is written.
 void launch_infer(const Net& net, int n_crops, hipStream_t s);
+// Predictions of n_pairs (crop, mesh, yaw) pairs in three launches: launch_infer's
+// two kernels, the second of which also computes the first head layer's per-crop and
+// per-mesh terms, then one thread per pair adds them and the yaw terms.
+void launch_infer_predict(const Net& net, int n_crops, int n_mesh, const Pair* pairs,
+                          int n_pairs, float* pred, hipStream_t s);
 // Pairs whose crop index is outside [0, n_crops) or mesh outside [0, n_mesh) are
 // ignored by the backward pass and predicted as NaN.
-// The first head layer splits into a per-crop part (features), a per-mesh part
-// (embedding and bias) and the yaw terms, so inference evaluates the two parts
-// once per crop and per mesh and only adds them per pair.
-void launch_predict(const Net& net, int n_crops, int n_mesh, const Pair* pairs, int n_pairs,
-                    float* pred, hipStream_t s);
 void launch_backward(const Net& net, int n_crops, int n_mesh, const Pair* pairs,
                      const float* target, int n_pairs, hipStream_t s);
 // The trunk's backward pass from net.dfeat (pooled-feature gradients of n_crops

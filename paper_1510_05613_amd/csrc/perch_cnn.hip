@@ -371,19 +371,34 @@ __global__ void __launch_bounds__(256)
 // from LDS copies, which leaves a wave the registers to issue all eighteen patch
 // loads of its conv3 tile at once.  a3 in LDS has a zero row and column before the
 // image (slot (y + 1) 17 + x + 1).
+//
+// HEAD: also the first head layer's per-crop term of every hidden unit from the
+// pooled features, hid[n][r] = sum_i hW1[r][i] feat[n][i], and (workgroups m <
+// n_mesh) the per-mesh term hid[n_img + m][r] = hb1[r] + sum_e hW1[r][64 + e]
+// emb[m][e], in k_head_parts' order.
 constexpr int kConv34Threads = 512;
 
+template <bool HEAD>
 __global__ void __launch_bounds__(kConv34Threads)
     k_conv34_pool(const bf16_t* __restrict__ a2, const bf16_t* __restrict__ W3,
                   const float* __restrict__ b3, const bf16_t* __restrict__ W4,
-                  const float* __restrict__ b4, float* __restrict__ feat, int n_img) {
+                  const float* __restrict__ b4, float* __restrict__ feat, int n_img,
+                  const Params P, int n_mesh, float* __restrict__ hid) {
   constexpr int NK = KDim<kC>::KP / 16, KP = KDim<kC>::KP, WROW = KP + 8;
   __shared__ __align__(16) bf16_t s3[17 * 17 * kPixStride];
   __shared__ __align__(16) bf16_t s4[8 * 8 * kC];
   __shared__ __align__(16) bf16_t sw[2][kC * WROW];
   __shared__ __align__(16) float sb[2 * kC];
+  __shared__ float sfeat[kFeat];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int co = lane & 31, kh = 8 * (lane >> 5);
+  if (HEAD && tid < kHid)
+    for (int m = blockIdx.x; m < n_mesh; m += gridDim.x) {
+      const float* w = P.hW1 + tid * kIn + kFeat;
+      float z = P.hb1[tid];
+      for (int e = 0; e < kEmb; ++e) z = fmaf(w[e], P.emb[m * kEmb + e], z);
+      hid[(n_img + m) * kHid + tid] = z;
+    }
   if (tid < 2 * kC) sb[tid] = tid < kC ? b3[tid] : b4[tid - kC];
   for (int i = tid; i < 2 * kC * KP / 8; i += blockDim.x) {
     const int l = i / (kC * KP / 8), j = i % (kC * KP / 8), r = j / (KP / 8), c8 = j % (KP / 8);
@@ -438,6 +453,20 @@ __global__ void __launch_bounds__(kConv34Threads)
       }
       feat[n * kFeat + tid] = sm / 64.0f;
       feat[n * kFeat + kC + tid] = sc / 4.0f;
+      if (HEAD) {
+        sfeat[tid] = sm / 64.0f;
+        sfeat[kC + tid] = sc / 4.0f;
+      }
+    }
+    if (HEAD) {
+      // sfeat is rewritten only after the next crop's first two barriers
+      lds_barrier();
+      if (tid < kHid) {
+        const float* w = P.hW1 + tid * kIn;
+        float z = 0.0f;
+        for (int i = 0; i < kFeat; ++i) z = fmaf(w[i], sfeat[i], z);
+        hid[n * kHid + tid] = z;
+      }
     }
   }
 }
@@ -615,48 +644,11 @@ __device__ __forceinline__ bool pair_ok(const Pair& pr, int n_crops, int n_mesh)
   return pr.crop >= 0 && pr.crop < n_crops && pr.mesh >= 0 && pr.mesh < n_mesh;
 }
 
-// Prediction per pair (NaN for a pair with an out-of-range crop or mesh index).
-__global__ void k_head_fwd(const float* feat, const Params P, const Pair* pairs, int n_pairs,
-                           int n_crops, int n_mesh, float* pred) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= n_pairs) return;
-  if (!pair_ok(pairs[q], n_crops, n_mesh)) {
-    pred[q] = __uint_as_float(0x7fc00000u);
-    return;
-  }
-  float h[kIn];
-  head_input(feat, P.emb, pairs[q], h);
-  float y = P.hb2[0];
-  for (int r = 0; r < kHid; ++r) {
-    float z = P.hb1[r];
-    for (int i = 0; i < kIn; ++i) z = fmaf(P.hW1[r * kIn + i], h[i], z);
-    y = fmaf(P.hw2[r], fmaxf(z, 0.0f), y);
-  }
-  pred[q] = y;
-}
-
-// Inference head, part 1: block b < n_crops holds crop b's feature term of every
-// hidden unit, A[b][r] = sum_i hW1[r][i] feat[b][i]; block n_crops + m holds mesh
-// m's term, B[m][r] = hb1[r] + sum_e hW1[r][64 + e] emb[m][e].
-__global__ void __launch_bounds__(kHid)
-    k_head_parts(const float* feat, const Params P, int n_crops, float* hid) {
-  __shared__ float x[kFeat];
-  const int b = blockIdx.x, r = threadIdx.x;
-  const bool crop = b < n_crops;
-  const int m = b - n_crops;
-  if (crop) x[r] = feat[b * kFeat + r];
-  else if (r < kEmb) x[r] = P.emb[m * kEmb + r];
-  __syncthreads();
-  const float* w = P.hW1 + r * kIn;
-  float z = crop ? 0.0f : P.hb1[r];
-  if (crop)
-    for (int i = 0; i < kFeat; ++i) z = fmaf(w[i], x[i], z);
-  else
-    for (int e = 0; e < kEmb; ++e) z = fmaf(w[kFeat + e], x[e], z);
-  hid[b * kHid + r] = z;
-}
-
-// Inference head, part 2: one pair per thread (NaN for an out-of-range pair).
+// The first head layer splits into a per-crop term (features), a per-mesh term
+// (embedding and bias; both computed by k_conv34_pool<true>) and the yaw terms, so
+// inference evaluates the first two once per crop and per mesh and only adds them
+// per pair.
+// Inference head per pair, one per thread (NaN for an out-of-range pair).
 __global__ void k_head_pairs(const float* hid, const Params P, const Pair* pairs, int n_pairs,
                              int n_crops, int n_mesh, float* pred) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
@@ -818,17 +810,22 @@ static int conv12_blocks(int n_crops) { return std::max(1, std::min(n_crops * kC
 void launch_infer(const Net& net, int n_crops, hipStream_t s) {
   hipLaunchKernelGGL(k_conv12_fwd, dim3(conv12_blocks(n_crops)), dim3(256), 0, s, net.crops,
                      net.Wb[0], net.P.cb[0], net.Wb[1], net.P.cb[1], net.a[2], n_crops);
-  hipLaunchKernelGGL(k_conv34_pool, dim3(std::max(1, std::min(n_crops, 512))), dim3(kConv34Threads), 0, s,
-                     net.a[2], net.Wb[2], net.P.cb[2], net.Wb[3], net.P.cb[3], net.feat, n_crops);
+  hipLaunchKernelGGL(k_conv34_pool<false>, dim3(std::max(1, std::min(n_crops, 512))),
+                     dim3(kConv34Threads), 0, s, net.a[2], net.Wb[2], net.P.cb[2], net.Wb[3],
+                     net.P.cb[3], net.feat, n_crops, net.P, 0, nullptr);
 }
 
-void launch_predict(const Net& net, int n_crops, int n_mesh, const Pair* pairs, int n_pairs,
-                    float* pred, hipStream_t s) {
-  if (n_pairs <= 0) return;
-  hipLaunchKernelGGL(k_head_parts, dim3(n_crops + n_mesh), dim3(kHid), 0, s, net.feat, net.P,
-                     n_crops, net.hid);
-  hipLaunchKernelGGL(k_head_pairs, dim3((n_pairs + 255) / 256), dim3(256), 0, s, net.hid, net.P,
-                     pairs, n_pairs, n_crops, n_mesh, pred);
+void launch_infer_predict(const Net& net, int n_crops, int n_mesh, const Pair* pairs,
+                          int n_pairs, float* pred, hipStream_t s) {
+  hipLaunchKernelGGL(k_conv12_fwd, dim3(conv12_blocks(n_crops)), dim3(256), 0, s, net.crops,
+                     net.Wb[0], net.P.cb[0], net.Wb[1], net.P.cb[1], net.a[2], n_crops);
+  hipLaunchKernelGGL(k_conv34_pool<true>,
+                     dim3(std::max(n_mesh, std::max(1, std::min(n_crops, 512)))),
+                     dim3(kConv34Threads), 0, s, net.a[2], net.Wb[2], net.P.cb[2], net.Wb[3],
+                     net.P.cb[3], net.feat, n_crops, net.P, n_mesh, net.hid);
+  if (n_pairs > 0)
+    hipLaunchKernelGGL(k_head_pairs, dim3((n_pairs + 255) / 256), dim3(256), 0, s, net.hid,
+                       net.P, pairs, n_pairs, n_crops, n_mesh, pred);
 }
 
 template <int CIN, int S, int HIN>

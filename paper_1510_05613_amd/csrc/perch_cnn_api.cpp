@@ -91,9 +91,8 @@ perch_status cnn_predict_on(perch_cnn* c, const uint16_t* crops, int n_crops, co
     return fail(PERCH_E_ARG, "batch (%d crops, %d pairs) above the network's capacity (%d, %d)",
                 n_crops, n_pairs, c ? c->max_crops : 0, c ? c->max_pairs : 0);
   c->net.crops = crops;
-  launch_infer(c->net, n_crops, s);
-  launch_predict(c->net, n_crops, c->n_mesh, reinterpret_cast<const Pair*>(pairs), n_pairs, pred,
-                 s);
+  launch_infer_predict(c->net, n_crops, c->n_mesh, reinterpret_cast<const Pair*>(pairs), n_pairs,
+                       pred, s);
   HIP_TRY(hipGetLastError());
   return PERCH_OK;
 }
@@ -297,9 +296,8 @@ perch_status perch_cnn_predict(perch_cnn* c, const uint16_t* crops_dev, int32_t 
   if (st) return st;
   if (!pred_dev) return fail(PERCH_E_ARG, "null output");
   c->net.crops = crops_dev;
-  launch_infer(c->net, n_crops, c->stream);
-  launch_predict(c->net, n_crops, c->n_mesh, reinterpret_cast<const Pair*>(pairs_dev), n_pairs,
-                 pred_dev, c->stream);
+  launch_infer_predict(c->net, n_crops, c->n_mesh, reinterpret_cast<const Pair*>(pairs_dev),
+                       n_pairs, pred_dev, c->stream);
   HIP_TRY(hipGetLastError());
   return PERCH_OK;
 }
