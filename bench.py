@@ -594,8 +594,8 @@ def learned_expansion_leg(reps: int = 20) -> dict:
         cost = torch.empty(topk, dtype=torch.int32, device="cuda")
         status = torch.empty_like(cost)
         stream = torch.cuda.current_stream()
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
-        times = []
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(7)]
+        times, fused = [], []
         for rep in range(reps + 2):
             ctx.set_parent([])
             torch.cuda.synchronize()
@@ -608,9 +608,15 @@ def learned_expansion_leg(reps: int = 20) -> dict:
             ev[3].record(stream)
             ctx.eval_children(top.contiguous(), cost, status)
             ev[4].record(stream)
+            # the learned search's own path: crops sampled inside the network's
+            # first kernel (perch_cnn_predict_scene), in place of the two stages above
+            ev[5].record(stream)
+            net.predict_scene(ctx, cells, pairs)
+            ev[6].record(stream)
             torch.cuda.synchronize()
             if rep >= 2:
                 times.append([ev[k].elapsed_time(ev[k + 1]) for k in range(4)])
+                fused.append(ev[5].elapsed_time(ev[6]))
         t = np.median(np.asarray(times), 0)
         tf = CNN_FWD_FLOPS * len(cells) / (t[1] * 1e-3) / 1e12
         out[f"config_{config}"] = {
@@ -618,7 +624,8 @@ def learned_expansion_leg(reps: int = 20) -> dict:
             "crops_ms": round(float(t[0]), 4), "network_ms": round(float(t[1]), 4),
             "rank_ms": round(float(t[2]), 4), "exact_topk_ms": round(float(t[3]), 4),
             "expansion_ms": round(float(t.sum()), 4), "network_tflops": round(tf, 2),
-            "network_frac": round(tf / PEAK_BF16_TFLOPS, 4)}
+            "network_frac": round(tf / PEAK_BF16_TFLOPS, 4),
+            "crops_and_network_fused_ms": round(float(np.median(fused)), 4)}
         ctx.close()
         net.close()
     out["workload"] = ("root expansion of held-out scene 10000: crops of every pose cell, "

@@ -342,6 +342,14 @@ perch_status perch_cnn_crops(perch_ctx* ctx, const float* xy, int32_t n, uint16_
  * Asynchronous on the network's stream. */
 perch_status perch_cnn_predict(perch_cnn* net, const uint16_t* crops_dev, int32_t n_crops,
                                const perch_cnn_pair* pairs_dev, int32_t n_pairs, float* pred_dev);
+/* perch_cnn_predict's predictions for the crops perch_cnn_crops_step(ctx, xy, n,
+ * the network's crop step) would make, without materialising them: the network's
+ * first kernel samples the context's observation and current parent composite
+ * itself (the values are bit-identical).  Runs on the context's stream.
+ * Synchronous. */
+perch_status perch_cnn_predict_scene(perch_cnn* net, perch_ctx* ctx, const float* xy, int32_t n,
+                                     const perch_cnn_pair* pairs_dev, int32_t n_pairs,
+                                     float* pred_dev);
 /* The learned search's ranking step (Sec. IV-C: only the children the learned
  * heuristic ranks best enter the inadmissible queue).  pred_dev (device, read
  * only): n_meshes x n_poses predictions, child u * n_poses + b = mesh position u,

@@ -64,11 +64,22 @@ void launch_forward(const Net& net, int n_crops, hipStream_t s);
 // conv3 + conv4 + pooling run as two fused kernels; of the activations only a[2]
 // is written.
 void launch_infer(const Net& net, int n_crops, hipStream_t s);
+// Crops sampled inside the first network kernel instead of read from net.crops:
+// the observation, the parent composite (float bits, +inf empty) and one descriptor
+// per crop, as launch_crops takes them.
+struct ImageCrops {
+  const float* obs;
+  const unsigned* pdepth;
+  int W, H;
+  const CropDesc* desc;
+};
 // Predictions of n_pairs (crop, mesh, yaw) pairs in three launches: launch_infer's
 // two kernels, the second of which also computes the first head layer's per-crop and
-// per-mesh terms, then one thread per pair adds them and the yaw terms.
+// per-mesh terms, then one thread per pair adds them and the yaw terms.  img: the
+// crops are sampled from the images (bit-identical to launch_crops' crops).
 void launch_infer_predict(const Net& net, int n_crops, int n_mesh, const Pair* pairs,
-                          int n_pairs, float* pred, hipStream_t s);
+                          int n_pairs, float* pred, hipStream_t s,
+                          const ImageCrops* img = nullptr);
 // Pairs whose crop index is outside [0, n_crops) or mesh outside [0, n_mesh) are
 // ignored by the backward pass and predicted as NaN.
 void launch_backward(const Net& net, int n_crops, int n_mesh, const Pair* pairs,

@@ -256,8 +256,30 @@ constexpr int kBandSlots = kCrop + 1;       // band row: col x at slot x + 1, pa
 constexpr int kPixStride = kC + 8;          // bfloat16 per LDS pixel (80 B spreads the banks)
 constexpr int kConv12Items = kCrop / 2 / kBandRows;  // work items per crop
 
+// Where k_conv12_fwd's input comes from: a crop tensor, or (IMG) the observation and
+// the parent composite, sampled per crop descriptor exactly as k_crops does.
+struct CropSource {
+  const bf16_t* crops;     // [n][64][64][2] (without IMG)
+  const float* obs;        // H x W observed depth (IMG)
+  const unsigned* pdepth;  // H x W parent composite, float bits, +inf empty (IMG)
+  int W, H;
+  const CropDesc* desc;    // one per crop (IMG)
+};
+
+// The two channels of the crop sample from observed depth z and parent depth bits k
+// at a pixel inside the image (k_crops' definition), packed as bfloat16 pairs.
+__device__ __forceinline__ unsigned crop_sample(float z, unsigned k, bool in_image, float zref) {
+  float a = 1.0f, b = 1.0f;
+  if (in_image) {
+    if (z > 0.0f) a = fminf(1.0f, fmaxf(-1.0f, (z - zref) * 4.0f));
+    if (k != 0x7f800000u) b = fminf(1.0f, fmaxf(-1.0f, (__uint_as_float(k) - zref) * 4.0f));
+  }
+  return (unsigned)f2bf(a) | ((unsigned)f2bf(b) << 16);
+}
+
+template <bool IMG>
 __global__ void __launch_bounds__(256)
-    k_conv12_fwd(const bf16_t* __restrict__ in, const bf16_t* __restrict__ W1,
+    k_conv12_fwd(const CropSource src, const bf16_t* __restrict__ W1,
                  const float* __restrict__ b1, const bf16_t* __restrict__ W2,
                  const float* __restrict__ b2, bf16_t* __restrict__ out, int n_img) {
   constexpr int NK1 = KDim<2>::KP / 16, KP1 = KDim<2>::KP;
@@ -286,18 +308,40 @@ __global__ void __launch_bounds__(256)
   for (int kc = 0; kc < NK2; ++kc)
     w2[kc] = *reinterpret_cast<const uint4*>(W2 + (size_t)co * KP2 + kc * 16 + kh);
   const int n_items = n_img * kConv12Items;
-  // 16 bytes of item `it`'s input rows: the load is clamped into the input and issued
-  // by every thread; `ok` says whether they are the item's (else zero padding)
-  auto fetch = [&](int it, bool& ok) {
-    const int itc = min(it, n_items - 1);
+  // Four samples (16 bytes) of item `it`'s input rows, issued by every thread: a
+  // 16-byte load clamped into the crop tensor, or (IMG) the four pixels' observed and
+  // parent depths, clamped into the image; `ok` says whether the row is the crop's
+  // (else conv1's zero padding).  The samples are formed when they go to LDS.
+  uint4 pre;
+  float pz[4], zref = 0.0f;
+  unsigned pk[4], inimg = 0u;
+  bool pre_ok;
+  auto fetch = [&](int it) {
+    const int itc = min(it, n_items - 1), n = itc / kConv12Items;
     const int yi = 2 * (itc % kConv12Items) * kBandRows - 2 + (tid % IN_U4) / 16;
     const int yc = min(max(yi, 0), kCrop - 1);
-    ok = it < n_items && yi == yc;
-    return *reinterpret_cast<const uint4*>(
-        in + (((size_t)(itc / kConv12Items) * kCrop + yc) * kCrop + 4 * (tid % 16)) * 2);
+    pre_ok = it < n_items && yi == yc;
+    if constexpr (IMG) {
+      const CropDesc d = src.desc[n];
+      const int st = d.step > 1 ? d.step : 1;
+      const int v = d.v0 + (yc - kCrop / 2) * st;
+      zref = d.zref;
+      inimg = 0u;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int u = d.u0 + (4 * (tid % 16) + q - kCrop / 2) * st;
+        const bool inb = u >= 0 && u < src.W && v >= 0 && v < src.H;
+        const size_t px = inb ? (size_t)v * src.W + u : 0;
+        pz[q] = src.obs[px];
+        pk[q] = src.pdepth[px];
+        inimg |= inb ? 1u << q : 0u;
+      }
+    } else {
+      pre = *reinterpret_cast<const uint4*>(
+          src.crops + (((size_t)n * kCrop + yc) * kCrop + 4 * (tid % 16)) * 2);
+    }
   };
-  bool pre_ok;
-  uint4 pre = fetch(blockIdx.x, pre_ok);
+  fetch(blockIdx.x);
   // the weight fragments land before the loop, whose waits then count only its own
   // loads and stores (a weight load pending at the loop entry would make the
   // compiler wait for every outstanding store in each iteration)
@@ -310,16 +354,23 @@ __global__ void __launch_bounds__(256)
   // the input of the next item goes to LDS during conv2 (conv1 is done with it),
   // long after its load was issued
   auto stage = [&]() {
-    if (tid < IN_U4)
+    if (tid < IN_U4) {
+      uint4 v = pre;
+      if constexpr (IMG)
+        v = make_uint4(crop_sample(pz[0], pk[0], inimg & 1u, zref),
+                       crop_sample(pz[1], pk[1], inimg & 2u, zref),
+                       crop_sample(pz[2], pk[2], inimg & 4u, zref),
+                       crop_sample(pz[3], pk[3], inimg & 8u, zref));
       *reinterpret_cast<uint4*>(sin + (tid / 16) * kInSlots + 4 + 4 * (tid % 16)) =
-          pre_ok ? pre : make_uint4(0u, 0u, 0u, 0u);
+          pre_ok ? v : make_uint4(0u, 0u, 0u, 0u);
+    }
   };
   stage();
   for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
     const int n = item / kConv12Items, r0 = (item % kConv12Items) * kBandRows;
     const int y0 = 2 * r0 - 1;  // conv1 row of band row 0
     lds_barrier();
-    pre = fetch(item + gridDim.x, pre_ok);
+    fetch(item + gridDim.x);
     // conv1: two 32-pixel tiles per band row; row -1 is conv2's zero padding
     for (int t = wave; t < 2 * kBandIn; t += 4) {
       const int yl = t >> 1, ox = (t & 1) * 32 + (lane & 31);
@@ -807,18 +858,37 @@ void launch_forward(const Net& net, int n_crops, hipStream_t s) {
 // on 256 CUs), each taking its share of the items.
 static int conv12_blocks(int n_crops) { return std::max(1, std::min(n_crops * kConv12Items, 768)); }
 
+static CropSource tensor_source(const bf16_t* crops) {
+  CropSource c{};
+  c.crops = crops;
+  return c;
+}
+
 void launch_infer(const Net& net, int n_crops, hipStream_t s) {
-  hipLaunchKernelGGL(k_conv12_fwd, dim3(conv12_blocks(n_crops)), dim3(256), 0, s, net.crops,
-                     net.Wb[0], net.P.cb[0], net.Wb[1], net.P.cb[1], net.a[2], n_crops);
+  hipLaunchKernelGGL(k_conv12_fwd<false>, dim3(conv12_blocks(n_crops)), dim3(256), 0, s,
+                     tensor_source(net.crops), net.Wb[0], net.P.cb[0], net.Wb[1], net.P.cb[1],
+                     net.a[2], n_crops);
   hipLaunchKernelGGL(k_conv34_pool<false>, dim3(std::max(1, std::min(n_crops, 512))),
                      dim3(kConv34Threads), 0, s, net.a[2], net.Wb[2], net.P.cb[2], net.Wb[3],
                      net.P.cb[3], net.feat, n_crops, net.P, 0, nullptr);
 }
 
 void launch_infer_predict(const Net& net, int n_crops, int n_mesh, const Pair* pairs,
-                          int n_pairs, float* pred, hipStream_t s) {
-  hipLaunchKernelGGL(k_conv12_fwd, dim3(conv12_blocks(n_crops)), dim3(256), 0, s, net.crops,
-                     net.Wb[0], net.P.cb[0], net.Wb[1], net.P.cb[1], net.a[2], n_crops);
+                          int n_pairs, float* pred, hipStream_t s, const ImageCrops* img) {
+  if (img) {
+    CropSource c{};
+    c.obs = img->obs;
+    c.pdepth = img->pdepth;
+    c.W = img->W;
+    c.H = img->H;
+    c.desc = img->desc;
+    hipLaunchKernelGGL(k_conv12_fwd<true>, dim3(conv12_blocks(n_crops)), dim3(256), 0, s, c,
+                       net.Wb[0], net.P.cb[0], net.Wb[1], net.P.cb[1], net.a[2], n_crops);
+  } else {
+    hipLaunchKernelGGL(k_conv12_fwd<false>, dim3(conv12_blocks(n_crops)), dim3(256), 0, s,
+                       tensor_source(net.crops), net.Wb[0], net.P.cb[0], net.Wb[1], net.P.cb[1],
+                       net.a[2], n_crops);
+  }
   hipLaunchKernelGGL(k_conv34_pool<true>,
                      dim3(std::max(n_mesh, std::max(1, std::min(n_crops, 512)))),
                      dim3(kConv34Threads), 0, s, net.a[2], net.Wb[2], net.P.cb[2], net.Wb[3],

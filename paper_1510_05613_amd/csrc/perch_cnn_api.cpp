@@ -97,6 +97,24 @@ perch_status cnn_predict_on(perch_cnn* c, const uint16_t* crops, int n_crops, co
   return PERCH_OK;
 }
 
+perch_status cnn_predict_scene_on(perch_cnn* c, perch_ctx* ctx, const void* desc_dev,
+                                  int n_crops, const void* pairs, int n_pairs, float* pred,
+                                  hipStream_t s) {
+  if (!c || n_crops < 1 || n_pairs < 1 || n_crops > c->max_crops || n_pairs > c->max_pairs)
+    return fail(PERCH_E_ARG, "batch (%d crops, %d pairs) above the network's capacity (%d, %d)",
+                n_crops, n_pairs, c ? c->max_crops : 0, c ? c->max_pairs : 0);
+  ImageCrops img;
+  img.obs = ctx->obs.as<float>();
+  img.pdepth = ctx->par_depth.as<unsigned>();
+  img.W = ctx->cam.W;
+  img.H = ctx->cam.H;
+  img.desc = reinterpret_cast<const CropDesc*>(desc_dev);
+  launch_infer_predict(c->net, n_crops, c->n_mesh, reinterpret_cast<const Pair*>(pairs), n_pairs,
+                       pred, s, &img);
+  HIP_TRY(hipGetLastError());
+  return PERCH_OK;
+}
+
 }  // namespace perch
 
 perch_status rank_children(perch_ctx* c, const float* pred, int n_poses, int n_meshes,
@@ -253,6 +271,27 @@ perch_status perch_cnn_crops(perch_ctx* ctx, const float* xy, int32_t n, uint16_
   launch_crops(ctx->obs.as<float>(), ctx->par_depth.as<unsigned>(), cam.W, cam.H,
                ctx->cnn_desc.as<CropDesc>(), n, crops_dev, ctx->stream);
   HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(ctx->stream));  // the host descriptors die here
+  return PERCH_OK;
+}
+
+perch_status perch_cnn_predict_scene(perch_cnn* net, perch_ctx* ctx, const float* xy, int32_t n,
+                                     const perch_cnn_pair* pairs_dev, int32_t n_pairs,
+                                     float* pred_dev) {
+  if (!net || !ctx || !xy || !pairs_dev || !pred_dev || n < 1 || n_pairs < 1)
+    return fail(PERCH_E_ARG, "bad arguments");
+  if (!ctx->has_obs) return fail(PERCH_E_STATE, "perch_set_observation not called");
+  if (ctx->parent_j < 0) return fail(PERCH_E_STATE, "perch_set_parent not called");
+  std::vector<CropDesc> d(n);
+  const Cam& cam = ctx->cam;
+  if (!crop_descriptors(cam.M, cam.fx, cam.fy, cam.cx, cam.cy, xy, n, d.data(), net->crop_step))
+    return fail(PERCH_E_ARG, "a crop centre lies behind the camera");
+  HIP_TRY(ctx->cnn_desc.ensure(sizeof(CropDesc) * n));
+  HIP_TRY(hipMemcpyAsync(ctx->cnn_desc.p, d.data(), sizeof(CropDesc) * n, hipMemcpyHostToDevice,
+                         ctx->stream));
+  perch_status st = cnn_predict_scene_on(net, ctx, ctx->cnn_desc.p, n, pairs_dev, n_pairs,
+                                         pred_dev, ctx->stream);
+  if (st) return st;
   HIP_TRY(hipStreamSynchronize(ctx->stream));  // the host descriptors die here
   return PERCH_OK;
 }

@@ -107,6 +107,12 @@ int cnn_crop_step(const perch_cnn* c);
 // stream in the learned search (perch_cnn_api.cpp).
 perch_status cnn_predict_on(perch_cnn* c, const uint16_t* crops, int n_crops, const void* pairs,
                             int n_pairs, float* pred, hipStream_t s);
+// The same predictions for crops sampled inside the network's first kernel from the
+// context's observation and current parent composite, one per descriptor of
+// desc_dev (device CropDesc array, the network's crop step), on stream s.
+perch_status cnn_predict_scene_on(perch_cnn* c, perch_ctx* ctx, const void* desc_dev,
+                                  int n_crops, const void* pairs, int n_pairs, float* pred,
+                                  hipStream_t s);
 
 }  // namespace perch
 

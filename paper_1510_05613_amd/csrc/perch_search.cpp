@@ -656,12 +656,12 @@ class Searcher {
     // device buffers kept by the context between searches (grown on demand)
     DevBuf* lb = c_->learned_bufs;
     DevBuf &d_desc = lb[0], &d_pairs = lb[1], &d_dist = lb[2], &d_pose = lb[3];
-    DevBuf &d_crops = lb[4], &d_pred = lb[5];  // lb[6..10]: the ranking's sort (rank_children)
+    DevBuf& d_pred = lb[5];  // lb[4] unused (crops are sampled inside the network's first
+                             // kernel); lb[6..10]: the ranking's buffers (rank_children)
     HIP_TRY(d_desc.ensure(sizeof(cnn::CropDesc) * n_cells));
     HIP_TRY(d_pairs.ensure(sizeof(perch_cnn_pair) * maxp));
     HIP_TRY(d_dist.ensure(sizeof(int) * nd));
     HIP_TRY(d_pose.ensure(sizeof(int) * P));
-    HIP_TRY(d_crops.ensure((size_t)n_cells * 64 * 64 * 2 * sizeof(uint16_t)));
     HIP_TRY(d_pred.ensure(sizeof(float) * maxp));
     hipStream_t st0 = c_->stream;
     // stream-ordered uploads; the host arrays outlive the search's first synchronisation
@@ -688,10 +688,8 @@ class Searcher {
       objs_of(n, po);
       perch_status st = perch_set_parent(c_, po, n.j);
       if (st) return st;
-      cnn::launch_crops(c_->obs.as<float>(), c_->par_depth.as<unsigned>(), cam.W, cam.H,
-                        d_desc.as<cnn::CropDesc>(), n_cells, d_crops.as<uint16_t>(), st0);
-      st = cnn_predict_on(o_.cnn, d_crops.as<uint16_t>(), n_cells, d_pairs.p, (int)maxp,
-                          d_pred.as<float>(), st0);
+      st = cnn_predict_scene_on(o_.cnn, c_, d_desc.p, n_cells, d_pairs.p, (int)maxp,
+                                d_pred.as<float>(), st0);
       if (st) return st;
       const int k = std::min(topk, cnt);
       all = k == cnt;

@@ -35,6 +35,7 @@ EXPORTS = ("perch_create", "perch_destroy", "perch_set_observation", "perch_add_
            "perch_batch_autotune",
            "perch_autotune", "perch_cnn_create", "perch_cnn_destroy", "perch_cnn_param_count",
            "perch_cnn_set_params", "perch_cnn_get_params", "perch_cnn_crops", "perch_cnn_predict",
+           "perch_cnn_predict_scene",
            "perch_cnn_set_crop_step",
            "perch_rank_children", "perch_cnn_train_step", "perch_cnn_gradients",
            "perch_posenet_create", "perch_posenet_destroy", "perch_posenet_param_count",
@@ -142,6 +143,7 @@ def load(path: str = LIB_PATH):
     L.perch_cnn_crops.argtypes = [P, P, I32, P]
     L.perch_cnn_set_crop_step.argtypes = [P, I32]
     L.perch_cnn_predict.argtypes = [P, P, I32, P, I32, P]
+    L.perch_cnn_predict_scene.argtypes = [P, P, P, I32, P, I32, P]
     L.perch_rank_children.argtypes = [P, P, I32, I32, P, I32, P, P, P]
     L.perch_cnn_train_step.argtypes = [P, P, I32, P, P, I32, C.c_float, C.POINTER(C.c_float)]
     L.perch_cnn_gradients.argtypes = [P, P, I32, P, P, I32, P, C.POINTER(C.c_float)]
@@ -594,6 +596,17 @@ class Cnn:
                                         pairs.shape[0], out.data_ptr()))
         return out
 
+    def predict_scene(self, ctx, xy, pairs):
+        """predict() of the crops Cnn.crops(ctx, xy, self.crop_step) would make, sampled
+        inside the network's first kernel (perch_cnn_predict_scene)."""
+        import torch
+
+        xy = np.ascontiguousarray(xy, np.float32).reshape(-1, 2)
+        out = torch.empty(pairs.shape[0], dtype=torch.float32, device="cuda")
+        _check(load().perch_cnn_predict_scene(self.h, ctx.h, xy.ctypes.data, len(xy),
+                                              pairs.data_ptr(), pairs.shape[0], out.data_ptr()))
+        return out
+
     def train_step(self, crops, pairs, target, lr: float, want_loss: bool = True):
         loss = C.c_float(0.0)
         _check(load().perch_cnn_train_step(self.h, crops.data_ptr(), crops.shape[0],
@@ -711,6 +724,17 @@ class PoseNet:
         _check(load().perch_posenet_predict(self.h, crops.data_ptr(), crops.shape[0],
                                             _dev_ptr(pairs, "int32", 2 * pairs.shape[0]),
                                             pairs.shape[0], out.data_ptr()))
+        return out
+
+    def predict_scene(self, ctx, xy, pairs):
+        """predict() of the crops Cnn.crops(ctx, xy, self.crop_step) would make, sampled
+        inside the network's first kernel (perch_cnn_predict_scene)."""
+        import torch
+
+        xy = np.ascontiguousarray(xy, np.float32).reshape(-1, 2)
+        out = torch.empty(pairs.shape[0], dtype=torch.float32, device="cuda")
+        _check(load().perch_cnn_predict_scene(self.h, ctx.h, xy.ctypes.data, len(xy),
+                                              pairs.data_ptr(), pairs.shape[0], out.data_ptr()))
         return out
 
     def train_step(self, crops, pairs, target, lr: float, want_loss: bool = True):

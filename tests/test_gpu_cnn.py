@@ -146,6 +146,33 @@ def test_inference_trunk_matches_training_trunk_and_oracle():
     assert np.max(np.abs(pred[sel] - want)) <= 1e-2 * (1.0 + np.max(np.abs(want)))
 
 
+def test_predict_scene_equals_crops_then_predict():
+    """perch_cnn_predict_scene samples the crops inside the network's first kernel: on
+    100 crops (more work items than resident workgroups), with a parent placed (both
+    channels in use) and crops reaching past the image, at crop steps 1 and 3, its
+    predictions equal perch_cnn_crops_step + perch_cnn_predict bit for bit."""
+    sc = H.c1_scene(0)
+    ctx = perch.context_from_scene(sc)
+    first = sc.gt_order[0]
+    ctx.set_parent([(int(sc.obj_mesh[first]), int(sc.gt_pose[first]))])
+    g = sc.grid
+    rng = np.random.default_rng(21)
+    n = 100
+    xy = np.stack([rng.uniform(g.x0 - 0.05, g.x0 + g.nx * g.step + 0.05, n),
+                   rng.uniform(g.y0 - 0.05, g.y0 + g.ny * g.step + 0.05, n)], 1).astype(np.float32)
+    ci = rng.integers(n, size=2 * n)
+    th = rng.uniform(0, 2 * np.pi, size=2 * n)
+    pairs = perch.Cnn.pairs(ci, rng.integers(3, size=2 * n), np.cos(th), np.sin(th))
+    net = perch.Cnn(3, max_crops=128, max_pairs=256)
+    net.set_params(_params(9))
+    for step in (1, 3):
+        net.set_crop_step(step)
+        want = net.predict(perch.Cnn.crops(ctx, xy, step), pairs).cpu().numpy()
+        got = net.predict_scene(ctx, xy, pairs).cpu().numpy()
+        assert np.isfinite(want).all()
+        assert np.array_equal(got.view(np.uint32), want.view(np.uint32)), step
+
+
 def test_gradients_match_oracle():
     crops, pairs, pairs_np, target = _small_batch(1)
     p = _params(5)
