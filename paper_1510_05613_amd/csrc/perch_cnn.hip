@@ -46,6 +46,26 @@ __device__ __forceinline__ int acc_row(int e, int lane) {
 // crops
 // ---------------------------------------------------------------------------
 
+// bfloat16(lo) | bfloat16(hi) << 16, rounded to nearest even (v_cvt_pk_bf16_f32).
+__device__ __forceinline__ unsigned pack_bf16(float lo, float hi) {
+  typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+  const bf16x2_t v = {(__bf16)lo, (__bf16)hi};
+  return __builtin_bit_cast(unsigned, v);
+}
+
+// The two channels of a crop sample at a pixel: (z - zref) / 0.25 clipped to
+// [-1, 1] for the observed depth z (1 where z <= 0: no return) and for the parent
+// depth with float bits k (1 where +inf: no parent point); 1 outside the image.
+// Shared by k_crops and the crops k_conv12_fwd samples itself.
+__device__ __forceinline__ unsigned crop_sample(float z, unsigned k, bool in_image, float zref) {
+  const float a = in_image && z > 0.0f
+                      ? __builtin_amdgcn_fmed3f((z - zref) * 4.0f, -1.0f, 1.0f) : 1.0f;
+  const float b = in_image && k != 0x7f800000u
+                      ? __builtin_amdgcn_fmed3f((__uint_as_float(k) - zref) * 4.0f, -1.0f, 1.0f)
+                      : 1.0f;
+  return pack_bf16(a, b);
+}
+
 // One crop per workgroup: 64 x 64 samples every `step` pixels around (u0, v0);
 // channel 0 the observed depth, channel 1 the parent composite, both as (z - zref)
 // / 0.25 clipped to [-1, 1], +1 where there is no return / no parent point or
@@ -62,16 +82,9 @@ __global__ void __launch_bounds__(1024)
   for (int t = threadIdx.x; t < kCrop * kCrop; t += blockDim.x) {
     const int cy = t / kCrop, cx = t % kCrop;
     const int u = d.u0 + (cx - kCrop / 2) * st, v = d.v0 + (cy - kCrop / 2) * st;
-    float a = 1.0f, b = 1.0f;
-    if (u >= 0 && u < W && v >= 0 && v < H) {
-      const float z = obs[v * W + u];
-      if (z > 0.0f) a = fminf(1.0f, fmaxf(-1.0f, (z - d.zref) * 4.0f));
-      if (pdepth) {
-        const unsigned k = pdepth[v * W + u];
-        if (k != 0x7f800000u) b = fminf(1.0f, fmaxf(-1.0f, (__uint_as_float(k) - d.zref) * 4.0f));
-      }
-    }
-    o[t] = (unsigned)f2bf(a) | ((unsigned)f2bf(b) << 16);
+    const bool inb = u >= 0 && u < W && v >= 0 && v < H;
+    const size_t px = inb ? (size_t)v * W + u : 0;
+    o[t] = crop_sample(obs[px], pdepth ? pdepth[px] : 0x7f800000u, inb, d.zref);
   }
 }
 
@@ -134,11 +147,6 @@ __device__ __forceinline__ uint4 patch8(const bf16_t* __restrict__ in, bool vali
 // channels 8 g + 4 (l / 32) + i in accumulator element 4 g + i (g, i = 0..3).  The
 // accumulation chain starts from the bias, and the ReLU and bfloat16 rounding give
 // four packed 8-byte stores per lane.
-__device__ __forceinline__ unsigned pack_bf16(float lo, float hi) {
-  typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
-  const bf16x2_t v = {(__bf16)lo, (__bf16)hi};  // v_cvt_pk_bf16_f32: round to nearest even
-  return __builtin_bit_cast(unsigned, v);
-}
 
 // The bias of the lane's accumulator elements: acc[4 g + i] = b[8 g + 4 (lane / 32) + i]
 // (b: 16-byte aligned, 32 channel biases).
@@ -265,17 +273,6 @@ struct CropSource {
   int W, H;
   const CropDesc* desc;    // one per crop (IMG)
 };
-
-// The two channels of the crop sample from observed depth z and parent depth bits k
-// at a pixel inside the image (k_crops' definition), packed as bfloat16 pairs.
-__device__ __forceinline__ unsigned crop_sample(float z, unsigned k, bool in_image, float zref) {
-  float a = 1.0f, b = 1.0f;
-  if (in_image) {
-    if (z > 0.0f) a = fminf(1.0f, fmaxf(-1.0f, (z - zref) * 4.0f));
-    if (k != 0x7f800000u) b = fminf(1.0f, fmaxf(-1.0f, (__uint_as_float(k) - zref) * 4.0f));
-  }
-  return (unsigned)f2bf(a) | ((unsigned)f2bf(b) << 16);
-}
 
 template <bool IMG>
 __global__ void __launch_bounds__(256)
