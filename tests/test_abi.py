@@ -47,6 +47,8 @@ def test_argument_errors_need_no_gpu():
     s.width, s.height, s.fx, s.fy, s.delta = 0, 10, 100.0, 100.0, 0.01
     assert L.perch_create(ctypes.byref(s), None, ctypes.byref(out)) == -1
     assert L.perch_eval_successors(None, None, 0, None, 0, None, None, None) == -1
+    assert L.perch_cnn_predict_scene(None, None, None, 0, None, 0, None) == -1
+    assert L.perch_cnn_predict(None, None, 0, None, 0, None) == -1
 
 
 def test_product_path_refuses_without_gpu():
