@@ -70,6 +70,23 @@ __device__ inline unsigned wave_incl_scan(unsigned x, int lane) {
   return x;
 }
 
+// Adds one to hist[d] for every active lane of the wavefront.  Predictions close in
+// value share their leading digits, so most lanes of a pass usually fall in one bin:
+// the lanes with the first active lane's digit are counted with one atomic, the
+// others add theirs one by one.
+__device__ inline void hist_add(unsigned* hist, bool act, unsigned d, int lane) {
+  const unsigned long long m = __ballot(act);
+  if (m == 0ull) return;
+  const int first = __builtin_ctzll(m);
+  const unsigned d0 = __shfl(d, first, 64);
+  const bool same = act && d == d0;
+  const unsigned long long ms = __ballot(same);
+  if (lane == first)
+    atomicAdd(&hist[d0], (unsigned)__popcll(ms));
+  else if (act && !same)
+    atomicAdd(&hist[d], 1u);
+}
+
 constexpr int kSelThreads = 1024;
 constexpr int kSelPer = kTopkMaxN / kSelThreads;  // keys held per thread, in registers
 
@@ -130,7 +147,7 @@ __global__ void __launch_bounds__(kSelThreads) k_select_topk(
     const unsigned hmask = pass ? (0xFFFFFFFFu << (shift + 8)) : 0u;
 #pragma unroll
     for (int j = 0; j < kSelPer; ++j)
-      if (j < per && i0 + j < nl && (r[j] & hmask) == pre) atomicAdd(&hist[(r[j] >> shift) & 255u], 1u);
+      hist_add(hist, j < per && i0 + j < nl && (r[j] & hmask) == pre, (r[j] >> shift) & 255u, lane);
     __syncthreads();
     if (wave == 0) {
       const unsigned h0 = hist[4 * lane], h1 = hist[4 * lane + 1], h2 = hist[4 * lane + 2],
