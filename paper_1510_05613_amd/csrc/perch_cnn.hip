@@ -696,9 +696,21 @@ __device__ __forceinline__ bool pair_ok(const Pair& pr, int n_crops, int n_mesh)
 // (embedding and bias; both computed by k_conv34_pool<true>) and the yaw terms, so
 // inference evaluates the first two once per crop and per mesh and only adds them
 // per pair.
-// Inference head per pair, one per thread (NaN for an out-of-range pair).
-__global__ void k_head_pairs(const float* hid, const Params P, const Pair* pairs, int n_pairs,
-                             int n_crops, int n_mesh, float* pred) {
+// Inference head per pair, one per thread (NaN for an out-of-range pair).  The
+// yaw weights and the output weights go to LDS first; each pair's per-crop and
+// per-mesh rows (64 floats each, 256-byte aligned) are read as float4.
+constexpr int kHeadPairThreads = 256;
+__global__ void __launch_bounds__(kHeadPairThreads)
+    k_head_pairs(const float* hid, const Params P, const Pair* pairs, int n_pairs, int n_crops,
+                 int n_mesh, float* pred) {
+  __shared__ float sw[3][kHid];  // cos-yaw weight, sin-yaw weight, output weight
+  for (int r = threadIdx.x; r < kHid; r += blockDim.x) {
+    const float* w = P.hW1 + r * kIn + kFeat + kEmb;
+    sw[0][r] = w[0];
+    sw[1][r] = w[1];
+    sw[2][r] = P.hw2[r];
+  }
+  __syncthreads();
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n_pairs) return;
   const Pair pr = pairs[q];
@@ -706,13 +718,19 @@ __global__ void k_head_pairs(const float* hid, const Params P, const Pair* pairs
     pred[q] = __uint_as_float(0x7fc00000u);
     return;
   }
-  const float* a = hid + pr.crop * kHid;
-  const float* bm = hid + (n_crops + pr.mesh) * kHid;
+  const float4* a = reinterpret_cast<const float4*>(hid + (size_t)pr.crop * kHid);
+  const float4* bm = reinterpret_cast<const float4*>(hid + (size_t)(n_crops + pr.mesh) * kHid);
   float y = P.hb2[0];
-  for (int r = 0; r < kHid; ++r) {
-    const float* w = P.hW1 + r * kIn + kFeat + kEmb;
-    const float z = fmaf(w[1], pr.sin_yaw, fmaf(w[0], pr.cos_yaw, a[r] + bm[r]));
-    y = fmaf(P.hw2[r], fmaxf(z, 0.0f), y);
+#pragma unroll
+  for (int r4 = 0; r4 < kHid / 4; ++r4) {
+    const float4 u = a[r4], v = bm[r4];
+    const float s4[4] = {u.x + v.x, u.y + v.y, u.z + v.z, u.w + v.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = 4 * r4 + j;
+      const float z = fmaf(sw[1][r], pr.sin_yaw, fmaf(sw[0][r], pr.cos_yaw, s4[j]));
+      y = fmaf(sw[2][r], fmaxf(z, 0.0f), y);
+    }
   }
   pred[q] = y;
 }
@@ -891,7 +909,8 @@ void launch_infer_predict(const Net& net, int n_crops, int n_mesh, const Pair* p
                      dim3(kConv34Threads), 0, s, net.a[2], net.Wb[2], net.P.cb[2], net.Wb[3],
                      net.P.cb[3], net.feat, n_crops, net.P, n_mesh, net.hid);
   if (n_pairs > 0)
-    hipLaunchKernelGGL(k_head_pairs, dim3((n_pairs + 255) / 256), dim3(256), 0, s, net.hid,
+    hipLaunchKernelGGL(k_head_pairs, dim3((n_pairs + kHeadPairThreads - 1) / kHeadPairThreads),
+                       dim3(kHeadPairThreads), 0, s, net.hid,
                        net.P, pairs, n_pairs, n_crops, n_mesh, pred);
 }
 
